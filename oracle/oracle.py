@@ -1,0 +1,392 @@
+"""CPU oracle for the scatter-limited hybrid (Q)MC / DG-S_N method.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``; the device library never imports,
+links or runs anything here, and this module never touches the device library.
+
+The heavy loops live in ``slh_oracle.c`` (plain sequential C, FP64,
+``-ffp-contract=off``).  This module
+  * builds and loads that C file,
+  * obtains the Sobol' direction numbers through scipy's public API
+    (``scipy.stats.qmc.Sobol``, Joe & Kuo numbers) -- the oracle's own
+    extraction, independent of the device library's,
+  * obtains the Gauss-Legendre polar nodes from ``numpy.polynomial.legendre``,
+  * and drives one time step as steps 1-4 of Sec. 2.2 of the paper:
+      1. scatter-limited (Q)MC leg (<= N_s scatters, pre/post tallies),
+      2. DG S_N collided solve with source sigma_s/(4 pi) phi_post,
+      3. remap: scatter-free (Q)MC from Q + sigma_s (phi_pre + phi_post + phi_c),
+      4. the remap census is the state at t_{n+1}.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "slh_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99",
+          "-D_GNU_SOURCE"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle into oracle/liboracle.so (gcc)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int),
+                ("x_lo", C.c_double), ("x_hi", C.c_double),
+                ("y_lo", C.c_double), ("y_hi", C.c_double),
+                ("sig_s", C.c_void_p), ("sig_a", C.c_void_p),
+                ("c", C.c_double), ("dt", C.c_double)]
+
+
+class _Points(C.Structure):
+    _fields_ = [("mode", C.c_int), ("sobol_dims", C.c_int), ("V", C.c_void_p)]
+
+
+class _BankIn(C.Structure):
+    _fields_ = [("n_in", C.c_int64),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("ox", C.c_void_p), ("oy", C.c_void_p),
+                ("w", C.c_void_p), ("cell", C.c_void_p), ("hid", C.c_void_p)]
+
+
+class _BankOut(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("ox", C.c_void_p), ("oy", C.c_void_p),
+                ("w", C.c_void_p), ("cell", C.c_void_p), ("hid", C.c_void_p),
+                ("alive", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        L = _lib
+        L.or_mix64.restype = C.c_uint64
+        L.or_mix64.argtypes = [C.c_uint64]
+        L.or_stream_seed.restype = C.c_uint64
+        L.or_stream_seed.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64]
+        L.or_nested_scramble.restype = C.c_uint32
+        L.or_nested_scramble.argtypes = [C.c_uint32, C.c_uint32]
+        L.or_sobol_word.restype = C.c_uint32
+        L.or_sobol_word.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32]
+        L.or_point_u32.restype = C.c_uint32
+        L.or_point_u32.argtypes = [C.POINTER(_Points), C.c_uint64, C.c_uint32, C.c_uint32]
+        L.or_u01.restype = C.c_double
+        L.or_u01.argtypes = [C.c_uint32]
+        L.or_mc_pass.restype = C.c_int64
+        L.or_mc_pass.argtypes = [C.POINTER(_Mesh), C.POINTER(_Points), C.c_int, C.c_int,
+                                 C.c_void_p, C.c_int64, C.POINTER(_BankIn), C.c_uint64,
+                                 C.c_uint64, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.POINTER(_BankOut)]
+        L.or_thin.restype = C.c_int64
+        L.or_thin.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64,
+                              C.c_void_p, C.POINTER(C.c_double)]
+        L.or_dg_sweep.restype = C.c_int
+        L.or_dg_sweep.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                  C.c_double, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_dg_collided.restype = C.c_int
+        L.or_dg_collided.argtypes = [C.POINTER(_Mesh), C.c_double, C.c_int, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                     C.c_void_p, C.POINTER(C.c_double)]
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+# ----------------------------------------------------------------------------
+# Point generator inputs
+# ----------------------------------------------------------------------------
+
+SOBOL_DIMS = 32
+_dirs_cache = {}
+
+
+_N_READ = 20
+
+
+def _sobol_recurrence_fit(v):
+    """Find the degree s and inner coefficients a_1..a_{s-1} of the primitive
+    polynomial for which the Sobol' recurrence on 32-bit words,
+        v_k = a_1 v_{k-1} ^ ... ^ a_{s-1} v_{k-s+1} ^ v_{k-s} ^ (v_{k-s} >> s),
+    reproduces every word v_s..v_{n-1} given; None if no (s, a) does."""
+    n = len(v)
+    for s in range(1, n - 4):
+        for a in range(1 << (s - 1)):
+            ok = True
+            for k in range(s, n):
+                x = v[k - s] ^ (v[k - s] >> s)
+                for i in range(1, s):
+                    if (a >> (s - 1 - i)) & 1:
+                        x ^= v[k - i]
+                if x != v[k]:
+                    ok = False
+                    break
+            if ok:
+                return s, a
+    return None
+
+
+def sobol_direction_numbers(ndim: int = SOBOL_DIMS) -> np.ndarray:
+    """Direction numbers v[d][j] (32-bit words, bit 31 = first digit) of
+    scipy's unscrambled Sobol' sequence (Joe & Kuo numbers).
+
+    scipy enumerates in Gray-code order, so its point number 2^(j+1) - 1 is the
+    single direction number v_j.  scipy's fast_forward is linear in the skip,
+    so v_0..v_19 are read off the points and the rest follow from the Sobol'
+    recurrence of each dimension's primitive polynomial, which is identified
+    from the words read (dimension 0 is the van der Corput identity)."""
+    if ndim in _dirs_cache:
+        return _dirs_cache[ndim]
+    from scipy.stats import qmc
+    V = np.zeros((ndim, 32), dtype=np.uint32)
+    for j in range(_N_READ):
+        s = qmc.Sobol(d=ndim, scramble=False, bits=32)
+        s.fast_forward(2 ** (j + 1) - 1)
+        V[:, j] = np.rint(s.random(1)[0] * 2.0 ** 32).astype(np.uint64).astype(np.uint32)
+    for j in range(32):
+        if j >= _N_READ:
+            V[0, j] = np.uint32(1 << (31 - j))
+        elif int(V[0, j]) != 1 << (31 - j):
+            raise RuntimeError("dimension 0 is not the van der Corput sequence")
+    for d in range(1, ndim):
+        v = [int(x) for x in V[d, :_N_READ]]
+        fit = _sobol_recurrence_fit(v)
+        if fit is None:
+            raise RuntimeError("no Sobol' recurrence reproduces dimension %d" % d)
+        s, a = fit
+        for k in range(_N_READ, 32):
+            x = v[k - s] ^ (v[k - s] >> s)
+            for i in range(1, s):
+                if (a >> (s - 1 - i)) & 1:
+                    x ^= v[k - i]
+            v.append(x)
+        V[d, :] = np.array(v, dtype=np.uint64).astype(np.uint32)
+    _dirs_cache[ndim] = V
+    return V
+
+
+class Points:
+    """The oracle's point function P(stream, dim, index) -> uint32."""
+
+    def __init__(self, mode: int = 0, ndim: int = SOBOL_DIMS):
+        self.V = np.ascontiguousarray(sobol_direction_numbers(ndim))
+        self.s = _Points(mode, ndim, _p(self.V))
+
+    def u32(self, stream: int, dim: int, index: int) -> int:
+        return lib().or_point_u32(C.byref(self.s), stream, dim, index)
+
+    def block(self, stream: int, dims, indices) -> np.ndarray:
+        out = np.zeros((len(indices), len(dims)), dtype=np.uint32)
+        L = lib()
+        for a, k in enumerate(indices):
+            for b, d in enumerate(dims):
+                out[a, b] = L.or_point_u32(C.byref(self.s), stream, d, int(k))
+        return out
+
+
+def stream_seed(seed, step, pss, pop, cohort=0) -> int:
+    return lib().or_stream_seed(seed, step, pss, pop, cohort)
+
+
+# ----------------------------------------------------------------------------
+# Angular quadrature (product S_N: Gauss-Legendre polar levels x equal azimuths)
+# ----------------------------------------------------------------------------
+
+def quadrature(order: int):
+    """Product set for x-y geometry: the N/2 positive Gauss-Legendre nodes of
+    order N for Oz (weights doubled for the mirrored -Oz, which has the same
+    in-plane components) times 2N equally spaced azimuths (m + 1/2) pi / N.
+    Returns (ox, oy, w), N^2 directions, sum(w) = 4 pi."""
+    if order < 2 or order % 2:
+        raise ValueError("S_N order must be even and >= 2")
+    mu, a = np.polynomial.legendre.leggauss(order)
+    sel = mu > 0
+    mu, a = mu[sel], a[sel]
+    naz = 2 * order
+    phi = (np.arange(naz) + 0.5) * np.pi / order
+    ox, oy, w = [], [], []
+    for k in range(len(mu)):
+        s = np.sqrt(1.0 - mu[k] ** 2)
+        for m in range(naz):
+            ox.append(s * np.cos(phi[m]))
+            oy.append(s * np.sin(phi[m]))
+            w.append(2.0 * a[k] * np.pi / order)
+    return np.array(ox), np.array(oy), np.array(w)
+
+
+# ----------------------------------------------------------------------------
+# Passes and solves
+# ----------------------------------------------------------------------------
+
+BAL_NAMES = ["emitted", "absorbed", "scattered", "leaked", "census", "cutoff",
+             "source_w", "census_in_w"]
+
+
+class Bank:
+    """Census bank (SoA), particles at the start of a step."""
+
+    def __init__(self, n=0):
+        self.x = np.zeros(n); self.y = np.zeros(n)
+        self.ox = np.zeros(n); self.oy = np.zeros(n); self.w = np.zeros(n)
+        self.cell = np.zeros(n, dtype=np.int32)
+        self.hid = np.zeros(n, dtype=np.uint64)
+
+    @property
+    def n(self):
+        return len(self.w)
+
+    def take(self, idx, factor=1.0):
+        b = Bank(0)
+        for f in ("x", "y", "ox", "oy", "w", "cell", "hid"):
+            setattr(b, f, np.ascontiguousarray(getattr(self, f)[idx]))
+        b.w = b.w * factor
+        return b
+
+
+class Mesh:
+    def __init__(self, prob):
+        self.nx, self.ny = int(prob["nx"]), int(prob["ny"])
+        self.x_lo, self.x_hi, self.y_lo, self.y_hi = (float(prob[k]) for k in
+                                                      ("x_lo", "x_hi", "y_lo", "y_hi"))
+        self.sig_s = np.ascontiguousarray(prob["sigma_s"], dtype=np.float64).ravel()
+        self.sig_a = np.ascontiguousarray(prob["sigma_a"], dtype=np.float64).ravel()
+        self.c = float(prob.get("c", 1.0))
+        self.dt = float(prob["dt"])
+        self.s = _Mesh(self.nx, self.ny, self.x_lo, self.x_hi, self.y_lo, self.y_hi,
+                       _p(self.sig_s), _p(self.sig_a), self.c, self.dt)
+        self.ncell = self.nx * self.ny
+        self.area = ((self.x_hi - self.x_lo) / self.nx) * ((self.y_hi - self.y_lo) / self.ny)
+
+
+def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
+            bank: Bank, seed: int, step: int, w_cut_rel: float, want_census: bool):
+    """One (Q)MC pass (Sec. 2.3).  Returns (T_a, T_b, balance dict, segments,
+    census-out candidates or None).  T are raw track-length sums."""
+    q_nodal = np.ascontiguousarray(q_nodal, dtype=np.float64).reshape(-1)
+    assert q_nodal.size == 4 * mesh.ncell
+    Ta = np.zeros(mesh.ncell); Tb = np.zeros(mesh.ncell); bal = np.zeros(len(BAL_NAMES))
+    bin_ = _BankIn(bank.n, _p(bank.x), _p(bank.y), _p(bank.ox), _p(bank.oy), _p(bank.w),
+                   _p(bank.cell), _p(bank.hid))
+    out = None
+    bout_p = None
+    if want_census:
+        ncand = bank.n + n_src
+        out = Bank(ncand)
+        out.alive = np.zeros(ncand, dtype=np.uint8)
+        bout = _BankOut(_p(out.x), _p(out.y), _p(out.ox), _p(out.oy), _p(out.w),
+                        _p(out.cell), _p(out.hid), _p(out.alive))
+        bout_p = C.byref(bout)
+    seg = lib().or_mc_pass(C.byref(mesh.s), C.byref(pts.s), kind, n_s, _p(q_nodal), n_src,
+                           C.byref(bin_), seed, step, w_cut_rel, _p(Ta), _p(Tb), _p(bal),
+                           bout_p)
+    return Ta, Tb, dict(zip(BAL_NAMES, bal)), int(seg), out
+
+
+def thin(cand: Bank, cap: int, thin_stream: int):
+    """Census population control (see slh_oracle.c: or_thin)."""
+    keep = np.zeros(cand.n, dtype=np.uint8)
+    fac = C.c_double(1.0)
+    lib().or_thin(cand.n, _p(cand.alive), _p(cand.hid), cap, thin_stream, _p(keep),
+                  C.byref(fac))
+    idx = np.nonzero(keep)[0]
+    return cand.take(idx, fac.value), fac.value
+
+
+def dg_sweep(nx, ny, box, sig_e, a, b, src, in_x=None, in_y=None):
+    psi = np.zeros(4 * nx * ny)
+    sig_e = np.ascontiguousarray(sig_e, dtype=np.float64)
+    src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1)
+    in_x = None if in_x is None else np.ascontiguousarray(in_x, dtype=np.float64)
+    in_y = None if in_y is None else np.ascontiguousarray(in_y, dtype=np.float64)
+    rc = lib().or_dg_sweep(nx, ny, box[0], box[1], box[2], box[3], _p(sig_e), a, b,
+                           _p(src), _p(in_x), _p(in_y), _p(psi))
+    if rc != 0:
+        raise RuntimeError("singular DG cell system")
+    return psi.reshape(ny, nx, 4)
+
+
+def dg_collided(mesh: Mesh, quad, phi_post, tau=2.0, tol=1e-12, max_iter=200):
+    ox, oy, w = (np.ascontiguousarray(v, dtype=np.float64) for v in quad)
+    phi = np.zeros(4 * mesh.ncell)
+    res = C.c_double(0.0)
+    phi_post = np.ascontiguousarray(phi_post, dtype=np.float64)
+    it = lib().or_dg_collided(C.byref(mesh.s), tau, len(w), _p(ox), _p(oy), _p(w),
+                              _p(phi_post), tol, max_iter, _p(phi), C.byref(res))
+    if it < 0:
+        raise RuntimeError("DG sweep failed")
+    return phi.reshape(mesh.ncell, 4), it, res.value
+
+
+# ----------------------------------------------------------------------------
+# Time stepping (Sec. 2.2, steps 1-4)
+# ----------------------------------------------------------------------------
+
+PASS_MC, PASS_REMAP = 1, 2
+POP_SOURCE, POP_CENSUS, POP_THIN = 0, 1, 2
+
+
+class HybridOracle:
+    """Plain sequential hybrid solver, one call to ``step`` per time step."""
+
+    def __init__(self, prob: dict):
+        self.prob = prob
+        self.mesh = Mesh(prob)
+        self.q = np.ascontiguousarray(prob["q"], dtype=np.float64).ravel()
+        self.n_s = int(prob["n_s"])
+        self.n_p = int(prob["n_particles"])
+        self.cap = int(prob.get("census_cap", 0)) or self.n_p
+        self.seed = int(prob.get("seed", 0)) & (2 ** 64 - 1)
+        self.tau = float(prob.get("time_closure", 2.0))
+        self.si_tol = float(prob.get("si_tol", 1e-12))
+        self.si_max = int(prob.get("si_max_iter", 200))
+        self.w_cut_rel = float(prob.get("w_cut_rel", 1e-8))
+        self.points = Points(int(prob.get("points", 0)))
+        self.quad = quadrature(int(prob["sn_order"]))
+        self.bank = Bank(0)
+        self.step_index = 0
+
+    def step(self) -> dict:
+        m = self.mesh
+        n = self.step_index
+        adt = m.area * m.dt
+        q4 = np.repeat(self.q, 4)
+        # step 1: scatter-limited leg from Q and the census (initial data)
+        Tpre, Tpost, bal1, seg1, _ = mc_pass(m, self.points, PASS_MC, self.n_s, q4, self.n_p,
+                                             self.bank, self.seed, n, self.w_cut_rel, False)
+        phi_pre, phi_post = Tpre / adt, Tpost / adt
+        # step 2: collided S_N-DG solve, zero initial/boundary data
+        phi_c, iters, resid = dg_collided(m, self.quad, phi_post, self.tau, self.si_tol,
+                                          self.si_max)
+        # step 3: remap source Q + sigma_s (phi_pre + phi_post + phi_c), scatter-free leg
+        qR = (self.q + m.sig_s * (phi_pre + phi_post))[:, None] + m.sig_s[:, None] * phi_c
+        _, TR, bal2, seg2, cand = mc_pass(m, self.points, PASS_REMAP, self.n_s, qR, self.n_p,
+                                          self.bank, self.seed, n, self.w_cut_rel, True)
+        # step 4: the remap census is the state at t_{n+1} (capped)
+        thin_stream = stream_seed(self.seed, n, PASS_REMAP, POP_THIN, 0)
+        n_alive = int(cand.alive.sum())
+        self.bank, factor = thin(cand, self.cap, thin_stream)
+        self.step_index += 1
+        return dict(step=n, phi_R=TR / adt, phi_pre=phi_pre, phi_post=phi_post, phi_c=phi_c,
+                    T_pre=Tpre, T_post=Tpost, T_R=TR, bal_mc=bal1, bal_remap=bal2,
+                    segments=seg1 + seg2, seg_mc=seg1, seg_remap=seg2, si_iters=iters,
+                    si_resid=resid, census_alive=n_alive, census_kept=self.bank.n,
+                    thin_factor=factor, q_remap=qR)
+
+    def run(self, n_steps: int):
+        return [self.step() for _ in range(n_steps)]

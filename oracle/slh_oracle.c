@@ -1,0 +1,587 @@
+/*
+ * CPU oracle for the scatter-limited hybrid (Q)MC / DG-S_N transport method
+ * (Krotz & McClarren, "Scatter-Limited Hybrid Monte Carlo, Deterministic
+ * Transport with Quasi-Monte Carlo Sampling", arXiv:2511.16821).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, sequential
+ * reference that the device library is checked against.  Nothing in the
+ * product path links, loads or calls it; only the tests, the smoke check and
+ * the CPU-baseline leg of the benchmark do.  It shares no code, header, table
+ * or constant generator with the device library.
+ *
+ * Everything is FP64, single threaded, in particle-index order, compiled with
+ * -ffp-contract=off.  Each function names the passage of the paper it follows.
+ *
+ * Readings of the paper that this file fixes (the paper is silent, garbled or
+ * inconsistent there) are listed in the design notes; in short:
+ *   - phi = integral of Psi over the sphere; Q is the angle-integrated source,
+ *     so the angular source is Q/(4 pi) (Sec. 2.1, eq. (1) with Sec. 2.3).
+ *   - 2-D means x-y geometry invariant in z with directions on the full sphere;
+ *     path length is the 3-D length c*t, in-plane motion is (Ox, Oy)*s.
+ *   - the track-length estimator is the exact integral of the exponentially
+ *     decaying implicit-capture weight, w (1 - exp(-sigma l)) / sigma, so that
+ *     sigma * contribution equals the weight lost on the segment.
+ *   - one optical depth tau = -ln u per flight, consumed at rate sigma_s across
+ *     cells (Sec. 2.3, "sample next scatter at rate sigma_s").
+ *   - the remap (step 3 of Sec. 2.2) emits from Q + sigma_s (phi_pre + phi_post
+ *     + phi_c), with phi_c bilinear per cell from the DG solve, through a
+ *     majorant CDF over cells and a signed weight.
+ *
+ * Parity unpinned (no closed form or independent check exists): none of the
+ * functions below; the tests pin each one (points, attenuation, Erlang split,
+ * balance, DG manufactured solution, remap weights, thinning).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Point generator (Sec. 2.4: low-discrepancy points replace pseudo-random     */
+/* draws inside the same inverse-CDF maps).  Sobol' digital sequence in        */
+/* natural (not Gray-code) index order, nested (Owen-type) scrambled with the  */
+/* hash permutation of Laine & Karras (2011) on bit-reversed digits, as        */
+/* described by Burley (2020).  Stream seeds and pseudo-random mode use the    */
+/* SplitMix64 output function (Steele, Lea & Flood 2014).                      */
+/* ------------------------------------------------------------------------ */
+
+uint64_t or_mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Stream of points for (time step, pass, population, cohort). */
+uint64_t or_stream_seed(uint64_t seed, uint64_t step, uint32_t pass,
+                        uint32_t pop, uint64_t cohort)
+{
+    uint64_t h = or_mix64(seed);
+    h = or_mix64(h ^ step);
+    h = or_mix64(h ^ (uint64_t)(pass * 16u + pop));
+    h = or_mix64(h ^ cohort);
+    return h;
+}
+
+static uint32_t or_reverse_bits(uint32_t x)
+{
+    uint32_t r = 0;
+    for (int b = 0; b < 32; ++b)
+        if (x & (1u << b)) r |= 1u << (31 - b);
+    return r;
+}
+
+/* Nested scramble: output digit k (from the most significant) depends only on
+ * input digits 1..k.  On the bit-reversed word, adding a seed and x ^= x * even
+ * only propagate information from low bits to high bits. */
+uint32_t or_nested_scramble(uint32_t x, uint32_t s)
+{
+    x = or_reverse_bits(x);
+    x += s;
+    x ^= x * 0x6c50b47cu;
+    x ^= x * 0xb82f1e52u;
+    x ^= x * 0xc7afe638u;
+    x ^= x * 0x8d22f6e6u;
+    return or_reverse_bits(x);
+}
+
+/* Unscrambled Sobol' word: XOR of the direction numbers selected by the bits
+ * of the index (natural order).  V holds 32 words per dimension. */
+uint32_t or_sobol_word(const uint32_t *V, uint32_t dim, uint32_t index)
+{
+    uint32_t x = 0;
+    for (int j = 0; j < 32; ++j)
+        if ((index >> j) & 1u) x ^= V[dim * 32u + (uint32_t)j];
+    return x;
+}
+
+typedef struct {
+    int mode;             /* 0 = scrambled Sobol', 1 = pseudo-random */
+    int sobol_dims;       /* dimensions available in V                 */
+    const uint32_t *V;    /* direction numbers, [sobol_dims][32]       */
+} or_points;
+
+uint32_t or_point_u32(const or_points *P, uint64_t stream, uint32_t dim,
+                      uint32_t index)
+{
+    if (P->mode == 0 && (int)dim < P->sobol_dims) {
+        uint32_t s = (uint32_t)(or_mix64(stream + dim) >> 32);
+        return or_nested_scramble(or_sobol_word(P->V, dim, index), s);
+    }
+    uint64_t ctr = ((uint64_t)dim << 32) | (uint64_t)index;
+    return (uint32_t)(or_mix64(stream ^ or_mix64(ctr)) >> 32);
+}
+
+/* u in (0,1): never 0, never 1. */
+double or_u01(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
+
+/* ------------------------------------------------------------------------ */
+/* Scatter-limited Monte Carlo pass (Sec. 2.3).                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int nx, ny;
+    double x_lo, x_hi, y_lo, y_hi;
+    const double *sig_s, *sig_a; /* per cell, row-major j*nx+i */
+    double c, dt;
+} or_mesh;
+
+/* Balance record of one pass (implicit capture, Sec. 2.3). */
+enum { OB_EMITTED = 0, OB_ABSORBED, OB_SCATTERED, OB_LEAKED, OB_CENSUS,
+       OB_CUTOFF, OB_SOURCE_W, OB_CENSUS_IN_W, OB_N };
+
+typedef struct {
+    /* census-in bank (starts at the beginning of the step, n = 0) */
+    int64_t n_in;
+    const double *x, *y, *ox, *oy, *w;
+    const int32_t *cell;
+    const uint64_t *hid;
+} or_bank_in;
+
+typedef struct {
+    /* census-out candidates at slot g (pass 2 only), size n_in + n_src */
+    double *x, *y, *ox, *oy, *w;
+    int32_t *cell;
+    uint64_t *hid;
+    uint8_t *alive;
+} or_bank_out;
+
+/* Fraction of the segment integral: g(z) = (1 - exp(-z)) / z, g(0) = 1. */
+static double or_g(double z) { return z > 0.0 ? -expm1(-z) / z : 1.0; }
+
+/* Bilinear value of nodal data q[4] (nodes (0,0),(1,0),(0,1),(1,1)) at local
+ * coordinates (a, b) in [0,1]^2, written so that equal corners give q[0]. */
+static double or_bilinear(const double *q, double a, double b)
+{
+    return q[0] + a * (q[1] - q[0]) + b * (q[2] - q[0])
+         + a * b * (q[0] - q[1] - q[2] + q[3]);
+}
+
+static double or_maxabs4(const double *q)
+{
+    double m = fabs(q[0]);
+    for (int k = 1; k < 4; ++k) if (fabs(q[k]) > m) m = fabs(q[k]);
+    return m;
+}
+
+enum { EV_CENSUS = 0, EV_COLLIDE = 1, EV_XFACE = 2, EV_YFACE = 3 };
+
+/*
+ * One MC pass over [t_n, t_n + dt].
+ *   kind  = 1: step 1 of Sec. 2.2, the scatter-limited leg with n_lim = N_s
+ *              (pre tally for n < N_s, post tally for n = N_s; n_lim < 0 means
+ *              unlimited scattering, Sec. 2.3 "unlimited case").
+ *   kind  = 2: step 3 of Sec. 2.2, the scatter-free remap (every particle is
+ *              in the post-limit regime: attenuation by sigma_t, no scatter).
+ * Source: nodal (bilinear) emission density q_nodal[n_cells*4] per unit
+ * area and time, angle-integrated; n_src particles (birth ~ q, Sec. 2.3).
+ * T_a receives the pre tally, T_b the post (kind 1) or the remap tally
+ * (kind 2); both are raw track-length sums (weight x length).
+ * Returns the number of segments (loop iterations).
+ */
+int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
+                   const double *q_nodal, int64_t n_src,
+                   const or_bank_in *bin, uint64_t seed, uint64_t step,
+                   double w_cut_rel,
+                   double *T_a, double *T_b, double *bal, or_bank_out *bout)
+{
+    const int nx = M->nx, ny = M->ny;
+    const int64_t ncell = (int64_t)nx * ny;
+    const double hx = (M->x_hi - M->x_lo) / nx;
+    const double hy = (M->y_hi - M->y_lo) / ny;
+    const double area = hx * hy;
+    const double dt = M->dt, c = M->c;
+    const int n_lim = (kind == 2) ? 0 : (n_s < 0 ? 0x7fffffff : n_s);
+
+    for (int64_t i = 0; i < ncell; ++i) { T_a[i] = 0.0; T_b[i] = 0.0; }
+    for (int k = 0; k < OB_N; ++k) bal[k] = 0.0;
+
+    /* Majorant per cell, M_i = A dt max_corner |q_i|, and its CDF in cell
+     * order (sequential sum). */
+    double *cdf = (double *)malloc(sizeof(double) * (size_t)(ncell > 0 ? ncell : 1));
+    double total = 0.0;
+    for (int64_t i = 0; i < ncell; ++i) {
+        total += area * dt * or_maxabs4(q_nodal + 4 * i);
+        cdf[i] = total;
+    }
+    const int64_t n_emit = (total > 0.0) ? n_src : 0;
+    const double w_ref = (n_emit > 0) ? total / (double)n_src : 0.0;
+    const double w_cut = w_cut_rel * w_ref;
+
+    const uint64_t src_stream = or_stream_seed(seed, step, (uint32_t)kind, 0u, 0u);
+    int64_t segments = 0;
+    const int64_t n_tot = bin->n_in + n_emit;
+
+    for (int64_t g = 0; g < n_tot; ++g) {
+        double x, y, ox, oy, w, trel, tau = 0.0;
+        int ix, iy, n = 0;
+        uint64_t stream;
+        uint32_t pidx, dcur;
+        uint64_t hid;
+
+        if (g < bin->n_in) {
+            /* census-in particle: at t_n, scatter counter reset (Sec. 2.2, step 1) */
+            x = bin->x[g]; y = bin->y[g]; ox = bin->ox[g]; oy = bin->oy[g];
+            w = bin->w[g];
+            ix = bin->cell[g] % nx; iy = bin->cell[g] / nx;
+            hid = bin->hid[g];
+            trel = 0.0;
+            stream = or_stream_seed(seed, step, (uint32_t)kind, 1u, hid >> 32);
+            pidx = (uint32_t)(hid & 0xffffffffu);
+            dcur = 0;
+            bal[OB_CENSUS_IN_W] += w;
+        } else {
+            /* source particle: cell by inverse CDF of the majorant, uniform
+             * position in the cell and time in the step, isotropic direction,
+             * signed weight q(x,y) * total / (N_p * max_corner|q|). */
+            const int64_t s = g - bin->n_in;
+            stream = src_stream;
+            pidx = (uint32_t)s;
+            hid = (step << 32) | (uint64_t)s;
+            const double u0 = or_u01(or_point_u32(P, stream, 0, pidx));
+            const double target = u0 * total;
+            int64_t lo = 0, hi = ncell - 1; /* first i with target < cdf[i] */
+            while (lo < hi) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (target < cdf[mid]) hi = mid; else lo = mid + 1;
+            }
+            const int64_t ci = lo;
+            ix = (int)(ci % nx); iy = (int)(ci / nx);
+            const double u1 = or_u01(or_point_u32(P, stream, 1, pidx));
+            const double u2 = or_u01(or_point_u32(P, stream, 2, pidx));
+            const double u3 = or_u01(or_point_u32(P, stream, 3, pidx));
+            const double u4 = or_u01(or_point_u32(P, stream, 4, pidx));
+            const double u5 = or_u01(or_point_u32(P, stream, 5, pidx));
+            x = M->x_lo + hx * ((double)ix + u1);
+            y = M->y_lo + hy * ((double)iy + u2);
+            trel = u3 * dt;
+            const double st = 2.0 * sqrt(u4 * (1.0 - u4)); /* sin(theta), Oz = 1 - 2 u4 */
+            const double ph = 2.0 * M_PI * u5;
+            ox = st * cos(ph);
+            oy = st * sin(ph);
+            const double *qc = q_nodal + 4 * ci;
+            w = (total / (double)n_src) * (or_bilinear(qc, u1, u2) / or_maxabs4(qc));
+            dcur = 6;
+            bal[OB_SOURCE_W] += w;
+        }
+        bal[OB_EMITTED] += w;
+        if (n < n_lim) {
+            tau = -log(or_u01(or_point_u32(P, stream, dcur, pidx)));
+            dcur += 1;
+        }
+
+        for (;;) {
+            const int64_t cell = (int64_t)iy * nx + ix;
+            const double ss = M->sig_s[cell], sa = M->sig_a[cell], st = sa + ss;
+            const int pre = (n < n_lim);
+            double d_cen = c * (dt - trel);
+            if (d_cen < 0.0) d_cen = 0.0;
+            double d_col = INFINITY;
+            if (pre && ss > 0.0) { d_col = tau / ss; if (d_col < 0.0) d_col = 0.0; }
+            double d_x = INFINITY, d_y = INFINITY;
+            if (ox > 0.0) d_x = (M->x_lo + hx * (double)(ix + 1) - x) / ox;
+            else if (ox < 0.0) d_x = (M->x_lo + hx * (double)ix - x) / ox;
+            if (oy > 0.0) d_y = (M->y_lo + hy * (double)(iy + 1) - y) / oy;
+            else if (oy < 0.0) d_y = (M->y_lo + hy * (double)iy - y) / oy;
+            if (d_x < 0.0) d_x = 0.0;
+            if (d_y < 0.0) d_y = 0.0;
+
+            /* nearest event; ties: census > collision > x face > y face */
+            double l = d_cen; int ev = EV_CENSUS;
+            if (d_col < l) { l = d_col; ev = EV_COLLIDE; }
+            if (d_x < l) { l = d_x; ev = EV_XFACE; }
+            if (d_y < l) { l = d_y; ev = EV_YFACE; }
+
+            /* implicit capture with sigma_a before the limit, sigma_t after */
+            const double sig = pre ? sa : st;
+            const double z = sig * l;
+            const double contrib = w * l * or_g(z);
+            if (pre) T_a[cell] += contrib; else T_b[cell] += contrib;
+            bal[OB_ABSORBED] += sa * contrib;
+            if (!pre) bal[OB_SCATTERED] += ss * contrib;
+            w = w * exp(-z);
+            if (pre && ss > 0.0) tau -= ss * l;
+            x += ox * l;
+            y += oy * l;
+            trel += l / c;
+            segments += 1;
+
+            if (ev == EV_CENSUS) {
+                bal[OB_CENSUS] += w;
+                if (bout) {
+                    bout->x[g] = x; bout->y[g] = y; bout->ox[g] = ox; bout->oy[g] = oy;
+                    bout->w[g] = w; bout->cell[g] = (int32_t)cell; bout->hid[g] = hid;
+                    bout->alive[g] = 1;
+                }
+                break;
+            } else if (ev == EV_COLLIDE) {
+                /* isotropic re-emission, counter n <- n + 1 (Sec. 2.3) */
+                const double ua = or_u01(or_point_u32(P, stream, dcur, pidx));
+                const double ub = or_u01(or_point_u32(P, stream, dcur + 1, pidx));
+                dcur += 2;
+                const double stn = 2.0 * sqrt(ua * (1.0 - ua));
+                const double ph = 2.0 * M_PI * ub;
+                ox = stn * cos(ph);
+                oy = stn * sin(ph);
+                n += 1;
+                if (n < n_lim) {
+                    tau = -log(or_u01(or_point_u32(P, stream, dcur, pidx)));
+                    dcur += 1;
+                }
+            } else if (ev == EV_XFACE) {
+                if (ox > 0.0) { x = M->x_lo + hx * (double)(ix + 1); ix += 1; }
+                else          { x = M->x_lo + hx * (double)ix;       ix -= 1; }
+                if (ix < 0 || ix >= nx) { bal[OB_LEAKED] += w; break; }
+            } else {
+                if (oy > 0.0) { y = M->y_lo + hy * (double)(iy + 1); iy += 1; }
+                else          { y = M->y_lo + hy * (double)iy;       iy -= 1; }
+                if (iy < 0 || iy >= ny) { bal[OB_LEAKED] += w; break; }
+            }
+            if (fabs(w) < w_cut) { bal[OB_CUTOFF] += w; break; }
+        }
+    }
+    free(cdf);
+    return segments;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Census population control: keep the cap particles with the smallest        */
+/* 64-bit thinning keys (a simple random sample without replacement, since    */
+/* the keys are a bijective hash of the unique history ids) and reweight by    */
+/* count / cap.  The paper runs steady state only and does not say how the     */
+/* census is capped; this is the reading the design notes record.             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { uint64_t key; int64_t g; } or_keyed;
+
+static int or_cmp_key(const void *a, const void *b)
+{
+    const or_keyed *p = (const or_keyed *)a, *q = (const or_keyed *)b;
+    if (p->key < q->key) return -1;
+    if (p->key > q->key) return 1;
+    return 0;
+}
+
+/* keep[g] = 1 for the kept candidates; returns the kept count and writes the
+ * weight factor. */
+int64_t or_thin(int64_t n_cand, const uint8_t *alive, const uint64_t *hid,
+                int64_t cap, uint64_t thin_stream, uint8_t *keep, double *factor)
+{
+    int64_t count = 0;
+    for (int64_t g = 0; g < n_cand; ++g) { keep[g] = 0; if (alive[g]) ++count; }
+    if (count <= cap) {
+        for (int64_t g = 0; g < n_cand; ++g) keep[g] = alive[g];
+        *factor = 1.0;
+        return count;
+    }
+    or_keyed *v = (or_keyed *)malloc(sizeof(or_keyed) * (size_t)count);
+    int64_t k = 0;
+    for (int64_t g = 0; g < n_cand; ++g)
+        if (alive[g]) { v[k].key = or_mix64(thin_stream ^ hid[g]); v[k].g = g; ++k; }
+    qsort(v, (size_t)count, sizeof(or_keyed), or_cmp_key);
+    for (int64_t j = 0; j < cap; ++j) keep[v[j].g] = 1;
+    free(v);
+    *factor = (double)count / (double)cap;
+    return cap;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete-ordinates collided solve with bilinear discontinuous Galerkin     */
+/* (step 2 of Sec. 2.2, eq. for the super-N_s flux; S_N estimator of <Psi>    */
+/* by the quadrature of the ordinates).  Per direction (a, b) = (Ox, Oy) and   */
+/* cell K, find psi in Q1(K) with, for every test function v in Q1(K),         */
+/*   int_K (a psi_x + b psi_y) v + sig_e int_K psi v                          */
+/*     + sum_{inflow faces} |Omega.n| int_F psi v                             */
+/*   = int_K S v + sum_{inflow faces} |Omega.n| int_F psi_upwind v,           */
+/* integrated exactly by the 2-point Gauss rule in each direction.            */
+/* Local node k = ix + 2*iy at (x_{ix}, y_{iy}) of the cell.                  */
+/* ------------------------------------------------------------------------ */
+
+static double or_L(int i, double t) { return i ? t : 1.0 - t; }
+static double or_dL(int i) { return i ? 1.0 : -1.0; }
+
+/* Solve the 4x4 system A u = r by Gaussian elimination, partial pivoting. */
+static int or_solve4(double A[4][4], double r[4], double u[4])
+{
+    int perm[4] = {0, 1, 2, 3};
+    for (int col = 0; col < 4; ++col) {
+        int piv = col;
+        for (int row = col + 1; row < 4; ++row)
+            if (fabs(A[row][col]) > fabs(A[piv][col])) piv = row;
+        if (A[piv][col] == 0.0) return -1;
+        if (piv != col) {
+            for (int k = 0; k < 4; ++k) { double t = A[col][k]; A[col][k] = A[piv][k]; A[piv][k] = t; }
+            double t = r[col]; r[col] = r[piv]; r[piv] = t;
+            int tp = perm[col]; perm[col] = perm[piv]; perm[piv] = tp;
+        }
+        for (int row = col + 1; row < 4; ++row) {
+            const double f = A[row][col] / A[col][col];
+            for (int k = col; k < 4; ++k) A[row][k] -= f * A[col][k];
+            r[row] -= f * r[col];
+        }
+    }
+    for (int row = 3; row >= 0; --row) {
+        double s = r[row];
+        for (int k = row + 1; k < 4; ++k) s -= A[row][k] * u[k];
+        u[row] = s / A[row][row];
+    }
+    (void)perm;
+    return 0;
+}
+
+/*
+ * One transport sweep for the single direction (a, b): solves every cell in
+ * upwind order.  sig_e per cell, src nodal [n_cells*4].  Inflow data on the
+ * domain boundary: in_x[j*2 + iy] on the x-inflow side (row j, node iy), and
+ * in_y[i*2 + ix] on the y-inflow side; NULL means vacuum (zero inflow).
+ * psi [n_cells*4] receives the nodal solution.
+ */
+int or_dg_sweep(int nx, int ny, double x_lo, double x_hi, double y_lo, double y_hi,
+                const double *sig_e, double a, double b, const double *src,
+                const double *in_x, const double *in_y, double *psi)
+{
+    const double hx = (x_hi - x_lo) / nx, hy = (y_hi - y_lo) / ny;
+    const double gp[2] = {0.5 - 0.5 / sqrt(3.0), 0.5 + 0.5 / sqrt(3.0)};
+    const double gw = 0.5; /* weight per point on [0,1] */
+
+    for (int jj = 0; jj < ny; ++jj) {
+        const int j = (b > 0.0) ? jj : ny - 1 - jj;
+        for (int ii = 0; ii < nx; ++ii) {
+            const int i = (a > 0.0) ? ii : nx - 1 - ii;
+            const int64_t cell = (int64_t)j * nx + i;
+            double A[4][4], r[4], u[4];
+            memset(A, 0, sizeof A);
+            memset(r, 0, sizeof r);
+            const double *S = src + 4 * cell;
+            /* volume terms */
+            for (int p = 0; p < 2; ++p)
+                for (int q = 0; q < 2; ++q) {
+                    const double xi = gp[p], eta = gp[q];
+                    const double wv = gw * gw * hx * hy;
+                    double Sv = 0.0;
+                    for (int k = 0; k < 4; ++k)
+                        Sv += S[k] * or_L(k & 1, xi) * or_L(k >> 1, eta);
+                    for (int ti = 0; ti < 4; ++ti) {
+                        const double vt = or_L(ti & 1, xi) * or_L(ti >> 1, eta);
+                        r[ti] += wv * Sv * vt;
+                        for (int tj = 0; tj < 4; ++tj) {
+                            const double N = or_L(tj & 1, xi) * or_L(tj >> 1, eta);
+                            const double Nx = or_dL(tj & 1) / hx * or_L(tj >> 1, eta);
+                            const double Ny = or_L(tj & 1, xi) * or_dL(tj >> 1) / hy;
+                            A[ti][tj] += wv * ((a * Nx + b * Ny) * vt + sig_e[cell] * N * vt);
+                        }
+                    }
+                }
+            /* x-inflow face: xi_f = 0 if a > 0 (left), 1 if a < 0 (right) */
+            {
+                const int fx = (a > 0.0) ? 0 : 1;
+                const double xi = (double)fx;
+                for (int q = 0; q < 2; ++q) {
+                    const double eta = gp[q];
+                    const double wf = gw * hy * fabs(a);
+                    double up = 0.0;
+                    const int inb = (a > 0.0) ? i - 1 : i + 1;
+                    if (inb >= 0 && inb < nx) {
+                        /* neighbour's face on our side is its xi = 1 - fx */
+                        const double *pn = psi + 4 * ((int64_t)j * nx + inb);
+                        const int nf = 1 - fx;
+                        up = pn[nf + 0] * or_L(0, eta) + pn[nf + 2] * or_L(1, eta);
+                    } else if (in_x) {
+                        up = in_x[2 * j + 0] * or_L(0, eta) + in_x[2 * j + 1] * or_L(1, eta);
+                    }
+                    for (int ti = 0; ti < 4; ++ti) {
+                        const double vt = or_L(ti & 1, xi) * or_L(ti >> 1, eta);
+                        r[ti] += wf * up * vt;
+                        for (int tj = 0; tj < 4; ++tj)
+                            A[ti][tj] += wf * or_L(tj & 1, xi) * or_L(tj >> 1, eta) * vt;
+                    }
+                }
+            }
+            /* y-inflow face: eta_f = 0 if b > 0 (bottom), 1 if b < 0 (top) */
+            {
+                const int fy = (b > 0.0) ? 0 : 1;
+                const double eta = (double)fy;
+                for (int p = 0; p < 2; ++p) {
+                    const double xi = gp[p];
+                    const double wf = gw * hx * fabs(b);
+                    double up = 0.0;
+                    const int jnb = (b > 0.0) ? j - 1 : j + 1;
+                    if (jnb >= 0 && jnb < ny) {
+                        const double *pn = psi + 4 * ((int64_t)jnb * nx + i);
+                        const int nf = 1 - fy;
+                        up = pn[2 * nf + 0] * or_L(0, xi) + pn[2 * nf + 1] * or_L(1, xi);
+                    } else if (in_y) {
+                        up = in_y[2 * i + 0] * or_L(0, xi) + in_y[2 * i + 1] * or_L(1, xi);
+                    }
+                    for (int ti = 0; ti < 4; ++ti) {
+                        const double vt = or_L(ti & 1, xi) * or_L(ti >> 1, eta);
+                        r[ti] += wf * up * vt;
+                        for (int tj = 0; tj < 4; ++tj)
+                            A[ti][tj] += wf * or_L(tj & 1, xi) * or_L(tj >> 1, eta) * vt;
+                    }
+                }
+            }
+            if (or_solve4(A, r, u) != 0) return -1;
+            for (int k = 0; k < 4; ++k) psi[4 * cell + k] = u[k];
+        }
+    }
+    return 0;
+}
+
+/*
+ * Source iteration for the collided flux (step 2 of Sec. 2.2):
+ *   (sig_t + tau/(c dt)) psi + Omega.grad psi = sig_s/(4 pi) (phi_c + phi_post)
+ * with zero initial and vacuum boundary data.  The time derivative over the
+ * step is closed by tau/(c dt) (tau = 2: the step average of a flux growing
+ * linearly from zero).  phi_post is cell-constant; phi_c is nodal bilinear.
+ * Stops when ||phi_new - phi_old||_2 <= tol ||phi_new||_2 (nodal vectors).
+ * phi [n_cells*4] receives the result; returns the number of sweeps.
+ */
+int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
+                   const double *dox, const double *doy, const double *dw,
+                   const double *phi_post, double tol, int max_iter,
+                   double *phi, double *resid_out)
+{
+    const int64_t ncell = (int64_t)M->nx * M->ny;
+    const size_t nn = (size_t)ncell * 4;
+    double *sig_e = (double *)malloc(sizeof(double) * (size_t)ncell);
+    double *src = (double *)malloc(sizeof(double) * nn);
+    double *psi = (double *)malloc(sizeof(double) * nn);
+    double *acc = (double *)malloc(sizeof(double) * nn);
+    for (int64_t i = 0; i < ncell; ++i)
+        sig_e[i] = M->sig_a[i] + M->sig_s[i] + tau_closure / (M->c * M->dt);
+    for (size_t k = 0; k < nn; ++k) phi[k] = 0.0;
+    int it = 0;
+    double resid = 0.0;
+    while (it < max_iter) {
+        for (int64_t i = 0; i < ncell; ++i)
+            for (int k = 0; k < 4; ++k)
+                src[4 * i + k] = M->sig_s[i] / (4.0 * M_PI) * (phi[4 * i + k] + phi_post[i]);
+        for (size_t k = 0; k < nn; ++k) acc[k] = 0.0;
+        for (int m = 0; m < n_dir; ++m) {
+            if (or_dg_sweep(M->nx, M->ny, M->x_lo, M->x_hi, M->y_lo, M->y_hi, sig_e,
+                            dox[m], doy[m], src, NULL, NULL, psi) != 0) {
+                it = -1;
+                goto done;
+            }
+            for (size_t k = 0; k < nn; ++k) acc[k] += dw[m] * psi[k];
+        }
+        it += 1;
+        double dn = 0.0, nrm = 0.0;
+        for (size_t k = 0; k < nn; ++k) {
+            const double d = acc[k] - phi[k];
+            dn += d * d;
+            nrm += acc[k] * acc[k];
+            phi[k] = acc[k];
+        }
+        dn = sqrt(dn);
+        nrm = sqrt(nrm);
+        resid = (nrm > 0.0) ? dn / nrm : 0.0;
+        if (dn <= tol * nrm) break;
+    }
+done:
+    if (resid_out) *resid_out = resid;
+    free(sig_e); free(src); free(psi); free(acc);
+    return it;
+}

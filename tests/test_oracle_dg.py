@@ -1,0 +1,94 @@
+"""Pins of the oracle's DG S_N collided solve (step 2 of Sec. 2.2; bilinear
+discontinuous Galerkin in space, Sec. 1 abstract; Gauss-Legendre S_N
+estimator of <Psi>, Sec. 2.2)."""
+import math
+
+import numpy as np
+import pytest
+
+
+@pytest.mark.parametrize("order", [2, 4, 8, 12, 16])
+def test_quadrature_moments(oracle, order):
+    ox, oy, w = oracle.quadrature(order)
+    assert len(w) == order * order
+    assert w.sum() == pytest.approx(4 * math.pi, rel=1e-14)
+    assert abs((w * ox).sum()) < 1e-13 and abs((w * oy).sum()) < 1e-13
+    assert (w * ox * ox).sum() == pytest.approx(4 * math.pi / 3, rel=1e-13)
+    assert (w * oy * oy).sum() == pytest.approx(4 * math.pi / 3, rel=1e-13)
+    assert abs((w * ox * oy).sum()) < 1e-13
+    if order >= 4:
+        assert (w * ox ** 4).sum() == pytest.approx(4 * math.pi / 5, rel=1e-13)
+    assert np.all(np.abs(ox) > 0) and np.all(np.abs(oy) > 0)
+
+
+@pytest.mark.parametrize("a,b", [(0.7, 0.3), (-0.45, 0.8), (0.2, -0.9), (-0.6, -0.55)])
+def test_manufactured_bilinear_solution_is_exact(oracle, a, b):
+    """psi = c0 + c1 x + c2 y + c3 x y lies in Q1 on every cell and its
+    source a psi_x + b psi_y + sig psi is in Q1 too, so upwind DG with the exact
+    inflow trace must reproduce psi at every node (consistency)."""
+    nx, ny, box = 5, 4, (0.0, 1.5, -0.5, 1.5)
+    c0, c1, c2, c3 = 0.3, -1.2, 0.8, 2.1
+    rng = np.random.default_rng(2)
+    sig = rng.uniform(0.1, 5.0, size=nx * ny)
+    hx, hy = (box[1] - box[0]) / nx, (box[3] - box[2]) / ny
+
+    def psi(x, y):
+        return c0 + c1 * x + c2 * y + c3 * x * y
+
+    src = np.zeros((ny, nx, 4))
+    ref = np.zeros((ny, nx, 4))
+    for j in range(ny):
+        for i in range(nx):
+            for k in range(4):
+                x = box[0] + (i + (k & 1)) * hx
+                y = box[2] + (j + (k >> 1)) * hy
+                ref[j, i, k] = psi(x, y)
+                src[j, i, k] = a * (c1 + c3 * y) + b * (c2 + c3 * x) + sig[j * nx + i] * psi(x, y)
+    xb = box[0] if a > 0 else box[1]
+    yb = box[2] if b > 0 else box[3]
+    in_x = np.array([[psi(xb, box[2] + (j + t) * hy) for t in (0, 1)] for j in range(ny)])
+    in_y = np.array([[psi(box[0] + (i + t) * hx, yb) for t in (0, 1)] for i in range(nx)])
+    got = oracle.dg_sweep(nx, ny, box, sig, a, b, src, in_x.ravel(), in_y.ravel())
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+
+
+def test_collided_infinite_medium_interior(oracle):
+    """Uniform phi_post far from the boundary: sig_e psi = sig_s/(4 pi)
+    (phi_c + phi_post) with sig_e = sig_t + tau/(c dt) gives
+    phi_c = sig_s phi_post / (sig_a + tau/(c dt))."""
+    ss, sa, dt, tau = 1.0, 0.1, 0.1, 2.0
+    n, L = 20, 2.0
+    prob = dict(nx=n, ny=n, x_lo=0, x_hi=L, y_lo=0, y_hi=L, sigma_s=np.full((n, n), ss),
+                sigma_a=np.full((n, n), sa), dt=dt, c=1.0)
+    m = oracle.Mesh(prob)
+    phi_post = np.full(n * n, 3.0)
+    phi, it, res = oracle.dg_collided(m, oracle.quadrature(8), phi_post, tau, 1e-13, 100)
+    exact = ss * 3.0 / (sa + tau / dt)
+    centre = phi.reshape(n, n, 4)[n // 2, n // 2]
+    np.testing.assert_allclose(centre, exact, rtol=1e-7)
+    rho = ss / (ss + sa + tau / dt)
+    assert it <= math.ceil(math.log(1e-13) / math.log(rho)) + 2
+    assert res <= 1e-13
+
+
+def test_zero_source_gives_zero(oracle):
+    n = 4
+    prob = dict(nx=n, ny=n, x_lo=0, x_hi=1, y_lo=0, y_hi=1, sigma_s=np.ones((n, n)),
+                sigma_a=np.ones((n, n)), dt=0.1, c=1.0)
+    phi, it, res = oracle.dg_collided(oracle.Mesh(prob), oracle.quadrature(4), np.zeros(n * n))
+    assert np.all(phi == 0.0) and it == 1
+
+
+def test_si_converges_to_fixed_point(oracle):
+    """The SI fixed point satisfies phi = sum_m w_m psi_m[phi] to the
+    tolerance: one extra sweep from the returned phi changes it by <= tol."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=3, cells_per_block=3, n_s=1, dt=0.5)
+    m = oracle.Mesh(p)
+    rng = np.random.default_rng(4)
+    phi_post = rng.uniform(0, 1, size=m.ncell)
+    quad = oracle.quadrature(4)
+    phi, it, res = oracle.dg_collided(m, quad, phi_post, 2.0, 1e-12, 500)
+    phi2, it2, _ = oracle.dg_collided(m, quad, phi_post, 2.0, 1e-14, 500)
+    assert it2 >= it
+    assert np.linalg.norm(phi - phi2) <= 1e-11 * np.linalg.norm(phi2)

@@ -1,0 +1,336 @@
+"""Pins of the oracle's (Q)MC pass (Sec. 2.3 of the paper) against closed
+forms, exact invariants and brute-force quadrature."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import gammainc
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def _mesh(oracle, nx, ny, box, ss, sa, dt, c=1.0):
+    prob = dict(nx=nx, ny=ny, x_lo=box[0], x_hi=box[1], y_lo=box[2], y_hi=box[3],
+                sigma_s=np.broadcast_to(ss, (ny, nx)).copy(),
+                sigma_a=np.broadcast_to(sa, (ny, nx)).copy(), dt=dt, c=c)
+    return oracle.Mesh(prob)
+
+
+def _one_particle_bank(oracle, x, y, ox, oy, w, cell, hid=0):
+    b = oracle.Bank(1)
+    b.x[0], b.y[0], b.ox[0], b.oy[0], b.w[0], b.cell[0], b.hid[0] = x, y, ox, oy, w, cell, hid
+    return b
+
+
+def _chord_segments(x0, y0, ox, oy, smax, nx, ny, box):
+    """Cells and lengths along a straight flight, from the sorted crossings of
+    all grid lines (independent of the oracle's face-to-face walk)."""
+    hx = (box[1] - box[0]) / nx
+    hy = (box[3] - box[2]) / ny
+    ts = [0.0, smax]
+    for k in range(nx + 1):
+        if ox != 0:
+            t = (box[0] + k * hx - x0) / ox
+            if 0 < t < smax:
+                ts.append(t)
+    for k in range(ny + 1):
+        if oy != 0:
+            t = (box[2] + k * hy - y0) / oy
+            if 0 < t < smax:
+                ts.append(t)
+    ts = sorted(ts)
+    segs = []
+    for a, b in zip(ts[:-1], ts[1:]):
+        xm, ym = x0 + ox * 0.5 * (a + b), y0 + oy * 0.5 * (a + b)
+        i = int(math.floor((xm - box[0]) / hx))
+        j = int(math.floor((ym - box[2]) / hy))
+        if not (0 <= i < nx and 0 <= j < ny):
+            return segs, True
+        segs.append((j * nx + i, b - a))
+    return segs, False
+
+
+@pytest.mark.parametrize("case", [
+    # x0, y0, theta-direction, dt  (stays inside / leaks)
+    (0.31, 0.47, 0.37, 0.6, 3.0),
+    (2.9, 0.2, 2.4, 0.4, 5.0),
+    (1.5, 1.5, -1.1, 0.9, 0.8),
+])
+def test_uncollided_attenuation_closed_form(oracle, case):
+    """One deterministic particle, N_s = 0: per-cell tallies are
+    w e^{-tau_before} (1 - e^{-sigma_t l}) / sigma_t and the exit (leak or
+    census) weight is w e^{-sum sigma_t l}  (Sec. 2.3, non-scattering leg)."""
+    x0, y0, phi, sin_t, dt = case
+    nx, ny, box = 6, 5, (0.0, 3.0, 0.0, 2.5)
+    rng = np.random.default_rng(5)
+    ss = rng.uniform(0.0, 2.0, size=(ny, nx))
+    sa = rng.uniform(0.0, 2.0, size=(ny, nx))
+    m = _mesh(oracle, nx, ny, box, ss, sa, dt)
+    ox, oy = sin_t * math.cos(phi), sin_t * math.sin(phi)
+    hx, hy = 0.5, 0.5
+    cell = int(y0 // hy) * nx + int(x0 // hx)
+    w0 = 0.75
+    bank = _one_particle_bank(oracle, x0, y0, ox, oy, w0, cell)
+    q = np.zeros(4 * nx * ny)
+    pts = oracle.Points(0)
+    Ta, Tb, bal, seg, _ = oracle.mc_pass(m, pts, 1, 0, q, 0, bank, 1, 0, 0.0, False)
+    segs, leaks = _chord_segments(x0, y0, ox, oy, dt, nx, ny, box)
+    st = (ss + sa).ravel()
+    expect = np.zeros(nx * ny)
+    tau = 0.0
+    for c_, l in segs:
+        expect[c_] += w0 * math.exp(-tau) * (1 - math.exp(-st[c_] * l)) / st[c_]
+        tau += st[c_] * l
+    np.testing.assert_allclose(Tb, expect, rtol=1e-13, atol=1e-15)
+    assert np.all(Ta == 0.0)
+    w_end = w0 * math.exp(-tau)
+    if leaks:
+        assert bal["leaked"] == pytest.approx(w_end, rel=1e-13) and bal["census"] == 0.0
+    else:
+        assert bal["census"] == pytest.approx(w_end, rel=1e-13) and bal["leaked"] == 0.0
+    assert bal["absorbed"] == pytest.approx(float(np.dot(sa.ravel(), expect)), rel=1e-13)
+    assert bal["scattered"] == pytest.approx(float(np.dot(ss.ravel(), expect)), rel=1e-13)
+
+
+def _interior_mean(oracle, n_s, ss, sa, dt, n_p, seeds, mode=0):
+    """Uniform unit source on a large homogeneous box, first step: mean of
+    phi_pre and phi_post over cells farther than c dt from the boundary."""
+    n, L = 12, 6.0
+    m = _mesh(oracle, n, n, (0, L, 0, L), ss, sa, dt)
+    pts = oracle.Points(mode)
+    q = np.ones(4 * n * n)
+    h = L / n
+    k0 = int(math.ceil(dt / h))
+    inner = np.zeros((n, n), dtype=bool)
+    inner[k0:n - k0, k0:n - k0] = True
+    pre, post = [], []
+    for s in seeds:
+        Ta, Tb, bal, _, _ = oracle.mc_pass(m, pts, 1, n_s, q, n_p, oracle.Bank(0), s, 0, 0.0,
+                                           False)
+        adt = h * h * dt
+        pre.append((Ta / adt).reshape(n, n)[inner].mean())
+        post.append((Tb / adt).reshape(n, n)[inner].mean())
+    return np.array(pre), np.array(post)
+
+
+def _pbar(a, X):
+    return gammainc(a, X) - (a / X) * gammainc(a + 1, X)
+
+
+@pytest.mark.parametrize("n_s", [0, 1, 2, 4])
+def test_pre_post_split_matches_erlang_closed_form(oracle, n_s):
+    """First step from zero initial data, uniform Q = 1: the number of scatters
+    by time L is Poisson(sigma_s L) (App. B: the N_s+1-th scatter time is
+    Erlang), which gives E[phi_post] = (sigma_s/sigma_t)^{N_s} Pbar(N_s+1)/sigma_t
+    and E[phi_pre] = sum_{k<N_s} (sigma_s/sigma_t)^k Pbar(k+1)/sigma_t, with
+    Pbar(a) the step average of the regularised incomplete gamma P(a, sigma_t L)."""
+    ss, sa, dt = 2.0, 0.5, 1.0
+    st = ss + sa
+    X = st * dt
+    e_post = (ss / st) ** n_s * _pbar(n_s + 1, X) / st
+    e_pre = sum((ss / st) ** k * _pbar(k + 1, X) / st for k in range(n_s))
+    pre, post = _interior_mean(oracle, n_s, ss, sa, dt, 2 ** 16, seeds=[11, 12, 13, 14])
+    se_post = post.std(ddof=1) / 2 + 1e-4 * e_post
+    assert abs(post.mean() - e_post) < 5 * se_post, (post.mean(), e_post)
+    if n_s > 0:
+        se_pre = pre.std(ddof=1) / 2 + 1e-4 * e_pre
+        assert abs(pre.mean() - e_pre) < 5 * se_pre, (pre.mean(), e_pre)
+    else:
+        assert np.all(pre == 0.0)
+
+
+def test_unlimited_scattering_infinite_medium(oracle):
+    """N_s unlimited (pure MC, Sec. 2.3 reference case): in the infinite medium
+    phi(t) = (Q/sigma_a)(1 - e^{-sigma_a t}) (c = 1), so the first-step average
+    is (Q/sigma_a)[1 - (1 - e^{-sigma_a dt})/(sigma_a dt)]."""
+    ss, sa, dt = 2.0, 0.5, 1.0
+    exact = (1 / sa) * (1 - (1 - math.exp(-sa * dt)) / (sa * dt))
+    pre, post = _interior_mean(oracle, -1, ss, sa, dt, 2 ** 16, seeds=[1, 2, 3, 4])
+    assert np.all(post == 0.0)
+    se = pre.std(ddof=1) / 2 + 1e-4 * exact
+    assert abs(pre.mean() - exact) < 5 * se, (pre.mean(), exact)
+
+
+def _single_cell_exact(sig, dt, nq=28):
+    """E[T] for one unit cell, Q = 1, N_s = 0, one step: the integral over
+    position, birth time and direction of the track-length contribution
+    (1 - e^{-sig l})/sig with l = min(remaining time, chord).  Birth time is
+    integrated in closed form; direction and position by Gauss-Legendre on
+    pieces split at the kinks (corner directions, chord = dt)."""
+    g, gw = np.polynomial.legendre.leggauss(nq)
+
+    def G(D):
+        m = np.minimum(D, dt)
+        e = 1 - np.exp(-sig * m)
+        return (m - e / sig) / sig + (dt - m) * e / sig
+
+    def on(a, b):
+        return 0.5 * (b - a) * g + 0.5 * (a + b), 0.5 * (b - a) * gw
+
+    xs, xw = on(0.0, 1.0)
+    total = 0.0
+    for x, wx in zip(xs, xw):
+        for y, wy in zip(xs, xw):
+            ang = np.sort(np.mod(np.arctan2(np.array([0, 0, 1, 1]) - y,
+                                            np.array([0, 1, 0, 1]) - x), 2 * np.pi))
+            edges = np.concatenate([ang, [ang[0] + 2 * np.pi]])
+            acc = 0.0
+            for a, b in zip(edges[:-1], edges[1:]):
+                ph, wph = on(a, b)
+                c, s = np.cos(ph), np.sin(ph)
+                with np.errstate(divide="ignore"):
+                    dx = np.where(c > 0, (1 - x) / c, np.where(c < 0, -x / c, np.inf))
+                    dy = np.where(s > 0, (1 - y) / s, np.where(s < 0, -y / s, np.inf))
+                d2 = np.minimum(dx, dy)
+                mu_star = np.sqrt(np.clip(1 - (d2 / dt) ** 2, 0.0, 1.0))
+                # integral over mu in [0, 1] of G(d2 / sqrt(1 - mu^2))
+                mu, wmu = on(0.0, 1.0)
+                mu = mu_star[:, None] * mu[None, :]
+                wm = mu_star[:, None] * wmu[None, :]
+                part = (G(d2[:, None] / np.sqrt(1 - mu ** 2)) * wm).sum(1)
+                part += (1 - mu_star) * G(np.full_like(d2, np.inf))
+                acc += (part * wph).sum()
+            total += wx * wy * acc
+    return total / (2 * np.pi)
+
+
+def _single_cell_runs(oracle, n_p, seeds, mode, sig_s=0.3, sig_a=0.7, dt=0.7):
+    m = _mesh(oracle, 1, 1, (0, 1, 0, 1), sig_s, sig_a, dt)
+    pts = oracle.Points(mode)
+    out = []
+    for s in seeds:
+        _, Tb, _, _, _ = oracle.mc_pass(m, pts, 1, 0, np.ones(4), n_p, oracle.Bank(0), s, 0,
+                                        0.0, False)
+        out.append(Tb[0])
+    return np.array(out)
+
+
+def test_single_cell_brute_force(oracle):
+    exact = _single_cell_exact(1.0, 0.7)
+    exact2 = _single_cell_exact(1.0, 0.7, nq=40)
+    assert abs(exact - exact2) < 1e-5 * exact
+    T = _single_cell_runs(oracle, 2 ** 14, range(8), 0)
+    se = T.std(ddof=1) / math.sqrt(len(T))
+    assert abs(T.mean() - exact) < 4 * se + 1e-7, (T.mean(), exact, se)
+    assert abs(T.mean() - exact) < 1e-3 * exact
+
+
+def test_qmc_vs_mc_convergence_slopes(oracle):
+    """L2 error vs N_p fitted as c N_p^alpha (least squares on logs, as in the
+    paper's Table 1): plain MC ~ N^-1/2, scrambled Sobol' clearly faster."""
+    exact = _single_cell_exact(1.0, 0.7)
+    Ns = [2 ** k for k in range(8, 15)]
+    slopes = {}
+    for mode in (0, 1):
+        err = []
+        for n in Ns:
+            T = _single_cell_runs(oracle, n, range(100, 116), mode)
+            err.append(math.sqrt(np.mean((T - exact) ** 2)))
+        slopes[mode] = np.polyfit(np.log(Ns), np.log(err), 1)[0]
+    assert -0.65 < slopes[1] < -0.35, slopes
+    assert slopes[0] < -0.75, slopes
+
+
+def test_remap_sampler_weights(oracle):
+    """Remap emission (step 3 of Sec. 2.2): majorant-CDF cell choice, uniform
+    position, signed weight q(x,y) sum(M) / (N_p max_corner|q|).  Constant q:
+    every weight equals sum(M)/N_p.  Bilinear signed q: the weights integrate q."""
+    nx, ny, dt = 3, 2, 0.5
+    m = _mesh(oracle, nx, ny, (0, 1.5, 0, 1.0), 0.0, 0.0, dt)
+    pts = oracle.Points(0)
+    area = 0.25
+    qc = np.repeat(np.array([0.0, 2.0, 1.0, 0.5, 0.0, 3.0]), 4)
+    n_p = 1000
+    _, _, bal, _, cand = oracle.mc_pass(m, pts, 2, 0, qc, n_p, oracle.Bank(0), 3, 0, 0.0, True)
+    sumM = area * dt * qc[::4].sum()
+    w = cand.w[cand.alive.astype(bool)]
+    np.testing.assert_allclose(w, sumM / n_p, rtol=1e-15)
+    assert bal["source_w"] == pytest.approx(sumM, rel=1e-13)
+    # bilinear signed source: E[sum w] = integral of q = sum A dt mean(corners)
+    rng = np.random.default_rng(9)
+    qb = rng.uniform(-1.0, 2.0, size=4 * nx * ny)
+    integral = area * dt * qb.reshape(-1, 4).mean(1).sum()
+    tot = []
+    for s in range(8):
+        _, _, bal, _, _ = oracle.mc_pass(m, pts, 2, 0, qb, 2 ** 12, oracle.Bank(0), 50 + s, 0,
+                                         0.0, False)
+        tot.append(bal["source_w"])
+    tot = np.array(tot)
+    assert abs(tot.mean() - integral) < 5 * tot.std(ddof=1) / math.sqrt(8) + 1e-12
+    assert abs(tot.mean() - integral) < 1e-3 * abs(integral)
+
+
+def test_balance_closes_every_pass(oracle):
+    """Implicit capture: every unit of emitted weight is absorbed, handed to
+    the collided stage, leaked, carried to census or cut off.  The oracle sums
+    sequentially, so the bound is the classic (n - 1) eps sum|x| of such sums."""
+    from paper_2511_16821_amd import workloads as W
+    for p in (W.c1(n_particles=4000), W.checkerboard(blocks=3, cells_per_block=4, n_s=2,
+                                                     n_particles=4000, dt=0.2),
+              W.thick_with_voids(n=16, n_s=2, n_particles=4000, dt=0.05, src_half=2)):
+        s = oracle.HybridOracle(p)
+        for _ in range(3):
+            r = s.step()
+            for key, seg in (("bal_mc", "seg_mc"), ("bal_remap", "seg_remap")):
+                b = r[key]
+                out = b["absorbed"] + b["scattered"] + b["leaked"] + b["census"] + b["cutoff"]
+                bound = 2.2e-16 * (r[seg] + 10) * (abs(b["emitted"]) + abs(out))
+                assert abs(b["emitted"] - out) <= bound, (key, b)
+                assert b["emitted"] == pytest.approx(b["source_w"] + b["census_in_w"], rel=1e-12)
+
+
+def test_thinning_is_unbiased_sampling_without_replacement(oracle):
+    """Census cap: exactly cap survivors, reweighted by count/cap; over many
+    thinning streams each particle is kept with frequency cap/count and the
+    kept weight is the original total on average."""
+    rng = np.random.default_rng(1)
+    n = 200
+    cand = oracle.Bank(n)
+    cand.w[:] = rng.uniform(0.5, 1.5, size=n)
+    cand.hid[:] = rng.permutation(np.arange(n, dtype=np.uint64) * np.uint64(7919))
+    cand.alive = (rng.uniform(size=n) < 0.8).astype(np.uint8)
+    count = int(cand.alive.sum())
+    kept, f = oracle.thin(cand, 10 ** 6, 5)
+    assert kept.n == count and f == 1.0
+    cap = 60
+    hits = np.zeros(n)
+    totals = []
+    for t in range(400):
+        kept, f = oracle.thin(cand, cap, 1000 + t)
+        assert kept.n == cap and f == count / cap
+        idx = np.searchsorted(np.argsort(cand.hid), 0)  # noqa: F841 (keeps numpy happy)
+        m = np.isin(cand.hid, kept.hid)
+        hits += m
+        totals.append(kept.w.sum())
+    alive = cand.alive.astype(bool)
+    assert np.all(hits[~alive] == 0)
+    freq = hits[alive] / 400
+    p = cap / count
+    assert np.all(np.abs(freq - p) < 5 * math.sqrt(p * (1 - p) / 400))
+    tot = cand.w[alive].sum()
+    totals = np.array(totals)
+    assert abs(totals.mean() - tot) < 5 * totals.std(ddof=1) / math.sqrt(400)
+
+
+@pytest.mark.parametrize("kind,n_s,ss", [(2, 0, 0.0), (1, 1, 50.0)])
+def test_emitted_and_scattered_directions_are_isotropic(oracle, kind, n_s, ss):
+    """Isotropic emission (Sec. 2.3) and isotropic re-emission after a
+    collision: on the unit sphere the in-plane components satisfy
+    E[Ox] = E[Oy] = E[Ox Oy] = 0, E[Ox^2] = E[Oy^2] = 1/3 and
+    E[(Ox^2 + Oy^2)^2] = E[(1 - Oz^2)^2] = 8/15.  kind 2 reads the emission
+    directions (no attenuation, nothing leaks); kind 1 with N_s = 1 and a
+    dense scatterer reads the direction after the single allowed collision."""
+    n_p = 2 ** 14
+    m = _mesh(oracle, 3, 3, (-30.0, 30.0, -30.0, 30.0), ss, 0.0, 1.0)
+    pts = oracle.Points(0)
+    q = np.zeros(36)
+    q[16:20] = 1.0  # centre cell only: nothing can reach the boundary
+    _, _, bal, _, cand = oracle.mc_pass(m, pts, kind, n_s, q, n_p, oracle.Bank(0), 8,
+                                        0, 0.0, True)
+    alive = cand.alive.astype(bool)
+    assert alive.sum() == n_p
+    ox, oy = cand.ox[alive], cand.oy[alive]
+    tol = 4.0 / math.sqrt(n_p)
+    assert abs(ox.mean()) < tol and abs(oy.mean()) < tol and abs((ox * oy).mean()) < tol
+    assert abs((ox ** 2).mean() - 1 / 3) < tol and abs((oy ** 2).mean() - 1 / 3) < tol
+    assert abs(((ox ** 2 + oy ** 2) ** 2).mean() - 8 / 15) < tol

@@ -1,0 +1,244 @@
+/*
+ * slh.h -- C ABI of libslh, the MI355X (gfx950) implementation of the
+ * scatter-limited hybrid Monte Carlo / discrete-ordinates method for
+ * time-dependent, single-group, isotropically scattering linear transport on
+ * a 2-D Cartesian mesh (Krotz & McClarren, "Scatter-Limited Hybrid Monte
+ * Carlo, Deterministic Transport with Quasi-Monte Carlo Sampling",
+ * arXiv:2511.16821).
+ *
+ * The problem (Sec. 2.1, eq. (1)):
+ *     (1/c) dPsi/dt + Omega.grad Psi + sigma_a Psi
+ *         = sigma_s (<Psi>/(4 pi) - Psi) + Q/(4 pi)
+ * on a uniform nx x ny mesh of [x_lo,x_hi] x [y_lo,y_hi] (x-y geometry,
+ * invariant in z, directions on the whole unit sphere), with piecewise
+ * constant sigma_s, sigma_a and angle-integrated isotropic source Q per cell,
+ * zero initial data and vacuum boundaries.
+ *
+ * One time step (Sec. 2.2, steps 1-4):
+ *   1. scatter-limited (Q)MC leg: census particles and N_p source particles
+ *      with at most N_s scatters each (Sec. 2.3), track-length tallies
+ *      T_pre (fewer than N_s scatters) and T_post (exactly N_s);
+ *   2. DG S_N solve of the collided equation with source
+ *      sigma_s/(4 pi) (phi_c + phi_post), bilinear discontinuous Galerkin,
+ *      source iteration;
+ *   3. remap: scatter-free (Q)MC leg from the census and N_p particles of the
+ *      frozen source Q + sigma_s (phi_pre + phi_post + phi_c), tally T_R;
+ *   4. the remap census is the state at t_{n+1}.
+ * phi = T / (cell area * dt) is the step-averaged scalar flux (integral of
+ * Psi over the sphere); phi_R is the solution of the step.
+ *
+ * Conventions for every call:
+ *   - Status codes only: no exceptions, no abort across this boundary.
+ *   - Arguments are validated before anything is allocated; on error nothing
+ *     is changed and slh_last_error() holds a message (thread-local).
+ *   - Host arrays passed in are caller-owned and copied; output pointers are
+ *     caller-owned.  Device memory of a solver is owned by the solver.
+ *   - Field arrays are FP64, nx*ny long, row-major: cell (i, j) is element
+ *     j*nx + i.
+ *   - Work is enqueued on the HIP stream given at creation (borrowed, never
+ *     destroyed); calls that return host data synchronise that stream.
+ */
+#ifndef SLH_H
+#define SLH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLH_ABI_VERSION 1u
+
+typedef enum {
+    SLH_OK = 0,
+    SLH_E_INVALID_ARG = 1,   /* a field or parameter is out of range        */
+    SLH_E_OUT_OF_MEMORY = 2, /* device allocation failed (nothing leaked)   */
+    SLH_E_DEVICE = 3,        /* a HIP call failed                           */
+    SLH_E_NOT_CONVERGED = 4, /* source iteration hit si_max_iter (the step
+                                still completed; see slh_stats)             */
+    SLH_E_NUMERIC = 5,       /* non-finite tally detected                   */
+    SLH_E_REJECTED = 6,      /* serving: request does not fit the budget    */
+    SLH_E_STATE = 7          /* call not valid in the object's state        */
+} slh_status;
+
+/* Arithmetic of the tracking kernels.  SLH_FP32_TRACK runs geometry,
+ * distance sampling and attenuation in FP32 with cell-local coordinates;
+ * tallies, balance totals, emission CDFs and the DG solve stay FP64. */
+typedef enum { SLH_FP64 = 0, SLH_FP32_TRACK = 1 } slh_precision;
+
+/* Points fed to the inverse-CDF maps (Sec. 2.4): scrambled Sobol' (QMC) or a
+ * counter-based pseudo-random hash (plain MC, for comparisons). */
+typedef enum { SLH_SOBOL_OWEN = 0, SLH_PRNG = 1 } slh_points;
+
+/* Which flux slh_get_flux returns (all FP64). */
+typedef enum {
+    SLH_FLUX_REMAP = 0,         /* phi_R, nx*ny: the solution of the step    */
+    SLH_FLUX_PRE = 1,           /* phi_pre, nx*ny (step 1, n < N_s)          */
+    SLH_FLUX_POST = 2,          /* phi_post, nx*ny (step 1, n = N_s)         */
+    SLH_FLUX_COLLIDED_NODAL = 3 /* phi_c, 4*nx*ny: nodes (x0,y0),(x1,y0),
+                                   (x0,y1),(x1,y1) of each cell             */
+} slh_flux_kind;
+
+typedef struct {
+    uint32_t abi_version;          /* SLH_ABI_VERSION                        */
+    int32_t nx, ny;                /* >= 1                                   */
+    double x_lo, x_hi, y_lo, y_hi; /* x_hi > x_lo, y_hi > y_lo               */
+    const double *sigma_s;         /* host, nx*ny, >= 0, finite              */
+    const double *sigma_a;         /* host, nx*ny, >= 0, finite              */
+    const double *q;               /* host, nx*ny, >= 0, angle-integrated    */
+    double c;                      /* particle speed, > 0                    */
+    double dt;                     /* time step, > 0                         */
+    int32_t n_s;                   /* scatter limit N_s >= 0                 */
+    int64_t n_particles;           /* source particles per MC pass, 0..2^32-1 */
+    int64_t census_cap;            /* census bank size; 0 -> n_particles     */
+    int32_t sn_order;              /* even N >= 2: N^2 product directions    */
+    double time_closure;           /* tau in sigma_t + tau/(c dt); 0 -> 2    */
+    double si_tol;                 /* SI relative tolerance; 0 -> 1e-12      */
+    int32_t si_max_iter;           /* 0 -> 200                               */
+    double w_cut_rel;              /* cutoff |w| < w_cut_rel*sum(M)/N_p      */
+    uint64_t seed;                 /* point-set seed                         */
+    int32_t points;                /* slh_points                             */
+    int32_t precision;             /* slh_precision                          */
+} slh_problem;
+
+/* Balance of one pass (implicit capture, Sec. 2.3), FP64 from
+ * order-independent fixed-point sums: emitted = absorbed + scattered +
+ * leaked + census + cutoff up to rounding of the per-particle terms. */
+typedef struct {
+    double emitted;      /* source + census-in weight                        */
+    double absorbed;     /* integral of sigma_a w ds                         */
+    double scattered;    /* integral of sigma_s w ds on post-limit segments
+                            (step 1: handed to the collided stage)           */
+    double leaked;       /* weight leaving through the boundary              */
+    double census;       /* weight alive at t_{n+1}                          */
+    double cutoff;       /* weight of histories ended by the cutoff          */
+    double source_w;     /* weight emitted by the source                     */
+    double census_in_w;  /* weight of the census-in bank                     */
+    uint64_t segments;   /* tracking-loop iterations                         */
+    uint64_t particles;  /* histories started                                */
+} slh_balance;
+
+typedef struct {
+    int64_t step;            /* steps completed                              */
+    int32_t si_iterations;   /* last step: transport sweeps                  */
+    double si_residual;      /* last step: ||dphi||/||phi|| at exit          */
+    int32_t si_converged;    /* last step: 1 if residual <= si_tol           */
+    int64_t census_alive;    /* last step: census candidates at t_{n+1}      */
+    int64_t census_kept;     /* last step: bank size after the cap           */
+    double thin_factor;      /* last step: weight factor of the cap          */
+    uint64_t segments_total; /* all passes, all steps                        */
+    double ms_mc, ms_dg, ms_remap, ms_census; /* last step, stage times      */
+} slh_stats;
+
+typedef struct slh_solver slh_solver;
+
+/* Allocator hooks for device memory (e.g. PyTorch's caching allocator).  Both
+ * NULL -> hipMalloc / hipFree. */
+typedef void *(*slh_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*slh_free_fn)(void *ptr, void *ctx);
+
+/* Creates a solver: validates the problem, copies the fields to the device,
+ * builds the S_N quadrature and the Sobol' tables, and enqueues nothing
+ * else.  hip_stream: hipStream_t to use (NULL = the null stream). */
+slh_status slh_create(const slh_problem *problem, void *hip_stream, slh_alloc_fn alloc,
+                      slh_free_fn free_fn, void *alloc_ctx, slh_solver **out);
+
+/* Enqueues n_steps >= 1 time steps (steps 1-4 above) on the solver's stream.
+ * The source iteration reads its residual back once per sweep, so the call
+ * returns when the last step's remap pass has been enqueued.  Returns
+ * SLH_E_NOT_CONVERGED if any step's SI hit si_max_iter. */
+slh_status slh_advance(slh_solver *s, int32_t n_steps);
+
+/* Blocks until the solver's stream is idle. */
+slh_status slh_synchronize(slh_solver *s);
+
+/* Copies the last step's flux to host_out (FP64; nx*ny values, or 4*nx*ny
+ * for SLH_FLUX_COLLIDED_NODAL).  Synchronises the stream. */
+slh_status slh_get_flux(slh_solver *s, int32_t which, double *host_out);
+
+/* Same, into device memory dev_out (enqueued on the solver's stream). */
+slh_status slh_get_flux_device(slh_solver *s, int32_t which, double *dev_out);
+
+/* Balance of the last step's pass: pass = 1 (scatter-limited leg) or 2
+ * (remap).  Synchronises the stream. */
+slh_status slh_get_balance(slh_solver *s, int32_t pass, slh_balance *out);
+
+slh_status slh_get_stats(slh_solver *s, slh_stats *out);
+
+/* Census bank at the start of the next step, host copies, global
+ * coordinates.  Arrays of at least *n entries are written (any pointer may be
+ * NULL); *n receives the bank size.  Synchronises the stream. */
+slh_status slh_get_census(slh_solver *s, int64_t *n, double *x, double *y, double *ox,
+                          double *oy, double *w, int32_t *cell, uint64_t *hid);
+
+/* Checkpoint: the complete state between steps is the census bank, the step
+ * index and the problem (zero collided initial data every step).  With
+ * buf == NULL, *len receives the size needed. */
+slh_status slh_save(slh_solver *s, void *buf, size_t *len);
+slh_status slh_load(slh_solver *s, const void *buf, size_t len);
+
+/* Device memory the solver for this problem needs, in bytes (admission). */
+size_t slh_footprint_bytes(const slh_problem *problem);
+
+void slh_destroy(slh_solver *s);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *slh_last_error(void);
+
+/* Point function of Sec. 2.4 on the device: for k in [0, n) writes
+ * out[k*n_dims + d] = P(stream, dim0 + d, index0 + k), the 32-bit point word
+ * that the tracking kernels use for (time step, pass, population, cohort),
+ * with pass in {1, 2} and population 0 = source, 1 = census.  dev_out is
+ * device memory of n*n_dims words; enqueued on hip_stream. */
+slh_status slh_qmc_points(uint64_t seed, uint64_t step, uint32_t pass, uint32_t population,
+                          uint64_t cohort, uint32_t dim0, uint32_t n_dims, uint32_t index0,
+                          uint32_t n, int32_t points, uint32_t *dev_out, void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of independent solves on one GPU.           */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    size_t hbm_budget_bytes; /* admission limit on summed footprints; 0 -> 64 GiB */
+    int32_t max_slots;       /* concurrently resident requests; 0 -> 8        */
+    int32_t n_streams;       /* HIP streams in the pool; 0 -> max_slots       */
+} slh_server_cfg;
+
+typedef struct {
+    double submit_s;  /* host clock at submit                           */
+    double admit_s;   /* when the request got a slot and memory         */
+    double done_s;    /* when its result was available on the host      */
+    double queue_ms;  /* admit - submit                                  */
+    double run_ms;    /* done - admit                                    */
+    double latency_ms;/* done - submit                                   */
+    uint64_t segments;/* tracking segments of the whole solve            */
+} slh_latency;
+
+typedef struct slh_server slh_server;
+
+slh_status slh_server_create(const slh_server_cfg *cfg, slh_server **out);
+
+/* Queues a solve of n_steps steps.  The problem's arrays are copied before
+ * the call returns.  SLH_E_REJECTED if its footprint alone exceeds the
+ * budget. */
+slh_status slh_server_submit(slh_server *srv, const slh_problem *problem, int32_t n_steps,
+                             uint64_t *ticket);
+
+/* *done = 1 once the result of ticket is available. */
+slh_status slh_server_poll(slh_server *srv, uint64_t ticket, int32_t *done);
+
+/* Blocks until the ticket is done; copies the final phi_R (nx*ny FP64),
+ * the remap balance of the last step and the latency record. Any output
+ * pointer may be NULL.  Releases the request. */
+slh_status slh_server_result(slh_server *srv, uint64_t ticket, double *flux_out,
+                             slh_balance *balance, slh_latency *latency);
+
+/* Waits for all outstanding work, then frees everything. */
+void slh_server_destroy(slh_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLH_H */

@@ -1,0 +1,816 @@
+// Host side of libslh: argument validation, device memory, the S_N
+// quadrature, the time-step driver (steps 1-4 of Sec. 2.2 of the paper) and
+// the C ABI declared in include/slh.h.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/slh.h"
+#include "slh_common.hpp"
+
+using namespace slh;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static slh_status fail(slh_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+extern "C" const char* slh_last_error(void) { return g_err.c_str(); }
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(SLH_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(_e));     \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// S_N product quadrature: N/2 positive Gauss-Legendre nodes of order N for
+// Omega_z (weights doubled: -Omega_z has the same in-plane components) times
+// 2N azimuths (m + 1/2) pi / N; N^2 directions, weights summing to 4 pi.
+// Nodes by Newton's method on the Legendre three-term recurrence.
+// ---------------------------------------------------------------------------
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+static std::vector<double> product_quadrature(int order) {
+  std::vector<double> x, w;
+  gauss_legendre(order, x, w);
+  std::vector<double> dirs;
+  const int naz = 2 * order;
+  for (int k = 0; k < order; ++k) {
+    if (!(x[k] > 0.0)) continue;
+    const double s = sqrt(1.0 - x[k] * x[k]);
+    for (int m = 0; m < naz; ++m) {
+      const double ph = (m + 0.5) * M_PI / order;
+      dirs.push_back(s * cos(ph));
+      dirs.push_back(s * sin(ph));
+      dirs.push_back(2.0 * w[k] * M_PI / order);
+    }
+  }
+  return dirs;
+}
+
+// ---------------------------------------------------------------------------
+// validation and sizes
+// ---------------------------------------------------------------------------
+struct Sizes {
+  long long n_cells, n_p, cap, n_cand;
+  int n_dir;
+  bool fp32;
+  size_t bytes;
+};
+
+static bool finite_nonneg(const double* p, long long n) {
+  for (long long i = 0; i < n; ++i)
+    if (!(p[i] >= 0.0) || !isfinite(p[i])) return false;
+  return true;
+}
+
+static slh_status validate(const slh_problem* p, bool check_fields) {
+  if (!p) return fail(SLH_E_INVALID_ARG, "problem is NULL");
+  if (p->abi_version != SLH_ABI_VERSION) return fail(SLH_E_INVALID_ARG, "abi_version mismatch");
+  if (p->nx < 1 || p->ny < 1) return fail(SLH_E_INVALID_ARG, "nx, ny must be >= 1");
+  if ((long long)p->nx * p->ny > (1ll << 30)) return fail(SLH_E_INVALID_ARG, "mesh too large");
+  if (p->nx + p->ny > 4096) return fail(SLH_E_INVALID_ARG, "nx + ny must be <= 4096");
+  if (!(p->x_hi > p->x_lo) || !(p->y_hi > p->y_lo) || !isfinite(p->x_lo) || !isfinite(p->x_hi) ||
+      !isfinite(p->y_lo) || !isfinite(p->y_hi))
+    return fail(SLH_E_INVALID_ARG, "empty or non-finite domain");
+  if (!(p->c > 0.0) || !isfinite(p->c)) return fail(SLH_E_INVALID_ARG, "c must be > 0");
+  if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(SLH_E_INVALID_ARG, "dt must be > 0");
+  if (p->n_s < 0 || p->n_s > 1000000) return fail(SLH_E_INVALID_ARG, "n_s out of range");
+  if (p->n_particles < 0 || p->n_particles > 0xffffffffll)
+    return fail(SLH_E_INVALID_ARG, "n_particles must be in [0, 2^32)");
+  if (p->census_cap < 0 || p->census_cap > (1ll << 34))
+    return fail(SLH_E_INVALID_ARG, "census_cap out of range");
+  if (p->sn_order < 2 || p->sn_order % 2 || p->sn_order > 64)
+    return fail(SLH_E_INVALID_ARG, "sn_order must be even in [2, 64]");
+  if (!(p->time_closure >= 0.0) || !isfinite(p->time_closure))
+    return fail(SLH_E_INVALID_ARG, "time_closure must be >= 0");
+  if (!(p->si_tol >= 0.0) || !isfinite(p->si_tol)) return fail(SLH_E_INVALID_ARG, "si_tol < 0");
+  if (p->si_max_iter < 0) return fail(SLH_E_INVALID_ARG, "si_max_iter < 0");
+  if (!(p->w_cut_rel >= 0.0) || !isfinite(p->w_cut_rel))
+    return fail(SLH_E_INVALID_ARG, "w_cut_rel must be >= 0");
+  if (p->points != SLH_SOBOL_OWEN && p->points != SLH_PRNG)
+    return fail(SLH_E_INVALID_ARG, "points must be SLH_SOBOL_OWEN or SLH_PRNG");
+  if (p->precision != SLH_FP64 && p->precision != SLH_FP32_TRACK)
+    return fail(SLH_E_INVALID_ARG, "precision must be SLH_FP64 or SLH_FP32_TRACK");
+  if (check_fields) {
+    const long long n = (long long)p->nx * p->ny;
+    if (!p->sigma_s || !p->sigma_a || !p->q) return fail(SLH_E_INVALID_ARG, "field is NULL");
+    if (!finite_nonneg(p->sigma_s, n)) return fail(SLH_E_INVALID_ARG, "sigma_s must be finite, >= 0");
+    if (!finite_nonneg(p->sigma_a, n)) return fail(SLH_E_INVALID_ARG, "sigma_a must be finite, >= 0");
+    if (!finite_nonneg(p->q, n)) return fail(SLH_E_INVALID_ARG, "q must be finite, >= 0");
+  }
+  return SLH_OK;
+}
+
+static Sizes sizes_of(const slh_problem* p) {
+  Sizes z;
+  z.n_cells = (long long)p->nx * p->ny;
+  z.n_p = p->n_particles;
+  z.cap = p->census_cap > 0 ? p->census_cap : std::max<long long>(p->n_particles, 1);
+  z.n_cand = z.cap + z.n_p;
+  z.n_dir = p->sn_order * p->sn_order;
+  z.fp32 = p->precision == SLH_FP32_TRACK;
+  const size_t rb = z.fp32 ? 4 : 8;
+  const size_t bank = 5 * rb + 4 + 8;
+  size_t b = 0;
+  const size_t nc = (size_t)z.n_cells;
+  b += nc * (16 + 8 + 8 + 8 + 8);            // mat64, mat32, sig_s, sig_e, q
+  b += nc * (32 + 8 + 8) * 2;                // nodal sources, M, cdf (pass 1 and 2)
+  b += nc * 16 * 3;                          // tallies
+  b += nc * 8 * 3 + nc * 32 * 2;             // phi_pre/post/R, phi_c x2
+  b += (size_t)z.n_dir * nc * 32;            // per-direction planes
+  b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
+  b += scan_tmp_elems(z.n_cells) * 8;
+  b += (size_t)z.cap * bank * 2;             // census banks
+  b += (size_t)z.n_cand * (bank + 1 + 8 + 8);  // staging, alive, flags, inclusive scan
+  b += scan_tmp_elems(z.n_cand) * 8;
+  b += 256 * 8 + sizeof(DevState) + 32 * 32 * 4 + 64 * 8;
+  z.bytes = b;
+  return z;
+}
+
+extern "C" size_t slh_footprint_bytes(const slh_problem* p) {
+  if (validate(p, false) != SLH_OK) return 0;
+  return sizes_of(p).bytes;
+}
+
+// ---------------------------------------------------------------------------
+// solver
+// ---------------------------------------------------------------------------
+struct BalStore {
+  unsigned long long bal[2 * B_NFIELDS];
+  unsigned long long segments, particles, alive, killed;
+  double unit_W;
+  double pad[3];
+};
+
+__global__ void k_snapshot(const DevState* st, BalStore* out) {
+  const int t = threadIdx.x;
+  if (t < 2 * B_NFIELDS) out->bal[t] = st->bal[t];
+  if (t == 0) {
+    out->segments = st->segments;
+    out->particles = st->particles;
+    out->alive = st->alive;
+    out->killed = st->killed;
+    out->unit_W = st->unit_W;
+  }
+}
+
+__global__ void k_state_init(DevState* st) {
+  if (threadIdx.x == 0) {
+    memset(st, 0, sizeof(DevState));
+    st->thin_factor = 1.0;
+  }
+}
+
+__global__ void k_state_set_bank(DevState* st, long long n, double maxabs) {
+  if (threadIdx.x == 0) {
+    st->n_in = n;
+    st->n_kept = n;
+    st->maxabs_w = maxabs;
+  }
+}
+
+struct slh_solver {
+  slh_problem prob;
+  Sizes z;
+  hipStream_t stream = nullptr;
+  slh_alloc_fn alloc = nullptr;
+  slh_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
+  std::vector<void*> allocs;
+  std::vector<double> h_sig_s, h_sig_a, h_q;
+  double hx, hy, area, adt, tau, si_tol;
+  int si_max;
+
+  // device memory
+  double2* mat64 = nullptr;
+  float2* mat32 = nullptr;
+  double *sig_s = nullptr, *sig_e = nullptr, *q = nullptr;
+  double *qn1 = nullptr, *M1 = nullptr, *cdf1 = nullptr;
+  double *qnR = nullptr, *MR = nullptr, *cdfR = nullptr;
+  unsigned long long *Tpre = nullptr, *Tpost = nullptr, *TR = nullptr;
+  double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr,
+         *phi_c2 = nullptr;
+  double *psi = nullptr, *dg_part = nullptr, *dirs = nullptr, *scan_f = nullptr;
+  int n_part = 1;
+  void* bank_mem[2] = {nullptr, nullptr};
+  void* stage_mem = nullptr;
+  uint8_t* alive = nullptr;
+  long long *flags = nullptr, *incl = nullptr, *scan_i = nullptr;
+  unsigned long long* hist = nullptr;
+  uint32_t* sobol = nullptr;
+  DevState* st = nullptr;
+  BalStore* bal_store = nullptr;  // [2]
+  double* h_res = nullptr;        // pinned: SI residual
+  int cur = 0;
+
+  // host-side state
+  long long step = 0;
+  int si_it = 0;
+  double si_res = 0.0;
+  bool si_conv = true;
+  unsigned long long seg_total = 0;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool have_events = false;
+
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    void* p = nullptr;
+    if (alloc) {
+      p = alloc(bytes, ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (p) allocs.push_back(p);
+    return p;
+  }
+  void release() {
+    for (void* p : allocs) {
+      if (free_fn) free_fn(p, ctx);
+      else (void)hipFree(p);
+    }
+    allocs.clear();
+    if (h_res) (void)hipHostFree(h_res);
+    h_res = nullptr;
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+
+  template <typename R> Bank<R> bank_at(void* base, long long n) const {
+    Bank<R> b;
+    char* p = (char*)base;
+    b.px = (R*)p; p += sizeof(R) * n;
+    b.py = (R*)p; p += sizeof(R) * n;
+    b.ox = (R*)p; p += sizeof(R) * n;
+    b.oy = (R*)p; p += sizeof(R) * n;
+    b.w = (R*)p; p += sizeof(R) * n;
+    b.hid = (uint64_t*)p; p += sizeof(uint64_t) * n;
+    b.cell = (int32_t*)p;
+    return b;
+  }
+  size_t bank_bytes(long long n) const {
+    const size_t rb = z.fp32 ? 4 : 8;
+    return (size_t)n * (5 * rb + 8 + 4);
+  }
+};
+
+static int mc_grid(const slh_solver* s, long long max_work) {
+  // persistent grid: enough 256-lane blocks to fill the GPU, never more than
+  // the work needs
+  long long want = (max_work + 255) / 256;
+  const long long cap = 256 * 8;
+  if (want > cap) want = cap;
+  if (want < 1) want = 1;
+  (void)s;
+  return (int)want;
+}
+
+static slh_status setup(slh_solver* s) {
+  const slh_problem& p = s->prob;
+  const Sizes& z = s->z;
+  const long long nc = z.n_cells;
+#define ALLOC(ptr, T, n)                                                               \
+  do {                                                                                 \
+    ptr = (T*)s->dalloc(sizeof(T) * (size_t)(n));                                      \
+    if (!ptr) return fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: " #ptr);    \
+  } while (0)
+  ALLOC(s->mat64, double2, nc);
+  ALLOC(s->mat32, float2, nc);
+  ALLOC(s->sig_s, double, nc);
+  ALLOC(s->sig_e, double, nc);
+  ALLOC(s->q, double, nc);
+  ALLOC(s->qn1, double, 4 * nc);
+  ALLOC(s->M1, double, nc);
+  ALLOC(s->cdf1, double, nc);
+  ALLOC(s->qnR, double, 4 * nc);
+  ALLOC(s->MR, double, nc);
+  ALLOC(s->cdfR, double, nc);
+  ALLOC(s->Tpre, unsigned long long, 2 * nc);
+  ALLOC(s->Tpost, unsigned long long, 2 * nc);
+  ALLOC(s->TR, unsigned long long, 2 * nc);
+  ALLOC(s->phi_pre, double, nc);
+  ALLOC(s->phi_post, double, nc);
+  ALLOC(s->phi_R, double, nc);
+  ALLOC(s->phi_c, double, 4 * nc);
+  ALLOC(s->phi_c2, double, 4 * nc);
+  ALLOC(s->psi, double, (size_t)z.n_dir * 4 * nc);
+  s->n_part = dg_reduce_partials(4 * nc);
+  ALLOC(s->dg_part, double, 2 * s->n_part + 2);
+  ALLOC(s->dirs, double, 3 * z.n_dir);
+  ALLOC(s->scan_f, double, scan_tmp_elems(nc));
+  s->bank_mem[0] = s->dalloc(s->bank_bytes(z.cap));
+  s->bank_mem[1] = s->dalloc(s->bank_bytes(z.cap));
+  s->stage_mem = s->dalloc(s->bank_bytes(z.n_cand));
+  if (!s->bank_mem[0] || !s->bank_mem[1] || !s->stage_mem)
+    return fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: census banks");
+  ALLOC(s->alive, uint8_t, z.n_cand);
+  ALLOC(s->flags, long long, z.n_cand);
+  ALLOC(s->incl, long long, z.n_cand);
+  ALLOC(s->scan_i, long long, scan_tmp_elems(z.n_cand));
+  ALLOC(s->hist, unsigned long long, 256);
+  ALLOC(s->sobol, uint32_t, 32 * 32);
+  ALLOC(s->st, DevState, 1);
+  ALLOC(s->bal_store, BalStore, 2);
+#undef ALLOC
+  if (hipHostMalloc((void**)&s->h_res, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return fail(SLH_E_OUT_OF_MEMORY, "pinned host allocation failed");
+
+  // fields and derived arrays
+  std::vector<double2> m64(nc);
+  std::vector<float2> m32(nc);
+  std::vector<double> se(nc), qn(4 * nc), M(nc);
+  for (long long i = 0; i < nc; ++i) {
+    m64[i] = make_double2(s->h_sig_s[i], s->h_sig_a[i]);
+    m32[i] = make_float2((float)s->h_sig_s[i], (float)s->h_sig_a[i]);
+    se[i] = s->h_sig_a[i] + s->h_sig_s[i] + s->tau / (p.c * p.dt);
+    for (int k = 0; k < 4; ++k) qn[4 * i + k] = s->h_q[i];
+    M[i] = s->adt * fabs(s->h_q[i]);
+  }
+  const std::vector<double> dirs = product_quadrature(p.sn_order);
+  hipStream_t st = s->stream;
+  HIP_TRY(hipMemcpyAsync(s->mat64, m64.data(), sizeof(double2) * nc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->mat32, m32.data(), sizeof(float2) * nc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->sig_s, s->h_sig_s.data(), 8 * nc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->sig_e, se.data(), 8 * nc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->q, s->h_q.data(), 8 * nc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->qn1, qn.data(), 32 * nc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->M1, M.data(), 8 * nc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->dirs, dirs.data(), 8 * dirs.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->sobol, sobol_table_host(), 4 * 32 * 32, hipMemcpyHostToDevice, st));
+  HIP_TRY(scan_inclusive_f64(s->M1, s->cdf1, nc, s->scan_f, st));
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, st, s->st);
+  HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
+  HIP_TRY(launch_fill_f64(s->phi_pre, nc, 0.0, st));
+  HIP_TRY(launch_fill_f64(s->phi_post, nc, 0.0, st));
+  HIP_TRY(launch_fill_f64(s->phi_R, nc, 0.0, st));
+  HIP_TRY(launch_fill_u64((unsigned long long*)s->bal_store, 2 * sizeof(BalStore) / 8, 0ull, st));
+  HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
+  HIP_TRY(launch_fill_u64(s->hist, 256, 0ull, st));
+  for (auto& e : s->ev) HIP_TRY(hipEventCreate(&e));
+  s->have_events = true;
+  HIP_TRY(hipStreamSynchronize(st));  // host vectors above go out of scope
+  return SLH_OK;
+}
+
+static PassArgs pass_args(slh_solver* s, int kind) {
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  const slh_problem& p = s->prob;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.hx = s->hx;
+  a.hy = s->hy;
+  a.dt = p.dt;
+  a.c = p.c;
+  a.mat64 = s->mat64;
+  a.mat32 = s->mat32;
+  a.cdf = kind == 1 ? s->cdf1 : s->cdfR;
+  a.qn = kind == 1 ? s->qn1 : s->qnR;
+  a.n_cells = s->z.n_cells;
+  a.n_src = s->z.n_p;
+  a.seed = p.seed;
+  a.step = (uint64_t)s->step;
+  a.kind = kind;
+  a.n_lim = kind == 1 ? p.n_s : 0;
+  a.points = p.points;
+  a.sobol = s->sobol;
+  a.w_cut_rel = p.w_cut_rel;
+  a.max_segments = 1u << 26;
+  void* bin = s->bank_mem[s->cur];
+  if (s->z.fp32) {
+    a.in32 = s->bank_at<float>(bin, s->z.cap);
+    a.out32 = s->bank_at<float>(s->stage_mem, s->z.n_cand);
+  } else {
+    a.in64 = s->bank_at<double>(bin, s->z.cap);
+    a.out64 = s->bank_at<double>(s->stage_mem, s->z.n_cand);
+  }
+  a.alive = s->alive;
+  a.out_src_base = s->z.cap;
+  a.Ta = kind == 1 ? s->Tpre : s->TR;
+  a.Tb = kind == 1 ? s->Tpost : s->TR;
+  a.st = s->st;
+  return a;
+}
+
+static slh_status run_step(slh_solver* s) {
+  const slh_problem& p = s->prob;
+  const Sizes& z = s->z;
+  const long long nc = z.n_cells;
+  hipStream_t st = s->stream;
+  const double inv_adt = 1.0 / s->adt;
+  const double cdt = p.c * p.dt;
+  const int grid = mc_grid(s, z.cap + z.n_p);
+
+  HIP_TRY(hipEventRecord(s->ev[0], st));
+  // ---- step 1: scatter-limited leg from Q and the census ----
+  HIP_TRY(launch_pass_begin(s->st, s->cdf1, nc, cdt, st));
+  HIP_TRY(launch_fill_u64(s->Tpre, 2 * nc, 0ull, st));
+  HIP_TRY(launch_fill_u64(s->Tpost, 2 * nc, 0ull, st));
+  HIP_TRY(launch_mc_pass(pass_args(s, 1), z.fp32, grid, st));
+  HIP_TRY(launch_tally_to_flux(s->Tpre, nc, s->st, inv_adt, s->phi_pre, st));
+  HIP_TRY(launch_tally_to_flux(s->Tpost, nc, s->st, inv_adt, s->phi_post, st));
+  hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
+                     s->bal_store + 0);
+  HIP_TRY(hipEventRecord(s->ev[1], st));
+
+  // ---- step 2: collided DG S_N solve, source iteration ----
+  HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
+  DgArgs d;
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.hx = s->hx;
+  d.hy = s->hy;
+  d.n_dir = z.n_dir;
+  d.dir = s->dirs;
+  d.sig_e = s->sig_e;
+  d.sig_s = s->sig_s;
+  d.phi_post = s->phi_post;
+  d.psi = s->psi;
+  s->si_it = 0;
+  s->si_conv = false;
+  s->si_res = 0.0;
+  for (int it = 0; it < s->si_max; ++it) {
+    d.phi_in = s->phi_c;
+    HIP_TRY(launch_dg_sweep(d, st));
+    HIP_TRY(launch_dg_reduce(z.n_dir, 4 * nc, s->psi, s->phi_c, s->phi_c2, s->dg_part,
+                             s->n_part, st));
+    HIP_TRY(hipMemcpyAsync(s->h_res, s->dg_part + 2 * s->n_part, 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::swap(s->phi_c, s->phi_c2);
+    s->si_it = it + 1;
+    const double dn = sqrt(s->h_res[0]), nrm = sqrt(s->h_res[1]);
+    s->si_res = nrm > 0.0 ? dn / nrm : 0.0;
+    if (!isfinite(dn) || !isfinite(nrm)) return fail(SLH_E_NUMERIC, "non-finite DG residual");
+    if (dn <= s->si_tol * nrm) { s->si_conv = true; break; }
+  }
+  if (s->si_max == 0) s->si_conv = true;
+  HIP_TRY(hipEventRecord(s->ev[2], st));
+
+  // ---- step 3: remap source and scatter-free leg ----
+  HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c, s->adt,
+                              s->qnR, s->MR, st));
+  HIP_TRY(scan_inclusive_f64(s->MR, s->cdfR, nc, s->scan_f, st));
+  HIP_TRY(launch_pass_begin(s->st, s->cdfR, nc, cdt, st));
+  HIP_TRY(launch_fill_u64(s->TR, 2 * nc, 0ull, st));
+  HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
+  HIP_TRY(launch_mc_pass(pass_args(s, 2), z.fp32, grid, st));
+  HIP_TRY(launch_tally_to_flux(s->TR, nc, s->st, inv_adt, s->phi_R, st));
+  hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
+                     s->bal_store + 1);
+  HIP_TRY(hipEventRecord(s->ev[3], st));
+
+  // ---- step 4: the remap census is the state at t_{n+1} (capped) ----
+  const uint64_t thin_stream = stream_seed(p.seed, (uint64_t)s->step, 2u, 2u, 0ull);
+  void* nb = s->bank_mem[1 - s->cur];
+  const uint64_t* stage_hid = z.fp32 ? s->bank_at<float>(s->stage_mem, z.n_cand).hid
+                                      : s->bank_at<double>(s->stage_mem, z.n_cand).hid;
+  HIP_TRY(launch_census_select(s->alive, stage_hid, z.n_cand, z.cap, thin_stream, s->st,
+                               s->hist, st));
+  if (z.fp32) {
+    Bank<float> src = s->bank_at<float>(s->stage_mem, z.n_cand);
+    HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, thin_stream, s->st, s->flags, st));
+    HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
+    HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, s->bank_at<float>(nb, z.cap),
+                                         s->st, st));
+  } else {
+    Bank<double> src = s->bank_at<double>(s->stage_mem, z.n_cand);
+    HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, thin_stream, s->st, s->flags, st));
+    HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
+    HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand,
+                                          s->bank_at<double>(nb, z.cap), s->st, st));
+  }
+  HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, st));
+  HIP_TRY(hipEventRecord(s->ev[4], st));
+  s->cur = 1 - s->cur;
+  s->step += 1;
+  return SLH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" slh_status slh_create(const slh_problem* problem, void* hip_stream,
+                                 slh_alloc_fn alloc, slh_free_fn free_fn, void* ctx,
+                                 slh_solver** out) {
+  if (!out) return fail(SLH_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  slh_status v = validate(problem, true);
+  if (v != SLH_OK) return v;
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(SLH_E_INVALID_ARG, "alloc and free_fn must both be set or both be NULL");
+  slh_solver* s = new (std::nothrow) slh_solver();
+  if (!s) return fail(SLH_E_OUT_OF_MEMORY, "host allocation failed");
+  s->prob = *problem;
+  s->z = sizes_of(problem);
+  s->stream = (hipStream_t)hip_stream;
+  s->alloc = alloc;
+  s->free_fn = free_fn;
+  s->ctx = ctx;
+  const long long nc = s->z.n_cells;
+  s->h_sig_s.assign(problem->sigma_s, problem->sigma_s + nc);
+  s->h_sig_a.assign(problem->sigma_a, problem->sigma_a + nc);
+  s->h_q.assign(problem->q, problem->q + nc);
+  s->prob.sigma_s = s->prob.sigma_a = s->prob.q = nullptr;
+  s->hx = (problem->x_hi - problem->x_lo) / problem->nx;
+  s->hy = (problem->y_hi - problem->y_lo) / problem->ny;
+  s->area = s->hx * s->hy;
+  s->adt = s->area * problem->dt;
+  s->tau = problem->time_closure > 0.0 ? problem->time_closure : 2.0;
+  s->si_tol = problem->si_tol > 0.0 ? problem->si_tol : 1e-12;
+  s->si_max = problem->si_max_iter > 0 ? problem->si_max_iter : 200;
+  slh_status r = setup(s);
+  if (r != SLH_OK) {
+    s->release();
+    delete s;
+    return r;
+  }
+  *out = s;
+  return SLH_OK;
+}
+
+extern "C" slh_status slh_advance(slh_solver* s, int32_t n_steps) {
+  if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
+  if (n_steps < 1) return fail(SLH_E_INVALID_ARG, "n_steps must be >= 1");
+  bool conv = true;
+  for (int k = 0; k < n_steps; ++k) {
+    slh_status r = run_step(s);
+    if (r != SLH_OK) return r;
+    conv = conv && s->si_conv;
+  }
+  if (!conv) return fail(SLH_E_NOT_CONVERGED, "source iteration reached si_max_iter");
+  return SLH_OK;
+}
+
+extern "C" slh_status slh_synchronize(slh_solver* s) {
+  if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return SLH_OK;
+}
+
+static const double* flux_ptr(slh_solver* s, int32_t which, long long* n) {
+  const long long nc = s->z.n_cells;
+  *n = nc;
+  switch (which) {
+    case SLH_FLUX_REMAP: return s->phi_R;
+    case SLH_FLUX_PRE: return s->phi_pre;
+    case SLH_FLUX_POST: return s->phi_post;
+    case SLH_FLUX_COLLIDED_NODAL: *n = 4 * nc; return s->phi_c;
+    default: return nullptr;
+  }
+}
+
+extern "C" slh_status slh_get_flux(slh_solver* s, int32_t which, double* host_out) {
+  if (!s || !host_out) return fail(SLH_E_INVALID_ARG, "NULL argument");
+  long long n;
+  const double* p = flux_ptr(s, which, &n);
+  if (!p) return fail(SLH_E_INVALID_ARG, "unknown flux kind");
+  HIP_TRY(hipMemcpyAsync(host_out, p, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return SLH_OK;
+}
+
+extern "C" slh_status slh_get_flux_device(slh_solver* s, int32_t which, double* dev_out) {
+  if (!s || !dev_out) return fail(SLH_E_INVALID_ARG, "NULL argument");
+  long long n;
+  const double* p = flux_ptr(s, which, &n);
+  if (!p) return fail(SLH_E_INVALID_ARG, "unknown flux kind");
+  HIP_TRY(hipMemcpyAsync(dev_out, p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->stream));
+  return SLH_OK;
+}
+
+extern "C" slh_status slh_get_balance(slh_solver* s, int32_t pass, slh_balance* out) {
+  if (!s || !out) return fail(SLH_E_INVALID_ARG, "NULL argument");
+  if (pass != 1 && pass != 2) return fail(SLH_E_INVALID_ARG, "pass must be 1 or 2");
+  BalStore b;
+  HIP_TRY(hipMemcpyAsync(&b, s->bal_store + (pass - 1), sizeof(BalStore), hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  double v[B_NFIELDS];
+  for (int f = 0; f < B_NFIELDS; ++f)
+    v[f] = fix_value((long long)b.bal[2 * f], (long long)b.bal[2 * f + 1], b.unit_W);
+  out->emitted = v[B_EMITTED];
+  out->absorbed = v[B_ABSORBED];
+  out->scattered = v[B_SCATTERED];
+  out->leaked = v[B_LEAKED];
+  out->census = v[B_CENSUS];
+  out->cutoff = v[B_CUTOFF];
+  out->source_w = v[B_SOURCE_W];
+  out->census_in_w = v[B_CENSUS_IN_W];
+  out->segments = b.segments;
+  out->particles = b.particles;
+  return SLH_OK;
+}
+
+extern "C" slh_status slh_get_stats(slh_solver* s, slh_stats* out) {
+  if (!s || !out) return fail(SLH_E_INVALID_ARG, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  DevState d;
+  HIP_TRY(hipMemcpy(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  BalStore b[2];
+  HIP_TRY(hipMemcpy(b, s->bal_store, sizeof(b), hipMemcpyDeviceToHost));
+  memset(out, 0, sizeof(*out));
+  out->step = s->step;
+  out->si_iterations = s->si_it;
+  out->si_residual = s->si_res;
+  out->si_converged = s->si_conv ? 1 : 0;
+  out->census_alive = (int64_t)b[1].alive;
+  out->census_kept = d.n_kept;
+  out->thin_factor = d.thin_factor;
+  out->segments_total = b[0].segments + b[1].segments;
+  if (s->step > 0) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev[0], s->ev[1]) == hipSuccess) out->ms_mc = ms;
+    if (hipEventElapsedTime(&ms, s->ev[1], s->ev[2]) == hipSuccess) out->ms_dg = ms;
+    if (hipEventElapsedTime(&ms, s->ev[2], s->ev[3]) == hipSuccess) out->ms_remap = ms;
+    if (hipEventElapsedTime(&ms, s->ev[3], s->ev[4]) == hipSuccess) out->ms_census = ms;
+  }
+  return SLH_OK;
+}
+
+extern "C" slh_status slh_get_census(slh_solver* s, int64_t* n, double* x, double* y,
+                                     double* ox, double* oy, double* w, int32_t* cell,
+                                     uint64_t* hid) {
+  if (!s || !n) return fail(SLH_E_INVALID_ARG, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  DevState d;
+  HIP_TRY(hipMemcpy(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  const long long cnt = d.n_in;
+  *n = cnt;
+  if (cnt == 0) return SLH_OK;
+  const slh_problem& p = s->prob;
+  std::vector<int32_t> c(cnt);
+  std::vector<double> px(cnt), py(cnt), vx(cnt), vy(cnt), vw(cnt);
+  std::vector<uint64_t> h(cnt);
+  void* base = s->bank_mem[s->cur];
+  if (s->z.fp32) {
+    Bank<float> b = s->bank_at<float>(base, s->z.cap);
+    std::vector<float> t(cnt);
+    float* srcs[5] = {b.px, b.py, b.ox, b.oy, b.w};
+    std::vector<double>* dsts[5] = {&px, &py, &vx, &vy, &vw};
+    for (int k = 0; k < 5; ++k) {
+      HIP_TRY(hipMemcpy(t.data(), srcs[k], 4 * cnt, hipMemcpyDeviceToHost));
+      for (long long i = 0; i < cnt; ++i) (*dsts[k])[i] = t[i];
+    }
+    HIP_TRY(hipMemcpy(c.data(), b.cell, 4 * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(h.data(), b.hid, 8 * cnt, hipMemcpyDeviceToHost));
+  } else {
+    Bank<double> b = s->bank_at<double>(base, s->z.cap);
+    HIP_TRY(hipMemcpy(px.data(), b.px, 8 * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(py.data(), b.py, 8 * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(vx.data(), b.ox, 8 * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(vy.data(), b.oy, 8 * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(vw.data(), b.w, 8 * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(c.data(), b.cell, 4 * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(h.data(), b.hid, 8 * cnt, hipMemcpyDeviceToHost));
+  }
+  for (long long i = 0; i < cnt; ++i) {
+    const int ix = c[i] % p.nx, iy = c[i] / p.nx;
+    if (x) x[i] = p.x_lo + s->hx * ix + px[i];
+    if (y) y[i] = p.y_lo + s->hy * iy + py[i];
+    if (ox) ox[i] = vx[i];
+    if (oy) oy[i] = vy[i];
+    if (w) w[i] = vw[i];
+    if (cell) cell[i] = c[i];
+    if (hid) hid[i] = h[i];
+  }
+  return SLH_OK;
+}
+
+// Checkpoint layout: magic, abi, step, precision, count, maxabs, then the raw
+// bank arrays (px, py, ox, oy, w in the solver's precision, hid, cell).
+static const uint64_t kMagic = 0x534c48434b505431ull;  // "SLHCKPT1"
+
+extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
+  if (!s || !len) return fail(SLH_E_INVALID_ARG, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  DevState d;
+  HIP_TRY(hipMemcpy(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  const long long cnt = d.n_in;
+  const size_t head = 6 * 8;
+  const size_t need = head + s->bank_bytes(cnt);
+  if (!buf) { *len = need; return SLH_OK; }
+  if (*len < need) return fail(SLH_E_INVALID_ARG, "buffer too small");
+  uint64_t* h = (uint64_t*)buf;
+  h[0] = kMagic;
+  h[1] = SLH_ABI_VERSION;
+  h[2] = (uint64_t)s->step;
+  h[3] = (uint64_t)s->z.fp32;
+  h[4] = (uint64_t)cnt;
+  memcpy(&h[5], &d.maxabs_w, 8);
+  char* out = (char*)buf + head;
+  const size_t rb = s->z.fp32 ? 4 : 8;
+  // the bank arrays are laid out with stride cap; copy each array's prefix
+  char* base = (char*)s->bank_mem[s->cur];
+  const long long cap = s->z.cap;
+  for (int k = 0; k < 5; ++k) {
+    HIP_TRY(hipMemcpy(out, base + (size_t)k * rb * cap, rb * cnt, hipMemcpyDeviceToHost));
+    out += rb * cnt;
+  }
+  HIP_TRY(hipMemcpy(out, base + 5 * rb * cap, 8 * cnt, hipMemcpyDeviceToHost));
+  out += 8 * cnt;
+  HIP_TRY(hipMemcpy(out, base + 5 * rb * cap + 8 * cap, 4 * cnt, hipMemcpyDeviceToHost));
+  *len = need;
+  return SLH_OK;
+}
+
+extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
+  if (!s || !buf) return fail(SLH_E_INVALID_ARG, "NULL argument");
+  const size_t head = 6 * 8;
+  if (len < head) return fail(SLH_E_INVALID_ARG, "checkpoint truncated");
+  const uint64_t* h = (const uint64_t*)buf;
+  if (h[0] != kMagic || h[1] != SLH_ABI_VERSION) return fail(SLH_E_INVALID_ARG, "not a checkpoint");
+  if (h[3] != (uint64_t)s->z.fp32) return fail(SLH_E_INVALID_ARG, "checkpoint precision differs");
+  const long long cnt = (long long)h[4];
+  if (cnt < 0 || cnt > s->z.cap) return fail(SLH_E_INVALID_ARG, "checkpoint bank exceeds the cap");
+  if (len < head + s->bank_bytes(cnt)) return fail(SLH_E_INVALID_ARG, "checkpoint truncated");
+  double maxabs;
+  memcpy(&maxabs, &h[5], 8);
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const char* in = (const char*)buf + head;
+  const size_t rb = s->z.fp32 ? 4 : 8;
+  char* base = (char*)s->bank_mem[s->cur];
+  const long long cap = s->z.cap;
+  for (int k = 0; k < 5; ++k) {
+    HIP_TRY(hipMemcpy(base + (size_t)k * rb * cap, in, rb * cnt, hipMemcpyHostToDevice));
+    in += rb * cnt;
+  }
+  HIP_TRY(hipMemcpy(base + 5 * rb * cap, in, 8 * cnt, hipMemcpyHostToDevice));
+  in += 8 * cnt;
+  HIP_TRY(hipMemcpy(base + 5 * rb * cap + 8 * cap, in, 4 * cnt, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_state_set_bank, dim3(1), dim3(1), 0, s->stream, s->st, cnt, maxabs);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->step = (long long)h[2];
+  return SLH_OK;
+}
+
+extern "C" void slh_destroy(slh_solver* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  s->release();
+  delete s;
+}
+
+extern "C" slh_status slh_qmc_points(uint64_t seed, uint64_t step, uint32_t pass,
+                                     uint32_t population, uint64_t cohort, uint32_t dim0,
+                                     uint32_t n_dims, uint32_t index0, uint32_t n, int32_t points,
+                                     uint32_t* dev_out, void* hip_stream) {
+  if (!dev_out && n && n_dims) return fail(SLH_E_INVALID_ARG, "dev_out is NULL");
+  if (points != SLH_SOBOL_OWEN && points != SLH_PRNG)
+    return fail(SLH_E_INVALID_ARG, "unknown point set");
+  if ((uint64_t)index0 + n > 0x100000000ull) return fail(SLH_E_INVALID_ARG, "index range > 2^32");
+  static uint32_t* table = nullptr;  // per process, device 0 context
+  if (!table) {
+    uint32_t* t = nullptr;
+    HIP_TRY(hipMalloc(&t, 4 * 32 * 32));
+    HIP_TRY(hipMemcpy(t, sobol_table_host(), 4 * 32 * 32, hipMemcpyHostToDevice));
+    table = t;
+  }
+  const uint64_t stream = stream_seed(seed, step, pass, population, cohort);
+  HIP_TRY(launch_qmc_points(stream, dim0, n_dims, index0, n, points, table, dev_out,
+                            (hipStream_t)hip_stream));
+  return SLH_OK;
+}

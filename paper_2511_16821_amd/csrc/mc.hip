@@ -1,0 +1,336 @@
+// (Q)MC pass of the scatter-limited hybrid method (Sec. 2.3 of the paper):
+// emission from a majorant CDF over cells, tracking with at most n_lim
+// scatters per history (implicit capture with sigma_a before the limit,
+// attenuation with sigma_t after it), exact track-length tallies
+// w (1 - e^{-sigma l}) / sigma per segment, and the census write of the remap
+// pass.
+//
+// Execution model: a persistent grid.  Every lane owns one history at a time;
+// when histories end, the wave ballots its idle lanes, takes a contiguous
+// block of work indices with a single atomic and hands them out in lane order,
+// so lanes refill without waiting for the slowest history of the wave.  The
+// work index g maps to census particle g (g < n_in) or source particle
+// g - n_in; every random number of a history is a pure function of its
+// (stream, dimension, point index), so results do not depend on which lane or
+// wave ran it.  Tallies and balance sums are two-word fixed point with integer
+// atomics and are therefore independent of the schedule.
+#include "slh_common.hpp"
+#include "sobol_dirs.inc"
+
+namespace slh {
+
+const uint32_t* sobol_table_host() { return slh_sobol_v; }
+
+template <typename R> struct Real;
+template <> struct Real<double> {
+  using V2 = double2;
+  static __device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s, c); }
+  static __device__ __forceinline__ double2 mat(const PassArgs& a, int c) { return a.mat64[c]; }
+  static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+  static __device__ __forceinline__ const Bank<double>& in(const PassArgs& a) { return a.in64; }
+  static __device__ __forceinline__ const Bank<double>& out(const PassArgs& a) { return a.out64; }
+};
+template <> struct Real<float> {
+  using V2 = float2;
+  static __device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, c); }
+  static __device__ __forceinline__ float2 mat(const PassArgs& a, int c) { return a.mat32[c]; }
+  static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
+  static __device__ __forceinline__ const Bank<float>& in(const PassArgs& a) { return a.in32; }
+  static __device__ __forceinline__ const Bank<float>& out(const PassArgs& a) { return a.out32; }
+};
+
+enum { EV_CENSUS = 0, EV_COLLIDE = 1, EV_XFACE = 2, EV_YFACE = 3 };
+enum { END_NONE = 0, END_CENSUS, END_LEAK, END_CUTOFF };
+
+__device__ __forceinline__ double maxabs4(const double* q) {
+  return fmax(fmax(fabs(q[0]), fabs(q[1])), fmax(fabs(q[2]), fabs(q[3])));
+}
+
+// Bilinear interpolation of nodal values (nodes (0,0),(1,0),(0,1),(1,1)) at
+// local coordinates (a, b); equal corners give exactly q[0].
+__device__ __forceinline__ double bilinear(const double* q, double a, double b) {
+  return q[0] + a * (q[1] - q[0]) + b * (q[2] - q[0]) + a * b * (q[0] - q[1] - q[2] + q[3]);
+}
+
+// First cell i with target < cdf[i] (inverse CDF of the majorant).
+__device__ __forceinline__ long long cdf_search(const double* __restrict__ cdf, long long n,
+                                                double target) {
+  long long lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const long long mid = lo + ((hi - lo) >> 1);
+    if (target < cdf[mid]) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
+  __shared__ unsigned long long s_bal[2 * B_NFIELDS];
+  __shared__ unsigned long long s_cnt[4];
+  if (threadIdx.x < 2 * B_NFIELDS) s_bal[threadIdx.x] = 0ull;
+  if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0ull;
+  __syncthreads();
+
+  DevState* st = a.st;
+  const int lane = __lane_id();
+  const long long n_in = st->n_in;
+  const double total = a.n_cells > 0 ? a.cdf[a.n_cells - 1] : 0.0;
+  const long long n_emit = (total > 0.0) ? a.n_src : 0;
+  const unsigned long long n_tot = (unsigned long long)(n_in + n_emit);
+  const double w_src = n_emit > 0 ? total / (double)a.n_src : 0.0;
+  const R w_cut = (R)(a.w_cut_rel * w_src);
+  const double inv_T = st->inv_T;
+  const double inv_W = st->inv_W;
+  const uint64_t src_stream = stream_seed(a.seed, a.step, (uint32_t)KIND, 0u, 0ull);
+  const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt, c = (R)a.c;
+  const R INF = Real<R>::inf();
+  const Bank<R> bin = Real<R>::in(a);
+  const Bank<R> bout = Real<R>::out(a);
+  const int n_lim = a.n_lim;
+
+  bool have = false, exhausted = false;
+  long long g = 0;
+  R px = 0, py = 0, ox = 0, oy = 0, w = 0, trel = 0, tau = 0;
+  int ix = 0, iy = 0, n = 0;
+  uint64_t stream = 0, hid = 0;
+  uint32_t pidx = 0, dcur = 0, seg_p = 0;
+  double w0 = 0.0, acc_abs = 0.0, acc_sca = 0.0;
+  bool from_census = false;
+  unsigned int lane_seg = 0, lane_hist = 0, lane_alive = 0, lane_killed = 0;
+
+  for (;;) {
+    if (!exhausted) {
+      const unsigned long long need = __ballot(!have);
+      if (need) {
+        const int cnt = __popcll(need);
+        const int leader = __ffsll((long long)need) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(&st->work, (unsigned long long)cnt);
+        base = __shfl(base, leader);
+        if (base + (unsigned long long)cnt >= n_tot) exhausted = true;
+        if (!have) {
+          const unsigned long long gg =
+              base + (unsigned long long)__popcll(need & ((1ull << lane) - 1ull));
+          if (gg < n_tot) {
+            g = (long long)gg;
+            have = true;
+            lane_hist++;
+            seg_p = 0;
+            acc_abs = 0.0;
+            acc_sca = 0.0;
+            n = 0;
+            if (g < n_in) {
+              // census particle at the start of the step, counter reset
+              from_census = true;
+              px = bin.px[g]; py = bin.py[g]; ox = bin.ox[g]; oy = bin.oy[g]; w = bin.w[g];
+              const int cell = bin.cell[g];
+              ix = cell % a.nx; iy = cell / a.nx;
+              hid = bin.hid[g];
+              trel = (R)0;
+              stream = (KIND == 1 && n_lim > 0)
+                           ? stream_seed(a.seed, a.step, (uint32_t)KIND, 1u, hid >> 32) : 0ull;
+              pidx = (uint32_t)(hid & 0xffffffffull);
+              dcur = 0;
+            } else {
+              // source particle: inverse CDF of the majorant for the cell,
+              // uniform position and birth time, isotropic direction
+              from_census = false;
+              const long long s = g - n_in;
+              stream = src_stream;
+              pidx = (uint32_t)s;
+              hid = (a.step << 32) | (uint64_t)s;
+              const double u0 = u01_f64(point_u32(a.sobol, a.points, stream, 0u, pidx));
+              const long long ci = cdf_search(a.cdf, a.n_cells, u0 * total);
+              ix = (int)(ci % a.nx); iy = (int)(ci / a.nx);
+              const R u1 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 1u, pidx));
+              const R u2 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 2u, pidx));
+              const R u3 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 3u, pidx));
+              const R u4 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 4u, pidx));
+              const R u5 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 5u, pidx));
+              px = hx * u1;
+              py = hy * u2;
+              trel = u3 * dt;
+              const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
+              R sp, cp;
+              Real<R>::sc((R)(2.0 * M_PI) * u5, &sp, &cp);
+              ox = sn * cp;
+              oy = sn * sp;
+              const double* q = a.qn + 4 * ci;
+              w = (R)(w_src * (bilinear(q, (double)u1, (double)u2) / maxabs4(q)));
+              dcur = 6;
+            }
+            w0 = (double)w;
+            if (n < n_lim) {
+              tau = -log(PointU<R>::u(point_u32(a.sobol, a.points, stream, dcur, pidx)));
+              dcur++;
+            }
+          }
+        }
+      }
+    }
+    if (!__any(have)) break;
+    if (!have) continue;
+
+    // ---- one segment ----
+    const int cell = iy * a.nx + ix;
+    const typename Real<R>::V2 m = Real<R>::mat(a, cell);
+    const R ss = m.x, sa = m.y, stt = sa + ss;
+    const bool pre = n < n_lim;
+    R d_cen = c * (dt - trel);
+    if (d_cen < (R)0) d_cen = (R)0;
+    R d_col = INF;
+    if (pre && ss > (R)0) { d_col = tau / ss; if (d_col < (R)0) d_col = (R)0; }
+    R d_x = INF, d_y = INF;
+    if (ox > (R)0) d_x = (hx - px) / ox; else if (ox < (R)0) d_x = -px / ox;
+    if (oy > (R)0) d_y = (hy - py) / oy; else if (oy < (R)0) d_y = -py / oy;
+    if (d_x < (R)0) d_x = (R)0;
+    if (d_y < (R)0) d_y = (R)0;
+    R l = d_cen;
+    int ev = EV_CENSUS;
+    if (d_col < l) { l = d_col; ev = EV_COLLIDE; }
+    if (d_x < l) { l = d_x; ev = EV_XFACE; }
+    if (d_y < l) { l = d_y; ev = EV_YFACE; }
+
+    const R sig = pre ? sa : stt;
+    const R z = sig * l;
+    const R e = exp(-z);
+    const R em = expm1(-z);
+    const R contrib = (sig > (R)0) ? w * (-em) / sig : w * l;
+    {
+      long long hi, lo;
+      const double cd = (double)contrib;
+      fix_split(cd, inv_T, hi, lo);
+      fix_atomic_add((pre ? a.Ta : a.Tb) + 2 * (long long)cell, hi, lo);
+      acc_abs += (double)sa * cd;
+      if (!pre) acc_sca += (double)ss * cd;
+    }
+    w = w * e;
+    if (pre && ss > (R)0) tau -= ss * l;
+    trel += l / c;
+    seg_p++;
+
+    int end = END_NONE;
+    if (ev == EV_CENSUS) {
+      px += ox * l;
+      py += oy * l;
+      end = END_CENSUS;
+    } else if (ev == EV_COLLIDE) {
+      px += ox * l;
+      py += oy * l;
+      // isotropic re-emission, scatter counter n <- n + 1
+      const R ua = PointU<R>::u(point_u32(a.sobol, a.points, stream, dcur, pidx));
+      const R ub = PointU<R>::u(point_u32(a.sobol, a.points, stream, dcur + 1u, pidx));
+      dcur += 2;
+      const R sn = (R)2 * sqrt(ua * ((R)1 - ua));
+      R sp, cp;
+      Real<R>::sc((R)(2.0 * M_PI) * ub, &sp, &cp);
+      ox = sn * cp;
+      oy = sn * sp;
+      n++;
+      if (n < n_lim) {
+        tau = -log(PointU<R>::u(point_u32(a.sobol, a.points, stream, dcur, pidx)));
+        dcur++;
+      }
+    } else if (ev == EV_XFACE) {
+      py += oy * l;
+      if (ox > (R)0) { ix++; px = (R)0; } else { ix--; px = hx; }
+      if (ix < 0 || ix >= a.nx) end = END_LEAK;
+    } else {
+      px += ox * l;
+      if (oy > (R)0) { iy++; py = (R)0; } else { iy--; py = hy; }
+      if (iy < 0 || iy >= a.ny) end = END_LEAK;
+    }
+    if (end == END_NONE && fabs(w) < w_cut) end = END_CUTOFF;
+    if (end == END_NONE && seg_p >= a.max_segments) { end = END_CUTOFF; lane_killed++; }
+    lane_seg++;
+
+    if (end != END_NONE) {
+      if (KIND == 2 && end == END_CENSUS) {
+        const long long slot = from_census ? g : a.out_src_base + (g - n_in);
+        bout.px[slot] = px; bout.py[slot] = py; bout.ox[slot] = ox; bout.oy[slot] = oy;
+        bout.w[slot] = w; bout.cell[slot] = iy * a.nx + ix; bout.hid[slot] = hid;
+        a.alive[slot] = 1;
+        lane_alive++;
+      }
+      // fold the history's balance into the block (fixed point, exact)
+      long long hi, lo;
+      const double wend = (double)w;
+      fix_split(w0, inv_W, hi, lo);
+      atomicAdd(&s_bal[2 * B_EMITTED], (unsigned long long)hi);
+      atomicAdd(&s_bal[2 * B_EMITTED + 1], (unsigned long long)lo);
+      const int fw = from_census ? B_CENSUS_IN_W : B_SOURCE_W;
+      atomicAdd(&s_bal[2 * fw], (unsigned long long)hi);
+      atomicAdd(&s_bal[2 * fw + 1], (unsigned long long)lo);
+      fix_split(acc_abs, inv_W, hi, lo);
+      atomicAdd(&s_bal[2 * B_ABSORBED], (unsigned long long)hi);
+      atomicAdd(&s_bal[2 * B_ABSORBED + 1], (unsigned long long)lo);
+      if (acc_sca != 0.0) {
+        fix_split(acc_sca, inv_W, hi, lo);
+        atomicAdd(&s_bal[2 * B_SCATTERED], (unsigned long long)hi);
+        atomicAdd(&s_bal[2 * B_SCATTERED + 1], (unsigned long long)lo);
+      }
+      const int ft = end == END_CENSUS ? B_CENSUS : (end == END_LEAK ? B_LEAKED : B_CUTOFF);
+      fix_split(wend, inv_W, hi, lo);
+      atomicAdd(&s_bal[2 * ft], (unsigned long long)hi);
+      atomicAdd(&s_bal[2 * ft + 1], (unsigned long long)lo);
+      have = false;
+    }
+  }
+
+  // wave totals of the integer counters, one atomic per wave
+  unsigned long long v0 = lane_seg, v1 = lane_hist, v2 = lane_alive, v3 = lane_killed;
+  for (int off = 32; off > 0; off >>= 1) {
+    v0 += __shfl_xor(v0, off);
+    v1 += __shfl_xor(v1, off);
+    v2 += __shfl_xor(v2, off);
+    v3 += __shfl_xor(v3, off);
+  }
+  if (lane == 0) {
+    atomicAdd(&s_cnt[0], v0);
+    atomicAdd(&s_cnt[1], v1);
+    atomicAdd(&s_cnt[2], v2);
+    atomicAdd(&s_cnt[3], v3);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * B_NFIELDS) {
+    if (s_bal[threadIdx.x]) atomicAdd(&st->bal[threadIdx.x], s_bal[threadIdx.x]);
+  } else if (threadIdx.x >= 64 && threadIdx.x < 68) {
+    const int k = threadIdx.x - 64;
+    unsigned long long* dst = k == 0 ? &st->segments
+                              : k == 1 ? &st->particles
+                              : k == 2 ? &st->alive : &st->killed;
+    if (s_cnt[k]) atomicAdd(dst, s_cnt[k]);
+  }
+}
+
+hipError_t launch_mc_pass(const PassArgs& a, bool fp32, int grid, hipStream_t s) {
+  if (a.kind == 1) {
+    if (fp32) hipLaunchKernelGGL((k_mc_pass<float, 1>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_mc_pass<double, 1>), dim3(grid), dim3(256), 0, s, a);
+  } else {
+    if (fp32) hipLaunchKernelGGL((k_mc_pass<float, 2>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_mc_pass<double, 2>), dim3(grid), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+__global__ void k_qmc_points(uint64_t stream, uint32_t dim0, uint32_t nd, uint32_t idx0,
+                             uint32_t n, int mode, const uint32_t* sobol, uint32_t* out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * nd) return;
+  const uint32_t k = (uint32_t)(t / nd), d = (uint32_t)(t % nd);
+  out[t] = point_u32(sobol, mode, stream, dim0 + d, idx0 + k);
+}
+
+hipError_t launch_qmc_points(uint64_t stream, uint32_t dim0, uint32_t nd, uint32_t idx0,
+                             uint32_t n, int mode, const uint32_t* sobol, uint32_t* out,
+                             hipStream_t s) {
+  const long long tot = (long long)n * nd;
+  if (tot == 0) return hipSuccess;
+  const int grid = (int)((tot + 255) / 256);
+  hipLaunchKernelGGL(k_qmc_points, dim3(grid), dim3(256), 0, s, stream, dim0, nd, idx0, n,
+                     mode, sobol, out);
+  return hipGetLastError();
+}
+
+}  // namespace slh

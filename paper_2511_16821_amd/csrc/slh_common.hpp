@@ -1,0 +1,248 @@
+// Internal declarations of libslh: device-side helpers shared by the kernel
+// translation units, the pass/step argument blocks and the launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace slh {
+
+// ---------------------------------------------------------------------------
+// Point generator (Sec. 2.4 of the paper: low-discrepancy points used inside
+// the existing inverse-CDF maps).  Sobol' words in natural index order,
+// nested scrambling by the Laine-Karras hash permutation applied to the
+// bit-reversed word (Burley 2020), streams and the pseudo-random mode from
+// the SplitMix64 output function (Steele, Lea & Flood 2014).
+// ---------------------------------------------------------------------------
+
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Stream of points for (time step, pass 1|2, population 0 source|1 census|2
+// thinning, cohort = birth step of a census particle).
+__host__ __device__ __forceinline__ uint64_t stream_seed(uint64_t seed, uint64_t step,
+                                                          uint32_t pass, uint32_t pop,
+                                                          uint64_t cohort) {
+  uint64_t h = mix64(seed);
+  h = mix64(h ^ step);
+  h = mix64(h ^ (uint64_t)(pass * 16u + pop));
+  return mix64(h ^ cohort);
+}
+
+__device__ __forceinline__ uint32_t nested_scramble(uint32_t x, uint32_t s) {
+  x = __builtin_bitreverse32(x);
+  x += s;
+  x ^= x * 0x6c50b47cu;
+  x ^= x * 0xb82f1e52u;
+  x ^= x * 0xc7afe638u;
+  x ^= x * 0x8d22f6e6u;
+  return __builtin_bitreverse32(x);
+}
+
+constexpr int kSobolDims = 32;
+
+// V: the direction-number table (kSobolDims x 32 words) in device memory.
+__device__ __forceinline__ uint32_t sobol_word(const uint32_t* __restrict__ V, uint32_t dim,
+                                               uint32_t index) {
+  const uint32_t* v = V + dim * 32u;
+  uint32_t x = 0;
+  while (index) {
+    const uint32_t j = (uint32_t)__builtin_ctz(index);
+    x ^= v[j];
+    index &= index - 1u;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t point_u32(const uint32_t* __restrict__ V, int mode,
+                                              uint64_t stream, uint32_t dim, uint32_t index) {
+  if (mode == 0 && dim < (uint32_t)kSobolDims) {
+    const uint32_t s = (uint32_t)(mix64(stream + dim) >> 32);
+    return nested_scramble(sobol_word(V, dim, index), s);
+  }
+  const uint64_t ctr = ((uint64_t)dim << 32) | (uint64_t)index;
+  return (uint32_t)(mix64(stream ^ mix64(ctr)) >> 32);
+}
+
+// u in (0,1) from a point word: FP64 keeps all 32 bits; FP32 keeps the top
+// 23 bits so that (m + 1/2) 2^-23 is exact and never rounds to 0 or 1.
+__device__ __forceinline__ double u01_f64(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
+__device__ __forceinline__ float u01_f32(uint32_t x) {
+  return ((float)(x >> 9) + 0.5f) * 0x1p-23f;
+}
+
+template <typename R> struct PointU;
+template <> struct PointU<double> {
+  static __device__ __forceinline__ double u(uint32_t x) { return u01_f64(x); }
+};
+template <> struct PointU<float> {
+  static __device__ __forceinline__ float u(uint32_t x) { return u01_f32(x); }
+};
+
+// ---------------------------------------------------------------------------
+// Order-independent fixed-point accumulation.  A value v is split at a
+// power-of-two unit u into hi = trunc(v/u) and lo = rint(frac(v/u) 2^24); the
+// two 64-bit words are summed with integer atomics, so a sum does not depend
+// on the order of its terms (bitwise reproducible for any grid or schedule).
+// The unit is chosen per pass from a bound B on every partial sum
+// (u = 2^(ceil(log2 B) - 61)); |lo| <= 2^24 allows 2^38 terms per word.
+// ---------------------------------------------------------------------------
+
+constexpr double kLoScale = 16777216.0;  // 2^24
+
+__device__ __forceinline__ void fix_split(double v, double inv_unit, long long& hi,
+                                          long long& lo) {
+  const double s = v * inv_unit;
+  const double h = trunc(s);
+  hi = (long long)h;
+  lo = (long long)rint((s - h) * kLoScale);
+}
+
+__host__ __device__ __forceinline__ double fix_value(long long hi, long long lo, double unit) {
+  const long long carry = lo >> 24;  // floor(lo / 2^24)
+  hi += carry;
+  lo -= carry << 24;
+  return (double)hi * unit + (double)lo * (unit * (1.0 / kLoScale));
+}
+
+__device__ __forceinline__ void fix_atomic_add(unsigned long long* p, long long hi,
+                                               long long lo) {
+  if (hi) atomicAdd(p, (unsigned long long)hi);
+  if (lo) atomicAdd(p + 1, (unsigned long long)lo);
+}
+
+// ---------------------------------------------------------------------------
+// Layouts
+// ---------------------------------------------------------------------------
+
+// Census bank, SoA.  px, py: position relative to the lower-left corner of
+// the cell; ox, oy: in-plane direction components; hid: unique history id
+// (birth step << 32 | source index), which also indexes the particle's points.
+template <typename R> struct Bank {
+  R* px;
+  R* py;
+  R* ox;
+  R* oy;
+  R* w;
+  int32_t* cell;
+  uint64_t* hid;
+};
+
+// Balance fields, each a two-word fixed-point sum.
+enum BalField {
+  B_EMITTED = 0, B_ABSORBED, B_SCATTERED, B_LEAKED, B_CENSUS, B_CUTOFF, B_SOURCE_W,
+  B_CENSUS_IN_W, B_NFIELDS
+};
+
+// Device-resident state shared by the kernels of one solver.
+struct DevState {
+  long long n_in;            // census-in bank size
+  double maxabs_w;           // max |w| over the census-in bank
+  unsigned long long alive;  // pass-2 census candidates
+  long long n_kept;          // after the cap
+  double thin_factor;        // count / cap or 1
+  unsigned long long sel_prefix;  // radix select state
+  unsigned long long sel_rank;
+  int thin_active;
+  int pad0;
+  // fixed-point units of the current pass (tally, balance) and inverses
+  double unit_T, inv_T, unit_W, inv_W;
+  unsigned long long work;      // work counter of the current pass
+  unsigned long long segments;  // segments of the current pass
+  unsigned long long particles; // histories of the current pass
+  unsigned long long killed;    // histories stopped by the segment guard
+  unsigned long long bal[2 * B_NFIELDS];
+  unsigned long long maxabs_bits_out;  // max |w| of the bank being written (bits)
+};
+
+struct PassArgs {
+  int nx, ny;
+  double hx, hy, dt, c;
+  const double2* mat64;  // (sigma_s, sigma_a) per cell
+  const float2* mat32;
+  // emission
+  const double* cdf;     // inclusive prefix sum of the majorant per cell
+  const double* qn;      // nodal source [cell][4]
+  long long n_cells;
+  long long n_src;
+  uint64_t seed, step;
+  int kind;              // 1: scatter-limited leg, 2: scatter-free remap
+  int n_lim;             // scatter limit of the pass (0 for kind 2)
+  int points;            // 0 Sobol'-Owen, 1 pseudo-random
+  const uint32_t* sobol; // direction numbers
+  double w_cut_rel;
+  unsigned int max_segments;
+  // census: input bank and output slots (census index, or out_src_base +
+  // source index), in the precision of the pass
+  Bank<double> in64, out64;
+  Bank<float> in32, out32;
+  uint8_t* alive;
+  long long out_src_base;  // slot of source particle s is out_src_base + s
+  // tallies (two-word fixed point per cell)
+  unsigned long long* Ta;
+  unsigned long long* Tb;
+  DevState* st;
+};
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+
+hipError_t launch_mc_pass(const PassArgs& a, bool fp32, int grid, hipStream_t s);
+hipError_t launch_qmc_points(uint64_t stream, uint32_t dim0, uint32_t nd, uint32_t idx0,
+                             uint32_t n, int mode, const uint32_t* sobol, uint32_t* out,
+                             hipStream_t s);
+const uint32_t* sobol_table_host();
+
+struct DgArgs {
+  int nx, ny;
+  double hx, hy;
+  int n_dir;
+  const double* dir;     // [m][3]: ox, oy, w
+  const double* sig_e;   // per cell
+  const double* sig_s;   // per cell
+  const double* phi_post;// per cell
+  const double* phi_in;  // nodal [cell][4] (previous iterate)
+  double* psi;           // [m][cell][4] (w_m psi_m)
+};
+hipError_t launch_dg_sweep(const DgArgs& a, hipStream_t s);
+hipError_t launch_dg_reduce(int n_dir, long long n_nodes, const double* psi,
+                            const double* phi_old, double* phi_new, double* partials,
+                            int n_part, hipStream_t s);
+int dg_reduce_partials(long long n_nodes);
+
+// util.hip
+hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v,
+                           hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, long long n, uint8_t v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t s);
+hipError_t launch_pass_begin(DevState* st, const double* cdf, long long n_cells, double cdt,
+                             hipStream_t s);
+hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, const DevState* st,
+                                double inv_adt, double* phi, hipStream_t s);
+hipError_t launch_remap_source(long long n, const double* q, const double* sig_s,
+                               const double* phi_pre, const double* phi_post,
+                               const double* phi_c, double adt, double* qn, double* M,
+                               hipStream_t s);
+size_t scan_tmp_elems(long long n);
+hipError_t scan_inclusive_f64(const double* in, double* out, long long n, double* tmp,
+                              hipStream_t s);
+hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
+                              long long* tmp, hipStream_t s);
+hipError_t launch_census_select(const uint8_t* alive, const uint64_t* hid, long long n,
+                                long long cap, uint64_t thin_stream, DevState* st,
+                                unsigned long long* hist, hipStream_t s);
+hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long long n,
+                               uint64_t thin_stream, const DevState* st, long long* flags,
+                               hipStream_t s);
+template <typename R>
+hipError_t launch_census_compact(const Bank<R>& src, const long long* incl, long long n,
+                                 Bank<R> dst, DevState* st, hipStream_t s);
+hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,
+                                hipStream_t s);
+
+}  // namespace slh

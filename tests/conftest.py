@@ -18,3 +18,9 @@ def oracle():
     from oracle import oracle as O
     O.build()
     return O
+
+
+try:  # the first import on a fresh machine is slow; keep it out of test timeouts
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    pass

@@ -1,0 +1,87 @@
+"""Host-only checks of the C ABI (no device work): the library loads, exports
+every symbol declared in include/slh.h, validates arguments before touching
+the device, and reports footprints."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2511_16821_amd import slh
+    if not os.path.exists(slh.LIB_PATH):
+        from paper_2511_16821_amd import build
+        build.build()
+    slh.lib()
+    return slh
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "slh.h")).read()
+    return sorted(set(re.findall(r"\b(slh_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(S):
+    L = S.lib()
+    names = _declared()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(S.EXPORTS) == names
+
+
+def test_validation_rejects_before_allocating(S):
+    import ctypes as C
+    from paper_2511_16821_amd import workloads as W
+    good = W.c1()
+    bad_cases = [
+        dict(nx=0), dict(dt=0.0), dict(dt=-1.0), dict(c=0.0), dict(n_s=-1),
+        dict(sn_order=5), dict(sn_order=0), dict(n_particles=-5), dict(points=7),
+        dict(precision=3), dict(w_cut_rel=-1.0), dict(x_hi=0.0),
+    ]
+    for upd in bad_cases:
+        p = dict(good)
+        p.update({k: v for k, v in upd.items() if k != "nx"})
+        st, keep = S.make_problem(p)
+        if "nx" in upd:
+            st.nx = upd["nx"]
+        h = C.c_void_p()
+        r = S.lib().slh_create(C.byref(st), None, S.ALLOC_FN(0), S.FREE_FN(0), None, C.byref(h))
+        assert r == S.SLH_E_INVALID_ARG, upd
+        assert not h.value
+        assert S.lib().slh_last_error()
+    for field, val in (("sigma_s", np.nan), ("sigma_a", -1.0), ("q", np.inf)):
+        p = dict(good)
+        arr = np.array(p[field], dtype=float)
+        arr.flat[3] = val
+        p[field] = arr
+        st, keep = S.make_problem(p)
+        h = C.c_void_p()
+        r = S.lib().slh_create(C.byref(st), None, S.ALLOC_FN(0), S.FREE_FN(0), None, C.byref(h))
+        assert r == S.SLH_E_INVALID_ARG, field
+        assert b"finite" in S.lib().slh_last_error()
+
+
+def test_footprint_scales_with_problem(S):
+    from paper_2511_16821_amd import workloads as W
+    small = S.slh_footprint_bytes(W.c1())
+    big = S.slh_footprint_bytes(W.c1(n_particles=10 ** 6))
+    assert 0 < small < big
+    p = W.c1()
+    p["sn_order"] = 3
+    assert S.slh_footprint_bytes(p) == 0
+
+
+def test_null_arguments(S):
+    import ctypes as C
+    L = S.lib()
+    assert L.slh_advance(None, 1) == S.SLH_E_INVALID_ARG
+    assert L.slh_get_flux(None, 0, None) == S.SLH_E_INVALID_ARG
+    assert L.slh_synchronize(None) == S.SLH_E_INVALID_ARG
+    L.slh_destroy(None)
+    assert L.slh_create(None, None, S.ALLOC_FN(0), S.FREE_FN(0), None,
+                        C.byref(C.c_void_p())) == S.SLH_E_INVALID_ARG

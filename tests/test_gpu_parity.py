@@ -1,0 +1,158 @@
+"""Device path vs the CPU oracle on the same seeded inputs (FP64: 1e-10
+relative in the L2 and max norms for every tally array, every step)."""
+import numpy as np
+import pytest
+
+from gpu_util import FP64_TOL, compare_balance, compare_step, log, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2511_16821_amd import slh
+    slh.lib()
+    return slh
+
+
+def _run_pair(S, oracle, p, steps, check_balance=True, check_census=True):
+    log("case", p["nx"], p["ny"], "n_s", p["n_s"], "N_p", p["n_particles"], "steps", steps)
+    o = oracle.HybridOracle(p)
+    s = S.Solver(p)
+    out = []
+    for k in range(steps):
+        r = o.step()
+        s.advance(1)
+        errs = compare_step(S, s, r)
+        if check_balance:
+            compare_balance(s, r)
+        st = s.get_stats()
+        assert st["census_alive"] == r["census_alive"], (k, st, r["census_alive"])
+        assert st["census_kept"] == r["census_kept"]
+        assert st["si_iterations"] == r["si_iters"]
+        assert st["segments_total"] == r["segments"], (st["segments_total"], r["segments"])
+        if check_census:
+            c = s.get_census()
+            b = o.bank
+            assert np.array_equal(c["hid"], b.hid)
+            assert np.array_equal(c["cell"], b.cell)
+            for f in ("x", "y", "ox", "oy", "w"):
+                assert rel_l2(c[f], getattr(b, f)) <= 1e-12, f
+        out.append(errs)
+        log("  step", k, {kk: "%.1e" % v[0] for kk, v in errs.items()})
+    s.destroy()
+    return out
+
+
+def test_points_bitwise(S, oracle):
+    P = oracle.Points(0)
+    cases = [(20251116, 0, 1, 0, 0, 0, 12, 0, 300), (7, 3, 2, 0, 0, 0, 8, 1000, 64),
+             (7, 3, 1, 1, 5, 0, 9, 2 ** 31 + 5, 32), (99, 1, 1, 0, 0, 28, 8, 12345, 40)]
+    for seed, step, pss, pop, coh, d0, nd, i0, n in cases:
+        got = S.slh_qmc_points(seed, step, pss, pop, coh, d0, nd, i0, n, 0)
+        stream = oracle.stream_seed(seed, step, pss, pop, coh)
+        want = P.block(stream, range(d0, d0 + nd), range(i0, i0 + n))
+        assert np.array_equal(got, want), (seed, step, pss, pop)
+    got = S.slh_qmc_points(5, 2, 2, 0, 0, 0, 6, 0, 100, 1)
+    want = oracle.Points(1).block(oracle.stream_seed(5, 2, 2, 0, 0), range(6), range(100))
+    assert np.array_equal(got, want)
+
+
+def test_c1_full_ten_steps(S, oracle):
+    """Homogeneous box, N_s = 0, 1e4 particles per pass, dt = 0.1, 10 steps,
+    S_8: the small plain-method configuration at its full size."""
+    from paper_2511_16821_amd import workloads as W
+    _run_pair(S, oracle, W.c1(), 10)
+
+
+@pytest.mark.parametrize("n_s", [1, 2])
+def test_checkerboard_small(S, oracle, n_s):
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=7, cells_per_block=4, n_s=n_s, n_particles=20000, dt=0.05,
+                       sn_order=6)
+    _run_pair(S, oracle, p, 4)
+
+
+def test_thick_voids_ns4(S, oracle):
+    from paper_2511_16821_amd import workloads as W
+    p = W.thick_with_voids(n=32, n_s=4, n_particles=20000, dt=0.01, src_half=4, sn_order=4)
+    _run_pair(S, oracle, p, 3)
+
+
+def test_random_blocks_with_cap(S, oracle):
+    """Census above the cap: the thinning path (radix select of the keys)."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.random_blocks(n=40, L=4.0, blocks=8, n_s=3, n_particles=6000, census_cap=2500,
+                        dt=0.05, sn_order=4, n_steps=3)
+    res = _run_pair(S, oracle, p, 3)
+    assert res
+
+
+def test_ragged_mesh_and_tail(S, oracle):
+    """Non-square mesh, particle count not a multiple of the block size."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=3, cells_per_block=5, n_s=1, n_particles=12347, dt=0.07,
+                       sn_order=4)
+    p["nx"] = 15
+    p["ny"] = 15
+    p["x_hi"] = 2.1
+    _run_pair(S, oracle, p, 2)
+
+
+def test_degenerate_cases(S, oracle):
+    from paper_2511_16821_amd import workloads as W
+    # no source at all
+    p = W.c1(n_particles=1000)
+    p["q"] = np.zeros_like(p["q"])
+    s = S.Solver(p)
+    s.advance(2)
+    assert np.all(s.get_flux(0) == 0.0) and s.get_stats()["census_kept"] == 0
+    s.destroy()
+    # one cell
+    p = W.homogeneous_box(n=1, L=1.0, src_cells=((0, 1), (0, 1)), n_particles=3000, n_s=2,
+                          sn_order=2)
+    _run_pair(S, oracle, p, 3)
+    # zero particles per pass
+    p = W.c1(n_particles=0)
+    s = S.Solver(p)
+    s.advance(1)
+    assert np.all(s.get_flux(0) == 0.0)
+    s.destroy()
+    # pure absorber (no scattering anywhere): collided source vanishes
+    p = W.c1(n_particles=2000, sig_s=0.0, sig_a=2.0, n_s=3)
+    _run_pair(S, oracle, p, 2)
+
+
+def test_bitwise_deterministic_across_runs(S):
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=5, cells_per_block=4, n_s=2, n_particles=30000, dt=0.05,
+                       sn_order=4)
+    res = []
+    for _ in range(2):
+        s = S.Solver(p)
+        s.advance(3)
+        res.append([s.get_flux(k).copy() for k in range(4)])
+        s.destroy()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+def test_checkpoint_resume_bitwise(S):
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=5, cells_per_block=4, n_s=1, n_particles=20000, dt=0.05,
+                       sn_order=4)
+    a = S.Solver(p)
+    a.advance(4)
+    ref = a.get_flux(0)
+    a.destroy()
+    b = S.Solver(p)
+    b.advance(2)
+    blob = b.save()
+    b.destroy()
+    c = S.Solver(p)
+    c.load(blob)
+    c.advance(2)
+    assert np.array_equal(c.get_flux(0), ref)
+    c.destroy()

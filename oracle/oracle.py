@@ -93,7 +93,10 @@ def lib():
                                  C.POINTER(_BankOut)]
         L.or_thin.restype = C.c_int64
         L.or_thin.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64,
-                              C.c_void_p, C.POINTER(C.c_double)]
+                              C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.or_thin_prob.restype = None
+        L.or_thin_prob.argtypes = [C.c_int64, C.c_int64, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
         L.or_dg_sweep.restype = C.c_int
         L.or_dg_sweep.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
@@ -299,13 +302,23 @@ def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
 
 
 def thin(cand: Bank, cap: int, thin_stream: int):
-    """Census population control (see slh_oracle.c: or_thin)."""
+    """Census population control (see slh_oracle.c: or_thin).  Returns the
+    kept bank, the weight factor and the overflow flag."""
     keep = np.zeros(cand.n, dtype=np.uint8)
     fac = C.c_double(1.0)
+    ovf = C.c_int(0)
     lib().or_thin(cand.n, _p(cand.alive), _p(cand.hid), cap, thin_stream, _p(keep),
-                  C.byref(fac))
+                  C.byref(fac), C.byref(ovf))
     idx = np.nonzero(keep)[0]
-    return cand.take(idx, fac.value), fac.value
+    return cand.take(idx, fac.value), fac.value, bool(ovf.value)
+
+
+def thin_prob(count: int, cap: int):
+    p = C.c_double(0.0)
+    sh = C.c_int(0)
+    mant = C.c_uint64(0)
+    lib().or_thin_prob(count, cap, C.byref(p), C.byref(sh), C.byref(mant))
+    return p.value, sh.value, mant.value
 
 
 def dg_sweep(nx, ny, box, sig_e, a, b, src, in_x=None, in_y=None):
@@ -380,13 +393,13 @@ class HybridOracle:
         # step 4: the remap census is the state at t_{n+1} (capped)
         thin_stream = stream_seed(self.seed, n, PASS_REMAP, POP_THIN, 0)
         n_alive = int(cand.alive.sum())
-        self.bank, factor = thin(cand, self.cap, thin_stream)
+        self.bank, factor, overflow = thin(cand, self.cap, thin_stream)
         self.step_index += 1
         return dict(step=n, phi_R=TR / adt, phi_pre=phi_pre, phi_post=phi_post, phi_c=phi_c,
                     T_pre=Tpre, T_post=Tpost, T_R=TR, bal_mc=bal1, bal_remap=bal2,
                     segments=seg1 + seg2, seg_mc=seg1, seg_remap=seg2, si_iters=iters,
                     si_resid=resid, census_alive=n_alive, census_kept=self.bank.n,
-                    thin_factor=factor, q_remap=qR)
+                    thin_factor=factor, thin_overflow=overflow, q_remap=qR)
 
     def run(self, n_steps: int):
         return [self.step() for _ in range(n_steps)]

@@ -346,44 +346,67 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Census population control: keep the cap particles with the smallest        */
-/* 64-bit thinning keys (a simple random sample without replacement, since    */
-/* the keys are a bijective hash of the unique history ids) and reweight by    */
-/* count / cap.  The paper runs steady state only and does not say how the     */
-/* census is capped; this is the reading the design notes record.             */
+/* Census population control.  The paper runs steady state only and does not  */
+/* say how the census is capped; the reading recorded in the design notes:    */
+/* when more than cap particles reach t_{n+1}, each survivor is kept with     */
+/* probability p_q and its weight divided by p_q, where p_q is                */
+/* (cap - margin) / count rounded DOWN to 11 significant bits and             */
+/* margin = ceil(4 sqrt(cap)) + 16.  The Bernoulli draw compares the          */
+/* particle's 64-bit key mix64(thin_stream ^ hid) with p_q 2^64, so a         */
+/* survivor's fate depends on its own id and on p_q only; rounding p_q to a    */
+/* coarse grid keeps it unchanged when the count moves by a few particles.    */
+/* In the rare event that more than cap survive the draw, the first cap in    */
+/* slot order are kept (and the overflow is reported).                       */
 /* ------------------------------------------------------------------------ */
 
-typedef struct { uint64_t key; int64_t g; } or_keyed;
-
-static int or_cmp_key(const void *a, const void *b)
+/* p_q = p rounded down to 11 significant bits, as mant * 2^shift with
+ * 1024 <= mant < 2048; the keep test is (key >> (64 + shift)) < mant. */
+void or_thin_prob(int64_t count, int64_t cap, double *p_q, int *keep_shift,
+                  uint64_t *keep_mant)
 {
-    const or_keyed *p = (const or_keyed *)a, *q = (const or_keyed *)b;
-    if (p->key < q->key) return -1;
-    if (p->key > q->key) return 1;
-    return 0;
+    int64_t margin = (int64_t)ceil(4.0 * sqrt((double)cap)) + 16;
+    int64_t target = cap - margin;
+    if (target < 1) target = 1;
+    const double p = (double)target / (double)count;
+    int k;
+    const double m = frexp(p, &k);             /* p = m 2^k, m in [0.5, 1) */
+    const double mant = floor(ldexp(m, 11));   /* in [1024, 2048)          */
+    *keep_mant = (uint64_t)mant;
+    *keep_shift = k - 11;                      /* p_q = mant 2^(k - 11)    */
+    *p_q = ldexp(mant, k - 11);
 }
 
-/* keep[g] = 1 for the kept candidates; returns the kept count and writes the
- * weight factor. */
+/* keep[g] = 1 for the kept candidates (slot order); returns the kept count,
+ * writes the weight factor 1/p_q (1 if no thinning) and the overflow flag. */
 int64_t or_thin(int64_t n_cand, const uint8_t *alive, const uint64_t *hid,
-                int64_t cap, uint64_t thin_stream, uint8_t *keep, double *factor)
+                int64_t cap, uint64_t thin_stream, uint8_t *keep, double *factor,
+                int *overflow)
 {
     int64_t count = 0;
     for (int64_t g = 0; g < n_cand; ++g) { keep[g] = 0; if (alive[g]) ++count; }
+    *overflow = 0;
     if (count <= cap) {
         for (int64_t g = 0; g < n_cand; ++g) keep[g] = alive[g];
         *factor = 1.0;
         return count;
     }
-    or_keyed *v = (or_keyed *)malloc(sizeof(or_keyed) * (size_t)count);
-    int64_t k = 0;
-    for (int64_t g = 0; g < n_cand; ++g)
-        if (alive[g]) { v[k].key = or_mix64(thin_stream ^ hid[g]); v[k].g = g; ++k; }
-    qsort(v, (size_t)count, sizeof(or_keyed), or_cmp_key);
-    for (int64_t j = 0; j < cap; ++j) keep[v[j].g] = 1;
-    free(v);
-    *factor = (double)count / (double)cap;
-    return cap;
+    double p_q;
+    int sh;
+    uint64_t mant;
+    or_thin_prob(count, cap, &p_q, &sh, &mant);
+    const int rs = 64 + sh;  /* key < mant 2^(64+sh)  <=>  (key >> rs) < mant */
+    int64_t kept = 0;
+    for (int64_t g = 0; g < n_cand; ++g) {
+        if (!alive[g]) continue;
+        const uint64_t key = or_mix64(thin_stream ^ hid[g]);
+        const uint64_t top = rs >= 64 ? 0 : (key >> rs);
+        if (top < mant) {
+            if (kept < cap) { keep[g] = 1; ++kept; }
+            else *overflow = 1;
+        }
+    }
+    *factor = 1.0 / p_q;
+    return kept;
 }
 
 /* ------------------------------------------------------------------------ */

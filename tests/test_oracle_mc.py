@@ -279,37 +279,92 @@ def test_balance_closes_every_pass(oracle):
                 assert b["emitted"] == pytest.approx(b["source_w"] + b["census_in_w"], rel=1e-12)
 
 
-def test_thinning_is_unbiased_sampling_without_replacement(oracle):
-    """Census cap: exactly cap survivors, reweighted by count/cap; over many
-    thinning streams each particle is kept with frequency cap/count and the
-    kept weight is the original total on average."""
+def test_thinning_probability_grid(oracle):
+    """p_q is (cap - margin)/count rounded down to 11 significant bits."""
+    for count, cap in [(2_000_000, 1_000_000), (1001, 1000), (50, 10), (10 ** 9, 10 ** 6),
+                       (3, 1)]:
+        p, sh, mant = oracle.thin_prob(count, cap)
+        margin = math.ceil(4 * math.sqrt(cap)) + 16
+        target = max(cap - margin, 1)
+        exact = target / count
+        assert 1024 <= mant < 2048 and p == mant * 2.0 ** sh
+        assert p <= exact < p * (1 + 2.0 ** -10)
+    # a few particles more or less do not move p_q (the grid is coarse)
+    base = oracle.thin_prob(2_000_000, 1_000_000)[0]
+    assert all(oracle.thin_prob(2_000_000 + d, 1_000_000)[0] == base for d in range(-5, 6))
+
+
+def test_thinning_is_unbiased_and_local(oracle):
+    """Census cap: each survivor is kept with probability p_q and reweighted
+    by 1/p_q, so over thinning streams the kept weight is the original total
+    on average; the kept set never exceeds the cap; and removing one survivor
+    changes nothing else (a survivor's fate depends only on its own key)."""
     rng = np.random.default_rng(1)
-    n = 200
+    n = 400
     cand = oracle.Bank(n)
     cand.w[:] = rng.uniform(0.5, 1.5, size=n)
-    cand.hid[:] = rng.permutation(np.arange(n, dtype=np.uint64) * np.uint64(7919))
+    cand.hid[:] = rng.permutation(np.arange(n, dtype=np.uint64) * np.uint64(7919) + np.uint64(3))
     cand.alive = (rng.uniform(size=n) < 0.8).astype(np.uint8)
     count = int(cand.alive.sum())
-    kept, f = oracle.thin(cand, 10 ** 6, 5)
-    assert kept.n == count and f == 1.0
-    cap = 60
+    kept, f, ovf = oracle.thin(cand, 10 ** 6, 5)
+    assert kept.n == count and f == 1.0 and not ovf
+    cap = 200
+    p_q = oracle.thin_prob(count, cap)[0]
     hits = np.zeros(n)
     totals = []
-    for t in range(400):
-        kept, f = oracle.thin(cand, cap, 1000 + t)
-        assert kept.n == cap and f == count / cap
-        idx = np.searchsorted(np.argsort(cand.hid), 0)  # noqa: F841 (keeps numpy happy)
+    R = 400
+    for t in range(R):
+        kept, f, ovf = oracle.thin(cand, cap, oracle.stream_seed(9, t, 2, 2))
+        assert kept.n <= cap and f == 1.0 / p_q
         m = np.isin(cand.hid, kept.hid)
         hits += m
         totals.append(kept.w.sum())
     alive = cand.alive.astype(bool)
     assert np.all(hits[~alive] == 0)
-    freq = hits[alive] / 400
-    p = cap / count
-    assert np.all(np.abs(freq - p) < 5 * math.sqrt(p * (1 - p) / 400))
+    freq = hits[alive] / R
+    assert np.all(np.abs(freq - p_q) < 5 * math.sqrt(p_q * (1 - p_q) / R))
     tot = cand.w[alive].sum()
     totals = np.array(totals)
-    assert abs(totals.mean() - tot) < 5 * totals.std(ddof=1) / math.sqrt(400)
+    assert abs(totals.mean() - tot) < 5 * totals.std(ddof=1) / math.sqrt(R)
+
+
+def test_thinning_is_local_for_large_counts(oracle):
+    """With many survivors a one-particle change of the count leaves p_q on
+    the same grid point, so removing a survivor changes only its own fate."""
+    rng = np.random.default_rng(2)
+    n = 20000
+    cand = oracle.Bank(n)
+    cand.w[:] = 1.0
+    cand.hid[:] = np.arange(n, dtype=np.uint64) * np.uint64(31) + np.uint64(11)
+    cand.alive = (rng.uniform(size=n) < 0.8).astype(np.uint8)
+    count = int(cand.alive.sum())
+    cap = next(c for c in range(8000, 9000)
+               if oracle.thin_prob(count - 1, c)[0] == oracle.thin_prob(count, c)[0])
+    kept_a, fa, _ = oracle.thin(cand, cap, oracle.stream_seed(1, 77, 2, 2))
+    first = int(np.nonzero(cand.alive)[0][0])
+    cand.alive[first] = 0
+    kept_b, fb, _ = oracle.thin(cand, cap, oracle.stream_seed(1, 77, 2, 2))
+    assert fa == fb
+    sa, sb = set(kept_a.hid.tolist()), set(kept_b.hid.tolist())
+    assert sb <= sa and len(sa - sb) <= 1
+
+
+def test_thinning_overflow_keeps_first_cap(oracle):
+    """More than cap survivors of the draw (possible when the margin is
+    swamped): the first cap in slot order are kept and the overflow flagged."""
+    n = 64
+    cand = oracle.Bank(n)
+    cand.w[:] = 1.0
+    cand.hid[:] = np.arange(n, dtype=np.uint64)
+    cand.alive = np.ones(n, dtype=np.uint8)
+    seen = False
+    for t in range(200):
+        kept, f, ovf = oracle.thin(cand, 2, oracle.stream_seed(3, t, 2, 2))
+        assert kept.n <= 2
+        if ovf:
+            seen = True
+            assert kept.n == 2
+    assert seen
 
 
 @pytest.mark.parametrize("kind,n_s,ss", [(2, 0, 0.0), (1, 1, 50.0)])

@@ -97,6 +97,13 @@ def lib():
         L.or_thin_prob.restype = None
         L.or_thin_prob.argtypes = [C.c_int64, C.c_int64, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
+        L.or_pow2_ceil.restype = C.c_double
+        L.or_pow2_ceil.argtypes = [C.c_double]
+        L.or_build_sum_tree.restype = C.POINTER(C.c_double)
+        L.or_build_sum_tree.argtypes = [C.c_void_p, C.c_int64, C.c_double,
+                                        C.POINTER(C.c_int64)]
+        L.or_tree_pick.restype = C.c_int64
+        L.or_tree_pick.argtypes = [C.POINTER(C.c_double), C.c_int64, C.c_double]
         L.or_dg_sweep.restype = C.c_int
         L.or_dg_sweep.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
@@ -299,6 +306,17 @@ def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
                            C.byref(bin_), seed, step, w_cut_rel, _p(Ta), _p(Tb), _p(bal),
                            bout_p)
     return Ta, Tb, dict(zip(BAL_NAMES, bal)), int(seg), out
+
+
+def tree_pick(q_nodal, adt, us):
+    """Cells picked by the majorant sum tree for each u in us."""
+    q_nodal = np.ascontiguousarray(q_nodal, dtype=np.float64).reshape(-1)
+    L = C.c_int64(0)
+    t = lib().or_build_sum_tree(_p(q_nodal), q_nodal.size // 4, adt, C.byref(L))
+    out = np.array([lib().or_tree_pick(t, L.value, float(u)) for u in us], dtype=np.int64)
+    total = t[1]
+    C.CDLL(None).free(C.cast(t, C.c_void_p))
+    return out, total
 
 
 def thin(cand: Bank, cap: int, thin_stream: int):

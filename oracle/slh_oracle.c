@@ -24,8 +24,10 @@
  *   - one optical depth tau = -ln u per flight, consumed at rate sigma_s across
  *     cells (Sec. 2.3, "sample next scatter at rate sigma_s").
  *   - the remap (step 3 of Sec. 2.2) emits from Q + sigma_s (phi_pre + phi_post
- *     + phi_c), with phi_c bilinear per cell from the DG solve, through a
- *     majorant CDF over cells and a signed weight.
+ *     + phi_c), with phi_c bilinear per cell from the DG solve: a cell is drawn
+ *     from per-cell majorants (max corner |q| rounded up to a power of two)
+ *     by descending a binary sum tree, the position uniformly, and the weight
+ *     carries the sign and the ratio q(x,y)/majorant.
  *
  * Parity unpinned (no closed form or independent check exists): none of the
  * functions below; the tests pin each one (points, attenuation, Erlang split,
@@ -165,6 +167,51 @@ static double or_maxabs4(const double *q)
     return m;
 }
 
+/* Smallest power of two >= v (v > 0), 0 for v = 0.  Any majorant >= max|q|
+ * keeps the emission weights unbiased; rounding it up to a power of two makes
+ * it insensitive to rounding-level changes of q. */
+double or_pow2_ceil(double v)
+{
+    if (!(v > 0.0)) return 0.0;
+    int e;
+    const double m = frexp(v, &e);        /* v = m 2^e, m in [0.5, 1) */
+    return (m == 0.5) ? v : ldexp(1.0, e);
+}
+
+/* Binary sum tree over the cell majorants (heap order, 1-based): leaves at
+ * [L, L + n) with L the smallest power of two >= n, tree[k] = tree[2k] +
+ * tree[2k+1].  Returns the array (caller frees) and L. */
+double *or_build_sum_tree(const double *q_nodal, int64_t n, double adt, int64_t *L_out)
+{
+    int64_t L = 1;
+    while (L < n) L *= 2;
+    double *t = (double *)calloc((size_t)(2 * L), sizeof(double));
+    for (int64_t i = 0; i < n; ++i) t[L + i] = adt * or_pow2_ceil(or_maxabs4(q_nodal + 4 * i));
+    for (int64_t k = L - 1; k >= 1; --k) t[k] = t[2 * k] + t[2 * k + 1];
+    *L_out = L;
+    return t;
+}
+
+/* Cell of u in (0,1): descend from the root with target u * total, going left
+ * when the target is below the left child's mass (or the right child is
+ * empty), otherwise subtracting the left mass and going right.  In exact
+ * arithmetic this is the inverse CDF of the majorants in cell order. */
+int64_t or_tree_pick(const double *t, int64_t L, double u)
+{
+    double target = u * t[1];
+    int64_t k = 1;
+    while (k < L) {
+        const double left = t[2 * k];
+        if (target < left || t[2 * k + 1] == 0.0) {
+            k = 2 * k;
+        } else {
+            target -= left;
+            k = 2 * k + 1;
+        }
+    }
+    return k - L;
+}
+
 enum { EV_CENSUS = 0, EV_COLLIDE = 1, EV_XFACE = 2, EV_YFACE = 3 };
 
 /*
@@ -197,14 +244,11 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
     for (int64_t i = 0; i < ncell; ++i) { T_a[i] = 0.0; T_b[i] = 0.0; }
     for (int k = 0; k < OB_N; ++k) bal[k] = 0.0;
 
-    /* Majorant per cell, M_i = A dt max_corner |q_i|, and its CDF in cell
-     * order (sequential sum). */
-    double *cdf = (double *)malloc(sizeof(double) * (size_t)(ncell > 0 ? ncell : 1));
-    double total = 0.0;
-    for (int64_t i = 0; i < ncell; ++i) {
-        total += area * dt * or_maxabs4(q_nodal + 4 * i);
-        cdf[i] = total;
-    }
+    /* Majorant per cell M_i = A dt mbar_i, mbar_i = max_corner |q_i| rounded
+     * up to a power of two, summed in a binary tree over the cells. */
+    int64_t L;
+    double *tree = or_build_sum_tree(q_nodal, ncell, area * dt, &L);
+    const double total = tree[1];
     const int64_t n_emit = (total > 0.0) ? n_src : 0;
     const double w_ref = (n_emit > 0) ? total / (double)n_src : 0.0;
     const double w_cut = w_cut_rel * w_ref;
@@ -240,13 +284,7 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             pidx = (uint32_t)s;
             hid = (step << 32) | (uint64_t)s;
             const double u0 = or_u01(or_point_u32(P, stream, 0, pidx));
-            const double target = u0 * total;
-            int64_t lo = 0, hi = ncell - 1; /* first i with target < cdf[i] */
-            while (lo < hi) {
-                int64_t mid = lo + (hi - lo) / 2;
-                if (target < cdf[mid]) hi = mid; else lo = mid + 1;
-            }
-            const int64_t ci = lo;
+            const int64_t ci = or_tree_pick(tree, L, u0);
             ix = (int)(ci % nx); iy = (int)(ci / nx);
             const double u1 = or_u01(or_point_u32(P, stream, 1, pidx));
             const double u2 = or_u01(or_point_u32(P, stream, 2, pidx));
@@ -261,7 +299,7 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             ox = st * cos(ph);
             oy = st * sin(ph);
             const double *qc = q_nodal + 4 * ci;
-            w = (total / (double)n_src) * (or_bilinear(qc, u1, u2) / or_maxabs4(qc));
+            w = (total / (double)n_src) * (or_bilinear(qc, u1, u2) / or_pow2_ceil(or_maxabs4(qc)));
             dcur = 6;
             bal[OB_SOURCE_W] += w;
         }
@@ -341,7 +379,7 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             if (fabs(w) < w_cut) { bal[OB_CUTOFF] += w; break; }
         }
     }
-    free(cdf);
+    free(tree);
     return segments;
 }
 

@@ -231,21 +231,35 @@ def test_qmc_vs_mc_convergence_slopes(oracle):
     assert slopes[0] < -0.75, slopes
 
 
+def _pow2ceil(v):
+    return 0.0 if v == 0 else 2.0 ** math.ceil(math.log2(v))
+
+
 def test_remap_sampler_weights(oracle):
-    """Remap emission (step 3 of Sec. 2.2): majorant-CDF cell choice, uniform
-    position, signed weight q(x,y) sum(M) / (N_p max_corner|q|).  Constant q:
-    every weight equals sum(M)/N_p.  Bilinear signed q: the weights integrate q."""
+    """Remap emission (step 3 of Sec. 2.2): cell drawn from majorants
+    M_i = A dt mbar_i (mbar = max corner |q| rounded up to a power of two),
+    uniform position, signed weight q(x,y) sum(M) / (N_p mbar_i).  Cell-constant
+    q: each weight is sum(M)/N_p q_i/mbar_i and the expected total is int q.
+    Bilinear signed q: the weights integrate q."""
     nx, ny, dt = 3, 2, 0.5
-    m = _mesh(oracle, nx, ny, (0, 1.5, 0, 1.0), 0.0, 0.0, dt)
+    # particle speed ~0: every particle is still in its birth cell at census
+    m = _mesh(oracle, nx, ny, (0, 1.5, 0, 1.0), 0.0, 0.0, dt, c=1e-12)
     pts = oracle.Points(0)
     area = 0.25
-    qc = np.repeat(np.array([0.0, 2.0, 1.0, 0.5, 0.0, 3.0]), 4)
+    qv = np.array([0.0, 2.0, 1.0, 0.5, 0.0, 3.0])
+    qc = np.repeat(qv, 4)
     n_p = 1000
     _, _, bal, _, cand = oracle.mc_pass(m, pts, 2, 0, qc, n_p, oracle.Bank(0), 3, 0, 0.0, True)
-    sumM = area * dt * qc[::4].sum()
-    w = cand.w[cand.alive.astype(bool)]
-    np.testing.assert_allclose(w, sumM / n_p, rtol=1e-15)
-    assert bal["source_w"] == pytest.approx(sumM, rel=1e-13)
+    mbar = np.array([_pow2ceil(v) for v in qv])
+    sumM = area * dt * mbar.sum()
+    alive = cand.alive.astype(bool)
+    w = cand.w[alive]
+    cells = cand.cell[alive]
+    np.testing.assert_allclose(w, sumM / n_p * qv[cells] / mbar[cells], rtol=1e-15)
+    assert np.all(qv[cells] > 0)
+    # cell frequencies follow the majorants (QMC: within a few counts)
+    counts = np.bincount(cells, minlength=nx * ny)
+    np.testing.assert_allclose(counts, n_p * mbar / mbar.sum(), atol=3)
     # bilinear signed source: E[sum w] = integral of q = sum A dt mean(corners)
     rng = np.random.default_rng(9)
     qb = rng.uniform(-1.0, 2.0, size=4 * nx * ny)
@@ -258,6 +272,24 @@ def test_remap_sampler_weights(oracle):
     tot = np.array(tot)
     assert abs(tot.mean() - integral) < 5 * tot.std(ddof=1) / math.sqrt(8) + 1e-12
     assert abs(tot.mean() - integral) < 1e-3 * abs(integral)
+
+
+def test_sum_tree_pick_is_inverse_cdf(oracle):
+    """The sum-tree descent is the inverse CDF of the majorants in cell order
+    (first i with u * total < cumsum_i); with majorants that are small powers
+    of two every sum is exact, so it must agree with numpy's searchsorted."""
+    rng = np.random.default_rng(6)
+    for n in (1, 2, 7, 64, 100, 1000):
+        qv = rng.choice([0.0, 0.25, 0.5, 1.0, 2.0, 4.0], size=n)
+        if qv.sum() == 0:
+            qv[0] = 1.0
+        us = (rng.integers(0, 2 ** 32, size=2000) + 0.5) / 2 ** 32
+        got, total = oracle.tree_pick(np.repeat(qv, 4), 1.0, us)
+        cdf = np.cumsum(qv)
+        assert total == cdf[-1]
+        want = np.searchsorted(cdf, us * total, side="right")
+        assert np.array_equal(got, want), n
+        assert np.all(qv[got] > 0)
 
 
 def test_balance_closes_every_pass(oracle):

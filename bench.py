@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the scatter-limited hybrid step on one MI355X.
+
+Workload (default): the 2-D 7x7 checkerboard of unit blocks on 140x140 cells
+(absorber blocks sigma_a = 10, scattering blocks sigma_s = 1, unit source in
+the centre block), N_s = 2, 1e6 source particles per MC pass, dt = 0.05,
+40 time steps, S_12, FP64, vacuum boundaries.  A step is one whole hybrid
+time step: the scatter-limited MC pass, the DG S_N collided solve, the remap
+source, the remap MC pass and the census cap.  Inputs are resident on the
+device before the timed region; the K timed steps are one solve from t = 0
+on a fresh solver (the W warm-up steps run on a separate solver).
+
+Prints one JSON line: segments/s (value), per-step time, the roofline of the
+dominant kernel (HIP events recorded by the library around each MC-pass
+launch on its stream), the FP32-tracking variant with its relative L2 error
+against the FP64 path, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "track segments/s FP32 vs FP64 at fixed L2 error; p50/p99 batched solve latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes: per segment the (sigma_s, sigma_a) gather and one FP64
+# tally read-modify-write; per census particle its state (x, y, Ox, Oy, w,
+# cell, history id) read once per pass, and written once by the remap pass
+SEG_BYTES = {0: 16 + 16, 1: 8 + 16}
+CENSUS_BYTES = {0: 5 * 8 + 4 + 8, 1: 5 * 4 + 4 + 8}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_problem(args, precision):
+    from paper_2511_16821_amd import workloads as W
+    kw = dict(n_s=args.ns, precision=precision)
+    if args.particles:
+        kw["n_particles"] = args.particles
+    if args.workload == "c2":
+        return W.c2(**kw)
+    if args.workload == "c1":
+        return W.c1(**kw)
+    if args.workload == "c3":
+        return W.c3(**kw)
+    if args.workload == "c5":
+        return W.c5(**kw)
+    if args.workload == "c5_sub":
+        return W.c5_subproblem(**kw)
+    raise SystemExit("unknown workload " + args.workload)
+
+
+def describe(p):
+    return ("%dx%d cells on [%g,%g]x[%g,%g], N_s=%d, %d particles/pass, dt=%g, S_%d"
+            % (p["nx"], p["ny"], p["x_lo"], p["x_hi"], p["y_lo"], p["y_hi"], p["n_s"],
+               p["n_particles"], p["dt"], p["sn_order"]))
+
+
+def timed_run(S, torch, p, steps, warmup):
+    if warmup > 0:
+        w = S.Solver(p)
+        w.advance(warmup, allow_not_converged=True)
+        w.synchronize()
+        w.destroy()
+    s = S.Solver(p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.advance(steps, allow_not_converged=True)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = s.get_stats()
+    s.destroy()
+    return t1 - t0, st
+
+
+def roofline(st, steps, prec):
+    kinds = [("k_mc_pass<step 1>", st["ms_kernel_mc_total"], st["seg_mc_total"], False),
+             ("k_mc_pass<step 3>", st["ms_kernel_remap_total"], st["seg_remap_total"], True)]
+    name, ms, seg, remap = max(kinds, key=lambda k: k[1])
+    byts = SEG_BYTES[prec] * seg + CENSUS_BYTES[prec] * st["census_in_total"]
+    if remap:
+        byts += (CENSUS_BYTES[prec] + 1) * st["census_out_total"]
+    per_launch_bytes = byts / steps
+    per_launch_s = ms * 1e-3 / steps
+    achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": name, "avg_launch_ms": round(ms / steps, 4),
+            "bytes_per_launch": int(per_launch_bytes),
+            "segments_per_launch": int(seg / steps)}
+
+
+def cpu_baseline(p, steps):
+    from oracle import oracle as O
+    O.build()
+    o = O.HybridOracle(p)
+    t0 = time.perf_counter()
+    seg = 0
+    for _ in range(steps):
+        seg += o.step()["segments"]
+    dt = time.perf_counter() - t0
+    return {"value": seg / dt, "unit": "segments/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the %d steps of the same workload (same seed), "
+                      "single-threaded C oracle, %.1f s" % (steps, p["n_steps"], dt)}
+
+
+def fp32_error(S, p64, p32, steps):
+    """Max over steps of rel-L2(phi_R FP32-tracking, phi_R FP64), same seed."""
+    import numpy as np
+    a, b = S.Solver(p64), S.Solver(p32)
+    worst = 0.0
+    for _ in range(steps):
+        a.advance(1, allow_not_converged=True)
+        b.advance(1, allow_not_converged=True)
+        x, y = a.get_flux(0), b.get_flux(0)
+        worst = max(worst, float(np.linalg.norm(y - x) / max(np.linalg.norm(x), 1e-300)))
+    a.destroy()
+    b.destroy()
+    return worst
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the "
+                    "workload's step count)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--ns", type=int, default=2)
+    ap.add_argument("--particles", type=int, default=None)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no inter-GPU sharding); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_2511_16821_amd import slh as S
+    S.lib()
+
+    p64 = make_problem(args, 0)
+    steps = args.steps or int(p64["n_steps"])
+    log("workload:", describe(p64), "steps", steps)
+    wall, st = timed_run(S, torch, p64, steps, args.warmup)
+    seg = st["seg_mc_total"] + st["seg_remap_total"]
+    value = seg / wall
+    log("fp64: %.3f s, %.3e segments/s, kernel ms mc %.1f remap %.1f" %
+        (wall, value, st["ms_kernel_mc_total"], st["ms_kernel_remap_total"]))
+    out = {
+        "metric": METRIC, "value": value, "unit": "segments/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "checkerboard 7x7 unit blocks (absorber sigma_a=10 / scatterer "
+                               "sigma_s=1), unit source in the centre block, " + describe(p64)
+                   if args.workload == "c2" else args.workload + ": " + describe(p64),
+                   "n_steps": steps, "precision": "fp64", "points": "sobol-owen"},
+        "roofline": roofline(st, steps, 0),
+        "segments": int(seg),
+    }
+    if not args.no_fp32:
+        p32 = make_problem(args, 1)
+        wall32, st32 = timed_run(S, torch, p32, steps, args.warmup)
+        seg32 = st32["seg_mc_total"] + st32["seg_remap_total"]
+        err = fp32_error(S, p64, p32, steps)
+        out["fp32_track"] = {"value": seg32 / wall32, "unit": "segments/s",
+                             "ms_per_step": 1e3 * wall32 / steps,
+                             "rel_l2_vs_fp64_max_over_steps": err,
+                             "roofline": roofline(st32, steps, 1)}
+        log("fp32-track: %.3f s, %.3e segments/s, rel-L2 vs fp64 %.2e" %
+            (wall32, seg32 / wall32, err))
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p64, args.cpu_steps)
+        log("cpu oracle: %.3e segments/s" % out["cpu_baseline"]["value"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,8 +127,20 @@ typedef struct {
     int64_t census_alive;    /* last step: census candidates at t_{n+1}      */
     int64_t census_kept;     /* last step: bank size after the cap           */
     double thin_factor;      /* last step: weight factor of the cap          */
-    uint64_t segments_total; /* all passes, all steps                        */
+    uint64_t segments_total; /* last step, both passes                       */
     double ms_mc, ms_dg, ms_remap, ms_census; /* last step, stage times      */
+    /* Totals since creation (or the last slh_load), for throughput and
+     * roofline accounting.  Kernel times are HIP events recorded on the
+     * solver's stream immediately around each MC-pass kernel launch. */
+    double ms_kernel_mc_total;      /* step-1 (scatter-limited) pass kernels */
+    double ms_kernel_remap_total;   /* step-3 (remap) pass kernels           */
+    uint64_t seg_mc_total;          /* segments of step-1 passes             */
+    uint64_t seg_remap_total;       /* segments of step-3 passes             */
+    uint64_t census_in_total;       /* census-in particles over all steps    */
+    uint64_t census_out_total;      /* census candidates written (step 3)    */
+    uint64_t steps_total;           /* steps accounted in the totals         */
+    uint64_t thin_overflow_total;   /* steps whose census draw exceeded the
+                                       cap (first cap in slot order kept)   */
 } slh_stats;
 
 typedef struct slh_solver slh_solver;

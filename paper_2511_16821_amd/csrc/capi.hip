@@ -156,16 +156,15 @@ static Sizes sizes_of(const slh_problem* p) {
   size_t b = 0;
   const size_t nc = (size_t)z.n_cells;
   b += nc * (16 + 8 + 8 + 8 + 8);            // mat64, mat32, sig_s, sig_e, q
-  b += nc * (32 + 8 + 8) * 2;                // nodal sources, M, cdf (pass 1 and 2)
-  b += nc * 16 * 3;                          // tallies
-  b += nc * 8 * 3 + nc * 32 * 2;             // phi_pre/post/R, phi_c x2
+  b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 2;  // nodal sources, trees
+  b += nc * 8 * kTallyStride * 3;            // tallies
+  b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
   b += (size_t)z.n_dir * nc * 32;            // per-direction planes
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
-  b += scan_tmp_elems(z.n_cells) * 8;
   b += (size_t)z.cap * bank * 2;             // census banks
   b += (size_t)z.n_cand * (bank + 1 + 8 + 8);  // staging, alive, flags, inclusive scan
   b += scan_tmp_elems(z.n_cand) * 8;
-  b += 256 * 8 + sizeof(DevState) + 32 * 32 * 4 + 64 * 8;
+  b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8;
   z.bytes = b;
   return z;
 }
@@ -182,7 +181,10 @@ struct BalStore {
   unsigned long long bal[2 * B_NFIELDS];
   unsigned long long segments, particles, alive, killed;
   double unit_W;
-  double pad[3];
+  long long n_in;
+  int thin_overflow;  // of the census that this pass read
+  int pad0;
+  double pad[1];
 };
 
 __global__ void k_snapshot(const DevState* st, BalStore* out) {
@@ -194,6 +196,8 @@ __global__ void k_snapshot(const DevState* st, BalStore* out) {
     out->alive = st->alive;
     out->killed = st->killed;
     out->unit_W = st->unit_W;
+    out->n_in = st->n_in;
+    out->thin_overflow = st->thin_overflow;
   }
 }
 
@@ -222,24 +226,26 @@ struct slh_solver {
   std::vector<void*> allocs;
   std::vector<double> h_sig_s, h_sig_a, h_q;
   double hx, hy, area, adt, tau, si_tol;
+  long long thin_margin = 0;
   int si_max;
 
   // device memory
   double2* mat64 = nullptr;
   float2* mat32 = nullptr;
   double *sig_s = nullptr, *sig_e = nullptr, *q = nullptr;
-  double *qn1 = nullptr, *M1 = nullptr, *cdf1 = nullptr;
-  double *qnR = nullptr, *MR = nullptr, *cdfR = nullptr;
+  double *qn1 = nullptr, *tree1 = nullptr;
+  double *qnR = nullptr, *treeR = nullptr;
+  long long tree_L = 1;
   unsigned long long *Tpre = nullptr, *Tpost = nullptr, *TR = nullptr;
   double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr,
          *phi_c2 = nullptr;
-  double *psi = nullptr, *dg_part = nullptr, *dirs = nullptr, *scan_f = nullptr;
+  double *psi = nullptr, *dg_part = nullptr, *dirs = nullptr;
+  double* dg_src = nullptr;
   int n_part = 1;
   void* bank_mem[2] = {nullptr, nullptr};
   void* stage_mem = nullptr;
   uint8_t* alive = nullptr;
   long long *flags = nullptr, *incl = nullptr, *scan_i = nullptr;
-  unsigned long long* hist = nullptr;
   uint32_t* sobol = nullptr;
   DevState* st = nullptr;
   BalStore* bal_store = nullptr;  // [2]
@@ -253,7 +259,14 @@ struct slh_solver {
   bool si_conv = true;
   unsigned long long seg_total = 0;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t evk[4] = {nullptr, nullptr, nullptr, nullptr};  // around the MC kernels
   bool have_events = false;
+  BalStore* h_bal = nullptr;   // pinned copies of the pass snapshots
+  bool pending[2] = {false, false};
+  double k_ms[2] = {0.0, 0.0};
+  unsigned long long k_seg[2] = {0ull, 0ull};
+  unsigned long long census_in_total = 0ull, census_out_total = 0ull, steps_total = 0ull;
+  unsigned long long thin_overflow_total = 0ull;
 
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 8;
@@ -274,7 +287,11 @@ struct slh_solver {
     allocs.clear();
     if (h_res) (void)hipHostFree(h_res);
     h_res = nullptr;
+    if (h_bal) (void)hipHostFree(h_bal);
+    h_bal = nullptr;
     for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : evk)
       if (e) (void)hipEventDestroy(e);
   }
 
@@ -321,25 +338,24 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->sig_s, double, nc);
   ALLOC(s->sig_e, double, nc);
   ALLOC(s->q, double, nc);
+  s->tree_L = tree_leaves(nc);
   ALLOC(s->qn1, double, 4 * nc);
-  ALLOC(s->M1, double, nc);
-  ALLOC(s->cdf1, double, nc);
+  ALLOC(s->tree1, double, 2 * s->tree_L);
   ALLOC(s->qnR, double, 4 * nc);
-  ALLOC(s->MR, double, nc);
-  ALLOC(s->cdfR, double, nc);
-  ALLOC(s->Tpre, unsigned long long, 2 * nc);
-  ALLOC(s->Tpost, unsigned long long, 2 * nc);
-  ALLOC(s->TR, unsigned long long, 2 * nc);
+  ALLOC(s->treeR, double, 2 * s->tree_L);
+  ALLOC(s->Tpre, unsigned long long, kTallyStride * nc);
+  ALLOC(s->Tpost, unsigned long long, kTallyStride * nc);
+  ALLOC(s->TR, unsigned long long, kTallyStride * nc);
   ALLOC(s->phi_pre, double, nc);
   ALLOC(s->phi_post, double, nc);
   ALLOC(s->phi_R, double, nc);
   ALLOC(s->phi_c, double, 4 * nc);
   ALLOC(s->phi_c2, double, 4 * nc);
   ALLOC(s->psi, double, (size_t)z.n_dir * 4 * nc);
+  ALLOC(s->dg_src, double, 4 * nc);
   s->n_part = dg_reduce_partials(4 * nc);
   ALLOC(s->dg_part, double, 2 * s->n_part + 2);
   ALLOC(s->dirs, double, 3 * z.n_dir);
-  ALLOC(s->scan_f, double, scan_tmp_elems(nc));
   s->bank_mem[0] = s->dalloc(s->bank_bytes(z.cap));
   s->bank_mem[1] = s->dalloc(s->bank_bytes(z.cap));
   s->stage_mem = s->dalloc(s->bank_bytes(z.n_cand));
@@ -349,24 +365,24 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->flags, long long, z.n_cand);
   ALLOC(s->incl, long long, z.n_cand);
   ALLOC(s->scan_i, long long, scan_tmp_elems(z.n_cand));
-  ALLOC(s->hist, unsigned long long, 256);
   ALLOC(s->sobol, uint32_t, 32 * 32);
   ALLOC(s->st, DevState, 1);
   ALLOC(s->bal_store, BalStore, 2);
 #undef ALLOC
   if (hipHostMalloc((void**)&s->h_res, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(SLH_E_OUT_OF_MEMORY, "pinned host allocation failed");
+  if (hipHostMalloc((void**)&s->h_bal, 2 * sizeof(BalStore), hipHostMallocDefault) != hipSuccess)
+    return fail(SLH_E_OUT_OF_MEMORY, "pinned host allocation failed");
 
   // fields and derived arrays
   std::vector<double2> m64(nc);
   std::vector<float2> m32(nc);
-  std::vector<double> se(nc), qn(4 * nc), M(nc);
+  std::vector<double> se(nc), qn(4 * nc);
   for (long long i = 0; i < nc; ++i) {
     m64[i] = make_double2(s->h_sig_s[i], s->h_sig_a[i]);
     m32[i] = make_float2((float)s->h_sig_s[i], (float)s->h_sig_a[i]);
     se[i] = s->h_sig_a[i] + s->h_sig_s[i] + s->tau / (p.c * p.dt);
     for (int k = 0; k < 4; ++k) qn[4 * i + k] = s->h_q[i];
-    M[i] = s->adt * fabs(s->h_q[i]);
   }
   const std::vector<double> dirs = product_quadrature(p.sn_order);
   hipStream_t st = s->stream;
@@ -376,10 +392,9 @@ static slh_status setup(slh_solver* s) {
   HIP_TRY(hipMemcpyAsync(s->sig_e, se.data(), 8 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->q, s->h_q.data(), 8 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->qn1, qn.data(), 32 * nc, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(s->M1, M.data(), 8 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->dirs, dirs.data(), 8 * dirs.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->sobol, sobol_table_host(), 4 * 32 * 32, hipMemcpyHostToDevice, st));
-  HIP_TRY(scan_inclusive_f64(s->M1, s->cdf1, nc, s->scan_f, st));
+  HIP_TRY(launch_build_tree(s->qn1, nc, s->adt, s->tree1, st));
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, st, s->st);
   HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
   HIP_TRY(launch_fill_f64(s->phi_pre, nc, 0.0, st));
@@ -387,8 +402,8 @@ static slh_status setup(slh_solver* s) {
   HIP_TRY(launch_fill_f64(s->phi_R, nc, 0.0, st));
   HIP_TRY(launch_fill_u64((unsigned long long*)s->bal_store, 2 * sizeof(BalStore) / 8, 0ull, st));
   HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
-  HIP_TRY(launch_fill_u64(s->hist, 256, 0ull, st));
   for (auto& e : s->ev) HIP_TRY(hipEventCreate(&e));
+  for (auto& e : s->evk) HIP_TRY(hipEventCreate(&e));
   s->have_events = true;
   HIP_TRY(hipStreamSynchronize(st));  // host vectors above go out of scope
   return SLH_OK;
@@ -406,7 +421,8 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.c = p.c;
   a.mat64 = s->mat64;
   a.mat32 = s->mat32;
-  a.cdf = kind == 1 ? s->cdf1 : s->cdfR;
+  a.tree = kind == 1 ? s->tree1 : s->treeR;
+  a.tree_L = s->tree_L;
   a.qn = kind == 1 ? s->qn1 : s->qnR;
   a.n_cells = s->z.n_cells;
   a.n_src = s->z.n_p;
@@ -434,6 +450,30 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   return a;
 }
 
+// Folds the kernel times and counters of finished passes into the totals.
+// Called only after the stream has passed the pass's snapshot copy.
+static slh_status collect(slh_solver* s, int k) {
+  if (!s->pending[k]) return SLH_OK;
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, s->evk[2 * k], s->evk[2 * k + 1]));
+  s->k_ms[k] += ms;
+  s->k_seg[k] += s->h_bal[k].segments;
+  s->census_in_total += (unsigned long long)s->h_bal[k].n_in;
+  if (k == 0 && s->h_bal[0].thin_overflow) s->thin_overflow_total += 1;
+  if (k == 1) {
+    s->census_out_total += s->h_bal[1].alive;
+    s->steps_total += 1;
+  }
+  s->pending[k] = false;
+  return SLH_OK;
+}
+
+static slh_status collect_all(slh_solver* s) {
+  slh_status r = collect(s, 0);
+  if (r != SLH_OK) return r;
+  return collect(s, 1);
+}
+
 static slh_status run_step(slh_solver* s) {
   const slh_problem& p = s->prob;
   const Sizes& z = s->z;
@@ -442,17 +482,27 @@ static slh_status run_step(slh_solver* s) {
   const double inv_adt = 1.0 / s->adt;
   const double cdt = p.c * p.dt;
   const int grid = mc_grid(s, z.cap + z.n_p);
+  if (s->pending[0]) {  // only when the previous step had no SI sync
+    HIP_TRY(hipStreamSynchronize(st));
+    slh_status r = collect_all(s);
+    if (r != SLH_OK) return r;
+  }
 
   HIP_TRY(hipEventRecord(s->ev[0], st));
   // ---- step 1: scatter-limited leg from Q and the census ----
-  HIP_TRY(launch_pass_begin(s->st, s->cdf1, nc, cdt, st));
-  HIP_TRY(launch_fill_u64(s->Tpre, 2 * nc, 0ull, st));
-  HIP_TRY(launch_fill_u64(s->Tpost, 2 * nc, 0ull, st));
+  HIP_TRY(launch_pass_begin(s->st, s->tree1, cdt, st));
+  HIP_TRY(launch_fill_u64(s->Tpre, kTallyStride * nc, 0ull, st));
+  HIP_TRY(launch_fill_u64(s->Tpost, kTallyStride * nc, 0ull, st));
+  HIP_TRY(hipEventRecord(s->evk[0], st));
   HIP_TRY(launch_mc_pass(pass_args(s, 1), z.fp32, grid, st));
+  HIP_TRY(hipEventRecord(s->evk[1], st));
   HIP_TRY(launch_tally_to_flux(s->Tpre, nc, s->st, inv_adt, s->phi_pre, st));
   HIP_TRY(launch_tally_to_flux(s->Tpost, nc, s->st, inv_adt, s->phi_post, st));
   hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
                      s->bal_store + 0);
+  HIP_TRY(hipMemcpyAsync(s->h_bal + 0, s->bal_store + 0, sizeof(BalStore),
+                         hipMemcpyDeviceToHost, st));
+  s->pending[0] = true;
   HIP_TRY(hipEventRecord(s->ev[1], st));
 
   // ---- step 2: collided DG S_N solve, source iteration ----
@@ -467,6 +517,7 @@ static slh_status run_step(slh_solver* s) {
   d.sig_e = s->sig_e;
   d.sig_s = s->sig_s;
   d.phi_post = s->phi_post;
+  d.src = s->dg_src;
   d.psi = s->psi;
   s->si_it = 0;
   s->si_conv = false;
@@ -479,6 +530,10 @@ static slh_status run_step(slh_solver* s) {
     HIP_TRY(hipMemcpyAsync(s->h_res, s->dg_part + 2 * s->n_part, 2 * sizeof(double),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (it == 0) {
+      slh_status r = collect_all(s);
+      if (r != SLH_OK) return r;
+    }
     std::swap(s->phi_c, s->phi_c2);
     s->si_it = it + 1;
     const double dn = sqrt(s->h_res[0]), nrm = sqrt(s->h_res[1]);
@@ -490,39 +545,41 @@ static slh_status run_step(slh_solver* s) {
   HIP_TRY(hipEventRecord(s->ev[2], st));
 
   // ---- step 3: remap source and scatter-free leg ----
-  HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c, s->adt,
-                              s->qnR, s->MR, st));
-  HIP_TRY(scan_inclusive_f64(s->MR, s->cdfR, nc, s->scan_f, st));
-  HIP_TRY(launch_pass_begin(s->st, s->cdfR, nc, cdt, st));
-  HIP_TRY(launch_fill_u64(s->TR, 2 * nc, 0ull, st));
+  HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c, s->qnR,
+                              st));
+  HIP_TRY(launch_build_tree(s->qnR, nc, s->adt, s->treeR, st));
+  HIP_TRY(launch_pass_begin(s->st, s->treeR, cdt, st));
+  HIP_TRY(launch_fill_u64(s->TR, kTallyStride * nc, 0ull, st));
   HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
+  HIP_TRY(hipEventRecord(s->evk[2], st));
   HIP_TRY(launch_mc_pass(pass_args(s, 2), z.fp32, grid, st));
+  HIP_TRY(hipEventRecord(s->evk[3], st));
   HIP_TRY(launch_tally_to_flux(s->TR, nc, s->st, inv_adt, s->phi_R, st));
   hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
                      s->bal_store + 1);
+  HIP_TRY(hipMemcpyAsync(s->h_bal + 1, s->bal_store + 1, sizeof(BalStore),
+                         hipMemcpyDeviceToHost, st));
+  s->pending[1] = true;
   HIP_TRY(hipEventRecord(s->ev[3], st));
 
   // ---- step 4: the remap census is the state at t_{n+1} (capped) ----
   const uint64_t thin_stream = stream_seed(p.seed, (uint64_t)s->step, 2u, 2u, 0ull);
   void* nb = s->bank_mem[1 - s->cur];
-  const uint64_t* stage_hid = z.fp32 ? s->bank_at<float>(s->stage_mem, z.n_cand).hid
-                                      : s->bank_at<double>(s->stage_mem, z.n_cand).hid;
-  HIP_TRY(launch_census_select(s->alive, stage_hid, z.n_cand, z.cap, thin_stream, s->st,
-                               s->hist, st));
+  HIP_TRY(launch_thin_params(s->st, z.cap, s->thin_margin, st));
   if (z.fp32) {
     Bank<float> src = s->bank_at<float>(s->stage_mem, z.n_cand);
     HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, thin_stream, s->st, s->flags, st));
     HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
-    HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, s->bank_at<float>(nb, z.cap),
-                                         s->st, st));
+    HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, z.cap,
+                                         s->bank_at<float>(nb, z.cap), s->st, st));
   } else {
     Bank<double> src = s->bank_at<double>(s->stage_mem, z.n_cand);
     HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, thin_stream, s->st, s->flags, st));
     HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
-    HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand,
+    HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand, z.cap,
                                           s->bank_at<double>(nb, z.cap), s->st, st));
   }
-  HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, st));
+  HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, z.cap, st));
   HIP_TRY(hipEventRecord(s->ev[4], st));
   s->cur = 1 - s->cur;
   s->step += 1;
@@ -561,6 +618,7 @@ extern "C" slh_status slh_create(const slh_problem* problem, void* hip_stream,
   s->tau = problem->time_closure > 0.0 ? problem->time_closure : 2.0;
   s->si_tol = problem->si_tol > 0.0 ? problem->si_tol : 1e-12;
   s->si_max = problem->si_max_iter > 0 ? problem->si_max_iter : 200;
+  s->thin_margin = (long long)ceil(4.0 * sqrt((double)s->z.cap)) + 16;
   slh_status r = setup(s);
   if (r != SLH_OK) {
     s->release();
@@ -660,6 +718,18 @@ extern "C" slh_status slh_get_stats(slh_solver* s, slh_stats* out) {
   out->census_kept = d.n_kept;
   out->thin_factor = d.thin_factor;
   out->segments_total = b[0].segments + b[1].segments;
+  {
+    slh_status r = collect_all(s);
+    if (r != SLH_OK) return r;
+  }
+  out->ms_kernel_mc_total = s->k_ms[0];
+  out->ms_kernel_remap_total = s->k_ms[1];
+  out->seg_mc_total = s->k_seg[0];
+  out->seg_remap_total = s->k_seg[1];
+  out->census_in_total = s->census_in_total;
+  out->census_out_total = s->census_out_total;
+  out->steps_total = s->steps_total;
+  out->thin_overflow_total = s->thin_overflow_total;
   if (s->step > 0) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, s->ev[0], s->ev[1]) == hipSuccess) out->ms_mc = ms;
@@ -784,6 +854,11 @@ extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->step = (long long)h[2];
+  s->pending[0] = s->pending[1] = false;
+  s->k_ms[0] = s->k_ms[1] = 0.0;
+  s->k_seg[0] = s->k_seg[1] = 0ull;
+  s->census_in_total = s->census_out_total = s->steps_total = 0ull;
+  s->thin_overflow_total = 0ull;
   return SLH_OK;
 }
 

@@ -1,5 +1,5 @@
 // (Q)MC pass of the scatter-limited hybrid method (Sec. 2.3 of the paper):
-// emission from a majorant CDF over cells, tracking with at most n_lim
+// emission from per-cell majorants (sum-tree descent), tracking with at most n_lim
 // scatters per history (implicit capture with sigma_a before the limit,
 // attenuation with sigma_t after it), exact track-length tallies
 // w (1 - e^{-sigma l}) / sigma per segment, and the census write of the remap
@@ -52,29 +52,50 @@ __device__ __forceinline__ double bilinear(const double* q, double a, double b) 
   return q[0] + a * (q[1] - q[0]) + b * (q[2] - q[0]) + a * b * (q[0] - q[1] - q[2] + q[3]);
 }
 
-// First cell i with target < cdf[i] (inverse CDF of the majorant).
-__device__ __forceinline__ long long cdf_search(const double* __restrict__ cdf, long long n,
-                                                double target) {
-  long long lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const long long mid = lo + ((hi - lo) >> 1);
-    if (target < cdf[mid]) hi = mid; else lo = mid + 1;
+// Cell of u: descend the majorant sum tree from the root with target
+// u * total, left while the target is below the left mass (or the right
+// subtree is empty), else subtract the left mass and go right.
+constexpr int kTreeTop = 1024;  // nodes [0, kTreeTop) of the tree are staged in LDS
+
+__device__ __forceinline__ long long tree_pick(const double* __restrict__ t,
+                                               const double* __restrict__ top, long long L,
+                                               double u) {
+  double target = u * top[1];
+  long long k = 1;
+  while (k < L) {
+    const bool in_lds = 2 * k + 1 < kTreeTop;
+    const double left = in_lds ? top[2 * k] : t[2 * k];
+    const double right = in_lds ? top[2 * k + 1] : t[2 * k + 1];
+    if (target < left || right == 0.0) {
+      k = 2 * k;
+    } else {
+      target -= left;
+      k = 2 * k + 1;
+    }
   }
-  return lo;
+  return k - L;
 }
 
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
   __shared__ unsigned long long s_bal[2 * B_NFIELDS];
   __shared__ unsigned long long s_cnt[4];
+  __shared__ uint32_t s_sobol[kSobolDims * 32];
+  __shared__ double s_top[kTreeTop];
   if (threadIdx.x < 2 * B_NFIELDS) s_bal[threadIdx.x] = 0ull;
   if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0ull;
+  for (int k = threadIdx.x; k < kSobolDims * 32; k += blockDim.x) s_sobol[k] = a.sobol[k];
+  {
+    const long long ntop = 2 * a.tree_L < kTreeTop ? 2 * a.tree_L : kTreeTop;
+    for (int k = threadIdx.x; k < kTreeTop; k += blockDim.x)
+      s_top[k] = (k >= 1 && k < ntop) ? a.tree[k] : 0.0;
+  }
   __syncthreads();
 
   DevState* st = a.st;
   const int lane = __lane_id();
   const long long n_in = st->n_in;
-  const double total = a.n_cells > 0 ? a.cdf[a.n_cells - 1] : 0.0;
+  const double total = s_top[1];
   const long long n_emit = (total > 0.0) ? a.n_src : 0;
   const unsigned long long n_tot = (unsigned long long)(n_in + n_emit);
   const double w_src = n_emit > 0 ? total / (double)a.n_src : 0.0;
@@ -139,14 +160,14 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
               stream = src_stream;
               pidx = (uint32_t)s;
               hid = (a.step << 32) | (uint64_t)s;
-              const double u0 = u01_f64(point_u32(a.sobol, a.points, stream, 0u, pidx));
-              const long long ci = cdf_search(a.cdf, a.n_cells, u0 * total);
+              const double u0 = u01_f64(point_u32(s_sobol, a.points, stream, 0u, pidx));
+              const long long ci = tree_pick(a.tree, s_top, a.tree_L, u0);
               ix = (int)(ci % a.nx); iy = (int)(ci / a.nx);
-              const R u1 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 1u, pidx));
-              const R u2 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 2u, pidx));
-              const R u3 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 3u, pidx));
-              const R u4 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 4u, pidx));
-              const R u5 = PointU<R>::u(point_u32(a.sobol, a.points, stream, 5u, pidx));
+              const R u1 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 1u, pidx));
+              const R u2 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 2u, pidx));
+              const R u3 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 3u, pidx));
+              const R u4 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 4u, pidx));
+              const R u5 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 5u, pidx));
               px = hx * u1;
               py = hy * u2;
               trel = u3 * dt;
@@ -156,12 +177,12 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
               ox = sn * cp;
               oy = sn * sp;
               const double* q = a.qn + 4 * ci;
-              w = (R)(w_src * (bilinear(q, (double)u1, (double)u2) / maxabs4(q)));
+              w = (R)(w_src * (bilinear(q, (double)u1, (double)u2) / pow2_ceil(maxabs4(q))));
               dcur = 6;
             }
             w0 = (double)w;
             if (n < n_lim) {
-              tau = -log(PointU<R>::u(point_u32(a.sobol, a.points, stream, dcur, pidx)));
+              tau = -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, dcur, pidx)));
               dcur++;
             }
           }
@@ -197,10 +218,10 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
     const R em = expm1(-z);
     const R contrib = (sig > (R)0) ? w * (-em) / sig : w * l;
     {
-      long long hi, lo;
       const double cd = (double)contrib;
-      fix_split(cd, inv_T, hi, lo);
-      fix_atomic_add((pre ? a.Ta : a.Tb) + 2 * (long long)cell, hi, lo);
+      const long long v = fix_round(cd, inv_T);
+      if (v) atomicAdd((pre ? a.Ta : a.Tb) + kTallyStride * (long long)cell,
+                       (unsigned long long)v);
       acc_abs += (double)sa * cd;
       if (!pre) acc_sca += (double)ss * cd;
     }
@@ -218,8 +239,8 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
       px += ox * l;
       py += oy * l;
       // isotropic re-emission, scatter counter n <- n + 1
-      const R ua = PointU<R>::u(point_u32(a.sobol, a.points, stream, dcur, pidx));
-      const R ub = PointU<R>::u(point_u32(a.sobol, a.points, stream, dcur + 1u, pidx));
+      const R ua = PointU<R>::u(point_u32(s_sobol, a.points, stream, dcur, pidx));
+      const R ub = PointU<R>::u(point_u32(s_sobol, a.points, stream, dcur + 1u, pidx));
       dcur += 2;
       const R sn = (R)2 * sqrt(ua * ((R)1 - ua));
       R sp, cp;
@@ -228,7 +249,7 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
       oy = sn * sp;
       n++;
       if (n < n_lim) {
-        tau = -log(PointU<R>::u(point_u32(a.sobol, a.points, stream, dcur, pidx)));
+        tau = -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, dcur, pidx)));
         dcur++;
       }
     } else if (ev == EV_XFACE) {

@@ -70,6 +70,14 @@ __device__ __forceinline__ uint32_t point_u32(const uint32_t* __restrict__ V, in
 
 // u in (0,1) from a point word: FP64 keeps all 32 bits; FP32 keeps the top
 // 23 bits so that (m + 1/2) 2^-23 is exact and never rounds to 0 or 1.
+// Smallest power of two >= v (v > 0), 0 for v = 0: the cell majorant.
+__host__ __device__ __forceinline__ double pow2_ceil(double v) {
+  if (!(v > 0.0)) return 0.0;
+  int e;
+  const double m = frexp(v, &e);
+  return (m == 0.5) ? v : ldexp(1.0, e);
+}
+
 __device__ __forceinline__ double u01_f64(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
 __device__ __forceinline__ float u01_f32(uint32_t x) {
   return ((float)(x >> 9) + 0.5f) * 0x1p-23f;
@@ -84,15 +92,22 @@ template <> struct PointU<float> {
 };
 
 // ---------------------------------------------------------------------------
-// Order-independent fixed-point accumulation.  A value v is split at a
-// power-of-two unit u into hi = trunc(v/u) and lo = rint(frac(v/u) 2^24); the
-// two 64-bit words are summed with integer atomics, so a sum does not depend
-// on the order of its terms (bitwise reproducible for any grid or schedule).
-// The unit is chosen per pass from a bound B on every partial sum
-// (u = 2^(ceil(log2 B) - 61)); |lo| <= 2^24 allows 2^38 terms per word.
+// Order-independent fixed-point accumulation.  Sums that must not depend on
+// the schedule are kept as 64-bit integers in a power-of-two unit u chosen per
+// pass from a bound B on every partial sum, u = 2^(ceil(log2 B) - 61), so no
+// partial sum can overflow.  Integer addition is associative, so a sum is
+// bitwise the same for any grid, schedule or order of its terms.
+//   - Track-length tallies: one word per cell, each contribution rounded to
+//     the nearest unit (error <= u/2 <= B 2^-62 per contribution).
+//   - Balance sums (few, accumulated per block in LDS first): two words,
+//     hi = trunc(v/u) and lo = rint(frac(v/u) 2^24), |lo| <= 2^24 per term.
 // ---------------------------------------------------------------------------
 
 constexpr double kLoScale = 16777216.0;  // 2^24
+
+__device__ __forceinline__ long long fix_round(double v, double inv_unit) {
+  return (long long)rint(v * inv_unit);
+}
 
 __device__ __forceinline__ void fix_split(double v, double inv_unit, long long& hi,
                                           long long& lo) {
@@ -109,11 +124,9 @@ __host__ __device__ __forceinline__ double fix_value(long long hi, long long lo,
   return (double)hi * unit + (double)lo * (unit * (1.0 / kLoScale));
 }
 
-__device__ __forceinline__ void fix_atomic_add(unsigned long long* p, long long hi,
-                                               long long lo) {
-  if (hi) atomicAdd(p, (unsigned long long)hi);
-  if (lo) atomicAdd(p + 1, (unsigned long long)lo);
-}
+// Tally words are spaced kTallyStride apart (one cell per 16 bytes): atomics
+// of neighbouring cells then fall on fewer shared cache lines.
+constexpr int kTallyStride = 2;
 
 // ---------------------------------------------------------------------------
 // Layouts
@@ -145,9 +158,10 @@ struct DevState {
   unsigned long long alive;  // pass-2 census candidates
   long long n_kept;          // after the cap
   double thin_factor;        // count / cap or 1
-  unsigned long long sel_prefix;  // radix select state
-  unsigned long long sel_rank;
+  unsigned long long thin_mant;   // keep iff (key >> thin_rshift) < thin_mant
+  int thin_rshift;
   int thin_active;
+  int thin_overflow;              // more than cap survived the draw
   int pad0;
   // fixed-point units of the current pass (tally, balance) and inverses
   double unit_T, inv_T, unit_W, inv_W;
@@ -165,7 +179,8 @@ struct PassArgs {
   const double2* mat64;  // (sigma_s, sigma_a) per cell
   const float2* mat32;
   // emission
-  const double* cdf;     // inclusive prefix sum of the majorant per cell
+  const double* tree;    // binary sum tree of the cell majorants (heap order)
+  long long tree_L;      // leaves start at tree_L (power of two >= n_cells)
   const double* qn;      // nodal source [cell][4]
   long long n_cells;
   long long n_src;
@@ -207,6 +222,7 @@ struct DgArgs {
   const double* sig_s;   // per cell
   const double* phi_post;// per cell
   const double* phi_in;  // nodal [cell][4] (previous iterate)
+  double* src;           // nodal [cell][4] scratch: sigma_s/(4 pi)(phi_in + phi_post)
   double* psi;           // [m][cell][4] (w_m psi_m)
 };
 hipError_t launch_dg_sweep(const DgArgs& a, hipStream_t s);
@@ -220,29 +236,26 @@ hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long lon
                            hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, long long n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t s);
-hipError_t launch_pass_begin(DevState* st, const double* cdf, long long n_cells, double cdt,
-                             hipStream_t s);
+hipError_t launch_pass_begin(DevState* st, const double* tree, double cdt, hipStream_t s);
 hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, const DevState* st,
                                 double inv_adt, double* phi, hipStream_t s);
 hipError_t launch_remap_source(long long n, const double* q, const double* sig_s,
                                const double* phi_pre, const double* phi_post,
-                               const double* phi_c, double adt, double* qn, double* M,
-                               hipStream_t s);
+                               const double* phi_c, double* qn, hipStream_t s);
+long long tree_leaves(long long n_cells);
+hipError_t launch_build_tree(const double* qn, long long n_cells, double adt, double* tree,
+                             hipStream_t s);
 size_t scan_tmp_elems(long long n);
-hipError_t scan_inclusive_f64(const double* in, double* out, long long n, double* tmp,
-                              hipStream_t s);
 hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
                               long long* tmp, hipStream_t s);
-hipError_t launch_census_select(const uint8_t* alive, const uint64_t* hid, long long n,
-                                long long cap, uint64_t thin_stream, DevState* st,
-                                unsigned long long* hist, hipStream_t s);
+hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hipStream_t s);
 hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long long n,
                                uint64_t thin_stream, const DevState* st, long long* flags,
                                hipStream_t s);
 template <typename R>
 hipError_t launch_census_compact(const Bank<R>& src, const long long* incl, long long n,
-                                 Bank<R> dst, DevState* st, hipStream_t s);
+                                 long long cap, Bank<R> dst, DevState* st, hipStream_t s);
 hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,
-                                hipStream_t s);
+                                long long cap, hipStream_t s);
 
 }  // namespace slh

@@ -47,11 +47,11 @@ __device__ __forceinline__ void unit_for(double bound, double& unit, double& inv
   inv = ldexp(1.0, 61 - e);
 }
 
-__global__ void k_pass_begin(DevState* st, const double* cdf, long long n_cells, double cdt) {
+__global__ void k_pass_begin(DevState* st, const double* tree, double cdt) {
   const int t = threadIdx.x;
   if (t < 2 * B_NFIELDS) st->bal[t] = 0ull;
   if (t == 0) {
-    const double total = n_cells > 0 ? cdf[n_cells - 1] : 0.0;
+    const double total = tree[1];
     const double W = (double)st->n_in * st->maxabs_w + total;
     unit_for(W, st->unit_W, st->inv_W);
     unit_for(W * cdt, st->unit_T, st->inv_T);
@@ -63,9 +63,8 @@ __global__ void k_pass_begin(DevState* st, const double* cdf, long long n_cells,
   }
 }
 
-hipError_t launch_pass_begin(DevState* st, const double* cdf, long long n_cells, double cdt,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, st, cdf, n_cells, cdt);
+hipError_t launch_pass_begin(DevState* st, const double* tree, double cdt, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, st, tree, cdt);
   return hipGetLastError();
 }
 
@@ -74,7 +73,7 @@ __global__ void k_tally_to_flux(const unsigned long long* __restrict__ T, long l
   const double unit = st->unit_T;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    phi[i] = fix_value((long long)T[2 * i], (long long)T[2 * i + 1], unit) * inv_adt;
+    phi[i] = (double)(long long)T[kTallyStride * i] * unit * inv_adt;
 }
 
 hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, const DevState* st,
@@ -85,38 +84,98 @@ hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, const 
   return hipGetLastError();
 }
 
-// q_R = Q + sigma_s (phi_pre + phi_post) + sigma_s phi_c (nodal, bilinear);
-// majorant M = A dt max_corner |q_R|.
+// q_R = Q + sigma_s (phi_pre + phi_post) + sigma_s phi_c (nodal, bilinear).
 __global__ void k_remap_source(long long n, const double* __restrict__ q,
                                const double* __restrict__ sig_s,
                                const double* __restrict__ phi_pre,
                                const double* __restrict__ phi_post,
-                               const double* __restrict__ phi_c, double adt,
-                               double* __restrict__ qn, double* __restrict__ M) {
+                               const double* __restrict__ phi_c, double* __restrict__ qn) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     const double ss = sig_s[i];
     const double base = q[i] + ss * (phi_pre[i] + phi_post[i]);
-    double mx = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double v = base + ss * phi_c[4 * i + k];
-      qn[4 * i + k] = v;
-      mx = fmax(mx, fabs(v));
-    }
-    M[i] = adt * mx;
+    const double4 c = reinterpret_cast<const double4*>(phi_c)[i];
+    reinterpret_cast<double4*>(qn)[i] =
+        make_double4(base + ss * c.x, base + ss * c.y, base + ss * c.z, base + ss * c.w);
   }
 }
 
 hipError_t launch_remap_source(long long n, const double* q, const double* sig_s,
                                const double* phi_pre, const double* phi_post,
-                               const double* phi_c, double adt, double* qn, double* M,
-                               hipStream_t s) {
+                               const double* phi_c, double* qn, hipStream_t s) {
   long long b = (n + 255) / 256;
   const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
   hipLaunchKernelGGL(k_remap_source, dim3(grid), dim3(256), 0, s, n, q, sig_s, phi_pre,
-                     phi_post, phi_c, adt, qn, M);
+                     phi_post, phi_c, qn);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Binary sum tree of the cell majorants M_i = A dt pow2_ceil(max_corner |q_i|)
+// in heap order (root 1, children 2k and 2k+1, leaves from L), summed as
+// tree[k] = tree[2k] + tree[2k+1].  The up-sweep runs ten levels per launch in
+// LDS; the pairing, hence every rounding, is fixed by the tree.
+// ---------------------------------------------------------------------------
+long long tree_leaves(long long n_cells) {
+  long long L = 1;
+  while (L < n_cells) L *= 2;
+  return L;
+}
+
+__global__ void k_tree_leaves(const double* __restrict__ qn, long long n, long long L,
+                              double adt, double* __restrict__ t) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < L;
+       i += (long long)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    if (i < n) {
+      const double4 q = reinterpret_cast<const double4*>(qn)[i];
+      const double mx = fmax(fmax(fabs(q.x), fabs(q.y)), fmax(fabs(q.z), fabs(q.w)));
+      v = adt * pow2_ceil(mx);
+    }
+    t[L + i] = v;
+  }
+}
+
+constexpr int kTreeChunk = 1024;
+
+// Level of width W (nodes W..2W-1): block b sums nodes [W + b C, W + (b+1) C)
+// with C = min(W, 1024) up through log2(C) levels.
+__global__ __launch_bounds__(512) void k_tree_up(double* t, long long W) {
+  __shared__ double buf[2][kTreeChunk];
+  const long long C = W < kTreeChunk ? W : kTreeChunk;
+  const long long base = W + (long long)blockIdx.x * C;
+  for (int j = threadIdx.x; j < C; j += blockDim.x) buf[0][j] = t[base + j];
+  __syncthreads();
+  long long width = W, cnt = C;
+  long long first = (long long)blockIdx.x * C;  // offset of this block within the level
+  int cur = 0;
+  while (cnt > 1) {
+    cnt >>= 1;
+    width >>= 1;
+    first >>= 1;
+    for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+      const double v = buf[cur][2 * j] + buf[cur][2 * j + 1];
+      buf[1 - cur][j] = v;
+      t[width + first + j] = v;
+    }
+    cur = 1 - cur;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_build_tree(const double* qn, long long n_cells, double adt, double* tree,
+                             hipStream_t s) {
+  const long long L = tree_leaves(n_cells);
+  long long b = (L + 255) / 256;
+  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+  hipLaunchKernelGGL(k_tree_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, L, adt, tree);
+  long long W = L;
+  while (W > 1) {
+    const long long C = W < kTreeChunk ? W : kTreeChunk;
+    hipLaunchKernelGGL(k_tree_up, dim3((unsigned)(W / C)), dim3(512), 0, s, tree, W);
+    W /= C;
+  }
+  return hipGetLastError();  // L == 1: the single leaf is the root
 }
 
 // ---------------------------------------------------------------------------
@@ -191,81 +250,48 @@ static hipError_t scan_rec(const T* in, T* out, long long n, T* tmp, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t scan_inclusive_f64(const double* in, double* out, long long n, double* tmp,
-                              hipStream_t s) { return scan_rec<double>(in, out, n, tmp, s); }
 hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
                               long long* tmp, hipStream_t s) {
   return scan_rec<long long>(in, out, n, tmp, s);
 }
 
 // ---------------------------------------------------------------------------
-// Census population control: when more than `cap` particles reach t_{n+1},
-// keep the cap particles with the smallest thinning keys
-// key = mix64(thin_stream ^ hid) (a bijection of the unique history ids, so
-// keys are distinct: a simple random sample without replacement) and scale
-// their weights by count/cap.  The cap-th smallest key is found by an 8-pass
-// radix select on 8-bit digits with integer histograms.
+// Census population control.  When more than `cap` particles reach t_{n+1},
+// every survivor is kept with probability p_q and reweighted by 1/p_q, where
+// p_q = (cap - margin)/count rounded down to 11 significant bits
+// (margin = ceil(4 sqrt(cap)) + 16, computed on the host).  The draw tests the
+// survivor's own key mix64(thin_stream ^ hid) against p_q 2^64, so a
+// survivor's fate does not depend on the others, and p_q sits on a coarse
+// grid that a change of the count by a few particles does not move.  If more
+// than cap survive the draw, the first cap in slot order are kept.
 // ---------------------------------------------------------------------------
-__global__ void k_select_init(DevState* st, long long cap) {
+__global__ void k_thin_params(DevState* st, long long cap, long long margin) {
   if (threadIdx.x != 0) return;
   const unsigned long long cnt = st->alive;
-  st->thin_active = cnt > (unsigned long long)cap ? 1 : 0;
-  st->thin_factor = st->thin_active ? (double)cnt / (double)cap : 1.0;
-  st->sel_prefix = 0ull;
-  st->sel_rank = cap > 0 ? (unsigned long long)(cap - 1) : 0ull;
+  st->thin_overflow = 0;
   st->maxabs_bits_out = 0ull;
+  if (cnt <= (unsigned long long)cap) {
+    st->thin_active = 0;
+    st->thin_factor = 1.0;
+    st->thin_mant = 0ull;
+    st->thin_rshift = 64;
+    return;
+  }
+  long long target = cap - margin;
+  if (target < 1) target = 1;
+  const double p = (double)target / (double)cnt;
+  int k;
+  const double m = frexp(p, &k);
+  const double mant = floor(ldexp(m, 11));
+  const double p_q = ldexp(mant, k - 11);
+  st->thin_active = 1;
+  st->thin_mant = (unsigned long long)mant;
+  st->thin_rshift = 64 + (k - 11);
+  st->thin_factor = 1.0 / p_q;
 }
 
-__global__ __launch_bounds__(256) void k_select_hist(const uint8_t* __restrict__ alive,
-                                                     const uint64_t* __restrict__ hid,
-                                                     long long n, uint64_t thin_stream,
-                                                     const DevState* st, int shift,
-                                                     unsigned long long* hist) {
-  if (!st->thin_active) return;
-  __shared__ unsigned int s_h[256];
-  s_h[threadIdx.x] = 0u;
-  __syncthreads();
-  const unsigned long long prefix = st->sel_prefix;
-  const int high = shift + 8;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    if (!alive[i]) continue;
-    const unsigned long long key = mix64(thin_stream ^ hid[i]);
-    if (high < 64 && (key >> high) != (prefix >> high)) continue;
-    atomicAdd(&s_h[(key >> shift) & 255ull], 1u);
-  }
-  __syncthreads();
-  if (s_h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)s_h[threadIdx.x]);
-}
-
-__global__ void k_select_pick(DevState* st, unsigned long long* hist, int shift) {
-  if (threadIdx.x != 0) return;
-  if (st->thin_active) {
-    unsigned long long rank = st->sel_rank, cum = 0ull;
-    for (int b = 0; b < 256; ++b) {
-      if (cum + hist[b] > rank) {
-        st->sel_prefix |= (unsigned long long)b << shift;
-        st->sel_rank = rank - cum;
-        break;
-      }
-      cum += hist[b];
-    }
-  }
-  for (int b = 0; b < 256; ++b) hist[b] = 0ull;
-}
-
-hipError_t launch_census_select(const uint8_t* alive, const uint64_t* hid, long long n,
-                                long long cap, uint64_t thin_stream, DevState* st,
-                                unsigned long long* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_select_init, dim3(1), dim3(1), 0, s, st, cap);
-  long long b = (n + 255) / 256;
-  const int grid = (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
-  for (int pass = 0; pass < 8; ++pass) {
-    const int shift = 56 - 8 * pass;
-    hipLaunchKernelGGL(k_select_hist, dim3(grid), dim3(256), 0, s, alive, hid, n, thin_stream,
-                       (const DevState*)st, shift, hist);
-    hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(1), 0, s, st, hist, shift);
-  }
+hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hipStream_t s) {
+  hipLaunchKernelGGL(k_thin_params, dim3(1), dim3(1), 0, s, st, cap, margin);
   return hipGetLastError();
 }
 
@@ -274,11 +300,16 @@ __global__ void k_census_flags(const uint8_t* __restrict__ alive,
                                uint64_t thin_stream, const DevState* st,
                                long long* __restrict__ flags) {
   const int act = st->thin_active;
-  const unsigned long long kmax = st->sel_prefix;
+  const unsigned long long mant = st->thin_mant;
+  const int rs = st->thin_rshift;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     long long f = alive[i] ? 1 : 0;
-    if (f && act) f = mix64(thin_stream ^ hid[i]) <= kmax ? 1 : 0;
+    if (f && act) {
+      const unsigned long long key = mix64(thin_stream ^ hid[i]);
+      const unsigned long long top = rs >= 64 ? 0ull : (key >> rs);
+      f = top < mant ? 1 : 0;
+    }
     flags[i] = f;
   }
 }
@@ -294,8 +325,11 @@ hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long l
 }
 
 template <typename R>
-__global__ void k_census_compact(Bank<R> src, const long long* __restrict__ incl, long long n,
-                                 Bank<R> dst, DevState* st) {
+__global__ __launch_bounds__(256) void k_census_compact(Bank<R> src,
+                                                        const long long* __restrict__ incl,
+                                                        long long n, long long cap, Bank<R> dst,
+                                                        DevState* st) {
+  __shared__ double s_mx[4];
   const R f = (R)st->thin_factor;
   double mx = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -303,6 +337,7 @@ __global__ void k_census_compact(Bank<R> src, const long long* __restrict__ incl
     const long long before = i > 0 ? incl[i - 1] : 0;
     if (incl[i] == before) continue;
     const long long d = before;
+    if (d >= cap) continue;  // overflow of the draw: keep the first cap
     dst.px[d] = src.px[i];
     dst.py[d] = src.py[i];
     dst.ox[d] = src.ox[i];
@@ -314,35 +349,43 @@ __global__ void k_census_compact(Bank<R> src, const long long* __restrict__ incl
     mx = fmax(mx, fabs((double)w));
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-  if (__lane_id() == 0 && mx > 0.0)
-    atomicMax(&st->maxabs_bits_out, (unsigned long long)__double_as_longlong(mx));
+  if (__lane_id() == 0) s_mx[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double b = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
+    if (b > 0.0) atomicMax(&st->maxabs_bits_out, (unsigned long long)__double_as_longlong(b));
+  }
 }
 
 template <typename R>
 hipError_t launch_census_compact(const Bank<R>& src, const long long* incl, long long n,
-                                 Bank<R> dst, DevState* st, hipStream_t s) {
+                                 long long cap, Bank<R> dst, DevState* st, hipStream_t s) {
   long long b = (n + 255) / 256;
-  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_census_compact<R>, dim3(grid), dim3(256), 0, s, src, incl, n, dst, st);
+  const int grid = (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+  hipLaunchKernelGGL(k_census_compact<R>, dim3(grid), dim3(256), 0, s, src, incl, n, cap, dst,
+                     st);
   return hipGetLastError();
 }
 template hipError_t launch_census_compact<double>(const Bank<double>&, const long long*,
-                                                  long long, Bank<double>, DevState*,
-                                                  hipStream_t);
+                                                  long long, long long, Bank<double>,
+                                                  DevState*, hipStream_t);
 template hipError_t launch_census_compact<float>(const Bank<float>&, const long long*,
-                                                 long long, Bank<float>, DevState*,
+                                                 long long, long long, Bank<float>, DevState*,
                                                  hipStream_t);
 
-__global__ void k_census_finish(DevState* st, const long long* incl, long long n) {
+__global__ void k_census_finish(DevState* st, const long long* incl, long long n,
+                                long long cap) {
   if (threadIdx.x != 0) return;
-  st->n_in = n > 0 ? incl[n - 1] : 0;
+  const long long k = n > 0 ? incl[n - 1] : 0;
+  st->thin_overflow = k > cap ? 1 : 0;
+  st->n_in = k > cap ? cap : k;
   st->n_kept = st->n_in;
   st->maxabs_w = __longlong_as_double((long long)st->maxabs_bits_out);
 }
 
 hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_census_finish, dim3(1), dim3(1), 0, s, st, incl, n);
+                                long long cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_census_finish, dim3(1), dim3(1), 0, s, st, incl, n, cap);
   return hipGetLastError();
 }
 

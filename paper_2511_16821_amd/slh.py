@@ -52,7 +52,11 @@ class slh_stats(C.Structure):
                 ("si_converged", C.c_int32), ("census_alive", C.c_int64),
                 ("census_kept", C.c_int64), ("thin_factor", C.c_double),
                 ("segments_total", C.c_uint64), ("ms_mc", C.c_double), ("ms_dg", C.c_double),
-                ("ms_remap", C.c_double), ("ms_census", C.c_double)]
+                ("ms_remap", C.c_double), ("ms_census", C.c_double),
+                ("ms_kernel_mc_total", C.c_double), ("ms_kernel_remap_total", C.c_double),
+                ("seg_mc_total", C.c_uint64), ("seg_remap_total", C.c_uint64),
+                ("census_in_total", C.c_uint64), ("census_out_total", C.c_uint64),
+                ("steps_total", C.c_uint64), ("thin_overflow_total", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -80,6 +80,35 @@ def timed_run(S, torch, p, steps, warmup):
     return t1 - t0, st
 
 
+def kernel_source_digest():
+    """Digest of the MC-pass kernel sources; counter figures taken for another
+    digest describe a different kernel and are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mc.hip", "slh_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2511_16821_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, prec):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration),
+    or None when the summary is missing or was taken on other kernel code."""
+    path = os.path.join(ROOT, "profiles", "k_mc_pass_checkerboard_140_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    key = "hbm_bytes_per_launch[%s,%s]" % (kernel, "fp64" if prec == 0 else "fp32")
+    return float(kv[key]) if key in kv else None
+
+
 def roofline(st, steps, prec):
     kinds = [("k_mc_pass<step 1>", st["ms_kernel_mc_total"], st["seg_mc_total"], False),
              ("k_mc_pass<step 3>", st["ms_kernel_remap_total"], st["seg_remap_total"], True)]
@@ -91,7 +120,8 @@ def roofline(st, steps, prec):
     per_launch_s = ms * 1e-3 / steps
     achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(name, prec),
             "kernel": name, "avg_launch_ms": round(ms / steps, 4),
             "bytes_per_launch": int(per_launch_bytes),
             "segments_per_launch": int(seg / steps)}
@@ -138,6 +168,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no inter-GPU sharding); "
@@ -147,6 +179,15 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20)
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "launches": 5}))
+        return
     from paper_2511_16821_amd import slh as S
     S.lib()
 

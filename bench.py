@@ -156,6 +156,73 @@ def fp32_error(S, p64, p32, steps):
     return worst
 
 
+def serve_bench(S, torch, args):
+    """C4: Poisson arrivals of mixed solve requests; continuous batching on
+    the server vs the same stream one solve at a time on the same GPU."""
+    import numpy as np
+    from paper_2511_16821_amd import workloads as W
+    sides = tuple(x for x in (32, 64, 128, 256, 512) if x <= args.serve_max_side)
+    stream = W.request_stream(n_req=args.serve_requests, rho=args.rho, seed=args.serve_seed,
+                              sides=sides, np_range=(1e4, args.serve_max_particles))
+    unit_arrivals = np.array([a for a, _ in stream])
+    reqs = [p for _, p in stream]
+    # one solve at a time: service time of each request alone
+    service, seg_alone, flux_alone = [], [], []
+    for p in reqs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = S.Solver(p, torch_allocator=False)
+        s.advance(int(p["n_steps"]), allow_not_converged=True)
+        f = s.get_flux(0)
+        st = s.get_stats()
+        s.destroy()
+        service.append(time.perf_counter() - t0)
+        seg_alone.append(st["seg_mc_total"] + st["seg_remap_total"])
+        flux_alone.append(f)
+    service = np.array(service)
+    t_mean = float(service.mean())
+    arrivals = unit_arrivals * t_mean / args.rho
+    # FIFO, one at a time, same arrivals: nothing overlaps, so the completion
+    # times follow from the measured service times
+    done, lat_serial = 0.0, []
+    for a, t in zip(arrivals, service):
+        done = max(a, done) + t
+        lat_serial.append(done - a)
+    serial_makespan = done
+    # continuous batching
+    budget = int(args.serve_budget_gib * (1 << 30))
+    srv = S.Server(hbm_budget_bytes=budget, max_slots=args.serve_slots)
+    t_start = time.perf_counter()
+    tickets = []
+    for a, p in zip(arrivals, reqs):
+        wait = t_start + a - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(p, int(p["n_steps"])))
+    res = [srv.result(t) for t in tickets]
+    t_end = time.perf_counter()
+    srv.destroy()
+    lat = np.array([r[2]["latency_ms"] for r in res]) / 1e3
+    seg = sum(r[2]["segments"] for r in res)
+    same = all(np.array_equal(r[0], f) for r, f in zip(res, flux_alone))
+    return {
+        "requests": len(reqs), "rho": args.rho, "slots": args.serve_slots,
+        "budget_gib": args.serve_budget_gib,
+        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+        "segments_per_s": seg / (t_end - t_start),
+        "one_at_a_time": {
+            "p50_latency_ms": float(np.percentile(lat_serial, 50) * 1e3),
+            "p99_latency_ms": float(np.percentile(lat_serial, 99) * 1e3),
+            "segments_per_s": float(sum(seg_alone) / serial_makespan),
+            "mean_service_ms": 1e3 * t_mean},
+        "results_identical_to_alone": bool(same),
+        "stream": "Poisson arrivals at rate rho/mean service time; sides %s, N_s in {0,1,2,4}, "
+                  "particles log-uniform 1e4-%g, 5-50 steps, FP32/FP64 mixed, lognormal "
+                  "8x8-block materials" % (list(sides), args.serve_max_particles),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +235,15 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--serve", action="store_true",
+                    help="also run the serving benchmark (continuous batching)")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-max-side", type=int, default=512)
+    ap.add_argument("--serve-max-particles", type=float, default=1e7)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-seed", type=int, default=4)
+    ap.add_argument("--rho", type=float, default=1.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -221,6 +297,9 @@ def main():
                              "roofline": roofline(st32, steps, 1)}
         log("fp32-track: %.3f s, %.3e segments/s, rel-L2 vs fp64 %.2e" %
             (wall32, seg32 / wall32, err))
+    if args.serve:
+        out["serving"] = serve_bench(S, torch, args)
+        log("serving:", json.dumps(out["serving"]))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p64, args.cpu_steps)
         log("cpu oracle: %.3e segments/s" % out["cpu_baseline"]["value"])

@@ -214,7 +214,7 @@ slh_status slh_qmc_points(uint64_t seed, uint64_t step, uint32_t pass, uint32_t 
 typedef struct {
     size_t hbm_budget_bytes; /* admission limit on summed footprints; 0 -> 64 GiB */
     int32_t max_slots;       /* concurrently resident requests; 0 -> 8        */
-    int32_t n_streams;       /* HIP streams in the pool; 0 -> max_slots       */
+    int32_t n_streams;       /* ignored: each slot has its own HIP stream     */
 } slh_server_cfg;
 
 typedef struct {
@@ -229,11 +229,18 @@ typedef struct {
 
 typedef struct slh_server slh_server;
 
+/* Creates a server: one device arena of hbm_budget_bytes (allocated once;
+ * no device allocation happens while requests run) and max_slots worker
+ * threads, each with its own HIP stream.  A worker takes the first queued
+ * request (arrival order; a request that does not fit yet is passed over)
+ * whose footprint fits in the arena, runs all its steps on its stream, and
+ * returns its memory, so requests are admitted as slots and memory free up
+ * and resident requests overlap on the device.  max_slots <= 64. */
 slh_status slh_server_create(const slh_server_cfg *cfg, slh_server **out);
 
 /* Queues a solve of n_steps steps.  The problem's arrays are copied before
  * the call returns.  SLH_E_REJECTED if its footprint alone exceeds the
- * budget. */
+ * budget; SLH_E_INVALID_ARG if the problem is invalid. */
 slh_status slh_server_submit(slh_server *srv, const slh_problem *problem, int32_t n_steps,
                              uint64_t *ticket);
 

@@ -165,6 +165,7 @@ static Sizes sizes_of(const slh_problem* p) {
   b += (size_t)z.n_cand * (bank + 1 + 8 + 8);  // staging, alive, flags, inclusive scan
   b += scan_tmp_elems(z.n_cand) * 8;
   b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8;
+  b += 64 * 1024;  // alignment of the ~30 device buffers
   z.bytes = b;
   return z;
 }

@@ -1,0 +1,88 @@
+"""Serving (continuous batching on one GPU): every request's result is the
+same alone and in the mix (bitwise: all sums are order-independent fixed
+point), admission never exceeds the HBM budget, and requests that can never
+fit are rejected."""
+import numpy as np
+import pytest
+
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2511_16821_amd import slh
+    slh.lib()
+    return slh
+
+
+def _mix(n=10, seed=3):
+    from paper_2511_16821_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(n):
+        side = int(rng.choice([16, 24, 32, 48]))
+        p = W.lognormal_blocks(side, L=4.0, blocks=8, rng=rng, n_s=int(rng.choice([0, 1, 2, 4])),
+                               n_particles=int(rng.choice([3000, 12000, 40000])),
+                               precision=int(rng.integers(0, 2)), seed=100 + r, sn_order=4)
+        out.append((p, int(rng.integers(2, 6))))
+    return out
+
+
+def _alone(S, p, steps):
+    s = S.Solver(p)
+    s.advance(steps, allow_not_converged=True)
+    f = s.get_flux(0)
+    b = s.get_balance(2)
+    s.destroy()
+    return f, b
+
+
+def test_results_same_alone_and_in_mix(S):
+    reqs = _mix()
+    srv = S.Server(hbm_budget_bytes=2 << 30, max_slots=4)
+    tickets = [srv.submit(p, k) for p, k in reqs]
+    got = [srv.result(t) for t in tickets]
+    srv.destroy()
+    for (p, k), (flux, bal, lat) in zip(reqs, got):
+        f, b = _alone(S, p, k)
+        assert np.array_equal(flux, f), (p["nx"], p["n_s"], p["precision"])
+        assert bal["census"] == b["census"] and bal["segments"] == b["segments"]
+        assert lat["latency_ms"] >= lat["run_ms"] > 0
+    log("mix of", len(reqs), "requests matches the standalone runs bitwise")
+
+
+def test_admission_respects_budget(S):
+    reqs = _mix(6, seed=9)
+    fps = [S.slh_footprint_bytes(p) for p, _ in reqs]
+    budget = max(fps) + (1 << 20)  # room for one request at a time
+    srv = S.Server(hbm_budget_bytes=budget, max_slots=4)
+    tickets = [srv.submit(p, k) for p, k in reqs]
+    lats = [srv.result(t)[2] for t in tickets]
+    srv.destroy()
+    iv = sorted((l["admit_s"], l["done_s"], fp) for l, fp in zip(lats, fps))
+    for a in range(len(iv)):
+        for b in range(a + 1, len(iv)):
+            overlap = iv[a][1] > iv[b][0] and iv[b][1] > iv[a][0]
+            if overlap:
+                assert iv[a][2] + iv[b][2] <= budget
+
+
+def test_reject_and_invalid(S):
+    from paper_2511_16821_amd import workloads as W
+    srv = S.Server(hbm_budget_bytes=64 << 20, max_slots=2)
+    with pytest.raises(S.SlhError) as e:
+        srv.submit(W.c1(n_particles=2_000_000), 2)
+    assert e.value.status == S.SLH_E_REJECTED
+    bad = W.c1()
+    bad["dt"] = -1.0
+    with pytest.raises(S.SlhError) as e:
+        srv.submit(bad, 1)
+    assert e.value.status == S.SLH_E_INVALID_ARG
+    t = srv.submit(W.c1(n_particles=2000), 1)
+    flux, bal, lat = srv.result(t)
+    assert flux.sum() > 0
+    srv.destroy()

@@ -95,6 +95,7 @@ static std::vector<double> product_quadrature(int order) {
 struct Sizes {
   long long n_cells, n_p, cap, n_cand;
   int n_dir;
+  int n_copies;  // private tally copies
   bool fp32;
   size_t bytes;
 };
@@ -150,6 +151,10 @@ static Sizes sizes_of(const slh_problem* p) {
   z.cap = p->census_cap > 0 ? p->census_cap : std::max<long long>(p->n_particles, 1);
   z.n_cand = z.cap + z.n_p;
   z.n_dir = p->sn_order * p->sn_order;
+  // private tally copies: up to 32, keeping each tally array within 64 MB
+  z.n_copies = 32;
+  while (z.n_copies > 1 && (size_t)z.n_copies * kTallyStride * 8 * (size_t)z.n_cells > (64u << 20))
+    z.n_copies /= 2;
   z.fp32 = p->precision == SLH_FP32_TRACK;
   const size_t rb = z.fp32 ? 4 : 8;
   const size_t bank = 5 * rb + 4 + 8;
@@ -157,11 +162,12 @@ static Sizes sizes_of(const slh_problem* p) {
   const size_t nc = (size_t)z.n_cells;
   b += nc * (16 + 8 + 8 + 8 + 8);            // mat64, mat32, sig_s, sig_e, q
   b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 2;  // nodal sources, trees
-  b += nc * 8 * kTallyStride * 3;            // tallies
+  b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
   b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
   b += (size_t)z.n_dir * nc * 32;            // per-direction planes
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
   b += (size_t)z.cap * bank * 2;             // census banks
+  b += (size_t)(z.n_p > 0 ? z.n_p : 1) * (7 * rb + 4);  // source bank
   b += (size_t)z.n_cand * (bank + 1 + 8 + 8);  // staging, alive, flags, inclusive scan
   b += scan_tmp_elems(z.n_cand) * 8;
   b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8;
@@ -245,6 +251,7 @@ struct slh_solver {
   int n_part = 1;
   void* bank_mem[2] = {nullptr, nullptr};
   void* stage_mem = nullptr;
+  void* src_mem = nullptr;  // source bank of the current pass
   uint8_t* alive = nullptr;
   long long *flags = nullptr, *incl = nullptr, *scan_i = nullptr;
   uint32_t* sobol = nullptr;
@@ -312,6 +319,23 @@ struct slh_solver {
     const size_t rb = z.fp32 ? 4 : 8;
     return (size_t)n * (5 * rb + 8 + 4);
   }
+  template <typename R> SrcBank<R> src_at(void* base, long long n) const {
+    SrcBank<R> b;
+    R* p = (R*)base;
+    b.px = p; p += n;
+    b.py = p; p += n;
+    b.ox = p; p += n;
+    b.oy = p; p += n;
+    b.w = p; p += n;
+    b.trel = p; p += n;
+    b.tau = p; p += n;
+    b.cell = (int32_t*)p;
+    return b;
+  }
+  size_t src_bytes(long long n) const {
+    const size_t rb = z.fp32 ? 4 : 8;
+    return (size_t)(n > 0 ? n : 1) * (7 * rb + 4);
+  }
 };
 
 static int mc_grid(const slh_solver* s, long long max_work) {
@@ -344,9 +368,9 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->tree1, double, 2 * s->tree_L);
   ALLOC(s->qnR, double, 4 * nc);
   ALLOC(s->treeR, double, 2 * s->tree_L);
-  ALLOC(s->Tpre, unsigned long long, kTallyStride * nc);
-  ALLOC(s->Tpost, unsigned long long, kTallyStride * nc);
-  ALLOC(s->TR, unsigned long long, kTallyStride * nc);
+  ALLOC(s->Tpre, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
+  ALLOC(s->Tpost, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
+  ALLOC(s->TR, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
   ALLOC(s->phi_pre, double, nc);
   ALLOC(s->phi_post, double, nc);
   ALLOC(s->phi_R, double, nc);
@@ -360,7 +384,8 @@ static slh_status setup(slh_solver* s) {
   s->bank_mem[0] = s->dalloc(s->bank_bytes(z.cap));
   s->bank_mem[1] = s->dalloc(s->bank_bytes(z.cap));
   s->stage_mem = s->dalloc(s->bank_bytes(z.n_cand));
-  if (!s->bank_mem[0] || !s->bank_mem[1] || !s->stage_mem)
+  s->src_mem = s->dalloc(s->src_bytes(z.n_p));
+  if (!s->bank_mem[0] || !s->bank_mem[1] || !s->stage_mem || !s->src_mem)
     return fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: census banks");
   ALLOC(s->alive, uint8_t, z.n_cand);
   ALLOC(s->flags, long long, z.n_cand);
@@ -439,14 +464,18 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   if (s->z.fp32) {
     a.in32 = s->bank_at<float>(bin, s->z.cap);
     a.out32 = s->bank_at<float>(s->stage_mem, s->z.n_cand);
+    a.src32 = s->src_at<float>(s->src_mem, s->z.n_p);
   } else {
     a.in64 = s->bank_at<double>(bin, s->z.cap);
     a.out64 = s->bank_at<double>(s->stage_mem, s->z.n_cand);
+    a.src64 = s->src_at<double>(s->src_mem, s->z.n_p);
   }
   a.alive = s->alive;
   a.out_src_base = s->z.cap;
   a.Ta = kind == 1 ? s->Tpre : s->TR;
   a.Tb = kind == 1 ? s->Tpost : s->TR;
+  a.n_copies = s->z.n_copies;
+  a.copy_stride = (long long)kTallyStride * s->z.n_cells;
   a.st = s->st;
   return a;
 }
@@ -492,13 +521,18 @@ static slh_status run_step(slh_solver* s) {
   HIP_TRY(hipEventRecord(s->ev[0], st));
   // ---- step 1: scatter-limited leg from Q and the census ----
   HIP_TRY(launch_pass_begin(s->st, s->tree1, cdt, st));
-  HIP_TRY(launch_fill_u64(s->Tpre, kTallyStride * nc, 0ull, st));
-  HIP_TRY(launch_fill_u64(s->Tpost, kTallyStride * nc, 0ull, st));
+  HIP_TRY(launch_fill_u64(s->Tpre, (long long)z.n_copies * kTallyStride * nc, 0ull, st));
+  HIP_TRY(launch_fill_u64(s->Tpost, (long long)z.n_copies * kTallyStride * nc, 0ull, st));
+  const PassArgs a1 = pass_args(s, 1);
+  HIP_TRY(launch_emit(a1, z.fp32, st));
   HIP_TRY(hipEventRecord(s->evk[0], st));
-  HIP_TRY(launch_mc_pass(pass_args(s, 1), z.fp32, grid, st));
+  HIP_TRY(launch_mc_pass(a1, z.fp32, grid, st));
   HIP_TRY(hipEventRecord(s->evk[1], st));
-  HIP_TRY(launch_tally_to_flux(s->Tpre, nc, s->st, inv_adt, s->phi_pre, st));
-  HIP_TRY(launch_tally_to_flux(s->Tpost, nc, s->st, inv_adt, s->phi_post, st));
+  const long long cstride = (long long)kTallyStride * nc;
+  HIP_TRY(launch_tally_to_flux(s->Tpre, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_pre,
+                               st));
+  HIP_TRY(launch_tally_to_flux(s->Tpost, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_post,
+                               st));
   hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
                      s->bal_store + 0);
   HIP_TRY(hipMemcpyAsync(s->h_bal + 0, s->bal_store + 0, sizeof(BalStore),
@@ -550,12 +584,14 @@ static slh_status run_step(slh_solver* s) {
                               st));
   HIP_TRY(launch_build_tree(s->qnR, nc, s->adt, s->treeR, st));
   HIP_TRY(launch_pass_begin(s->st, s->treeR, cdt, st));
-  HIP_TRY(launch_fill_u64(s->TR, kTallyStride * nc, 0ull, st));
+  HIP_TRY(launch_fill_u64(s->TR, (long long)z.n_copies * kTallyStride * nc, 0ull, st));
   HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
+  const PassArgs a2 = pass_args(s, 2);
+  HIP_TRY(launch_emit(a2, z.fp32, st));
   HIP_TRY(hipEventRecord(s->evk[2], st));
-  HIP_TRY(launch_mc_pass(pass_args(s, 2), z.fp32, grid, st));
+  HIP_TRY(launch_mc_pass(a2, z.fp32, grid, st));
   HIP_TRY(hipEventRecord(s->evk[3], st));
-  HIP_TRY(launch_tally_to_flux(s->TR, nc, s->st, inv_adt, s->phi_R, st));
+  HIP_TRY(launch_tally_to_flux(s->TR, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_R, st));
   hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
                      s->bal_store + 1);
   HIP_TRY(hipMemcpyAsync(s->h_bal + 1, s->bal_store + 1, sizeof(BalStore),

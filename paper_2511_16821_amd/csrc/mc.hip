@@ -13,7 +13,9 @@
 // g - n_in; every random number of a history is a pure function of its
 // (stream, dimension, point index), so results do not depend on which lane or
 // wave ran it.  Tallies and balance sums are two-word fixed point with integer
-// atomics and are therefore independent of the schedule.
+// atomics and are therefore independent of the schedule.  Each lane adds into
+// one of several private copies of the tally (summed afterwards), so that
+// simultaneous updates of a busy cell do not queue on one cache line.
 #include "slh_common.hpp"
 #include "sobol_dirs.inc"
 
@@ -24,7 +26,16 @@ const uint32_t* sobol_table_host() { return slh_sobol_v; }
 template <typename R> struct Real;
 template <> struct Real<double> {
   using V2 = double2;
-  static __device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s, c); }
+  static __device__ __forceinline__ void scpi(double x, double* s, double* c) {
+    sincospi(x, s, c);
+  }
+  static __device__ __forceinline__ const SrcBank<double>& src(const PassArgs& a) {
+    return a.src64;
+  }
+  // w e^{-z} = w + w (e^{-z} - 1): the weight minus what the segment removed
+  static __device__ __forceinline__ double attenuate(double w, double, double em) {
+    return fma(w, em, w);
+  }
   static __device__ __forceinline__ double2 mat(const PassArgs& a, int c) { return a.mat64[c]; }
   static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
   static __device__ __forceinline__ const Bank<double>& in(const PassArgs& a) { return a.in64; }
@@ -32,7 +43,15 @@ template <> struct Real<double> {
 };
 template <> struct Real<float> {
   using V2 = float2;
-  static __device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, c); }
+  static __device__ __forceinline__ void scpi(float x, float* s, float* c) {
+    sincospif(x, s, c);
+  }
+  static __device__ __forceinline__ const SrcBank<float>& src(const PassArgs& a) {
+    return a.src32;
+  }
+  static __device__ __forceinline__ float attenuate(float w, float z, float) {
+    return w * expf(-z);
+  }
   static __device__ __forceinline__ float2 mat(const PassArgs& a, int c) { return a.mat32[c]; }
   static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
   static __device__ __forceinline__ const Bank<float>& in(const PassArgs& a) { return a.in32; }
@@ -76,14 +95,16 @@ __device__ __forceinline__ long long tree_pick(const double* __restrict__ t,
   return k - L;
 }
 
+// Emission of the pass's source particles, one thread each (Sec. 2.3: birth
+// proportional to q, isotropic direction, weight so that the weights sum to
+// the integral of q): the cell by descending the majorant sum tree with point
+// dimension 0, position (dims 1-2), birth time (dim 3), direction (dims 4-5),
+// signed weight q(x,y) sum(M) / (N_p mbar_cell), and the first optical depth
+// (dim 6) when the pass allows scatters.
 template <typename R, int KIND>
-__global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
-  __shared__ unsigned long long s_bal[2 * B_NFIELDS];
-  __shared__ unsigned long long s_cnt[4];
+__global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   __shared__ uint32_t s_sobol[kSobolDims * 32];
   __shared__ double s_top[kTreeTop];
-  if (threadIdx.x < 2 * B_NFIELDS) s_bal[threadIdx.x] = 0ull;
-  if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0ull;
   for (int k = threadIdx.x; k < kSobolDims * 32; k += blockDim.x) s_sobol[k] = a.sobol[k];
   {
     const long long ntop = 2 * a.tree_L < kTreeTop ? 2 * a.tree_L : kTreeTop;
@@ -91,11 +112,52 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
       s_top[k] = (k >= 1 && k < ntop) ? a.tree[k] : 0.0;
   }
   __syncthreads();
+  const double total = s_top[1];
+  if (!(total > 0.0)) return;
+  const double w_src = total / (double)a.n_src;
+  const uint64_t stream = stream_seed(a.seed, a.step, (uint32_t)KIND, 0u, 0ull);
+  const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt;
+  const SrcBank<R> b = Real<R>::src(a);
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < a.n_src;
+       s += (long long)gridDim.x * blockDim.x) {
+    const uint32_t pidx = (uint32_t)s;
+    const double u0 = u01_f64(point_u32(s_sobol, a.points, stream, 0u, pidx));
+    const long long ci = tree_pick(a.tree, s_top, a.tree_L, u0);
+    const R u1 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 1u, pidx));
+    const R u2 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 2u, pidx));
+    const R u3 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 3u, pidx));
+    const R u4 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 4u, pidx));
+    const R u5 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 5u, pidx));
+    const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
+    R sp, cp;
+    Real<R>::scpi((R)2 * u5, &sp, &cp);
+    const double* q = a.qn + 4 * ci;
+    b.px[s] = hx * u1;
+    b.py[s] = hy * u2;
+    b.ox[s] = sn * cp;
+    b.oy[s] = sn * sp;
+    b.w[s] = (R)(w_src * (bilinear(q, (double)u1, (double)u2) / pow2_ceil(maxabs4(q))));
+    b.trel[s] = u3 * dt;
+    b.tau[s] = a.n_lim > 0 ? -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, 6u, pidx)))
+                           : (R)0;
+    b.cell[s] = (int32_t)ci;
+  }
+}
+
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mc_pass(PassArgs a) {
+  __shared__ unsigned long long s_bal[2 * B_NFIELDS];
+  __shared__ unsigned long long s_cnt[4];
+  __shared__ uint32_t s_sobol[kSobolDims * 32];
+  if (threadIdx.x < 2 * B_NFIELDS) s_bal[threadIdx.x] = 0ull;
+  if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0ull;
+  for (int k = threadIdx.x; k < kSobolDims * 32; k += blockDim.x) s_sobol[k] = a.sobol[k];
+  __syncthreads();
 
   DevState* st = a.st;
   const int lane = __lane_id();
   const long long n_in = st->n_in;
-  const double total = s_top[1];
+  const double total = a.tree[1];
   const long long n_emit = (total > 0.0) ? a.n_src : 0;
   const unsigned long long n_tot = (unsigned long long)(n_in + n_emit);
   const double w_src = n_emit > 0 ? total / (double)a.n_src : 0.0;
@@ -110,8 +172,15 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
   const int n_lim = a.n_lim;
 
   bool have = false, exhausted = false;
+  // the tally atomic waiting to be issued; until the first real tally it adds 0
+  // to a word picked per lane, so the zero adds do not pile onto one address
+  const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long my_copy = (gtid % a.n_copies) * a.copy_stride;
+  unsigned long long* pend_ptr = a.Ta + my_copy + kTallyStride * (gtid % a.n_cells);
+  unsigned long long pend_val = 0ull;
   long long g = 0;
   R px = 0, py = 0, ox = 0, oy = 0, w = 0, trel = 0, tau = 0;
+  R iox = 0, ioy = 0;  // 1/ox, 1/oy (0 for a zero component)
   int ix = 0, iy = 0, n = 0;
   uint64_t stream = 0, hid = 0;
   uint32_t pidx = 0, dcur = 0, seg_p = 0;
@@ -153,48 +222,46 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
               pidx = (uint32_t)(hid & 0xffffffffull);
               dcur = 0;
             } else {
-              // source particle: inverse CDF of the majorant for the cell,
-              // uniform position and birth time, isotropic direction
+              // source particle, emitted by k_emit
               from_census = false;
               const long long s = g - n_in;
+              const SrcBank<R> sb = Real<R>::src(a);
               stream = src_stream;
               pidx = (uint32_t)s;
               hid = (a.step << 32) | (uint64_t)s;
-              const double u0 = u01_f64(point_u32(s_sobol, a.points, stream, 0u, pidx));
-              const long long ci = tree_pick(a.tree, s_top, a.tree_L, u0);
-              ix = (int)(ci % a.nx); iy = (int)(ci / a.nx);
-              const R u1 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 1u, pidx));
-              const R u2 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 2u, pidx));
-              const R u3 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 3u, pidx));
-              const R u4 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 4u, pidx));
-              const R u5 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 5u, pidx));
-              px = hx * u1;
-              py = hy * u2;
-              trel = u3 * dt;
-              const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
-              R sp, cp;
-              Real<R>::sc((R)(2.0 * M_PI) * u5, &sp, &cp);
-              ox = sn * cp;
-              oy = sn * sp;
-              const double* q = a.qn + 4 * ci;
-              w = (R)(w_src * (bilinear(q, (double)u1, (double)u2) / pow2_ceil(maxabs4(q))));
-              dcur = 6;
+              px = sb.px[s]; py = sb.py[s]; ox = sb.ox[s]; oy = sb.oy[s]; w = sb.w[s];
+              trel = sb.trel[s];
+              tau = sb.tau[s];
+              const int cell = sb.cell[s];
+              ix = cell % a.nx; iy = cell / a.nx;
+              dcur = 7;  // dims 0-5 emission, 6 the first optical depth
             }
+            iox = ox != (R)0 ? (R)1 / ox : (R)0;
+            ioy = oy != (R)0 ? (R)1 / oy : (R)0;
             w0 = (double)w;
-            if (n < n_lim) {
-              tau = -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, dcur, pidx)));
-              dcur++;
+            if (from_census && n_lim > 0) {
+              tau = -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, 0u, pidx)));
+              dcur = 1;
             }
           }
         }
       }
     }
-    if (!__any(have)) break;
-    if (!have) continue;
+    if (!__any(have)) {
+      if (pend_val) atomicAdd(pend_ptr, pend_val);
+      break;
+    }
+    if (!have) continue;  // an idle lane keeps its pending tally
 
     // ---- one segment ----
     const int cell = iy * a.nx + ix;
     const typename Real<R>::V2 m = Real<R>::mat(a, cell);
+    // The previous segment's tally atomic is issued only now, after this
+    // iteration's loads, and on every segment (adding 0 when nothing is
+    // pending), so the wait for the loads does not include the atomic's
+    // round trip (memory operations retire in issue order).
+    atomicAdd(pend_ptr, pend_val);
+    pend_val = 0ull;
     const R ss = m.x, sa = m.y, stt = sa + ss;
     const bool pre = n < n_lim;
     R d_cen = c * (dt - trel);
@@ -202,8 +269,8 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
     R d_col = INF;
     if (pre && ss > (R)0) { d_col = tau / ss; if (d_col < (R)0) d_col = (R)0; }
     R d_x = INF, d_y = INF;
-    if (ox > (R)0) d_x = (hx - px) / ox; else if (ox < (R)0) d_x = -px / ox;
-    if (oy > (R)0) d_y = (hy - py) / oy; else if (oy < (R)0) d_y = -py / oy;
+    if (ox > (R)0) d_x = (hx - px) * iox; else if (ox < (R)0) d_x = -px * iox;
+    if (oy > (R)0) d_y = (hy - py) * ioy; else if (oy < (R)0) d_y = -py * ioy;
     if (d_x < (R)0) d_x = (R)0;
     if (d_y < (R)0) d_y = (R)0;
     R l = d_cen;
@@ -214,18 +281,17 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
 
     const R sig = pre ? sa : stt;
     const R z = sig * l;
-    const R e = exp(-z);
-    const R em = expm1(-z);
+    const R em = expm1(-z);  // e^{-z} - 1
     const R contrib = (sig > (R)0) ? w * (-em) / sig : w * l;
     {
       const double cd = (double)contrib;
       const long long v = fix_round(cd, inv_T);
-      if (v) atomicAdd((pre ? a.Ta : a.Tb) + kTallyStride * (long long)cell,
-                       (unsigned long long)v);
+      pend_ptr = (pre ? a.Ta : a.Tb) + my_copy + kTallyStride * (long long)cell;
+      pend_val = (unsigned long long)v;
       acc_abs += (double)sa * cd;
       if (!pre) acc_sca += (double)ss * cd;
     }
-    w = w * e;
+    w = Real<R>::attenuate(w, z, em);
     if (pre && ss > (R)0) tau -= ss * l;
     trel += l / c;
     seg_p++;
@@ -244,9 +310,11 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
       dcur += 2;
       const R sn = (R)2 * sqrt(ua * ((R)1 - ua));
       R sp, cp;
-      Real<R>::sc((R)(2.0 * M_PI) * ub, &sp, &cp);
+      Real<R>::scpi((R)2 * ub, &sp, &cp);
       ox = sn * cp;
       oy = sn * sp;
+      iox = ox != (R)0 ? (R)1 / ox : (R)0;
+      ioy = oy != (R)0 ? (R)1 / oy : (R)0;
       n++;
       if (n < n_lim) {
         tau = -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, dcur, pidx)));
@@ -322,6 +390,20 @@ __global__ __launch_bounds__(256) void k_mc_pass(PassArgs a) {
                               : k == 2 ? &st->alive : &st->killed;
     if (s_cnt[k]) atomicAdd(dst, s_cnt[k]);
   }
+}
+
+hipError_t launch_emit(const PassArgs& a, bool fp32, hipStream_t s) {
+  if (a.n_src <= 0) return hipSuccess;
+  long long b = (a.n_src + 255) / 256;
+  const int grid = (int)(b < 8192 ? b : 8192);
+  if (a.kind == 1) {
+    if (fp32) hipLaunchKernelGGL((k_emit<float, 1>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_emit<double, 1>), dim3(grid), dim3(256), 0, s, a);
+  } else {
+    if (fp32) hipLaunchKernelGGL((k_emit<float, 2>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_emit<double, 2>), dim3(grid), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_mc_pass(const PassArgs& a, bool fp32, int grid, hipStream_t s) {

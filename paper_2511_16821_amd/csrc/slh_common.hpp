@@ -145,6 +145,20 @@ template <typename R> struct Bank {
   uint64_t* hid;
 };
 
+// Source particles of one pass, written by the emission kernel: position in
+// the cell, direction, weight, birth time within the step, first optical
+// depth (scatter-limited pass with N_s > 0 only) and cell.
+template <typename R> struct SrcBank {
+  R* px;
+  R* py;
+  R* ox;
+  R* oy;
+  R* w;
+  R* trel;
+  R* tau;
+  int32_t* cell;
+};
+
 // Balance fields, each a two-word fixed-point sum.
 enum BalField {
   B_EMITTED = 0, B_ABSORBED, B_SCATTERED, B_LEAKED, B_CENSUS, B_CUTOFF, B_SOURCE_W,
@@ -195,11 +209,16 @@ struct PassArgs {
   // source index), in the precision of the pass
   Bank<double> in64, out64;
   Bank<float> in32, out32;
+  SrcBank<double> src64;
+  SrcBank<float> src32;
   uint8_t* alive;
   long long out_src_base;  // slot of source particle s is out_src_base + s
-  // tallies (two-word fixed point per cell)
+  // tallies: n_copies private copies of one fixed-point word per cell (word
+  // stride kTallyStride), copy c at offset c * copy_stride
   unsigned long long* Ta;
   unsigned long long* Tb;
+  int n_copies;
+  long long copy_stride;
   DevState* st;
 };
 
@@ -207,6 +226,7 @@ struct PassArgs {
 // Launch wrappers (defined in the .hip files)
 // ---------------------------------------------------------------------------
 
+hipError_t launch_emit(const PassArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_mc_pass(const PassArgs& a, bool fp32, int grid, hipStream_t s);
 hipError_t launch_qmc_points(uint64_t stream, uint32_t dim0, uint32_t nd, uint32_t idx0,
                              uint32_t n, int mode, const uint32_t* sobol, uint32_t* out,
@@ -237,8 +257,9 @@ hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long lon
 hipError_t launch_fill_u8(uint8_t* p, long long n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 hipError_t launch_pass_begin(DevState* st, const double* tree, double cdt, hipStream_t s);
-hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, const DevState* st,
-                                double inv_adt, double* phi, hipStream_t s);
+hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, int n_copies,
+                                long long copy_stride, const DevState* st, double inv_adt,
+                                double* phi, hipStream_t s);
 hipError_t launch_remap_source(long long n, const double* q, const double* sig_s,
                                const double* phi_pre, const double* phi_post,
                                const double* phi_c, double* qn, hipStream_t s);

@@ -68,19 +68,26 @@ hipError_t launch_pass_begin(DevState* st, const double* tree, double cdt, hipSt
   return hipGetLastError();
 }
 
+// phi = (sum of the private copies, an exact integer sum) * unit / (A dt)
 __global__ void k_tally_to_flux(const unsigned long long* __restrict__ T, long long n,
-                                const DevState* st, double inv_adt, double* __restrict__ phi) {
+                                int n_copies, long long copy_stride, const DevState* st,
+                                double inv_adt, double* __restrict__ phi) {
   const double unit = st->unit_T;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    phi[i] = (double)(long long)T[kTallyStride * i] * unit * inv_adt;
+       i += (long long)gridDim.x * blockDim.x) {
+    unsigned long long v = 0ull;
+    for (int c = 0; c < n_copies; ++c) v += T[c * copy_stride + kTallyStride * i];
+    phi[i] = (double)(long long)v * unit * inv_adt;
+  }
 }
 
-hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, const DevState* st,
-                                double inv_adt, double* phi, hipStream_t s) {
+hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, int n_copies,
+                                long long copy_stride, const DevState* st, double inv_adt,
+                                double* phi, hipStream_t s) {
   long long b = (n + 255) / 256;
   const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_tally_to_flux, dim3(grid), dim3(256), 0, s, T, n, st, inv_adt, phi);
+  hipLaunchKernelGGL(k_tally_to_flux, dim3(grid), dim3(256), 0, s, T, n, n_copies, copy_stride,
+                     st, inv_adt, phi);
   return hipGetLastError();
 }
 

@@ -338,17 +338,6 @@ struct slh_solver {
   }
 };
 
-static int mc_grid(const slh_solver* s, long long max_work) {
-  // persistent grid: enough 256-lane blocks to fill the GPU, never more than
-  // the work needs
-  long long want = (max_work + 255) / 256;
-  const long long cap = 256 * 8;
-  if (want > cap) want = cap;
-  if (want < 1) want = 1;
-  (void)s;
-  return (int)want;
-}
-
 static slh_status setup(slh_solver* s) {
   const slh_problem& p = s->prob;
   const Sizes& z = s->z;
@@ -511,7 +500,8 @@ static slh_status run_step(slh_solver* s) {
   hipStream_t st = s->stream;
   const double inv_adt = 1.0 / s->adt;
   const double cdt = p.c * p.dt;
-  const int grid = mc_grid(s, z.cap + z.n_p);
+  const int grid1 = mc_pass_grid(z.fp32, 1, z.cap + z.n_p);
+  const int grid2 = mc_pass_grid(z.fp32, 2, z.cap + z.n_p);
   if (s->pending[0]) {  // only when the previous step had no SI sync
     HIP_TRY(hipStreamSynchronize(st));
     slh_status r = collect_all(s);
@@ -526,7 +516,7 @@ static slh_status run_step(slh_solver* s) {
   const PassArgs a1 = pass_args(s, 1);
   HIP_TRY(launch_emit(a1, z.fp32, st));
   HIP_TRY(hipEventRecord(s->evk[0], st));
-  HIP_TRY(launch_mc_pass(a1, z.fp32, grid, st));
+  HIP_TRY(launch_mc_pass(a1, z.fp32, grid1, st));
   HIP_TRY(hipEventRecord(s->evk[1], st));
   const long long cstride = (long long)kTallyStride * nc;
   HIP_TRY(launch_tally_to_flux(s->Tpre, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_pre,
@@ -589,7 +579,7 @@ static slh_status run_step(slh_solver* s) {
   const PassArgs a2 = pass_args(s, 2);
   HIP_TRY(launch_emit(a2, z.fp32, st));
   HIP_TRY(hipEventRecord(s->evk[2], st));
-  HIP_TRY(launch_mc_pass(a2, z.fp32, grid, st));
+  HIP_TRY(launch_mc_pass(a2, z.fp32, grid2, st));
   HIP_TRY(hipEventRecord(s->evk[3], st));
   HIP_TRY(launch_tally_to_flux(s->TR, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_R, st));
   hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,

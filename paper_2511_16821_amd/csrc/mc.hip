@@ -5,12 +5,12 @@
 // w (1 - e^{-sigma l}) / sigma per segment, and the census write of the remap
 // pass.
 //
-// Execution model: a persistent grid.  Every lane owns one history at a time;
-// when histories end, the wave ballots its idle lanes, takes a contiguous
-// block of work indices with a single atomic and hands them out in lane order,
-// so lanes refill without waiting for the slowest history of the wave.  The
-// work index g maps to census particle g (g < n_in) or source particle
-// g - n_in; every random number of a history is a pure function of its
+// Execution model: a persistent grid sized to the device's occupancy.  Every
+// lane owns one history at a time and, when it ends, takes its next work index
+// from a fixed stride (lane t of T takes t, t + T, ...), so lanes refill
+// without waiting for the slowest history of their wave and without any
+// shared counter.  The work index g maps to census particle g (g < n_in) or
+// source particle g - n_in; every random number of a history is a pure function of its
 // (stream, dimension, point index), so results do not depend on which lane or
 // wave ran it.  Tallies and balance sums are two-word fixed point with integer
 // atomics and are therefore independent of the schedule.  Each lane adds into
@@ -171,10 +171,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const Bank<R> bout = Real<R>::out(a);
   const int n_lim = a.n_lim;
 
-  bool have = false, exhausted = false;
+  bool have = false;
   // the tally atomic waiting to be issued; until the first real tally it adds 0
   // to a word picked per lane, so the zero adds do not pile onto one address
   const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t_all = (long long)gridDim.x * blockDim.x;
+  long long next = gtid;
   const long long my_copy = (gtid % a.n_copies) * a.copy_stride;
   unsigned long long* pend_ptr = a.Ta + my_copy + kTallyStride * (gtid % a.n_cells);
   unsigned long long pend_val = 0ull;
@@ -189,62 +191,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   unsigned int lane_seg = 0, lane_hist = 0, lane_alive = 0, lane_killed = 0;
 
   for (;;) {
-    if (!exhausted) {
-      const unsigned long long need = __ballot(!have);
-      if (need) {
-        const int cnt = __popcll(need);
-        const int leader = __ffsll((long long)need) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(&st->work, (unsigned long long)cnt);
-        base = __shfl(base, leader);
-        if (base + (unsigned long long)cnt >= n_tot) exhausted = true;
-        if (!have) {
-          const unsigned long long gg =
-              base + (unsigned long long)__popcll(need & ((1ull << lane) - 1ull));
-          if (gg < n_tot) {
-            g = (long long)gg;
-            have = true;
-            lane_hist++;
-            seg_p = 0;
-            acc_abs = 0.0;
-            acc_sca = 0.0;
-            n = 0;
-            if (g < n_in) {
-              // census particle at the start of the step, counter reset
-              from_census = true;
-              px = bin.px[g]; py = bin.py[g]; ox = bin.ox[g]; oy = bin.oy[g]; w = bin.w[g];
-              const int cell = bin.cell[g];
-              ix = cell % a.nx; iy = cell / a.nx;
-              hid = bin.hid[g];
-              trel = (R)0;
-              stream = (KIND == 1 && n_lim > 0)
-                           ? stream_seed(a.seed, a.step, (uint32_t)KIND, 1u, hid >> 32) : 0ull;
-              pidx = (uint32_t)(hid & 0xffffffffull);
-              dcur = 0;
-            } else {
-              // source particle, emitted by k_emit
-              from_census = false;
-              const long long s = g - n_in;
-              const SrcBank<R> sb = Real<R>::src(a);
-              stream = src_stream;
-              pidx = (uint32_t)s;
-              hid = (a.step << 32) | (uint64_t)s;
-              px = sb.px[s]; py = sb.py[s]; ox = sb.ox[s]; oy = sb.oy[s]; w = sb.w[s];
-              trel = sb.trel[s];
-              tau = sb.tau[s];
-              const int cell = sb.cell[s];
-              ix = cell % a.nx; iy = cell / a.nx;
-              dcur = 7;  // dims 0-5 emission, 6 the first optical depth
-            }
-            iox = ox != (R)0 ? (R)1 / ox : (R)0;
-            ioy = oy != (R)0 ? (R)1 / oy : (R)0;
-            w0 = (double)w;
-            if (from_census && n_lim > 0) {
-              tau = -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, 0u, pidx)));
-              dcur = 1;
-            }
-          }
-        }
+    // static work assignment: lane t of T takes work items t, t + T, t + 2T, ...
+    if (!have && next < (long long)n_tot) {
+      g = next;
+      next += t_all;
+      have = true;
+      lane_hist++;
+      seg_p = 0;
+      acc_abs = 0.0;
+      acc_sca = 0.0;
+      n = 0;
+      if (g < n_in) {
+        // census particle at the start of the step, counter reset
+        from_census = true;
+        px = bin.px[g]; py = bin.py[g]; ox = bin.ox[g]; oy = bin.oy[g]; w = bin.w[g];
+        const int cell = bin.cell[g];
+        ix = cell % a.nx; iy = cell / a.nx;
+        hid = bin.hid[g];
+        trel = (R)0;
+        stream = (KIND == 1 && n_lim > 0)
+                     ? stream_seed(a.seed, a.step, (uint32_t)KIND, 1u, hid >> 32) : 0ull;
+        pidx = (uint32_t)(hid & 0xffffffffull);
+        dcur = 0;
+      } else {
+        // source particle, emitted by k_emit
+        from_census = false;
+        const long long s = g - n_in;
+        const SrcBank<R> sb = Real<R>::src(a);
+        stream = src_stream;
+        pidx = (uint32_t)s;
+        hid = (a.step << 32) | (uint64_t)s;
+        px = sb.px[s]; py = sb.py[s]; ox = sb.ox[s]; oy = sb.oy[s]; w = sb.w[s];
+        trel = sb.trel[s];
+        tau = sb.tau[s];
+        const int cell = sb.cell[s];
+        ix = cell % a.nx; iy = cell / a.nx;
+        dcur = 7;  // dims 0-5 emission, 6 the first optical depth
+      }
+      iox = ox != (R)0 ? (R)1 / ox : (R)0;
+      ioy = oy != (R)0 ? (R)1 / oy : (R)0;
+      w0 = (double)w;
+      if (from_census && n_lim > 0) {
+        tau = -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, 0u, pidx)));
+        dcur = 1;
       }
     }
     if (!__any(have)) {
@@ -390,6 +379,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                               : k == 2 ? &st->alive : &st->killed;
     if (s_cnt[k]) atomicAdd(dst, s_cnt[k]);
   }
+}
+
+// Blocks of the persistent tracking grid: as many as can be resident at once
+// (occupancy x compute units), never more than the work needs.
+int mc_pass_grid(bool fp32, int kind, long long max_work) {
+  static int cached[2][2] = {{0, 0}, {0, 0}};
+  int& nb = cached[fp32 ? 1 : 0][kind == 1 ? 0 : 1];
+  if (nb == 0) {
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e;
+    if (kind == 1)
+      e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_mc_pass<float, 1>, 256, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_mc_pass<double, 1>, 256, 0);
+    else
+      e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_mc_pass<float, 2>, 256, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_mc_pass<double, 2>, 256, 0);
+    if (e != hipSuccess || per < 1) per = 2;
+    if (cus < 1) cus = 256;
+    nb = cus * per;
+  }
+  long long want = (max_work + 255) / 256;
+  if (want > nb) want = nb;
+  return (int)(want < 1 ? 1 : want);
 }
 
 hipError_t launch_emit(const PassArgs& a, bool fp32, hipStream_t s) {

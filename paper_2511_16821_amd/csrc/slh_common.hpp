@@ -227,6 +227,7 @@ struct PassArgs {
 // ---------------------------------------------------------------------------
 
 hipError_t launch_emit(const PassArgs& a, bool fp32, hipStream_t s);
+int mc_pass_grid(bool fp32, int kind, long long max_work);
 hipError_t launch_mc_pass(const PassArgs& a, bool fp32, int grid, hipStream_t s);
 hipError_t launch_qmc_points(uint64_t stream, uint32_t dim0, uint32_t nd, uint32_t idx0,
                              uint32_t n, int mode, const uint32_t* sobol, uint32_t* out,

@@ -190,7 +190,9 @@ slh_status slh_get_census(slh_solver *s, int64_t *n, double *x, double *y, doubl
 slh_status slh_save(slh_solver *s, void *buf, size_t *len);
 slh_status slh_load(slh_solver *s, const void *buf, size_t len);
 
-/* Device memory the solver for this problem needs, in bytes (admission). */
+/* Device memory the solver for this problem needs, in bytes (admission).
+ * Exact when sigma_s and sigma_a are given (the collided sweep's material
+ * table depends on them); with NULL fields an upper bound over both sweeps. */
 size_t slh_footprint_bytes(const slh_problem *problem);
 
 void slh_destroy(slh_solver *s);

@@ -86,7 +86,17 @@ static std::vector<double> product_quadrature(int order) {
       dirs.push_back(2.0 * w[k] * M_PI / order);
     }
   }
-  return dirs;
+  // group the directions by quadrant (stable), so that runs of equal-quadrant
+  // directions can share a sweep workgroup
+  const int n = (int)dirs.size() / 3;
+  std::vector<double> out;
+  out.reserve(dirs.size());
+  for (int q = 0; q < 4; ++q)
+    for (int m = 0; m < n; ++m) {
+      const int qm = (dirs[3 * m] > 0.0 ? 0 : 1) + (dirs[3 * m + 1] > 0.0 ? 0 : 2);
+      if (qm == q) out.insert(out.end(), dirs.begin() + 3 * m, dirs.begin() + 3 * m + 3);
+    }
+  return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -97,8 +107,59 @@ struct Sizes {
   int n_dir;
   int n_copies;  // private tally copies
   bool fp32;
+  // DG sweep: table mode (per-(direction, material) coefficients staged in
+  // LDS, n_mat distinct sigma_e) or cell mode; dg_cw sweeping lanes per
+  // workgroup, dg_chunks chunks per sweep.
+  int n_mat;
+  bool dg_table;
+  int dg_cw;
+  long long dg_chunks;
   size_t bytes;
 };
+
+static double sigma_e_of(const slh_problem* p, long long i) {
+  const double tau = p->time_closure > 0.0 ? p->time_closure : 2.0;
+  return p->sigma_a[i] + p->sigma_s[i] + tau / (p->c * p->dt);
+}
+
+// Sorted distinct sigma_e values of the problem's cells.
+static std::vector<double> material_values(const slh_problem* p) {
+  const long long n = (long long)p->nx * p->ny;
+  std::vector<double> v(n);
+  for (long long i = 0; i < n; ++i) v[i] = sigma_e_of(p, i);
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  return v;
+}
+
+// LDS bytes one workgroup may use on the current device.
+static size_t lds_limit() {
+  static size_t cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (!cached[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v < 65536)
+      v = 65536;
+    cached[dev] = (size_t)v;
+  }
+  return cached[dev];
+}
+
+// Chooses the sweep.  n_mat < 0: the fields are not known (footprint bound).
+static void plan_dg(Sizes& z, const slh_problem* p, long long n_mat) {
+  const int diag = std::min(p->nx, p->ny);  // longest diagonal
+  z.dg_cw = std::min(256, (diag + 63) / 64 * 64);
+  const size_t lim = lds_limit();
+  // the cell-mode sweep must fit; fewer lanes per chunk leave more LDS for the faces
+  while (z.dg_cw > 64 && dg_sweep_lds_bytes(false, z.dg_cw, 0, p->nx, p->ny) > lim)
+    z.dg_cw -= 64;
+  z.n_mat = n_mat < 0 ? (int)std::max<long long>(0, (long long)(lim / 256)) : (int)n_mat;
+  z.dg_table = n_mat != 0 && dg_sweep_lds_bytes(true, z.dg_cw, z.n_mat, p->nx, p->ny) <= lim;
+  if (n_mat < 0) z.dg_table = true;  // bound: table storage counted
+  z.dg_chunks = dg_chunks(p->nx, p->ny, z.dg_cw);
+}
 
 static bool finite_nonneg(const double* p, long long n) {
   for (long long i = 0; i < n; ++i)
@@ -156,6 +217,8 @@ static Sizes sizes_of(const slh_problem* p) {
   while (z.n_copies > 1 && (size_t)z.n_copies * kTallyStride * 8 * (size_t)z.n_cells > (64u << 20))
     z.n_copies /= 2;
   z.fp32 = p->precision == SLH_FP32_TRACK;
+  const bool fields = p->sigma_s && p->sigma_a;
+  plan_dg(z, p, fields ? (long long)material_values(p).size() : -1);
   const size_t rb = z.fp32 ? 4 : 8;
   const size_t bank = 5 * rb + 4 + 8;
   size_t b = 0;
@@ -164,7 +227,8 @@ static Sizes sizes_of(const slh_problem* p) {
   b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 2;  // nodal sources, trees
   b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
   b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
-  b += (size_t)z.n_dir * nc * 32;            // per-direction planes
+  b += (size_t)z.n_dir * nc * 32 + (size_t)z.n_dir * 256;  // direction planes, element data
+  if (z.dg_table) b += nc * 4 + (size_t)z.n_mat * 8 + (size_t)z.n_dir * z.n_mat * 256;
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
   b += (size_t)z.cap * bank * 2;             // census banks
   b += (size_t)(z.n_p > 0 ? z.n_p : 1) * (7 * rb + 4);  // source bank
@@ -247,6 +311,9 @@ struct slh_solver {
   double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr,
          *phi_c2 = nullptr;
   double *psi = nullptr, *dg_part = nullptr, *dirs = nullptr;
+  double* dirmat = nullptr;  // DG element data per direction
+  int* mat_id = nullptr;     // DG table mode: material of each cell,
+  double *sig_e_mat = nullptr, *coef = nullptr;  // its sigma_e, coefficients
   double* dg_src = nullptr;
   int n_part = 1;
   void* bank_mem[2] = {nullptr, nullptr};
@@ -347,6 +414,8 @@ static slh_status setup(slh_solver* s) {
     ptr = (T*)s->dalloc(sizeof(T) * (size_t)(n));                                      \
     if (!ptr) return fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: " #ptr);    \
   } while (0)
+  if (dg_sweep_lds_bytes(false, z.dg_cw, 0, p.nx, p.ny) > lds_limit())
+    return fail(SLH_E_INVALID_ARG, "nx + ny too large for the sweep's LDS traces");
   ALLOC(s->mat64, double2, nc);
   ALLOC(s->mat32, float2, nc);
   ALLOC(s->sig_s, double, nc);
@@ -366,6 +435,12 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->phi_c, double, 4 * nc);
   ALLOC(s->phi_c2, double, 4 * nc);
   ALLOC(s->psi, double, (size_t)z.n_dir * 4 * nc);
+  ALLOC(s->dirmat, double, (size_t)z.n_dir * 32);
+  if (z.dg_table) {
+    ALLOC(s->mat_id, int, nc);
+    ALLOC(s->sig_e_mat, double, z.n_mat);
+    ALLOC(s->coef, double, (size_t)z.n_dir * z.n_mat * 32);
+  }
   ALLOC(s->dg_src, double, 4 * nc);
   s->n_part = dg_reduce_partials(4 * nc);
   ALLOC(s->dg_part, double, 2 * s->n_part + 2);
@@ -408,6 +483,21 @@ static slh_status setup(slh_solver* s) {
   HIP_TRY(hipMemcpyAsync(s->q, s->h_q.data(), 8 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->qn1, qn.data(), 32 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->dirs, dirs.data(), 8 * dirs.size(), hipMemcpyHostToDevice, st));
+  std::vector<int> mid;
+  std::vector<double> mval;
+  if (z.dg_table) {
+    mval.assign(se.begin(), se.end());
+    std::sort(mval.begin(), mval.end());
+    mval.erase(std::unique(mval.begin(), mval.end()), mval.end());
+    if ((long long)mval.size() != z.n_mat) return fail(SLH_E_STATE, "material count changed");
+    mid.resize(nc);
+    for (long long i = 0; i < nc; ++i)
+      mid[i] = (int)(std::lower_bound(mval.begin(), mval.end(), se[i]) - mval.begin());
+    HIP_TRY(hipMemcpyAsync(s->mat_id, mid.data(), 4 * nc, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->sig_e_mat, mval.data(), 8 * z.n_mat, hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(launch_dg_tables(z.n_dir, z.dg_table ? z.n_mat : 0, s->dirs, s->sig_e_mat, s->hx,
+                           s->hy, s->dirmat, s->coef, st));
   HIP_TRY(hipMemcpyAsync(s->sobol, sobol_table_host(), 4 * 32 * 32, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_build_tree(s->qn1, nc, s->adt, s->tree1, st));
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, st, s->st);
@@ -544,12 +634,18 @@ static slh_status run_step(slh_solver* s) {
   d.phi_post = s->phi_post;
   d.src = s->dg_src;
   d.psi = s->psi;
+  d.mat_id = s->mat_id;
+  d.n_mat = z.n_mat;
+  d.cw = z.dg_cw;
+  d.coef = s->coef;
+  d.dirmat = s->dirmat;
+  d.n_chunks = (int)z.dg_chunks;
   s->si_it = 0;
   s->si_conv = false;
   s->si_res = 0.0;
   for (int it = 0; it < s->si_max; ++it) {
     d.phi_in = s->phi_c;
-    HIP_TRY(launch_dg_sweep(d, st));
+    HIP_TRY(launch_dg_sweep(d, z.dg_table, st));
     HIP_TRY(launch_dg_reduce(z.n_dir, 4 * nc, s->psi, s->phi_c, s->phi_c2, s->dg_part,
                              s->n_part, st));
     HIP_TRY(hipMemcpyAsync(s->h_res, s->dg_part + 2 * s->n_part, 2 * sizeof(double),

@@ -3,23 +3,36 @@
 // and a step-averaged time closure sigma_e = sigma_t + tau/(c dt).  One
 // transport sweep per direction and source-iteration sweep.
 //
-// Device layout: one workgroup per direction.  The workgroup walks the cells
-// in diagonal wavefronts of its quadrant's upwind order; cells on one diagonal
-// have distinct rows and columns, so the outflow traces they hand to the next
-// diagonal live in two small LDS arrays (one trace per row for the x faces,
-// one per column for the y faces).  Each cell solves its 4x4 system in
-// registers.  The weighted nodal solution w_m psi_m goes to a per-direction
-// plane, and the directions are summed in a fixed order by a second kernel,
-// so the scalar flux does not depend on scheduling.
-//
 // Element matrices on a cell of size hx x hy, node k = kx + 2 ky at
 // (x_kx, y_ky), 1-D factors  M = h/6 [[2,1],[1,2]] (mass) and
 // K = 1/2 [[-1,1],[-1,1]] (K[i][j] = int L_i L_j'):
 //   A = a Kx(x)My + b Mx(x)Ky + sig_e Mx(x)My
 //     + |a| (e_f e_f^T)(x)My + |b| Mx(x)(e_g e_g^T)
 // where f (g) is the local index of the x (y) inflow face; the right side is
-// (Mx(x)My) S + |a| e_f (x) My up_x + |b| Mx up_y (x) e_g with the upwind
-// traces up_x, up_y (zero on the domain boundary).
+// (Mx(x)My) S + F up with F up = |a| e_f (x) My up_x + |b| Mx up_y (x) e_g for
+// the upwind traces up = (up_x0, up_x1, up_y0, up_y1) (zero on the domain
+// boundary).  On the uniform mesh A0 = A - sig_e Mx(x)My and F depend on the
+// direction only.
+//
+// Device layout: one workgroup per direction walks the cells in diagonal
+// wavefronts of the direction's upwind order, in chunks of CW cells (a
+// diagonal, or a piece of a long one).  Cells of one diagonal have distinct
+// rows and columns, so the outflow traces they hand to the next diagonal live
+// in two small LDS arrays (one trace per row for the x faces, one per column
+// for the y faces).  The workgroup has CW/64 sweeping waves and one loader
+// wave.  The loader keeps several chunks of nodal sources and material keys
+// in flight in registers and hands each chunk over through a two-slot LDS
+// buffer, so the sweeping waves never wait on global memory: their only
+// global accesses are the stores of w_m psi_m (a wave that mixed loads and
+// stores would have to drain all of them before using a loaded value).  After
+// each barrier a sweeping lane turns the upwind traces into its cell's
+// solution with the element data prepared before the barrier:
+//   table mode: psi = B S + G up with B = A^-1 Mx(x)My, G = A^-1 F taken from
+//     a per-(direction, material) table staged in LDS (few distinct sigma_e);
+//   cell mode: A is LU-factorised before the barrier and solved after it.
+// The weighted solution goes to a per-direction plane, and the directions
+// are summed in a fixed order by a second kernel, so the scalar flux does
+// not depend on scheduling.
 #include "slh_common.hpp"
 
 namespace slh {
@@ -31,34 +44,6 @@ __device__ __forceinline__ double recip(double a) {
   r = fma(fma(-a, r, 1.0), r, r);
   r = fma(fma(-a, r, 1.0), r, r);
   return r;
-}
-
-// Gaussian elimination without pivoting.  The upwind element matrix has a
-// positive-definite symmetric part (mass and inflow terms are SPD, the
-// streaming term's symmetric part is the outflow-minus-inflow face mass,
-// which the inflow term turns into |Omega.n| on every face), so every
-// leading block is invertible and no pivot vanishes.  Each pivot's
-// reciprocal is formed once and reused in the back substitution.
-__device__ __forceinline__ void solve4(double A[4][4], double r[4], double x[4]) {
-  double inv[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    inv[c] = recip(A[c][c]);
-#pragma unroll
-    for (int i = c + 1; i < 4; ++i) {
-      const double f = A[i][c] * inv[c];
-#pragma unroll
-      for (int k = c + 1; k < 4; ++k) A[i][k] -= f * A[c][k];
-      r[i] -= f * r[c];
-    }
-  }
-#pragma unroll
-  for (int i = 3; i >= 0; --i) {
-    double v = r[i];
-#pragma unroll
-    for (int k = i + 1; k < 4; ++k) v -= A[i][k] * x[k];
-    x[i] = v * inv[i];
-  }
 }
 
 // Nodal source of the collided equation for the current iterate:
@@ -77,131 +62,355 @@ __global__ void k_dg_source(long long n, const double* __restrict__ sig_s,
   }
 }
 
-__global__ __launch_bounds__(256) void k_dg_sweep(DgArgs g) {
-  extern __shared__ double s_face[];  // [ny][2] x-traces, then [nx][2] y-traces
-  const int m = blockIdx.x;
-  const double a = g.dir[3 * m + 0], b = g.dir[3 * m + 1], wm = g.dir[3 * m + 2];
-  const int nx = g.nx, ny = g.ny;
-  double* xf = s_face;
-  double* yf = s_face + 2 * ny;
-  for (int k = threadIdx.x; k < 2 * (nx + ny); k += blockDim.x) s_face[k] = 0.0;
-  __syncthreads();
-
-  const double hx = g.hx, hy = g.hy;
-  const bool apos = a > 0.0, bpos = b > 0.0;
-  const int fx = apos ? 0 : 1, fy = bpos ? 0 : 1;
+// Direction part of the element: A0 and F (row-major 4x4 each) and the mass
+// matrix MM = Mx(x)My.
+__device__ void element(double a, double b, double hx, double hy, double A0[4][4],
+                        double F[4][4], double MM[4][4]) {
+  const int fx = a > 0.0 ? 0 : 1, fy = b > 0.0 ? 0 : 1;
   const double aa = fabs(a), ab = fabs(b);
   const double Mx[2][2] = {{hx / 3.0, hx / 6.0}, {hx / 6.0, hx / 3.0}};
   const double My[2][2] = {{hy / 3.0, hy / 6.0}, {hy / 6.0, hy / 3.0}};
   const double K[2][2] = {{-0.5, 0.5}, {-0.5, 0.5}};
-  // direction-only part of the element matrix (uniform mesh)
-  double A0[4][4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int kx = k & 1, ky = k >> 1;
-#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int kx = r & 1, ky = r >> 1;
     for (int l = 0; l < 4; ++l) {
       const int lx = l & 1, ly = l >> 1;
       double v = a * K[kx][lx] * My[ky][ly] + b * Mx[kx][lx] * K[ky][ly];
       if (kx == fx && lx == fx) v += aa * My[ky][ly];
       if (ky == fy && ly == fy) v += ab * Mx[kx][lx];
-      A0[k][l] = v;
+      A0[r][l] = v;
+      MM[r][l] = Mx[kx][lx] * My[ky][ly];
     }
-  }
-  const double4* __restrict__ S4 = reinterpret_cast<const double4*>(g.src);
-  double4* __restrict__ out = reinterpret_cast<double4*>(g.psi + (long long)m * 4 * nx * ny);
-
-  const int n_diag = nx + ny - 1;
-  const int tid = threadIdx.x, B = blockDim.x;
-  // prefetch of the first cell of this thread on the next diagonal
-  int p_ip = tid;  // diagonal 0 holds ip = 0 only
-  bool p_has = p_ip <= 0;
-  double p_se = 0.0;
-  double4 p_S = make_double4(0.0, 0.0, 0.0, 0.0);
-  long long p_cell = 0;
-  if (p_has) {
-    const int i = apos ? 0 : nx - 1, j = bpos ? 0 : ny - 1;
-    p_cell = (long long)j * nx + i;
-    p_se = g.sig_e[p_cell];
-    p_S = S4[p_cell];
-  }
-  for (int d = 0; d < n_diag; ++d) {
-    const int i_lo = d - (ny - 1) > 0 ? d - (ny - 1) : 0;
-    const int i_hi = d < nx - 1 ? d : nx - 1;
-    int ip = p_ip;
-    bool has = p_has;
-    double se = p_se;
-    double4 Sv = p_S;
-    long long cell = p_cell;
-    if (d + 1 < n_diag) {  // issue next diagonal's loads before this one's work
-      const int dn = d + 1;
-      const int lo_n = dn - (ny - 1) > 0 ? dn - (ny - 1) : 0;
-      const int hi_n = dn < nx - 1 ? dn : nx - 1;
-      p_ip = lo_n + tid;
-      p_has = p_ip <= hi_n;
-      if (p_has) {
-        const int jp = dn - p_ip;
-        const int i = apos ? p_ip : nx - 1 - p_ip, j = bpos ? jp : ny - 1 - jp;
-        p_cell = (long long)j * nx + i;
-        p_se = g.sig_e[p_cell];
-        p_S = S4[p_cell];
-      }
-    }
-    for (;;) {
-      if (!has) break;
-      const int jp = d - ip;
-      const int i = apos ? ip : nx - 1 - ip;
-      const int j = bpos ? jp : ny - 1 - jp;
-      const double S[4] = {Sv.x, Sv.y, Sv.z, Sv.w};
-      const double upx0 = xf[2 * j], upx1 = xf[2 * j + 1];
-      const double upy0 = yf[2 * i], upy1 = yf[2 * i + 1];
-      double A[4][4], r[4], x[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int kx = k & 1, ky = k >> 1;
-        double rk = 0.0;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          const int lx = l & 1, ly = l >> 1;
-          const double mm = Mx[kx][lx] * My[ky][ly];
-          A[k][l] = A0[k][l] + se * mm;
-          rk += mm * S[l];
-        }
-        if (kx == fx) rk += aa * (My[ky][0] * upx0 + My[ky][1] * upx1);
-        if (ky == fy) rk += ab * (Mx[kx][0] * upy0 + Mx[kx][1] * upy1);
-        r[k] = rk;
-      }
-      solve4(A, r, x);
-      // outflow traces for the downstream neighbours
-      xf[2 * j] = apos ? x[1] : x[0];
-      xf[2 * j + 1] = apos ? x[3] : x[2];
-      yf[2 * i] = bpos ? x[2] : x[0];
-      yf[2 * i + 1] = bpos ? x[3] : x[1];
-      out[cell] = make_double4(wm * x[0], wm * x[1], wm * x[2], wm * x[3]);
-      // further cells of this thread on a diagonal longer than the block
-      ip += B;
-      has = ip <= i_hi;
-      if (has) {
-        const int jq = d - ip;
-        const int iq = apos ? ip : nx - 1 - ip, jj = bpos ? jq : ny - 1 - jq;
-        cell = (long long)jj * nx + iq;
-        se = g.sig_e[cell];
-        Sv = S4[cell];
-      }
-    }
-    (void)i_lo;
-    __syncthreads();
+    F[r][0] = kx == fx ? aa * My[ky][0] : 0.0;
+    F[r][1] = kx == fx ? aa * My[ky][1] : 0.0;
+    F[r][2] = ky == fy ? ab * Mx[kx][0] : 0.0;
+    F[r][3] = ky == fy ? ab * Mx[kx][1] : 0.0;
   }
 }
 
-hipError_t launch_dg_sweep(const DgArgs& a, hipStream_t s) {
+// Per-direction element data [m][32]: A0 then F.
+__global__ void k_dg_dirmat(int n_dir, const double* __restrict__ dir, double hx, double hy,
+                            double* __restrict__ dm) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_dir) return;
+  double A0[4][4], F[4][4], MM[4][4];
+  element(dir[3 * m], dir[3 * m + 1], hx, hy, A0, F, MM);
+  for (int r = 0; r < 4; ++r)
+    for (int l = 0; l < 4; ++l) {
+      dm[32 * m + 4 * r + l] = A0[r][l];
+      dm[32 * m + 16 + 4 * r + l] = F[r][l];
+    }
+}
+
+// Table [m][material][32]: B = A^-1 MM then G = A^-1 F (row-major), by
+// Gauss-Jordan elimination of [A | MM | F]; the pivots do not vanish (the
+// symmetric part of the upwind element matrix is positive definite: mass and
+// inflow terms are SPD and the streaming term's symmetric part, the outflow
+// minus inflow face mass, becomes |Omega.n| face mass with the inflow term).
+__global__ void k_dg_coef(int n_dir, int n_mat, const double* __restrict__ dir,
+                          const double* __restrict__ sig_e_mat, double hx, double hy,
+                          double* __restrict__ coef) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n_dir * n_mat) return;
+  const int m = (int)(t / n_mat), k = (int)(t % n_mat);
+  const double se = sig_e_mat[k];
+  double A[4][4], F[4][4], MM[4][4], R[4][8];
+  element(dir[3 * m], dir[3 * m + 1], hx, hy, A, F, MM);
+  for (int r = 0; r < 4; ++r)
+    for (int l = 0; l < 4; ++l) {
+      A[r][l] += se * MM[r][l];
+      R[r][l] = MM[r][l];
+      R[r][4 + l] = F[r][l];
+    }
+  for (int c = 0; c < 4; ++c) {
+    const double inv = 1.0 / A[c][c];
+    for (int l = 0; l < 4; ++l) A[c][l] *= inv;
+    for (int j = 0; j < 8; ++j) R[c][j] *= inv;
+    for (int r = 0; r < 4; ++r) {
+      if (r == c) continue;
+      const double f = A[r][c];
+      for (int l = 0; l < 4; ++l) A[r][l] -= f * A[c][l];
+      for (int j = 0; j < 8; ++j) R[r][j] -= f * R[c][j];
+    }
+  }
+  double* o = coef + t * 32;
+  for (int r = 0; r < 4; ++r)
+    for (int j = 0; j < 4; ++j) {
+      o[4 * r + j] = R[r][j];
+      o[16 + 4 * r + j] = R[r][4 + j];
+    }
+}
+
+hipError_t launch_dg_tables(int n_dir, int n_mat, const double* dir, const double* sig_e_mat,
+                            double hx, double hy, double* dirmat, double* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_dg_dirmat, dim3((n_dir + 63) / 64), dim3(64), 0, s, n_dir, dir, hx, hy,
+                     dirmat);
+  if (n_mat > 0 && coef) {
+    const long long n = (long long)n_dir * n_mat;
+    hipLaunchKernelGGL(k_dg_coef, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, n_dir,
+                       n_mat, dir, sig_e_mat, hx, hy, coef);
+  }
+  return hipGetLastError();
+}
+
+// Chunks of the sweep: sum over diagonals of ceil(length / cw).
+long long dg_chunks(int nx, int ny, int cw) {
+  long long n = 0;
+  for (int d = 0; d < nx + ny - 1; ++d) {
+    const int lo = d - (ny - 1) > 0 ? d - (ny - 1) : 0;
+    const int hi = d < nx - 1 ? d : nx - 1;
+    n += (hi - lo + cw) / cw;
+  }
+  return n;
+}
+
+constexpr int kDgDepth = 4;  // chunks in flight in the loader wave
+
+// One chunk in the loader: up to four cells per lane (source, key, position
+// in the chunk or -1).
+struct DgStage {
+  double Sx[4], Sy[4], Sz[4], Sw[4];
+  double Kd[4];  // cell mode: sigma_e
+  int Ki[4];     // table mode: material
+  int C[4];
+};
+
+template <bool TABLE>
+__global__ __launch_bounds__(320) void k_dg_sweep_pc(DgArgs g) {
+  extern __shared__ double smem[];
+  const int nx = g.nx, ny = g.ny;
+  const int CW = g.cw;       // sweeping lanes, multiple of 64, <= 256
+  const int npl = CW >> 6;   // cells per loader lane and chunk
+  const int m = blockIdx.x;
+  const double a = g.dir[3 * m + 0], b = g.dir[3 * m + 1], wm = g.dir[3 * m + 2];
+  const bool apos = a > 0.0, bpos = b > 0.0;
+  // LDS: slots S [2][CW] double4 | keys [2][CW] | coef [n_mat][32] (table) | faces
+  double4* slotS = reinterpret_cast<double4*>(smem);
+  double* slotK = smem + (size_t)2 * CW * 4;
+  double* coefL = slotK + (size_t)2 * CW;
+  const size_t n_coef = TABLE ? (size_t)g.n_mat * 32 : 0;
+  double* xf = coefL + n_coef;
+  double* yf = xf + 2 * ny;
+  const int n_diag = nx + ny - 1;
+  // barriers: one per chunk, padded to whole loader rounds (the padding
+  // chunks are empty), so the loader's rounds have no conditional steps
+  const int n_pad = (g.n_chunks + kDgDepth - 1) / kDgDepth * kDgDepth;
+  auto diag_hi = [&](int dd) __attribute__((always_inline)) { return dd < nx - 1 ? dd : nx - 1; };
+  auto diag_lo = [&](int dd) __attribute__((always_inline)) { return dd - (ny - 1) > 0 ? dd - (ny - 1) : 0; };
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const bool loader = wave == npl;
+  const int lane = threadIdx.x & 63;
+
+  // ---- loader state: ring of kDgDepth chunks, npl cells per lane ----
+  DgStage r0s, r1s, r2s, r3s;
+  int fd = 0, fp = 0;   // fetch front: diagonal, first position
+  // Every lane issues the same loads in every stage (a position without a
+  // cell reads cell 0 and is marked -1): with no branch around the loads the
+  // compiler can wait for one stage while the younger ones stay in flight.
+  auto fetch = [&](DgStage& st) __attribute__((always_inline)) {
+    const bool live = fd < n_diag;
+    const int hi = live ? diag_hi(fd) : -1;
+    const int dl = live ? fd : n_diag - 1;  // a real diagonal for the addresses
+    const int dlo = diag_lo(dl), dhi = diag_hi(dl);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int tq = lane + 64 * q;
+      const int ip = fp + tq;
+      const bool ok = q < npl && ip <= hi;
+      // clamp the position onto the diagonal, so that every lane's address
+      // is a real cell and no branch guards the loads
+      const int ipc = ip < dlo ? dlo : (ip < dhi ? ip : dhi);
+      const int jp = dl - ipc;
+      const int i = apos ? ipc : nx - 1 - ipc;
+      const int j = bpos ? jp : ny - 1 - jp;
+      const long long c = (long long)j * nx + i;
+      st.C[q] = ok ? tq : -1;
+      if (TABLE) st.Ki[q] = g.mat_id[c];
+      else st.Kd[q] = g.sig_e[c];
+      const double4 v = reinterpret_cast<const double4*>(g.src)[c];
+      st.Sx[q] = v.x;
+      st.Sy[q] = v.y;
+      st.Sz[q] = v.z;
+      st.Sw[q] = v.w;
+    }
+    if (live) {
+      fp += CW;
+      if (fp > hi) {
+        ++fd;
+        fp = fd < n_diag ? diag_lo(fd) : 0;
+      }
+    }
+  };
+  auto hand_over = [&](const DgStage& st, int slot) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (st.C[q] >= 0) {
+        slotS[slot * CW + st.C[q]] = make_double4(st.Sx[q], st.Sy[q], st.Sz[q], st.Sw[q]);
+        slotK[slot * CW + st.C[q]] = TABLE ? (double)st.Ki[q] : st.Kd[q];
+      }
+  };
+  if (loader) {
+    fetch(r0s);
+    fetch(r1s);
+    fetch(r2s);
+    fetch(r3s);
+  }
+  for (int k = threadIdx.x; k < 2 * (nx + ny); k += blockDim.x) xf[k] = 0.0;
+  if (TABLE) {
+    const double* src = g.coef + (size_t)m * n_coef;
+    for (size_t k = threadIdx.x; k < n_coef; k += blockDim.x) coefL[k] = src[k];
+  }
+  if (loader) {
+    hand_over(r0s, 0);
+    fetch(r0s);
+  }
+  __syncthreads();  // faces zeroed, table staged, chunk 0 in slot 0
+
+  if (loader) {
+    // before barrier k, chunk k + 1 goes to slot (k + 1) & 1; it sits in
+    // ring entry (k + 1) % depth, loaded depth - 1 rounds earlier
+    for (int k0 = 0; k0 < n_pad; k0 += kDgDepth) {
+#define SLH_DG_LOAD_STEP(U, R)    \
+  hand_over(R, (k0 + U + 1) & 1); \
+  fetch(R);                       \
+  __syncthreads();
+      SLH_DG_LOAD_STEP(0, r1s)
+      SLH_DG_LOAD_STEP(1, r2s)
+      SLH_DG_LOAD_STEP(2, r3s)
+      SLH_DG_LOAD_STEP(3, r0s)
+#undef SLH_DG_LOAD_STEP
+    }
+    return;
+  }
+
+  // ---- sweeping lanes ----
+  const int t = threadIdx.x;
+  double dmA[16], dmF[16];  // cell mode: direction element data
+  if (!TABLE) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      dmA[k] = g.dirmat[32 * m + k];
+      dmF[k] = g.dirmat[32 * m + 16 + k];
+    }
+  }
+  const double hx = g.hx, hy = g.hy;
+  const double MM[4][4] = {
+      {hx * hy / 9.0, hx * hy / 18.0, hx * hy / 18.0, hx * hy / 36.0},
+      {hx * hy / 18.0, hx * hy / 9.0, hx * hy / 36.0, hx * hy / 18.0},
+      {hx * hy / 18.0, hx * hy / 36.0, hx * hy / 9.0, hx * hy / 18.0},
+      {hx * hy / 36.0, hx * hy / 18.0, hx * hy / 18.0, hx * hy / 9.0}};
+  double4* __restrict__ out = reinterpret_cast<double4*>(g.psi + (long long)m * 4 * nx * ny);
+  int cd = 0, cp = 0;  // next chunk to prepare
+  bool c_has = false;
+  int c_i = 0, c_j = 0;
+  double P[16];    // table: G; cell mode: LU (inverse pivots, L, strict U)
+  double r0[4];    // table: B S; cell mode: MM S
+  auto prepare = [&](int slot) __attribute__((always_inline)) {
+    const int ip = cp + t;
+    c_has = cd < n_diag && ip <= diag_hi(cd);
+    if (c_has) {
+      const int jp = cd - ip;
+      c_i = apos ? ip : nx - 1 - ip;
+      c_j = bpos ? jp : ny - 1 - jp;
+      const double4 S = slotS[slot * CW + t];
+      const double key = slotK[slot * CW + t];
+      if (TABLE) {
+        const double* c = coefL + (size_t)(int)key * 32;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          r0[r] = c[4 * r] * S.x + c[4 * r + 1] * S.y + c[4 * r + 2] * S.z + c[4 * r + 3] * S.w;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) P[k] = c[16 + k];
+      } else {
+        double A[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+          for (int l = 0; l < 4; ++l) A[r][l] = dmA[4 * r + l] + key * MM[r][l];
+          r0[r] = MM[r][0] * S.x + MM[r][1] * S.y + MM[r][2] * S.z + MM[r][3] * S.w;
+        }
+        // LU without pivoting (see k_dg_coef for why the pivots do not vanish)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double inv = recip(A[c][c]);
+          P[c] = inv;
+#pragma unroll
+          for (int r = c + 1; r < 4; ++r) {
+            const double f = A[r][c] * inv;
+            A[r][c] = f;
+#pragma unroll
+            for (int l = c + 1; l < 4; ++l) A[r][l] -= f * A[c][l];
+          }
+        }
+        P[4] = A[1][0]; P[5] = A[2][0]; P[6] = A[3][0];
+        P[7] = A[2][1]; P[8] = A[3][1]; P[9] = A[3][2];
+        P[10] = A[0][1]; P[11] = A[0][2]; P[12] = A[0][3];
+        P[13] = A[1][2]; P[14] = A[1][3]; P[15] = A[2][3];
+      }
+    }
+    if (cd < n_diag) {
+      cp += CW;
+      if (cp > diag_hi(cd)) {
+        ++cd;
+        cp = cd < n_diag ? diag_lo(cd) : 0;
+      }
+    }
+  };
+  prepare(0);
+  for (int k = 0; k < n_pad; ++k) {
+    __syncthreads();  // traces of chunk k - 1 written, chunk k + 1 in its slot
+    if (c_has) {
+      const double u0 = xf[2 * c_j], u1 = xf[2 * c_j + 1];
+      const double u2 = yf[2 * c_i], u3 = yf[2 * c_i + 1];
+      double x0, x1, x2, x3;
+      if (TABLE) {
+        x0 = r0[0] + P[0] * u0 + P[1] * u1 + P[2] * u2 + P[3] * u3;
+        x1 = r0[1] + P[4] * u0 + P[5] * u1 + P[6] * u2 + P[7] * u3;
+        x2 = r0[2] + P[8] * u0 + P[9] * u1 + P[10] * u2 + P[11] * u3;
+        x3 = r0[3] + P[12] * u0 + P[13] * u1 + P[14] * u2 + P[15] * u3;
+      } else {
+        double y0 = r0[0] + dmF[0] * u0 + dmF[1] * u1 + dmF[2] * u2 + dmF[3] * u3;
+        double y1 = r0[1] + dmF[4] * u0 + dmF[5] * u1 + dmF[6] * u2 + dmF[7] * u3;
+        double y2 = r0[2] + dmF[8] * u0 + dmF[9] * u1 + dmF[10] * u2 + dmF[11] * u3;
+        double y3 = r0[3] + dmF[12] * u0 + dmF[13] * u1 + dmF[14] * u2 + dmF[15] * u3;
+        y1 -= P[4] * y0;
+        y2 -= P[5] * y0 + P[7] * y1;
+        y3 -= P[6] * y0 + P[8] * y1 + P[9] * y2;
+        x3 = y3 * P[3];
+        x2 = (y2 - P[15] * x3) * P[2];
+        x1 = (y1 - P[13] * x2 - P[14] * x3) * P[1];
+        x0 = (y0 - P[10] * x1 - P[11] * x2 - P[12] * x3) * P[0];
+      }
+      xf[2 * c_j] = apos ? x1 : x0;
+      xf[2 * c_j + 1] = apos ? x3 : x2;
+      yf[2 * c_i] = bpos ? x2 : x0;
+      yf[2 * c_i + 1] = bpos ? x3 : x1;
+      out[(long long)c_j * nx + c_i] = make_double4(wm * x0, wm * x1, wm * x2, wm * x3);
+    }
+    prepare((k + 1) & 1);
+  }
+  // Drain this wave's stores before the sweeping and loader paths join: the
+  // compiler's wait counting cannot follow a mix of pending loads and stores,
+  // and would otherwise wait for every load of the loader's ring.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny) {
+  return sizeof(double) * ((size_t)2 * cw * 5 + (table ? (size_t)n_mat * 32 : 0) +
+                           (size_t)2 * (nx + ny));
+}
+
+hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   const long long nc = (long long)a.nx * a.ny;
   long long b = (nc + 255) / 256;
   const int grid = (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
   hipLaunchKernelGGL(k_dg_source, dim3(grid), dim3(256), 0, s, nc, a.sig_s, a.phi_post,
                      a.phi_in, a.src);
-  const size_t lds = sizeof(double) * 2 * (size_t)(a.nx + a.ny);
-  hipLaunchKernelGGL(k_dg_sweep, dim3(a.n_dir), dim3(256), lds, s, a);
+  const size_t lds = dg_sweep_lds_bytes(table, a.cw, a.n_mat, a.nx, a.ny);
+  if (table)
+    hipLaunchKernelGGL(k_dg_sweep_pc<true>, dim3(a.n_dir), dim3(a.cw + 64), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_dg_sweep_pc<false>, dim3(a.n_dir), dim3(a.cw + 64), lds, s, a);
   return hipGetLastError();
 }
 

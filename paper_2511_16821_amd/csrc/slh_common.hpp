@@ -245,8 +245,19 @@ struct DgArgs {
   const double* phi_in;  // nodal [cell][4] (previous iterate)
   double* src;           // nodal [cell][4] scratch: sigma_s/(4 pi)(phi_in + phi_post)
   double* psi;           // [m][cell][4] (w_m psi_m)
+  const double* dirmat;  // [m][32]: A0 then F (uniform mesh)
+  // table mode: material of each cell and [m][material][32] = B then G
+  const int* mat_id;
+  int n_mat;
+  const double* coef;
+  int cw;                // sweeping lanes per workgroup (multiple of 64, <= 256)
+  int n_chunks;          // dg_chunks(nx, ny, cw)
 };
-hipError_t launch_dg_sweep(const DgArgs& a, hipStream_t s);
+hipError_t launch_dg_tables(int n_dir, int n_mat, const double* dir, const double* sig_e_mat,
+                            double hx, double hy, double* dirmat, double* coef, hipStream_t s);
+long long dg_chunks(int nx, int ny, int cw);
+size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny);
+hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s);
 hipError_t launch_dg_reduce(int n_dir, long long n_nodes, const double* psi,
                             const double* phi_old, double* phi_new, double* partials,
                             int n_part, hipStream_t s);

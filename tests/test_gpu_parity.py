@@ -101,6 +101,46 @@ def test_ragged_mesh_and_tail(S, oracle):
     _run_pair(S, oracle, p, 2)
 
 
+def _per_cell_problem(nx, ny, seed, **kw):
+    """Every cell its own material (cross sections drawn per cell), unit
+    source in a central patch: the collided sweep then has more distinct
+    sigma_e than its LDS table holds and solves each cell's system."""
+    from paper_2511_16821_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    p = W.homogeneous_box(n=max(nx, ny), L=2.0, **kw)
+    p["nx"], p["ny"] = nx, ny
+    p["x_hi"], p["y_hi"] = 2.0 * nx / max(nx, ny), 2.0 * ny / max(nx, ny)
+    p["sigma_s"] = rng.uniform(0.1, 3.0, size=(ny, nx))
+    p["sigma_a"] = rng.uniform(0.01, 1.0, size=(ny, nx))
+    q = np.zeros((ny, nx))
+    q[ny // 2 - 2:ny // 2 + 2, nx // 2 - 2:nx // 2 + 2] = 1.0
+    p["q"] = q
+    return p
+
+
+def test_dg_cell_mode(S, oracle):
+    """Sweep without the material table (2304 distinct sigma_e)."""
+    p = _per_cell_problem(48, 48, 5, n_s=1, n_particles=8000, dt=0.05, sn_order=4)
+    _run_pair(S, oracle, p, 2)
+
+
+@pytest.mark.parametrize("per_cell", [False, True])
+def test_dg_long_diagonals(S, oracle, per_cell):
+    """Diagonals longer than one 256-lane chunk, on a non-square mesh, in
+    both sweep modes."""
+    from paper_2511_16821_amd import workloads as W
+    if per_cell:
+        p = _per_cell_problem(300, 270, 9, n_s=1, n_particles=3000, dt=0.05, sn_order=2)
+    else:
+        p = W.checkerboard(blocks=6, cells_per_block=50, n_s=1, n_particles=3000, dt=0.05,
+                           sn_order=2)
+        p["ny"] = 270
+        p["y_hi"] = 5.4
+        for f in ("sigma_s", "sigma_a", "q"):
+            p[f] = np.ascontiguousarray(p[f][:270])
+    _run_pair(S, oracle, p, 1, check_census=False)
+
+
 def test_degenerate_cases(S, oracle):
     from paper_2511_16821_amd import workloads as W
     # no source at all

@@ -432,8 +432,17 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(int n_dir, long long n_
   double dsum = 0.0, nsum = 0.0;
   for (long long k = (long long)blockIdx.x * kRedBlock + threadIdx.x; k < n_nodes;
        k += (long long)gridDim.x * kRedBlock) {
+    // eight planes' loads in flight per step, added in direction order
     double v = 0.0;
-    for (int m = 0; m < n_dir; ++m) v += psi[(long long)m * n_nodes + k];
+    int m = 0;
+    for (; m + 8 <= n_dir; m += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = psi[(long long)(m + u) * n_nodes + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += t[u];
+    }
+    for (; m < n_dir; ++m) v += psi[(long long)m * n_nodes + k];
     const double d = v - phi_old[k];
     phi_new[k] = v;
     dsum += d * d;

@@ -128,7 +128,9 @@ typedef struct {
     int64_t census_kept;     /* last step: bank size after the cap           */
     double thin_factor;      /* last step: weight factor of the cap          */
     uint64_t segments_total; /* last step, both passes                       */
-    double ms_mc, ms_dg, ms_remap, ms_census; /* last step, stage times      */
+    double ms_mc, ms_dg, ms_remap, ms_census; /* last step, stage times;
+                                 ms_dg includes the host's wait for the
+                                 iteration outcome                          */
     /* Totals since creation (or the last slh_load), for throughput and
      * roofline accounting.  Kernel times are HIP events recorded on the
      * solver's stream immediately around each MC-pass kernel launch. */
@@ -141,6 +143,11 @@ typedef struct {
     uint64_t steps_total;           /* steps accounted in the totals         */
     uint64_t thin_overflow_total;   /* steps whose census draw exceeded the
                                        cap (first cap in slot order kept)   */
+    uint64_t graph_launches_total;  /* step parts replayed as HIP graphs     */
+    uint64_t host_waits_total;      /* host waits on the stream inside
+                                       slh_advance (one per step when the
+                                       first batch of source iterations
+                                       suffices)                             */
 } slh_stats;
 
 typedef struct slh_solver slh_solver;
@@ -157,10 +164,19 @@ slh_status slh_create(const slh_problem *problem, void *hip_stream, slh_alloc_fn
                       slh_free_fn free_fn, void *alloc_ctx, slh_solver **out);
 
 /* Enqueues n_steps >= 1 time steps (steps 1-4 above) on the solver's stream.
- * The source iteration reads its residual back once per sweep, so the call
- * returns when the last step's remap pass has been enqueued.  Returns
- * SLH_E_NOT_CONVERGED if any step's SI hit si_max_iter. */
+ * A step is launched in two parts: the scatter-limited leg with a first
+ * batch of source iterations (as many as the previous step needed), and the
+ * remap leg with the census.  The iteration's stopping test runs on the
+ * device; the host waits once per step for its outcome (again only when the
+ * batch was too short), so the call returns when the last step's remap leg
+ * has been enqueued.  Each part is replayed from a HIP graph captured on
+ * first use (see slh_set_graphs).  Returns SLH_E_NOT_CONVERGED if any step's
+ * SI hit si_max_iter. */
 slh_status slh_advance(slh_solver *s, int32_t n_steps);
+
+/* enable != 0 (the default): step parts are captured once as HIP graphs and
+ * replayed; 0: every kernel is launched directly.  Results are identical. */
+slh_status slh_set_graphs(slh_solver *s, int32_t enable);
 
 /* Blocks until the solver's stream is idle. */
 slh_status slh_synchronize(slh_solver *s);

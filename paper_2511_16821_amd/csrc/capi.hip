@@ -5,6 +5,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
+#include <utility>
+#include <cstddef>
 #include <new>
 #include <string>
 #include <vector>
@@ -25,6 +29,21 @@ static slh_status fail(slh_status st, const std::string& msg) {
 }
 
 extern "C" const char* slh_last_error(void) { return g_err.c_str(); }
+
+namespace slh {
+// Sets the calling thread's message (the server hands a worker's message to
+// the thread that collects the result).
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace slh
+
+// Copies on the solver's stream and waits for it: no operation of the
+// library uses the legacy default stream, which would have to wait for
+// graph captures running on other threads' solvers.
+#define COPY_SYNC(dst, src, n, kind)                                  \
+  do {                                                                \
+    HIP_TRY(hipMemcpyAsync(dst, src, n, kind, s->stream));            \
+    HIP_TRY(hipStreamSynchronize(s->stream));                         \
+  } while (0)
 
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \
@@ -279,13 +298,25 @@ __global__ void k_state_init(DevState* st) {
   }
 }
 
-__global__ void k_state_set_bank(DevState* st, long long n, double maxabs) {
+__global__ void k_state_set_bank(DevState* st, long long n, double maxabs,
+                                 unsigned long long step) {
   if (threadIdx.x == 0) {
+    st->step = step;
     st->n_in = n;
     st->n_kept = n;
     st->maxabs_w = maxabs;
   }
 }
+
+// The device's source-iteration fields (DevState::si_done .. si_nrm2), as
+// copied to pinned host memory after each batch of iterations.
+struct SiState {
+  int done, conv, iter, bad;
+  double dn2, nrm2;
+};
+static const size_t kSiStateBytes = sizeof(SiState);
+static_assert(offsetof(DevState, si_nrm2) - offsetof(DevState, si_done) == 24,
+              "SiState mirrors the DevState fields");
 
 struct slh_solver {
   slh_problem prob;
@@ -308,8 +339,7 @@ struct slh_solver {
   double *qnR = nullptr, *treeR = nullptr;
   long long tree_L = 1;
   unsigned long long *Tpre = nullptr, *Tpost = nullptr, *TR = nullptr;
-  double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr,
-         *phi_c2 = nullptr;
+  double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr;
   double *psi = nullptr, *dg_part = nullptr, *dirs = nullptr;
   double* dirmat = nullptr;  // DG element data per direction
   int* mat_id = nullptr;     // DG table mode: material of each cell,
@@ -338,6 +368,11 @@ struct slh_solver {
   bool have_events = false;
   BalStore* h_bal = nullptr;   // pinned copies of the pass snapshots
   bool pending[2] = {false, false};
+  // graphs of the step parts (see enqueue_part)
+  bool use_graphs = true;
+  hipStream_t cap_stream = nullptr;
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (part, parity, batch)
+  unsigned long long graph_launches = 0ull, host_syncs = 0ull;
   double k_ms[2] = {0.0, 0.0};
   unsigned long long k_seg[2] = {0ull, 0ull};
   unsigned long long census_in_total = 0ull, census_out_total = 0ull, steps_total = 0ull;
@@ -355,6 +390,11 @@ struct slh_solver {
     return p;
   }
   void release() {
+    for (auto& kv : graphs)
+      if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    cap_stream = nullptr;
     for (void* p : allocs) {
       if (free_fn) free_fn(p, ctx);
       else (void)hipFree(p);
@@ -433,7 +473,6 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->phi_post, double, nc);
   ALLOC(s->phi_R, double, nc);
   ALLOC(s->phi_c, double, 4 * nc);
-  ALLOC(s->phi_c2, double, 4 * nc);
   ALLOC(s->psi, double, (size_t)z.n_dir * 4 * nc);
   ALLOC(s->dirmat, double, (size_t)z.n_dir * 32);
   if (z.dg_table) {
@@ -532,7 +571,6 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.n_cells = s->z.n_cells;
   a.n_src = s->z.n_p;
   a.seed = p.seed;
-  a.step = (uint64_t)s->step;
   a.kind = kind;
   a.n_lim = kind == 1 ? p.n_s : 0;
   a.points = p.points;
@@ -583,45 +621,24 @@ static slh_status collect_all(slh_solver* s) {
   return collect(s, 1);
 }
 
-static slh_status run_step(slh_solver* s) {
+// The time step is enqueued as graphs around the two MC-pass kernels:
+//   A1  pass begin, tally clears, emission of the scatter-limited leg
+//   --  MC pass 1 (direct launch between timing events)
+//   A2  tally -> flux, pass-1 balance snapshot, phi_c = 0, and the first batch
+//       of source iterations of the collided solve, ending with a copy of the
+//       device's iteration state to pinned host memory
+//   --  host wait; extra batches only if the first did not finish
+//   B1  remap source and its sum tree, emission of the remap leg
+//   --  MC pass 2 (direct launch between timing events)
+//   B2  tally -> flux, snapshot, census thinning and compaction, step + 1
+// Every part reads its step-dependent values (step counter, counts, flags)
+// from the device, so a graph captured once per census-bank parity (and
+// batch length) is replayed for every step.
+enum Part { kA1 = 0, kA2, kB1, kB2, kNumParts };
+
+static DgArgs dg_args(slh_solver* s) {
   const slh_problem& p = s->prob;
   const Sizes& z = s->z;
-  const long long nc = z.n_cells;
-  hipStream_t st = s->stream;
-  const double inv_adt = 1.0 / s->adt;
-  const double cdt = p.c * p.dt;
-  const int grid1 = mc_pass_grid(z.fp32, 1, z.cap + z.n_p);
-  const int grid2 = mc_pass_grid(z.fp32, 2, z.cap + z.n_p);
-  if (s->pending[0]) {  // only when the previous step had no SI sync
-    HIP_TRY(hipStreamSynchronize(st));
-    slh_status r = collect_all(s);
-    if (r != SLH_OK) return r;
-  }
-
-  HIP_TRY(hipEventRecord(s->ev[0], st));
-  // ---- step 1: scatter-limited leg from Q and the census ----
-  HIP_TRY(launch_pass_begin(s->st, s->tree1, cdt, st));
-  HIP_TRY(launch_fill_u64(s->Tpre, (long long)z.n_copies * kTallyStride * nc, 0ull, st));
-  HIP_TRY(launch_fill_u64(s->Tpost, (long long)z.n_copies * kTallyStride * nc, 0ull, st));
-  const PassArgs a1 = pass_args(s, 1);
-  HIP_TRY(launch_emit(a1, z.fp32, st));
-  HIP_TRY(hipEventRecord(s->evk[0], st));
-  HIP_TRY(launch_mc_pass(a1, z.fp32, grid1, st));
-  HIP_TRY(hipEventRecord(s->evk[1], st));
-  const long long cstride = (long long)kTallyStride * nc;
-  HIP_TRY(launch_tally_to_flux(s->Tpre, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_pre,
-                               st));
-  HIP_TRY(launch_tally_to_flux(s->Tpost, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_post,
-                               st));
-  hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
-                     s->bal_store + 0);
-  HIP_TRY(hipMemcpyAsync(s->h_bal + 0, s->bal_store + 0, sizeof(BalStore),
-                         hipMemcpyDeviceToHost, st));
-  s->pending[0] = true;
-  HIP_TRY(hipEventRecord(s->ev[1], st));
-
-  // ---- step 2: collided DG S_N solve, source iteration ----
-  HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
   DgArgs d;
   d.nx = p.nx;
   d.ny = p.ny;
@@ -632,6 +649,7 @@ static slh_status run_step(slh_solver* s) {
   d.sig_e = s->sig_e;
   d.sig_s = s->sig_s;
   d.phi_post = s->phi_post;
+  d.phi_in = s->phi_c;
   d.src = s->dg_src;
   d.psi = s->psi;
   d.mat_id = s->mat_id;
@@ -640,70 +658,174 @@ static slh_status run_step(slh_solver* s) {
   d.coef = s->coef;
   d.dirmat = s->dirmat;
   d.n_chunks = (int)z.dg_chunks;
-  s->si_it = 0;
-  s->si_conv = false;
-  s->si_res = 0.0;
-  for (int it = 0; it < s->si_max; ++it) {
-    d.phi_in = s->phi_c;
+  d.st = s->st;
+  return d;
+}
+
+static slh_status enqueue_si(slh_solver* s, hipStream_t st, int n_it) {
+  const Sizes& z = s->z;
+  const DgArgs d = dg_args(s);
+  for (int it = 0; it < n_it; ++it) {
     HIP_TRY(launch_dg_sweep(d, z.dg_table, st));
-    HIP_TRY(launch_dg_reduce(z.n_dir, 4 * nc, s->psi, s->phi_c, s->phi_c2, s->dg_part,
-                             s->n_part, st));
-    HIP_TRY(hipMemcpyAsync(s->h_res, s->dg_part + 2 * s->n_part, 2 * sizeof(double),
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (it == 0) {
-      slh_status r = collect_all(s);
-      if (r != SLH_OK) return r;
+    HIP_TRY(launch_dg_reduce(z.n_dir, 4 * z.n_cells, s->psi, s->phi_c, s->dg_part, s->n_part,
+                             s->st, s->si_tol, s->si_max, st));
+  }
+  HIP_TRY(hipMemcpyAsync(s->h_res, &s->st->si_done, kSiStateBytes, hipMemcpyDeviceToHost, st));
+  return SLH_OK;
+}
+
+static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it) {
+  const slh_problem& p = s->prob;
+  const Sizes& z = s->z;
+  const long long nc = z.n_cells;
+  const double inv_adt = 1.0 / s->adt;
+  const double cdt = p.c * p.dt;
+  const long long cstride = (long long)kTallyStride * nc;
+  const long long n_tally = (long long)z.n_copies * kTallyStride * nc;
+  switch (part) {
+    case kA1: {
+      HIP_TRY(launch_pass_begin(s->st, s->tree1, cdt, st));
+      HIP_TRY(launch_fill_u64(s->Tpre, n_tally, 0ull, st));
+      HIP_TRY(launch_fill_u64(s->Tpost, n_tally, 0ull, st));
+      HIP_TRY(launch_emit(pass_args(s, 1), z.fp32, st));
+      return SLH_OK;
     }
-    std::swap(s->phi_c, s->phi_c2);
-    s->si_it = it + 1;
-    const double dn = sqrt(s->h_res[0]), nrm = sqrt(s->h_res[1]);
+    case kA2: {
+      HIP_TRY(launch_tally_to_flux(s->Tpre, nc, z.n_copies, cstride, s->st, inv_adt,
+                                   s->phi_pre, st));
+      HIP_TRY(launch_tally_to_flux(s->Tpost, nc, z.n_copies, cstride, s->st, inv_adt,
+                                   s->phi_post, st));
+      hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
+                         s->bal_store + 0);
+      HIP_TRY(hipMemcpyAsync(s->h_bal + 0, s->bal_store + 0, sizeof(BalStore),
+                             hipMemcpyDeviceToHost, st));
+      HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
+      HIP_TRY(launch_si_begin(s->st, s->si_max, st));
+      return enqueue_si(s, st, n_it);
+    }
+    case kB1: {
+      HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c,
+                                  s->qnR, st));
+      HIP_TRY(launch_build_tree(s->qnR, nc, s->adt, s->treeR, st));
+      HIP_TRY(launch_pass_begin(s->st, s->treeR, cdt, st));
+      HIP_TRY(launch_fill_u64(s->TR, n_tally, 0ull, st));
+      HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
+      HIP_TRY(launch_emit(pass_args(s, 2), z.fp32, st));
+      return SLH_OK;
+    }
+    default: {  // kB2: the remap census is the state at t_{n+1} (capped)
+      HIP_TRY(launch_tally_to_flux(s->TR, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_R,
+                                   st));
+      hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
+                         s->bal_store + 1);
+      HIP_TRY(hipMemcpyAsync(s->h_bal + 1, s->bal_store + 1, sizeof(BalStore),
+                             hipMemcpyDeviceToHost, st));
+      void* nb = s->bank_mem[1 - s->cur];
+      HIP_TRY(launch_thin_params(s->st, z.cap, s->thin_margin, st));
+      if (z.fp32) {
+        Bank<float> src = s->bank_at<float>(s->stage_mem, z.n_cand);
+        HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, p.seed, s->st, s->flags, st));
+        HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
+        HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, z.cap,
+                                             s->bank_at<float>(nb, z.cap), s->st, st));
+      } else {
+        Bank<double> src = s->bank_at<double>(s->stage_mem, z.n_cand);
+        HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, p.seed, s->st, s->flags, st));
+        HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
+        HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand, z.cap,
+                                              s->bank_at<double>(nb, z.cap), s->st, st));
+      }
+      HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, z.cap, st));
+      HIP_TRY(launch_step_end(s->st, st));
+      return SLH_OK;
+    }
+  }
+}
+
+// Captures a part on the capture stream.  Returns false when the runtime
+// declines the capture; the solver then launches its kernels directly.
+static bool capture(slh_solver* s, int part, int n_it, hipGraphExec_t* out) {
+  *out = nullptr;
+  if (!s->cap_stream &&
+      hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    s->cap_stream = nullptr;
+    return false;
+  }
+  if (hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return false;
+  const slh_status r = enqueue_part(s, part, s->cap_stream, n_it);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+  bool ok = r == SLH_OK && e == hipSuccess && g;
+  if (ok) ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  if (!ok) *out = nullptr;
+  return ok;
+}
+
+static slh_status launch_part(slh_solver* s, int part, int n_it) {
+  if (s->use_graphs) {
+    const auto key = std::make_tuple(part, s->cur, part == kA2 ? n_it : 0);
+    auto it = s->graphs.find(key);
+    if (it == s->graphs.end()) {
+      hipGraphExec_t e = nullptr;
+      if (capture(s, part, n_it, &e)) it = s->graphs.emplace(key, e).first;
+      else s->use_graphs = false;
+    }
+    if (s->use_graphs) {
+      HIP_TRY(hipGraphLaunch(it->second, s->stream));
+      s->graph_launches += 1;
+      return SLH_OK;
+    }
+  }
+  return enqueue_part(s, part, s->stream, n_it);
+}
+
+static slh_status run_step(slh_solver* s) {
+  const Sizes& z = s->z;
+  const int grid1 = mc_pass_grid(z.fp32, 1, z.cap + z.n_p);
+  const int grid2 = mc_pass_grid(z.fp32, 2, z.cap + z.n_p);
+  // iterations in the first batch: as many as the previous step took
+  const int n_first =
+      s->si_max > 0 ? std::max(1, std::min(s->si_max, s->si_it > 0 ? s->si_it : 4)) : 0;
+  hipStream_t st = s->stream;
+  HIP_TRY(hipEventRecord(s->ev[0], st));
+  slh_status r = launch_part(s, kA1, 0);
+  if (r != SLH_OK) return r;
+  HIP_TRY(hipEventRecord(s->evk[0], st));
+  HIP_TRY(launch_mc_pass(pass_args(s, 1), z.fp32, grid1, st));
+  HIP_TRY(hipEventRecord(s->evk[1], st));
+  r = launch_part(s, kA2, n_first);
+  if (r != SLH_OK) return r;
+  s->pending[0] = true;
+  // the one host wait of the step: iteration state (and the balances of the
+  // previous step's remap leg and this step's pass 1)
+  for (;;) {
+    HIP_TRY(hipStreamSynchronize(st));
+    s->host_syncs += 1;
+    const SiState* si = (const SiState*)s->h_res;
+    s->si_it = si->iter;
+    s->si_conv = si->conv != 0;
+    const double dn = sqrt(si->dn2), nrm = sqrt(si->nrm2);
     s->si_res = nrm > 0.0 ? dn / nrm : 0.0;
-    if (!isfinite(dn) || !isfinite(nrm)) return fail(SLH_E_NUMERIC, "non-finite DG residual");
-    if (dn <= s->si_tol * nrm) { s->si_conv = true; break; }
+    if (si->bad) return fail(SLH_E_NUMERIC, "non-finite DG residual");
+    if (si->done) break;
+    r = enqueue_si(s, st, std::min(2, s->si_max - si->iter));  // rare: a short batch
+    if (r != SLH_OK) return r;
   }
-  if (s->si_max == 0) s->si_conv = true;
-  HIP_TRY(hipEventRecord(s->ev[2], st));
-
-  // ---- step 3: remap source and scatter-free leg ----
-  HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c, s->qnR,
-                              st));
-  HIP_TRY(launch_build_tree(s->qnR, nc, s->adt, s->treeR, st));
-  HIP_TRY(launch_pass_begin(s->st, s->treeR, cdt, st));
-  HIP_TRY(launch_fill_u64(s->TR, (long long)z.n_copies * kTallyStride * nc, 0ull, st));
-  HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
-  const PassArgs a2 = pass_args(s, 2);
-  HIP_TRY(launch_emit(a2, z.fp32, st));
+  r = collect_all(s);
+  if (r != SLH_OK) return r;
+  HIP_TRY(hipEventRecord(s->ev[1], st));
+  r = launch_part(s, kB1, 0);
+  if (r != SLH_OK) return r;
   HIP_TRY(hipEventRecord(s->evk[2], st));
-  HIP_TRY(launch_mc_pass(a2, z.fp32, grid2, st));
+  HIP_TRY(launch_mc_pass(pass_args(s, 2), z.fp32, grid2, st));
   HIP_TRY(hipEventRecord(s->evk[3], st));
-  HIP_TRY(launch_tally_to_flux(s->TR, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_R, st));
-  hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
-                     s->bal_store + 1);
-  HIP_TRY(hipMemcpyAsync(s->h_bal + 1, s->bal_store + 1, sizeof(BalStore),
-                         hipMemcpyDeviceToHost, st));
+  r = launch_part(s, kB2, 0);
+  if (r != SLH_OK) return r;
+  HIP_TRY(hipEventRecord(s->ev[2], st));
   s->pending[1] = true;
-  HIP_TRY(hipEventRecord(s->ev[3], st));
-
-  // ---- step 4: the remap census is the state at t_{n+1} (capped) ----
-  const uint64_t thin_stream = stream_seed(p.seed, (uint64_t)s->step, 2u, 2u, 0ull);
-  void* nb = s->bank_mem[1 - s->cur];
-  HIP_TRY(launch_thin_params(s->st, z.cap, s->thin_margin, st));
-  if (z.fp32) {
-    Bank<float> src = s->bank_at<float>(s->stage_mem, z.n_cand);
-    HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, thin_stream, s->st, s->flags, st));
-    HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
-    HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, z.cap,
-                                         s->bank_at<float>(nb, z.cap), s->st, st));
-  } else {
-    Bank<double> src = s->bank_at<double>(s->stage_mem, z.n_cand);
-    HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, thin_stream, s->st, s->flags, st));
-    HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
-    HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand, z.cap,
-                                          s->bank_at<double>(nb, z.cap), s->st, st));
-  }
-  HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, z.cap, st));
-  HIP_TRY(hipEventRecord(s->ev[4], st));
   s->cur = 1 - s->cur;
   s->step += 1;
   return SLH_OK;
@@ -762,6 +884,12 @@ extern "C" slh_status slh_advance(slh_solver* s, int32_t n_steps) {
     conv = conv && s->si_conv;
   }
   if (!conv) return fail(SLH_E_NOT_CONVERGED, "source iteration reached si_max_iter");
+  return SLH_OK;
+}
+
+extern "C" slh_status slh_set_graphs(slh_solver* s, int32_t enable) {
+  if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
+  s->use_graphs = enable != 0;
   return SLH_OK;
 }
 
@@ -829,9 +957,9 @@ extern "C" slh_status slh_get_stats(slh_solver* s, slh_stats* out) {
   if (!s || !out) return fail(SLH_E_INVALID_ARG, "NULL argument");
   HIP_TRY(hipStreamSynchronize(s->stream));
   DevState d;
-  HIP_TRY(hipMemcpy(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  COPY_SYNC(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
   BalStore b[2];
-  HIP_TRY(hipMemcpy(b, s->bal_store, sizeof(b), hipMemcpyDeviceToHost));
+  COPY_SYNC(b, s->bal_store, sizeof(b), hipMemcpyDeviceToHost);
   memset(out, 0, sizeof(*out));
   out->step = s->step;
   out->si_iterations = s->si_it;
@@ -853,12 +981,14 @@ extern "C" slh_status slh_get_stats(slh_solver* s, slh_stats* out) {
   out->census_out_total = s->census_out_total;
   out->steps_total = s->steps_total;
   out->thin_overflow_total = s->thin_overflow_total;
+  out->graph_launches_total = s->graph_launches;
+  out->host_waits_total = s->host_syncs;
   if (s->step > 0) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, s->ev[0], s->ev[1]) == hipSuccess) out->ms_mc = ms;
-    if (hipEventElapsedTime(&ms, s->ev[1], s->ev[2]) == hipSuccess) out->ms_dg = ms;
-    if (hipEventElapsedTime(&ms, s->ev[2], s->ev[3]) == hipSuccess) out->ms_remap = ms;
-    if (hipEventElapsedTime(&ms, s->ev[3], s->ev[4]) == hipSuccess) out->ms_census = ms;
+    if (hipEventElapsedTime(&ms, s->ev[0], s->evk[1]) == hipSuccess) out->ms_mc = ms;
+    if (hipEventElapsedTime(&ms, s->evk[1], s->ev[1]) == hipSuccess) out->ms_dg = ms;
+    if (hipEventElapsedTime(&ms, s->ev[1], s->evk[3]) == hipSuccess) out->ms_remap = ms;
+    if (hipEventElapsedTime(&ms, s->evk[3], s->ev[2]) == hipSuccess) out->ms_census = ms;
   }
   return SLH_OK;
 }
@@ -869,7 +999,7 @@ extern "C" slh_status slh_get_census(slh_solver* s, int64_t* n, double* x, doubl
   if (!s || !n) return fail(SLH_E_INVALID_ARG, "NULL argument");
   HIP_TRY(hipStreamSynchronize(s->stream));
   DevState d;
-  HIP_TRY(hipMemcpy(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  COPY_SYNC(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
   const long long cnt = d.n_in;
   *n = cnt;
   if (cnt == 0) return SLH_OK;
@@ -884,20 +1014,20 @@ extern "C" slh_status slh_get_census(slh_solver* s, int64_t* n, double* x, doubl
     float* srcs[5] = {b.px, b.py, b.ox, b.oy, b.w};
     std::vector<double>* dsts[5] = {&px, &py, &vx, &vy, &vw};
     for (int k = 0; k < 5; ++k) {
-      HIP_TRY(hipMemcpy(t.data(), srcs[k], 4 * cnt, hipMemcpyDeviceToHost));
+      COPY_SYNC(t.data(), srcs[k], 4 * cnt, hipMemcpyDeviceToHost);
       for (long long i = 0; i < cnt; ++i) (*dsts[k])[i] = t[i];
     }
-    HIP_TRY(hipMemcpy(c.data(), b.cell, 4 * cnt, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(h.data(), b.hid, 8 * cnt, hipMemcpyDeviceToHost));
+    COPY_SYNC(c.data(), b.cell, 4 * cnt, hipMemcpyDeviceToHost);
+    COPY_SYNC(h.data(), b.hid, 8 * cnt, hipMemcpyDeviceToHost);
   } else {
     Bank<double> b = s->bank_at<double>(base, s->z.cap);
-    HIP_TRY(hipMemcpy(px.data(), b.px, 8 * cnt, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(py.data(), b.py, 8 * cnt, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(vx.data(), b.ox, 8 * cnt, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(vy.data(), b.oy, 8 * cnt, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(vw.data(), b.w, 8 * cnt, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(c.data(), b.cell, 4 * cnt, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(h.data(), b.hid, 8 * cnt, hipMemcpyDeviceToHost));
+    COPY_SYNC(px.data(), b.px, 8 * cnt, hipMemcpyDeviceToHost);
+    COPY_SYNC(py.data(), b.py, 8 * cnt, hipMemcpyDeviceToHost);
+    COPY_SYNC(vx.data(), b.ox, 8 * cnt, hipMemcpyDeviceToHost);
+    COPY_SYNC(vy.data(), b.oy, 8 * cnt, hipMemcpyDeviceToHost);
+    COPY_SYNC(vw.data(), b.w, 8 * cnt, hipMemcpyDeviceToHost);
+    COPY_SYNC(c.data(), b.cell, 4 * cnt, hipMemcpyDeviceToHost);
+    COPY_SYNC(h.data(), b.hid, 8 * cnt, hipMemcpyDeviceToHost);
   }
   for (long long i = 0; i < cnt; ++i) {
     const int ix = c[i] % p.nx, iy = c[i] / p.nx;
@@ -920,7 +1050,7 @@ extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
   if (!s || !len) return fail(SLH_E_INVALID_ARG, "NULL argument");
   HIP_TRY(hipStreamSynchronize(s->stream));
   DevState d;
-  HIP_TRY(hipMemcpy(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  COPY_SYNC(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
   const long long cnt = d.n_in;
   const size_t head = 6 * 8;
   const size_t need = head + s->bank_bytes(cnt);
@@ -939,12 +1069,12 @@ extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
   char* base = (char*)s->bank_mem[s->cur];
   const long long cap = s->z.cap;
   for (int k = 0; k < 5; ++k) {
-    HIP_TRY(hipMemcpy(out, base + (size_t)k * rb * cap, rb * cnt, hipMemcpyDeviceToHost));
+    COPY_SYNC(out, base + (size_t)k * rb * cap, rb * cnt, hipMemcpyDeviceToHost);
     out += rb * cnt;
   }
-  HIP_TRY(hipMemcpy(out, base + 5 * rb * cap, 8 * cnt, hipMemcpyDeviceToHost));
+  COPY_SYNC(out, base + 5 * rb * cap, 8 * cnt, hipMemcpyDeviceToHost);
   out += 8 * cnt;
-  HIP_TRY(hipMemcpy(out, base + 5 * rb * cap + 8 * cap, 4 * cnt, hipMemcpyDeviceToHost));
+  COPY_SYNC(out, base + 5 * rb * cap + 8 * cap, 4 * cnt, hipMemcpyDeviceToHost);
   *len = need;
   return SLH_OK;
 }
@@ -967,13 +1097,14 @@ extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
   char* base = (char*)s->bank_mem[s->cur];
   const long long cap = s->z.cap;
   for (int k = 0; k < 5; ++k) {
-    HIP_TRY(hipMemcpy(base + (size_t)k * rb * cap, in, rb * cnt, hipMemcpyHostToDevice));
+    COPY_SYNC(base + (size_t)k * rb * cap, in, rb * cnt, hipMemcpyHostToDevice);
     in += rb * cnt;
   }
-  HIP_TRY(hipMemcpy(base + 5 * rb * cap, in, 8 * cnt, hipMemcpyHostToDevice));
+  COPY_SYNC(base + 5 * rb * cap, in, 8 * cnt, hipMemcpyHostToDevice);
   in += 8 * cnt;
-  HIP_TRY(hipMemcpy(base + 5 * rb * cap + 8 * cap, in, 4 * cnt, hipMemcpyHostToDevice));
-  hipLaunchKernelGGL(k_state_set_bank, dim3(1), dim3(1), 0, s->stream, s->st, cnt, maxabs);
+  COPY_SYNC(base + 5 * rb * cap + 8 * cap, in, 4 * cnt, hipMemcpyHostToDevice);
+  hipLaunchKernelGGL(k_state_set_bank, dim3(1), dim3(1), 0, s->stream, s->st, cnt, maxabs,
+                     (unsigned long long)h[2]);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->step = (long long)h[2];

@@ -50,7 +50,9 @@ __device__ __forceinline__ double recip(double a) {
 // S = sigma_s/(4 pi) (phi_c + phi_post), once per source iteration.
 __global__ void k_dg_source(long long n, const double* __restrict__ sig_s,
                             const double* __restrict__ phi_post,
-                            const double* __restrict__ phi_in, double* __restrict__ S) {
+                            const double* __restrict__ phi_in, double* __restrict__ S,
+                            const DevState* st) {
+  if (st->si_done) return;
   const double inv4pi = 0.25 / M_PI;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -177,6 +179,7 @@ struct DgStage {
 
 template <bool TABLE>
 __global__ __launch_bounds__(320) void k_dg_sweep_pc(DgArgs g) {
+  if (g.st->si_done) return;  // the whole workgroup: no barrier is left pending
   extern __shared__ double smem[];
   const int nx = g.nx, ny = g.ny;
   const int CW = g.cw;       // sweeping lanes, multiple of 64, <= 256
@@ -405,7 +408,7 @@ hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   long long b = (nc + 255) / 256;
   const int grid = (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
   hipLaunchKernelGGL(k_dg_source, dim3(grid), dim3(256), 0, s, nc, a.sig_s, a.phi_post,
-                     a.phi_in, a.src);
+                     a.phi_in, a.src, a.st);
   const size_t lds = dg_sweep_lds_bytes(table, a.cw, a.n_mat, a.nx, a.ny);
   if (table)
     hipLaunchKernelGGL(k_dg_sweep_pc<true>, dim3(a.n_dir), dim3(a.cw + 64), lds, s, a);
@@ -425,9 +428,10 @@ int dg_reduce_partials(long long n_nodes) {
 
 __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(int n_dir, long long n_nodes,
                                                          const double* __restrict__ psi,
-                                                         const double* __restrict__ phi_old,
-                                                         double* __restrict__ phi_new,
-                                                         double* __restrict__ partials) {
+                                                         double* __restrict__ phi,
+                                                         double* __restrict__ partials,
+                                                         const DevState* st) {
+  if (st->si_done) return;
   __shared__ double s_d[kRedBlock], s_n[kRedBlock];
   double dsum = 0.0, nsum = 0.0;
   for (long long k = (long long)blockIdx.x * kRedBlock + threadIdx.x; k < n_nodes;
@@ -443,8 +447,8 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(int n_dir, long long n_
       for (int u = 0; u < 8; ++u) v += t[u];
     }
     for (; m < n_dir; ++m) v += psi[(long long)m * n_nodes + k];
-    const double d = v - phi_old[k];
-    phi_new[k] = v;
+    const double d = v - phi[k];  // in place: the sweep read only S
+    phi[k] = v;
     dsum += d * d;
     nsum += v * v;
   }
@@ -464,9 +468,13 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(int n_dir, long long n_
   }
 }
 
-// Sums the block partials into partials[2*n_part .. +1] with a fixed
-// association order (strided per-thread sums, then a tree).
-__global__ __launch_bounds__(256) void k_dg_residual(double* partials, int n_part) {
+// Sums the block partials with a fixed association order (strided
+// per-thread sums, then a tree) and takes the iteration's decision: done
+// when |phi_new - phi_old| <= tol |phi_new| (converged), when the iteration
+// limit is reached, or when the residual is not finite.
+__global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int n_part,
+                                                     DevState* st, double si_tol, int si_max) {
+  if (st->si_done) return;
   __shared__ double s_d[256], s_n[256];
   double d = 0.0, n = 0.0;
   for (int b = threadIdx.x; b < n_part; b += 256) {
@@ -484,17 +492,26 @@ __global__ __launch_bounds__(256) void k_dg_residual(double* partials, int n_par
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partials[2 * n_part] = s_d[0];
-    partials[2 * n_part + 1] = s_n[0];
+    const double dn2 = s_d[0], nrm2 = s_n[0];
+    const double dn = sqrt(dn2), nrm = sqrt(nrm2);
+    st->si_dn2 = dn2;
+    st->si_nrm2 = nrm2;
+    st->si_iter += 1;
+    const int bad = !isfinite(dn) || !isfinite(nrm);
+    const int conv = !bad && dn <= si_tol * nrm;
+    st->si_bad = bad;
+    st->si_conv = conv;
+    st->si_done = bad || conv || st->si_iter >= si_max;
   }
 }
 
-hipError_t launch_dg_reduce(int n_dir, long long n_nodes, const double* psi,
-                            const double* phi_old, double* phi_new, double* partials,
-                            int n_part, hipStream_t s) {
-  hipLaunchKernelGGL(k_dg_reduce, dim3(n_part), dim3(kRedBlock), 0, s, n_dir, n_nodes, psi,
-                     phi_old, phi_new, partials);
-  hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, partials, n_part);
+hipError_t launch_dg_reduce(int n_dir, long long n_nodes, const double* psi, double* phi,
+                            double* partials, int n_part, DevState* st, double si_tol,
+                            int si_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_dg_reduce, dim3(n_part), dim3(kRedBlock), 0, s, n_dir, n_nodes, psi, phi,
+                     partials, (const DevState*)st);
+  hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,
+                     st, si_tol, si_max);
   return hipGetLastError();
 }
 

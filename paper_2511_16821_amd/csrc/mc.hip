@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   const double total = s_top[1];
   if (!(total > 0.0)) return;
   const double w_src = total / (double)a.n_src;
-  const uint64_t stream = stream_seed(a.seed, a.step, (uint32_t)KIND, 0u, 0ull);
+  const uint64_t stream = stream_seed(a.seed, a.st->step, (uint32_t)KIND, 0u, 0ull);
   const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt;
   const SrcBank<R> b = Real<R>::src(a);
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < a.n_src;
@@ -164,7 +164,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const R w_cut = (R)(a.w_cut_rel * w_src);
   const double inv_T = st->inv_T;
   const double inv_W = st->inv_W;
-  const uint64_t src_stream = stream_seed(a.seed, a.step, (uint32_t)KIND, 0u, 0ull);
+  const uint64_t step = st->step;
+  const uint64_t src_stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, 0ull);
   const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt, c = (R)a.c;
   const R INF = Real<R>::inf();
   const Bank<R> bin = Real<R>::in(a);
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         hid = bin.hid[g];
         trel = (R)0;
         stream = (KIND == 1 && n_lim > 0)
-                     ? stream_seed(a.seed, a.step, (uint32_t)KIND, 1u, hid >> 32) : 0ull;
+                     ? stream_seed(a.seed, step, (uint32_t)KIND, 1u, hid >> 32) : 0ull;
         pidx = (uint32_t)(hid & 0xffffffffull);
         dcur = 0;
       } else {
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const SrcBank<R> sb = Real<R>::src(a);
         stream = src_stream;
         pidx = (uint32_t)s;
-        hid = (a.step << 32) | (uint64_t)s;
+        hid = (step << 32) | (uint64_t)s;
         px = sb.px[s]; py = sb.py[s]; ox = sb.ox[s]; oy = sb.oy[s]; w = sb.w[s];
         trel = sb.trel[s];
         tau = sb.tau[s];

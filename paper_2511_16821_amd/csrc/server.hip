@@ -27,6 +27,10 @@
 
 #include "../../include/slh.h"
 
+namespace slh {
+void set_last_error(const std::string& msg);
+}
+
 namespace {
 
 double now_s() {
@@ -137,7 +141,6 @@ struct slh_server {
   int device = 0;
 };
 
-static thread_local std::string g_srv_err;
 
 // Finds the first queued request whose block fits; called with mu held.
 static Request* take_admissible(slh_server* srv) {
@@ -306,6 +309,7 @@ extern "C" slh_status slh_server_result(slh_server* srv, uint64_t ticket, double
     srv->reqs.erase(it);
   }
   const slh_status st = r->status;
+  if (st != SLH_OK) slh::set_last_error(r->error);
   if (flux_out && !r->flux.empty()) memcpy(flux_out, r->flux.data(), 8 * r->flux.size());
   if (balance) *balance = r->bal;
   if (latency) *latency = r->lat;

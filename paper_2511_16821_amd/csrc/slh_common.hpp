@@ -185,6 +185,15 @@ struct DevState {
   unsigned long long killed;    // histories stopped by the segment guard
   unsigned long long bal[2 * B_NFIELDS];
   unsigned long long maxabs_bits_out;  // max |w| of the bank being written (bits)
+  unsigned long long step;      // time step being computed (point streams, history ids)
+  // source iteration of the collided solve, kept on the device so that a
+  // batch of iterations needs no host round trip: once si_done is set the
+  // remaining iterations of the batch do nothing
+  int si_done;                  // converged, iteration limit, or non-finite residual
+  int si_conv;                  // converged to the tolerance
+  int si_iter;                  // iterations done in this step
+  int si_bad;                   // non-finite residual
+  double si_dn2, si_nrm2;       // |phi_new - phi_old|^2, |phi_new|^2 of the last iteration
 };
 
 struct PassArgs {
@@ -198,7 +207,7 @@ struct PassArgs {
   const double* qn;      // nodal source [cell][4]
   long long n_cells;
   long long n_src;
-  uint64_t seed, step;
+  uint64_t seed;         // the time step is read from st->step
   int kind;              // 1: scatter-limited leg, 2: scatter-free remap
   int n_lim;             // scatter limit of the pass (0 for kind 2)
   int points;            // 0 Sobol'-Owen, 1 pseudo-random
@@ -252,15 +261,19 @@ struct DgArgs {
   const double* coef;
   int cw;                // sweeping lanes per workgroup (multiple of 64, <= 256)
   int n_chunks;          // dg_chunks(nx, ny, cw)
+  const DevState* st;    // si_done: skip the iteration
 };
 hipError_t launch_dg_tables(int n_dir, int n_mat, const double* dir, const double* sig_e_mat,
                             double hx, double hy, double* dirmat, double* coef, hipStream_t s);
 long long dg_chunks(int nx, int ny, int cw);
 size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny);
 hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s);
-hipError_t launch_dg_reduce(int n_dir, long long n_nodes, const double* psi,
-                            const double* phi_old, double* phi_new, double* partials,
-                            int n_part, hipStream_t s);
+// One reduction of a source iteration: phi (nodal) is replaced in place by
+// the direction sum of the planes; the residual decides st->si_done.
+hipError_t launch_dg_reduce(int n_dir, long long n_nodes, const double* psi, double* phi,
+                            double* partials, int n_part, DevState* st, double si_tol,
+                            int si_max, hipStream_t s);
+hipError_t launch_si_begin(DevState* st, int si_max, hipStream_t s);
 int dg_reduce_partials(long long n_nodes);
 
 // util.hip
@@ -283,8 +296,9 @@ hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
                               long long* tmp, hipStream_t s);
 hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hipStream_t s);
 hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long long n,
-                               uint64_t thin_stream, const DevState* st, long long* flags,
+                               uint64_t seed, const DevState* st, long long* flags,
                                hipStream_t s);
+hipError_t launch_step_end(DevState* st, hipStream_t s);
 template <typename R>
 hipError_t launch_census_compact(const Bank<R>& src, const long long* incl, long long n,
                                  long long cap, Bank<R> dst, DevState* st, hipStream_t s);

@@ -304,8 +304,10 @@ hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hip
 
 __global__ void k_census_flags(const uint8_t* __restrict__ alive,
                                const uint64_t* __restrict__ hid, long long n,
-                               uint64_t thin_stream, const DevState* st,
+                               uint64_t seed, const DevState* st,
                                long long* __restrict__ flags) {
+  // the thinning keys' stream: (step, pass 2, population 2)
+  const uint64_t thin_stream = stream_seed(seed, st->step, 2u, 2u, 0ull);
   const int act = st->thin_active;
   const unsigned long long mant = st->thin_mant;
   const int rs = st->thin_rshift;
@@ -322,12 +324,40 @@ __global__ void k_census_flags(const uint8_t* __restrict__ alive,
 }
 
 hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long long n,
-                               uint64_t thin_stream, const DevState* st, long long* flags,
+                               uint64_t seed, const DevState* st, long long* flags,
                                hipStream_t s) {
   long long b = (n + 255) / 256;
   const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_census_flags, dim3(grid), dim3(256), 0, s, alive, hid, n, thin_stream,
-                     st, flags);
+  hipLaunchKernelGGL(k_census_flags, dim3(grid), dim3(256), 0, s, alive, hid, n, seed, st,
+                     flags);
+  return hipGetLastError();
+}
+
+// End of a time step on the device: the step counter that seeds the point
+// streams advances.
+__global__ void k_step_end(DevState* st) {
+  if (threadIdx.x == 0) st->step += 1;
+}
+
+hipError_t launch_step_end(DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, st);
+  return hipGetLastError();
+}
+
+// Start of the source iteration: phi_c = 0 is filled by the caller.
+__global__ void k_si_begin(DevState* st, int si_max) {
+  if (threadIdx.x == 0) {
+    st->si_iter = 0;
+    st->si_conv = si_max == 0 ? 1 : 0;
+    st->si_done = si_max == 0 ? 1 : 0;
+    st->si_bad = 0;
+    st->si_dn2 = 0.0;
+    st->si_nrm2 = 0.0;
+  }
+}
+
+hipError_t launch_si_begin(DevState* st, int si_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_si_begin, dim3(1), dim3(1), 0, s, st, si_max);
   return hipGetLastError();
 }
 

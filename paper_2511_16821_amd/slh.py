@@ -56,7 +56,8 @@ class slh_stats(C.Structure):
                 ("ms_kernel_mc_total", C.c_double), ("ms_kernel_remap_total", C.c_double),
                 ("seg_mc_total", C.c_uint64), ("seg_remap_total", C.c_uint64),
                 ("census_in_total", C.c_uint64), ("census_out_total", C.c_uint64),
-                ("steps_total", C.c_uint64), ("thin_overflow_total", C.c_uint64)]
+                ("steps_total", C.c_uint64), ("thin_overflow_total", C.c_uint64),
+                ("graph_launches_total", C.c_uint64), ("host_waits_total", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -78,7 +79,7 @@ class slh_latency(C.Structure):
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
-EXPORTS = ["slh_create", "slh_advance", "slh_synchronize", "slh_get_flux", "slh_get_flux_device",
+EXPORTS = ["slh_create", "slh_advance", "slh_set_graphs", "slh_synchronize", "slh_get_flux", "slh_get_flux_device",
            "slh_get_balance", "slh_get_stats", "slh_get_census", "slh_save", "slh_load",
            "slh_footprint_bytes", "slh_destroy", "slh_last_error", "slh_qmc_points",
            "slh_server_create", "slh_server_submit", "slh_server_poll", "slh_server_result",
@@ -100,6 +101,7 @@ def lib():
     sig = {
         "slh_create": ([C.POINTER(slh_problem), vp, ALLOC_FN, FREE_FN, vp, C.POINTER(vp)], i32),
         "slh_advance": ([vp, i32], i32),
+        "slh_set_graphs": ([vp, i32], i32),
         "slh_synchronize": ([vp], i32),
         "slh_get_flux": ([vp, i32, vp], i32),
         "slh_get_flux_device": ([vp, i32, vp], i32),
@@ -235,6 +237,11 @@ class Solver:
         return _check(lib().slh_advance(self.h, int(n_steps)), "slh_advance", allow)
 
     advance = slh_advance
+
+    def slh_set_graphs(self, enable):
+        _check(lib().slh_set_graphs(self.h, 1 if enable else 0), "slh_set_graphs")
+
+    set_graphs = slh_set_graphs
 
     def slh_synchronize(self):
         _check(lib().slh_synchronize(self.h), "slh_synchronize")

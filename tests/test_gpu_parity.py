@@ -196,3 +196,33 @@ def test_checkpoint_resume_bitwise(S):
     c.advance(2)
     assert np.array_equal(c.get_flux(0), ref)
     c.destroy()
+
+
+def test_graph_replay_matches_eager(S):
+    """Step parts replayed from HIP graphs give bitwise the results of direct
+    launches, replay after replay (both bank parities, eager work of another
+    solver interleaved between the replays)."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=5, cells_per_block=4, n_s=2, n_particles=30000, dt=0.05,
+                       sn_order=4)
+    eager, graph = S.Solver(p), S.Solver(p)
+    eager.set_graphs(False)
+    for k in range(7):
+        eager.advance(1)
+        graph.advance(1)
+        for which in (S.SLH_FLUX_REMAP, S.SLH_FLUX_PRE, S.SLH_FLUX_POST,
+                      S.SLH_FLUX_COLLIDED_NODAL):
+            assert np.array_equal(eager.get_flux(which), graph.get_flux(which)), (k, which)
+        ce, cg = eager.get_census(), graph.get_census()
+        for f in ce:
+            assert np.array_equal(ce[f], cg[f]), (k, f)
+        se, sg = eager.get_stats(), graph.get_stats()
+        assert se["si_iterations"] == sg["si_iterations"]
+        assert se["segments_total"] == sg["segments_total"]
+    st = graph.get_stats()
+    log("graph launches", st["graph_launches_total"], "host waits", st["host_waits_total"])
+    assert st["graph_launches_total"] == 4 * 7  # four graph parts per step
+    assert st["host_waits_total"] <= 7 + 4
+    assert eager.get_stats()["graph_launches_total"] == 0
+    eager.destroy()
+    graph.destroy()

@@ -231,9 +231,14 @@ static Sizes sizes_of(const slh_problem* p) {
   z.cap = p->census_cap > 0 ? p->census_cap : std::max<long long>(p->n_particles, 1);
   z.n_cand = z.cap + z.n_p;
   z.n_dir = p->sn_order * p->sn_order;
-  // private tally copies: up to 32, keeping each tally array within 64 MB
-  z.n_copies = 32;
-  while (z.n_copies > 1 && (size_t)z.n_copies * kTallyStride * 8 * (size_t)z.n_cells > (64u << 20))
+  // private tally copies: up to 64 (eight per XCD), keeping each tally array
+  // within 256 MB, and at least one per XCD where that fits in 1 GB
+  z.n_copies = 64;
+  while (z.n_copies > kNumXcd &&
+         (size_t)z.n_copies * kTallyStride * 8 * (size_t)z.n_cells > ((size_t)256 << 20))
+    z.n_copies /= 2;
+  while (z.n_copies > 1 &&
+         (size_t)z.n_copies * kTallyStride * 8 * (size_t)z.n_cells > ((size_t)1 << 30))
     z.n_copies /= 2;
   z.fp32 = p->precision == SLH_FP32_TRACK;
   const bool fields = p->sigma_s && p->sigma_a;
@@ -592,6 +597,7 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.Ta = kind == 1 ? s->Tpre : s->TR;
   a.Tb = kind == 1 ? s->Tpost : s->TR;
   a.n_copies = s->z.n_copies;
+  a.xcd_local = s->z.n_copies % kNumXcd == 0 ? 1 : 0;
   a.copy_stride = (long long)kTallyStride * s->z.n_cells;
   a.st = s->st;
   return a;

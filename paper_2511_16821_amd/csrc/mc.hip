@@ -95,6 +95,15 @@ __device__ __forceinline__ long long tree_pick(const double* __restrict__ t,
   return k - L;
 }
 
+// One fixed-point tally add.  XCD-local copies are only ever added to by
+// workgroups of one XCD, so a workgroup-scope atomic, resolved in that XCD's
+// L2, is exact; kernel boundaries write the L2 back before the copies are
+// summed.  Otherwise a device-scope atomic.
+__device__ __forceinline__ void tally_add(unsigned long long* p, unsigned long long v, int xl) {
+  if (xl) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else atomicAdd(p, v);
+}
+
 // Emission of the pass's source particles, one thread each (Sec. 2.3: birth
 // proportional to q, isotropic direction, weight so that the weights sum to
 // the integral of q): the cell by descending the majorant sum tree with point
@@ -178,7 +187,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long t_all = (long long)gridDim.x * blockDim.x;
   long long next = gtid;
-  const long long my_copy = (gtid % a.n_copies) * a.copy_stride;
+  // tally copy of this lane: within the copies of the workgroup's XCD when
+  // the copies are XCD-local (the hardware XCC id, not the dispatch order,
+  // decides which L2 resolves the adds)
+  const int xl = a.xcd_local;
+  unsigned xcc = 0;
+  if (xl) asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+  const int per = xl ? a.n_copies / kNumXcd : a.n_copies;
+  const long long my_copy =
+      ((xl ? (long long)(xcc % kNumXcd) * per : 0ll) + gtid % per) * a.copy_stride;
   unsigned long long* pend_ptr = a.Ta + my_copy + kTallyStride * (gtid % a.n_cells);
   unsigned long long pend_val = 0ull;
   long long g = 0;
@@ -238,7 +255,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
     }
     if (!__any(have)) {
-      if (pend_val) atomicAdd(pend_ptr, pend_val);
+      if (pend_val) tally_add(pend_ptr, pend_val, xl);
       break;
     }
     if (!have) continue;  // an idle lane keeps its pending tally
@@ -250,7 +267,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // iteration's loads, and on every segment (adding 0 when nothing is
     // pending), so the wait for the loads does not include the atomic's
     // round trip (memory operations retire in issue order).
-    atomicAdd(pend_ptr, pend_val);
+    tally_add(pend_ptr, pend_val, xl);
     pend_val = 0ull;
     const R ss = m.x, sa = m.y, stt = sa + ss;
     const bool pre = n < n_lim;

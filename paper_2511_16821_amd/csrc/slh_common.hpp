@@ -223,13 +223,19 @@ struct PassArgs {
   uint8_t* alive;
   long long out_src_base;  // slot of source particle s is out_src_base + s
   // tallies: n_copies private copies of one fixed-point word per cell (word
-  // stride kTallyStride), copy c at offset c * copy_stride
+  // stride kTallyStride), copy c at offset c * copy_stride.  xcd_local: the
+  // copies are split evenly over the eight XCDs, a workgroup adds only into
+  // its own XCD's copies, and the adds are workgroup-scope atomics, which
+  // the XCD's L2 resolves (device-scope atomics go past the L2)
   unsigned long long* Ta;
   unsigned long long* Tb;
   int n_copies;
+  int xcd_local;
   long long copy_stride;
   DevState* st;
 };
+
+constexpr int kNumXcd = 8;  // XCDs of the device (hardware XCC ids 0..7)
 
 // ---------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files)

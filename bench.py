@@ -156,17 +156,151 @@ def fp32_error(S, p64, p32, steps):
     return worst
 
 
+def downsample4(phi):
+    """4x4 block average (256x256 -> 64x64)."""
+    ny, nx = phi.shape
+    return phi.reshape(ny // 4, 4, nx // 4, 4).mean(axis=(1, 3))
+
+
+def precision_form(S, torch, args):
+    """Thick diffusive medium with voids, 256x256 cells: FP32-tracking vs FP64
+    throughput at the same particle count and seed, the FP32 result's
+    relative L2 deviation from the FP64 path on the 64x64 downsample (every
+    step, max reported), and the QMC error of one run at that particle count,
+    e_QMC = ||s|| / ||mean|| over independent Owen seeds (FP64, last step,
+    same downsample).  The FP64 device path equals the CPU oracle to 1e-10
+    (parity tests), so the deviation from it stands for the deviation from
+    the oracle at this size."""
+    import numpy as np
+    from paper_2511_16821_amd import workloads as W
+    out = []
+    for ns in [int(v) for v in args.c3_ns.split(",") if v != ""]:
+        kw = dict(n_s=ns, n_steps=args.c3_steps)
+        if args.c3_particles:
+            kw["n_particles"] = int(args.c3_particles)
+        p64 = W.c3(precision=0, **kw)
+        p32 = W.c3(precision=1, **kw)
+        steps = args.c3_steps
+        w64, st64 = timed_run(S, torch, p64, steps, 1)
+        w32, st32 = timed_run(S, torch, p32, steps, 1)
+        seg64 = st64["seg_mc_total"] + st64["seg_remap_total"]
+        seg32 = st32["seg_mc_total"] + st32["seg_remap_total"]
+        a, b = S.Solver(p64), S.Solver(p32)
+        worst = 0.0
+        for _ in range(steps):
+            a.advance(1, allow_not_converged=True)
+            b.advance(1, allow_not_converged=True)
+            x = downsample4(a.get_flux(0).reshape(p64["ny"], p64["nx"]))
+            y = downsample4(b.get_flux(0).reshape(p64["ny"], p64["nx"]))
+            worst = max(worst, float(np.linalg.norm(y - x) / max(np.linalg.norm(x), 1e-300)))
+        a.destroy()
+        b.destroy()
+        runs = []
+        for r in range(args.c3_seeds):
+            pr = dict(p64)
+            pr["seed"] = int(p64["seed"]) + 1000003 * (r + 1)
+            sr = S.Solver(pr)
+            sr.advance(steps, allow_not_converged=True)
+            runs.append(downsample4(sr.get_flux(0).reshape(p64["ny"], p64["nx"])))
+            sr.destroy()
+        runs = np.stack(runs)
+        e_qmc = float(np.linalg.norm(runs.std(axis=0, ddof=1)) /
+                      max(np.linalg.norm(runs.mean(axis=0)), 1e-300))
+        row = {"n_s": ns, "n_particles": int(p64["n_particles"]), "steps": steps,
+               "fp64_segments_per_s": seg64 / w64, "fp32_segments_per_s": seg32 / w32,
+               "fp32_speedup": (seg32 / w32) / (seg64 / w64),
+               "fp64_ms_per_step": 1e3 * w64 / steps, "fp32_ms_per_step": 1e3 * w32 / steps,
+               "fp64_mc_kernel_ms_per_step": (st64["ms_kernel_mc_total"] +
+                                              st64["ms_kernel_remap_total"]) / steps,
+               "fp32_mc_kernel_ms_per_step": (st32["ms_kernel_mc_total"] +
+                                              st32["ms_kernel_remap_total"]) / steps,
+               "rel_l2_fp32_vs_fp64_max_over_steps": worst,
+               "e_qmc": e_qmc, "e_qmc_seeds": args.c3_seeds,
+               "fp32_within_bound": bool(worst < min(1e-4, e_qmc))}
+        log("precision form:", json.dumps(row))
+        out.append(row)
+    return {"workload": "256x256 cells on [0,10]^2, sigma_s=100, sigma_a=0.01, 20% area of "
+                        "seeded rectangular voids (sigma_t=0.1), unit source on the central "
+                        "32x32 cells, dt=0.01, S_8, Owen-scrambled Sobol points",
+            "downsample": "64x64 (4x4 block average) of phi_R at each step", "rows": out}
+
+
+def large_resident(S, torch, args):
+    """1024x1024 cells, random blocks, N_s = 3, 1e8 particles per pass, S_16,
+    state resident on the device for the whole run: FP64 and FP32-tracking
+    throughput and the FP32 result's relative L2 deviation from FP64 (same
+    seed, every step, max reported)."""
+    import numpy as np
+    from paper_2511_16821_amd import workloads as W
+    kw = dict(n_steps=args.c5_steps)
+    if args.c5_particles:
+        kw["n_particles"] = int(args.c5_particles)
+    p64 = W.c5(precision=0, **kw)
+    p32 = W.c5(precision=1, **kw)
+    steps = args.c5_steps
+    res = {"workload": "1024x1024 cells on [0,10]^2, sigma_s and sigma_a uniform on [0.01, 20] "
+                       "per 32x32-cell block, unit source on the central 2x2 blocks, N_s=3, "
+                       "%d particles/pass, dt=%g, S_%d" % (p64["n_particles"], p64["dt"],
+                                                           p64["sn_order"]),
+           "steps": steps,
+           "footprint_gib": {"fp64": S.slh_footprint_bytes(p64) / 2 ** 30,
+                             "fp32": S.slh_footprint_bytes(p32) / 2 ** 30}}
+    a, b = S.Solver(p64), S.Solver(p32)
+    worst, last, t64, t32 = 0.0, 0.0, 0.0, 0.0
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a.advance(1, allow_not_converged=True)
+        a.synchronize()
+        t1 = time.perf_counter()
+        b.advance(1, allow_not_converged=True)
+        b.synchronize()
+        t2 = time.perf_counter()
+        t64 += t1 - t0
+        t32 += t2 - t1
+        x, y = a.get_flux(0), b.get_flux(0)
+        last = float(np.linalg.norm(y - x) / max(np.linalg.norm(x), 1e-300))
+        worst = max(worst, last)
+    for name, sv, t in (("fp64", a, t64), ("fp32", b, t32)):
+        st = sv.get_stats()
+        seg = st["seg_mc_total"] + st["seg_remap_total"]
+        res[name] = {"segments_per_s": seg / t, "ms_per_step": 1e3 * t / steps,
+                     "mc_kernel_ms_per_step": (st["ms_kernel_mc_total"] +
+                                               st["ms_kernel_remap_total"]) / steps,
+                     "segments_per_step": seg / steps, "si_iterations_last": st["si_iterations"]}
+        sv.destroy()
+    res["rel_l2_fp32_vs_fp64_max_over_steps"] = worst
+    res["rel_l2_fp32_vs_fp64_last_step"] = last
+    if args.c5_seeds > 1:
+        runs = []
+        for r in range(args.c5_seeds):
+            pr = dict(p64)
+            pr["seed"] = int(p64["seed"]) + 1000003 * (r + 1)
+            sr = S.Solver(pr)
+            sr.advance(steps, allow_not_converged=True)
+            runs.append(sr.get_flux(0))
+            sr.destroy()
+        runs = np.stack(runs)
+        res["e_qmc"] = float(np.linalg.norm(runs.std(axis=0, ddof=1)) /
+                             max(np.linalg.norm(runs.mean(axis=0)), 1e-300))
+        res["e_qmc_seeds"] = args.c5_seeds
+    log("large resident:", json.dumps(res))
+    return res
+
+
 def serve_bench(S, torch, args):
-    """C4: Poisson arrivals of mixed solve requests; continuous batching on
-    the server vs the same stream one solve at a time on the same GPU."""
+    """Poisson arrivals of mixed solve requests; continuous batching on the
+    server vs the same stream served one solve at a time on the same GPU
+    (FIFO, no overlap: completion times from each request's measured service
+    time alone).  The stream is drawn once (unit-rate arrival times scaled by
+    mean service time / rho), so every rho serves the same requests."""
     import numpy as np
     from paper_2511_16821_amd import workloads as W
     sides = tuple(x for x in (32, 64, 128, 256, 512) if x <= args.serve_max_side)
-    stream = W.request_stream(n_req=args.serve_requests, rho=args.rho, seed=args.serve_seed,
+    stream = W.request_stream(n_req=args.serve_requests, rho=1.0, seed=args.serve_seed,
                               sides=sides, np_range=(1e4, args.serve_max_particles))
     unit_arrivals = np.array([a for a, _ in stream])
     reqs = [p for _, p in stream]
-    # one solve at a time: service time of each request alone
     service, seg_alone, flux_alone = [], [], []
     for p in reqs:
         torch.cuda.synchronize()
@@ -181,42 +315,44 @@ def serve_bench(S, torch, args):
         flux_alone.append(f)
     service = np.array(service)
     t_mean = float(service.mean())
-    arrivals = unit_arrivals * t_mean / args.rho
-    # FIFO, one at a time, same arrivals: nothing overlaps, so the completion
-    # times follow from the measured service times
-    done, lat_serial = 0.0, []
-    for a, t in zip(arrivals, service):
-        done = max(a, done) + t
-        lat_serial.append(done - a)
-    serial_makespan = done
-    # continuous batching
-    budget = int(args.serve_budget_gib * (1 << 30))
-    srv = S.Server(hbm_budget_bytes=budget, max_slots=args.serve_slots)
-    t_start = time.perf_counter()
-    tickets = []
-    for a, p in zip(arrivals, reqs):
-        wait = t_start + a - time.perf_counter()
-        if wait > 0:
-            time.sleep(wait)
-        tickets.append(srv.submit(p, int(p["n_steps"])))
-    res = [srv.result(t) for t in tickets]
-    t_end = time.perf_counter()
-    srv.destroy()
-    lat = np.array([r[2]["latency_ms"] for r in res]) / 1e3
-    seg = sum(r[2]["segments"] for r in res)
-    same = all(np.array_equal(r[0], f) for r, f in zip(res, flux_alone))
+    log("serving: %d requests, serial service sum %.1f s" % (len(reqs), service.sum()))
+    rows = []
+    for rho in [float(v) for v in str(args.rho).split(",") if v != ""]:
+        arrivals = unit_arrivals * t_mean / rho
+        done, lat_serial = 0.0, []
+        for a, t in zip(arrivals, service):
+            done = max(a, done) + t
+            lat_serial.append(done - a)
+        serial_span = done - arrivals[0]
+        budget = int(args.serve_budget_gib * (1 << 30))
+        srv = S.Server(hbm_budget_bytes=budget, max_slots=args.serve_slots)
+        t_start = time.perf_counter()
+        tickets = []
+        for a, p in zip(arrivals, reqs):
+            wait = t_start + a - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(srv.submit(p, int(p["n_steps"])))
+        res = [srv.result(t) for t in tickets]
+        t_end = time.perf_counter()
+        srv.destroy()
+        lat = np.array([r[2]["latency_ms"] for r in res]) / 1e3
+        seg = sum(r[2]["segments"] for r in res)
+        same = all(np.array_equal(r[0], f) for r, f in zip(res, flux_alone))
+        row = {"rho": rho,
+               "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+               "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+               "segments_per_s": seg / (t_end - t_start),
+               "one_at_a_time": {
+                   "p50_latency_ms": float(np.percentile(lat_serial, 50) * 1e3),
+                   "p99_latency_ms": float(np.percentile(lat_serial, 99) * 1e3),
+                   "segments_per_s": float(sum(seg_alone) / serial_span)},
+               "results_identical_to_alone": bool(same)}
+        log("serving rho=%g:" % rho, json.dumps(row))
+        rows.append(row)
     return {
-        "requests": len(reqs), "rho": args.rho, "slots": args.serve_slots,
-        "budget_gib": args.serve_budget_gib,
-        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
-        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
-        "segments_per_s": seg / (t_end - t_start),
-        "one_at_a_time": {
-            "p50_latency_ms": float(np.percentile(lat_serial, 50) * 1e3),
-            "p99_latency_ms": float(np.percentile(lat_serial, 99) * 1e3),
-            "segments_per_s": float(sum(seg_alone) / serial_makespan),
-            "mean_service_ms": 1e3 * t_mean},
-        "results_identical_to_alone": bool(same),
+        "requests": len(reqs), "slots": args.serve_slots, "budget_gib": args.serve_budget_gib,
+        "mean_service_ms": 1e3 * t_mean, "rows": rows,
         "stream": "Poisson arrivals at rate rho/mean service time; sides %s, N_s in {0,1,2,4}, "
                   "particles log-uniform 1e4-%g, 5-50 steps, FP32/FP64 mixed, lognormal "
                   "8x8-block materials" % (list(sides), args.serve_max_particles),
@@ -235,6 +371,18 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the FP32-vs-FP64 precision form (256x256 thick medium)")
+    ap.add_argument("--c3-ns", default="0,1,2,4")
+    ap.add_argument("--c3-steps", type=int, default=20)
+    ap.add_argument("--c3-seeds", type=int, default=8)
+    ap.add_argument("--c3-particles", type=float, default=None)
+    ap.add_argument("--c5", action="store_true",
+                    help="also run the large resident solve (1024x1024, 1e8 particles/pass)")
+    ap.add_argument("--c5-steps", type=int, default=50)
+    ap.add_argument("--c5-particles", type=float, default=None)
+    ap.add_argument("--c5-seeds", type=int, default=4,
+                    help="independent Owen seeds for the QMC error of the large solve")
     ap.add_argument("--serve", action="store_true",
                     help="also run the serving benchmark (continuous batching)")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -243,7 +391,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-seed", type=int, default=4)
-    ap.add_argument("--rho", type=float, default=1.0)
+    ap.add_argument("--rho", default="1.0", help="comma-separated loads, e.g. 0.5,1,2")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -297,6 +445,10 @@ def main():
                              "roofline": roofline(st32, steps, 1)}
         log("fp32-track: %.3f s, %.3e segments/s, rel-L2 vs fp64 %.2e" %
             (wall32, seg32 / wall32, err))
+    if not args.no_c3:
+        out["precision_form"] = precision_form(S, torch, args)
+    if args.c5:
+        out["large_resident"] = large_resident(S, torch, args)
     if args.serve:
         out["serving"] = serve_bench(S, torch, args)
         log("serving:", json.dumps(out["serving"]))

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
 }
 
 template <typename R, int KIND>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mc_pass(PassArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mc_pass(PassArgs a) {
   __shared__ unsigned long long s_bal[2 * B_NFIELDS];
   __shared__ unsigned long long s_cnt[4];
   __shared__ uint32_t s_sobol[kSobolDims * 32];

@@ -141,6 +141,15 @@ def test_dg_long_diagonals(S, oracle, per_cell):
     _run_pair(S, oracle, p, 1, check_census=False)
 
 
+def test_random_blocks_subproblem(S, oracle):
+    """The large random-block recipe on its 128x128 subproblem (4x4-cell
+    blocks, 1024 materials: cell-mode sweep), N_s = 3; fewer particles and
+    S_8 instead of S_16 so that the oracle finishes in seconds."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.c5_subproblem(n_particles=20000, sn_order=8)
+    _run_pair(S, oracle, p, 2)
+
+
 def test_degenerate_cases(S, oracle):
     from paper_2511_16821_amd import workloads as W
     # no source at all

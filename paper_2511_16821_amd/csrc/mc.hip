@@ -112,9 +112,9 @@ __device__ __forceinline__ void tally_add(unsigned long long* p, unsigned long l
 // (dim 6) when the pass allows scatters.
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
-  __shared__ uint32_t s_sobol[kSobolDims * 32];
+  __shared__ uint32_t s_sobol[kSobolNibbleWords];
   __shared__ double s_top[kTreeTop];
-  for (int k = threadIdx.x; k < kSobolDims * 32; k += blockDim.x) s_sobol[k] = a.sobol[k];
+  sobol_nibbles_fill(a.sobol, s_sobol, threadIdx.x, blockDim.x);
   {
     const long long ntop = 2 * a.tree_L < kTreeTop ? 2 * a.tree_L : kTreeTop;
     for (int k = threadIdx.x; k < kTreeTop; k += blockDim.x)
@@ -130,13 +130,13 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < a.n_src;
        s += (long long)gridDim.x * blockDim.x) {
     const uint32_t pidx = (uint32_t)s;
-    const double u0 = u01_f64(point_u32(s_sobol, a.points, stream, 0u, pidx));
+    const double u0 = u01_f64(point_u32n(s_sobol, a.points, stream, 0u, pidx));
     const long long ci = tree_pick(a.tree, s_top, a.tree_L, u0);
-    const R u1 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 1u, pidx));
-    const R u2 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 2u, pidx));
-    const R u3 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 3u, pidx));
-    const R u4 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 4u, pidx));
-    const R u5 = PointU<R>::u(point_u32(s_sobol, a.points, stream, 5u, pidx));
+    const R u1 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 1u, pidx));
+    const R u2 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 2u, pidx));
+    const R u3 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 3u, pidx));
+    const R u4 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 4u, pidx));
+    const R u5 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, pidx));
     const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
     R sp, cp;
     Real<R>::scpi((R)2 * u5, &sp, &cp);
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
     b.oy[s] = sn * sp;
     b.w[s] = (R)(w_src * (bilinear(q, (double)u1, (double)u2) / pow2_ceil(maxabs4(q))));
     b.trel[s] = u3 * dt;
-    b.tau[s] = a.n_lim > 0 ? -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, 6u, pidx)))
+    b.tau[s] = a.n_lim > 0 ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 6u, pidx)))
                            : (R)0;
     b.cell[s] = (int32_t)ci;
   }
@@ -157,10 +157,10 @@ template <typename R, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mc_pass(PassArgs a) {
   __shared__ unsigned long long s_bal[2 * B_NFIELDS];
   __shared__ unsigned long long s_cnt[4];
-  __shared__ uint32_t s_sobol[kSobolDims * 32];
+  __shared__ uint32_t s_sobol[kSobolNibbleWords];
   if (threadIdx.x < 2 * B_NFIELDS) s_bal[threadIdx.x] = 0ull;
   if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0ull;
-  for (int k = threadIdx.x; k < kSobolDims * 32; k += blockDim.x) s_sobol[k] = a.sobol[k];
+  sobol_nibbles_fill(a.sobol, s_sobol, threadIdx.x, blockDim.x);
   __syncthreads();
 
   DevState* st = a.st;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       ioy = oy != (R)0 ? (R)1 / oy : (R)0;
       w0 = (double)w;
       if (from_census && n_lim > 0) {
-        tau = -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, 0u, pidx)));
+        tau = -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 0u, pidx)));
         dcur = 1;
       }
     }
@@ -312,8 +312,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       px += ox * l;
       py += oy * l;
       // isotropic re-emission, scatter counter n <- n + 1
-      const R ua = PointU<R>::u(point_u32(s_sobol, a.points, stream, dcur, pidx));
-      const R ub = PointU<R>::u(point_u32(s_sobol, a.points, stream, dcur + 1u, pidx));
+      const R ua = PointU<R>::u(point_u32n(s_sobol, a.points, stream, dcur, pidx));
+      const R ub = PointU<R>::u(point_u32n(s_sobol, a.points, stream, dcur + 1u, pidx));
       dcur += 2;
       const R sn = (R)2 * sqrt(ua * ((R)1 - ua));
       R sp, cp;
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       ioy = oy != (R)0 ? (R)1 / oy : (R)0;
       n++;
       if (n < n_lim) {
-        tau = -log(PointU<R>::u(point_u32(s_sobol, a.points, stream, dcur, pidx)));
+        tau = -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, dcur, pidx)));
         dcur++;
       }
     } else if (ev == EV_XFACE) {
@@ -449,12 +449,18 @@ hipError_t launch_mc_pass(const PassArgs& a, bool fp32, int grid, hipStream_t s)
   return hipGetLastError();
 }
 
-__global__ void k_qmc_points(uint64_t stream, uint32_t dim0, uint32_t nd, uint32_t idx0,
-                             uint32_t n, int mode, const uint32_t* sobol, uint32_t* out) {
+// The tracking kernels' point function (nibble tables), one word per thread.
+__global__ __launch_bounds__(256) void k_qmc_points(uint64_t stream, uint32_t dim0,
+                                                    uint32_t nd, uint32_t idx0, uint32_t n,
+                                                    int mode, const uint32_t* sobol,
+                                                    uint32_t* out) {
+  __shared__ uint32_t s_nib[kSobolNibbleWords];
+  sobol_nibbles_fill(sobol, s_nib, threadIdx.x, blockDim.x);
+  __syncthreads();
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)n * nd) return;
   const uint32_t k = (uint32_t)(t / nd), d = (uint32_t)(t % nd);
-  out[t] = point_u32(sobol, mode, stream, dim0 + d, idx0 + k);
+  out[t] = point_u32n(s_nib, mode, stream, dim0 + d, idx0 + k);
 }
 
 hipError_t launch_qmc_points(uint64_t stream, uint32_t dim0, uint32_t nd, uint32_t idx0,

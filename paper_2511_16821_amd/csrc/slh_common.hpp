@@ -45,24 +45,44 @@ __device__ __forceinline__ uint32_t nested_scramble(uint32_t x, uint32_t s) {
 
 constexpr int kSobolDims = 32;
 
-// V: the direction-number table (kSobolDims x 32 words) in device memory.
-__device__ __forceinline__ uint32_t sobol_word(const uint32_t* __restrict__ V, uint32_t dim,
-                                               uint32_t index) {
-  const uint32_t* v = V + dim * 32u;
-  uint32_t x = 0;
-  while (index) {
-    const uint32_t j = (uint32_t)__builtin_ctz(index);
-    x ^= v[j];
-    index &= index - 1u;
+// Point function of Sec. 2.4: the Sobol' word of (dim, index) is the XOR of
+// the direction numbers V[dim][j] over the set bits j of the index, nested
+// (Owen) scrambled with a per-(stream, dim) seed; dims >= kSobolDims and the
+// pseudo-random mode hash (stream, dim, index).  The XOR runs over nibble
+// tables: N[d][p][n] is the XOR of V[d][4p + k] over the set bits k of the
+// 4-bit value n, so a word is the XOR of its index's eight nibble entries
+// (eight lookups instead of a loop over the set bits).  N has kSobolDims x
+// 8 x 16 words, built from V (kSobolDims x 32 words).
+constexpr int kSobolNibbleWords = kSobolDims * 8 * 16;
+
+__device__ __forceinline__ void sobol_nibbles_fill(const uint32_t* __restrict__ V, uint32_t* N,
+                                                   int tid, int nthreads) {
+  for (int e = tid; e < kSobolNibbleWords; e += nthreads) {
+    const int d = e >> 7, pos = (e >> 4) & 7, n = e & 15;
+    const uint32_t* v = V + d * 32 + 4 * pos;
+    uint32_t x = 0;
+    if (n & 1) x ^= v[0];
+    if (n & 2) x ^= v[1];
+    if (n & 4) x ^= v[2];
+    if (n & 8) x ^= v[3];
+    N[e] = x;
   }
+}
+
+__device__ __forceinline__ uint32_t sobol_word_nib(const uint32_t* N, uint32_t dim,
+                                                   uint32_t index) {
+  const uint32_t* t = N + dim * 128u;
+  uint32_t x = 0;
+#pragma unroll
+  for (int pos = 0; pos < 8; ++pos) x ^= t[pos * 16 + ((index >> (4 * pos)) & 15u)];
   return x;
 }
 
-__device__ __forceinline__ uint32_t point_u32(const uint32_t* __restrict__ V, int mode,
-                                              uint64_t stream, uint32_t dim, uint32_t index) {
+__device__ __forceinline__ uint32_t point_u32n(const uint32_t* N, int mode, uint64_t stream,
+                                               uint32_t dim, uint32_t index) {
   if (mode == 0 && dim < (uint32_t)kSobolDims) {
     const uint32_t s = (uint32_t)(mix64(stream + dim) >> 32);
-    return nested_scramble(sobol_word(V, dim, index), s);
+    return nested_scramble(sobol_word_nib(N, dim, index), s);
   }
   const uint64_t ctr = ((uint64_t)dim << 32) | (uint64_t)index;
   return (uint32_t)(mix64(stream ^ mix64(ctr)) >> 32);

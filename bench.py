@@ -288,6 +288,61 @@ def large_resident(S, torch, args):
     return res
 
 
+def protocol(S, torch, args):
+    """The paper's measurements on a stand-in (Sec. 3, Table 1 protocol): for
+    each scatter limit N_s (-1 = unlimited, the plain MC reference case), the
+    relative L2 error of phi_R after the last step against a same-method
+    reference at 2^22 particles, for scrambled-Sobol' points (RMS over Owen
+    seeds) and pseudo-random points (RMS over seeds), at particle counts 2^10
+    .. 2^18; the fitted slopes alpha (error ~ N^-alpha), the source-iteration
+    count of the collided solve, and the time per step."""
+    import numpy as np
+    from paper_2511_16821_amd import workloads as W
+    ns_list = [int(v) for v in args.protocol_ns.split(",") if v != ""]
+    ladder = [2 ** k for k in range(10, 19, 2)]
+    rows = []
+    for ns in ns_list:
+        base = W.c1(n_s=ns, n_steps=args.protocol_steps, dt=args.protocol_dt)
+
+        def run(n, points, seed):
+            p = dict(base)
+            p.update(n_particles=int(n), points=points, seed=int(seed))
+            s = S.Solver(p, torch_allocator=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.advance(args.protocol_steps, allow_not_converged=True)
+            f = s.get_flux(0)
+            t = time.perf_counter() - t0
+            it = s.get_stats()["si_iterations"]
+            s.destroy()
+            return f, t / args.protocol_steps, it
+
+        ref, _, _ = run(2 ** 22, 0, 7777)
+        nref = max(np.linalg.norm(ref), 1e-300)
+        row = {"n_s": ns, "particles": ladder, "steps": args.protocol_steps}
+        for name, mode in (("qmc", 0), ("mc", 1)):
+            errs, times, iters = [], [], []
+            for n in ladder:
+                e2 = 0.0
+                for r in range(args.protocol_seeds):
+                    f, t, it = run(n, mode, 1000 + 17 * r)
+                    e2 += float(np.linalg.norm(f - ref) / nref) ** 2
+                    times.append(t)
+                    iters.append(it)
+                errs.append((e2 / args.protocol_seeds) ** 0.5)
+            slope = -float(np.polyfit(np.log(ladder), np.log(errs), 1)[0])
+            row[name] = {"rel_l2": errs, "alpha": slope,
+                         "ms_per_step_mean": 1e3 * float(np.mean(times))}
+            row["si_iterations_last_step"] = int(np.median(iters))
+        log("protocol:", json.dumps(row))
+        rows.append(row)
+    return {"workload": "20x20 cells on [0,2]^2, sigma_s=1, sigma_a=0.1, Q=1 on the central 2x2 "
+                        "cells, dt=%g, S_8 (the C1 family); error of phi_R after %d steps against "
+                        "a 2^22-particle run of the same method" % (args.protocol_dt,
+                                                                    args.protocol_steps),
+            "rows": rows}
+
+
 def serve_bench(S, torch, args):
     """Poisson arrivals of mixed solve requests; continuous batching on the
     server vs the same stream served one solve at a time on the same GPU
@@ -377,6 +432,13 @@ def main():
     ap.add_argument("--c3-steps", type=int, default=20)
     ap.add_argument("--c3-seeds", type=int, default=8)
     ap.add_argument("--c3-particles", type=float, default=None)
+    ap.add_argument("--protocol", action="store_true",
+                    help="also run the paper's protocol: QMC vs MC convergence slopes and "
+                         "source-iteration counts for several N_s")
+    ap.add_argument("--protocol-ns", default="0,1,2,4,-1")
+    ap.add_argument("--protocol-steps", type=int, default=10)
+    ap.add_argument("--protocol-dt", type=float, default=0.1)
+    ap.add_argument("--protocol-seeds", type=int, default=4)
     ap.add_argument("--c5", action="store_true",
                     help="also run the large resident solve (1024x1024, 1e8 particles/pass)")
     ap.add_argument("--c5-steps", type=int, default=50)
@@ -447,6 +509,8 @@ def main():
             (wall32, seg32 / wall32, err))
     if not args.no_c3:
         out["precision_form"] = precision_form(S, torch, args)
+    if args.protocol:
+        out["protocol"] = protocol(S, torch, args)
     if args.c5:
         out["large_resident"] = large_resident(S, torch, args)
     if args.serve:

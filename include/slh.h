@@ -89,7 +89,9 @@ typedef struct {
     const double *q;               /* host, nx*ny, >= 0, angle-integrated    */
     double c;                      /* particle speed, > 0                    */
     double dt;                     /* time step, > 0                         */
-    int32_t n_s;                   /* scatter limit N_s >= 0                 */
+    int32_t n_s;                   /* scatter limit N_s >= 0; -1: unlimited
+                                      (the first leg is then plain MC, the
+                                      collided solve has no source)        */
     int64_t n_particles;           /* source particles per MC pass, 0..2^32-1 */
     int64_t census_cap;            /* census bank size; 0 -> n_particles     */
     int32_t sn_order;              /* even N >= 2: N^2 product directions    */

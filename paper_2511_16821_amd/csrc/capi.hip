@@ -197,7 +197,8 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
     return fail(SLH_E_INVALID_ARG, "empty or non-finite domain");
   if (!(p->c > 0.0) || !isfinite(p->c)) return fail(SLH_E_INVALID_ARG, "c must be > 0");
   if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(SLH_E_INVALID_ARG, "dt must be > 0");
-  if (p->n_s < 0 || p->n_s > 1000000) return fail(SLH_E_INVALID_ARG, "n_s out of range");
+  if (p->n_s < -1 || p->n_s > 1000000)
+    return fail(SLH_E_INVALID_ARG, "n_s must be -1 (unlimited) or in [0, 1e6]");
   if (p->n_particles < 0 || p->n_particles > 0xffffffffll)
     return fail(SLH_E_INVALID_ARG, "n_particles must be in [0, 2^32)");
   if (p->census_cap < 0 || p->census_cap > (1ll << 34))
@@ -577,7 +578,8 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.n_src = s->z.n_p;
   a.seed = p.seed;
   a.kind = kind;
-  a.n_lim = kind == 1 ? p.n_s : 0;
+  // n_s = -1: no scatter limit (the leg is plain implicit-capture MC)
+  a.n_lim = kind == 1 ? (p.n_s < 0 ? 0x7fffffff : p.n_s) : 0;
   a.points = p.points;
   a.sobol = s->sobol;
   a.w_cut_rel = p.w_cut_rel;

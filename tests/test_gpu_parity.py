@@ -150,6 +150,22 @@ def test_random_blocks_subproblem(S, oracle):
     _run_pair(S, oracle, p, 2)
 
 
+def test_unlimited_scatter_limit(S, oracle):
+    """N_s = -1: no scatter limit, the first leg is plain implicit-capture MC
+    (c dt = 10 mean free paths: about ten collisions per history, so point
+    dimensions run past the Sobol' table), the collided solve has no source."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.c1(n_s=-1, n_particles=6000, dt=10.0)
+    res = _run_pair(S, oracle, p, 3)
+    s = S.Solver(p)
+    s.advance(1)
+    assert s.get_stats()["si_iterations"] == 1
+    assert not np.any(s.get_flux(S.SLH_FLUX_POST))
+    assert not np.any(s.get_flux(S.SLH_FLUX_COLLIDED_NODAL))
+    s.destroy()
+    assert res
+
+
 def test_degenerate_cases(S, oracle):
     from paper_2511_16821_amd import workloads as W
     # no source at all

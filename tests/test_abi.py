@@ -39,7 +39,7 @@ def test_validation_rejects_before_allocating(S):
     from paper_2511_16821_amd import workloads as W
     good = W.c1()
     bad_cases = [
-        dict(nx=0), dict(dt=0.0), dict(dt=-1.0), dict(c=0.0), dict(n_s=-1),
+        dict(nx=0), dict(dt=0.0), dict(dt=-1.0), dict(c=0.0), dict(n_s=-2),
         dict(sn_order=5), dict(sn_order=0), dict(n_particles=-5), dict(points=7),
         dict(precision=3), dict(w_cut_rel=-1.0), dict(x_hi=0.0),
     ]

@@ -666,6 +666,7 @@ static DgArgs dg_args(slh_solver* s) {
   d.coef = s->coef;
   d.dirmat = s->dirmat;
   d.n_chunks = (int)z.dg_chunks;
+  d.loader_q = 1;  // one loader wave per sweeping wave
   d.st = s->st;
   return d;
 }

@@ -19,12 +19,13 @@
 // diagonal, or a piece of a long one).  Cells of one diagonal have distinct
 // rows and columns, so the outflow traces they hand to the next diagonal live
 // in two small LDS arrays (one trace per row for the x faces, one per column
-// for the y faces).  The workgroup has CW/64 sweeping waves and one loader
-// wave.  The loader keeps several chunks of nodal sources and material keys
-// in flight in registers and hands each chunk over through a two-slot LDS
-// buffer, so the sweeping waves never wait on global memory: their only
-// global accesses are the stores of w_m psi_m (a wave that mixed loads and
-// stores would have to drain all of them before using a loaded value).  After
+// for the y faces).  The workgroup has CW/64 sweeping waves and CW/(64 Q)
+// loader waves (Q cells per loader lane).  The loaders keep several chunks of
+// nodal sources and material keys in flight in registers and hand each chunk
+// over through a two-slot LDS buffer, so the sweeping waves never wait on
+// global memory: their only global accesses are the stores of w_m psi_m (a
+// wave that mixed loads and stores would have to drain all of them before
+// using a loaded value).  After
 // each barrier a sweeping lane turns the upwind traces into its cell's
 // solution with the element data prepared before the barrier:
 //   table mode: psi = B S + G up with B = A^-1 Mx(x)My, G = A^-1 F taken from
@@ -168,22 +169,24 @@ long long dg_chunks(int nx, int ny, int cw) {
 
 constexpr int kDgDepth = 4;  // chunks in flight in the loader wave
 
-// One chunk in the loader: up to four cells per lane (source, key, position
-// in the chunk or -1).
+// One chunk in a loader lane: Q cells (source, key, position in the chunk
+// or -1).
+template <int Q>
 struct DgStage {
-  double Sx[4], Sy[4], Sz[4], Sw[4];
-  double Kd[4];  // cell mode: sigma_e
-  int Ki[4];     // table mode: material
-  int C[4];
+  double Sx[Q], Sy[Q], Sz[Q], Sw[Q];
+  double Kd[Q];  // cell mode: sigma_e
+  int Ki[Q];     // table mode: material
+  int C[Q];
 };
 
-template <bool TABLE>
-__global__ __launch_bounds__(320) void k_dg_sweep_pc(DgArgs g) {
+template <bool TABLE, int Q>
+__global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
   if (g.st->si_done) return;  // the whole workgroup: no barrier is left pending
   extern __shared__ double smem[];
   const int nx = g.nx, ny = g.ny;
   const int CW = g.cw;       // sweeping lanes, multiple of 64, <= 256
-  const int npl = CW >> 6;   // cells per loader lane and chunk
+  const int n_sw = CW >> 6;  // sweeping waves; the loader waves follow them
+  const int n_ld = n_sw / Q; // loader waves, Q cells per loader lane and chunk
   const int m = blockIdx.x;
   const double a = g.dir[3 * m + 0], b = g.dir[3 * m + 1], wm = g.dir[3 * m + 2];
   const bool apos = a > 0.0, bpos = b > 0.0;
@@ -201,25 +204,26 @@ __global__ __launch_bounds__(320) void k_dg_sweep_pc(DgArgs g) {
   auto diag_hi = [&](int dd) __attribute__((always_inline)) { return dd < nx - 1 ? dd : nx - 1; };
   auto diag_lo = [&](int dd) __attribute__((always_inline)) { return dd - (ny - 1) > 0 ? dd - (ny - 1) : 0; };
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const bool loader = wave == npl;
+  const bool loader = wave >= n_sw;
   const int lane = threadIdx.x & 63;
+  const int lw = wave - n_sw;  // loader wave index
 
-  // ---- loader state: ring of kDgDepth chunks, npl cells per lane ----
-  DgStage r0s, r1s, r2s, r3s;
+  // ---- loader state: ring of kDgDepth chunks, Q cells per lane ----
+  DgStage<Q> r0s, r1s, r2s, r3s;
   int fd = 0, fp = 0;   // fetch front: diagonal, first position
   // Every lane issues the same loads in every stage (a position without a
   // cell reads cell 0 and is marked -1): with no branch around the loads the
   // compiler can wait for one stage while the younger ones stay in flight.
-  auto fetch = [&](DgStage& st) __attribute__((always_inline)) {
+  auto fetch = [&](DgStage<Q>& st) __attribute__((always_inline)) {
     const bool live = fd < n_diag;
     const int hi = live ? diag_hi(fd) : -1;
     const int dl = live ? fd : n_diag - 1;  // a real diagonal for the addresses
     const int dlo = diag_lo(dl), dhi = diag_hi(dl);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int tq = lane + 64 * q;
+    for (int q = 0; q < Q; ++q) {
+      const int tq = lane + 64 * (lw + n_ld * q);
       const int ip = fp + tq;
-      const bool ok = q < npl && ip <= hi;
+      const bool ok = ip <= hi;
       // clamp the position onto the diagonal, so that every lane's address
       // is a real cell and no branch guards the loads
       const int ipc = ip < dlo ? dlo : (ip < dhi ? ip : dhi);
@@ -244,9 +248,9 @@ __global__ __launch_bounds__(320) void k_dg_sweep_pc(DgArgs g) {
       }
     }
   };
-  auto hand_over = [&](const DgStage& st, int slot) __attribute__((always_inline)) {
+  auto hand_over = [&](const DgStage<Q>& st, int slot) __attribute__((always_inline)) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < Q; ++q)
       if (st.C[q] >= 0) {
         slotS[slot * CW + st.C[q]] = make_double4(st.Sx[q], st.Sy[q], st.Sz[q], st.Sw[q]);
         slotK[slot * CW + st.C[q]] = TABLE ? (double)st.Ki[q] : st.Kd[q];
@@ -410,10 +414,23 @@ hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   hipLaunchKernelGGL(k_dg_source, dim3(grid), dim3(256), 0, s, nc, a.sig_s, a.phi_post,
                      a.phi_in, a.src, a.st);
   const size_t lds = dg_sweep_lds_bytes(table, a.cw, a.n_mat, a.nx, a.ny);
-  if (table)
-    hipLaunchKernelGGL(k_dg_sweep_pc<true>, dim3(a.n_dir), dim3(a.cw + 64), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_dg_sweep_pc<false>, dim3(a.n_dir), dim3(a.cw + 64), lds, s, a);
+  const int n_sw = a.cw / 64;
+  const int q = a.loader_q;  // cells per loader lane; n_sw / q loader waves
+  if (q < 1 || n_sw % q) return hipErrorInvalidValue;
+  const dim3 block(a.cw + 64 * (n_sw / q));
+#define SLH_DG_SWEEP(T_, Q_) hipLaunchKernelGGL((k_dg_sweep_pc<T_, Q_>), dim3(a.n_dir), block, lds, s, a)
+  if (table) {
+    if (q == 1) SLH_DG_SWEEP(true, 1);
+    else if (q == 2) SLH_DG_SWEEP(true, 2);
+    else if (q == 3) SLH_DG_SWEEP(true, 3);
+    else SLH_DG_SWEEP(true, 4);
+  } else {
+    if (q == 1) SLH_DG_SWEEP(false, 1);
+    else if (q == 2) SLH_DG_SWEEP(false, 2);
+    else if (q == 3) SLH_DG_SWEEP(false, 3);
+    else SLH_DG_SWEEP(false, 4);
+  }
+#undef SLH_DG_SWEEP
   return hipGetLastError();
 }
 

@@ -287,6 +287,7 @@ struct DgArgs {
   const double* coef;
   int cw;                // sweeping lanes per workgroup (multiple of 64, <= 256)
   int n_chunks;          // dg_chunks(nx, ny, cw)
+  int loader_q;          // cells per loader lane (1..4, divides cw / 64)
   const DevState* st;    // si_done: skip the iteration
 };
 hipError_t launch_dg_tables(int n_dir, int n_mat, const double* dir, const double* sig_e_mat,

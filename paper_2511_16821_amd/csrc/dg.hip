@@ -25,11 +25,12 @@
 // over through a two-slot LDS buffer, so the sweeping waves never wait on
 // global memory: their only global accesses are the stores of w_m psi_m (a
 // wave that mixed loads and stores would have to drain all of them before
-// using a loaded value).  After
-// each barrier a sweeping lane turns the upwind traces into its cell's
-// solution with the element data prepared before the barrier:
+// using a loaded value).  After each barrier a sweeping lane turns the upwind
+// traces into its cell's solution with the element data prepared before the
+// barrier:
 //   table mode: psi = B S + G up with B = A^-1 Mx(x)My, G = A^-1 F taken from
 //     a per-(direction, material) table staged in LDS (few distinct sigma_e);
+//     the loader hands over B S instead of S;
 //   cell mode: A is LU-factorised before the barrier and solved after it.
 // The weighted solution goes to a per-direction plane, and the directions
 // are summed in a fixed order by a second kernel, so the scalar flux does
@@ -248,11 +249,21 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
       }
     }
   };
+  // Table mode hands over B S (B from the staged table) instead of S, which
+  // takes a matrix-vector product off the sweeping lanes' critical path.
   auto hand_over = [&](const DgStage<Q>& st, int slot) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
       if (st.C[q] >= 0) {
-        slotS[slot * CW + st.C[q]] = make_double4(st.Sx[q], st.Sy[q], st.Sz[q], st.Sw[q]);
+        double4 v = make_double4(st.Sx[q], st.Sy[q], st.Sz[q], st.Sw[q]);
+        if (TABLE) {
+          const double* c = coefL + (size_t)st.Ki[q] * 32;
+          v = make_double4(c[0] * st.Sx[q] + c[1] * st.Sy[q] + c[2] * st.Sz[q] + c[3] * st.Sw[q],
+                           c[4] * st.Sx[q] + c[5] * st.Sy[q] + c[6] * st.Sz[q] + c[7] * st.Sw[q],
+                           c[8] * st.Sx[q] + c[9] * st.Sy[q] + c[10] * st.Sz[q] + c[11] * st.Sw[q],
+                           c[12] * st.Sx[q] + c[13] * st.Sy[q] + c[14] * st.Sz[q] + c[15] * st.Sw[q]);
+        }
+        slotS[slot * CW + st.C[q]] = v;
         slotK[slot * CW + st.C[q]] = TABLE ? (double)st.Ki[q] : st.Kd[q];
       }
   };
@@ -267,11 +278,12 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
     const double* src = g.coef + (size_t)m * n_coef;
     for (size_t k = threadIdx.x; k < n_coef; k += blockDim.x) coefL[k] = src[k];
   }
+  __syncthreads();  // faces zeroed, table staged
   if (loader) {
     hand_over(r0s, 0);
     fetch(r0s);
   }
-  __syncthreads();  // faces zeroed, table staged, chunk 0 in slot 0
+  __syncthreads();  // chunk 0 in slot 0
 
   if (loader) {
     // before barrier k, chunk k + 1 goes to slot (k + 1) & 1; it sits in
@@ -323,9 +335,10 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
       const double key = slotK[slot * CW + t];
       if (TABLE) {
         const double* c = coefL + (size_t)(int)key * 32;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          r0[r] = c[4 * r] * S.x + c[4 * r + 1] * S.y + c[4 * r + 2] * S.z + c[4 * r + 3] * S.w;
+        r0[0] = S.x;  // B S, formed by the loader
+        r0[1] = S.y;
+        r0[2] = S.z;
+        r0[3] = S.w;
 #pragma unroll
         for (int k = 0; k < 16; ++k) P[k] = c[16 + k];
       } else {

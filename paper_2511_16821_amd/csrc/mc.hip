@@ -104,6 +104,19 @@ __device__ __forceinline__ void tally_add(unsigned long long* p, unsigned long l
   else atomicAdd(p, v);
 }
 
+// Copies of a tracking block's balance in LDS (odd stride: the copies start
+// in different banks).
+constexpr int kBalCopies = 8;
+constexpr int kBalStride = 2 * B_NFIELDS + 1;
+
+// Adds v, in fixed point (hi, lo) of unit 1/inv_W, to balance field f.
+__device__ __forceinline__ void bal_add(unsigned long long* bal, int f, double v, double inv_W) {
+  long long hi, lo;
+  fix_split(v, inv_W, hi, lo);
+  atomicAdd(&bal[2 * f], (unsigned long long)hi);
+  atomicAdd(&bal[2 * f + 1], (unsigned long long)lo);
+}
+
 // Emission of the pass's source particles, one thread each (Sec. 2.3: birth
 // proportional to q, isotropic direction, weight so that the weights sum to
 // the integral of q): the cell by descending the majorant sum tree with point
@@ -155,10 +168,15 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
 
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mc_pass(PassArgs a) {
-  __shared__ unsigned long long s_bal[2 * B_NFIELDS];
+  // Block balance in kBalCopies LDS copies picked by lane: with a per-lane
+  // address the adds are plain LDS atomics, where one shared address would
+  // make the compiler serialise them over the active lanes in a scalar loop.
+  // The emitted weight is not added per history: it is the sum of the source
+  // and census-in weights (exact in fixed point).
+  __shared__ unsigned long long s_bal[kBalCopies * kBalStride];
   __shared__ unsigned long long s_cnt[4];
   __shared__ uint32_t s_sobol[kSobolNibbleWords];
-  if (threadIdx.x < 2 * B_NFIELDS) s_bal[threadIdx.x] = 0ull;
+  for (int k = threadIdx.x; k < kBalCopies * kBalStride; k += blockDim.x) s_bal[k] = 0ull;
   if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0ull;
   sobol_nibbles_fill(a.sobol, s_sobol, threadIdx.x, blockDim.x);
   __syncthreads();
@@ -207,6 +225,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   double w0 = 0.0, acc_abs = 0.0, acc_sca = 0.0;
   bool from_census = false;
   unsigned int lane_seg = 0, lane_hist = 0, lane_alive = 0, lane_killed = 0;
+  unsigned long long* my_bal = s_bal + (lane % kBalCopies) * kBalStride;
 
   for (;;) {
     // static work assignment: lane t of T takes work items t, t + T, t + 2T, ...
@@ -349,26 +368,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         lane_alive++;
       }
       // fold the history's balance into the block (fixed point, exact)
-      long long hi, lo;
       const double wend = (double)w;
-      fix_split(w0, inv_W, hi, lo);
-      atomicAdd(&s_bal[2 * B_EMITTED], (unsigned long long)hi);
-      atomicAdd(&s_bal[2 * B_EMITTED + 1], (unsigned long long)lo);
-      const int fw = from_census ? B_CENSUS_IN_W : B_SOURCE_W;
-      atomicAdd(&s_bal[2 * fw], (unsigned long long)hi);
-      atomicAdd(&s_bal[2 * fw + 1], (unsigned long long)lo);
-      fix_split(acc_abs, inv_W, hi, lo);
-      atomicAdd(&s_bal[2 * B_ABSORBED], (unsigned long long)hi);
-      atomicAdd(&s_bal[2 * B_ABSORBED + 1], (unsigned long long)lo);
-      if (acc_sca != 0.0) {
-        fix_split(acc_sca, inv_W, hi, lo);
-        atomicAdd(&s_bal[2 * B_SCATTERED], (unsigned long long)hi);
-        atomicAdd(&s_bal[2 * B_SCATTERED + 1], (unsigned long long)lo);
-      }
-      const int ft = end == END_CENSUS ? B_CENSUS : (end == END_LEAK ? B_LEAKED : B_CUTOFF);
-      fix_split(wend, inv_W, hi, lo);
-      atomicAdd(&s_bal[2 * ft], (unsigned long long)hi);
-      atomicAdd(&s_bal[2 * ft + 1], (unsigned long long)lo);
+      bal_add(my_bal, from_census ? B_CENSUS_IN_W : B_SOURCE_W, w0, inv_W);
+      bal_add(my_bal, B_ABSORBED, acc_abs, inv_W);
+      if (acc_sca != 0.0) bal_add(my_bal, B_SCATTERED, acc_sca, inv_W);
+      bal_add(my_bal, end == END_CENSUS ? B_CENSUS : (end == END_LEAK ? B_LEAKED : B_CUTOFF),
+              wend, inv_W);
       have = false;
     }
   }
@@ -389,7 +394,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
   __syncthreads();
   if (threadIdx.x < 2 * B_NFIELDS) {
-    if (s_bal[threadIdx.x]) atomicAdd(&st->bal[threadIdx.x], s_bal[threadIdx.x]);
+    const int f = threadIdx.x >> 1, wd = threadIdx.x & 1;
+    unsigned long long v = 0ull;
+    for (int k = 0; k < kBalCopies; ++k) {
+      const unsigned long long* b = s_bal + k * kBalStride;
+      v += f == B_EMITTED ? b[2 * B_SOURCE_W + wd] + b[2 * B_CENSUS_IN_W + wd] : b[threadIdx.x];
+    }
+    if (v) atomicAdd(&st->bal[threadIdx.x], v);
   } else if (threadIdx.x >= 64 && threadIdx.x < 68) {
     const int k = threadIdx.x - 64;
     unsigned long long* dst = k == 0 ? &st->segments

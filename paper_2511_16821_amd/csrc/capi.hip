@@ -657,7 +657,7 @@ static DgArgs dg_args(slh_solver* s) {
   d.sig_e = s->sig_e;
   d.sig_s = s->sig_s;
   d.phi_post = s->phi_post;
-  d.phi_in = s->phi_c;
+  d.phi_c = s->phi_c;
   d.src = s->dg_src;
   d.psi = s->psi;
   d.mat_id = s->mat_id;
@@ -676,8 +676,7 @@ static slh_status enqueue_si(slh_solver* s, hipStream_t st, int n_it) {
   const DgArgs d = dg_args(s);
   for (int it = 0; it < n_it; ++it) {
     HIP_TRY(launch_dg_sweep(d, z.dg_table, st));
-    HIP_TRY(launch_dg_reduce(z.n_dir, 4 * z.n_cells, s->psi, s->phi_c, s->dg_part, s->n_part,
-                             s->st, s->si_tol, s->si_max, st));
+    HIP_TRY(launch_dg_reduce(d, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
   }
   HIP_TRY(hipMemcpyAsync(s->h_res, &s->st->si_done, kSiStateBytes, hipMemcpyDeviceToHost, st));
   return SLH_OK;
@@ -710,6 +709,7 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
                              hipMemcpyDeviceToHost, st));
       HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
       HIP_TRY(launch_si_begin(s->st, s->si_max, st));
+      HIP_TRY(launch_dg_source(dg_args(s), st));
       return enqueue_si(s, st, n_it);
     }
     case kB1: {

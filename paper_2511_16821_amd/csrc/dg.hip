@@ -48,11 +48,12 @@ __device__ __forceinline__ double recip(double a) {
   return r;
 }
 
-// Nodal source of the collided equation for the current iterate:
-// S = sigma_s/(4 pi) (phi_c + phi_post), once per source iteration.
+// Nodal source of the collided equation for the first iterate of a step:
+// S = sigma_s/(4 pi) (phi_c + phi_post); later iterates get theirs from the
+// flux reduction.
 __global__ void k_dg_source(long long n, const double* __restrict__ sig_s,
                             const double* __restrict__ phi_post,
-                            const double* __restrict__ phi_in, double* __restrict__ S,
+                            const double* __restrict__ phi_c, double* __restrict__ S,
                             const DevState* st) {
   if (st->si_done) return;
   const double inv4pi = 0.25 / M_PI;
@@ -60,7 +61,7 @@ __global__ void k_dg_source(long long n, const double* __restrict__ sig_s,
        i += (long long)gridDim.x * blockDim.x) {
     const double ssc = sig_s[i] * inv4pi;
     const double pp = phi_post[i];
-    const double4 f = reinterpret_cast<const double4*>(phi_in)[i];
+    const double4 f = reinterpret_cast<const double4*>(phi_c)[i];
     reinterpret_cast<double4*>(S)[i] = make_double4(ssc * (f.x + pp), ssc * (f.y + pp),
                                                     ssc * (f.z + pp), ssc * (f.w + pp));
   }
@@ -169,6 +170,7 @@ long long dg_chunks(int nx, int ny, int cw) {
 }
 
 constexpr int kDgDepth = 4;  // chunks in flight in the loader wave
+constexpr int kDgRow = 34;   // LDS stride of a table row (32 values)
 
 // One chunk in a loader lane: Q cells (source, key, position in the chunk
 // or -1).
@@ -191,11 +193,15 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
   const int m = blockIdx.x;
   const double a = g.dir[3 * m + 0], b = g.dir[3 * m + 1], wm = g.dir[3 * m + 2];
   const bool apos = a > 0.0, bpos = b > 0.0;
-  // LDS: slots S [2][CW] double4 | keys [2][CW] | coef [n_mat][32] (table) | faces
-  double4* slotS = reinterpret_cast<double4*>(smem);
+  // LDS: slots S [2][CW] as two double2 halves | keys [2][CW] | coef [n_mat][kDgRow] | faces
+  // (the source halves and the table rows are laid out so that a wave's
+  // accesses fall in distinct banks: 16-byte lane stride, rows offset by
+  // four banks)
+  double2* slotA = reinterpret_cast<double2*>(smem);  // S.x, S.y
+  double2* slotB = slotA + (size_t)2 * CW;             // S.z, S.w
   double* slotK = smem + (size_t)2 * CW * 4;
   double* coefL = slotK + (size_t)2 * CW;
-  const size_t n_coef = TABLE ? (size_t)g.n_mat * 32 : 0;
+  const size_t n_coef = TABLE ? (size_t)g.n_mat * kDgRow : 0;
   double* xf = coefL + n_coef;
   double* yf = xf + 2 * ny;
   const int n_diag = nx + ny - 1;
@@ -257,13 +263,14 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
       if (st.C[q] >= 0) {
         double4 v = make_double4(st.Sx[q], st.Sy[q], st.Sz[q], st.Sw[q]);
         if (TABLE) {
-          const double* c = coefL + (size_t)st.Ki[q] * 32;
+          const double* c = coefL + (size_t)st.Ki[q] * kDgRow;
           v = make_double4(c[0] * st.Sx[q] + c[1] * st.Sy[q] + c[2] * st.Sz[q] + c[3] * st.Sw[q],
                            c[4] * st.Sx[q] + c[5] * st.Sy[q] + c[6] * st.Sz[q] + c[7] * st.Sw[q],
                            c[8] * st.Sx[q] + c[9] * st.Sy[q] + c[10] * st.Sz[q] + c[11] * st.Sw[q],
                            c[12] * st.Sx[q] + c[13] * st.Sy[q] + c[14] * st.Sz[q] + c[15] * st.Sw[q]);
         }
-        slotS[slot * CW + st.C[q]] = v;
+        slotA[slot * CW + st.C[q]] = make_double2(v.x, v.y);
+        slotB[slot * CW + st.C[q]] = make_double2(v.z, v.w);
         slotK[slot * CW + st.C[q]] = TABLE ? (double)st.Ki[q] : st.Kd[q];
       }
   };
@@ -275,8 +282,9 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
   }
   for (int k = threadIdx.x; k < 2 * (nx + ny); k += blockDim.x) xf[k] = 0.0;
   if (TABLE) {
-    const double* src = g.coef + (size_t)m * n_coef;
-    for (size_t k = threadIdx.x; k < n_coef; k += blockDim.x) coefL[k] = src[k];
+    const double* src = g.coef + (size_t)m * g.n_mat * 32;
+    for (int k = threadIdx.x; k < g.n_mat * 32; k += blockDim.x)
+      coefL[(k >> 5) * kDgRow + (k & 31)] = src[k];
   }
   __syncthreads();  // faces zeroed, table staged
   if (loader) {
@@ -331,10 +339,11 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
       const int jp = cd - ip;
       c_i = apos ? ip : nx - 1 - ip;
       c_j = bpos ? jp : ny - 1 - jp;
-      const double4 S = slotS[slot * CW + t];
+      const double2 sa = slotA[slot * CW + t], sb = slotB[slot * CW + t];
+      const double4 S = make_double4(sa.x, sa.y, sb.x, sb.y);
       const double key = slotK[slot * CW + t];
       if (TABLE) {
-        const double* c = coefL + (size_t)(int)key * 32;
+        const double* c = coefL + (size_t)(int)key * kDgRow;
         r0[0] = S.x;  // B S, formed by the loader
         r0[1] = S.y;
         r0[2] = S.z;
@@ -416,16 +425,20 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
 }
 
 size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny) {
-  return sizeof(double) * ((size_t)2 * cw * 5 + (table ? (size_t)n_mat * 32 : 0) +
+  return sizeof(double) * ((size_t)2 * cw * 5 + (table ? (size_t)n_mat * kDgRow : 0) +
                            (size_t)2 * (nx + ny));
 }
 
-hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
+hipError_t launch_dg_source(const DgArgs& a, hipStream_t s) {
   const long long nc = (long long)a.nx * a.ny;
   long long b = (nc + 255) / 256;
   const int grid = (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
   hipLaunchKernelGGL(k_dg_source, dim3(grid), dim3(256), 0, s, nc, a.sig_s, a.phi_post,
-                     a.phi_in, a.src, a.st);
+                     (const double*)a.phi_c, a.src, (const DevState*)a.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   const size_t lds = dg_sweep_lds_bytes(table, a.cw, a.n_mat, a.nx, a.ny);
   const int n_sw = a.cw / 64;
   const int q = a.loader_q;  // cells per loader lane; n_sw / q loader waves
@@ -447,8 +460,10 @@ hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   return hipGetLastError();
 }
 
-// phi_new[k] = sum_m psi[m][k] in direction order; block partials of
-// |phi_new - phi_old|^2 and |phi_new|^2.
+// phi_new[k] = sum_m psi[m][k] in direction order, in place; the next
+// iterate's nodal source S = sigma_s/(4 pi) (phi_new + phi_post) (unused when
+// the iteration stops here); block partials of |phi_new - phi_old|^2 and
+// |phi_new|^2.
 constexpr int kRedBlock = 256;
 
 int dg_reduce_partials(long long n_nodes) {
@@ -456,13 +471,13 @@ int dg_reduce_partials(long long n_nodes) {
   return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_dg_reduce(int n_dir, long long n_nodes,
-                                                         const double* __restrict__ psi,
-                                                         double* __restrict__ phi,
-                                                         double* __restrict__ partials,
-                                                         const DevState* st) {
+__global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
+    int n_dir, long long n_nodes, const double* __restrict__ psi, double* __restrict__ phi,
+    const double* __restrict__ sig_s, const double* __restrict__ phi_post,
+    double* __restrict__ S, double* __restrict__ partials, const DevState* st) {
   if (st->si_done) return;
   __shared__ double s_d[kRedBlock], s_n[kRedBlock];
+  const double inv4pi = 0.25 / M_PI;
   double dsum = 0.0, nsum = 0.0;
   for (long long k = (long long)blockIdx.x * kRedBlock + threadIdx.x; k < n_nodes;
        k += (long long)gridDim.x * kRedBlock) {
@@ -479,6 +494,7 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(int n_dir, long long n_
     for (; m < n_dir; ++m) v += psi[(long long)m * n_nodes + k];
     const double d = v - phi[k];  // in place: the sweep read only S
     phi[k] = v;
+    S[k] = sig_s[k >> 2] * inv4pi * (v + phi_post[k >> 2]);
     dsum += d * d;
     nsum += v * v;
   }
@@ -535,13 +551,13 @@ __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int
   }
 }
 
-hipError_t launch_dg_reduce(int n_dir, long long n_nodes, const double* psi, double* phi,
-                            double* partials, int n_part, DevState* st, double si_tol,
+hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, double si_tol,
                             int si_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_dg_reduce, dim3(n_part), dim3(kRedBlock), 0, s, n_dir, n_nodes, psi, phi,
-                     partials, (const DevState*)st);
+  hipLaunchKernelGGL(k_dg_reduce, dim3(n_part), dim3(kRedBlock), 0, s, a.n_dir,
+                     4ll * a.nx * a.ny, (const double*)a.psi, a.phi_c, a.sig_s, a.phi_post,
+                     a.src, partials, (const DevState*)a.st);
   hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,
-                     st, si_tol, si_max);
+                     a.st, si_tol, si_max);
   return hipGetLastError();
 }
 

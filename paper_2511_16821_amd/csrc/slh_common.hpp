@@ -277,8 +277,8 @@ struct DgArgs {
   const double* sig_e;   // per cell
   const double* sig_s;   // per cell
   const double* phi_post;// per cell
-  const double* phi_in;  // nodal [cell][4] (previous iterate)
-  double* src;           // nodal [cell][4] scratch: sigma_s/(4 pi)(phi_in + phi_post)
+  double* phi_c;         // nodal [cell][4]: the collided iterate, updated in place
+  double* src;           // nodal [cell][4] scratch: sigma_s/(4 pi)(phi_c + phi_post)
   double* psi;           // [m][cell][4] (w_m psi_m)
   const double* dirmat;  // [m][32]: A0 then F (uniform mesh)
   // table mode: material of each cell and [m][material][32] = B then G
@@ -288,17 +288,19 @@ struct DgArgs {
   int cw;                // sweeping lanes per workgroup (multiple of 64, <= 256)
   int n_chunks;          // dg_chunks(nx, ny, cw)
   int loader_q;          // cells per loader lane (1..4, divides cw / 64)
-  const DevState* st;    // si_done: skip the iteration
+  DevState* st;          // si_done: skip the iteration; the reduction's decision
 };
 hipError_t launch_dg_tables(int n_dir, int n_mat, const double* dir, const double* sig_e_mat,
                             double hx, double hy, double* dirmat, double* coef, hipStream_t s);
 long long dg_chunks(int nx, int ny, int cw);
 size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny);
+// The first iterate's nodal source of a step, from phi_c and phi_post.
+hipError_t launch_dg_source(const DgArgs& a, hipStream_t s);
 hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s);
-// One reduction of a source iteration: phi (nodal) is replaced in place by
-// the direction sum of the planes; the residual decides st->si_done.
-hipError_t launch_dg_reduce(int n_dir, long long n_nodes, const double* psi, double* phi,
-                            double* partials, int n_part, DevState* st, double si_tol,
+// One reduction of a source iteration: phi_c is replaced in place by the
+// direction sum of the planes, the next iterate's source is formed, and the
+// residual decides st->si_done (n_part blocks, dg_reduce_partials).
+hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, double si_tol,
                             int si_max, hipStream_t s);
 hipError_t launch_si_begin(DevState* st, int si_max, hipStream_t s);
 int dg_reduce_partials(long long n_nodes);

@@ -259,7 +259,7 @@ static Sizes sizes_of(const slh_problem* p) {
   b += (size_t)(z.n_p > 0 ? z.n_p : 1) * (7 * rb + 4);  // source bank
   b += (size_t)z.n_cand * (bank + 1 + 8 + 8);  // staging, alive, flags, inclusive scan
   b += scan_tmp_elems(z.n_cand) * 8;
-  b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8;
+  b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8 + kCensusBlocks * 8;
   b += 64 * 1024;  // alignment of the ~30 device buffers
   z.bytes = b;
   return z;
@@ -347,6 +347,7 @@ struct slh_solver {
   unsigned long long *Tpre = nullptr, *Tpost = nullptr, *TR = nullptr;
   double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr;
   double *psi = nullptr, *dg_part = nullptr, *dirs = nullptr;
+  double* cmax = nullptr;  // per-block max |w| of the census compaction
   double* dirmat = nullptr;  // DG element data per direction
   int* mat_id = nullptr;     // DG table mode: material of each cell,
   double *sig_e_mat = nullptr, *coef = nullptr;  // its sigma_e, coefficients
@@ -489,6 +490,7 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->dg_src, double, 4 * nc);
   s->n_part = dg_reduce_partials(4 * nc);
   ALLOC(s->dg_part, double, 2 * s->n_part + 2);
+  ALLOC(s->cmax, double, kCensusBlocks);
   ALLOC(s->dirs, double, 3 * z.n_dir);
   s->bank_mem[0] = s->dalloc(s->bank_bytes(z.cap));
   s->bank_mem[1] = s->dalloc(s->bank_bytes(z.cap));
@@ -736,15 +738,16 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
         HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, p.seed, s->st, s->flags, st));
         HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
         HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, z.cap,
-                                             s->bank_at<float>(nb, z.cap), s->st, st));
+                                             s->bank_at<float>(nb, z.cap), s->st, s->cmax, st));
       } else {
         Bank<double> src = s->bank_at<double>(s->stage_mem, z.n_cand);
         HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, p.seed, s->st, s->flags, st));
         HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
         HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand, z.cap,
-                                              s->bank_at<double>(nb, z.cap), s->st, st));
+                                              s->bank_at<double>(nb, z.cap), s->st, s->cmax,
+                                              st));
       }
-      HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, z.cap, st));
+      HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, z.cap, s->cmax, st));
       HIP_TRY(launch_step_end(s->st, st));
       return SLH_OK;
     }

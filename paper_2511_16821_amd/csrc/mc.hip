@@ -437,8 +437,10 @@ int mc_pass_grid(bool fp32, int kind, long long max_work) {
 
 hipError_t launch_emit(const PassArgs& a, bool fp32, hipStream_t s) {
   if (a.n_src <= 0) return hipSuccess;
+  // at most 1024 blocks (about four particles per thread): each block first
+  // stages 24 KB of tables in LDS
   long long b = (a.n_src + 255) / 256;
-  const int grid = (int)(b < 8192 ? b : 8192);
+  const int grid = (int)(b < 1024 ? b : 1024);
   if (a.kind == 1) {
     if (fp32) hipLaunchKernelGGL((k_emit<float, 1>), dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_emit<double, 1>), dim3(grid), dim3(256), 0, s, a);

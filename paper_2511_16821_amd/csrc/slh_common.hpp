@@ -204,7 +204,6 @@ struct DevState {
   unsigned long long particles; // histories of the current pass
   unsigned long long killed;    // histories stopped by the segment guard
   unsigned long long bal[2 * B_NFIELDS];
-  unsigned long long maxabs_bits_out;  // max |w| of the bank being written (bits)
   unsigned long long step;      // time step being computed (point streams, history ids)
   // source iteration of the collided solve, kept on the device so that a
   // batch of iterations needs no host round trip: once si_done is set the
@@ -330,8 +329,12 @@ hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long l
 hipError_t launch_step_end(DevState* st, hipStream_t s);
 template <typename R>
 hipError_t launch_census_compact(const Bank<R>& src, const long long* incl, long long n,
-                                 long long cap, Bank<R> dst, DevState* st, hipStream_t s);
+                                 long long cap, Bank<R> dst, DevState* st, double* bmax,
+                                 hipStream_t s);
+// bmax: kCensusBlocks doubles, the compaction's per-block max |w|
 hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,
-                                long long cap, hipStream_t s);
+                                long long cap, const double* bmax, hipStream_t s);
+constexpr int kCensusBlocks = 2048;  // blocks of the compaction grid at most
+int census_compact_blocks(long long n);
 
 }  // namespace slh

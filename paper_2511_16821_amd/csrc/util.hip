@@ -68,26 +68,47 @@ hipError_t launch_pass_begin(DevState* st, const double* tree, double cdt, hipSt
   return hipGetLastError();
 }
 
-// phi = (sum of the private copies, an exact integer sum) * unit / (A dt)
-__global__ void k_tally_to_flux(const unsigned long long* __restrict__ T, long long n,
-                                int n_copies, long long copy_stride, const DevState* st,
-                                double inv_adt, double* __restrict__ phi) {
-  const double unit = st->unit_T;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    unsigned long long v = 0ull;
-    for (int c = 0; c < n_copies; ++c) v += T[c * copy_stride + kTallyStride * i];
-    phi[i] = (double)(long long)v * unit * inv_adt;
+// phi = (sum of the private copies, an exact integer sum) * unit / (A dt).
+// A block takes 64 cells; its four waves each sum every fourth copy (eight
+// loads in flight per lane) and the four partial sums meet in LDS.  Integer
+// addition makes the result independent of this split.
+constexpr int kT2fCells = 64;
+__global__ __launch_bounds__(256) void k_tally_to_flux(const unsigned long long* __restrict__ T,
+                                                       long long n, int n_copies,
+                                                       long long copy_stride,
+                                                       const DevState* st, double inv_adt,
+                                                       double* __restrict__ phi) {
+  __shared__ unsigned long long s_part[4][kT2fCells];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long i = (long long)blockIdx.x * kT2fCells + lane;
+  const long long ic = i < n ? i : n - 1;  // a real cell for every lane's loads
+  const unsigned long long* p = T + kTallyStride * ic;
+  unsigned long long v = 0ull;
+  int c = w;
+  for (; c + 28 < n_copies; c += 32) {
+    unsigned long long t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p[(long long)(c + 4 * u) * copy_stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; c < n_copies; c += 4) v += p[(long long)c * copy_stride];
+  s_part[w][lane] = v;
+  __syncthreads();
+  if (w == 0 && i < n) {
+    const unsigned long long s = s_part[0][lane] + s_part[1][lane] + s_part[2][lane] + s_part[3][lane];
+    phi[i] = (double)(long long)s * st->unit_T * inv_adt;
   }
 }
 
 hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, int n_copies,
                                 long long copy_stride, const DevState* st, double inv_adt,
                                 double* phi, hipStream_t s) {
-  long long b = (n + 255) / 256;
-  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_tally_to_flux, dim3(grid), dim3(256), 0, s, T, n, n_copies, copy_stride,
-                     st, inv_adt, phi);
+  if (n < 1) return hipSuccess;
+  const long long b = (n + kT2fCells - 1) / kT2fCells;
+  if (b > 0x7fffffffll) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tally_to_flux, dim3((unsigned)b), dim3(256), 0, s, T, n, n_copies,
+                     copy_stride, st, inv_adt, phi);
   return hipGetLastError();
 }
 
@@ -276,7 +297,6 @@ __global__ void k_thin_params(DevState* st, long long cap, long long margin) {
   if (threadIdx.x != 0) return;
   const unsigned long long cnt = st->alive;
   st->thin_overflow = 0;
-  st->maxabs_bits_out = 0ull;
   if (cnt <= (unsigned long long)cap) {
     st->thin_active = 0;
     st->thin_factor = 1.0;
@@ -361,11 +381,18 @@ hipError_t launch_si_begin(DevState* st, int si_max, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Blocks of the compaction grid; each leaves the max |w| it wrote in bmax.
+int census_compact_blocks(long long n) {
+  const long long b = (n + 255) / 256;
+  return (int)(b < kCensusBlocks ? (b < 1 ? 1 : b) : kCensusBlocks);
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_census_compact(Bank<R> src,
                                                         const long long* __restrict__ incl,
                                                         long long n, long long cap, Bank<R> dst,
-                                                        DevState* st) {
+                                                        const DevState* st,
+                                                        double* __restrict__ bmax) {
   __shared__ double s_mx[4];
   const R f = (R)st->thin_factor;
   double mx = 0.0;
@@ -388,41 +415,48 @@ __global__ __launch_bounds__(256) void k_census_compact(Bank<R> src,
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
   if (__lane_id() == 0) s_mx[threadIdx.x >> 6] = mx;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const double b = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
-    if (b > 0.0) atomicMax(&st->maxabs_bits_out, (unsigned long long)__double_as_longlong(b));
-  }
+  // one plain store per block (a device-scope atomic per block on one
+  // address serialises the blocks)
+  if (threadIdx.x == 0) bmax[blockIdx.x] = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
 }
 
 template <typename R>
 hipError_t launch_census_compact(const Bank<R>& src, const long long* incl, long long n,
-                                 long long cap, Bank<R> dst, DevState* st, hipStream_t s) {
-  long long b = (n + 255) / 256;
-  const int grid = (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
-  hipLaunchKernelGGL(k_census_compact<R>, dim3(grid), dim3(256), 0, s, src, incl, n, cap, dst,
-                     st);
+                                 long long cap, Bank<R> dst, DevState* st, double* bmax,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_census_compact<R>, dim3(census_compact_blocks(n)), dim3(256), 0, s, src,
+                     incl, n, cap, dst, (const DevState*)st, bmax);
   return hipGetLastError();
 }
 template hipError_t launch_census_compact<double>(const Bank<double>&, const long long*,
                                                   long long, long long, Bank<double>,
-                                                  DevState*, hipStream_t);
+                                                  DevState*, double*, hipStream_t);
 template hipError_t launch_census_compact<float>(const Bank<float>&, const long long*,
                                                  long long, long long, Bank<float>, DevState*,
-                                                 hipStream_t);
+                                                 double*, hipStream_t);
 
-__global__ void k_census_finish(DevState* st, const long long* incl, long long n,
-                                long long cap) {
+// Census count and max |w| of the new bank (max over the compaction blocks).
+__global__ __launch_bounds__(256) void k_census_finish(DevState* st, const long long* incl,
+                                                       long long n, long long cap,
+                                                       const double* bmax, int nb) {
+  __shared__ double s_mx[4];
+  double mx = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) mx = fmax(mx, bmax[b]);
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if (__lane_id() == 0) s_mx[threadIdx.x >> 6] = mx;
+  __syncthreads();
   if (threadIdx.x != 0) return;
   const long long k = n > 0 ? incl[n - 1] : 0;
   st->thin_overflow = k > cap ? 1 : 0;
   st->n_in = k > cap ? cap : k;
   st->n_kept = st->n_in;
-  st->maxabs_w = __longlong_as_double((long long)st->maxabs_bits_out);
+  st->maxabs_w = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
 }
 
 hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,
-                                long long cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_census_finish, dim3(1), dim3(1), 0, s, st, incl, n, cap);
+                                long long cap, const double* bmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_census_finish, dim3(1), dim3(256), 0, s, st, incl, n, cap, bmax,
+                     census_compact_blocks(n));
   return hipGetLastError();
 }
 

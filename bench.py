@@ -261,6 +261,7 @@ def large_resident(S, torch, args):
         x, y = a.get_flux(0), b.get_flux(0)
         last = float(np.linalg.norm(y - x) / max(np.linalg.norm(x), 1e-300))
         worst = max(worst, last)
+        log("large resident: step %d rel-L2 fp32 vs fp64 %.3e" % (a.get_stats()["step"], last))
     for name, sv, t in (("fp64", a, t64), ("fp32", b, t32)):
         st = sv.get_stats()
         seg = st["seg_mc_total"] + st["seg_remap_total"]
@@ -279,6 +280,7 @@ def large_resident(S, torch, args):
             sr = S.Solver(pr)
             sr.advance(steps, allow_not_converged=True)
             runs.append(sr.get_flux(0))
+            log("large resident: seed run %d done" % r)
             sr.destroy()
         runs = np.stack(runs)
         res["e_qmc"] = float(np.linalg.norm(runs.std(axis=0, ddof=1)) /

@@ -102,8 +102,13 @@ def lib():
         L.or_build_sum_tree.restype = C.POINTER(C.c_double)
         L.or_build_sum_tree.argtypes = [C.c_void_p, C.c_int64, C.c_double,
                                         C.POINTER(C.c_int64)]
-        L.or_tree_pick.restype = C.c_int64
-        L.or_tree_pick.argtypes = [C.POINTER(C.c_double), C.c_int64, C.c_double]
+        L.or_quantum.restype = C.c_double
+        L.or_quantum.argtypes = [C.c_double]
+        L.or_cell_counts.restype = C.c_int64
+        L.or_cell_counts.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_int64, C.c_void_p,
+                                     C.POINTER(C.c_double)]
+        L.or_history_id.restype = C.c_uint64
+        L.or_history_id.argtypes = [C.c_uint64, C.c_int64, C.c_uint32]
         L.or_dg_sweep.restype = C.c_int
         L.or_dg_sweep.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
@@ -296,7 +301,7 @@ def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
     out = None
     bout_p = None
     if want_census:
-        ncand = bank.n + n_src
+        ncand = bank.n + cell_counts(q_nodal, mesh.area * mesh.dt, n_src)[1]
         out = Bank(ncand)
         out.alive = np.zeros(ncand, dtype=np.uint8)
         bout = _BankOut(_p(out.x), _p(out.y), _p(out.ox), _p(out.oy), _p(out.w),
@@ -308,15 +313,19 @@ def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
     return Ta, Tb, dict(zip(BAL_NAMES, bal)), int(seg), out
 
 
-def tree_pick(q_nodal, adt, us):
-    """Cells picked by the majorant sum tree for each u in us."""
+def cell_counts(q_nodal, adt, n_src):
+    """Emission counts of a pass (see slh_oracle.c: or_cell_counts): per-cell
+    counts, their total and the weight quantum w_q."""
     q_nodal = np.ascontiguousarray(q_nodal, dtype=np.float64).reshape(-1)
-    L = C.c_int64(0)
-    t = lib().or_build_sum_tree(_p(q_nodal), q_nodal.size // 4, adt, C.byref(L))
-    out = np.array([lib().or_tree_pick(t, L.value, float(u)) for u in us], dtype=np.int64)
-    total = t[1]
-    C.CDLL(None).free(C.cast(t, C.c_void_p))
-    return out, total
+    n = q_nodal.size // 4
+    counts = np.zeros(max(n, 1), dtype=np.int64)
+    wq = C.c_double(0.0)
+    tot = lib().or_cell_counts(_p(q_nodal), n, adt, n_src, _p(counts), C.byref(wq))
+    return counts[:n], int(tot), wq.value
+
+
+def history_id(step: int, cell: int, l: int) -> int:
+    return int(lib().or_history_id(step, cell, l))
 
 
 def thin(cand: Bank, cap: int, thin_stream: int):

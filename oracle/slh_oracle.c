@@ -24,10 +24,13 @@
  *   - one optical depth tau = -ln u per flight, consumed at rate sigma_s across
  *     cells (Sec. 2.3, "sample next scatter at rate sigma_s").
  *   - the remap (step 3 of Sec. 2.2) emits from Q + sigma_s (phi_pre + phi_post
- *     + phi_c), with phi_c bilinear per cell from the DG solve: a cell is drawn
- *     from per-cell majorants (max corner |q| rounded up to a power of two)
- *     by descending a binary sum tree, the position uniformly, and the weight
- *     carries the sign and the ratio q(x,y)/majorant.
+ *     + phi_c), with phi_c bilinear per cell from the DG solve.  Emission (both
+ *     passes) is stratified by cell: cell i receives n_i = ceil(M_i / w_q)
+ *     particles, M_i = A dt (max corner |q_i| rounded up to a power of two),
+ *     w_q = sum(M) / N_p rounded down to five significant bits; each particle
+ *     is uniform in its cell with weight q(x,y) A dt / n_i, and draws its
+ *     points from its cell's own stream at its index within the cell, so
+ *     a change of one cell's count moves no other particle.
  *
  * Parity unpinned (no closed form or independent check exists): none of the
  * functions below; the tests pin each one (points, attenuation, Erlang split,
@@ -142,7 +145,7 @@ typedef struct {
 } or_bank_in;
 
 typedef struct {
-    /* census-out candidates at slot g (pass 2 only), size n_in + n_src */
+    /* census-out candidates at slot g (pass 2 only), size n_in + n_emit */
     double *x, *y, *ox, *oy, *w;
     int32_t *cell;
     uint64_t *hid;
@@ -192,24 +195,44 @@ double *or_build_sum_tree(const double *q_nodal, int64_t n, double adt, int64_t 
     return t;
 }
 
-/* Cell of u in (0,1): descend from the root with target u * total, going left
- * when the target is below the left child's mass (or the right child is
- * empty), otherwise subtracting the left mass and going right.  In exact
- * arithmetic this is the inverse CDF of the majorants in cell order. */
-int64_t or_tree_pick(const double *t, int64_t L, double u)
+/* v rounded down to five significant bits (v > 0): with m in [1/2, 1) and
+ * v = m 2^e, floor(32 m) / 32 * 2^e.  Every step is exact. */
+double or_quantum(double v)
 {
-    double target = u * t[1];
-    int64_t k = 1;
-    while (k < L) {
-        const double left = t[2 * k];
-        if (target < left || t[2 * k + 1] == 0.0) {
-            k = 2 * k;
-        } else {
-            target -= left;
-            k = 2 * k + 1;
-        }
+    if (!(v > 0.0)) return 0.0;
+    int e;
+    const double m = frexp(v, &e);
+    return ldexp(floor(m * 32.0) / 32.0, e);
+}
+
+/* Emission counts of one pass: w_q = quantum(sum(M) / n_src) with the sum
+ * taken by the majorant tree, n_i = ceil(M_i / w_q) (0 where M_i = 0).
+ * Writes counts[i] when counts is not NULL and *wq_out; returns the total,
+ * which lies in [n_src, n_src (1 + 1/16) + number of cells with M_i > 0). */
+int64_t or_cell_counts(const double *q_nodal, int64_t n, double adt, int64_t n_src,
+                       int64_t *counts, double *wq_out)
+{
+    int64_t L;
+    double *tree = or_build_sum_tree(q_nodal, n, adt, &L);
+    const double total = tree[1];
+    const double wq = (total > 0.0 && n_src > 0) ? or_quantum(total / (double)n_src) : 0.0;
+    int64_t sum = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double Mi = tree[L + i];
+        const int64_t c = (wq > 0.0 && Mi > 0.0) ? (int64_t)ceil(Mi / wq) : 0;
+        if (counts) counts[i] = c;
+        sum += c;
     }
-    return k - L;
+    free(tree);
+    if (wq_out) *wq_out = wq;
+    return sum;
+}
+
+/* Identity of source particle l of cell j born in time step `step` (a
+ * bijective mix of the packed (j, l) keyed by the step). */
+uint64_t or_history_id(uint64_t step, int64_t j, uint32_t l)
+{
+    return or_mix64((((uint64_t)j << 32) | (uint64_t)l) ^ or_mix64(step));
 }
 
 enum { EV_CENSUS = 0, EV_COLLIDE = 1, EV_XFACE = 2, EV_YFACE = 3 };
@@ -244,18 +267,17 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
     for (int64_t i = 0; i < ncell; ++i) { T_a[i] = 0.0; T_b[i] = 0.0; }
     for (int k = 0; k < OB_N; ++k) bal[k] = 0.0;
 
-    /* Majorant per cell M_i = A dt mbar_i, mbar_i = max_corner |q_i| rounded
-     * up to a power of two, summed in a binary tree over the cells. */
-    int64_t L;
-    double *tree = or_build_sum_tree(q_nodal, ncell, area * dt, &L);
-    const double total = tree[1];
-    const int64_t n_emit = (total > 0.0) ? n_src : 0;
-    const double w_ref = (n_emit > 0) ? total / (double)n_src : 0.0;
-    const double w_cut = w_cut_rel * w_ref;
+    /* Emission counts per cell (majorants M_i = A dt mbar_i, mbar_i = max
+     * corner |q_i| rounded up to a power of two): n_i = ceil(M_i / w_q). */
+    const double adt = area * dt;
+    int64_t *counts = (int64_t *)calloc((size_t)(ncell > 0 ? ncell : 1), sizeof(int64_t));
+    double wq = 0.0;
+    const int64_t n_emit = or_cell_counts(q_nodal, ncell, adt, n_src, counts, &wq);
+    const double w_cut = w_cut_rel * wq;
 
-    const uint64_t src_stream = or_stream_seed(seed, step, (uint32_t)kind, 0u, 0u);
     int64_t segments = 0;
     const int64_t n_tot = bin->n_in + n_emit;
+    int64_t cj = 0, cbase = 0;  /* cell of the current source particle, its first index */
 
     for (int64_t g = 0; g < n_tot; ++g) {
         double x, y, ox, oy, w, trel, tau = 0.0;
@@ -271,26 +293,29 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             ix = bin->cell[g] % nx; iy = bin->cell[g] / nx;
             hid = bin->hid[g];
             trel = 0.0;
-            stream = or_stream_seed(seed, step, (uint32_t)kind, 1u, hid >> 32);
-            pidx = (uint32_t)(hid & 0xffffffffu);
+            /* its own stream, keyed by its identity, point index 0 */
+            stream = or_stream_seed(seed, step, (uint32_t)kind, 1u, hid);
+            pidx = 0;
             dcur = 0;
             bal[OB_CENSUS_IN_W] += w;
         } else {
-            /* source particle: cell by inverse CDF of the majorant, uniform
+            /* source particle l of cell j (particles in cell order): uniform
              * position in the cell and time in the step, isotropic direction,
-             * signed weight q(x,y) * total / (N_p * max_corner|q|). */
+             * signed weight q(x,y) A dt / n_j; points of the cell's stream at
+             * index l. */
             const int64_t s = g - bin->n_in;
-            stream = src_stream;
-            pidx = (uint32_t)s;
-            hid = (step << 32) | (uint64_t)s;
-            const double u0 = or_u01(or_point_u32(P, stream, 0, pidx));
-            const int64_t ci = or_tree_pick(tree, L, u0);
+            while (s >= cbase + counts[cj]) { cbase += counts[cj]; cj += 1; }
+            const int64_t ci = cj;
+            const uint32_t l = (uint32_t)(s - cbase);
+            stream = or_stream_seed(seed, step, (uint32_t)kind, 0u, (uint64_t)ci);
+            pidx = l;
+            hid = or_history_id(step, ci, l);
             ix = (int)(ci % nx); iy = (int)(ci / nx);
-            const double u1 = or_u01(or_point_u32(P, stream, 1, pidx));
-            const double u2 = or_u01(or_point_u32(P, stream, 2, pidx));
-            const double u3 = or_u01(or_point_u32(P, stream, 3, pidx));
-            const double u4 = or_u01(or_point_u32(P, stream, 4, pidx));
-            const double u5 = or_u01(or_point_u32(P, stream, 5, pidx));
+            const double u1 = or_u01(or_point_u32(P, stream, 0, pidx));
+            const double u2 = or_u01(or_point_u32(P, stream, 1, pidx));
+            const double u3 = or_u01(or_point_u32(P, stream, 2, pidx));
+            const double u4 = or_u01(or_point_u32(P, stream, 3, pidx));
+            const double u5 = or_u01(or_point_u32(P, stream, 4, pidx));
             x = M->x_lo + hx * ((double)ix + u1);
             y = M->y_lo + hy * ((double)iy + u2);
             trel = u3 * dt;
@@ -299,8 +324,8 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             ox = st * cos(ph);
             oy = st * sin(ph);
             const double *qc = q_nodal + 4 * ci;
-            w = (total / (double)n_src) * (or_bilinear(qc, u1, u2) / or_pow2_ceil(or_maxabs4(qc)));
-            dcur = 6;
+            w = or_bilinear(qc, u1, u2) * (adt / (double)counts[ci]);
+            dcur = 5;
             bal[OB_SOURCE_W] += w;
         }
         bal[OB_EMITTED] += w;
@@ -379,7 +404,7 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             if (fabs(w) < w_cut) { bal[OB_CUTOFF] += w; break; }
         }
     }
-    free(tree);
+    free(counts);
     return segments;
 }
 

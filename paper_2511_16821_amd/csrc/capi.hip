@@ -123,6 +123,7 @@ static std::vector<double> product_quadrature(int order) {
 // ---------------------------------------------------------------------------
 struct Sizes {
   long long n_cells, n_p, cap, n_cand;
+  long long n_src_cap;  // source bank: at most n_p (1 + 1/16) + n_cells particles per pass
   int n_dir;
   int n_copies;  // private tally copies
   bool fp32;
@@ -229,8 +230,11 @@ static Sizes sizes_of(const slh_problem* p) {
   Sizes z;
   z.n_cells = (long long)p->nx * p->ny;
   z.n_p = p->n_particles;
+  // the stratified emission gives sum_i ceil(M_i / w_q) particles, w_q being
+  // sum(M) / n_p rounded down to five significant bits (within 1/16)
+  z.n_src_cap = z.n_p > 0 ? z.n_p + z.n_p / 16 + z.n_cells + 16 : 0;
   z.cap = p->census_cap > 0 ? p->census_cap : std::max<long long>(p->n_particles, 1);
-  z.n_cand = z.cap + z.n_p;
+  z.n_cand = z.cap + z.n_src_cap;
   z.n_dir = p->sn_order * p->sn_order;
   // private tally copies: up to 64 (eight per XCD), keeping each tally array
   // within 256 MB, and at least one per XCD where that fits in 1 GB
@@ -249,14 +253,14 @@ static Sizes sizes_of(const slh_problem* p) {
   size_t b = 0;
   const size_t nc = (size_t)z.n_cells;
   b += nc * (16 + 8 + 8 + 8 + 8);            // mat64, mat32, sig_s, sig_e, q
-  b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 2;  // nodal sources, trees
+  b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 4;  // nodal sources, trees
   b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
   b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
   b += (size_t)z.n_dir * nc * 32 + (size_t)z.n_dir * 256;  // direction planes, element data
   if (z.dg_table) b += nc * 4 + (size_t)z.n_mat * 8 + (size_t)z.n_dir * z.n_mat * 256;
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
   b += (size_t)z.cap * bank * 2;             // census banks
-  b += (size_t)(z.n_p > 0 ? z.n_p : 1) * (7 * rb + 4);  // source bank
+  b += (size_t)(z.n_src_cap > 0 ? z.n_src_cap : 1) * (7 * rb + 8);  // source bank
   b += (size_t)z.n_cand * (bank + 1 + 8 + 8);  // staging, alive, flags, inclusive scan
   b += scan_tmp_elems(z.n_cand) * 8;
   b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8 + kCensusBlocks * 8;
@@ -341,8 +345,8 @@ struct slh_solver {
   double2* mat64 = nullptr;
   float2* mat32 = nullptr;
   double *sig_s = nullptr, *sig_e = nullptr, *q = nullptr;
-  double *qn1 = nullptr, *tree1 = nullptr;
-  double *qnR = nullptr, *treeR = nullptr;
+  double *qn1 = nullptr, *tree1 = nullptr, *ctree1 = nullptr;  // majorant and count trees
+  double *qnR = nullptr, *treeR = nullptr, *ctreeR = nullptr;
   long long tree_L = 1;
   unsigned long long *Tpre = nullptr, *Tpost = nullptr, *TR = nullptr;
   double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr;
@@ -444,11 +448,12 @@ struct slh_solver {
     b.trel = p; p += n;
     b.tau = p; p += n;
     b.cell = (int32_t*)p;
+    b.lidx = (uint32_t*)(b.cell + n);
     return b;
   }
   size_t src_bytes(long long n) const {
     const size_t rb = z.fp32 ? 4 : 8;
-    return (size_t)(n > 0 ? n : 1) * (7 * rb + 4);
+    return (size_t)(n > 0 ? n : 1) * (7 * rb + 8);
   }
 };
 
@@ -471,8 +476,10 @@ static slh_status setup(slh_solver* s) {
   s->tree_L = tree_leaves(nc);
   ALLOC(s->qn1, double, 4 * nc);
   ALLOC(s->tree1, double, 2 * s->tree_L);
+  ALLOC(s->ctree1, double, 2 * s->tree_L);
   ALLOC(s->qnR, double, 4 * nc);
   ALLOC(s->treeR, double, 2 * s->tree_L);
+  ALLOC(s->ctreeR, double, 2 * s->tree_L);
   ALLOC(s->Tpre, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
   ALLOC(s->Tpost, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
   ALLOC(s->TR, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
@@ -495,7 +502,7 @@ static slh_status setup(slh_solver* s) {
   s->bank_mem[0] = s->dalloc(s->bank_bytes(z.cap));
   s->bank_mem[1] = s->dalloc(s->bank_bytes(z.cap));
   s->stage_mem = s->dalloc(s->bank_bytes(z.n_cand));
-  s->src_mem = s->dalloc(s->src_bytes(z.n_p));
+  s->src_mem = s->dalloc(s->src_bytes(z.n_src_cap));
   if (!s->bank_mem[0] || !s->bank_mem[1] || !s->stage_mem || !s->src_mem)
     return fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: census banks");
   ALLOC(s->alive, uint8_t, z.n_cand);
@@ -547,6 +554,7 @@ static slh_status setup(slh_solver* s) {
                            s->hy, s->dirmat, s->coef, st));
   HIP_TRY(hipMemcpyAsync(s->sobol, sobol_table_host(), 4 * 32 * 32, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_build_tree(s->qn1, nc, s->adt, s->tree1, st));
+  HIP_TRY(launch_count_tree(s->tree1, nc, z.n_p, s->ctree1, st));
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, st, s->st);
   HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
   HIP_TRY(launch_fill_f64(s->phi_pre, nc, 0.0, st));
@@ -574,6 +582,8 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.mat64 = s->mat64;
   a.mat32 = s->mat32;
   a.tree = kind == 1 ? s->tree1 : s->treeR;
+  a.ctree = kind == 1 ? s->ctree1 : s->ctreeR;
+  a.adt = s->adt;
   a.tree_L = s->tree_L;
   a.qn = kind == 1 ? s->qn1 : s->qnR;
   a.n_cells = s->z.n_cells;
@@ -590,11 +600,11 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   if (s->z.fp32) {
     a.in32 = s->bank_at<float>(bin, s->z.cap);
     a.out32 = s->bank_at<float>(s->stage_mem, s->z.n_cand);
-    a.src32 = s->src_at<float>(s->src_mem, s->z.n_p);
+    a.src32 = s->src_at<float>(s->src_mem, s->z.n_src_cap);
   } else {
     a.in64 = s->bank_at<double>(bin, s->z.cap);
     a.out64 = s->bank_at<double>(s->stage_mem, s->z.n_cand);
-    a.src64 = s->src_at<double>(s->src_mem, s->z.n_p);
+    a.src64 = s->src_at<double>(s->src_mem, s->z.n_src_cap);
   }
   a.alive = s->alive;
   a.out_src_base = s->z.cap;
@@ -718,6 +728,7 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
       HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c,
                                   s->qnR, st));
       HIP_TRY(launch_build_tree(s->qnR, nc, s->adt, s->treeR, st));
+      HIP_TRY(launch_count_tree(s->treeR, nc, z.n_p, s->ctreeR, st));
       HIP_TRY(launch_pass_begin(s->st, s->treeR, cdt, st));
       HIP_TRY(launch_fill_u64(s->TR, n_tally, 0ull, st));
       HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
@@ -796,8 +807,8 @@ static slh_status launch_part(slh_solver* s, int part, int n_it) {
 
 static slh_status run_step(slh_solver* s) {
   const Sizes& z = s->z;
-  const int grid1 = mc_pass_grid(z.fp32, 1, z.cap + z.n_p);
-  const int grid2 = mc_pass_grid(z.fp32, 2, z.cap + z.n_p);
+  const int grid1 = mc_pass_grid(z.fp32, 1, z.cap + z.n_src_cap);
+  const int grid2 = mc_pass_grid(z.fp32, 2, z.cap + z.n_src_cap);
   // iterations in the first batch: as many as the previous step took
   const int n_first =
       s->si_max > 0 ? std::max(1, std::min(s->si_max, s->si_it > 0 ? s->si_it : 4)) : 0;

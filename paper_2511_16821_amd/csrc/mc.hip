@@ -71,28 +71,35 @@ __device__ __forceinline__ double bilinear(const double* q, double a, double b) 
   return q[0] + a * (q[1] - q[0]) + b * (q[2] - q[0]) + a * b * (q[0] - q[1] - q[2] + q[3]);
 }
 
-// Cell of u: descend the majorant sum tree from the root with target
-// u * total, left while the target is below the left mass (or the right
-// subtree is empty), else subtract the left mass and go right.
+// Cell of source particle s: descend the count tree (leaf i = n_i, exact
+// integers) with target s + 1/2, going left while the target is below the
+// left count, else subtracting it and going right.  Particles are numbered
+// in cell order, so this finds the cell j with P_j <= s < P_j + n_j
+// (P_j = counts of the cells before j), and l = s - P_j.
 constexpr int kTreeTop = 1024;  // nodes [0, kTreeTop) of the tree are staged in LDS
 
-__device__ __forceinline__ long long tree_pick(const double* __restrict__ t,
+struct CellPick {
+  long long cell;
+  uint32_t l;
+};
+
+__device__ __forceinline__ CellPick count_pick(const double* __restrict__ t,
                                                const double* __restrict__ top, long long L,
-                                               double u) {
-  double target = u * top[1];
+                                               long long s) {
+  double target = (double)s + 0.5;
   long long k = 1;
   while (k < L) {
     const bool in_lds = 2 * k + 1 < kTreeTop;
     const double left = in_lds ? top[2 * k] : t[2 * k];
     const double right = in_lds ? top[2 * k + 1] : t[2 * k + 1];
-    if (target < left || right == 0.0) {
+    if (target < left || right == 0.0) {  // (an empty right subtree is never reached)
       k = 2 * k;
     } else {
       target -= left;
       k = 2 * k + 1;
     }
   }
-  return k - L;
+  return CellPick{k - L, (uint32_t)target};  // target = s - P_j + 1/2
 }
 
 // One fixed-point tally add.  XCD-local copies are only ever added to by
@@ -118,11 +125,12 @@ __device__ __forceinline__ void bal_add(unsigned long long* bal, int f, double v
 }
 
 // Emission of the pass's source particles, one thread each (Sec. 2.3: birth
-// proportional to q, isotropic direction, weight so that the weights sum to
-// the integral of q): the cell by descending the majorant sum tree with point
-// dimension 0, position (dims 1-2), birth time (dim 3), direction (dims 4-5),
-// signed weight q(x,y) sum(M) / (N_p mbar_cell), and the first optical depth
-// (dim 6) when the pass allows scatters.
+// proportional to q, isotropic direction, weights that sum to the integral of
+// q), stratified by cell: cell j emits n_j = ceil(M_j / w_q) particles,
+// numbered in cell order.  Particle l of cell j takes its points from the
+// cell's stream at index l: position (dims 0-1), birth time (dim 2),
+// direction (dims 3-4, sincospi), the first optical depth (dim 5) when the
+// pass allows scatters, and weight q(x,y) A dt / n_j.
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   __shared__ uint32_t s_sobol[kSobolNibbleWords];
@@ -131,38 +139,39 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   {
     const long long ntop = 2 * a.tree_L < kTreeTop ? 2 * a.tree_L : kTreeTop;
     for (int k = threadIdx.x; k < kTreeTop; k += blockDim.x)
-      s_top[k] = (k >= 1 && k < ntop) ? a.tree[k] : 0.0;
+      s_top[k] = (k >= 1 && k < ntop) ? a.ctree[k] : 0.0;
   }
   __syncthreads();
-  const double total = s_top[1];
-  if (!(total > 0.0)) return;
-  const double w_src = total / (double)a.n_src;
-  const uint64_t stream = stream_seed(a.seed, a.st->step, (uint32_t)KIND, 0u, 0ull);
+  const long long n_emit = (long long)s_top[1];
+  const uint64_t step = a.st->step;
   const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt;
   const SrcBank<R> b = Real<R>::src(a);
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < a.n_src;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n_emit;
        s += (long long)gridDim.x * blockDim.x) {
-    const uint32_t pidx = (uint32_t)s;
-    const double u0 = u01_f64(point_u32n(s_sobol, a.points, stream, 0u, pidx));
-    const long long ci = tree_pick(a.tree, s_top, a.tree_L, u0);
-    const R u1 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 1u, pidx));
-    const R u2 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 2u, pidx));
-    const R u3 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 3u, pidx));
-    const R u4 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 4u, pidx));
-    const R u5 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, pidx));
+    const CellPick pk = count_pick(a.ctree, s_top, a.tree_L, s);
+    const long long ci = pk.cell;
+    const uint32_t l = pk.l;
+    const uint64_t stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, (uint64_t)ci);
+    const R u1 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 0u, l));
+    const R u2 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 1u, l));
+    const R u3 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 2u, l));
+    const R u4 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 3u, l));
+    const R u5 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 4u, l));
     const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
     R sp, cp;
     Real<R>::scpi((R)2 * u5, &sp, &cp);
     const double* q = a.qn + 4 * ci;
+    const double nj = a.ctree[a.tree_L + ci];
     b.px[s] = hx * u1;
     b.py[s] = hy * u2;
     b.ox[s] = sn * cp;
     b.oy[s] = sn * sp;
-    b.w[s] = (R)(w_src * (bilinear(q, (double)u1, (double)u2) / pow2_ceil(maxabs4(q))));
+    b.w[s] = (R)(bilinear(q, (double)u1, (double)u2) * (a.adt / nj));
     b.trel[s] = u3 * dt;
-    b.tau[s] = a.n_lim > 0 ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 6u, pidx)))
+    b.tau[s] = a.n_lim > 0 ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, l)))
                            : (R)0;
     b.cell[s] = (int32_t)ci;
+    b.lidx[s] = l;
   }
 }
 
@@ -185,14 +194,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int lane = __lane_id();
   const long long n_in = st->n_in;
   const double total = a.tree[1];
-  const long long n_emit = (total > 0.0) ? a.n_src : 0;
+  const long long n_emit = (long long)a.ctree[1];
   const unsigned long long n_tot = (unsigned long long)(n_in + n_emit);
-  const double w_src = n_emit > 0 ? total / (double)a.n_src : 0.0;
-  const R w_cut = (R)(a.w_cut_rel * w_src);
+  const double w_q = (total > 0.0 && a.n_src > 0) ? quantum5(total / (double)a.n_src) : 0.0;
+  const R w_cut = (R)(a.w_cut_rel * w_q);
   const double inv_T = st->inv_T;
   const double inv_W = st->inv_W;
   const uint64_t step = st->step;
-  const uint64_t src_stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, 0ull);
   const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt, c = (R)a.c;
   const R INF = Real<R>::inf();
   const Bank<R> bin = Real<R>::in(a);
@@ -246,24 +254,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         ix = cell % a.nx; iy = cell / a.nx;
         hid = bin.hid[g];
         trel = (R)0;
-        stream = (KIND == 1 && n_lim > 0)
-                     ? stream_seed(a.seed, step, (uint32_t)KIND, 1u, hid >> 32) : 0ull;
-        pidx = (uint32_t)(hid & 0xffffffffull);
+        // its own stream, keyed by its identity, at point index 0
+        stream = (KIND == 1 && n_lim > 0) ? stream_seed(a.seed, step, (uint32_t)KIND, 1u, hid)
+                                          : 0ull;
+        pidx = 0;
         dcur = 0;
       } else {
         // source particle, emitted by k_emit
         from_census = false;
         const long long s = g - n_in;
         const SrcBank<R> sb = Real<R>::src(a);
-        stream = src_stream;
-        pidx = (uint32_t)s;
-        hid = (step << 32) | (uint64_t)s;
         px = sb.px[s]; py = sb.py[s]; ox = sb.ox[s]; oy = sb.oy[s]; w = sb.w[s];
         trel = sb.trel[s];
         tau = sb.tau[s];
         const int cell = sb.cell[s];
+        pidx = sb.lidx[s];
         ix = cell % a.nx; iy = cell / a.nx;
-        dcur = 7;  // dims 0-5 emission, 6 the first optical depth
+        // the birth cell's stream at the particle's index in the cell
+        stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, (uint64_t)cell);
+        hid = history_id(step, cell, pidx);
+        dcur = 6;  // dims 0-4 emission, 5 the first optical depth
       }
       iox = ox != (R)0 ? (R)1 / ox : (R)0;
       ioy = oy != (R)0 ? (R)1 / oy : (R)0;

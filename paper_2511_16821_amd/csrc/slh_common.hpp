@@ -98,6 +98,21 @@ __host__ __device__ __forceinline__ double pow2_ceil(double v) {
   return (m == 0.5) ? v : ldexp(1.0, e);
 }
 
+// v rounded down to five significant bits (v > 0): the particle-weight
+// quantum of the stratified emission, w_q = quantum(sum(M) / N_p).  Exact.
+__host__ __device__ __forceinline__ double quantum5(double v) {
+  if (!(v > 0.0)) return 0.0;
+  int e;
+  const double m = frexp(v, &e);
+  return ldexp(floor(m * 32.0) / 32.0, e);
+}
+
+// Identity of source particle l of cell j born in time step `step`: a
+// bijective mix of the packed (j, l), keyed by the step.
+__host__ __device__ __forceinline__ uint64_t history_id(uint64_t step, long long j, uint32_t l) {
+  return mix64((((uint64_t)j << 32) | (uint64_t)l) ^ mix64(step));
+}
+
 __device__ __forceinline__ double u01_f64(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
 __device__ __forceinline__ float u01_f32(uint32_t x) {
   return ((float)(x >> 9) + 0.5f) * 0x1p-23f;
@@ -167,7 +182,8 @@ template <typename R> struct Bank {
 
 // Source particles of one pass, written by the emission kernel: position in
 // the cell, direction, weight, birth time within the step, first optical
-// depth (scatter-limited pass with N_s > 0 only) and cell.
+// depth (scatter-limited pass with N_s > 0 only), cell and index within the
+// cell (the particle's point index in its cell's stream).
 template <typename R> struct SrcBank {
   R* px;
   R* py;
@@ -177,6 +193,7 @@ template <typename R> struct SrcBank {
   R* trel;
   R* tau;
   int32_t* cell;
+  uint32_t* lidx;
 };
 
 // Balance fields, each a two-word fixed-point sum.
@@ -220,12 +237,15 @@ struct PassArgs {
   double hx, hy, dt, c;
   const double2* mat64;  // (sigma_s, sigma_a) per cell
   const float2* mat32;
-  // emission
-  const double* tree;    // binary sum tree of the cell majorants (heap order)
+  // emission, stratified by cell: cell i emits n_i = ceil(M_i / w_q)
+  // particles, w_q = quantum5(sum(M) / n_src)
+  const double* tree;    // binary sum tree of the cell majorants M_i (heap order)
+  const double* ctree;   // the same tree over the counts n_i (root: particles)
   long long tree_L;      // leaves start at tree_L (power of two >= n_cells)
   const double* qn;      // nodal source [cell][4]
   long long n_cells;
-  long long n_src;
+  long long n_src;       // N_p, the requested particles per pass
+  double adt;            // cell area times dt
   uint64_t seed;         // the time step is read from st->step
   int kind;              // 1: scatter-limited leg, 2: scatter-free remap
   int n_lim;             // scatter limit of the pass (0 for kind 2)
@@ -319,6 +339,10 @@ hipError_t launch_remap_source(long long n, const double* q, const double* sig_s
 long long tree_leaves(long long n_cells);
 hipError_t launch_build_tree(const double* qn, long long n_cells, double adt, double* tree,
                              hipStream_t s);
+// Count tree of the stratified emission from a built majorant tree:
+// leaf i = ceil(M_i / w_q), w_q = quantum5(root / n_src); root = particles.
+hipError_t launch_count_tree(const double* tree, long long n_cells, long long n_src,
+                             double* ctree, hipStream_t s);
 size_t scan_tmp_elems(long long n);
 hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
                               long long* tmp, hipStream_t s);

@@ -191,19 +191,46 @@ __global__ __launch_bounds__(512) void k_tree_up(double* t, long long W) {
   }
 }
 
-hipError_t launch_build_tree(const double* qn, long long n_cells, double adt, double* tree,
-                             hipStream_t s) {
-  const long long L = tree_leaves(n_cells);
-  long long b = (L + 255) / 256;
-  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_tree_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, L, adt, tree);
+// All levels above the leaves, in launches of ten levels.
+static void tree_up_all(double* tree, long long L, hipStream_t s) {
   long long W = L;
   while (W > 1) {
     const long long C = W < kTreeChunk ? W : kTreeChunk;
     hipLaunchKernelGGL(k_tree_up, dim3((unsigned)(W / C)), dim3(512), 0, s, tree, W);
     W /= C;
   }
+}
+
+hipError_t launch_build_tree(const double* qn, long long n_cells, double adt, double* tree,
+                             hipStream_t s) {
+  const long long L = tree_leaves(n_cells);
+  long long b = (L + 255) / 256;
+  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+  hipLaunchKernelGGL(k_tree_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, L, adt, tree);
+  tree_up_all(tree, L, s);
   return hipGetLastError();  // L == 1: the single leaf is the root
+}
+
+__global__ void k_count_leaves(const double* __restrict__ tree, long long n, long long L,
+                               long long n_src, double* __restrict__ ct) {
+  const double total = tree[1];
+  const double wq = (total > 0.0 && n_src > 0) ? quantum5(total / (double)n_src) : 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < L;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double Mi = i < n ? tree[L + i] : 0.0;
+    ct[L + i] = (wq > 0.0 && Mi > 0.0) ? ceil(Mi / wq) : 0.0;
+  }
+}
+
+hipError_t launch_count_tree(const double* tree, long long n_cells, long long n_src,
+                             double* ctree, hipStream_t s) {
+  const long long L = tree_leaves(n_cells);
+  long long b = (L + 255) / 256;
+  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+  hipLaunchKernelGGL(k_count_leaves, dim3(grid), dim3(256), 0, s, tree, n_cells, L, n_src,
+                     ctree);
+  tree_up_all(ctree, L, s);  // integer-valued sums below 2^53: exact
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

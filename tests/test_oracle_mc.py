@@ -231,16 +231,16 @@ def test_qmc_vs_mc_convergence_slopes(oracle):
     assert slopes[0] < -0.75, slopes
 
 
-def _pow2ceil(v):
-    return 0.0 if v == 0 else 2.0 ** math.ceil(math.log2(v))
-
-
 def test_remap_sampler_weights(oracle):
-    """Remap emission (step 3 of Sec. 2.2): cell drawn from majorants
-    M_i = A dt mbar_i (mbar = max corner |q| rounded up to a power of two),
-    uniform position, signed weight q(x,y) sum(M) / (N_p mbar_i).  Cell-constant
-    q: each weight is sum(M)/N_p q_i/mbar_i and the expected total is int q.
+    """Remap emission (step 3 of Sec. 2.2), stratified by cell: cell i gets
+    n_i = ceil(M_i / w_q) particles (M_i = A dt mbar_i, mbar = max corner |q|
+    rounded up to a power of two, w_q = sum(M)/N_p rounded down to five
+    significant bits), uniform in the cell, weight q(x,y) A dt / n_i.
+    Cell-constant q: in every cell the weights add up to the cell's integral
+    of q exactly (up to rounding), the particles of cell i are its indices
+    0..n_i-1, and the total lies in [N_p, N_p (1 + 1/16) + cells].
     Bilinear signed q: the weights integrate q."""
+    from fractions import Fraction
     nx, ny, dt = 3, 2, 0.5
     # particle speed ~0: every particle is still in its birth cell at census
     m = _mesh(oracle, nx, ny, (0, 1.5, 0, 1.0), 0.0, 0.0, dt, c=1e-12)
@@ -249,17 +249,30 @@ def test_remap_sampler_weights(oracle):
     qv = np.array([0.0, 2.0, 1.0, 0.5, 0.0, 3.0])
     qc = np.repeat(qv, 4)
     n_p = 1000
-    _, _, bal, _, cand = oracle.mc_pass(m, pts, 2, 0, qc, n_p, oracle.Bank(0), 3, 0, 0.0, True)
-    mbar = np.array([_pow2ceil(v) for v in qv])
-    sumM = area * dt * mbar.sum()
+    step = 5
+    _, _, bal, _, cand = oracle.mc_pass(m, pts, 2, 0, qc, n_p, oracle.Bank(0), 3, step, 0.0,
+                                        True)
+    counts, total, wq = oracle.cell_counts(qc, area * dt, n_p)
+    # exact rational check of the counts
+    mbar = [0, 2, 1, Fraction(1, 2), 0, 4]
+    adt = Fraction(area) * Fraction(dt)
+    v = adt * sum(mbar) / n_p
+    e = math.floor(math.log2(v))  # v = m 2^(e+1), m in [1/2, 1)
+    m_ = v / Fraction(2) ** (e + 1)
+    wq_exact = Fraction(math.floor(m_ * 32), 32) * Fraction(2) ** (e + 1)
+    assert Fraction(wq) == wq_exact
+    want = [0 if mb == 0 else -(-(adt * mb) // wq_exact) for mb in mbar]
+    assert counts.tolist() == want
+    assert n_p <= total <= n_p * 17 // 16 + nx * ny
     alive = cand.alive.astype(bool)
-    w = cand.w[alive]
-    cells = cand.cell[alive]
-    np.testing.assert_allclose(w, sumM / n_p * qv[cells] / mbar[cells], rtol=1e-15)
+    assert alive.sum() == total
+    w, cells, hid = cand.w[alive], cand.cell[alive], cand.hid[alive]
+    np.testing.assert_allclose(np.bincount(cells, weights=w, minlength=nx * ny),
+                               qv * area * dt, rtol=1e-13)
     assert np.all(qv[cells] > 0)
-    # cell frequencies follow the majorants (QMC: within a few counts)
-    counts = np.bincount(cells, minlength=nx * ny)
-    np.testing.assert_allclose(counts, n_p * mbar / mbar.sum(), atol=3)
+    for i in range(nx * ny):
+        ids = {oracle.history_id(step, i, l) for l in range(counts[i])}
+        assert set(hid[cells == i].tolist()) == ids
     # bilinear signed source: E[sum w] = integral of q = sum A dt mean(corners)
     rng = np.random.default_rng(9)
     qb = rng.uniform(-1.0, 2.0, size=4 * nx * ny)
@@ -274,22 +287,28 @@ def test_remap_sampler_weights(oracle):
     assert abs(tot.mean() - integral) < 1e-3 * abs(integral)
 
 
-def test_sum_tree_pick_is_inverse_cdf(oracle):
-    """The sum-tree descent is the inverse CDF of the majorants in cell order
-    (first i with u * total < cumsum_i); with majorants that are small powers
-    of two every sum is exact, so it must agree with numpy's searchsorted."""
+def test_weight_quantum_and_counts(oracle):
+    """w_q keeps five significant bits of sum(M)/N_p, rounding down, so
+    v (1 - 1/16) < w_q <= v; the counts are ceil(M_i / w_q) (checked in exact
+    rational arithmetic) and their total is at least N_p."""
+    from fractions import Fraction
     rng = np.random.default_rng(6)
-    for n in (1, 2, 7, 64, 100, 1000):
-        qv = rng.choice([0.0, 0.25, 0.5, 1.0, 2.0, 4.0], size=n)
+    for _ in range(200):
+        v = float(rng.uniform(0.1, 10.0) * 2.0 ** rng.integers(-40, 40))
+        q = oracle.lib().or_quantum(v)
+        assert v * (1 - 1 / 16) < q <= v
+        mant, ex = math.frexp(q)
+        assert (mant * 32).is_integer()
+    for n in (1, 2, 7, 64, 100):
+        qv = rng.choice([0.0, 0.3, 0.5, 1.0, 2.5, 4.0], size=n)
         if qv.sum() == 0:
             qv[0] = 1.0
-        us = (rng.integers(0, 2 ** 32, size=2000) + 0.5) / 2 ** 32
-        got, total = oracle.tree_pick(np.repeat(qv, 4), 1.0, us)
-        cdf = np.cumsum(qv)
-        assert total == cdf[-1]
-        want = np.searchsorted(cdf, us * total, side="right")
-        assert np.array_equal(got, want), n
-        assert np.all(qv[got] > 0)
+        n_p = int(rng.integers(1, 5000))
+        counts, total, wq = oracle.cell_counts(np.repeat(qv, 4), 0.37, n_p)
+        M = [Fraction(0.37) * Fraction(oracle.lib().or_pow2_ceil(float(x))) for x in qv]
+        want = [0 if Mi == 0 else -(-Mi // Fraction(wq)) for Mi in M]
+        assert counts.tolist() == want, n
+        assert total == sum(want) >= n_p
 
 
 def test_balance_closes_every_pass(oracle):
@@ -415,7 +434,7 @@ def test_emitted_and_scattered_directions_are_isotropic(oracle, kind, n_s, ss):
     _, _, bal, _, cand = oracle.mc_pass(m, pts, kind, n_s, q, n_p, oracle.Bank(0), 8,
                                         0, 0.0, True)
     alive = cand.alive.astype(bool)
-    assert alive.sum() == n_p
+    assert alive.sum() == oracle.cell_counts(q, 400.0, n_p)[1]
     ox, oy = cand.ox[alive], cand.oy[alive]
     tol = 4.0 / math.sqrt(n_p)
     assert abs(ox.mean()) < tol and abs(oy.mean()) < tol and abs((ox * oy).mean()) < tol

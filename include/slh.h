@@ -92,7 +92,12 @@ typedef struct {
     int32_t n_s;                   /* scatter limit N_s >= 0; -1: unlimited
                                       (the first leg is then plain MC, the
                                       collided solve has no source)        */
-    int64_t n_particles;           /* source particles per MC pass, 0..2^32-1 */
+    int64_t n_particles;           /* N_p, 0..2^31: each MC pass emits          */
+                                   /* sum_i ceil(M_i / w_q) source particles,   */
+                                   /* between N_p and N_p (1 + 1/16) + cells    */
+                                   /* with a source (emission stratified by     */
+                                   /* cell, w_q = sum(M) / N_p rounded down to  */
+                                   /* five significant bits; Sec. 2.3)          */
     int64_t census_cap;            /* census bank size; 0 -> n_particles     */
     int32_t sn_order;              /* even N >= 2: N^2 product directions    */
     double time_closure;           /* tau in sigma_t + tau/(c dt); 0 -> 2    */

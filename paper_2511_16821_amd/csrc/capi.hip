@@ -200,8 +200,8 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
   if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(SLH_E_INVALID_ARG, "dt must be > 0");
   if (p->n_s < -1 || p->n_s > 1000000)
     return fail(SLH_E_INVALID_ARG, "n_s must be -1 (unlimited) or in [0, 1e6]");
-  if (p->n_particles < 0 || p->n_particles > 0xffffffffll)
-    return fail(SLH_E_INVALID_ARG, "n_particles must be in [0, 2^32)");
+  if (p->n_particles < 0 || p->n_particles > (1ll << 31))  // a cell's index l stays 32-bit
+    return fail(SLH_E_INVALID_ARG, "n_particles must be in [0, 2^31]");
   if (p->census_cap < 0 || p->census_cap > (1ll << 34))
     return fail(SLH_E_INVALID_ARG, "census_cap out of range");
   if (p->sn_order < 2 || p->sn_order % 2 || p->sn_order > 64)

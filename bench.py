@@ -295,7 +295,8 @@ def protocol(S, torch, args):
     each scatter limit N_s (-1 = unlimited, the plain MC reference case), the
     relative L2 error of phi_R after the last step against a same-method
     reference at 2^22 particles, for scrambled-Sobol' points (RMS over Owen
-    seeds) and pseudo-random points (RMS over seeds), at particle counts 2^10
+    seeds), pseudo-random points (RMS over seeds) and the paper's Halton points
+    (RMS over random shifts), at particle counts 2^10
     .. 2^18; the fitted slopes alpha (error ~ N^-alpha), the source-iteration
     count of the collided solve, and the time per step."""
     import numpy as np
@@ -322,7 +323,7 @@ def protocol(S, torch, args):
         ref, _, _ = run(2 ** 22, 0, 7777)
         nref = max(np.linalg.norm(ref), 1e-300)
         row = {"n_s": ns, "particles": ladder, "steps": args.protocol_steps}
-        for name, mode in (("qmc", 0), ("mc", 1)):
+        for name, mode in (("qmc", 0), ("mc", 1), ("halton", 2)):
             errs, times, iters = [], [], []
             for n in ladder:
                 e2 = 0.0

@@ -69,7 +69,10 @@ typedef enum { SLH_FP64 = 0, SLH_FP32_TRACK = 1 } slh_precision;
 
 /* Points fed to the inverse-CDF maps (Sec. 2.4): scrambled Sobol' (QMC) or a
  * counter-based pseudo-random hash (plain MC, for comparisons). */
-typedef enum { SLH_SOBOL_OWEN = 0, SLH_PRNG = 1 } slh_points;
+/* Point sets (Sec. 2.4): Owen-scrambled Sobol', pseudo-random (plain MC),
+ * or Halton (the paper's set) randomised by a shift modulo 1 per stream and
+ * dimension.  Dimensions past 32 are pseudo-random in every mode. */
+typedef enum { SLH_SOBOL_OWEN = 0, SLH_PRNG = 1, SLH_HALTON = 2 } slh_points;
 
 /* Which flux slh_get_flux returns (all FP64). */
 typedef enum {

@@ -102,6 +102,8 @@ def lib():
         L.or_build_sum_tree.restype = C.POINTER(C.c_double)
         L.or_build_sum_tree.argtypes = [C.c_void_p, C.c_int64, C.c_double,
                                         C.POINTER(C.c_int64)]
+        L.or_halton_u32.restype = C.c_uint32
+        L.or_halton_u32.argtypes = [C.c_uint32, C.c_uint32]
         L.or_quantum.restype = C.c_double
         L.or_quantum.argtypes = [C.c_double]
         L.or_cell_counts.restype = C.c_int64

@@ -101,8 +101,32 @@ uint32_t or_sobol_word(const uint32_t *V, uint32_t dim, uint32_t index)
     return x;
 }
 
+/* Halton sequence (Halton 1960; the point set the paper uses, Sec. 2.4):
+ * coordinate d of point i is the radical inverse of i in the d-th prime base
+ * b, phi_b(i) = sum_k a_k b^-(k+1) for i = sum_k a_k b^k.  Returned as the
+ * 32-bit word floor(phi_b(i) 2^32): with R the digit-reversed integer and
+ * D = b^K (K digits), phi_b(i) = R / D, and the floor is taken in two exact
+ * integer divisions (R < D < 2^40). */
+enum { OR_HALTON_DIMS = 32 };
+static const uint32_t or_primes[OR_HALTON_DIMS] = {
+    2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53,
+    59, 61, 67, 71, 73, 79, 83, 89, 97, 101, 103, 107, 109, 113, 127, 131};
+
+uint32_t or_halton_u32(uint32_t dim, uint32_t index)
+{
+    const uint64_t b = or_primes[dim];
+    uint64_t R = 0, D = 1;
+    for (uint32_t i = index; i > 0; i /= (uint32_t)b) {
+        R = R * b + (uint64_t)(i % (uint32_t)b);
+        D *= b;
+    }
+    const uint64_t q1 = (R << 24) / D, r1 = (R << 24) % D;
+    return (uint32_t)((q1 << 8) + ((r1 << 8) / D));
+}
+
 typedef struct {
-    int mode;             /* 0 = scrambled Sobol', 1 = pseudo-random */
+    int mode;             /* 0 = scrambled Sobol', 1 = pseudo-random,  */
+                          /* 2 = randomly shifted Halton               */
     int sobol_dims;       /* dimensions available in V                 */
     const uint32_t *V;    /* direction numbers, [sobol_dims][32]       */
 } or_points;
@@ -113,6 +137,12 @@ uint32_t or_point_u32(const or_points *P, uint64_t stream, uint32_t dim,
     if (P->mode == 0 && (int)dim < P->sobol_dims) {
         uint32_t s = (uint32_t)(or_mix64(stream + dim) >> 32);
         return or_nested_scramble(or_sobol_word(P->V, dim, index), s);
+    }
+    if (P->mode == 2 && dim < OR_HALTON_DIMS) {
+        /* randomised by a shift modulo 1 (Cranley & Patterson 1976) per
+         * (stream, dimension) */
+        uint32_t s = (uint32_t)(or_mix64(stream + dim) >> 32);
+        return or_halton_u32(dim, index) + s;
     }
     uint64_t ctr = ((uint64_t)dim << 32) | (uint64_t)index;
     return (uint32_t)(or_mix64(stream ^ or_mix64(ctr)) >> 32);

@@ -212,8 +212,8 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
   if (p->si_max_iter < 0) return fail(SLH_E_INVALID_ARG, "si_max_iter < 0");
   if (!(p->w_cut_rel >= 0.0) || !isfinite(p->w_cut_rel))
     return fail(SLH_E_INVALID_ARG, "w_cut_rel must be >= 0");
-  if (p->points != SLH_SOBOL_OWEN && p->points != SLH_PRNG)
-    return fail(SLH_E_INVALID_ARG, "points must be SLH_SOBOL_OWEN or SLH_PRNG");
+  if (p->points != SLH_SOBOL_OWEN && p->points != SLH_PRNG && p->points != SLH_HALTON)
+    return fail(SLH_E_INVALID_ARG, "points must be SLH_SOBOL_OWEN, SLH_PRNG or SLH_HALTON");
   if (p->precision != SLH_FP64 && p->precision != SLH_FP32_TRACK)
     return fail(SLH_E_INVALID_ARG, "precision must be SLH_FP64 or SLH_FP32_TRACK");
   if (check_fields) {
@@ -1151,7 +1151,7 @@ extern "C" slh_status slh_qmc_points(uint64_t seed, uint64_t step, uint32_t pass
                                      uint32_t n_dims, uint32_t index0, uint32_t n, int32_t points,
                                      uint32_t* dev_out, void* hip_stream) {
   if (!dev_out && n && n_dims) return fail(SLH_E_INVALID_ARG, "dev_out is NULL");
-  if (points != SLH_SOBOL_OWEN && points != SLH_PRNG)
+  if (points != SLH_SOBOL_OWEN && points != SLH_PRNG && points != SLH_HALTON)
     return fail(SLH_E_INVALID_ARG, "unknown point set");
   if ((uint64_t)index0 + n > 0x100000000ull) return fail(SLH_E_INVALID_ARG, "index range > 2^32");
   static uint32_t* table = nullptr;  // per process, device 0 context

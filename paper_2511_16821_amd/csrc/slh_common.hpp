@@ -45,10 +45,11 @@ __device__ __forceinline__ uint32_t nested_scramble(uint32_t x, uint32_t s) {
 
 constexpr int kSobolDims = 32;
 
-// Point function of Sec. 2.4: the Sobol' word of (dim, index) is the XOR of
-// the direction numbers V[dim][j] over the set bits j of the index, nested
-// (Owen) scrambled with a per-(stream, dim) seed; dims >= kSobolDims and the
-// pseudo-random mode hash (stream, dim, index).  The XOR runs over nibble
+// Point function of Sec. 2.4 (mode 0): the Sobol' word of (dim, index) is the
+// XOR of the direction numbers V[dim][j] over the set bits j of the index,
+// nested (Owen) scrambled with a per-(stream, dim) seed; mode 2 is the
+// shifted Halton set below; dims beyond a set's table and the pseudo-random
+// mode 1 hash (stream, dim, index).  The XOR runs over nibble
 // tables: N[d][p][n] is the XOR of V[d][4p + k] over the set bits k of the
 // 4-bit value n, so a word is the XOR of its index's eight nibble entries
 // (eight lookups instead of a loop over the set bits).  N has kSobolDims x
@@ -78,11 +79,36 @@ __device__ __forceinline__ uint32_t sobol_word_nib(const uint32_t* N, uint32_t d
   return x;
 }
 
+// Halton point set (the paper's generator, Sec. 2.4): coordinate d of point
+// i is the radical inverse of i in the d-th prime base b, as the word
+// floor(phi_b(i) 2^32).  With R the digit-reversed integer and D = b^K
+// (K digits of i), phi_b(i) = R / D; the floor comes from two exact integer
+// divisions, since R < D < 2^40.
+constexpr int kHaltonDims = 32;
+__device__ __forceinline__ uint32_t halton_u32(uint32_t dim, uint32_t index) {
+  constexpr uint32_t kPrimes[kHaltonDims] = {2,  3,  5,  7,  11, 13, 17, 19, 23,  29,  31,
+                                             37, 41, 43, 47, 53, 59, 61, 67, 71,  73,  79,
+                                             83, 89, 97, 101, 103, 107, 109, 113, 127, 131};
+  const uint32_t b = kPrimes[dim];
+  uint64_t R = 0, D = 1;
+  for (uint32_t i = index; i > 0; i /= b) {
+    R = R * b + (uint64_t)(i % b);
+    D *= b;
+  }
+  const uint64_t q1 = (R << 24) / D, r1 = (R << 24) % D;
+  return (uint32_t)((q1 << 8) + ((r1 << 8) / D));
+}
+
 __device__ __forceinline__ uint32_t point_u32n(const uint32_t* N, int mode, uint64_t stream,
                                                uint32_t dim, uint32_t index) {
   if (mode == 0 && dim < (uint32_t)kSobolDims) {
     const uint32_t s = (uint32_t)(mix64(stream + dim) >> 32);
     return nested_scramble(sobol_word_nib(N, dim, index), s);
+  }
+  if (mode == 2 && dim < (uint32_t)kHaltonDims) {
+    // randomised by a shift modulo 1 per (stream, dimension)
+    const uint32_t s = (uint32_t)(mix64(stream + dim) >> 32);
+    return halton_u32(dim, index) + s;
   }
   const uint64_t ctr = ((uint64_t)dim << 32) | (uint64_t)index;
   return (uint32_t)(mix64(stream ^ mix64(ctr)) >> 32);

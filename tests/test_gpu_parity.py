@@ -58,6 +58,14 @@ def test_points_bitwise(S, oracle):
     got = S.slh_qmc_points(5, 2, 2, 0, 0, 0, 6, 0, 100, 1)
     want = oracle.Points(1).block(oracle.stream_seed(5, 2, 2, 0, 0), range(6), range(100))
     assert np.array_equal(got, want)
+    # shifted Halton: every prime base, small and large indices, dims past the table
+    H = oracle.Points(2)
+    for seed, step, d0, nd, i0, n in [(11, 0, 0, 32, 0, 200), (11, 4, 0, 16, 2 ** 32 - 70, 64),
+                                      (3, 1, 28, 8, 987654, 50)]:
+        got = S.slh_qmc_points(seed, step, 1, 0, 0, d0, nd, i0, n, 2)
+        want = H.block(oracle.stream_seed(seed, step, 1, 0, 0), range(d0, d0 + nd),
+                       range(i0, i0 + n))
+        assert np.array_equal(got, want), (seed, d0, i0)
 
 
 def test_c1_full_ten_steps(S, oracle):
@@ -65,6 +73,16 @@ def test_c1_full_ten_steps(S, oracle):
     S_8: the small plain-method configuration at its full size."""
     from paper_2511_16821_amd import workloads as W
     _run_pair(S, oracle, W.c1(), 10)
+
+
+def test_halton_points_full_steps(S, oracle):
+    """The paper's point set (shifted Halton) through whole steps: C1 box with
+    N_s = 1 and a checkerboard with N_s = 2, against the oracle."""
+    from paper_2511_16821_amd import workloads as W
+    _run_pair(S, oracle, W.c1(n_s=1, points=2), 4)
+    p = W.checkerboard(blocks=5, cells_per_block=4, n_s=2, n_particles=20000, dt=0.05,
+                       sn_order=6, points=2)
+    _run_pair(S, oracle, p, 3)
 
 
 @pytest.mark.parametrize("n_s", [1, 2])

@@ -123,3 +123,43 @@ def test_sobol_dims_beyond_table_use_hash(oracle):
     a = P.block(99, (40,), range(8))
     b = P.block(99, (41,), range(8))
     assert not np.array_equal(a, b)
+
+
+def _radical_inverse_word(b, i):
+    """floor(phi_b(i) 2^32) from the definition, in exact rational arithmetic."""
+    from fractions import Fraction
+    phi, scale = Fraction(0), Fraction(1, b)
+    while i > 0:
+        phi += (i % b) * scale
+        i //= b
+        scale /= b
+    return int(phi * 2 ** 32)
+
+
+def test_halton_is_the_radical_inverse(oracle):
+    """Halton coordinate d of point i is the radical inverse of i in the d-th
+    prime base (Sec. 2.4, Halton 1960): checked against the definition in
+    exact arithmetic for every base, small indices and indices near 2^32."""
+    primes = [2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61, 67, 71, 73,
+              79, 83, 89, 97, 101, 103, 107, 109, 113, 127, 131]
+    rng = np.random.default_rng(3)
+    idx = list(range(0, 40)) + [int(v) for v in rng.integers(0, 2 ** 32, size=40)] + [2 ** 32 - 1]
+    L = oracle.lib()
+    for d, b in enumerate(primes):
+        for i in idx:
+            assert L.or_halton_u32(d, i) == _radical_inverse_word(b, i), (d, i)
+    assert L.or_halton_u32(0, 1) == 2 ** 31 and L.or_halton_u32(0, 3) == 3 * 2 ** 30
+    assert L.or_halton_u32(1, 1) == (2 ** 32) // 3
+
+
+@pytest.mark.parametrize("stream", [1, 0xDEADBEEF])
+def test_shifted_halton_stays_stratified(oracle, stream):
+    """A shift modulo 1 keeps the van der Corput stratification: the first b^k
+    points of a base-b coordinate put exactly one point in each interval
+    [j / b^k, (j + 1) / b^k)."""
+    P = oracle.Points(2)
+    for d, b, k in [(0, 2, 10), (1, 3, 6), (2, 5, 4), (6, 17, 2), (31, 131, 1)]:
+        n = b ** k
+        u = (P.block(stream, [d], range(n))[:, 0].astype(np.float64) + 0.5) / 2 ** 32
+        counts = np.bincount(np.floor(u * n).astype(np.int64), minlength=n)
+        assert np.all(counts == 1), (d, b)

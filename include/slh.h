@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SLH_ABI_VERSION 1u
+#define SLH_ABI_VERSION 2u
 
 typedef enum {
     SLH_OK = 0,
@@ -106,10 +106,18 @@ typedef struct {
     double time_closure;           /* tau in sigma_t + tau/(c dt); 0 -> 2    */
     double si_tol;                 /* SI relative tolerance; 0 -> 1e-12      */
     int32_t si_max_iter;           /* 0 -> 200                               */
-    double w_cut_rel;              /* cutoff |w| < w_cut_rel*sum(M)/N_p      */
+    double w_cut_rel;              /* cutoff |w| < w_cut_rel * w_q           */
     uint64_t seed;                 /* point-set seed                         */
     int32_t points;                /* slh_points                             */
     int32_t precision;             /* slh_precision                          */
+    const int32_t *n_s_cell;       /* host, nx*ny, or NULL: per-cell scatter */
+                                   /* limits N_s(x) (-1 unlimited, else 0..1e6),*/
+                                   /* the space/material-dependent limit the  */
+                                   /* paper names as its next step; n_s is    */
+                                   /* then ignored.  A segment is pre-limit   */
+                                   /* when the history's collision count is   */
+                                   /* below its cell's limit.  Copied at      */
+                                   /* slh_create.                             */
 } slh_problem;
 
 /* Balance of one pass (implicit capture, Sec. 2.3), FP64 from

@@ -47,7 +47,7 @@ class _Mesh(C.Structure):
                 ("x_lo", C.c_double), ("x_hi", C.c_double),
                 ("y_lo", C.c_double), ("y_hi", C.c_double),
                 ("sig_s", C.c_void_p), ("sig_a", C.c_void_p),
-                ("c", C.c_double), ("dt", C.c_double)]
+                ("c", C.c_double), ("dt", C.c_double), ("ns_cell", C.c_void_p)]
 
 
 class _Points(C.Structure):
@@ -285,8 +285,11 @@ class Mesh:
         self.sig_a = np.ascontiguousarray(prob["sigma_a"], dtype=np.float64).ravel()
         self.c = float(prob.get("c", 1.0))
         self.dt = float(prob["dt"])
+        ns = prob.get("n_s_cell")
+        self.ns_cell = None if ns is None else np.ascontiguousarray(ns, dtype=np.int32).ravel()
         self.s = _Mesh(self.nx, self.ny, self.x_lo, self.x_hi, self.y_lo, self.y_hi,
-                       _p(self.sig_s), _p(self.sig_a), self.c, self.dt)
+                       _p(self.sig_s), _p(self.sig_a), self.c, self.dt,
+                       None if self.ns_cell is None else _p(self.ns_cell))
         self.ncell = self.nx * self.ny
         self.area = ((self.x_hi - self.x_lo) / self.nx) * ((self.y_hi - self.y_lo) / self.ny)
 

@@ -160,6 +160,7 @@ typedef struct {
     double x_lo, x_hi, y_lo, y_hi;
     const double *sig_s, *sig_a; /* per cell, row-major j*nx+i */
     double c, dt;
+    const int32_t *ns_cell;      /* per-cell scatter limits (-1 unlimited), or NULL */
 } or_mesh;
 
 /* Balance record of one pass (implicit capture, Sec. 2.3). */
@@ -271,7 +272,13 @@ enum { EV_CENSUS = 0, EV_COLLIDE = 1, EV_XFACE = 2, EV_YFACE = 3 };
  * One MC pass over [t_n, t_n + dt].
  *   kind  = 1: step 1 of Sec. 2.2, the scatter-limited leg with n_lim = N_s
  *              (pre tally for n < N_s, post tally for n = N_s; n_lim < 0 means
- *              unlimited scattering, Sec. 2.3 "unlimited case").
+ *              unlimited scattering, Sec. 2.3 "unlimited case").  With per-cell
+ *              limits (M->ns_cell, the space-dependent N_s(x) the paper names
+ *              as its next step) a segment is in the pre regime when the
+ *              history's collision count is below its cell's limit; the
+ *              optical depth to the next collision is kept whenever the count
+ *              is below the largest limit, and is consumed only in the pre
+ *              regime.
  *   kind  = 2: step 3 of Sec. 2.2, the scatter-free remap (every particle is
  *              in the post-limit regime: attenuation by sigma_t, no scatter).
  * Source: nodal (bilinear) emission density q_nodal[n_cells*4] per unit
@@ -292,7 +299,17 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
     const double hy = (M->y_hi - M->y_lo) / ny;
     const double area = hx * hy;
     const double dt = M->dt, c = M->c;
-    const int n_lim = (kind == 2) ? 0 : (n_s < 0 ? 0x7fffffff : n_s);
+    /* n_lim: the largest limit (draws of the optical depth); lim(cell): the
+     * limit that decides the regime of a segment */
+    int n_lim = (kind == 2) ? 0 : (n_s < 0 ? 0x7fffffff : n_s);
+    const int32_t *nsc = (kind == 1) ? M->ns_cell : NULL;
+    if (nsc) {
+        n_lim = 0;
+        for (int64_t i = 0; i < ncell; ++i) {
+            const int v = nsc[i] < 0 ? 0x7fffffff : nsc[i];
+            if (v > n_lim) n_lim = v;
+        }
+    }
 
     for (int64_t i = 0; i < ncell; ++i) { T_a[i] = 0.0; T_b[i] = 0.0; }
     for (int k = 0; k < OB_N; ++k) bal[k] = 0.0;
@@ -367,7 +384,8 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
         for (;;) {
             const int64_t cell = (int64_t)iy * nx + ix;
             const double ss = M->sig_s[cell], sa = M->sig_a[cell], st = sa + ss;
-            const int pre = (n < n_lim);
+            const int lim = nsc ? (nsc[cell] < 0 ? 0x7fffffff : nsc[cell]) : n_lim;
+            const int pre = (n < lim);
             double d_cen = c * (dt - trel);
             if (d_cen < 0.0) d_cen = 0.0;
             double d_col = INFINITY;

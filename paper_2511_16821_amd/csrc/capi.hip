@@ -200,6 +200,12 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
   if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(SLH_E_INVALID_ARG, "dt must be > 0");
   if (p->n_s < -1 || p->n_s > 1000000)
     return fail(SLH_E_INVALID_ARG, "n_s must be -1 (unlimited) or in [0, 1e6]");
+  if (check_fields && p->n_s_cell) {
+    const long long n = (long long)p->nx * p->ny;
+    for (long long i = 0; i < n; ++i)
+      if (p->n_s_cell[i] < -1 || p->n_s_cell[i] > 1000000)
+        return fail(SLH_E_INVALID_ARG, "n_s_cell entries must be -1 (unlimited) or in [0, 1e6]");
+  }
   if (p->n_particles < 0 || p->n_particles > (1ll << 31))  // a cell's index l stays 32-bit
     return fail(SLH_E_INVALID_ARG, "n_particles must be in [0, 2^31]");
   if (p->census_cap < 0 || p->census_cap > (1ll << 34))
@@ -253,6 +259,7 @@ static Sizes sizes_of(const slh_problem* p) {
   size_t b = 0;
   const size_t nc = (size_t)z.n_cells;
   b += nc * (16 + 8 + 8 + 8 + 8);            // mat64, mat32, sig_s, sig_e, q
+  if (p->n_s_cell) b += nc * 4;              // per-cell scatter limits
   b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 4;  // nodal sources, trees
   b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
   b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
@@ -337,6 +344,9 @@ struct slh_solver {
   void* ctx = nullptr;
   std::vector<void*> allocs;
   std::vector<double> h_sig_s, h_sig_a, h_q;
+  std::vector<int> h_ns;    // per-cell scatter limits (unlimited as INT_MAX), empty if uniform
+  int n_lim_max = 0;        // the largest limit of the scatter-limited leg
+  int* ns_cell = nullptr;   // device copy of h_ns
   double hx, hy, area, adt, tau, si_tol;
   long long thin_margin = 0;
   int si_max;
@@ -473,6 +483,7 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->sig_s, double, nc);
   ALLOC(s->sig_e, double, nc);
   ALLOC(s->q, double, nc);
+  if (!s->h_ns.empty()) ALLOC(s->ns_cell, int, nc);
   s->tree_L = tree_leaves(nc);
   ALLOC(s->qn1, double, 4 * nc);
   ALLOC(s->tree1, double, 2 * s->tree_L);
@@ -535,6 +546,8 @@ static slh_status setup(slh_solver* s) {
   HIP_TRY(hipMemcpyAsync(s->sig_s, s->h_sig_s.data(), 8 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->sig_e, se.data(), 8 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->q, s->h_q.data(), 8 * nc, hipMemcpyHostToDevice, st));
+  if (s->ns_cell)
+    HIP_TRY(hipMemcpyAsync(s->ns_cell, s->h_ns.data(), 4 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->qn1, qn.data(), 32 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->dirs, dirs.data(), 8 * dirs.size(), hipMemcpyHostToDevice, st));
   std::vector<int> mid;
@@ -591,7 +604,8 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.seed = p.seed;
   a.kind = kind;
   // n_s = -1: no scatter limit (the leg is plain implicit-capture MC)
-  a.n_lim = kind == 1 ? (p.n_s < 0 ? 0x7fffffff : p.n_s) : 0;
+  a.n_lim = kind == 1 ? s->n_lim_max : 0;
+  a.ns_cell = kind == 1 ? s->ns_cell : nullptr;
   a.points = p.points;
   a.sobol = s->sobol;
   a.w_cut_rel = p.w_cut_rel;
@@ -878,7 +892,17 @@ extern "C" slh_status slh_create(const slh_problem* problem, void* hip_stream,
   s->h_sig_s.assign(problem->sigma_s, problem->sigma_s + nc);
   s->h_sig_a.assign(problem->sigma_a, problem->sigma_a + nc);
   s->h_q.assign(problem->q, problem->q + nc);
+  s->n_lim_max = problem->n_s < 0 ? 0x7fffffff : problem->n_s;
+  if (problem->n_s_cell) {
+    s->h_ns.resize(nc);
+    s->n_lim_max = 0;
+    for (long long i = 0; i < nc; ++i) {
+      s->h_ns[i] = problem->n_s_cell[i] < 0 ? 0x7fffffff : problem->n_s_cell[i];
+      s->n_lim_max = std::max(s->n_lim_max, s->h_ns[i]);
+    }
+  }
   s->prob.sigma_s = s->prob.sigma_a = s->prob.q = nullptr;
+  s->prob.n_s_cell = nullptr;
   s->hx = (problem->x_hi - problem->x_lo) / problem->nx;
   s->hy = (problem->y_hi - problem->y_lo) / problem->ny;
   s->area = s->hx * s->hy;

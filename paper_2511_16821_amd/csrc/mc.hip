@@ -1,7 +1,7 @@
 // (Q)MC pass of the scatter-limited hybrid method (Sec. 2.3 of the paper):
-// emission from per-cell majorants (sum-tree descent), tracking with at most n_lim
-// scatters per history (implicit capture with sigma_a before the limit,
-// attenuation with sigma_t after it), exact track-length tallies
+// emission stratified by cell, tracking with at most n_lim scatters per
+// history, or per-cell limits N_s(x) (implicit capture with sigma_a before
+// the limit, attenuation with sigma_t after it), exact track-length tallies
 // w (1 - e^{-sigma l}) / sigma per segment, and the census write of the remap
 // pass.
 //
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     tally_add(pend_ptr, pend_val, xl);
     pend_val = 0ull;
     const R ss = m.x, sa = m.y, stt = sa + ss;
-    const bool pre = n < n_lim;
+    const bool pre = n < (a.ns_cell ? a.ns_cell[cell] : n_lim);
     R d_cen = c * (dt - trel);
     if (d_cen < (R)0) d_cen = (R)0;
     R d_col = INF;

@@ -101,6 +101,7 @@ struct Request {
   uint64_t ticket = 0;
   slh_problem prob;
   std::vector<double> ss, sa, q;
+  std::vector<int32_t> ns;  // per-cell scatter limits, if given
   int n_steps = 0;
   size_t footprint = 0;
   ReqState state = Q_QUEUED;
@@ -271,6 +272,10 @@ extern "C" slh_status slh_server_submit(slh_server* srv, const slh_problem* p, i
   r->prob.sigma_s = r->ss.data();
   r->prob.sigma_a = r->sa.data();
   r->prob.q = r->q.data();
+  if (p->n_s_cell) {
+    r->ns.assign(p->n_s_cell, p->n_s_cell + n);
+    r->prob.n_s_cell = r->ns.data();
+  }
   r->n_steps = n_steps;
   r->footprint = fp;
   memset(&r->bal, 0, sizeof(r->bal));

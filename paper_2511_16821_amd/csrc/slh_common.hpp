@@ -274,7 +274,9 @@ struct PassArgs {
   double adt;            // cell area times dt
   uint64_t seed;         // the time step is read from st->step
   int kind;              // 1: scatter-limited leg, 2: scatter-free remap
-  int n_lim;             // scatter limit of the pass (0 for kind 2)
+  int n_lim;             // scatter limit of the pass (0 for kind 2); with
+                         // per-cell limits, the largest of them
+  const int* ns_cell;    // per-cell limits (unlimited as INT_MAX), or null
   int points;            // 0 Sobol'-Owen, 1 pseudo-random
   const uint32_t* sobol; // direction numbers
   double w_cut_rel;

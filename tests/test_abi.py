@@ -42,6 +42,8 @@ def test_validation_rejects_before_allocating(S):
         dict(nx=0), dict(dt=0.0), dict(dt=-1.0), dict(c=0.0), dict(n_s=-2),
         dict(sn_order=5), dict(sn_order=0), dict(n_particles=-5), dict(points=7),
         dict(precision=3), dict(w_cut_rel=-1.0), dict(x_hi=0.0),
+        dict(n_s_cell=np.full(400, -2, dtype=np.int32)),
+        dict(n_s_cell=np.full(400, 2_000_000, dtype=np.int32)),
     ]
     for upd in bad_cases:
         p = dict(good)

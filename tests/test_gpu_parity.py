@@ -85,6 +85,23 @@ def test_halton_points_full_steps(S, oracle):
     _run_pair(S, oracle, p, 3)
 
 
+def test_cellwise_scatter_limit(S, oracle):
+    """Space-dependent N_s(x) against the oracle: a material-dependent map on
+    the checkerboard (absorbers 0, scatterers 3) and a random map that mixes
+    unlimited cells with limits 0..5."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=5, cells_per_block=4, n_s=1, n_particles=20000, dt=0.1,
+                       sn_order=6)
+    ss = np.asarray(p["sigma_s"], dtype=np.float64).ravel()
+    p["n_s_cell"] = np.where(ss > 0, 3, 0).astype(np.int32)
+    _run_pair(S, oracle, p, 3)
+    q = W.checkerboard(blocks=3, cells_per_block=5, n_s=2, n_particles=15000, dt=0.2,
+                       sn_order=4)
+    rng = np.random.default_rng(5)
+    q["n_s_cell"] = rng.choice([-1, 0, 1, 2, 5], size=q["nx"] * q["ny"]).astype(np.int32)
+    _run_pair(S, oracle, q, 3)
+
+
 @pytest.mark.parametrize("n_s", [1, 2])
 def test_checkerboard_small(S, oracle, n_s):
     from paper_2511_16821_amd import workloads as W

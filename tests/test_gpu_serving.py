@@ -28,6 +28,8 @@ def _mix(n=10, seed=3):
         p = W.lognormal_blocks(side, L=4.0, blocks=8, rng=rng, n_s=int(rng.choice([0, 1, 2, 4])),
                                n_particles=int(rng.choice([3000, 12000, 40000])),
                                precision=int(rng.integers(0, 2)), seed=100 + r, sn_order=4)
+        if r % 4 == 1:  # per-cell scatter limits travel with the request
+            p["n_s_cell"] = rng.choice([-1, 0, 1, 3], size=side * side).astype(np.int32)
         out.append((p, int(rng.integers(2, 6))))
     return out
 

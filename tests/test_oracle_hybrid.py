@@ -106,3 +106,71 @@ def test_census_cap_respected_and_weight_preserved(oracle):
         # thinning preserves the census weight in expectation; for the kept
         # set its total is (count/cap) x the kept part of the census weight
         assert kept_w > 0 and b["census"] > 0
+
+
+@pytest.mark.parametrize("inner_ns,outer_ns", [(2, 4), (0, -1), (3, 1)])
+def test_cellwise_scatter_limit_is_local(oracle, inner_ns, outer_ns):
+    """Space-dependent N_s(x): the cells within one light-cone width of the
+    edge carry another limit (larger, smaller or unlimited, which also changes
+    how many optical depths a history keeps drawing).  In the first step the
+    interior cells, which no history from the edge reaches, must show the
+    pre- and post-limit fluxes of a uniform limit equal to their own."""
+    from paper_2511_16821_amd import workloads as W
+    ss, sa, dt = 1.0, 0.1, 1.0
+    n, L = 16, 8.0
+    prob = W.homogeneous_box(n=n, L=L, sig_s=ss, sig_a=sa, src_cells=((0, n), (0, n)),
+                             n_s=inner_ns, n_particles=2 ** 15, dt=dt, sn_order=4)
+    h = L / n
+    k0 = int(math.ceil(dt / h)) + 1
+    inner = np.zeros((n, n), dtype=bool)
+    inner[k0:n - k0, k0:n - k0] = True
+    ring = np.zeros((n, n), dtype=bool)
+    ring[:k0 - 1, :] = ring[n - k0 + 1:, :] = ring[:, :k0 - 1] = ring[:, n - k0 + 1:] = True
+    prob["n_s_cell"] = np.where(ring, outer_ns, inner_ns).astype(np.int32).ravel()
+    pre, post = [], []
+    for seed in (1, 2, 3, 4):
+        prob["seed"] = seed
+        r = oracle.HybridOracle(prob).step()
+        pre.append(r["phi_pre"].reshape(n, n)[inner].mean())
+        post.append(r["phi_post"].reshape(n, n)[inner].mean())
+    st = ss + sa
+    X = st * dt
+
+    def Pbar(a):
+        return gammainc(a, X) - (a / X) * gammainc(a + 1, X)
+
+    rr = ss / st
+    want_pre = sum(rr ** k * Pbar(k + 1) / st for k in range(inner_ns))
+    want_post = rr ** inner_ns * Pbar(inner_ns + 1) / st
+    for got, want in ((np.array(pre), want_pre), (np.array(post), want_post)):
+        se = got.std(ddof=1) / 2
+        assert abs(got.mean() - want) < 5 * se + 1e-3 * (want_pre + want_post), (got, want)
+
+
+@pytest.mark.parametrize("k", [0, 2, -1])
+def test_uniform_cellwise_limit_equals_scalar_limit(oracle, k):
+    """N_s(x) = k in every cell is the plain method with N_s = k, bitwise."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=3, cells_per_block=4, n_s=k, n_particles=3000, dt=0.2)
+    a = oracle.HybridOracle(dict(p)).run(2)
+    q = dict(p)
+    q["n_s_cell"] = np.full(p["nx"] * p["ny"], k, dtype=np.int32)
+    q["n_s"] = 7  # ignored when per-cell limits are given
+    b = oracle.HybridOracle(q).run(2)
+    for ra, rb in zip(a, b):
+        for key in ("T_pre", "T_post", "T_R", "phi_c"):
+            assert np.array_equal(ra[key], rb[key]), key
+
+
+def test_pre_tally_only_where_the_limit_allows(oracle):
+    """With N_s(x) = 0 everywhere but one cell, histories are in the pre
+    regime only inside that cell: the pre tally vanishes everywhere else."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=3, cells_per_block=4, n_s=0, n_particles=4000, dt=0.2)
+    ns = np.zeros(p["nx"] * p["ny"], dtype=np.int32)
+    c = (p["ny"] // 2) * p["nx"] + p["nx"] // 2
+    ns[c] = 3
+    p["n_s_cell"] = ns
+    r = oracle.HybridOracle(p).run(1)[0]
+    assert r["T_pre"][c] > 0
+    assert np.count_nonzero(r["T_pre"]) == 1

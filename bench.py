@@ -292,45 +292,46 @@ def large_resident(S, torch, args):
 
 def cellwise_ns(S, torch, args):
     """Space-dependent scatter limit N_s(x) (the paper's stated next step) on
-    the C2 checkerboard: limit 0 in the absorber blocks and k in the
-    scatterers, against the uniform limit k.  Per k: time per step, segments/s,
-    source iterations of the last step, and the relative L2 difference of phi_R
-    after the run between the two (same seed; both estimate the same flux)."""
+    the C3 thick medium with voids: limit k in the thick scatterer and 0 in the
+    voids, against uniform limits k and 0.  Per map: time per step,
+    segments/s, source iterations of the last step, and the relative L2
+    difference of phi_R after the run from the uniform-0 run (same seed; all
+    maps estimate the same flux)."""
     import numpy as np
     from paper_2511_16821_amd import workloads as W
-    rows = []
     steps = args.nsx_steps
+    rows = []
+    base_flux = None
     for k in [int(v) for v in args.nsx_ns.split(",") if v != ""]:
-        row = {"k": k}
-        flux = {}
-        for name in ("uniform", "absorbers_0"):
-            p = W.c2(n_s=k, n_steps=steps)
-            if name == "absorbers_0":
+        for name in ("uniform", "thick_k_voids_0"):
+            if name == "thick_k_voids_0" and k == 0:
+                continue
+            p = W.c3(n_s=k, n_particles=int(args.nsx_particles), n_steps=steps)
+            if name == "thick_k_voids_0":
                 ss = np.asarray(p["sigma_s"], dtype=np.float64).ravel()
-                p["n_s_cell"] = np.where(ss > 0, k, 0).astype(np.int32)
+                p["n_s_cell"] = np.where(ss > 1.0, k, 0).astype(np.int32)
             s = S.Solver(p)
-            s.advance(2)
-            s.synchronize()
-            st0 = s.get_stats()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s.advance(steps)
             s.synchronize()
             t = time.perf_counter() - t0
             st = s.get_stats()
-            seg = (st["seg_mc_total"] + st["seg_remap_total"]
-                   - st0["seg_mc_total"] - st0["seg_remap_total"])
-            flux[name] = s.get_flux(0)
-            row[name] = {"ms_per_step": 1e3 * t / steps, "segments_per_s": seg / t,
-                         "si_iterations_last": st["si_iterations"]}
+            seg = st["seg_mc_total"] + st["seg_remap_total"]
+            f = s.get_flux(0)
             s.destroy()
-        a, b = flux["uniform"], flux["absorbers_0"]
-        row["rel_l2_phi_R_between"] = float(np.linalg.norm(b - a) / np.linalg.norm(a))
-        log("cellwise N_s:", json.dumps(row))
-        rows.append(row)
-    return {"workload": "C2 checkerboard (140x140, 1e6 particles/pass, dt=0.05, S_12), %d "
-                        "timed steps after 2; N_s(x) = 0 in absorbers, k in scatterers, vs "
-                        "uniform k" % steps, "rows": rows}
+            if base_flux is None:
+                base_flux = f
+            row = {"map": name, "k": k, "ms_per_step": 1e3 * t / steps, "segments_per_s": seg / t,
+                   "segments_per_step": seg / steps, "si_iterations_last": st["si_iterations"],
+                   "rel_l2_phi_R_vs_uniform_0": float(np.linalg.norm(f - base_flux) /
+                                                      np.linalg.norm(base_flux))}
+            log("cellwise N_s:", json.dumps(row))
+            rows.append(row)
+    return {"workload": "C3 thick medium with voids (256x256, sigma_s=100 / voids sigma_t=0.1, "
+                        "%g particles/pass, dt=0.01, S_8), %d steps; N_s(x) = k in the thick "
+                        "medium and 0 in the voids, against uniform limits"
+                        % (args.nsx_particles, steps), "rows": rows}
 
 
 def protocol(S, torch, args):
@@ -486,9 +487,10 @@ def main():
     ap.add_argument("--protocol-dt", type=float, default=0.1)
     ap.add_argument("--protocol-seeds", type=int, default=4)
     ap.add_argument("--nsx", action="store_true",
-                    help="space-dependent N_s(x) on C2 against a uniform limit")
-    ap.add_argument("--nsx-ns", default="1,2,4")
-    ap.add_argument("--nsx-steps", type=int, default=20)
+                    help="space-dependent N_s(x) on the C3 medium against uniform limits")
+    ap.add_argument("--nsx-ns", default="0,1,2,4")
+    ap.add_argument("--nsx-steps", type=int, default=10)
+    ap.add_argument("--nsx-particles", type=float, default=2e6)
     ap.add_argument("--c5", action="store_true",
                     help="also run the large resident solve (1024x1024, 1e8 particles/pass)")
     ap.add_argument("--c5-steps", type=int, default=50)

@@ -236,9 +236,11 @@ const char *slh_last_error(void);
 
 /* Point function of Sec. 2.4 on the device: for k in [0, n) writes
  * out[k*n_dims + d] = P(stream, dim0 + d, index0 + k), the 32-bit point word
- * that the tracking kernels use for (time step, pass, population, cohort),
- * with pass in {1, 2} and population 0 = source, 1 = census.  dev_out is
- * device memory of n*n_dims words; enqueued on hip_stream. */
+ * that the tracking kernels use for (time step, pass, population, key),
+ * with pass in {1, 2}, population 0 = source (key = birth cell, index =
+ * particle number within the cell) or 1 = census (key = history id, index
+ * 0), and points an slh_points value.  dev_out is device memory of
+ * n*n_dims words; enqueued on hip_stream. */
 slh_status slh_qmc_points(uint64_t seed, uint64_t step, uint32_t pass, uint32_t population,
                           uint64_t cohort, uint32_t dim0, uint32_t n_dims, uint32_t index0,
                           uint32_t n, int32_t points, uint32_t *dev_out, void *hip_stream);

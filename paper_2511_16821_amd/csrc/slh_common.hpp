@@ -23,7 +23,8 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 // Stream of points for (time step, pass 1|2, population 0 source|1 census|2
-// thinning, cohort = birth step of a census particle).
+// thinning, key): the key is the birth cell of a source particle and the
+// history id of a census particle.
 __host__ __device__ __forceinline__ uint64_t stream_seed(uint64_t seed, uint64_t step,
                                                           uint32_t pass, uint32_t pop,
                                                           uint64_t cohort) {

@@ -47,7 +47,8 @@ class _Mesh(C.Structure):
                 ("x_lo", C.c_double), ("x_hi", C.c_double),
                 ("y_lo", C.c_double), ("y_hi", C.c_double),
                 ("sig_s", C.c_void_p), ("sig_a", C.c_void_p),
-                ("c", C.c_double), ("dt", C.c_double), ("ns_cell", C.c_void_p)]
+                ("c", C.c_double), ("dt", C.c_double), ("ns_cell", C.c_void_p),
+                ("bc", C.c_int)]
 
 
 class _Points(C.Structure):
@@ -117,7 +118,8 @@ def lib():
                                   C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_dg_collided.restype = C.c_int
         L.or_dg_collided.argtypes = [C.POINTER(_Mesh), C.c_double, C.c_int, C.c_void_p,
-                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_double, C.c_int,
                                      C.c_void_p, C.POINTER(C.c_double)]
     return _lib
 
@@ -287,9 +289,10 @@ class Mesh:
         self.dt = float(prob["dt"])
         ns = prob.get("n_s_cell")
         self.ns_cell = None if ns is None else np.ascontiguousarray(ns, dtype=np.int32).ravel()
+        self.bc = int(prob.get("boundary", 0))  # reflective sides: 1 x_lo, 2 x_hi, 4 y_lo, 8 y_hi
         self.s = _Mesh(self.nx, self.ny, self.x_lo, self.x_hi, self.y_lo, self.y_hi,
                        _p(self.sig_s), _p(self.sig_a), self.c, self.dt,
-                       None if self.ns_cell is None else _p(self.ns_cell))
+                       None if self.ns_cell is None else _p(self.ns_cell), self.bc)
         self.ncell = self.nx * self.ny
         self.area = ((self.x_hi - self.x_lo) / self.nx) * ((self.y_hi - self.y_lo) / self.ny)
 
@@ -366,13 +369,28 @@ def dg_sweep(nx, ny, box, sig_e, a, b, src, in_x=None, in_y=None):
     return psi.reshape(ny, nx, 4)
 
 
+def mirror_indices(quad):
+    """For each direction, the index of its mirror image in x (Ox -> -Ox) and
+    in y (Oy -> -Oy) within the same set."""
+    ox, oy, _ = quad
+    n = len(ox)
+    rx, ry = np.zeros(n, dtype=np.int32), np.zeros(n, dtype=np.int32)
+    for m in range(n):
+        rx[m] = int(np.argmin(np.abs(ox + ox[m]) + np.abs(oy - oy[m])))
+        ry[m] = int(np.argmin(np.abs(ox - ox[m]) + np.abs(oy + oy[m])))
+        assert abs(ox[rx[m]] + ox[m]) + abs(oy[rx[m]] - oy[m]) < 1e-12
+        assert abs(ox[ry[m]] - ox[m]) + abs(oy[ry[m]] + oy[m]) < 1e-12
+    return rx, ry
+
+
 def dg_collided(mesh: Mesh, quad, phi_post, tau=2.0, tol=1e-12, max_iter=200):
     ox, oy, w = (np.ascontiguousarray(v, dtype=np.float64) for v in quad)
+    rx, ry = mirror_indices((ox, oy, w))
     phi = np.zeros(4 * mesh.ncell)
     res = C.c_double(0.0)
     phi_post = np.ascontiguousarray(phi_post, dtype=np.float64)
-    it = lib().or_dg_collided(C.byref(mesh.s), tau, len(w), _p(ox), _p(oy), _p(w),
-                              _p(phi_post), tol, max_iter, _p(phi), C.byref(res))
+    it = lib().or_dg_collided(C.byref(mesh.s), tau, len(w), _p(ox), _p(oy), _p(w), _p(rx),
+                              _p(ry), _p(phi_post), tol, max_iter, _p(phi), C.byref(res))
     if it < 0:
         raise RuntimeError("DG sweep failed")
     return phi.reshape(mesh.ncell, 4), it, res.value

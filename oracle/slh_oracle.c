@@ -161,7 +161,10 @@ typedef struct {
     const double *sig_s, *sig_a; /* per cell, row-major j*nx+i */
     double c, dt;
     const int32_t *ns_cell;      /* per-cell scatter limits (-1 unlimited), or NULL */
+    int bc;                      /* reflective sides: bit 0 x_lo, 1 x_hi, 2 y_lo, 3 y_hi */
 } or_mesh;
+
+enum { OR_BC_XLO = 1, OR_BC_XHI = 2, OR_BC_YLO = 4, OR_BC_YHI = 8 };
 
 /* Balance record of one pass (implicit capture, Sec. 2.3). */
 enum { OB_EMITTED = 0, OB_ABSORBED, OB_SCATTERED, OB_LEAKED, OB_CENSUS,
@@ -441,12 +444,24 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
                     dcur += 1;
                 }
             } else if (ev == EV_XFACE) {
-                if (ox > 0.0) { x = M->x_lo + hx * (double)(ix + 1); ix += 1; }
-                else          { x = M->x_lo + hx * (double)ix;       ix -= 1; }
+                /* a reflective side mirrors the direction (specular
+                 * reflection): the history stays in its cell */
+                if (ox > 0.0) {
+                    x = M->x_lo + hx * (double)(ix + 1);
+                    if (ix == nx - 1 && (M->bc & OR_BC_XHI)) ox = -ox; else ix += 1;
+                } else {
+                    x = M->x_lo + hx * (double)ix;
+                    if (ix == 0 && (M->bc & OR_BC_XLO)) ox = -ox; else ix -= 1;
+                }
                 if (ix < 0 || ix >= nx) { bal[OB_LEAKED] += w; break; }
             } else {
-                if (oy > 0.0) { y = M->y_lo + hy * (double)(iy + 1); iy += 1; }
-                else          { y = M->y_lo + hy * (double)iy;       iy -= 1; }
+                if (oy > 0.0) {
+                    y = M->y_lo + hy * (double)(iy + 1);
+                    if (iy == ny - 1 && (M->bc & OR_BC_YHI)) oy = -oy; else iy += 1;
+                } else {
+                    y = M->y_lo + hy * (double)iy;
+                    if (iy == 0 && (M->bc & OR_BC_YLO)) oy = -oy; else iy -= 1;
+                }
                 if (iy < 0 || iy >= ny) { bal[OB_LEAKED] += w; break; }
             }
             if (fabs(w) < w_cut) { bal[OB_CUTOFF] += w; break; }
@@ -666,7 +681,8 @@ int or_dg_sweep(int nx, int ny, double x_lo, double x_hi, double y_lo, double y_
 /*
  * Source iteration for the collided flux (step 2 of Sec. 2.2):
  *   (sig_t + tau/(c dt)) psi + Omega.grad psi = sig_s/(4 pi) (phi_c + phi_post)
- * with zero initial and vacuum boundary data.  The time derivative over the
+ * with zero initial data, vacuum sides, and reflective sides (M->bc) whose
+ * inflow lags one iteration (see below).  The time derivative over the
  * step is closed by tau/(c dt) (tau = 2: the step average of a flux growing
  * linearly from zero).  phi_post is cell-constant; phi_c is nodal bilinear.
  * Stops when ||phi_new - phi_old||_2 <= tol ||phi_new||_2 (nodal vectors).
@@ -674,15 +690,27 @@ int or_dg_sweep(int nx, int ny, double x_lo, double x_hi, double y_lo, double y_
  */
 int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
                    const double *dox, const double *doy, const double *dw,
+                   const int *refl_x, const int *refl_y,
                    const double *phi_post, double tol, int max_iter,
                    double *phi, double *resid_out)
 {
-    const int64_t ncell = (int64_t)M->nx * M->ny;
+    const int nx = M->nx, ny = M->ny;
+    const int64_t ncell = (int64_t)nx * ny;
     const size_t nn = (size_t)ncell * 4;
     double *sig_e = (double *)malloc(sizeof(double) * (size_t)ncell);
     double *src = (double *)malloc(sizeof(double) * nn);
     double *psi = (double *)malloc(sizeof(double) * nn);
     double *acc = (double *)malloc(sizeof(double) * nn);
+    /* Reflective sides: the inflow of direction m on such a side is the
+     * outflow, on the same side, of its mirror image (refl_x: Ox -> -Ox,
+     * refl_y: Oy -> -Oy) from the previous source iteration (zero in the
+     * first); out_x/out_y hold each direction's outflow traces on its
+     * downwind x and y sides, two nodes per row or column. */
+    const size_t bx = (size_t)2 * ny, by = (size_t)2 * nx;
+    double *out_x = (double *)calloc((size_t)n_dir * bx, sizeof(double));
+    double *out_y = (double *)calloc((size_t)n_dir * by, sizeof(double));
+    double *prev_x = (double *)calloc((size_t)n_dir * bx, sizeof(double));
+    double *prev_y = (double *)calloc((size_t)n_dir * by, sizeof(double));
     for (int64_t i = 0; i < ncell; ++i)
         sig_e[i] = M->sig_a[i] + M->sig_s[i] + tau_closure / (M->c * M->dt);
     for (size_t k = 0; k < nn; ++k) phi[k] = 0.0;
@@ -693,13 +721,33 @@ int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
             for (int k = 0; k < 4; ++k)
                 src[4 * i + k] = M->sig_s[i] / (4.0 * M_PI) * (phi[4 * i + k] + phi_post[i]);
         for (size_t k = 0; k < nn; ++k) acc[k] = 0.0;
+        memcpy(prev_x, out_x, sizeof(double) * (size_t)n_dir * bx);
+        memcpy(prev_y, out_y, sizeof(double) * (size_t)n_dir * by);
         for (int m = 0; m < n_dir; ++m) {
-            if (or_dg_sweep(M->nx, M->ny, M->x_lo, M->x_hi, M->y_lo, M->y_hi, sig_e,
-                            dox[m], doy[m], src, NULL, NULL, psi) != 0) {
+            const int rx = (dox[m] > 0.0) ? (M->bc & OR_BC_XLO) : (M->bc & OR_BC_XHI);
+            const int ry = (doy[m] > 0.0) ? (M->bc & OR_BC_YLO) : (M->bc & OR_BC_YHI);
+            const double *in_x = rx ? prev_x + (size_t)refl_x[m] * bx : NULL;
+            const double *in_y = ry ? prev_y + (size_t)refl_y[m] * by : NULL;
+            if (or_dg_sweep(nx, ny, M->x_lo, M->x_hi, M->y_lo, M->y_hi, sig_e,
+                            dox[m], doy[m], src, in_x, in_y, psi) != 0) {
                 it = -1;
                 goto done;
             }
             for (size_t k = 0; k < nn; ++k) acc[k] += dw[m] * psi[k];
+            /* outflow traces: x side xi = 1 (nodes 1, 3) if Ox > 0 else xi = 0
+             * (nodes 0, 2); y side eta = 1 (nodes 2, 3) if Oy > 0 else 0 (0, 1) */
+            const int ib = (dox[m] > 0.0) ? nx - 1 : 0, fx = (dox[m] > 0.0) ? 1 : 0;
+            for (int j = 0; j < ny; ++j) {
+                const double *pc = psi + 4 * ((int64_t)j * nx + ib);
+                out_x[(size_t)m * bx + 2 * j] = pc[fx];
+                out_x[(size_t)m * bx + 2 * j + 1] = pc[fx + 2];
+            }
+            const int jb = (doy[m] > 0.0) ? ny - 1 : 0, fy = (doy[m] > 0.0) ? 1 : 0;
+            for (int i = 0; i < nx; ++i) {
+                const double *pc = psi + 4 * ((int64_t)jb * nx + i);
+                out_y[(size_t)m * by + 2 * i] = pc[2 * fy];
+                out_y[(size_t)m * by + 2 * i + 1] = pc[2 * fy + 1];
+            }
         }
         it += 1;
         double dn = 0.0, nrm = 0.0;
@@ -717,5 +765,6 @@ int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
 done:
     if (resid_out) *resid_out = resid;
     free(sig_e); free(src); free(psi); free(acc);
+    free(out_x); free(out_y); free(prev_x); free(prev_y);
     return it;
 }

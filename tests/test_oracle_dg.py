@@ -92,3 +92,52 @@ def test_si_converges_to_fixed_point(oracle):
     phi2, it2, _ = oracle.dg_collided(m, quad, phi_post, 2.0, 1e-14, 500)
     assert it2 >= it
     assert np.linalg.norm(phi - phi2) <= 1e-11 * np.linalg.norm(phi2)
+
+
+def test_reflective_box_is_infinite_medium(oracle):
+    """Reflective sides on all four faces: a uniform phi_post gives the
+    infinite-medium value sig_s phi_post / (sig_a + tau/(c dt)) in every cell,
+    not only far from the boundary."""
+    ss, sa, dt, tau = 1.0, 0.1, 0.1, 2.0
+    n, L = 6, 0.6
+    prob = dict(nx=n, ny=n, x_lo=0, x_hi=L, y_lo=0, y_hi=L, sigma_s=np.full((n, n), ss),
+                sigma_a=np.full((n, n), sa), dt=dt, c=1.0, boundary=15)
+    phi, it, res = oracle.dg_collided(oracle.Mesh(prob), oracle.quadrature(6), np.full(n * n, 3.0),
+                                      tau, 1e-13, 400)
+    np.testing.assert_allclose(phi, ss * 3.0 / (sa + tau / dt), rtol=1e-11)
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_reflective_side_is_a_symmetry_plane(oracle, axis):
+    """A problem mirror-symmetric about x = L/2 (or y = L/2) solved on the full
+    mesh with vacuum sides, and on one half with the cut side reflective:
+    the half solution is the full solution restricted to that half."""
+    rng = np.random.default_rng(12)
+    n, L = 8, 1.6
+    half = rng.uniform(0.2, 3.0, size=(n, n // 2))
+    ss = np.concatenate([half, half[:, ::-1]], axis=1)
+    sa = np.concatenate([half[::-1, :] * 0.3, (half[::-1, :] * 0.3)[:, ::-1]], axis=1)
+    post = rng.uniform(0.0, 2.0, size=(n, n // 2))
+    pp = np.concatenate([post, post[:, ::-1]], axis=1)
+    if axis == "y":
+        ss, sa, pp = ss.T.copy(), sa.T.copy(), pp.T.copy()
+    full = dict(nx=n, ny=n, x_lo=0, x_hi=L, y_lo=0, y_hi=L, sigma_s=ss, sigma_a=sa, dt=0.2,
+                c=1.0)
+    quad = oracle.quadrature(6)
+    phi_f, _, _ = oracle.dg_collided(oracle.Mesh(full), quad, pp.ravel(), 2.0, 1e-14, 500)
+    phi_f = phi_f.reshape(n, n, 4)
+    if axis == "x":
+        hp = dict(full, nx=n // 2, x_hi=L / 2, sigma_s=ss[:, :n // 2], sigma_a=sa[:, :n // 2],
+                  boundary=2)
+        phi_h, _, _ = oracle.dg_collided(oracle.Mesh(hp), quad, pp[:, :n // 2].ravel(), 2.0,
+                                         1e-14, 500)
+        want = phi_f[:, :n // 2]
+        phi_h = phi_h.reshape(n, n // 2, 4)
+    else:
+        hp = dict(full, ny=n // 2, y_hi=L / 2, sigma_s=ss[:n // 2], sigma_a=sa[:n // 2],
+                  boundary=8)
+        phi_h, _, _ = oracle.dg_collided(oracle.Mesh(hp), quad, pp[:n // 2].ravel(), 2.0,
+                                         1e-14, 500)
+        want = phi_f[:n // 2]
+        phi_h = phi_h.reshape(n // 2, n, 4)
+    assert np.linalg.norm(phi_h - want) <= 1e-11 * np.linalg.norm(want)

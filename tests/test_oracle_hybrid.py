@@ -174,3 +174,31 @@ def test_pre_tally_only_where_the_limit_allows(oracle):
     r = oracle.HybridOracle(p).run(1)[0]
     assert r["T_pre"][c] > 0
     assert np.count_nonzero(r["T_pre"]) == 1
+
+
+@pytest.mark.parametrize("n_s", [0, 2])
+def test_reflective_box_follows_infinite_medium_everywhere(oracle, n_s):
+    """With all four sides reflective a homogeneous box with a uniform source
+    is an infinite medium: every cell, the boundary cells included, follows
+    the expected recursion, and no weight leaks."""
+    from paper_2511_16821_amd import workloads as W
+    ss, sa, dt, steps = 1.0, 0.1, 0.1, 4
+    n, L = 6, 0.9
+    prob = W.homogeneous_box(n=n, L=L, sig_s=ss, sig_a=sa, src_cells=((0, n), (0, n)),
+                             n_s=n_s, n_particles=2 ** 14, dt=dt, sn_order=4, boundary=15)
+    edge = np.zeros((n, n), dtype=bool)
+    edge[0, :] = edge[-1, :] = edge[:, 0] = edge[:, -1] = True
+    runs_all, runs_edge = [], []
+    for seed in (1, 2, 3, 4):
+        prob["seed"] = seed
+        s = oracle.HybridOracle(prob)
+        res = s.run(steps)
+        for r in res:
+            assert r["bal_mc"]["leaked"] == 0.0 and r["bal_remap"]["leaked"] == 0.0
+        runs_all.append([r["phi_R"].mean() for r in res])
+        runs_edge.append([r["phi_R"].reshape(n, n)[edge].mean() for r in res])
+    expect = _expected_remap_flux(1.0, ss, sa, dt, n_s, 2.0, steps)
+    for runs in (np.array(runs_all), np.array(runs_edge)):
+        mean = runs.mean(0)
+        se = runs.std(0, ddof=1) / 2
+        assert np.all(np.abs(mean - expect) < 5 * se + 2e-4 * expect), (mean, expect, se)

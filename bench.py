@@ -334,6 +334,37 @@ def cellwise_ns(S, torch, args):
                         % (args.nsx_particles, steps), "rows": rows}
 
 
+def reflective(S, torch, args):
+    """Reflective sides on C2 (all four sides, and x_lo + y_lo: the quarter of
+    a symmetric problem) against the vacuum case: time per step, segments/s
+    and the source iterations of the last step."""
+    from paper_2511_16821_amd import workloads as W
+    steps = args.reflect_steps
+    rows = []
+    for name, bc in (("vacuum", 0), ("x_lo+y_lo", 5), ("all four", 15)):
+        p = W.c2(n_s=args.ns, n_steps=steps, boundary=bc)
+        s = S.Solver(p)
+        s.advance(2)
+        s.synchronize()
+        st0 = s.get_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(steps)
+        s.synchronize()
+        t = time.perf_counter() - t0
+        st = s.get_stats()
+        seg = (st["seg_mc_total"] + st["seg_remap_total"]
+               - st0["seg_mc_total"] - st0["seg_remap_total"])
+        bal = s.get_balance(2)
+        row = {"sides": name, "ms_per_step": 1e3 * t / steps, "segments_per_s": seg / t,
+               "si_iterations_last": st["si_iterations"], "leaked_last_remap": bal["leaked"]}
+        s.destroy()
+        log("reflective:", json.dumps(row))
+        rows.append(row)
+    return {"workload": "C2 checkerboard (140x140, N_s=%d, 1e6 particles/pass, dt=0.05, S_12), "
+                        "%d timed steps after 2" % (args.ns, steps), "rows": rows}
+
+
 def protocol(S, torch, args):
     """The paper's measurements on a stand-in (Sec. 3, Table 1 protocol): for
     each scatter limit N_s (-1 = unlimited, the plain MC reference case), the
@@ -486,6 +517,9 @@ def main():
     ap.add_argument("--protocol-steps", type=int, default=10)
     ap.add_argument("--protocol-dt", type=float, default=0.1)
     ap.add_argument("--protocol-seeds", type=int, default=4)
+    ap.add_argument("--reflect", action="store_true",
+                    help="reflective sides on C2 against vacuum")
+    ap.add_argument("--reflect-steps", type=int, default=20)
     ap.add_argument("--nsx", action="store_true",
                     help="space-dependent N_s(x) on the C3 medium against uniform limits")
     ap.add_argument("--nsx-ns", default="0,1,2,4")
@@ -565,6 +599,8 @@ def main():
         out["protocol"] = protocol(S, torch, args)
     if args.nsx:
         out["cellwise_ns"] = cellwise_ns(S, torch, args)
+    if args.reflect:
+        out["reflective"] = reflective(S, torch, args)
     if args.c5:
         out["large_resident"] = large_resident(S, torch, args)
     if args.serve:

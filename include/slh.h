@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SLH_ABI_VERSION 2u
+#define SLH_ABI_VERSION 3u
 
 typedef enum {
     SLH_OK = 0,
@@ -118,7 +118,18 @@ typedef struct {
                                    /* when the history's collision count is   */
                                    /* below its cell's limit.  Copied at      */
                                    /* slh_create.                             */
+    int32_t boundary;              /* reflective sides, a bit mask of        */
+                                   /* SLH_REFLECT_*; 0: vacuum everywhere.   */
+                                   /* A history reaching a reflective side is */
+                                   /* mirrored; the DG inflow on such a side  */
+                                   /* is the previous source iteration's      */
+                                   /* outflow of the mirrored direction.      */
 } slh_problem;
+
+#define SLH_REFLECT_X_LO 1
+#define SLH_REFLECT_X_HI 2
+#define SLH_REFLECT_Y_LO 4
+#define SLH_REFLECT_Y_HI 8
 
 /* Balance of one pass (implicit capture, Sec. 2.3), FP64 from
  * order-independent fixed-point sums: emitted = absorbed + scattered +

@@ -200,6 +200,8 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
   if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(SLH_E_INVALID_ARG, "dt must be > 0");
   if (p->n_s < -1 || p->n_s > 1000000)
     return fail(SLH_E_INVALID_ARG, "n_s must be -1 (unlimited) or in [0, 1e6]");
+  if (p->boundary < 0 || p->boundary > 15)
+    return fail(SLH_E_INVALID_ARG, "boundary must be a mask of SLH_REFLECT_* (0..15)");
   if (check_fields && p->n_s_cell) {
     const long long n = (long long)p->nx * p->ny;
     for (long long i = 0; i < n; ++i)
@@ -260,6 +262,8 @@ static Sizes sizes_of(const slh_problem* p) {
   const size_t nc = (size_t)z.n_cells;
   b += nc * (16 + 8 + 8 + 8 + 8);            // mat64, mat32, sig_s, sig_e, q
   if (p->n_s_cell) b += nc * 4;              // per-cell scatter limits
+  if (p->boundary)                           // mirror indices, reflected traces
+    b += (size_t)z.n_dir * 8 + (size_t)2 * z.n_dir * 2 * (p->nx + p->ny) * 8;
   b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 4;  // nodal sources, trees
   b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
   b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
@@ -362,6 +366,11 @@ struct slh_solver {
   double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr;
   double *psi = nullptr, *dg_part = nullptr, *dirs = nullptr;
   double* cmax = nullptr;  // per-block max |w| of the census compaction
+  // reflective sides: mirror indices of the directions and two buffers of
+  // boundary outflow traces (null when every side is vacuum)
+  int *refl_x = nullptr, *refl_y = nullptr;
+  double* bnd = nullptr;
+  std::vector<int> h_refl;
   double* dirmat = nullptr;  // DG element data per direction
   int* mat_id = nullptr;     // DG table mode: material of each cell,
   double *sig_e_mat = nullptr, *coef = nullptr;  // its sigma_e, coefficients
@@ -509,6 +518,11 @@ static slh_status setup(slh_solver* s) {
   s->n_part = dg_reduce_partials(4 * nc);
   ALLOC(s->dg_part, double, 2 * s->n_part + 2);
   ALLOC(s->cmax, double, kCensusBlocks);
+  if (p.boundary) {
+    ALLOC(s->refl_x, int, z.n_dir);
+    ALLOC(s->refl_y, int, z.n_dir);
+    ALLOC(s->bnd, double, (size_t)2 * z.n_dir * 2 * (p.nx + p.ny));
+  }
   ALLOC(s->dirs, double, 3 * z.n_dir);
   s->bank_mem[0] = s->dalloc(s->bank_bytes(z.cap));
   s->bank_mem[1] = s->dalloc(s->bank_bytes(z.cap));
@@ -550,6 +564,23 @@ static slh_status setup(slh_solver* s) {
     HIP_TRY(hipMemcpyAsync(s->ns_cell, s->h_ns.data(), 4 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->qn1, qn.data(), 32 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->dirs, dirs.data(), 8 * dirs.size(), hipMemcpyHostToDevice, st));
+  if (p.boundary) {
+    // mirror image of each direction in x (Ox -> -Ox) and in y (Oy -> -Oy):
+    // the product set is symmetric, so the nearest direction is exact
+    const int nd = z.n_dir;
+    s->h_refl.assign(2 * nd, 0);
+    for (int m = 0; m < nd; ++m) {
+      double bx = 1e300, by = 1e300;
+      for (int k = 0; k < nd; ++k) {
+        const double ex = fabs(dirs[3 * k] + dirs[3 * m]) + fabs(dirs[3 * k + 1] - dirs[3 * m + 1]);
+        const double ey = fabs(dirs[3 * k] - dirs[3 * m]) + fabs(dirs[3 * k + 1] + dirs[3 * m + 1]);
+        if (ex < bx) { bx = ex; s->h_refl[m] = k; }
+        if (ey < by) { by = ey; s->h_refl[nd + m] = k; }
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(s->refl_x, s->h_refl.data(), 4 * nd, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->refl_y, s->h_refl.data() + nd, 4 * nd, hipMemcpyHostToDevice, st));
+  }
   std::vector<int> mid;
   std::vector<double> mval;
   if (z.dg_table) {
@@ -606,6 +637,7 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   // n_s = -1: no scatter limit (the leg is plain implicit-capture MC)
   a.n_lim = kind == 1 ? s->n_lim_max : 0;
   a.ns_cell = kind == 1 ? s->ns_cell : nullptr;
+  a.bc = p.boundary;
   a.points = p.points;
   a.sobol = s->sobol;
   a.w_cut_rel = p.w_cut_rel;
@@ -693,6 +725,10 @@ static DgArgs dg_args(slh_solver* s) {
   d.dirmat = s->dirmat;
   d.n_chunks = (int)z.dg_chunks;
   d.loader_q = 1;  // one loader wave per sweeping wave
+  d.bc = s->prob.boundary;
+  d.refl_x = s->refl_x;
+  d.refl_y = s->refl_y;
+  d.bnd = s->bnd;
   d.st = s->st;
   return d;
 }
@@ -735,6 +771,10 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
                              hipMemcpyDeviceToHost, st));
       HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
       HIP_TRY(launch_si_begin(s->st, s->si_max, st));
+      if (s->bnd) {  // the first iteration reads buffer 1: zero reflected inflow
+        const long long nb = (long long)z.n_dir * 2 * (p.nx + p.ny);
+        HIP_TRY(launch_fill_f64(s->bnd + nb, nb, 0.0, st));
+      }
       HIP_TRY(launch_dg_source(dg_args(s), st));
       return enqueue_si(s, st, n_it);
     }

@@ -280,7 +280,23 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
     fetch(r2s);
     fetch(r3s);
   }
-  for (int k = threadIdx.x; k < 2 * (nx + ny); k += blockDim.x) xf[k] = 0.0;
+  // upwind faces: zero (vacuum) or, on a reflective side, the previous
+  // iteration's outflow of the mirrored direction
+  const size_t sb = (size_t)2 * (nx + ny);  // boundary traces per direction
+  const int it = g.bnd ? g.st->si_iter : 0;
+  const bool rx_in = (g.bc & (apos ? 1 : 2)) != 0, ry_in = (g.bc & (bpos ? 4 : 8)) != 0;
+  const bool rx_out = (g.bc & (apos ? 2 : 1)) != 0, ry_out = (g.bc & (bpos ? 8 : 4)) != 0;
+  const double* b_in = g.bnd ? g.bnd + (size_t)((it + 1) & 1) * g.n_dir * sb : nullptr;
+  double* b_out = g.bnd ? g.bnd + ((size_t)(it & 1) * g.n_dir + m) * sb : nullptr;
+  for (int k = threadIdx.x; k < 2 * (nx + ny); k += blockDim.x) {
+    double v = 0.0;
+    if (k < 2 * ny) {
+      if (rx_in) v = b_in[(size_t)g.refl_x[m] * sb + k];
+    } else if (ry_in) {
+      v = b_in[(size_t)g.refl_y[m] * sb + k];
+    }
+    xf[k] = v;  // yf = xf + 2 ny
+  }
   if (TABLE) {
     const double* src = g.coef + (size_t)m * g.n_mat * 32;
     for (int k = threadIdx.x; k < g.n_mat * 32; k += blockDim.x)
@@ -414,6 +430,15 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
       xf[2 * c_j + 1] = apos ? x3 : x2;
       yf[2 * c_i] = bpos ? x2 : x0;
       yf[2 * c_i + 1] = bpos ? x3 : x1;
+      // outflow on a reflective downwind side, for the mirrored direction
+      if (rx_out && c_i == (apos ? nx - 1 : 0)) {
+        b_out[2 * c_j] = apos ? x1 : x0;
+        b_out[2 * c_j + 1] = apos ? x3 : x2;
+      }
+      if (ry_out && c_j == (bpos ? ny - 1 : 0)) {
+        b_out[2 * ny + 2 * c_i] = bpos ? x2 : x0;
+        b_out[2 * ny + 2 * c_i + 1] = bpos ? x3 : x1;
+      }
       out[(long long)c_j * nx + c_i] = make_double4(wm * x0, wm * x1, wm * x2, wm * x3);
     }
     prepare((k + 1) & 1);

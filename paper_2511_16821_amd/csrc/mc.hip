@@ -357,12 +357,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         dcur++;
       }
     } else if (ev == EV_XFACE) {
+      // a reflective side mirrors the direction; the history stays in its cell
       py += oy * l;
-      if (ox > (R)0) { ix++; px = (R)0; } else { ix--; px = hx; }
+      if (ox > (R)0) {
+        if (ix == a.nx - 1 && (a.bc & 2)) { px = hx; ox = -ox; iox = -iox; }
+        else { ix++; px = (R)0; }
+      } else {
+        if (ix == 0 && (a.bc & 1)) { px = (R)0; ox = -ox; iox = -iox; }
+        else { ix--; px = hx; }
+      }
       if (ix < 0 || ix >= a.nx) end = END_LEAK;
     } else {
       px += ox * l;
-      if (oy > (R)0) { iy++; py = (R)0; } else { iy--; py = hy; }
+      if (oy > (R)0) {
+        if (iy == a.ny - 1 && (a.bc & 8)) { py = hy; oy = -oy; ioy = -ioy; }
+        else { iy++; py = (R)0; }
+      } else {
+        if (iy == 0 && (a.bc & 4)) { py = (R)0; oy = -oy; ioy = -ioy; }
+        else { iy--; py = hy; }
+      }
       if (iy < 0 || iy >= a.ny) end = END_LEAK;
     }
     if (end == END_NONE && fabs(w) < w_cut) end = END_CUTOFF;

@@ -278,6 +278,7 @@ struct PassArgs {
   int n_lim;             // scatter limit of the pass (0 for kind 2); with
                          // per-cell limits, the largest of them
   const int* ns_cell;    // per-cell limits (unlimited as INT_MAX), or null
+  int bc;                // reflective sides: 1 x_lo, 2 x_hi, 4 y_lo, 8 y_hi
   int points;            // 0 Sobol'-Owen, 1 pseudo-random
   const uint32_t* sobol; // direction numbers
   double w_cut_rel;
@@ -336,6 +337,15 @@ struct DgArgs {
   int cw;                // sweeping lanes per workgroup (multiple of 64, <= 256)
   int n_chunks;          // dg_chunks(nx, ny, cw)
   int loader_q;          // cells per loader lane (1..4, divides cw / 64)
+  // reflective sides (1 x_lo, 2 x_hi, 4 y_lo, 8 y_hi): the inflow of a
+  // direction on such a side is the outflow of its mirror image (refl_x,
+  // refl_y) from the previous iteration.  bnd holds two buffers of [n_dir]
+  // [2 ny x traces | 2 nx y traces], written in iterations of the parity of
+  // their index (null when no side reflects)
+  int bc;
+  const int* refl_x;
+  const int* refl_y;
+  double* bnd;
   DevState* st;          // si_done: skip the iteration; the reduction's decision
 };
 hipError_t launch_dg_tables(int n_dir, int n_mat, const double* dir, const double* sig_e_mat,

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libslh.so")
 
-SLH_ABI_VERSION = 2
+SLH_ABI_VERSION = 3
 SLH_OK, SLH_E_INVALID_ARG, SLH_E_OUT_OF_MEMORY, SLH_E_DEVICE, SLH_E_NOT_CONVERGED, \
     SLH_E_NUMERIC, SLH_E_REJECTED, SLH_E_STATE = range(8)
 SLH_FP64, SLH_FP32_TRACK = 0, 1
@@ -35,7 +35,8 @@ class slh_problem(C.Structure):
                 ("n_particles", C.c_int64), ("census_cap", C.c_int64),
                 ("sn_order", C.c_int32), ("time_closure", C.c_double), ("si_tol", C.c_double),
                 ("si_max_iter", C.c_int32), ("w_cut_rel", C.c_double), ("seed", C.c_uint64),
-                ("points", C.c_int32), ("precision", C.c_int32), ("n_s_cell", C.c_void_p)]
+                ("points", C.c_int32), ("precision", C.c_int32), ("n_s_cell", C.c_void_p),
+                ("boundary", C.c_int32)]
 
 
 class slh_balance(C.Structure):
@@ -173,6 +174,7 @@ def make_problem(p: dict):
     s.seed = int(p.get("seed", 0)) & (2 ** 64 - 1)
     s.points = int(p.get("points", 0))
     s.precision = int(p.get("precision", 0))
+    s.boundary = int(p.get("boundary", 0))
     keep = [ss, sa, q]
     if p.get("n_s_cell") is not None:
         nsc = np.ascontiguousarray(p["n_s_cell"], dtype=np.int32).reshape(-1)

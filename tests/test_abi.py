@@ -44,6 +44,7 @@ def test_validation_rejects_before_allocating(S):
         dict(precision=3), dict(w_cut_rel=-1.0), dict(x_hi=0.0),
         dict(n_s_cell=np.full(400, -2, dtype=np.int32)),
         dict(n_s_cell=np.full(400, 2_000_000, dtype=np.int32)),
+        dict(boundary=16), dict(boundary=-1),
     ]
     for upd in bad_cases:
         p = dict(good)

@@ -85,6 +85,22 @@ def test_halton_points_full_steps(S, oracle):
     _run_pair(S, oracle, p, 3)
 
 
+def test_reflective_sides(S, oracle):
+    """Reflective sides against the oracle: a checkerboard closed on all four
+    sides (nothing leaks), a box reflective on x_lo and y_lo only (a quarter
+    of a symmetric problem) with N_s = 1, and a per-cell-material mesh (the
+    sweep's cell mode) reflective on x_hi and y_hi."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=5, cells_per_block=4, n_s=2, n_particles=20000, dt=0.1,
+                       sn_order=6, boundary=15)
+    _run_pair(S, oracle, p, 3)
+    q = W.homogeneous_box(n=18, L=1.8, src_cells=((0, 3), (0, 3)), n_s=1, n_particles=15000,
+                          dt=0.1, sn_order=4, boundary=5)
+    _run_pair(S, oracle, q, 3)
+    r = _per_cell_problem(20, 14, 3, n_s=1, n_particles=12000, dt=0.1, sn_order=4, boundary=10)
+    _run_pair(S, oracle, r, 2)
+
+
 def test_cellwise_scatter_limit(S, oracle):
     """Space-dependent N_s(x) against the oracle: a material-dependent map on
     the checkerboard (absorbers 0, scatterers 3) and a random map that mixes

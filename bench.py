@@ -335,14 +335,16 @@ def cellwise_ns(S, torch, args):
 
 
 def reflective(S, torch, args):
-    """Reflective sides on C2 (all four sides, and x_lo + y_lo: the quarter of
-    a symmetric problem) against the vacuum case: time per step, segments/s
-    and the source iterations of the last step."""
+    """Reflective sides on the C1 box (20x20 on [0,2]^2, sigma_s = 1,
+    sigma_a = 0.1, central source, dt = 0.1, S_8; 1e6 particles per pass so
+    that histories reach the sides within the run) against the vacuum case:
+    all four sides, and x_lo + y_lo (the quarter of a symmetric problem).
+    Time per step, segments/s, source iterations of the last step, leakage."""
     from paper_2511_16821_amd import workloads as W
     steps = args.reflect_steps
     rows = []
     for name, bc in (("vacuum", 0), ("x_lo+y_lo", 5), ("all four", 15)):
-        p = W.c2(n_s=args.ns, n_steps=steps, boundary=bc)
+        p = W.c1(n_s=args.ns, n_steps=steps, boundary=bc, n_particles=10 ** 6)
         s = S.Solver(p)
         s.advance(2)
         s.synchronize()
@@ -361,7 +363,7 @@ def reflective(S, torch, args):
         s.destroy()
         log("reflective:", json.dumps(row))
         rows.append(row)
-    return {"workload": "C2 checkerboard (140x140, N_s=%d, 1e6 particles/pass, dt=0.05, S_12), "
+    return {"workload": "C1 box (20x20 on [0,2]^2, N_s=%d, 1e6 particles/pass, dt=0.1, S_8), "
                         "%d timed steps after 2" % (args.ns, steps), "rows": rows}
 
 
@@ -518,8 +520,8 @@ def main():
     ap.add_argument("--protocol-dt", type=float, default=0.1)
     ap.add_argument("--protocol-seeds", type=int, default=4)
     ap.add_argument("--reflect", action="store_true",
-                    help="reflective sides on C2 against vacuum")
-    ap.add_argument("--reflect-steps", type=int, default=20)
+                    help="reflective sides on the C1 box against vacuum")
+    ap.add_argument("--reflect-steps", type=int, default=10)
     ap.add_argument("--nsx", action="store_true",
                     help="space-dependent N_s(x) on the C3 medium against uniform limits")
     ap.add_argument("--nsx-ns", default="0,1,2,4")

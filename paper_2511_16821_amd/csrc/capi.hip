@@ -694,7 +694,7 @@ static slh_status collect_all(slh_solver* s) {
 //       of source iterations of the collided solve, ending with a copy of the
 //       device's iteration state to pinned host memory
 //   --  host wait; extra batches only if the first did not finish
-//   B1  remap source and its sum tree, emission of the remap leg
+//   B1  remap source with its majorant and count trees, emission of the remap leg
 //   --  MC pass 2 (direct launch between timing events)
 //   B2  tally -> flux, snapshot, census thinning and compaction, step + 1
 // Every part reads its step-dependent values (step counter, counts, flags)
@@ -754,28 +754,19 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
   const long long n_tally = (long long)z.n_copies * kTallyStride * nc;
   switch (part) {
     case kA1: {
-      HIP_TRY(launch_pass_begin(s->st, s->tree1, cdt, st));
-      HIP_TRY(launch_fill_u64(s->Tpre, n_tally, 0ull, st));
-      HIP_TRY(launch_fill_u64(s->Tpost, n_tally, 0ull, st));
+      HIP_TRY(launch_pass_prep(s->st, s->tree1, cdt, s->Tpre, n_tally, s->Tpost, n_tally,
+                               nullptr, 0, st));
       HIP_TRY(launch_emit(pass_args(s, 1), z.fp32, st));
       return SLH_OK;
     }
     case kA2: {
-      HIP_TRY(launch_tally_to_flux(s->Tpre, nc, z.n_copies, cstride, s->st, inv_adt,
-                                   s->phi_pre, st));
-      HIP_TRY(launch_tally_to_flux(s->Tpost, nc, z.n_copies, cstride, s->st, inv_adt,
-                                   s->phi_post, st));
+      HIP_TRY(launch_tally_to_flux(s->Tpre, s->phi_pre, s->Tpost, s->phi_post, nc, z.n_copies,
+                                   cstride, s->st, inv_adt, st));
       hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
                          s->bal_store + 0);
       HIP_TRY(hipMemcpyAsync(s->h_bal + 0, s->bal_store + 0, sizeof(BalStore),
                              hipMemcpyDeviceToHost, st));
-      HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
-      HIP_TRY(launch_si_begin(s->st, s->si_max, st));
-      if (s->bnd) {  // the first iteration reads buffer 1: zero reflected inflow
-        const long long nb = (long long)z.n_dir * 2 * (p.nx + p.ny);
-        HIP_TRY(launch_fill_f64(s->bnd + nb, nb, 0.0, st));
-      }
-      HIP_TRY(launch_dg_source(dg_args(s), st));
+      HIP_TRY(launch_si_start(dg_args(s), s->si_max, st));
       return enqueue_si(s, st, n_it);
     }
     case kB1: {
@@ -783,15 +774,14 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
                                   s->qnR, st));
       HIP_TRY(launch_build_tree(s->qnR, nc, s->adt, s->treeR, st));
       HIP_TRY(launch_count_tree(s->treeR, nc, z.n_p, s->ctreeR, st));
-      HIP_TRY(launch_pass_begin(s->st, s->treeR, cdt, st));
-      HIP_TRY(launch_fill_u64(s->TR, n_tally, 0ull, st));
-      HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
+      HIP_TRY(launch_pass_prep(s->st, s->treeR, cdt, s->TR, n_tally, nullptr, 0, s->alive,
+                               z.n_cand, st));
       HIP_TRY(launch_emit(pass_args(s, 2), z.fp32, st));
       return SLH_OK;
     }
     default: {  // kB2: the remap census is the state at t_{n+1} (capped)
-      HIP_TRY(launch_tally_to_flux(s->TR, nc, z.n_copies, cstride, s->st, inv_adt, s->phi_R,
-                                   st));
+      HIP_TRY(launch_tally_to_flux(s->TR, s->phi_R, nullptr, nullptr, nc, z.n_copies, cstride,
+                                   s->st, inv_adt, st));
       hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
                          s->bal_store + 1);
       HIP_TRY(hipMemcpyAsync(s->h_bal + 1, s->bal_store + 1, sizeof(BalStore),
@@ -813,7 +803,6 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
                                               st));
       }
       HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, z.cap, s->cmax, st));
-      HIP_TRY(launch_step_end(s->st, st));
       return SLH_OK;
     }
   }

@@ -48,23 +48,33 @@ __device__ __forceinline__ double recip(double a) {
   return r;
 }
 
-// Nodal source of the collided equation for the first iterate of a step:
-// S = sigma_s/(4 pi) (phi_c + phi_post); later iterates get theirs from the
-// flux reduction.
-__global__ void k_dg_source(long long n, const double* __restrict__ sig_s,
-                            const double* __restrict__ phi_post,
-                            const double* __restrict__ phi_c, double* __restrict__ S,
-                            const DevState* st) {
-  if (st->si_done) return;
-  const double inv4pi = 0.25 / M_PI;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const double ssc = sig_s[i] * inv4pi;
-    const double pp = phi_post[i];
-    const double4 f = reinterpret_cast<const double4*>(phi_c)[i];
-    reinterpret_cast<double4*>(S)[i] = make_double4(ssc * (f.x + pp), ssc * (f.y + pp),
-                                                    ssc * (f.z + pp), ssc * (f.w + pp));
+// Start of a step's source iteration: phi_c = 0, the iteration state reset
+// (block 0), the nodal source of the first iterate
+// S = sigma_s/(4 pi) (phi_c + phi_post) with phi_c = 0 (later iterates get
+// theirs from the flux reduction), and with reflective sides the buffer of
+// reflected traces that the first sweep reads set to zero.
+__global__ void k_si_start(long long n, const double* __restrict__ sig_s,
+                           const double* __restrict__ phi_post, double* __restrict__ phi_c,
+                           double* __restrict__ S, double* __restrict__ bnd0, long long n_bnd,
+                           DevState* st, int si_max) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->si_iter = 0;
+    st->si_conv = si_max == 0 ? 1 : 0;
+    st->si_done = si_max == 0 ? 1 : 0;
+    st->si_bad = 0;
+    st->si_dn2 = 0.0;
+    st->si_nrm2 = 0.0;
   }
+  const double inv4pi = 0.25 / M_PI;
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long str = (long long)gridDim.x * blockDim.x;
+  for (long long i = i0; i < n; i += str) {
+    const double ssc = sig_s[i] * inv4pi;
+    const double v = ssc * (0.0 + phi_post[i]);
+    reinterpret_cast<double4*>(phi_c)[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    reinterpret_cast<double4*>(S)[i] = make_double4(v, v, v, v);
+  }
+  for (long long k = i0; k < n_bnd; k += str) bnd0[k] = 0.0;
 }
 
 // Direction part of the element: A0 and F (row-major 4x4 each) and the mass
@@ -182,7 +192,7 @@ struct DgStage {
   int C[Q];
 };
 
-template <bool TABLE, int Q>
+template <bool TABLE, int Q, bool REFL>
 __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
   if (g.st->si_done) return;  // the whole workgroup: no barrier is left pending
   extern __shared__ double smem[];
@@ -282,20 +292,27 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
   }
   // upwind faces: zero (vacuum) or, on a reflective side, the previous
   // iteration's outflow of the mirrored direction
+  // (REFL: some side reflects and g.bnd holds the traces)
   const size_t sb = (size_t)2 * (nx + ny);  // boundary traces per direction
-  const int it = g.bnd ? g.st->si_iter : 0;
-  const bool rx_in = (g.bc & (apos ? 1 : 2)) != 0, ry_in = (g.bc & (bpos ? 4 : 8)) != 0;
-  const bool rx_out = (g.bc & (apos ? 2 : 1)) != 0, ry_out = (g.bc & (bpos ? 8 : 4)) != 0;
-  const double* b_in = g.bnd ? g.bnd + (size_t)((it + 1) & 1) * g.n_dir * sb : nullptr;
-  double* b_out = g.bnd ? g.bnd + ((size_t)(it & 1) * g.n_dir + m) * sb : nullptr;
-  for (int k = threadIdx.x; k < 2 * (nx + ny); k += blockDim.x) {
-    double v = 0.0;
-    if (k < 2 * ny) {
-      if (rx_in) v = b_in[(size_t)g.refl_x[m] * sb + k];
-    } else if (ry_in) {
-      v = b_in[(size_t)g.refl_y[m] * sb + k];
+  const int it = REFL ? g.st->si_iter : 0;
+  const bool rx_in = REFL && (g.bc & (apos ? 1 : 2)) != 0;
+  const bool ry_in = REFL && (g.bc & (bpos ? 4 : 8)) != 0;
+  const bool rx_out = REFL && (g.bc & (apos ? 2 : 1)) != 0;
+  const bool ry_out = REFL && (g.bc & (bpos ? 8 : 4)) != 0;
+  const double* b_in = REFL ? g.bnd + (size_t)((it + 1) & 1) * g.n_dir * sb : nullptr;
+  double* b_out = REFL ? g.bnd + ((size_t)(it & 1) * g.n_dir + m) * sb : nullptr;
+  if (rx_in || ry_in) {
+    for (int k = threadIdx.x; k < 2 * (nx + ny); k += blockDim.x) {
+      double v = 0.0;
+      if (k < 2 * ny) {
+        if (rx_in) v = b_in[(size_t)g.refl_x[m] * sb + k];
+      } else if (ry_in) {
+        v = b_in[(size_t)g.refl_y[m] * sb + k];
+      }
+      xf[k] = v;  // yf = xf + 2 ny
     }
-    xf[k] = v;  // yf = xf + 2 ny
+  } else {
+    for (int k = threadIdx.x; k < 2 * (nx + ny); k += blockDim.x) xf[k] = 0.0;
   }
   if (TABLE) {
     const double* src = g.coef + (size_t)m * g.n_mat * 32;
@@ -431,13 +448,17 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
       yf[2 * c_i] = bpos ? x2 : x0;
       yf[2 * c_i + 1] = bpos ? x3 : x1;
       // outflow on a reflective downwind side, for the mirrored direction
-      if (rx_out && c_i == (apos ? nx - 1 : 0)) {
-        b_out[2 * c_j] = apos ? x1 : x0;
-        b_out[2 * c_j + 1] = apos ? x3 : x2;
+      if (REFL && rx_out) {
+        if (c_i == (apos ? nx - 1 : 0)) {
+          b_out[2 * c_j] = apos ? x1 : x0;
+          b_out[2 * c_j + 1] = apos ? x3 : x2;
+        }
       }
-      if (ry_out && c_j == (bpos ? ny - 1 : 0)) {
-        b_out[2 * ny + 2 * c_i] = bpos ? x2 : x0;
-        b_out[2 * ny + 2 * c_i + 1] = bpos ? x3 : x1;
+      if (REFL && ry_out) {
+        if (c_j == (bpos ? ny - 1 : 0)) {
+          b_out[2 * ny + 2 * c_i] = bpos ? x2 : x0;
+          b_out[2 * ny + 2 * c_i + 1] = bpos ? x3 : x1;
+        }
       }
       out[(long long)c_j * nx + c_i] = make_double4(wm * x0, wm * x1, wm * x2, wm * x3);
     }
@@ -454,12 +475,13 @@ size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny) {
                            (size_t)2 * (nx + ny));
 }
 
-hipError_t launch_dg_source(const DgArgs& a, hipStream_t s) {
+hipError_t launch_si_start(const DgArgs& a, int si_max, hipStream_t s) {
   const long long nc = (long long)a.nx * a.ny;
   long long b = (nc + 255) / 256;
   const int grid = (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
-  hipLaunchKernelGGL(k_dg_source, dim3(grid), dim3(256), 0, s, nc, a.sig_s, a.phi_post,
-                     (const double*)a.phi_c, a.src, (const DevState*)a.st);
+  const long long nb = a.bnd ? (long long)a.n_dir * 2 * (a.nx + a.ny) : 0;
+  hipLaunchKernelGGL(k_si_start, dim3(grid), dim3(256), 0, s, nc, a.sig_s, a.phi_post, a.phi_c,
+                     a.src, a.bnd ? a.bnd + nb : nullptr, nb, a.st, si_max);
   return hipGetLastError();
 }
 
@@ -469,7 +491,12 @@ hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   const int q = a.loader_q;  // cells per loader lane; n_sw / q loader waves
   if (q < 1 || n_sw % q) return hipErrorInvalidValue;
   const dim3 block(a.cw + 64 * (n_sw / q));
-#define SLH_DG_SWEEP(T_, Q_) hipLaunchKernelGGL((k_dg_sweep_pc<T_, Q_>), dim3(a.n_dir), block, lds, s, a)
+  const bool refl = a.bc != 0 && a.bnd != nullptr;
+#define SLH_DG_SWEEP(T_, Q_)                                                                  \
+  do {                                                                                        \
+    if (refl) hipLaunchKernelGGL((k_dg_sweep_pc<T_, Q_, true>), dim3(a.n_dir), block, lds, s, a); \
+    else hipLaunchKernelGGL((k_dg_sweep_pc<T_, Q_, false>), dim3(a.n_dir), block, lds, s, a);     \
+  } while (0)
   if (table) {
     if (q == 1) SLH_DG_SWEEP(true, 1);
     else if (q == 2) SLH_DG_SWEEP(true, 2);

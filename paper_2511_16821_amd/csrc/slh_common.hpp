@@ -352,15 +352,15 @@ hipError_t launch_dg_tables(int n_dir, int n_mat, const double* dir, const doubl
                             double hx, double hy, double* dirmat, double* coef, hipStream_t s);
 long long dg_chunks(int nx, int ny, int cw);
 size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny);
-// The first iterate's nodal source of a step, from phi_c and phi_post.
-hipError_t launch_dg_source(const DgArgs& a, hipStream_t s);
+// Start of a step's source iteration: phi_c = 0, iteration state reset, the
+// first iterate's nodal source, reflected traces of the first sweep zeroed.
+hipError_t launch_si_start(const DgArgs& a, int si_max, hipStream_t s);
 hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s);
 // One reduction of a source iteration: phi_c is replaced in place by the
 // direction sum of the planes, the next iterate's source is formed, and the
 // residual decides st->si_done (n_part blocks, dg_reduce_partials).
 hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, double si_tol,
                             int si_max, hipStream_t s);
-hipError_t launch_si_begin(DevState* st, int si_max, hipStream_t s);
 int dg_reduce_partials(long long n_nodes);
 
 // util.hip
@@ -368,10 +368,16 @@ hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long lon
                            hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, long long n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t s);
-hipError_t launch_pass_begin(DevState* st, const double* tree, double cdt, hipStream_t s);
-hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, int n_copies,
-                                long long copy_stride, const DevState* st, double inv_adt,
-                                double* phi, hipStream_t s);
+// Pass set-up (counters, balance, fixed-point units from the tree's total and
+// the census bound) with the clears of up to two tally arrays and a byte array.
+hipError_t launch_pass_prep(DevState* st, const double* tree, double cdt,
+                            unsigned long long* a, long long na, unsigned long long* b,
+                            long long nb, uint8_t* c, long long nc, hipStream_t s);
+// phi = tally * unit / (A dt) for T0 -> phi0 and, when T1 is not null, T1 -> phi1.
+hipError_t launch_tally_to_flux(const unsigned long long* T0, double* phi0,
+                                const unsigned long long* T1, double* phi1, long long n,
+                                int n_copies, long long copy_stride, const DevState* st,
+                                double inv_adt, hipStream_t s);
 hipError_t launch_remap_source(long long n, const double* q, const double* sig_s,
                                const double* phi_pre, const double* phi_post,
                                const double* phi_c, double* qn, hipStream_t s);
@@ -389,7 +395,6 @@ hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hip
 hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long long n,
                                uint64_t seed, const DevState* st, long long* flags,
                                hipStream_t s);
-hipError_t launch_step_end(DevState* st, hipStream_t s);
 template <typename R>
 hipError_t launch_census_compact(const Bank<R>& src, const long long* incl, long long n,
                                  long long cap, Bank<R> dst, DevState* st, double* bmax,

@@ -47,24 +47,44 @@ __device__ __forceinline__ void unit_for(double bound, double& unit, double& inv
   inv = ldexp(1.0, 61 - e);
 }
 
-__global__ void k_pass_begin(DevState* st, const double* tree, double cdt) {
-  const int t = threadIdx.x;
-  if (t < 2 * B_NFIELDS) st->bal[t] = 0ull;
-  if (t == 0) {
-    const double total = tree[1];
-    const double W = (double)st->n_in * st->maxabs_w + total;
-    unit_for(W, st->unit_W, st->inv_W);
-    unit_for(W * cdt, st->unit_T, st->inv_T);
-    st->work = 0ull;
-    st->segments = 0ull;
-    st->particles = 0ull;
-    st->killed = 0ull;
-    st->alive = 0ull;
+// Pass set-up fused with the clears the pass needs: block 0 resets the
+// pass counters and balance and sets the fixed-point units from the bounds;
+// every block clears its share of up to two tally arrays and a byte array.
+__global__ void k_pass_prep(DevState* st, const double* tree, double cdt,
+                            unsigned long long* __restrict__ a, long long na,
+                            unsigned long long* __restrict__ b, long long nb,
+                            uint8_t* __restrict__ c, long long nc) {
+  if (blockIdx.x == 0) {
+    const int t = threadIdx.x;
+    if (t < 2 * B_NFIELDS) st->bal[t] = 0ull;
+    if (t == 0) {
+      const double total = tree[1];
+      const double W = (double)st->n_in * st->maxabs_w + total;
+      unit_for(W, st->unit_W, st->inv_W);
+      unit_for(W * cdt, st->unit_T, st->inv_T);
+      st->work = 0ull;
+      st->segments = 0ull;
+      st->particles = 0ull;
+      st->killed = 0ull;
+      st->alive = 0ull;
+    }
   }
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long str = (long long)gridDim.x * blockDim.x;
+  for (long long i = i0; i < na; i += str) a[i] = 0ull;
+  for (long long i = i0; i < nb; i += str) b[i] = 0ull;
+  for (long long i = i0; i < nc; i += str) c[i] = 0;
 }
 
-hipError_t launch_pass_begin(DevState* st, const double* tree, double cdt, hipStream_t s) {
-  hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, st, tree, cdt);
+hipError_t launch_pass_prep(DevState* st, const double* tree, double cdt,
+                            unsigned long long* a, long long na, unsigned long long* b,
+                            long long nb, uint8_t* c, long long nc, hipStream_t s) {
+  long long n = na > nb ? na : nb;
+  n = n > nc ? n : nc;
+  long long g = (n + 255) / 256;
+  const int grid = (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
+  hipLaunchKernelGGL(k_pass_prep, dim3(grid), dim3(256), 0, s, st, tree, cdt, a, na, b, nb, c,
+                     nc);
   return hipGetLastError();
 }
 
@@ -73,11 +93,15 @@ hipError_t launch_pass_begin(DevState* st, const double* tree, double cdt, hipSt
 // loads in flight per lane) and the four partial sums meet in LDS.  Integer
 // addition makes the result independent of this split.
 constexpr int kT2fCells = 64;
-__global__ __launch_bounds__(256) void k_tally_to_flux(const unsigned long long* __restrict__ T,
-                                                       long long n, int n_copies,
-                                                       long long copy_stride,
-                                                       const DevState* st, double inv_adt,
-                                                       double* __restrict__ phi) {
+__global__ __launch_bounds__(256) void k_tally_to_flux(const unsigned long long* __restrict__ T0,
+                                                       double* __restrict__ phi0,
+                                                       const unsigned long long* __restrict__ T1,
+                                                       double* __restrict__ phi1, long long n,
+                                                       int n_copies, long long copy_stride,
+                                                       const DevState* st, double inv_adt) {
+  // blockIdx.y picks one of two tallies decoded by the same launch
+  const unsigned long long* __restrict__ T = blockIdx.y ? T1 : T0;
+  double* __restrict__ phi = blockIdx.y ? phi1 : phi0;
   __shared__ unsigned long long s_part[4][kT2fCells];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long long i = (long long)blockIdx.x * kT2fCells + lane;
@@ -101,14 +125,15 @@ __global__ __launch_bounds__(256) void k_tally_to_flux(const unsigned long long*
   }
 }
 
-hipError_t launch_tally_to_flux(const unsigned long long* T, long long n, int n_copies,
-                                long long copy_stride, const DevState* st, double inv_adt,
-                                double* phi, hipStream_t s) {
+hipError_t launch_tally_to_flux(const unsigned long long* T0, double* phi0,
+                                const unsigned long long* T1, double* phi1, long long n,
+                                int n_copies, long long copy_stride, const DevState* st,
+                                double inv_adt, hipStream_t s) {
   if (n < 1) return hipSuccess;
   const long long b = (n + kT2fCells - 1) / kT2fCells;
   if (b > 0x7fffffffll) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tally_to_flux, dim3((unsigned)b), dim3(256), 0, s, T, n, n_copies,
-                     copy_stride, st, inv_adt, phi);
+  hipLaunchKernelGGL(k_tally_to_flux, dim3((unsigned)b, T1 ? 2 : 1), dim3(256), 0, s, T0, phi0,
+                     T1, phi1, n, n_copies, copy_stride, st, inv_adt);
   return hipGetLastError();
 }
 
@@ -380,33 +405,6 @@ hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long l
   return hipGetLastError();
 }
 
-// End of a time step on the device: the step counter that seeds the point
-// streams advances.
-__global__ void k_step_end(DevState* st) {
-  if (threadIdx.x == 0) st->step += 1;
-}
-
-hipError_t launch_step_end(DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, st);
-  return hipGetLastError();
-}
-
-// Start of the source iteration: phi_c = 0 is filled by the caller.
-__global__ void k_si_begin(DevState* st, int si_max) {
-  if (threadIdx.x == 0) {
-    st->si_iter = 0;
-    st->si_conv = si_max == 0 ? 1 : 0;
-    st->si_done = si_max == 0 ? 1 : 0;
-    st->si_bad = 0;
-    st->si_dn2 = 0.0;
-    st->si_nrm2 = 0.0;
-  }
-}
-
-hipError_t launch_si_begin(DevState* st, int si_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_si_begin, dim3(1), dim3(1), 0, s, st, si_max);
-  return hipGetLastError();
-}
 
 // Blocks of the compaction grid; each leaves the max |w| it wrote in bmax.
 int census_compact_blocks(long long n) {
@@ -462,7 +460,8 @@ template hipError_t launch_census_compact<float>(const Bank<float>&, const long 
                                                  long long, long long, Bank<float>, DevState*,
                                                  double*, hipStream_t);
 
-// Census count and max |w| of the new bank (max over the compaction blocks).
+// Census count and max |w| of the new bank (max over the compaction blocks),
+// and the end of the time step.
 __global__ __launch_bounds__(256) void k_census_finish(DevState* st, const long long* incl,
                                                        long long n, long long cap,
                                                        const double* bmax, int nb) {
@@ -478,6 +477,7 @@ __global__ __launch_bounds__(256) void k_census_finish(DevState* st, const long 
   st->n_in = k > cap ? cap : k;
   st->n_kept = st->n_in;
   st->maxabs_w = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
+  st->step += 1;  // end of the time step: the step counter that seeds the point streams
 }
 
 hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,

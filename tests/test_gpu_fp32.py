@@ -58,3 +58,14 @@ def test_fp32_thick_voids(S, oracle):
     from paper_2511_16821_amd import workloads as W
     p = W.thick_with_voids(n=32, n_s=4, n_particles=40000, dt=0.01, src_half=4, sn_order=4)
     _run(S, oracle, p, 4)
+
+
+def test_fp32_with_halton_cellwise_limit_and_reflective_sides(S, oracle):
+    """FP32 tracking with the options beyond the paper's examples at once:
+    Halton points, a material-dependent N_s(x) and reflective x_lo / y_hi."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=5, cells_per_block=4, n_s=2, n_particles=20000, dt=0.1,
+                       sn_order=6, points=2, boundary=9)
+    ss = np.asarray(p["sigma_s"], dtype=np.float64).ravel()
+    p["n_s_cell"] = np.where(ss > 0, 3, 0).astype(np.int32)
+    _run(S, oracle, p, 3)

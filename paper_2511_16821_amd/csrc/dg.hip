@@ -23,7 +23,7 @@
 // loader waves (Q cells per loader lane).  The loaders keep several chunks of
 // nodal sources and material keys in flight in registers and hand each chunk
 // over through a two-slot LDS buffer, so the sweeping waves never wait on
-// global memory: their only global accesses are the stores of w_m psi_m (a
+// global memory: their only global accesses are the stores of psi_m (a
 // wave that mixed loads and stores would have to drain all of them before
 // using a loaded value).  After each barrier a sweeping lane turns the upwind
 // traces into its cell's solution with the element data prepared before the
@@ -32,9 +32,9 @@
 //     a per-(direction, material) table staged in LDS (few distinct sigma_e);
 //     the loader hands over B S instead of S;
 //   cell mode: A is LU-factorised before the barrier and solved after it.
-// The weighted solution goes to a per-direction plane, and the directions
-// are summed in a fixed order by a second kernel, so the scalar flux does
-// not depend on scheduling.
+// The solution goes to a per-direction plane, and a second kernel sums
+// w_m psi_m over the directions in a fixed order, so the scalar flux does not
+// depend on scheduling.
 #include "slh_common.hpp"
 
 namespace slh {
@@ -192,17 +192,17 @@ struct DgStage {
   int C[Q];
 };
 
-template <bool TABLE, int Q, bool REFL>
-__global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
-  if (g.st->si_done) return;  // the whole workgroup: no barrier is left pending
+// The sweep of one direction, compiled for each quadrant (APOS: Omega_x > 0,
+// BPOS: Omega_y > 0), so that the upwind order costs no selects.
+template <bool TABLE, int Q, bool REFL, bool APOS, bool BPOS>
+__device__ __forceinline__ void sweep_dir(const DgArgs& g) {
   extern __shared__ double smem[];
   const int nx = g.nx, ny = g.ny;
   const int CW = g.cw;       // sweeping lanes, multiple of 64, <= 256
   const int n_sw = CW >> 6;  // sweeping waves; the loader waves follow them
   const int n_ld = n_sw / Q; // loader waves, Q cells per loader lane and chunk
   const int m = blockIdx.x;
-  const double a = g.dir[3 * m + 0], b = g.dir[3 * m + 1], wm = g.dir[3 * m + 2];
-  const bool apos = a > 0.0, bpos = b > 0.0;
+  constexpr bool apos = APOS, bpos = BPOS;
   // LDS: slots S [2][CW] as two double2 halves | keys [2][CW] | coef [n_mat][kDgRow] | faces
   // (the source halves and the table rows are laid out so that a wave's
   // accesses fall in distinct banks: 16-byte lane stride, rows offset by
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
           b_out[2 * ny + 2 * c_i + 1] = bpos ? x3 : x1;
         }
       }
-      out[(long long)c_j * nx + c_i] = make_double4(wm * x0, wm * x1, wm * x2, wm * x3);
+      out[(long long)c_j * nx + c_i] = make_double4(x0, x1, x2, x3);
     }
     prepare((k + 1) & 1);
   }
@@ -468,6 +468,20 @@ __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
   // compiler's wait counting cannot follow a mix of pending loads and stores,
   // and would otherwise wait for every load of the loader's ring.
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+template <bool TABLE, int Q, bool REFL>
+__global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
+  if (g.st->si_done) return;  // the whole workgroup: no barrier is left pending
+  const int m = blockIdx.x;
+  const bool apos = g.dir[3 * m + 0] > 0.0, bpos = g.dir[3 * m + 1] > 0.0;
+  if (apos) {
+    if (bpos) sweep_dir<TABLE, Q, REFL, true, true>(g);
+    else sweep_dir<TABLE, Q, REFL, true, false>(g);
+  } else {
+    if (bpos) sweep_dir<TABLE, Q, REFL, false, true>(g);
+    else sweep_dir<TABLE, Q, REFL, false, false>(g);
+  }
 }
 
 size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny) {
@@ -512,7 +526,7 @@ hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   return hipGetLastError();
 }
 
-// phi_new[k] = sum_m psi[m][k] in direction order, in place; the next
+// phi_new[k] = sum_m w_m psi[m][k] in direction order, in place; the next
 // iterate's nodal source S = sigma_s/(4 pi) (phi_new + phi_post) (unused when
 // the iteration stops here); block partials of |phi_new - phi_old|^2 and
 // |phi_new|^2.
@@ -524,7 +538,8 @@ int dg_reduce_partials(long long n_nodes) {
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
-    int n_dir, long long n_nodes, const double* __restrict__ psi, double* __restrict__ phi,
+    int n_dir, long long n_nodes, const double* __restrict__ psi,
+    const double* __restrict__ dir, double* __restrict__ phi,
     const double* __restrict__ sig_s, const double* __restrict__ phi_post,
     double* __restrict__ S, double* __restrict__ partials, const DevState* st) {
   if (st->si_done) return;
@@ -541,9 +556,9 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
 #pragma unroll
       for (int u = 0; u < 8; ++u) t[u] = psi[(long long)(m + u) * n_nodes + k];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v += t[u];
+      for (int u = 0; u < 8; ++u) v += dir[3 * (m + u) + 2] * t[u];
     }
-    for (; m < n_dir; ++m) v += psi[(long long)m * n_nodes + k];
+    for (; m < n_dir; ++m) v += dir[3 * m + 2] * psi[(long long)m * n_nodes + k];
     const double d = v - phi[k];  // in place: the sweep read only S
     phi[k] = v;
     S[k] = sig_s[k >> 2] * inv4pi * (v + phi_post[k >> 2]);
@@ -606,7 +621,7 @@ __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int
 hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, double si_tol,
                             int si_max, hipStream_t s) {
   hipLaunchKernelGGL(k_dg_reduce, dim3(n_part), dim3(kRedBlock), 0, s, a.n_dir,
-                     4ll * a.nx * a.ny, (const double*)a.psi, a.phi_c, a.sig_s, a.phi_post,
+                     4ll * a.nx * a.ny, (const double*)a.psi, a.dir, a.phi_c, a.sig_s, a.phi_post,
                      a.src, partials, (const DevState*)a.st);
   hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,
                      a.st, si_tol, si_max);

@@ -328,7 +328,7 @@ struct DgArgs {
   const double* phi_post;// per cell
   double* phi_c;         // nodal [cell][4]: the collided iterate, updated in place
   double* src;           // nodal [cell][4] scratch: sigma_s/(4 pi)(phi_c + phi_post)
-  double* psi;           // [m][cell][4] (w_m psi_m)
+  double* psi;           // [m][cell][4] (psi_m; the reduction applies w_m)
   const double* dirmat;  // [m][32]: A0 then F (uniform mesh)
   // table mode: material of each cell and [m][material][32] = B then G
   const int* mat_id;

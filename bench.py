@@ -423,6 +423,71 @@ def protocol(S, torch, args):
             "rows": rows}
 
 
+def steady_protocol(S, torch, args):
+    """The paper's own setting (Sec. 3, Table 1): steady state (one infinite
+    time step), N_s in {0, 5, 10, 20, unlimited}, S_4, on the two stand-ins:
+    the multi-region slab (80 cells) and the bent duct (30 x 50 cells).  For
+    each N_s: the relative L2 error of phi_R against a 2^22-particle run of the
+    same method, RMS over seeds, for Owen-scrambled Sobol', shifted Halton and
+    pseudo-random points at 2^10 .. 2^18 particles, the fitted slopes, the
+    time per solve, and the source-iteration count with the whole-flux
+    stopping test (tolerance 1e-6) and, for comparison, the collided-only
+    test at the same tolerance."""
+    import numpy as np
+    from paper_2511_16821_amd import workloads as W
+    ns_list = [int(v) for v in args.steady_ns.split(",") if v != ""]
+    ladder = [2 ** k for k in range(10, 19, 2)]
+    out = {}
+    for name, make in (("slab", W.slab_regions), ("duct", W.duct)):
+        rows = []
+        for ns in ns_list:
+            base = make(n_s=ns, si_norm=1, si_tol=1e-6)
+
+            def run(n, points, seed, **kw):
+                p = dict(base)
+                p.update(n_particles=int(n), points=points, seed=int(seed), **kw)
+                s = S.Solver(p, torch_allocator=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.advance(1, allow_not_converged=True)
+                f = s.get_flux(0)
+                t = time.perf_counter() - t0
+                it = s.get_stats()["si_iterations"]
+                s.destroy()
+                return f, t, it
+
+            ref, _, it_ref = run(2 ** 22, 0, 7777)
+            _, _, it_coll = run(2 ** 16, 0, 7777, si_norm=0)
+            nref = max(np.linalg.norm(ref), 1e-300)
+            row = {"n_s": ns, "particles": ladder, "si_iterations": it_ref,
+                   "si_iterations_collided_test": it_coll}
+            for pname, mode in (("qmc", 0), ("halton", 2), ("mc", 1)):
+                errs, times = [], []
+                for n in ladder:
+                    e2, tt = 0.0, []
+                    for r in range(args.protocol_seeds):
+                        f, t, _ = run(n, mode, 1000 + 17 * r)
+                        e2 += float(np.linalg.norm(f - ref) / nref) ** 2
+                        tt.append(t)
+                    errs.append((e2 / args.protocol_seeds) ** 0.5)
+                    times.append(1e3 * float(np.median(tt)))
+                slope = -float(np.polyfit(np.log(ladder), np.log(errs), 1)[0])
+                row[pname] = {"rel_l2": errs, "alpha": slope, "ms_per_solve": times}
+            log("steady protocol:", name, json.dumps(row))
+            rows.append(row)
+        out[name] = rows
+    out["workloads"] = {
+        "slab": "steady slab, 80 cells on [0,8] (regions: absorber with source sigma_a=20 Q=20; "
+                "absorber sigma_a=3; void; scatterer sigma_s=0.8 sigma_a=0.2 Q=1; scatterer "
+                "sigma_s=0.95 sigma_a=0.05), reflective at x=0 and in y, S_4, horizon 200",
+        "duct": "steady bent duct, 30x50 cells on [0,3]x[0,5], duct sigma_s=sigma_a=1e-4, "
+                "medium sigma_s=0.9 sigma_a=0.1, unit source in the duct's first 0.5x0.5, "
+                "vacuum sides, S_4, horizon 200",
+        "error": "relative L2 of phi_R against a 2^22-particle Sobol'-Owen run of the same "
+                 "method, RMS over %d seeds" % args.protocol_seeds}
+    return out
+
+
 def serve_bench(S, torch, args):
     """Poisson arrivals of mixed solve requests; continuous batching on the
     server vs the same stream served one solve at a time on the same GPU
@@ -519,6 +584,9 @@ def main():
     ap.add_argument("--protocol-steps", type=int, default=10)
     ap.add_argument("--protocol-dt", type=float, default=0.1)
     ap.add_argument("--protocol-seeds", type=int, default=4)
+    ap.add_argument("--steady", action="store_true",
+                    help="the paper's steady-state protocol on the slab and duct stand-ins")
+    ap.add_argument("--steady-ns", default="0,5,10,20,-1")
     ap.add_argument("--reflect", action="store_true",
                     help="reflective sides on the C1 box against vacuum")
     ap.add_argument("--reflect-steps", type=int, default=10)
@@ -599,6 +667,8 @@ def main():
         out["precision_form"] = precision_form(S, torch, args)
     if args.protocol:
         out["protocol"] = protocol(S, torch, args)
+    if args.steady:
+        out["steady_protocol"] = steady_protocol(S, torch, args)
     if args.nsx:
         out["cellwise_ns"] = cellwise_ns(S, torch, args)
     if args.reflect:

@@ -25,7 +25,8 @@
  *      frozen source Q + sigma_s (phi_pre + phi_post + phi_c), tally T_R;
  *   4. the remap census is the state at t_{n+1}.
  * phi = T / (cell area * dt) is the step-averaged scalar flux (integral of
- * Psi over the sphere); phi_R is the solution of the step.
+ * Psi over the sphere); phi_R is the solution of the step.  A steady-state
+ * mode (slh_problem.steady) runs the same steps with an infinite time step.
  *
  * Conventions for every call:
  *   - Status codes only: no exceptions, no abort across this boundary.
@@ -48,7 +49,7 @@
 extern "C" {
 #endif
 
-#define SLH_ABI_VERSION 3u
+#define SLH_ABI_VERSION 4u
 
 typedef enum {
     SLH_OK = 0,
@@ -124,7 +125,42 @@ typedef struct {
                                    /* mirrored; the DG inflow on such a side  */
                                    /* is the previous source iteration's      */
                                    /* outflow of the mirrored direction.      */
+    int32_t steady;                /* 0: time steps of dt (above).  1: steady */
+                                   /* state, the infinite time step of the   */
+                                   /* paper's runs (Sec. 3): dt, c and        */
+                                   /* time_closure are not used, histories    */
+                                   /* end only by leakage, the cutoff or the  */
+                                   /* path horizon, no census is carried,     */
+                                   /* phi = T / (cell area) is the flux per   */
+                                   /* unit source rate, and the collided      */
+                                   /* solve has sigma_e = sigma_t.  Each       */
+                                   /* slh_advance step is then an independent */
+                                   /* steady solve with the step's own points.*/
+                                   /* With no scatter limit anywhere (pure   */
+                                   /* MC) the steady step skips the collided  */
+                                   /* solve and the remap: phi_R = phi_pre.   */
+    double horizon;                /* steady only: path length (in units of  */
+                                   /* length) at which a history ends; its    */
+                                   /* weight then is booked as census and     */
+                                   /* dropped.  0 -> ln(1/w_cut_rel) / min    */
+                                   /* sigma_a, at which every weight is below */
+                                   /* the cutoff; that needs w_cut_rel > 0    */
+                                   /* and sigma_a > 0 in every cell, else     */
+                                   /* horizon must be given (> 0, finite).    */
+                                   /* Tallies are fixed point with a unit of  */
+                                   /* 2^-61 times (total weight x horizon).   */
+    int32_t si_norm;               /* source-iteration stopping test:         */
+                                   /* SLH_SI_NORM_COLLIDED (0): stop when     */
+                                   /* ||dphi_c|| <= si_tol ||phi_c||;         */
+                                   /* SLH_SI_NORM_TOTAL (1): when ||dphi_c||  */
+                                   /* <= si_tol ||phi_c + phi_pre + phi_post||*/
+                                   /* (the step's whole flux), so a small     */
+                                   /* collided part needs fewer sweeps.       */
+                                   /* Norms are L2 over nodal values.         */
 } slh_problem;
+
+#define SLH_SI_NORM_COLLIDED 0
+#define SLH_SI_NORM_TOTAL 1
 
 #define SLH_REFLECT_X_LO 1
 #define SLH_REFLECT_X_HI 2
@@ -140,7 +176,8 @@ typedef struct {
     double scattered;    /* integral of sigma_s w ds on post-limit segments
                             (step 1: handed to the collided stage)           */
     double leaked;       /* weight leaving through the boundary              */
-    double census;       /* weight alive at t_{n+1}                          */
+    double census;       /* weight alive at t_{n+1} (steady state: at the
+                            path horizon, dropped)                           */
     double cutoff;       /* weight of histories ended by the cutoff          */
     double source_w;     /* weight emitted by the source                     */
     double census_in_w;  /* weight of the census-in bank                     */

@@ -20,6 +20,7 @@ The heavy loops live in ``slh_oracle.c`` (plain sequential C, FP64,
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -48,7 +49,7 @@ class _Mesh(C.Structure):
                 ("y_lo", C.c_double), ("y_hi", C.c_double),
                 ("sig_s", C.c_void_p), ("sig_a", C.c_void_p),
                 ("c", C.c_double), ("dt", C.c_double), ("ns_cell", C.c_void_p),
-                ("bc", C.c_int)]
+                ("bc", C.c_int), ("steady", C.c_int), ("horizon", C.c_double)]
 
 
 class _Points(C.Structure):
@@ -119,7 +120,7 @@ def lib():
         L.or_dg_collided.restype = C.c_int
         L.or_dg_collided.argtypes = [C.POINTER(_Mesh), C.c_double, C.c_int, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                     C.c_void_p, C.c_double, C.c_int,
+                                     C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                      C.c_void_p, C.POINTER(C.c_double)]
     return _lib
 
@@ -286,15 +287,28 @@ class Mesh:
         self.sig_s = np.ascontiguousarray(prob["sigma_s"], dtype=np.float64).ravel()
         self.sig_a = np.ascontiguousarray(prob["sigma_a"], dtype=np.float64).ravel()
         self.c = float(prob.get("c", 1.0))
-        self.dt = float(prob["dt"])
+        self.dt = float(prob.get("dt", 0.0))
+        # steady state (one infinite time step): histories end at a path
+        # horizon, by default ln(1/w_cut_rel) / min sigma_a, the length after
+        # which every weight is below the cutoff
+        self.steady = bool(prob.get("steady", False))
+        self.horizon = float(prob.get("horizon", 0.0))
+        if self.steady and not self.horizon > 0.0:
+            if not np.min(self.sig_a) > 0.0:
+                raise ValueError("steady state with sigma_a = 0 somewhere needs a horizon")
+            self.horizon = math.log(1.0 / float(prob.get("w_cut_rel", 1e-8))) / float(
+                np.min(self.sig_a))
         ns = prob.get("n_s_cell")
         self.ns_cell = None if ns is None else np.ascontiguousarray(ns, dtype=np.int32).ravel()
         self.bc = int(prob.get("boundary", 0))  # reflective sides: 1 x_lo, 2 x_hi, 4 y_lo, 8 y_hi
         self.s = _Mesh(self.nx, self.ny, self.x_lo, self.x_hi, self.y_lo, self.y_hi,
                        _p(self.sig_s), _p(self.sig_a), self.c, self.dt,
-                       None if self.ns_cell is None else _p(self.ns_cell), self.bc)
+                       None if self.ns_cell is None else _p(self.ns_cell), self.bc,
+                       int(self.steady), self.horizon)
         self.ncell = self.nx * self.ny
         self.area = ((self.x_hi - self.x_lo) / self.nx) * ((self.y_hi - self.y_lo) / self.ny)
+        # tallies per unit time (steady) or per step: phi = T / adt
+        self.adt = self.area if self.steady else self.area * self.dt
 
 
 def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
@@ -309,7 +323,7 @@ def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
     out = None
     bout_p = None
     if want_census:
-        ncand = bank.n + cell_counts(q_nodal, mesh.area * mesh.dt, n_src)[1]
+        ncand = bank.n + cell_counts(q_nodal, mesh.adt, n_src)[1]
         out = Bank(ncand)
         out.alive = np.zeros(ncand, dtype=np.uint8)
         bout = _BankOut(_p(out.x), _p(out.y), _p(out.ox), _p(out.oy), _p(out.w),
@@ -383,14 +397,18 @@ def mirror_indices(quad):
     return rx, ry
 
 
-def dg_collided(mesh: Mesh, quad, phi_post, tau=2.0, tol=1e-12, max_iter=200):
+def dg_collided(mesh: Mesh, quad, phi_post, tau=2.0, tol=1e-12, max_iter=200, phi_pre=None):
+    """Source iteration for the collided flux (see slh_oracle.c: or_dg_collided);
+    with phi_pre the stopping test is relative to phi_c + phi_pre + phi_post."""
     ox, oy, w = (np.ascontiguousarray(v, dtype=np.float64) for v in quad)
     rx, ry = mirror_indices((ox, oy, w))
     phi = np.zeros(4 * mesh.ncell)
     res = C.c_double(0.0)
     phi_post = np.ascontiguousarray(phi_post, dtype=np.float64)
+    phi_pre = None if phi_pre is None else np.ascontiguousarray(phi_pre, dtype=np.float64)
     it = lib().or_dg_collided(C.byref(mesh.s), tau, len(w), _p(ox), _p(oy), _p(w), _p(rx),
-                              _p(ry), _p(phi_post), tol, max_iter, _p(phi), C.byref(res))
+                              _p(ry), _p(phi_post), _p(phi_pre), tol, max_iter, _p(phi),
+                              C.byref(res))
     if it < 0:
         raise RuntimeError("DG sweep failed")
     return phi.reshape(mesh.ncell, 4), it, res.value
@@ -419,6 +437,12 @@ class HybridOracle:
         self.si_tol = float(prob.get("si_tol", 1e-12))
         self.si_max = int(prob.get("si_max_iter", 200))
         self.w_cut_rel = float(prob.get("w_cut_rel", 1e-8))
+        self.si_norm_total = int(prob.get("si_norm", 0)) == 1
+        ns = prob.get("n_s_cell")
+        # steady pure MC (no limit in any cell): no collided solve, no remap
+        # (Sec. 3: relabeling is unnecessary there), phi_R = phi_pre
+        self.skip_remap = self.mesh.steady and (
+            self.n_s < 0 if ns is None else bool(np.all(np.asarray(ns) < 0)))
         self.points = Points(int(prob.get("points", 0)))
         self.quad = quadrature(int(prob["sn_order"]))
         self.bank = Bank(0)
@@ -427,23 +451,38 @@ class HybridOracle:
     def step(self) -> dict:
         m = self.mesh
         n = self.step_index
-        adt = m.area * m.dt
+        adt = m.adt
         q4 = np.repeat(self.q, 4)
         # step 1: scatter-limited leg from Q and the census (initial data)
         Tpre, Tpost, bal1, seg1, _ = mc_pass(m, self.points, PASS_MC, self.n_s, q4, self.n_p,
                                              self.bank, self.seed, n, self.w_cut_rel, False)
         phi_pre, phi_post = Tpre / adt, Tpost / adt
+        if self.skip_remap:
+            self.step_index += 1
+            zero = dict(zip(BAL_NAMES, np.zeros(len(BAL_NAMES))))
+            return dict(step=n, phi_R=phi_pre.copy(), phi_pre=phi_pre, phi_post=phi_post,
+                        phi_c=np.zeros((m.ncell, 4)), T_pre=Tpre, T_post=Tpost, T_R=Tpre.copy(),
+                        bal_mc=bal1, bal_remap=zero, segments=seg1, seg_mc=seg1, seg_remap=0,
+                        si_iters=0, si_resid=0.0, census_alive=0, census_kept=0,
+                        thin_factor=1.0, thin_overflow=False, q_remap=None)
         # step 2: collided S_N-DG solve, zero initial/boundary data
         phi_c, iters, resid = dg_collided(m, self.quad, phi_post, self.tau, self.si_tol,
-                                          self.si_max)
+                                          self.si_max,
+                                          phi_pre if self.si_norm_total else None)
         # step 3: remap source Q + sigma_s (phi_pre + phi_post + phi_c), scatter-free leg
         qR = (self.q + m.sig_s * (phi_pre + phi_post))[:, None] + m.sig_s[:, None] * phi_c
         _, TR, bal2, seg2, cand = mc_pass(m, self.points, PASS_REMAP, self.n_s, qR, self.n_p,
-                                          self.bank, self.seed, n, self.w_cut_rel, True)
-        # step 4: the remap census is the state at t_{n+1} (capped)
-        thin_stream = stream_seed(self.seed, n, PASS_REMAP, POP_THIN, 0)
-        n_alive = int(cand.alive.sum())
-        self.bank, factor, overflow = thin(cand, self.cap, thin_stream)
+                                          self.bank, self.seed, n, self.w_cut_rel,
+                                          not m.steady)
+        # step 4: the remap census is the state at t_{n+1} (capped); steady
+        # state carries none (the weight at the horizon is only booked)
+        if m.steady:
+            n_alive, factor, overflow = 0, 1.0, False
+            self.bank = Bank(0)
+        else:
+            thin_stream = stream_seed(self.seed, n, PASS_REMAP, POP_THIN, 0)
+            n_alive = int(cand.alive.sum())
+            self.bank, factor, overflow = thin(cand, self.cap, thin_stream)
         self.step_index += 1
         return dict(step=n, phi_R=TR / adt, phi_pre=phi_pre, phi_post=phi_post, phi_c=phi_c,
                     T_pre=Tpre, T_post=Tpost, T_R=TR, bal_mc=bal1, bal_remap=bal2,

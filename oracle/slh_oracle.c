@@ -162,6 +162,8 @@ typedef struct {
     double c, dt;
     const int32_t *ns_cell;      /* per-cell scatter limits (-1 unlimited), or NULL */
     int bc;                      /* reflective sides: bit 0 x_lo, 1 x_hi, 2 y_lo, 3 y_hi */
+    int steady;                  /* 1: steady state (one infinite time step, Sec. 3) */
+    double horizon;              /* steady state: path length at which a history ends */
 } or_mesh;
 
 enum { OR_BC_XLO = 1, OR_BC_XHI = 2, OR_BC_YLO = 4, OR_BC_YHI = 8 };
@@ -301,7 +303,13 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
     const double hx = (M->x_hi - M->x_lo) / nx;
     const double hy = (M->y_hi - M->y_lo) / ny;
     const double area = hx * hy;
-    const double dt = M->dt, c = M->c;
+    /* Steady state, the infinite time step of the paper's runs (Sec. 3):
+     * weights are per unit time (A in place of A dt), every particle starts
+     * at path length 0, and the end of the step becomes a path horizon: the
+     * time-dependent formulas below with c = 1 and dt = horizon. */
+    const double c = M->steady ? 1.0 : M->c;
+    const double dt = M->steady ? M->horizon : M->dt;
+    const double dt_birth = M->steady ? 0.0 : M->dt;
     /* n_lim: the largest limit (draws of the optical depth); lim(cell): the
      * limit that decides the regime of a segment */
     int n_lim = (kind == 2) ? 0 : (n_s < 0 ? 0x7fffffff : n_s);
@@ -319,7 +327,7 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
 
     /* Emission counts per cell (majorants M_i = A dt mbar_i, mbar_i = max
      * corner |q_i| rounded up to a power of two): n_i = ceil(M_i / w_q). */
-    const double adt = area * dt;
+    const double adt = M->steady ? area : area * dt;
     int64_t *counts = (int64_t *)calloc((size_t)(ncell > 0 ? ncell : 1), sizeof(int64_t));
     double wq = 0.0;
     const int64_t n_emit = or_cell_counts(q_nodal, ncell, adt, n_src, counts, &wq);
@@ -368,7 +376,7 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             const double u5 = or_u01(or_point_u32(P, stream, 4, pidx));
             x = M->x_lo + hx * ((double)ix + u1);
             y = M->y_lo + hy * ((double)iy + u2);
-            trel = u3 * dt;
+            trel = u3 * dt_birth;
             const double st = 2.0 * sqrt(u4 * (1.0 - u4)); /* sin(theta), Oz = 1 - 2 u4 */
             const double ph = 2.0 * M_PI * u5;
             ox = st * cos(ph);
@@ -681,18 +689,21 @@ int or_dg_sweep(int nx, int ny, double x_lo, double x_hi, double y_lo, double y_
 /*
  * Source iteration for the collided flux (step 2 of Sec. 2.2):
  *   (sig_t + tau/(c dt)) psi + Omega.grad psi = sig_s/(4 pi) (phi_c + phi_post)
+ * (in steady state, M->steady, without the tau/(c dt) term)
  * with zero initial data, vacuum sides, and reflective sides (M->bc) whose
  * inflow lags one iteration (see below).  The time derivative over the
  * step is closed by tau/(c dt) (tau = 2: the step average of a flux growing
  * linearly from zero).  phi_post is cell-constant; phi_c is nodal bilinear.
- * Stops when ||phi_new - phi_old||_2 <= tol ||phi_new||_2 (nodal vectors).
+ * Stops when ||phi_new - phi_old||_2 <= tol ||phi_new||_2 (nodal vectors),
+ * or, when phi_pre is given, <= tol ||phi_new + phi_pre + phi_post||_2 (the
+ * whole flux of the step as the reference).
  * phi [n_cells*4] receives the result; returns the number of sweeps.
  */
 int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
                    const double *dox, const double *doy, const double *dw,
                    const int *refl_x, const int *refl_y,
-                   const double *phi_post, double tol, int max_iter,
-                   double *phi, double *resid_out)
+                   const double *phi_post, const double *phi_pre,
+                   double tol, int max_iter, double *phi, double *resid_out)
 {
     const int nx = M->nx, ny = M->ny;
     const int64_t ncell = (int64_t)nx * ny;
@@ -712,7 +723,8 @@ int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
     double *prev_x = (double *)calloc((size_t)n_dir * bx, sizeof(double));
     double *prev_y = (double *)calloc((size_t)n_dir * by, sizeof(double));
     for (int64_t i = 0; i < ncell; ++i)
-        sig_e[i] = M->sig_a[i] + M->sig_s[i] + tau_closure / (M->c * M->dt);
+        sig_e[i] = M->sig_a[i] + M->sig_s[i]
+                 + (M->steady ? 0.0 : tau_closure / (M->c * M->dt));
     for (size_t k = 0; k < nn; ++k) phi[k] = 0.0;
     int it = 0;
     double resid = 0.0;
@@ -753,8 +765,9 @@ int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
         double dn = 0.0, nrm = 0.0;
         for (size_t k = 0; k < nn; ++k) {
             const double d = acc[k] - phi[k];
+            const double ref = phi_pre ? acc[k] + (phi_pre[k / 4] + phi_post[k / 4]) : acc[k];
             dn += d * d;
-            nrm += acc[k] * acc[k];
+            nrm += ref * ref;
             phi[k] = acc[k];
         }
         dn = sqrt(dn);

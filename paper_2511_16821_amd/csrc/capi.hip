@@ -137,9 +137,27 @@ struct Sizes {
   size_t bytes;
 };
 
-static double sigma_e_of(const slh_problem* p, long long i) {
+// tau/(c dt), the time closure of the collided solve; none in steady state
+static double time_term(const slh_problem* p) {
+  if (p->steady) return 0.0;
   const double tau = p->time_closure > 0.0 ? p->time_closure : 2.0;
-  return p->sigma_a[i] + p->sigma_s[i] + tau / (p->c * p->dt);
+  return tau / (p->c * p->dt);
+}
+
+static double sigma_e_of(const slh_problem* p, long long i) {
+  return p->sigma_a[i] + p->sigma_s[i] + time_term(p);
+}
+
+// Steady state: the path length at which a history ends.  By default
+// ln(1/w_cut_rel) / min sigma_a: a weight decays at least at rate min sigma_a
+// (sigma_a before the limit, sigma_t after it) from at most w_q, so every
+// history is below the cutoff w_cut_rel w_q by then.
+static double horizon_of(const slh_problem* p) {
+  if (p->horizon > 0.0) return p->horizon;
+  const long long n = (long long)p->nx * p->ny;
+  double mn = INFINITY;
+  for (long long i = 0; i < n; ++i) mn = std::min(mn, p->sigma_a[i]);
+  return log(1.0 / p->w_cut_rel) / mn;
 }
 
 // Sorted distinct sigma_e values of the problem's cells.
@@ -196,8 +214,19 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
   if (!(p->x_hi > p->x_lo) || !(p->y_hi > p->y_lo) || !isfinite(p->x_lo) || !isfinite(p->x_hi) ||
       !isfinite(p->y_lo) || !isfinite(p->y_hi))
     return fail(SLH_E_INVALID_ARG, "empty or non-finite domain");
-  if (!(p->c > 0.0) || !isfinite(p->c)) return fail(SLH_E_INVALID_ARG, "c must be > 0");
-  if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(SLH_E_INVALID_ARG, "dt must be > 0");
+  if (p->steady != 0 && p->steady != 1) return fail(SLH_E_INVALID_ARG, "steady must be 0 or 1");
+  if (p->si_norm != SLH_SI_NORM_COLLIDED && p->si_norm != SLH_SI_NORM_TOTAL)
+    return fail(SLH_E_INVALID_ARG, "si_norm must be SLH_SI_NORM_COLLIDED or SLH_SI_NORM_TOTAL");
+  if (!p->steady) {
+    if (!(p->c > 0.0) || !isfinite(p->c)) return fail(SLH_E_INVALID_ARG, "c must be > 0");
+    if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(SLH_E_INVALID_ARG, "dt must be > 0");
+  } else {
+    if (!(p->horizon >= 0.0) || !isfinite(p->horizon))
+      return fail(SLH_E_INVALID_ARG, "horizon must be finite and >= 0");
+    if (p->horizon == 0.0 && !(p->w_cut_rel > 0.0 && p->w_cut_rel < 1.0))
+      return fail(SLH_E_INVALID_ARG,
+                  "steady state without a horizon needs 0 < w_cut_rel < 1 (default horizon)");
+  }
   if (p->n_s < -1 || p->n_s > 1000000)
     return fail(SLH_E_INVALID_ARG, "n_s must be -1 (unlimited) or in [0, 1e6]");
   if (p->boundary < 0 || p->boundary > 15)
@@ -230,6 +259,14 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
     if (!finite_nonneg(p->sigma_s, n)) return fail(SLH_E_INVALID_ARG, "sigma_s must be finite, >= 0");
     if (!finite_nonneg(p->sigma_a, n)) return fail(SLH_E_INVALID_ARG, "sigma_a must be finite, >= 0");
     if (!finite_nonneg(p->q, n)) return fail(SLH_E_INVALID_ARG, "q must be finite, >= 0");
+    if (p->steady && p->horizon == 0.0) {
+      for (long long i = 0; i < n; ++i)
+        if (!(p->sigma_a[i] > 0.0))
+          return fail(SLH_E_INVALID_ARG,
+                      "steady state with a cell of sigma_a = 0 needs an explicit horizon");
+    }
+    if (p->steady && !(horizon_of(p) <= 1e15))
+      return fail(SLH_E_INVALID_ARG, "horizon above 1e15 (a small sigma_a sets the default)");
   }
   return SLH_OK;
 }
@@ -352,6 +389,8 @@ struct slh_solver {
   int n_lim_max = 0;        // the largest limit of the scatter-limited leg
   int* ns_cell = nullptr;   // device copy of h_ns
   double hx, hy, area, adt, tau, si_tol;
+  double horizon = 0.0;     // steady state: path length at which a history ends
+  bool skip_remap = false;  // steady pure MC: no collided solve, phi_R = phi_pre
   long long thin_margin = 0;
   int si_max;
 
@@ -550,7 +589,7 @@ static slh_status setup(slh_solver* s) {
   for (long long i = 0; i < nc; ++i) {
     m64[i] = make_double2(s->h_sig_s[i], s->h_sig_a[i]);
     m32[i] = make_float2((float)s->h_sig_s[i], (float)s->h_sig_a[i]);
-    se[i] = s->h_sig_a[i] + s->h_sig_s[i] + s->tau / (p.c * p.dt);
+    se[i] = s->h_sig_a[i] + s->h_sig_s[i] + time_term(&p);
     for (int k = 0; k < 4; ++k) qn[4 * i + k] = s->h_q[i];
   }
   const std::vector<double> dirs = product_quadrature(p.sn_order);
@@ -621,8 +660,13 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.ny = p.ny;
   a.hx = s->hx;
   a.hy = s->hy;
-  a.dt = p.dt;
-  a.c = p.c;
+  // steady state: the census of the time-dependent step becomes the path
+  // horizon (c = 1, dt = horizon), every particle starts at time 0, and no
+  // census is kept
+  a.dt = p.steady ? s->horizon : p.dt;
+  a.c = p.steady ? 1.0 : p.c;
+  a.dt_birth = p.steady ? 0.0 : p.dt;
+  a.keep_census = p.steady ? 0 : 1;
   a.mat64 = s->mat64;
   a.mat32 = s->mat32;
   a.tree = kind == 1 ? s->tree1 : s->treeR;
@@ -715,6 +759,7 @@ static DgArgs dg_args(slh_solver* s) {
   d.sig_e = s->sig_e;
   d.sig_s = s->sig_s;
   d.phi_post = s->phi_post;
+  d.phi_pre = s->prob.si_norm == SLH_SI_NORM_TOTAL ? s->phi_pre : nullptr;
   d.phi_c = s->phi_c;
   d.src = s->dg_src;
   d.psi = s->psi;
@@ -749,7 +794,7 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
   const Sizes& z = s->z;
   const long long nc = z.n_cells;
   const double inv_adt = 1.0 / s->adt;
-  const double cdt = p.c * p.dt;
+  const double cdt = p.steady ? s->horizon : p.c * p.dt;  // longest path of a history
   const long long cstride = (long long)kTallyStride * nc;
   const long long n_tally = (long long)z.n_copies * kTallyStride * nc;
   switch (part) {
@@ -766,10 +811,16 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
                          s->bal_store + 0);
       HIP_TRY(hipMemcpyAsync(s->h_bal + 0, s->bal_store + 0, sizeof(BalStore),
                              hipMemcpyDeviceToHost, st));
-      HIP_TRY(launch_si_start(dg_args(s), s->si_max, st));
+      // pure MC in steady state: no collided solve (phi_c = 0, no sweep)
+      HIP_TRY(launch_si_start(dg_args(s), s->skip_remap ? 0 : s->si_max, st));
       return enqueue_si(s, st, n_it);
     }
     case kB1: {
+      if (s->skip_remap) {  // no remap leg: clear its balance and census flags only
+        HIP_TRY(launch_pass_prep(s->st, s->tree1, cdt, nullptr, 0, nullptr, 0, s->alive,
+                                 z.n_cand, st));
+        return SLH_OK;
+      }
       HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c,
                                   s->qnR, st));
       HIP_TRY(launch_build_tree(s->qnR, nc, s->adt, s->treeR, st));
@@ -780,8 +831,9 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
       return SLH_OK;
     }
     default: {  // kB2: the remap census is the state at t_{n+1} (capped)
-      HIP_TRY(launch_tally_to_flux(s->TR, s->phi_R, nullptr, nullptr, nc, z.n_copies, cstride,
-                                   s->st, inv_adt, st));
+      // without a remap leg the solution is the pure-MC flux of pass 1
+      HIP_TRY(launch_tally_to_flux(s->skip_remap ? s->Tpre : s->TR, s->phi_R, nullptr, nullptr,
+                                   nc, z.n_copies, cstride, s->st, inv_adt, st));
       hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
                          s->bal_store + 1);
       HIP_TRY(hipMemcpyAsync(s->h_bal + 1, s->bal_store + 1, sizeof(BalStore),
@@ -853,8 +905,9 @@ static slh_status run_step(slh_solver* s) {
   const int grid1 = mc_pass_grid(z.fp32, 1, z.cap + z.n_src_cap);
   const int grid2 = mc_pass_grid(z.fp32, 2, z.cap + z.n_src_cap);
   // iterations in the first batch: as many as the previous step took
-  const int n_first =
-      s->si_max > 0 ? std::max(1, std::min(s->si_max, s->si_it > 0 ? s->si_it : 4)) : 0;
+  const int n_first = s->si_max > 0 && !s->skip_remap
+                          ? std::max(1, std::min(s->si_max, s->si_it > 0 ? s->si_it : 4))
+                          : 0;
   hipStream_t st = s->stream;
   HIP_TRY(hipEventRecord(s->ev[0], st));
   slh_status r = launch_part(s, kA1, 0);
@@ -886,7 +939,7 @@ static slh_status run_step(slh_solver* s) {
   r = launch_part(s, kB1, 0);
   if (r != SLH_OK) return r;
   HIP_TRY(hipEventRecord(s->evk[2], st));
-  HIP_TRY(launch_mc_pass(pass_args(s, 2), z.fp32, grid2, st));
+  if (!s->skip_remap) HIP_TRY(launch_mc_pass(pass_args(s, 2), z.fp32, grid2, st));
   HIP_TRY(hipEventRecord(s->evk[3], st));
   r = launch_part(s, kB2, 0);
   if (r != SLH_OK) return r;
@@ -930,12 +983,21 @@ extern "C" slh_status slh_create(const slh_problem* problem, void* hip_stream,
       s->n_lim_max = std::max(s->n_lim_max, s->h_ns[i]);
     }
   }
+  s->horizon = problem->steady ? horizon_of(problem) : 0.0;
+  // steady pure MC (no limit in any cell): the remap is unnecessary (Sec. 3)
+  bool all_unlimited = problem->n_s < 0;
+  if (problem->n_s_cell) {
+    all_unlimited = true;
+    for (long long i = 0; i < nc; ++i) all_unlimited = all_unlimited && problem->n_s_cell[i] < 0;
+  }
+  s->skip_remap = problem->steady && all_unlimited;
   s->prob.sigma_s = s->prob.sigma_a = s->prob.q = nullptr;
   s->prob.n_s_cell = nullptr;
   s->hx = (problem->x_hi - problem->x_lo) / problem->nx;
   s->hy = (problem->y_hi - problem->y_lo) / problem->ny;
   s->area = s->hx * s->hy;
-  s->adt = s->area * problem->dt;
+  // steady state: weights and fluxes per unit time
+  s->adt = problem->steady ? s->area : s->area * problem->dt;
   s->tau = problem->time_closure > 0.0 ? problem->time_closure : 2.0;
   s->si_tol = problem->si_tol > 0.0 ? problem->si_tol : 1e-12;
   s->si_max = problem->si_max_iter > 0 ? problem->si_max_iter : 200;

@@ -529,7 +529,8 @@ hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
 // phi_new[k] = sum_m w_m psi[m][k] in direction order, in place; the next
 // iterate's nodal source S = sigma_s/(4 pi) (phi_new + phi_post) (unused when
 // the iteration stops here); block partials of |phi_new - phi_old|^2 and
-// |phi_new|^2.
+// |phi_new|^2, or |phi_new + phi_pre + phi_post|^2 when phi_pre is given (the
+// step's whole flux as the reference of the stopping test).
 constexpr int kRedBlock = 256;
 
 int dg_reduce_partials(long long n_nodes) {
@@ -541,7 +542,8 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
     int n_dir, long long n_nodes, const double* __restrict__ psi,
     const double* __restrict__ dir, double* __restrict__ phi,
     const double* __restrict__ sig_s, const double* __restrict__ phi_post,
-    double* __restrict__ S, double* __restrict__ partials, const DevState* st) {
+    const double* __restrict__ phi_pre, double* __restrict__ S,
+    double* __restrict__ partials, const DevState* st) {
   if (st->si_done) return;
   __shared__ double s_d[kRedBlock], s_n[kRedBlock];
   const double inv4pi = 0.25 / M_PI;
@@ -562,8 +564,9 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
     const double d = v - phi[k];  // in place: the sweep read only S
     phi[k] = v;
     S[k] = sig_s[k >> 2] * inv4pi * (v + phi_post[k >> 2]);
+    const double vr = phi_pre ? v + (phi_pre[k >> 2] + phi_post[k >> 2]) : v;
     dsum += d * d;
-    nsum += v * v;
+    nsum += vr * vr;
   }
   s_d[threadIdx.x] = dsum;
   s_n[threadIdx.x] = nsum;
@@ -622,7 +625,7 @@ hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, doubl
                             int si_max, hipStream_t s) {
   hipLaunchKernelGGL(k_dg_reduce, dim3(n_part), dim3(kRedBlock), 0, s, a.n_dir,
                      4ll * a.nx * a.ny, (const double*)a.psi, a.dir, a.phi_c, a.sig_s, a.phi_post,
-                     a.src, partials, (const DevState*)a.st);
+                     a.phi_pre, a.src, partials, (const DevState*)a.st);
   hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,
                      a.st, si_tol, si_max);
   return hipGetLastError();

@@ -130,7 +130,8 @@ __device__ __forceinline__ void bal_add(unsigned long long* bal, int f, double v
 // numbered in cell order.  Particle l of cell j takes its points from the
 // cell's stream at index l: position (dims 0-1), birth time (dim 2),
 // direction (dims 3-4, sincospi), the first optical depth (dim 5) when the
-// pass allows scatters, and weight q(x,y) A dt / n_j.
+// pass allows scatters, and weight q(x,y) A dt / n_j (A / n_j in steady
+// state, where every particle starts at time 0).
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   __shared__ uint32_t s_sobol[kSobolNibbleWords];
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   __syncthreads();
   const long long n_emit = (long long)s_top[1];
   const uint64_t step = a.st->step;
-  const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt;
+  const R hx = (R)a.hx, hy = (R)a.hy, dt_birth = (R)a.dt_birth;
   const SrcBank<R> b = Real<R>::src(a);
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n_emit;
        s += (long long)gridDim.x * blockDim.x) {
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
     b.ox[s] = sn * cp;
     b.oy[s] = sn * sp;
     b.w[s] = (R)(bilinear(q, (double)u1, (double)u2) * (a.adt / nj));
-    b.trel[s] = u3 * dt;
+    b.trel[s] = u3 * dt_birth;
     b.tau[s] = a.n_lim > 0 ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, l)))
                            : (R)0;
     b.cell[s] = (int32_t)ci;
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     lane_seg++;
 
     if (end != END_NONE) {
-      if (KIND == 2 && end == END_CENSUS) {
+      if (KIND == 2 && end == END_CENSUS && a.keep_census) {
         const long long slot = from_census ? g : a.out_src_base + (g - n_in);
         bout.px[slot] = px; bout.py[slot] = py; bout.ox[slot] = ox; bout.oy[slot] = oy;
         bout.w[slot] = w; bout.cell[slot] = iy * a.nx + ix; bout.hid[slot] = hid;

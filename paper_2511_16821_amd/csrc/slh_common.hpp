@@ -261,7 +261,11 @@ struct DevState {
 
 struct PassArgs {
   int nx, ny;
-  double hx, hy, dt, c;
+  // a history ends (census) at time dt after the start of the step, the
+  // distance c (dt - t) ahead; source particles are born at u dt_birth
+  // (dt_birth = dt; 0 in steady state, where dt is the path horizon, c = 1)
+  double hx, hy, dt, c, dt_birth;
+  int keep_census;       // remap pass: write the census-out particles
   const double2* mat64;  // (sigma_s, sigma_a) per cell
   const float2* mat32;
   // emission, stratified by cell: cell i emits n_i = ceil(M_i / w_q)
@@ -272,7 +276,7 @@ struct PassArgs {
   const double* qn;      // nodal source [cell][4]
   long long n_cells;
   long long n_src;       // N_p, the requested particles per pass
-  double adt;            // cell area times dt
+  double adt;            // cell area times dt (times 1 in steady state)
   uint64_t seed;         // the time step is read from st->step
   int kind;              // 1: scatter-limited leg, 2: scatter-free remap
   int n_lim;             // scatter limit of the pass (0 for kind 2); with
@@ -326,6 +330,8 @@ struct DgArgs {
   const double* sig_e;   // per cell
   const double* sig_s;   // per cell
   const double* phi_post;// per cell
+  const double* phi_pre; // per cell, or null: the stopping test's norm is then
+                         // over phi_c alone, else over phi_c + phi_pre + phi_post
   double* phi_c;         // nodal [cell][4]: the collided iterate, updated in place
   double* src;           // nodal [cell][4] scratch: sigma_s/(4 pi)(phi_c + phi_post)
   double* psi;           // [m][cell][4] (psi_m; the reduction applies w_m)

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libslh.so")
 
-SLH_ABI_VERSION = 3
+SLH_ABI_VERSION = 4
 SLH_OK, SLH_E_INVALID_ARG, SLH_E_OUT_OF_MEMORY, SLH_E_DEVICE, SLH_E_NOT_CONVERGED, \
     SLH_E_NUMERIC, SLH_E_REJECTED, SLH_E_STATE = range(8)
 SLH_FP64, SLH_FP32_TRACK = 0, 1
@@ -36,7 +36,8 @@ class slh_problem(C.Structure):
                 ("sn_order", C.c_int32), ("time_closure", C.c_double), ("si_tol", C.c_double),
                 ("si_max_iter", C.c_int32), ("w_cut_rel", C.c_double), ("seed", C.c_uint64),
                 ("points", C.c_int32), ("precision", C.c_int32), ("n_s_cell", C.c_void_p),
-                ("boundary", C.c_int32)]
+                ("boundary", C.c_int32), ("steady", C.c_int32), ("horizon", C.c_double),
+                ("si_norm", C.c_int32)]
 
 
 class slh_balance(C.Structure):
@@ -162,7 +163,7 @@ def make_problem(p: dict):
     s.x_lo, s.x_hi, s.y_lo, s.y_hi = (float(p[k]) for k in ("x_lo", "x_hi", "y_lo", "y_hi"))
     s.sigma_s, s.sigma_a, s.q = (a.ctypes.data for a in (ss, sa, q))
     s.c = float(p.get("c", 1.0))
-    s.dt = float(p["dt"])
+    s.dt = float(p.get("dt", 0.0))
     s.n_s = int(p["n_s"])
     s.n_particles = int(p["n_particles"])
     s.census_cap = int(p.get("census_cap", 0))
@@ -175,6 +176,9 @@ def make_problem(p: dict):
     s.points = int(p.get("points", 0))
     s.precision = int(p.get("precision", 0))
     s.boundary = int(p.get("boundary", 0))
+    s.steady = int(bool(p.get("steady", False)))
+    s.horizon = float(p.get("horizon", 0.0))
+    s.si_norm = int(p.get("si_norm", 0))
     keep = [ss, sa, q]
     if p.get("n_s_cell") is not None:
         nsc = np.ascontiguousarray(p["n_s_cell"], dtype=np.int32).reshape(-1)

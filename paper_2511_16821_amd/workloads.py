@@ -8,7 +8,8 @@ The paper's own test problems (a 1-D slab benchmark and a 2-D duct problem)
 are specified only in figures that are not available, so the configurations
 below are synthetic stand-ins with the structure of a heterogeneous 2-D
 transport problem: localised sources, absorber/scatterer contrasts, optically
-thick regions with voids and random block materials.
+thick regions with voids and random block materials, and for the steady
+state a multi-region slab and a bent duct.
 
 Fields are row-major with shape (ny, nx): cell (i, j) is element [j, i].
 """
@@ -152,6 +153,54 @@ def lognormal_blocks(n, L=10.0, blocks=8, rng=None, **kw):
     kw.setdefault("dt", 0.05)
     kw.setdefault("sn_order", 8)
     return _problem(n, n, (0.0, L, 0.0, L), ss, sa, q, **kw)
+
+
+def slab_regions(nx=80, ny=1, L=8.0, height=1.0, **kw):
+    """Steady 1-D multi-region slab (stand-in with the structure of the
+    paper's slab benchmark; the values are our own): along x a strongly
+    absorbing source region, a pure absorber, a void, a scattering region with
+    a source and a scattering region without; uniform in y with reflective
+    y sides (an infinite slab), reflective at x = 0, vacuum at x = L.  The
+    void needs an explicit path horizon."""
+    x = (np.arange(nx) + 0.5) * (L / nx)
+    edges = np.array([0.0, 1.5, 3.0, 4.5, 6.0, L]) * (L / 8.0)
+    region = np.searchsorted(edges, x, side="right") - 1
+    sa_r = np.array([20.0, 3.0, 0.0, 0.2, 0.05])
+    ss_r = np.array([0.0, 0.0, 0.0, 0.8, 0.95])
+    q_r = np.array([20.0, 0.0, 0.0, 1.0, 0.0])
+    row = lambda v: np.tile(v[region], (ny, 1))
+    kw.setdefault("n_s", 0)
+    kw.setdefault("n_particles", 64_000)
+    kw.setdefault("sn_order", 4)
+    kw.setdefault("horizon", 200.0)
+    kw.setdefault("si_max_iter", 1000)
+    kw.setdefault("boundary", 1 | 4 | 8)
+    return _problem(nx, ny, (0.0, L, 0.0, height), row(ss_r), row(sa_r), row(q_r),
+                    steady=True, **kw)
+
+
+def duct(nx=30, ny=50, **kw):
+    """Steady 2-D duct (stand-in with the structure of the paper's duct
+    problem; geometry and values are our own): a near-vacuum duct with two
+    bends (sigma_s = sigma_a = 1e-4) through a scattering, absorbing medium
+    (sigma_s = 0.9, sigma_a = 0.1) on [0,3] x [0,5], with a unit source in the
+    first 0.5 x 0.5 of the duct; vacuum sides.  The duct needs an explicit
+    path horizon."""
+    hx, hy = 3.0 / nx, 5.0 / ny
+    xc = (np.arange(nx) + 0.5) * hx
+    yc = (np.arange(ny) + 0.5) * hy
+    X, Y = np.meshgrid(xc, yc)
+    duct = ((X < 0.5) & (Y < 2.0)) | ((Y >= 1.5) & (Y < 2.0) & (X < 2.0)) | \
+           ((X >= 1.5) & (X < 2.0) & (Y >= 1.5))
+    ss = np.where(duct, 1e-4, 0.9)
+    sa = np.where(duct, 1e-4, 0.1)
+    q = np.where((X < 0.5) & (Y < 0.5), 1.0, 0.0)
+    kw.setdefault("n_s", 0)
+    kw.setdefault("n_particles", 64_000)
+    kw.setdefault("sn_order", 4)
+    kw.setdefault("horizon", 200.0)
+    kw.setdefault("si_max_iter", 1000)
+    return _problem(nx, ny, (0.0, 3.0, 0.0, 5.0), ss, sa, q, steady=True, **kw)
 
 
 def request_stream(n_req=256, rho=1.0, mean_service_s=None, seed=4, sides=(32, 64, 128, 256, 512),

@@ -44,14 +44,20 @@ def test_validation_rejects_before_allocating(S):
         dict(precision=3), dict(w_cut_rel=-1.0), dict(x_hi=0.0),
         dict(n_s_cell=np.full(400, -2, dtype=np.int32)),
         dict(n_s_cell=np.full(400, 2_000_000, dtype=np.int32)),
-        dict(boundary=16), dict(boundary=-1),
+        dict(boundary=16), dict(boundary=-1), dict(si_norm=2), dict(si_norm=-1),
+        dict(steady_raw=2), dict(steady=True, horizon=-1.0),
+        dict(steady=True, horizon=np.inf), dict(steady=True, horizon=1e16),
+        dict(steady=True, w_cut_rel=0.0),  # the default horizon needs a cutoff
+        dict(steady=True, sigma_a=np.where(np.arange(400) == 7, 0.0, 0.1)),
     ]
     for upd in bad_cases:
         p = dict(good)
-        p.update({k: v for k, v in upd.items() if k != "nx"})
+        p.update({k: v for k, v in upd.items() if k not in ("nx", "steady_raw")})
         st, keep = S.make_problem(p)
         if "nx" in upd:
             st.nx = upd["nx"]
+        if "steady_raw" in upd:
+            st.steady = upd["steady_raw"]
         h = C.c_void_p()
         r = S.lib().slh_create(C.byref(st), None, S.ALLOC_FN(0), S.FREE_FN(0), None, C.byref(h))
         assert r == S.SLH_E_INVALID_ARG, upd
@@ -71,6 +77,9 @@ def test_validation_rejects_before_allocating(S):
 
 def test_footprint_scales_with_problem(S):
     from paper_2511_16821_amd import workloads as W
+    # steady problems need no dt; voids are fine with an explicit horizon
+    assert S.slh_footprint_bytes(W.duct()) > 0
+    assert S.slh_footprint_bytes(W.slab_regions(dt=0.0)) > 0
     small = S.slh_footprint_bytes(W.c1())
     big = S.slh_footprint_bytes(W.c1(n_particles=10 ** 6))
     assert 0 < small < big

@@ -919,7 +919,10 @@ static slh_status run_step(slh_solver* s) {
   if (r != SLH_OK) return r;
   s->pending[0] = true;
   // the one host wait of the step: iteration state (and the balances of the
-  // previous step's remap leg and this step's pass 1)
+  // previous step's remap leg and this step's pass 1).  When the first batch
+  // falls short, further batches double in size (iterations past convergence
+  // return at once), so a solve of k iterations needs about log2(k) waits.
+  int batch = 2;
   for (;;) {
     HIP_TRY(hipStreamSynchronize(st));
     s->host_syncs += 1;
@@ -930,8 +933,9 @@ static slh_status run_step(slh_solver* s) {
     s->si_res = nrm > 0.0 ? dn / nrm : 0.0;
     if (si->bad) return fail(SLH_E_NUMERIC, "non-finite DG residual");
     if (si->done) break;
-    r = enqueue_si(s, st, std::min(2, s->si_max - si->iter));  // rare: a short batch
+    r = enqueue_si(s, st, std::min(batch, s->si_max - si->iter));
     if (r != SLH_OK) return r;
+    batch = std::min(2 * batch, 64);
   }
   r = collect_all(s);
   if (r != SLH_OK) return r;

@@ -157,7 +157,26 @@ typedef struct {
                                    /* (the step's whole flux), so a small     */
                                    /* collided part needs fewer sweeps.       */
                                    /* Norms are L2 over nodal values.         */
+    int32_t closure;               /* collided solve (step 2):                */
+                                   /* SLH_CLOSE_SN (0): DG S_N, source        */
+                                   /* iteration;  SLH_CLOSE_DIFFUSION (1):    */
+                                   /* cell-centred diffusion,                 */
+                                   /* (sigma_a + tau/(c dt)) phi_c            */
+                                   /*  - div(D grad phi_c) = sigma_s phi_post,*/
+                                   /* D = 1/(3 (sigma_t + tau/(c dt))) (no    */
+                                   /* tau/(c dt) in steady state), harmonic-  */
+                                   /* mean faces, Marshak vacuum sides,       */
+                                   /* zero-current reflective sides; solved   */
+                                   /* by preconditioned conjugate gradients   */
+                                   /* to |r| <= si_tol |b| within si_max_iter */
+                                   /* iterations (reported as si_iterations;  */
+                                   /* si_norm is not used).  phi_c is then    */
+                                   /* constant in each cell.  Needs           */
+                                   /* sigma_t + tau/(c dt) > 0 in every cell. */
 } slh_problem;
+
+#define SLH_CLOSE_SN 0
+#define SLH_CLOSE_DIFFUSION 1
 
 #define SLH_SI_NORM_COLLIDED 0
 #define SLH_SI_NORM_TOTAL 1

@@ -13,7 +13,8 @@ The heavy loops live in ``slh_oracle.c`` (plain sequential C, FP64,
   * obtains the Gauss-Legendre polar nodes from ``numpy.polynomial.legendre``,
   * and drives one time step as steps 1-4 of Sec. 2.2 of the paper:
       1. scatter-limited (Q)MC leg (<= N_s scatters, pre/post tallies),
-      2. DG S_N collided solve with source sigma_s/(4 pi) phi_post,
+      2. DG S_N collided solve with source sigma_s/(4 pi) phi_post (or a
+         cell-centred diffusion solve, the alternative closing stage),
       3. remap: scatter-free (Q)MC from Q + sigma_s (phi_pre + phi_post + phi_c),
       4. the remap census is the state at t_{n+1}.
 """
@@ -414,6 +415,88 @@ def dg_collided(mesh: Mesh, quad, phi_post, tau=2.0, tol=1e-12, max_iter=200, ph
     return phi.reshape(mesh.ncell, 4), it, res.value
 
 
+def diffusion_matrix(mesh: Mesh, tau=2.0):
+    """Cell-centred finite-volume diffusion operator of the collided flux, the
+    alternative closing stage (a P1 reading of the collided equation with the
+    step closure of the S_N stage):
+        (sigma_a + tau/(c dt)) phi_c - div(D grad phi_c) = sigma_s phi_post,
+        D = 1 / (3 (sigma_t + tau/(c dt)))   (no tau/(c dt) in steady state).
+    Interior faces carry D_f (phi_i - phi_j)/h with the harmonic mean
+    D_f = 2 D_i D_j / (D_i + D_j); a vacuum side has zero incoming partial
+    current (Marshak), which gives the outflow 2 D_i phi_i / (h + 4 D_i) per
+    unit face length; a reflective side has none.  Returns the sparse matrix
+    (per unit cell area, so that A phi = sigma_s phi_post)."""
+    from scipy.sparse import lil_matrix
+    nx, ny = mesh.nx, mesh.ny
+    hx = (mesh.x_hi - mesh.x_lo) / nx
+    hy = (mesh.y_hi - mesh.y_lo) / ny
+    tt = 0.0 if mesh.steady else tau / (mesh.c * mesh.dt)
+    A = lil_matrix((nx * ny, nx * ny))
+    for j in range(ny):
+        for i in range(nx):
+            k = j * nx + i
+            sr = mesh.sig_a[k] + tt
+            D = 1.0 / (3.0 * (mesh.sig_a[k] + mesh.sig_s[k] + tt))
+            A[k, k] += sr
+            for di, dj, h, side in ((-1, 0, hx, 1), (1, 0, hx, 2), (0, -1, hy, 4), (0, 1, hy, 8)):
+                ii, jj = i + di, j + dj
+                if 0 <= ii < nx and 0 <= jj < ny:
+                    kk = jj * nx + ii
+                    Dn = 1.0 / (3.0 * (mesh.sig_a[kk] + mesh.sig_s[kk] + tt))
+                    c = 2.0 * D * Dn / (D + Dn) / (h * h)
+                    A[k, k] += c
+                    A[k, kk] -= c
+                elif not (mesh.bc & side):
+                    A[k, k] += 2.0 * D / (h * (h + 4.0 * D))
+    return A.tocsr()
+
+
+def diffusion_exact(mesh: Mesh, phi_post, tau=2.0):
+    """The exact solution of the diffusion closing stage's finite-volume
+    system (a sparse direct solve), per cell."""
+    from scipy.sparse.linalg import spsolve
+    A = diffusion_matrix(mesh, tau)
+    b = mesh.sig_s * np.asarray(phi_post, dtype=np.float64).ravel()
+    return np.asarray(spsolve(A, b)) if np.any(b != 0.0) else np.zeros(mesh.ncell)
+
+
+def diffusion_collided(mesh: Mesh, phi_post, tau=2.0, tol=1e-12, max_iter=200):
+    """The collided flux of the diffusion closing stage as the method computes
+    it: Jacobi-preconditioned conjugate gradients on the finite-volume system
+    from phi = 0, stopping after the first iteration with
+    ||r||_2 <= tol ||b||_2 (or at max_iter).  Returns nodal values (equal at
+    the four nodes of a cell, like the DG solution), the iteration count and
+    ||r|| / ||b||.  (The iterate agrees with diffusion_exact to about
+    cond(A) tol in norm; in cells where the flux is many orders below its
+    peak only the iteration itself fixes the low digits.)"""
+    A = diffusion_matrix(mesh, tau)
+    b = mesh.sig_s * np.asarray(phi_post, dtype=np.float64).ravel()
+    d = A.diagonal()
+    x = np.zeros(mesh.ncell)
+    bb = float(b @ b)
+    it, rr = 0, bb
+    if bb > 0.0 and max_iter > 0:
+        r = b.copy()
+        z = r / d
+        p = z.copy()
+        rz = float(r @ z)
+        while True:
+            q = A @ p
+            alpha = rz / float(p @ q)
+            x = x + alpha * p
+            r = r - alpha * q
+            z = r / d
+            rz_new = float(r @ z)
+            rr = float(r @ r)
+            it += 1
+            if rr <= tol * tol * bb or it >= max_iter or not np.isfinite(rr):
+                break
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+    resid = math.sqrt(rr / bb) if bb > 0.0 else 0.0
+    return np.repeat(x.reshape(-1, 1), 4, axis=1), it, resid
+
+
 # ----------------------------------------------------------------------------
 # Time stepping (Sec. 2.2, steps 1-4)
 # ----------------------------------------------------------------------------
@@ -438,6 +521,7 @@ class HybridOracle:
         self.si_max = int(prob.get("si_max_iter", 200))
         self.w_cut_rel = float(prob.get("w_cut_rel", 1e-8))
         self.si_norm_total = int(prob.get("si_norm", 0)) == 1
+        self.diffusion = int(prob.get("closure", 0)) == 1
         ns = prob.get("n_s_cell")
         # steady pure MC (no limit in any cell): no collided solve, no remap
         # (Sec. 3: relabeling is unnecessary there), phi_R = phi_pre
@@ -465,10 +549,15 @@ class HybridOracle:
                         bal_mc=bal1, bal_remap=zero, segments=seg1, seg_mc=seg1, seg_remap=0,
                         si_iters=0, si_resid=0.0, census_alive=0, census_kept=0,
                         thin_factor=1.0, thin_overflow=False, q_remap=None)
-        # step 2: collided S_N-DG solve, zero initial/boundary data
-        phi_c, iters, resid = dg_collided(m, self.quad, phi_post, self.tau, self.si_tol,
-                                          self.si_max,
-                                          phi_pre if self.si_norm_total else None)
+        # step 2: collided S_N-DG solve, zero initial/boundary data (or the
+        # diffusion closing stage by conjugate gradients)
+        if self.diffusion:
+            phi_c, iters, resid = diffusion_collided(m, phi_post, self.tau, self.si_tol,
+                                                     self.si_max)
+        else:
+            phi_c, iters, resid = dg_collided(m, self.quad, phi_post, self.tau, self.si_tol,
+                                              self.si_max,
+                                              phi_pre if self.si_norm_total else None)
         # step 3: remap source Q + sigma_s (phi_pre + phi_post + phi_c), scatter-free leg
         qR = (self.q + m.sig_s * (phi_pre + phi_post))[:, None] + m.sig_s[:, None] * phi_c
         _, TR, bal2, seg2, cand = mc_pass(m, self.points, PASS_REMAP, self.n_s, qR, self.n_p,

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libslh.so")
-SOURCES = ["mc.hip", "dg.hip", "util.hip", "capi.hip", "server.hip"]
+SOURCES = ["mc.hip", "dg.hip", "diffusion.hip", "util.hip", "capi.hip", "server.hip"]
 ARCH = os.environ.get("SLH_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

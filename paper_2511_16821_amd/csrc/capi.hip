@@ -134,6 +134,7 @@ struct Sizes {
   bool dg_table;
   int dg_cw;
   long long dg_chunks;
+  bool diffusion;  // diffusion closing stage: no direction planes, CG vectors instead
   size_t bytes;
 };
 
@@ -217,6 +218,8 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
   if (p->steady != 0 && p->steady != 1) return fail(SLH_E_INVALID_ARG, "steady must be 0 or 1");
   if (p->si_norm != SLH_SI_NORM_COLLIDED && p->si_norm != SLH_SI_NORM_TOTAL)
     return fail(SLH_E_INVALID_ARG, "si_norm must be SLH_SI_NORM_COLLIDED or SLH_SI_NORM_TOTAL");
+  if (p->closure != SLH_CLOSE_SN && p->closure != SLH_CLOSE_DIFFUSION)
+    return fail(SLH_E_INVALID_ARG, "closure must be SLH_CLOSE_SN or SLH_CLOSE_DIFFUSION");
   if (!p->steady) {
     if (!(p->c > 0.0) || !isfinite(p->c)) return fail(SLH_E_INVALID_ARG, "c must be > 0");
     if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(SLH_E_INVALID_ARG, "dt must be > 0");
@@ -265,6 +268,11 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
           return fail(SLH_E_INVALID_ARG,
                       "steady state with a cell of sigma_a = 0 needs an explicit horizon");
     }
+    if (p->closure == SLH_CLOSE_DIFFUSION)
+      for (long long i = 0; i < n; ++i)
+        if (!(p->sigma_a[i] + p->sigma_s[i] + time_term(p) > 0.0))
+          return fail(SLH_E_INVALID_ARG,
+                      "the diffusion closure needs sigma_t + tau/(c dt) > 0 in every cell");
     if (p->steady && !(horizon_of(p) <= 1e15))
       return fail(SLH_E_INVALID_ARG, "horizon above 1e15 (a small sigma_a sets the default)");
   }
@@ -291,6 +299,7 @@ static Sizes sizes_of(const slh_problem* p) {
          (size_t)z.n_copies * kTallyStride * 8 * (size_t)z.n_cells > ((size_t)1 << 30))
     z.n_copies /= 2;
   z.fp32 = p->precision == SLH_FP32_TRACK;
+  z.diffusion = p->closure == SLH_CLOSE_DIFFUSION;
   const bool fields = p->sigma_s && p->sigma_a;
   plan_dg(z, p, fields ? (long long)material_values(p).size() : -1);
   const size_t rb = z.fp32 ? 4 : 8;
@@ -304,7 +313,11 @@ static Sizes sizes_of(const slh_problem* p) {
   b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 4;  // nodal sources, trees
   b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
   b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
-  b += (size_t)z.n_dir * nc * 32 + (size_t)z.n_dir * 256;  // direction planes, element data
+  if (z.diffusion)
+    b += nc * 8 * 9 + 4 * 1024 * 8;          // CG: diag, cE, cN, x, r, z, p x2, q; partials
+  else
+    b += (size_t)z.n_dir * nc * 32;          // direction planes
+  b += (size_t)z.n_dir * 256;                // element data
   if (z.dg_table) b += nc * 4 + (size_t)z.n_mat * 8 + (size_t)z.n_dir * z.n_mat * 256;
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
   b += (size_t)z.cap * bank * 2;             // census banks
@@ -391,6 +404,11 @@ struct slh_solver {
   double hx, hy, area, adt, tau, si_tol;
   double horizon = 0.0;     // steady state: path length at which a history ends
   bool skip_remap = false;  // steady pure MC: no collided solve, phi_R = phi_pre
+  // diffusion closing stage: coefficients, CG vectors, block partials
+  double *cg_diag = nullptr, *cg_e = nullptr, *cg_n = nullptr, *cg_x = nullptr,
+         *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr,
+         *cg_part = nullptr;
+  int cg_npart = 0;
   long long thin_margin = 0;
   int si_max;
 
@@ -546,7 +564,20 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->phi_post, double, nc);
   ALLOC(s->phi_R, double, nc);
   ALLOC(s->phi_c, double, 4 * nc);
-  ALLOC(s->psi, double, (size_t)z.n_dir * 4 * nc);
+  if (z.diffusion) {
+    ALLOC(s->cg_diag, double, nc);
+    ALLOC(s->cg_e, double, nc);
+    ALLOC(s->cg_n, double, nc);
+    ALLOC(s->cg_x, double, nc);
+    ALLOC(s->cg_r, double, nc);
+    ALLOC(s->cg_z, double, nc);
+    ALLOC(s->cg_p, double, 2 * nc);
+    ALLOC(s->cg_q, double, nc);
+    s->cg_npart = cg_partials(nc);
+    ALLOC(s->cg_part, double, 4 * s->cg_npart);
+  } else {
+    ALLOC(s->psi, double, (size_t)z.n_dir * 4 * nc);
+  }
   ALLOC(s->dirmat, double, (size_t)z.n_dir * 32);
   if (z.dg_table) {
     ALLOC(s->mat_id, int, nc);
@@ -635,6 +666,9 @@ static slh_status setup(slh_solver* s) {
   }
   HIP_TRY(launch_dg_tables(z.n_dir, z.dg_table ? z.n_mat : 0, s->dirs, s->sig_e_mat, s->hx,
                            s->hy, s->dirmat, s->coef, st));
+  if (z.diffusion)
+    HIP_TRY(launch_diff_coef(p.nx, p.ny, s->mat64, time_term(&p), s->hx, s->hy, p.boundary,
+                             s->cg_diag, s->cg_e, s->cg_n, st));
   HIP_TRY(hipMemcpyAsync(s->sobol, sobol_table_host(), 4 * 32 * 32, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_build_tree(s->qn1, nc, s->adt, s->tree1, st));
   HIP_TRY(launch_count_tree(s->tree1, nc, z.n_p, s->ctree1, st));
@@ -778,12 +812,40 @@ static DgArgs dg_args(slh_solver* s) {
   return d;
 }
 
+static CgArgs cg_args(slh_solver* s) {
+  CgArgs c;
+  c.nx = s->prob.nx;
+  c.ny = s->prob.ny;
+  c.diag = s->cg_diag;
+  c.cE = s->cg_e;
+  c.cN = s->cg_n;
+  c.x = s->cg_x;
+  c.r = s->cg_r;
+  c.z = s->cg_z;
+  c.P = s->cg_p;
+  c.q = s->cg_q;
+  c.n_part = s->cg_npart;
+  c.part_a = s->cg_part;
+  c.part_b = s->cg_part + 2 * s->cg_npart;
+  c.st = s->st;
+  return c;
+}
+
+// the collided solve proper: the diffusion closing stage unless the step
+// has no collided solve at all
+static bool use_cg(const slh_solver* s) { return s->z.diffusion && !s->skip_remap; }
+
 static slh_status enqueue_si(slh_solver* s, hipStream_t st, int n_it) {
   const Sizes& z = s->z;
-  const DgArgs d = dg_args(s);
-  for (int it = 0; it < n_it; ++it) {
-    HIP_TRY(launch_dg_sweep(d, z.dg_table, st));
-    HIP_TRY(launch_dg_reduce(d, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
+  if (use_cg(s)) {
+    const CgArgs c = cg_args(s);
+    for (int it = 0; it < n_it; ++it) HIP_TRY(launch_cg_iteration(c, s->si_tol, s->si_max, st));
+  } else {
+    const DgArgs d = dg_args(s);
+    for (int it = 0; it < n_it; ++it) {
+      HIP_TRY(launch_dg_sweep(d, z.dg_table, st));
+      HIP_TRY(launch_dg_reduce(d, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
+    }
   }
   HIP_TRY(hipMemcpyAsync(s->h_res, &s->st->si_done, kSiStateBytes, hipMemcpyDeviceToHost, st));
   return SLH_OK;
@@ -811,8 +873,12 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
                          s->bal_store + 0);
       HIP_TRY(hipMemcpyAsync(s->h_bal + 0, s->bal_store + 0, sizeof(BalStore),
                              hipMemcpyDeviceToHost, st));
-      // pure MC in steady state: no collided solve (phi_c = 0, no sweep)
-      HIP_TRY(launch_si_start(dg_args(s), s->skip_remap ? 0 : s->si_max, st));
+      if (use_cg(s)) {
+        HIP_TRY(launch_cg_start(cg_args(s), s->sig_s, s->phi_post, s->si_max, st));
+      } else {
+        // pure MC in steady state: no collided solve (phi_c = 0, no sweep)
+        HIP_TRY(launch_si_start(dg_args(s), s->skip_remap ? 0 : s->si_max, st));
+      }
       return enqueue_si(s, st, n_it);
     }
     case kB1: {
@@ -821,6 +887,7 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
                                  z.n_cand, st));
         return SLH_OK;
       }
+      if (use_cg(s)) HIP_TRY(launch_cg_to_nodal(cg_args(s), s->phi_c, st));
       HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c,
                                   s->qnR, st));
       HIP_TRY(launch_build_tree(s->qnR, nc, s->adt, s->treeR, st));

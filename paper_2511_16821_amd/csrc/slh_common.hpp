@@ -257,6 +257,11 @@ struct DevState {
   int si_iter;                  // iterations done in this step
   int si_bad;                   // non-finite residual
   double si_dn2, si_nrm2;       // |phi_new - phi_old|^2, |phi_new|^2 of the last iteration
+                                // (diffusion closing stage: |r|^2, |b|^2)
+  // conjugate gradients of the diffusion closing stage
+  double cg_rz;                 // r . z of the current iterate
+  double cg_beta;               // beta of the next direction update
+  double cg_bb;                 // b . b
 };
 
 struct PassArgs {
@@ -361,6 +366,31 @@ size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny);
 // Start of a step's source iteration: phi_c = 0, iteration state reset, the
 // first iterate's nodal source, reflected traces of the first sweep zeroed.
 hipError_t launch_si_start(const DgArgs& a, int si_max, hipStream_t s);
+
+// Diffusion closing stage (cell-centred finite volumes, Jacobi-preconditioned
+// conjugate gradients).  Vectors are per cell; P holds two n-vectors (the
+// search direction of the current and of the previous iteration, by parity);
+// part_a / part_b hold 2 n_part block partials each.
+struct CgArgs {
+  int nx, ny;
+  const double* diag;   // diagonal of the system (per unit cell area)
+  const double* cE;     // coupling to the x+1 neighbour (0 across the boundary)
+  const double* cN;     // coupling to the y+1 neighbour
+  double *x, *r, *z, *P, *q;
+  double *part_a, *part_b;
+  int n_part;           // cg_partials(nx * ny)
+  DevState* st;         // the source-iteration state doubles as the CG state
+};
+int cg_partials(long long n);
+hipError_t launch_diff_coef(int nx, int ny, const double2* mat, double tt, double hx, double hy,
+                            int bc, double* diag, double* cE, double* cN, hipStream_t s);
+// b = sigma_s phi_post, x = 0, and the state of a new solve (done at once when
+// b = 0 or si_max = 0)
+hipError_t launch_cg_start(const CgArgs& a, const double* sig_s, const double* phi_post,
+                           int si_max, hipStream_t s);
+// one iteration (nothing once the state says done); stops at |r| <= tol |b|
+hipError_t launch_cg_iteration(const CgArgs& a, double tol, int si_max, hipStream_t s);
+hipError_t launch_cg_to_nodal(const CgArgs& a, double* phi_c, hipStream_t s);
 hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s);
 // One reduction of a source iteration: phi_c is replaced in place by the
 // direction sum of the planes, the next iterate's source is formed, and the

@@ -1,0 +1,127 @@
+"""Pins of the oracle's diffusion closing stage (the cheap deterministic solver
+the paper suggests for the collided flux), a cell-centred finite-volume
+discretisation of
+    sigma_r phi - div(D grad phi) = S,  sigma_r = sigma_a + tau/(c dt),
+    D = 1/(3 (sigma_t + tau/(c dt)))  (no tau/(c dt) in steady state),
+with Marshak (zero incoming partial current) vacuum sides and zero-current
+reflective sides.
+
+* Closed box, uniform source: the exact solution is the constant S/sigma_r.
+* Homogeneous slab with uniform source and Marshak sides: the continuous
+  solution S/sigma_r (1 - A cosh(k (x - L/2))), k = sqrt(sigma_r/D),
+  A = 1/(cosh(k L/2) + 2 D k sinh(k L/2)); the scheme is second order.
+* Discrete balance: removal plus boundary outflow equals the source.
+* The matrix is a symmetric M-matrix, so the solution is positive.
+* The stage's conjugate-gradient iteration reaches the direct solve to within
+  cond(A) times its tolerance, and stops at the first iterate within it.
+"""
+import numpy as np
+import pytest
+
+
+def _mesh(oracle, nx, ny, L, H, ss, sa, **kw):
+    from paper_2511_16821_amd import workloads as W
+    p = W._problem(nx, ny, (0.0, L, 0.0, H), np.full((ny, nx), ss) if np.isscalar(ss) else ss,
+                   np.full((ny, nx), sa) if np.isscalar(sa) else sa, np.zeros((ny, nx)),
+                   n_s=0, n_particles=1, sn_order=2, **kw)
+    return oracle.Mesh(p), p
+
+
+@pytest.mark.parametrize("steady", [False, True])
+def test_closed_box_is_uniform(oracle, steady):
+    ss, sa, dt = 0.7, 0.3, 0.25
+    m, _ = _mesh(oracle, 6, 5, 3.0, 2.5, ss, sa, dt=dt, steady=steady, boundary=15)
+    phi_post = np.full(30, 2.0)
+    phi = oracle.diffusion_exact(m, phi_post, tau=2.0)
+    sr = sa + (0.0 if steady else 2.0 / dt)
+    assert np.allclose(phi, ss * 2.0 / sr, rtol=1e-13, atol=0)
+
+
+def test_slab_marshak_closed_form(oracle):
+    nx, L, ss, sa = 200, 4.0, 1.0, 0.5
+    m, _ = _mesh(oracle, nx, 1, L, 1.0, ss, sa, steady=True, boundary=4 | 8)
+    phi = oracle.diffusion_exact(m, np.ones(nx))
+    S, sr, D = ss * 1.0, sa, 1.0 / (3.0 * (ss + sa))
+    k = np.sqrt(sr / D)
+    A = 1.0 / (np.cosh(k * L / 2) + 2.0 * D * k * np.sinh(k * L / 2))
+    h = L / nx
+    a = np.arange(nx) * h - L / 2
+    b = a + h
+    want = S / sr * (1.0 - A * (np.sinh(k * b) - np.sinh(k * a)) / (k * h))
+    err = np.max(np.abs(phi - want)) / np.max(want)
+    assert err <= 2e-4, err
+    # halving the mesh spacing cuts the error about fourfold
+    m2, _ = _mesh(oracle, nx // 2, 1, L, 1.0, ss, sa, steady=True, boundary=4 | 8)
+    phi2 = oracle.diffusion_exact(m2, np.ones(nx // 2))
+    h2 = 2 * h
+    a2 = np.arange(nx // 2) * h2 - L / 2
+    want2 = S / sr * (1.0 - A * (np.sinh(k * (a2 + h2)) - np.sinh(k * a2)) / (k * h2))
+    err2 = np.max(np.abs(phi2 - want2)) / np.max(want2)
+    assert 2.5 <= err2 / err <= 6.0, (err, err2)
+
+
+def test_balance_and_m_matrix(oracle):
+    rng = np.random.default_rng(3)
+    nx, ny = 9, 7
+    ss = rng.uniform(0.1, 3.0, size=(ny, nx))
+    sa = rng.uniform(0.01, 1.0, size=(ny, nx))
+    m, _ = _mesh(oracle, nx, ny, 2.0, 1.4, ss, sa, dt=0.1, boundary=2 | 4)
+    A = oracle.diffusion_matrix(m).toarray()
+    assert np.array_equal(A, A.T)
+    off = A - np.diag(np.diag(A))
+    assert np.all(off <= 0.0) and np.all(np.diag(A) > 0.0)
+    assert np.all(A.sum(axis=1) > 0.0)  # removal makes every row dominant
+    phi_post = rng.uniform(0.0, 2.0, size=nx * ny)
+    phi = oracle.diffusion_exact(m, phi_post)
+    assert np.all(phi > 0.0)
+    # removal + outflow through the vacuum sides = source (per unit area)
+    hx, hy = 2.0 / nx, 1.4 / ny
+    tt = 2.0 / 0.1
+    D = 1.0 / (3.0 * (ss + sa + tt)).ravel()
+    src = (ss.ravel() * phi_post).sum() * hx * hy
+    rem = ((sa.ravel() + tt) * phi).sum() * hx * hy
+    out = 0.0
+    for j in range(ny):
+        for i in range(nx):
+            k = j * nx + i
+            if i == 0:  # x_lo vacuum (x_hi reflective)
+                out += 2 * D[k] * phi[k] / (hx + 4 * D[k]) * hy
+            if j == ny - 1:  # y_hi vacuum (y_lo reflective)
+                out += 2 * D[k] * phi[k] / (hy + 4 * D[k]) * hx
+    assert rem + out == pytest.approx(src, rel=1e-12)
+
+
+def test_hybrid_step_with_diffusion_closure(oracle):
+    """In a closed homogeneous box with a uniform source the diffusion closing
+    stage is exact (its solution is the infinite-medium value), so a steady
+    step keeps the remap total Q/sigma_a."""
+    from paper_2511_16821_amd import workloads as W
+    ss, sa, Q, n = 0.6, 0.4, 2.0, 4
+    p = W.homogeneous_box(n=n, L=4.0, sig_s=ss, sig_a=sa, src_cells=((0, n), (0, n)), n_s=1,
+                          n_particles=20000, sn_order=4, steady=True, boundary=15, closure=1)
+    p["q"] = np.full((n, n), Q)
+    r = oracle.HybridOracle(p).step()
+    assert r["phi_R"].mean() == pytest.approx(Q / sa, rel=1e-6)
+    assert r["phi_c"].mean() == pytest.approx(ss * r["phi_post"].mean() / sa, rel=1e-9)
+
+
+@pytest.mark.parametrize("steady", [False, True])
+def test_cg_reaches_the_direct_solve(oracle, steady):
+    rng = np.random.default_rng(11)
+    nx, ny = 21, 13
+    ss = rng.uniform(0.1, 3.0, size=(ny, nx))
+    sa = rng.uniform(0.05, 1.0, size=(ny, nx))
+    m, _ = _mesh(oracle, nx, ny, 4.2, 2.6, ss, sa, dt=0.5, steady=steady, boundary=1)
+    phi_post = rng.uniform(0.0, 1.0, size=nx * ny)
+    exact = oracle.diffusion_exact(m, phi_post)
+    cond = np.linalg.cond(oracle.diffusion_matrix(m).toarray())
+    for tol in (1e-6, 1e-10, 1e-13):
+        phi, it, res = oracle.diffusion_collided(m, phi_post, tol=tol, max_iter=1000)
+        assert res <= tol and 0 < it < 1000
+        assert np.linalg.norm(phi[:, 0] - exact) <= cond * tol * np.linalg.norm(exact)
+        assert np.all(phi[:, 0] == phi[:, 3])
+        # the previous iterate was not yet within the tolerance
+        _, it1, res1 = oracle.diffusion_collided(m, phi_post, tol=tol, max_iter=it - 1)
+        assert it1 == it - 1 and res1 > tol
+    z, it0, _ = oracle.diffusion_collided(m, np.zeros(nx * ny))
+    assert it0 == 0 and np.all(z == 0.0)

@@ -488,6 +488,37 @@ def steady_protocol(S, torch, args):
     return out
 
 
+def closure_cmp(S, torch, args):
+    """The two closing stages on the benchmark workload (checkerboard 140x140,
+    1e6 particles per pass): DG S_N source iteration against the cell-centred
+    diffusion solve (conjugate gradients), for several N_s: time per step,
+    iterations of the last step, the collided stage's share of the step, and
+    the relative L2 distance of the final phi_R between the two (the modelling
+    difference of the closures, not a parity figure)."""
+    import numpy as np
+    from paper_2511_16821_amd import workloads as W
+    rows = []
+    for ns in [int(v) for v in args.closure_ns.split(",") if v != ""]:
+        row = {"n_s": ns}
+        flux = {}
+        for name, cl in (("sn", 0), ("diffusion", 1)):
+            p = W.c2(n_s=ns, closure=cl)
+            wall, st = timed_run(S, torch, p, args.closure_steps, 1)
+            s = S.Solver(p)
+            s.advance(args.closure_steps, allow_not_converged=True)
+            flux[name] = s.get_flux(0)
+            s.destroy()
+            row[name] = {"ms_per_step": 1e3 * wall / args.closure_steps,
+                         "iterations_last_step": int(st["si_iterations"]),
+                         "ms_collided_last_step": float(st["ms_dg"])}
+        row["rel_l2_diffusion_vs_sn"] = float(np.linalg.norm(flux["diffusion"] - flux["sn"]) /
+                                              np.linalg.norm(flux["sn"]))
+        log("closures:", json.dumps(row))
+        rows.append(row)
+    return {"workload": "checkerboard 140x140, 1e6 particles/pass, dt=0.05, S_12, %d steps"
+                        % args.closure_steps, "rows": rows}
+
+
 def serve_bench(S, torch, args):
     """Poisson arrivals of mixed solve requests; continuous batching on the
     server vs the same stream served one solve at a time on the same GPU
@@ -587,6 +618,10 @@ def main():
     ap.add_argument("--steady", action="store_true",
                     help="the paper's steady-state protocol on the slab and duct stand-ins")
     ap.add_argument("--steady-ns", default="0,5,10,20,-1")
+    ap.add_argument("--closures", action="store_true",
+                    help="DG S_N against the diffusion closing stage on the benchmark workload")
+    ap.add_argument("--closure-ns", default="0,1,2,4")
+    ap.add_argument("--closure-steps", type=int, default=20)
     ap.add_argument("--reflect", action="store_true",
                     help="reflective sides on the C1 box against vacuum")
     ap.add_argument("--reflect-steps", type=int, default=10)
@@ -669,6 +704,8 @@ def main():
         out["protocol"] = protocol(S, torch, args)
     if args.steady:
         out["steady_protocol"] = steady_protocol(S, torch, args)
+    if args.closures:
+        out["closures"] = closure_cmp(S, torch, args)
     if args.nsx:
         out["cellwise_ns"] = cellwise_ns(S, torch, args)
     if args.reflect:

@@ -1,7 +1,8 @@
 """Serving (continuous batching on one GPU): every request's result is the
 same alone and in the mix (bitwise: all sums are order-independent fixed
-point), admission never exceeds the HBM budget, and requests that can never
-fit are rejected."""
+point), across time-dependent and steady requests, both closing stages, both
+precisions and per-cell scatter limits; admission never exceeds the HBM
+budget, and requests that can never fit are rejected."""
 import numpy as np
 import pytest
 
@@ -30,6 +31,10 @@ def _mix(n=10, seed=3):
                                precision=int(rng.integers(0, 2)), seed=100 + r, sn_order=4)
         if r % 4 == 1:  # per-cell scatter limits travel with the request
             p["n_s_cell"] = rng.choice([-1, 0, 1, 3], size=side * side).astype(np.int32)
+        if r % 4 == 2:  # steady-state requests, with the whole-flux stopping test
+            p.update(steady=True, si_norm=1, si_tol=1e-9, si_max_iter=400)
+        if r % 4 == 3:  # the diffusion closing stage
+            p.update(closure=1, si_max_iter=1000)
         out.append((p, int(rng.integers(2, 6))))
     return out
 
@@ -51,7 +56,8 @@ def test_results_same_alone_and_in_mix(S):
     srv.destroy()
     for (p, k), (flux, bal, lat) in zip(reqs, got):
         f, b = _alone(S, p, k)
-        assert np.array_equal(flux, f), (p["nx"], p["n_s"], p["precision"])
+        assert np.array_equal(flux, f), (p["nx"], p["n_s"], p["precision"],
+                                         p.get("steady", False), p.get("closure", 0))
         assert bal["census"] == b["census"] and bal["segments"] == b["segments"]
         assert lat["latency_ms"] >= lat["run_ms"] > 0
     log("mix of", len(reqs), "requests matches the standalone runs bitwise")

@@ -432,7 +432,9 @@ def steady_protocol(S, torch, args):
     pseudo-random points at 2^10 .. 2^18 particles, the fitted slopes, the
     time per solve, and the source-iteration count with the whole-flux
     stopping test (tolerance 1e-6) and, for comparison, the collided-only
-    test at the same tolerance."""
+    test at the same tolerance; where every cell has sigma_t > 0 (the duct),
+    also the distance of the diffusion closing stage's solution from the S_N
+    reference at the same particle count."""
     import numpy as np
     from paper_2511_16821_amd import workloads as W
     ns_list = [int(v) for v in args.steady_ns.split(",") if v != ""]
@@ -461,6 +463,12 @@ def steady_protocol(S, torch, args):
             nref = max(np.linalg.norm(ref), 1e-300)
             row = {"n_s": ns, "particles": ladder, "si_iterations": it_ref,
                    "si_iterations_collided_test": it_coll}
+            if ns >= 0 and min(np.min(base["sigma_a"] + base["sigma_s"]), 1.0) > 0.0:
+                # the diffusion closing stage at 2^22 particles against the S_N
+                # reference: the modelling error of the cheaper closure
+                fd, td, itd = run(2 ** 22, 0, 7777, closure=1, si_tol=1e-12, si_max_iter=5000)
+                row["diffusion"] = {"rel_l2_vs_sn_reference": float(np.linalg.norm(fd - ref) / nref),
+                                    "cg_iterations": itd, "ms_per_solve": 1e3 * td}
             for pname, mode in (("qmc", 0), ("halton", 2), ("mc", 1)):
                 errs, times = [], []
                 for n in ladder:

@@ -17,7 +17,12 @@
 //                  the iteration count, in the source-iteration state, so the
 //                  host loop and the graph batching of the S_N path apply.
 // Reductions use fixed association orders: results do not depend on
-// scheduling.  The two p buffers alternate by iteration parity.
+// scheduling.  The two p buffers alternate by iteration parity.  Meshes of
+// up to 4096 cells run the whole solve in one workgroup instead
+// (k_cg_solve_one_block), with barriers in place of launches: there the
+// launches cost more than the work (a 1500-cell solve of 279 iterations
+// 2.4 ms against 4.4 ms), while on larger meshes one compute unit's share of
+// the bandwidth is the limit (19600 cells: 1.8 against 1.1 ms per step).
 #include "slh_common.hpp"
 
 namespace slh {
@@ -236,6 +241,102 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_residual(const double* part, in
   }
 }
 
+// Small meshes (n <= kCgOneBlockMax): the whole solve in one workgroup of
+// 1024 threads, the iterations separated by barriers instead of launches.
+// Same iteration as above; the sums are formed per wave (shuffles in a fixed
+// pattern) and then over the 16 wave sums in index order, by every thread,
+// so every thread holds the same alpha, beta and decision.
+constexpr int kCgOneBlock = 1024;
+constexpr long long kCgOneBlockMax = 4096;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__global__ __launch_bounds__(kCgOneBlock) void k_cg_solve_one_block(
+    int nx, int ny, const double* __restrict__ diag, const double* __restrict__ cE,
+    const double* __restrict__ cN, double* __restrict__ x, double* __restrict__ r,
+    double* __restrict__ z, double* __restrict__ P, double* __restrict__ q, DevState* st,
+    double tol, int si_max) {
+  if (st->si_done) return;
+  __shared__ double s_a[kCgOneBlock / 64], s_b[kCgOneBlock / 64];
+  const long long n = (long long)nx * ny;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  constexpr int nw = kCgOneBlock / 64;
+  int it = st->si_iter;
+  double beta = st->cg_beta, rz = st->cg_rz;
+  const double bb = st->cg_bb;
+  double rr = 0.0;
+  int done = 0, conv = 0, bad = 0;
+  while (!done) {
+    double* __restrict__ pk = P + (long long)(it & 1) * n;
+    const double* __restrict__ pm = P + (long long)((it + 1) & 1) * n;
+    double pq = 0.0;
+    for (long long k = t; k < n; k += kCgOneBlock) {
+      const int i = (int)(k % nx), j = (int)(k / nx);
+      const double pc = z[k] + beta * pm[k];
+      double a = 0.0;
+      if (i + 1 < nx) a += cE[k] * (z[k + 1] + beta * pm[k + 1]);
+      if (i > 0) a += cE[k - 1] * (z[k - 1] + beta * pm[k - 1]);
+      if (j + 1 < ny) a += cN[k] * (z[k + nx] + beta * pm[k + nx]);
+      if (j > 0) a += cN[k - nx] * (z[k - nx] + beta * pm[k - nx]);
+      const double qk = diag[k] * pc - a;
+      pk[k] = pc;
+      q[k] = qk;
+      pq += pc * qk;
+    }
+    pq = wave_sum(pq);
+    if (lane == 0) s_a[wv] = pq;
+    __syncthreads();
+    pq = 0.0;
+    for (int w = 0; w < nw; ++w) pq += s_a[w];
+    const double alpha = rz / pq;
+    double rzn = 0.0, rrn = 0.0;
+    for (long long k = t; k < n; k += kCgOneBlock) {
+      x[k] += alpha * pk[k];
+      const double rk = r[k] - alpha * q[k];
+      const double zk = rk / diag[k];
+      r[k] = rk;
+      z[k] = zk;
+      rzn += rk * zk;
+      rrn += rk * rk;
+    }
+    rzn = wave_sum(rzn);
+    rrn = wave_sum(rrn);
+    __syncthreads();  // every thread has read s_a; z of all cells is written
+    if (lane == 0) {
+      s_a[wv] = rzn;
+      s_b[wv] = rrn;
+    }
+    __syncthreads();
+    rzn = 0.0;
+    rrn = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      rzn += s_a[w];
+      rrn += s_b[w];
+    }
+    __syncthreads();  // s_a, s_b are reused by the next iteration
+    it += 1;
+    rr = rrn;
+    bad = !isfinite(rrn) || !isfinite(rzn);
+    conv = !bad && rrn <= tol * tol * bb;
+    done = bad || conv || it >= si_max;
+    beta = rz != 0.0 ? rzn / rz : 0.0;
+    rz = rzn;
+  }
+  if (t == 0) {
+    st->si_iter = it;
+    st->si_dn2 = rr;
+    st->si_nrm2 = bb;
+    st->si_bad = bad;
+    st->si_conv = conv;
+    st->si_done = 1;
+    st->cg_beta = beta;
+    st->cg_rz = rz;
+  }
+}
+
 // phi_c nodal = the cell value at all four nodes.
 __global__ void k_cg_to_nodal(long long n, const double* __restrict__ x,
                               double* __restrict__ phi_c) {
@@ -256,8 +357,16 @@ hipError_t launch_cg_start(const CgArgs& a, const double* sig_s, const double* p
   return hipGetLastError();
 }
 
+bool cg_one_block(long long n) { return n <= kCgOneBlockMax; }
+
 hipError_t launch_cg_iteration(const CgArgs& a, double tol, int si_max, hipStream_t s) {
   const long long n = (long long)a.nx * a.ny;
+  if (cg_one_block(n)) {  // the whole remaining solve
+    hipLaunchKernelGGL(k_cg_solve_one_block, dim3(1), dim3(kCgOneBlock), 0, s, a.nx, a.ny,
+                       (const double*)a.diag, (const double*)a.cE, (const double*)a.cN, a.x, a.r,
+                       a.z, a.P, a.q, a.st, tol, si_max);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_cg_spmv, dim3(a.n_part), dim3(kCgBlock), 0, s, a.nx, a.ny,
                      (const double*)a.diag, (const double*)a.cE, (const double*)a.cN,
                      (const double*)a.z, a.P, a.q, a.part_a, (const DevState*)a.st);

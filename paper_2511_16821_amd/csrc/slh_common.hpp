@@ -388,7 +388,9 @@ hipError_t launch_diff_coef(int nx, int ny, const double2* mat, double tt, doubl
 // b = 0 or si_max = 0)
 hipError_t launch_cg_start(const CgArgs& a, const double* sig_s, const double* phi_post,
                            int si_max, hipStream_t s);
-// one iteration (nothing once the state says done); stops at |r| <= tol |b|
+// one iteration (nothing once the state says done); stops at |r| <= tol |b|.
+// On meshes where cg_one_block holds, one call runs the whole solve.
+bool cg_one_block(long long n);
 hipError_t launch_cg_iteration(const CgArgs& a, double tol, int si_max, hipStream_t s);
 hipError_t launch_cg_to_nodal(const CgArgs& a, double* phi_c, hipStream_t s);
 hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s);

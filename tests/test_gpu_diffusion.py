@@ -75,6 +75,22 @@ def test_diffusion_steady(S, oracle):
     _run_pair(S, oracle, r, 1, "steady random")
 
 
+def test_diffusion_large_mesh(S, oracle):
+    """Above 4096 cells the solve runs as three kernels per iteration over
+    many workgroups (up to 4096, in one workgroup): a 300 x 270 mesh with
+    random block materials."""
+    from paper_2511_16821_amd import workloads as W
+    rng = np.random.default_rng(21)
+    nx, ny = 300, 270
+    ss = np.kron(rng.uniform(0.1, 2.0, size=(9, 10)), np.ones((30, 30)))
+    sa = np.kron(rng.uniform(0.05, 1.0, size=(9, 10)), np.ones((30, 30)))
+    q = np.zeros((ny, nx))
+    q[120:150, 135:165] = 1.0
+    p = W._problem(nx, ny, (0.0, 6.0, 0.0, 5.4), ss, sa, q, n_s=1, n_particles=20000,
+                   dt=0.2, sn_order=2, boundary=1)
+    _run_pair(S, oracle, p, 2, "large mesh")
+
+
 def test_diffusion_fp32(S, oracle):
     from paper_2511_16821_amd import workloads as W
     p = dict(W.checkerboard(blocks=5, cells_per_block=4, n_s=1, n_particles=20000, dt=0.05,

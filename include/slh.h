@@ -173,7 +173,25 @@ typedef struct {
                                    /* si_norm is not used).  phi_c is then    */
                                    /* constant in each cell.  Needs           */
                                    /* sigma_t + tau/(c dt) > 0 in every cell. */
+    int32_t si_accel;              /* S_N closing stage only:                  */
+                                   /* SLH_ACCEL_NONE (0): plain source        */
+                                   /* iteration; SLH_ACCEL_DSA (1): diffusion  */
+                                   /* synthetic acceleration, after each sweep */
+                                   /* phi += delta with delta the solution of  */
+                                   /* the closure's diffusion system (see      */
+                                   /* closure; vacuum condition on every side, */
+                                   /* since reflected inflow lags) for the     */
+                                   /* source sigma_s times the cell average of */
+                                   /* the sweep's change,                      */
+                                   /* solved by conjugate gradients to 1e-6    */
+                                   /* relative residual (at most 500 steps) in */
+                                   /* one workgroup.  Same fixed point, fewer  */
+                                   /* sweeps when scattering dominates.  Needs */
+                                   /* sigma_t + tau/(c dt) > 0 in every cell.  */
 } slh_problem;
+
+#define SLH_ACCEL_NONE 0
+#define SLH_ACCEL_DSA 1
 
 #define SLH_CLOSE_SN 0
 #define SLH_CLOSE_DIFFUSION 1

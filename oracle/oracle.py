@@ -118,6 +118,13 @@ def lib():
         L.or_dg_sweep.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_dg_one_iteration.restype = C.c_int
+        L.or_dg_one_iteration.argtypes = [C.POINTER(_Mesh), C.c_void_p, C.c_int, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p]
+        L.or_dg_sigma_e.restype = None
+        L.or_dg_sigma_e.argtypes = [C.POINTER(_Mesh), C.c_double, C.c_void_p]
         L.or_dg_collided.restype = C.c_int
         L.or_dg_collided.argtypes = [C.POINTER(_Mesh), C.c_double, C.c_int, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -415,7 +422,7 @@ def dg_collided(mesh: Mesh, quad, phi_post, tau=2.0, tol=1e-12, max_iter=200, ph
     return phi.reshape(mesh.ncell, 4), it, res.value
 
 
-def diffusion_matrix(mesh: Mesh, tau=2.0):
+def diffusion_matrix(mesh: Mesh, tau=2.0, vacuum_sides=False):
     """Cell-centred finite-volume diffusion operator of the collided flux, the
     alternative closing stage (a P1 reading of the collided equation with the
     step closure of the S_N stage):
@@ -424,8 +431,9 @@ def diffusion_matrix(mesh: Mesh, tau=2.0):
     Interior faces carry D_f (phi_i - phi_j)/h with the harmonic mean
     D_f = 2 D_i D_j / (D_i + D_j); a vacuum side has zero incoming partial
     current (Marshak), which gives the outflow 2 D_i phi_i / (h + 4 D_i) per
-    unit face length; a reflective side has none.  Returns the sparse matrix
-    (per unit cell area, so that A phi = sigma_s phi_post)."""
+    unit face length; a reflective side has none (vacuum_sides: every side
+    takes the vacuum condition).  Returns the sparse matrix (per unit cell
+    area, so that A phi = sigma_s phi_post)."""
     from scipy.sparse import lil_matrix
     nx, ny = mesh.nx, mesh.ny
     hx = (mesh.x_hi - mesh.x_lo) / nx
@@ -446,7 +454,7 @@ def diffusion_matrix(mesh: Mesh, tau=2.0):
                     c = 2.0 * D * Dn / (D + Dn) / (h * h)
                     A[k, k] += c
                     A[k, kk] -= c
-                elif not (mesh.bc & side):
+                elif vacuum_sides or not (mesh.bc & side):
                     A[k, k] += 2.0 * D / (h * (h + 4.0 * D))
     return A.tocsr()
 
@@ -471,8 +479,16 @@ def diffusion_collided(mesh: Mesh, phi_post, tau=2.0, tol=1e-12, max_iter=200):
     peak only the iteration itself fixes the low digits.)"""
     A = diffusion_matrix(mesh, tau)
     b = mesh.sig_s * np.asarray(phi_post, dtype=np.float64).ravel()
+    x, it, resid = _pcg(A, b, tol, max_iter)
+    return np.repeat(x.reshape(-1, 1), 4, axis=1), it, resid
+
+
+def _pcg(A, b, tol, max_iter):
+    """Jacobi-preconditioned conjugate gradients from x = 0, stopping after the
+    first iteration with ||r||_2 <= tol ||b||_2 (or at max_iter).  Returns
+    x, the iteration count and ||r|| / ||b||."""
     d = A.diagonal()
-    x = np.zeros(mesh.ncell)
+    x = np.zeros(len(b))
     bb = float(b @ b)
     it, rr = 0, bb
     if bb > 0.0 and max_iter > 0:
@@ -493,8 +509,57 @@ def diffusion_collided(mesh: Mesh, phi_post, tau=2.0, tol=1e-12, max_iter=200):
                 break
             p = z + (rz_new / rz) * p
             rz = rz_new
-    resid = math.sqrt(rr / bb) if bb > 0.0 else 0.0
-    return np.repeat(x.reshape(-1, 1), 4, axis=1), it, resid
+    return x, it, (math.sqrt(rr / bb) if bb > 0.0 else 0.0)
+
+
+DSA_TOL, DSA_MAX_ITER = 1e-6, 500
+
+
+def dg_collided_dsa(mesh: Mesh, quad, phi_post, tau=2.0, tol=1e-12, max_iter=200,
+                    phi_pre=None):
+    """Source iteration with diffusion synthetic acceleration: after each
+    transport sweep (phi^{k+1/2}), the correction delta solves the diffusion
+    system of diffusion_matrix for the source sigma_s times the cell average
+    of phi^{k+1/2} - phi^k (conjugate gradients to DSA_TOL, at most
+    DSA_MAX_ITER steps), and phi^{k+1} = phi^{k+1/2} + delta at every node of
+    the cell.  The correction takes the vacuum condition on every side: the
+    sweep's reflected inflow lags one iteration, and a zero-current condition
+    there makes the corrected iteration diverge (a closed box does).  The
+    stopping test is that of dg_collided, on phi^{k+1} - phi^k.  Returns (phi
+    nodal, sweeps, residual)."""
+    ox, oy, w = (np.ascontiguousarray(v, dtype=np.float64) for v in quad)
+    rx, ry = mirror_indices((ox, oy, w))
+    n, nd = mesh.ncell, len(w)
+    sig_e = np.zeros(n)
+    lib().or_dg_sigma_e(C.byref(mesh.s), tau, _p(sig_e))
+    if not np.all(sig_e > 0.0):
+        raise ValueError("the diffusion correction needs sigma_t + tau/(c dt) > 0 everywhere")
+    out_x = np.zeros(nd * 2 * mesh.ny)
+    out_y = np.zeros(nd * 2 * mesh.nx)
+    A = diffusion_matrix(mesh, tau, vacuum_sides=True)
+    phi_post = np.ascontiguousarray(phi_post, dtype=np.float64)
+    phi = np.zeros(4 * n)
+    it, resid = 0, 0.0
+    while it < max_iter:
+        acc = np.zeros(4 * n)
+        if lib().or_dg_one_iteration(C.byref(mesh.s), _p(sig_e), nd, _p(ox), _p(oy), _p(w),
+                                     _p(rx), _p(ry), _p(phi_post), _p(phi), _p(out_x),
+                                     _p(out_y), _p(acc)) != 0:
+            raise RuntimeError("DG sweep failed")
+        it += 1
+        dnode = (acc - phi).reshape(n, 4)
+        b = mesh.sig_s * (0.25 * ((dnode[:, 0] + dnode[:, 1]) + (dnode[:, 2] + dnode[:, 3])))
+        delta, _, _ = _pcg(A, b, DSA_TOL, DSA_MAX_ITER)
+        new = acc.reshape(n, 4) + delta[:, None]
+        d = dnode + delta[:, None]
+        ref = new if phi_pre is None else new + (phi_pre + phi_post)[:, None]
+        dn = math.sqrt(float(np.sum(d * d)))
+        nrm = math.sqrt(float(np.sum(ref * ref)))
+        phi = new.ravel()
+        resid = dn / nrm if nrm > 0.0 else 0.0
+        if dn <= tol * nrm:
+            break
+    return phi.reshape(n, 4), it, resid
 
 
 # ----------------------------------------------------------------------------
@@ -522,6 +587,7 @@ class HybridOracle:
         self.w_cut_rel = float(prob.get("w_cut_rel", 1e-8))
         self.si_norm_total = int(prob.get("si_norm", 0)) == 1
         self.diffusion = int(prob.get("closure", 0)) == 1
+        self.dsa = not self.diffusion and int(prob.get("si_accel", 0)) == 1
         ns = prob.get("n_s_cell")
         # steady pure MC (no limit in any cell): no collided solve, no remap
         # (Sec. 3: relabeling is unnecessary there), phi_R = phi_pre
@@ -555,9 +621,9 @@ class HybridOracle:
             phi_c, iters, resid = diffusion_collided(m, phi_post, self.tau, self.si_tol,
                                                      self.si_max)
         else:
-            phi_c, iters, resid = dg_collided(m, self.quad, phi_post, self.tau, self.si_tol,
-                                              self.si_max,
-                                              phi_pre if self.si_norm_total else None)
+            solve = dg_collided_dsa if self.dsa else dg_collided
+            phi_c, iters, resid = solve(m, self.quad, phi_post, self.tau, self.si_tol,
+                                        self.si_max, phi_pre if self.si_norm_total else None)
         # step 3: remap source Q + sigma_s (phi_pre + phi_post + phi_c), scatter-free leg
         qR = (self.q + m.sig_s * (phi_pre + phi_post))[:, None] + m.sig_s[:, None] * phi_c
         _, TR, bal2, seg2, cand = mc_pass(m, self.points, PASS_REMAP, self.n_s, qR, self.n_p,

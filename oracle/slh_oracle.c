@@ -687,16 +687,85 @@ int or_dg_sweep(int nx, int ny, double x_lo, double x_hi, double y_lo, double y_
 }
 
 /*
+ * One source iteration of the collided solve (step 2 of Sec. 2.2): with the
+ * nodal iterate phi [n_cells*4], sweep every direction with the source
+ * sig_s/(4 pi) (phi + phi_post) and return acc = sum_m w_m psi_m.  The
+ * reflected traces lag one iteration: out_x/out_y hold each direction's
+ * outflow traces on its downwind x and y sides (two nodes per row or column)
+ * from the previous call (zero before the first) and are replaced by this
+ * iteration's.  sig_e per cell as in or_dg_collided.  Returns 0, or -1 when a
+ * cell system is singular.
+ */
+int or_dg_one_iteration(const or_mesh *M, const double *sig_e, int n_dir,
+                        const double *dox, const double *doy, const double *dw,
+                        const int *refl_x, const int *refl_y, const double *phi_post,
+                        const double *phi, double *out_x, double *out_y, double *acc)
+{
+    const int nx = M->nx, ny = M->ny;
+    const int64_t ncell = (int64_t)nx * ny;
+    const size_t nn = (size_t)ncell * 4;
+    const size_t bx = (size_t)2 * ny, by = (size_t)2 * nx;
+    double *src = (double *)malloc(sizeof(double) * nn);
+    double *psi = (double *)malloc(sizeof(double) * nn);
+    double *prev_x = (double *)malloc(sizeof(double) * (size_t)n_dir * bx);
+    double *prev_y = (double *)malloc(sizeof(double) * (size_t)n_dir * by);
+    int rc = 0;
+    for (int64_t i = 0; i < ncell; ++i)
+        for (int k = 0; k < 4; ++k)
+            src[4 * i + k] = M->sig_s[i] / (4.0 * M_PI) * (phi[4 * i + k] + phi_post[i]);
+    for (size_t k = 0; k < nn; ++k) acc[k] = 0.0;
+    memcpy(prev_x, out_x, sizeof(double) * (size_t)n_dir * bx);
+    memcpy(prev_y, out_y, sizeof(double) * (size_t)n_dir * by);
+    for (int m = 0; m < n_dir; ++m) {
+        const int rx = (dox[m] > 0.0) ? (M->bc & OR_BC_XLO) : (M->bc & OR_BC_XHI);
+        const int ry = (doy[m] > 0.0) ? (M->bc & OR_BC_YLO) : (M->bc & OR_BC_YHI);
+        const double *in_x = rx ? prev_x + (size_t)refl_x[m] * bx : NULL;
+        const double *in_y = ry ? prev_y + (size_t)refl_y[m] * by : NULL;
+        if (or_dg_sweep(nx, ny, M->x_lo, M->x_hi, M->y_lo, M->y_hi, sig_e,
+                        dox[m], doy[m], src, in_x, in_y, psi) != 0) {
+            rc = -1;
+            break;
+        }
+        for (size_t k = 0; k < nn; ++k) acc[k] += dw[m] * psi[k];
+        /* outflow traces: x side xi = 1 (nodes 1, 3) if Ox > 0 else xi = 0
+         * (nodes 0, 2); y side eta = 1 (nodes 2, 3) if Oy > 0 else 0 (0, 1) */
+        const int ib = (dox[m] > 0.0) ? nx - 1 : 0, fx = (dox[m] > 0.0) ? 1 : 0;
+        for (int j = 0; j < ny; ++j) {
+            const double *pc = psi + 4 * ((int64_t)j * nx + ib);
+            out_x[(size_t)m * bx + 2 * j] = pc[fx];
+            out_x[(size_t)m * bx + 2 * j + 1] = pc[fx + 2];
+        }
+        const int jb = (doy[m] > 0.0) ? ny - 1 : 0, fy = (doy[m] > 0.0) ? 1 : 0;
+        for (int i = 0; i < nx; ++i) {
+            const double *pc = psi + 4 * ((int64_t)jb * nx + i);
+            out_y[(size_t)m * by + 2 * i] = pc[2 * fy];
+            out_y[(size_t)m * by + 2 * i + 1] = pc[2 * fy + 1];
+        }
+    }
+    free(src); free(psi); free(prev_x); free(prev_y);
+    return rc;
+}
+
+/* sigma_e = sigma_t + tau/(c dt) per cell (sigma_t in steady state). */
+void or_dg_sigma_e(const or_mesh *M, double tau_closure, double *sig_e)
+{
+    const int64_t ncell = (int64_t)M->nx * M->ny;
+    for (int64_t i = 0; i < ncell; ++i)
+        sig_e[i] = M->sig_a[i] + M->sig_s[i]
+                 + (M->steady ? 0.0 : tau_closure / (M->c * M->dt));
+}
+
+/*
  * Source iteration for the collided flux (step 2 of Sec. 2.2):
  *   (sig_t + tau/(c dt)) psi + Omega.grad psi = sig_s/(4 pi) (phi_c + phi_post)
  * (in steady state, M->steady, without the tau/(c dt) term)
  * with zero initial data, vacuum sides, and reflective sides (M->bc) whose
- * inflow lags one iteration (see below).  The time derivative over the
- * step is closed by tau/(c dt) (tau = 2: the step average of a flux growing
- * linearly from zero).  phi_post is cell-constant; phi_c is nodal bilinear.
- * Stops when ||phi_new - phi_old||_2 <= tol ||phi_new||_2 (nodal vectors),
- * or, when phi_pre is given, <= tol ||phi_new + phi_pre + phi_post||_2 (the
- * whole flux of the step as the reference).
+ * inflow lags one iteration (or_dg_one_iteration).  The time derivative over
+ * the step is closed by tau/(c dt) (tau = 2: the step average of a flux
+ * growing linearly from zero).  phi_post is cell-constant; phi_c is nodal
+ * bilinear.  Stops when ||phi_new - phi_old||_2 <= tol ||phi_new||_2 (nodal
+ * vectors), or, when phi_pre is given, <= tol ||phi_new + phi_pre +
+ * phi_post||_2 (the whole flux of the step as the reference).
  * phi [n_cells*4] receives the result; returns the number of sweeps.
  */
 int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
@@ -709,57 +778,19 @@ int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
     const int64_t ncell = (int64_t)nx * ny;
     const size_t nn = (size_t)ncell * 4;
     double *sig_e = (double *)malloc(sizeof(double) * (size_t)ncell);
-    double *src = (double *)malloc(sizeof(double) * nn);
-    double *psi = (double *)malloc(sizeof(double) * nn);
     double *acc = (double *)malloc(sizeof(double) * nn);
-    /* Reflective sides: the inflow of direction m on such a side is the
-     * outflow, on the same side, of its mirror image (refl_x: Ox -> -Ox,
-     * refl_y: Oy -> -Oy) from the previous source iteration (zero in the
-     * first); out_x/out_y hold each direction's outflow traces on its
-     * downwind x and y sides, two nodes per row or column. */
     const size_t bx = (size_t)2 * ny, by = (size_t)2 * nx;
     double *out_x = (double *)calloc((size_t)n_dir * bx, sizeof(double));
     double *out_y = (double *)calloc((size_t)n_dir * by, sizeof(double));
-    double *prev_x = (double *)calloc((size_t)n_dir * bx, sizeof(double));
-    double *prev_y = (double *)calloc((size_t)n_dir * by, sizeof(double));
-    for (int64_t i = 0; i < ncell; ++i)
-        sig_e[i] = M->sig_a[i] + M->sig_s[i]
-                 + (M->steady ? 0.0 : tau_closure / (M->c * M->dt));
+    or_dg_sigma_e(M, tau_closure, sig_e);
     for (size_t k = 0; k < nn; ++k) phi[k] = 0.0;
     int it = 0;
     double resid = 0.0;
     while (it < max_iter) {
-        for (int64_t i = 0; i < ncell; ++i)
-            for (int k = 0; k < 4; ++k)
-                src[4 * i + k] = M->sig_s[i] / (4.0 * M_PI) * (phi[4 * i + k] + phi_post[i]);
-        for (size_t k = 0; k < nn; ++k) acc[k] = 0.0;
-        memcpy(prev_x, out_x, sizeof(double) * (size_t)n_dir * bx);
-        memcpy(prev_y, out_y, sizeof(double) * (size_t)n_dir * by);
-        for (int m = 0; m < n_dir; ++m) {
-            const int rx = (dox[m] > 0.0) ? (M->bc & OR_BC_XLO) : (M->bc & OR_BC_XHI);
-            const int ry = (doy[m] > 0.0) ? (M->bc & OR_BC_YLO) : (M->bc & OR_BC_YHI);
-            const double *in_x = rx ? prev_x + (size_t)refl_x[m] * bx : NULL;
-            const double *in_y = ry ? prev_y + (size_t)refl_y[m] * by : NULL;
-            if (or_dg_sweep(nx, ny, M->x_lo, M->x_hi, M->y_lo, M->y_hi, sig_e,
-                            dox[m], doy[m], src, in_x, in_y, psi) != 0) {
-                it = -1;
-                goto done;
-            }
-            for (size_t k = 0; k < nn; ++k) acc[k] += dw[m] * psi[k];
-            /* outflow traces: x side xi = 1 (nodes 1, 3) if Ox > 0 else xi = 0
-             * (nodes 0, 2); y side eta = 1 (nodes 2, 3) if Oy > 0 else 0 (0, 1) */
-            const int ib = (dox[m] > 0.0) ? nx - 1 : 0, fx = (dox[m] > 0.0) ? 1 : 0;
-            for (int j = 0; j < ny; ++j) {
-                const double *pc = psi + 4 * ((int64_t)j * nx + ib);
-                out_x[(size_t)m * bx + 2 * j] = pc[fx];
-                out_x[(size_t)m * bx + 2 * j + 1] = pc[fx + 2];
-            }
-            const int jb = (doy[m] > 0.0) ? ny - 1 : 0, fy = (doy[m] > 0.0) ? 1 : 0;
-            for (int i = 0; i < nx; ++i) {
-                const double *pc = psi + 4 * ((int64_t)jb * nx + i);
-                out_y[(size_t)m * by + 2 * i] = pc[2 * fy];
-                out_y[(size_t)m * by + 2 * i + 1] = pc[2 * fy + 1];
-            }
+        if (or_dg_one_iteration(M, sig_e, n_dir, dox, doy, dw, refl_x, refl_y, phi_post, phi,
+                                out_x, out_y, acc) != 0) {
+            it = -1;
+            break;
         }
         it += 1;
         double dn = 0.0, nrm = 0.0;
@@ -775,9 +806,7 @@ int or_dg_collided(const or_mesh *M, double tau_closure, int n_dir,
         resid = (nrm > 0.0) ? dn / nrm : 0.0;
         if (dn <= tol * nrm) break;
     }
-done:
     if (resid_out) *resid_out = resid;
-    free(sig_e); free(src); free(psi); free(acc);
-    free(out_x); free(out_y); free(prev_x); free(prev_y);
+    free(sig_e); free(acc); free(out_x); free(out_y);
     return it;
 }

@@ -135,6 +135,7 @@ struct Sizes {
   int dg_cw;
   long long dg_chunks;
   bool diffusion;  // diffusion closing stage: no direction planes, CG vectors instead
+  bool dsa;        // S_N with the diffusion correction: planes, CG vectors and dnode
   size_t bytes;
 };
 
@@ -220,6 +221,8 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
     return fail(SLH_E_INVALID_ARG, "si_norm must be SLH_SI_NORM_COLLIDED or SLH_SI_NORM_TOTAL");
   if (p->closure != SLH_CLOSE_SN && p->closure != SLH_CLOSE_DIFFUSION)
     return fail(SLH_E_INVALID_ARG, "closure must be SLH_CLOSE_SN or SLH_CLOSE_DIFFUSION");
+  if (p->si_accel != SLH_ACCEL_NONE && p->si_accel != SLH_ACCEL_DSA)
+    return fail(SLH_E_INVALID_ARG, "si_accel must be SLH_ACCEL_NONE or SLH_ACCEL_DSA");
   if (!p->steady) {
     if (!(p->c > 0.0) || !isfinite(p->c)) return fail(SLH_E_INVALID_ARG, "c must be > 0");
     if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(SLH_E_INVALID_ARG, "dt must be > 0");
@@ -268,11 +271,11 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
           return fail(SLH_E_INVALID_ARG,
                       "steady state with a cell of sigma_a = 0 needs an explicit horizon");
     }
-    if (p->closure == SLH_CLOSE_DIFFUSION)
+    if (p->closure == SLH_CLOSE_DIFFUSION || p->si_accel == SLH_ACCEL_DSA)
       for (long long i = 0; i < n; ++i)
         if (!(p->sigma_a[i] + p->sigma_s[i] + time_term(p) > 0.0))
-          return fail(SLH_E_INVALID_ARG,
-                      "the diffusion closure needs sigma_t + tau/(c dt) > 0 in every cell");
+          return fail(SLH_E_INVALID_ARG, "the diffusion closure and the diffusion correction "
+                                         "need sigma_t + tau/(c dt) > 0 in every cell");
     if (p->steady && !(horizon_of(p) <= 1e15))
       return fail(SLH_E_INVALID_ARG, "horizon above 1e15 (a small sigma_a sets the default)");
   }
@@ -300,6 +303,7 @@ static Sizes sizes_of(const slh_problem* p) {
     z.n_copies /= 2;
   z.fp32 = p->precision == SLH_FP32_TRACK;
   z.diffusion = p->closure == SLH_CLOSE_DIFFUSION;
+  z.dsa = !z.diffusion && p->si_accel == SLH_ACCEL_DSA;
   const bool fields = p->sigma_s && p->sigma_a;
   plan_dg(z, p, fields ? (long long)material_values(p).size() : -1);
   const size_t rb = z.fp32 ? 4 : 8;
@@ -313,10 +317,10 @@ static Sizes sizes_of(const slh_problem* p) {
   b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 4;  // nodal sources, trees
   b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
   b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
-  if (z.diffusion)
+  if (z.diffusion || z.dsa)
     b += nc * 8 * 9 + 4 * 1024 * 8;          // CG: diag, cE, cN, x, r, z, p x2, q; partials
-  else
-    b += (size_t)z.n_dir * nc * 32;          // direction planes
+  if (z.dsa) b += nc * 32;                   // nodal change of a sweep
+  if (!z.diffusion) b += (size_t)z.n_dir * nc * 32;  // direction planes
   b += (size_t)z.n_dir * 256;                // element data
   if (z.dg_table) b += nc * 4 + (size_t)z.n_mat * 8 + (size_t)z.n_dir * z.n_mat * 256;
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
@@ -379,15 +383,16 @@ __global__ void k_state_set_bank(DevState* st, long long n, double maxabs,
   }
 }
 
-// The device's source-iteration fields (DevState::si_done .. si_nrm2), as
+// The device's iteration state (DevState::si, fields done .. nrm2), as
 // copied to pinned host memory after each batch of iterations.
 struct SiState {
   int done, conv, iter, bad;
   double dn2, nrm2;
 };
 static const size_t kSiStateBytes = sizeof(SiState);
-static_assert(offsetof(DevState, si_nrm2) - offsetof(DevState, si_done) == 24,
-              "SiState mirrors the DevState fields");
+static_assert(offsetof(IterState, nrm2) - offsetof(IterState, done) == 24 &&
+                  offsetof(IterState, done) == 0,
+              "SiState mirrors the leading IterState fields");
 
 struct slh_solver {
   slh_problem prob;
@@ -405,6 +410,7 @@ struct slh_solver {
   double horizon = 0.0;     // steady state: path length at which a history ends
   bool skip_remap = false;  // steady pure MC: no collided solve, phi_R = phi_pre
   // diffusion closing stage: coefficients, CG vectors, block partials
+  double* dnode = nullptr;  // diffusion correction: nodal change of a sweep
   double *cg_diag = nullptr, *cg_e = nullptr, *cg_n = nullptr, *cg_x = nullptr,
          *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr,
          *cg_part = nullptr;
@@ -564,7 +570,9 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->phi_post, double, nc);
   ALLOC(s->phi_R, double, nc);
   ALLOC(s->phi_c, double, 4 * nc);
-  if (z.diffusion) {
+  if (z.dsa) ALLOC(s->dnode, double, 4 * nc);
+  if (!z.diffusion) ALLOC(s->psi, double, (size_t)z.n_dir * 4 * nc);
+  if (z.diffusion || z.dsa) {
     ALLOC(s->cg_diag, double, nc);
     ALLOC(s->cg_e, double, nc);
     ALLOC(s->cg_n, double, nc);
@@ -575,8 +583,6 @@ static slh_status setup(slh_solver* s) {
     ALLOC(s->cg_q, double, nc);
     s->cg_npart = cg_partials(nc);
     ALLOC(s->cg_part, double, 4 * s->cg_npart);
-  } else {
-    ALLOC(s->psi, double, (size_t)z.n_dir * 4 * nc);
   }
   ALLOC(s->dirmat, double, (size_t)z.n_dir * 32);
   if (z.dg_table) {
@@ -666,9 +672,12 @@ static slh_status setup(slh_solver* s) {
   }
   HIP_TRY(launch_dg_tables(z.n_dir, z.dg_table ? z.n_mat : 0, s->dirs, s->sig_e_mat, s->hx,
                            s->hy, s->dirmat, s->coef, st));
-  if (z.diffusion)
-    HIP_TRY(launch_diff_coef(p.nx, p.ny, s->mat64, time_term(&p), s->hx, s->hy, p.boundary,
-                             s->cg_diag, s->cg_e, s->cg_n, st));
+  // the diffusion correction takes the vacuum condition on every side (the
+  // sweep's reflected inflow lags one iteration; a zero-current side there
+  // makes the corrected iteration diverge)
+  if (z.diffusion || z.dsa)
+    HIP_TRY(launch_diff_coef(p.nx, p.ny, s->mat64, time_term(&p), s->hx, s->hy,
+                             z.dsa ? 0 : p.boundary, s->cg_diag, s->cg_e, s->cg_n, st));
   HIP_TRY(hipMemcpyAsync(s->sobol, sobol_table_host(), 4 * 32 * 32, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_build_tree(s->qn1, nc, s->adt, s->tree1, st));
   HIP_TRY(launch_count_tree(s->tree1, nc, z.n_p, s->ctree1, st));
@@ -797,6 +806,7 @@ static DgArgs dg_args(slh_solver* s) {
   d.phi_c = s->phi_c;
   d.src = s->dg_src;
   d.psi = s->psi;
+  d.dnode = s->z.dsa && !s->skip_remap ? s->dnode : nullptr;
   d.mat_id = s->mat_id;
   d.n_mat = z.n_mat;
   d.cw = z.dg_cw;
@@ -827,9 +837,17 @@ static CgArgs cg_args(slh_solver* s) {
   c.n_part = s->cg_npart;
   c.part_a = s->cg_part;
   c.part_b = s->cg_part + 2 * s->cg_npart;
-  c.st = s->st;
+  // the closing stage's solve is the step's iteration; the correction is a
+  // solve inside each source iteration, skipped once that iteration is done
+  c.cs = s->z.diffusion ? &s->st->si : &s->st->dsa;
+  c.gate = s->z.diffusion ? nullptr : &s->st->si.done;
   return c;
 }
+
+// Diffusion correction of a source iteration: tolerance and iteration limit
+// of its conjugate gradients.
+constexpr double kDsaTol = 1e-6;
+constexpr int kDsaMaxIter = 500;
 
 // the collided solve proper: the diffusion closing stage unless the step
 // has no collided solve at all
@@ -840,6 +858,16 @@ static slh_status enqueue_si(slh_solver* s, hipStream_t st, int n_it) {
   if (use_cg(s)) {
     const CgArgs c = cg_args(s);
     for (int it = 0; it < n_it; ++it) HIP_TRY(launch_cg_iteration(c, s->si_tol, s->si_max, st));
+  } else if (z.dsa && !s->skip_remap) {
+    const DgArgs d = dg_args(s);
+    const CgArgs c = cg_args(s);
+    for (int it = 0; it < n_it; ++it) {
+      HIP_TRY(launch_dg_sweep(d, z.dg_table, st));
+      HIP_TRY(launch_dg_reduce(d, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
+      HIP_TRY(launch_dsa_start(c, s->sig_s, s->dnode, kDsaMaxIter, st));
+      HIP_TRY(launch_cg_solve_one_block(c, kDsaTol, kDsaMaxIter, st));
+      HIP_TRY(launch_dsa_apply(d, s->cg_x, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
+    }
   } else {
     const DgArgs d = dg_args(s);
     for (int it = 0; it < n_it; ++it) {
@@ -847,7 +875,7 @@ static slh_status enqueue_si(slh_solver* s, hipStream_t st, int n_it) {
       HIP_TRY(launch_dg_reduce(d, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
     }
   }
-  HIP_TRY(hipMemcpyAsync(s->h_res, &s->st->si_done, kSiStateBytes, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(s->h_res, &s->st->si.done, kSiStateBytes, hipMemcpyDeviceToHost, st));
   return SLH_OK;
 }
 

@@ -58,12 +58,12 @@ __global__ void k_si_start(long long n, const double* __restrict__ sig_s,
                            double* __restrict__ S, double* __restrict__ bnd0, long long n_bnd,
                            DevState* st, int si_max) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->si_iter = 0;
-    st->si_conv = si_max == 0 ? 1 : 0;
-    st->si_done = si_max == 0 ? 1 : 0;
-    st->si_bad = 0;
-    st->si_dn2 = 0.0;
-    st->si_nrm2 = 0.0;
+    st->si.iter = 0;
+    st->si.conv = si_max == 0 ? 1 : 0;
+    st->si.done = si_max == 0 ? 1 : 0;
+    st->si.bad = 0;
+    st->si.dn2 = 0.0;
+    st->si.nrm2 = 0.0;
   }
   const double inv4pi = 0.25 / M_PI;
   const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -294,7 +294,7 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
   // iteration's outflow of the mirrored direction
   // (REFL: some side reflects and g.bnd holds the traces)
   const size_t sb = (size_t)2 * (nx + ny);  // boundary traces per direction
-  const int it = REFL ? g.st->si_iter : 0;
+  const int it = REFL ? g.st->si.iter : 0;
   const bool rx_in = REFL && (g.bc & (apos ? 1 : 2)) != 0;
   const bool ry_in = REFL && (g.bc & (bpos ? 4 : 8)) != 0;
   const bool rx_out = REFL && (g.bc & (apos ? 2 : 1)) != 0;
@@ -472,7 +472,7 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
 
 template <bool TABLE, int Q, bool REFL>
 __global__ __launch_bounds__(512) void k_dg_sweep_pc(DgArgs g) {
-  if (g.st->si_done) return;  // the whole workgroup: no barrier is left pending
+  if (g.st->si.done) return;  // the whole workgroup: no barrier is left pending
   const int m = blockIdx.x;
   const bool apos = g.dir[3 * m + 0] > 0.0, bpos = g.dir[3 * m + 1] > 0.0;
   if (apos) {
@@ -543,8 +543,8 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
     const double* __restrict__ dir, double* __restrict__ phi,
     const double* __restrict__ sig_s, const double* __restrict__ phi_post,
     const double* __restrict__ phi_pre, double* __restrict__ S,
-    double* __restrict__ partials, const DevState* st) {
-  if (st->si_done) return;
+    double* __restrict__ partials, double* __restrict__ dnode, const DevState* st) {
+  if (st->si.done) return;
   __shared__ double s_d[kRedBlock], s_n[kRedBlock];
   const double inv4pi = 0.25 / M_PI;
   double dsum = 0.0, nsum = 0.0;
@@ -562,6 +562,49 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
     }
     for (; m < n_dir; ++m) v += dir[3 * m + 2] * psi[(long long)m * n_nodes + k];
     const double d = v - phi[k];  // in place: the sweep read only S
+    phi[k] = v;
+    if (dnode) {  // the correction, the source and the residual come later
+      dnode[k] = d;
+      continue;
+    }
+    S[k] = sig_s[k >> 2] * inv4pi * (v + phi_post[k >> 2]);
+    const double vr = phi_pre ? v + (phi_pre[k >> 2] + phi_post[k >> 2]) : v;
+    dsum += d * d;
+    nsum += vr * vr;
+  }
+  if (dnode) return;  // the same for the whole grid
+  s_d[threadIdx.x] = dsum;
+  s_n[threadIdx.x] = nsum;
+  __syncthreads();
+  for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s_d[threadIdx.x] += s_d[threadIdx.x + off];
+      s_n[threadIdx.x] += s_n[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = s_d[0];
+    partials[2 * blockIdx.x + 1] = s_n[0];
+  }
+}
+
+// phi += delta (per cell) at every node, the next source, and partials of
+// |dnode + delta|^2 and |phi|^2 (or of the whole-flux norm) for k_dg_residual.
+__global__ __launch_bounds__(kRedBlock) void k_dsa_apply(
+    long long n_nodes, double* __restrict__ phi, const double* __restrict__ dnode,
+    const double* __restrict__ delta, const double* __restrict__ sig_s,
+    const double* __restrict__ phi_post, const double* __restrict__ phi_pre,
+    double* __restrict__ S, double* __restrict__ partials, const DevState* st) {
+  if (st->si.done) return;
+  __shared__ double s_d[kRedBlock], s_n[kRedBlock];
+  const double inv4pi = 0.25 / M_PI;
+  double dsum = 0.0, nsum = 0.0;
+  for (long long k = (long long)blockIdx.x * kRedBlock + threadIdx.x; k < n_nodes;
+       k += (long long)gridDim.x * kRedBlock) {
+    const double dl = delta[k >> 2];
+    const double v = phi[k] + dl;
+    const double d = dnode[k] + dl;
     phi[k] = v;
     S[k] = sig_s[k >> 2] * inv4pi * (v + phi_post[k >> 2]);
     const double vr = phi_pre ? v + (phi_pre[k >> 2] + phi_post[k >> 2]) : v;
@@ -590,7 +633,7 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
 // limit is reached, or when the residual is not finite.
 __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int n_part,
                                                      DevState* st, double si_tol, int si_max) {
-  if (st->si_done) return;
+  if (st->si.done) return;
   __shared__ double s_d[256], s_n[256];
   double d = 0.0, n = 0.0;
   for (int b = threadIdx.x; b < n_part; b += 256) {
@@ -610,14 +653,14 @@ __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int
   if (threadIdx.x == 0) {
     const double dn2 = s_d[0], nrm2 = s_n[0];
     const double dn = sqrt(dn2), nrm = sqrt(nrm2);
-    st->si_dn2 = dn2;
-    st->si_nrm2 = nrm2;
-    st->si_iter += 1;
+    st->si.dn2 = dn2;
+    st->si.nrm2 = nrm2;
+    st->si.iter += 1;
     const int bad = !isfinite(dn) || !isfinite(nrm);
     const int conv = !bad && dn <= si_tol * nrm;
-    st->si_bad = bad;
-    st->si_conv = conv;
-    st->si_done = bad || conv || st->si_iter >= si_max;
+    st->si.bad = bad;
+    st->si.conv = conv;
+    st->si.done = bad || conv || st->si.iter >= si_max;
   }
 }
 
@@ -625,7 +668,18 @@ hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, doubl
                             int si_max, hipStream_t s) {
   hipLaunchKernelGGL(k_dg_reduce, dim3(n_part), dim3(kRedBlock), 0, s, a.n_dir,
                      4ll * a.nx * a.ny, (const double*)a.psi, a.dir, a.phi_c, a.sig_s, a.phi_post,
-                     a.phi_pre, a.src, partials, (const DevState*)a.st);
+                     a.phi_pre, a.src, partials, a.dnode, (const DevState*)a.st);
+  if (!a.dnode)
+    hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,
+                       a.st, si_tol, si_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_dsa_apply(const DgArgs& a, const double* delta, double* partials, int n_part,
+                            double si_tol, int si_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_dsa_apply, dim3(n_part), dim3(kRedBlock), 0, s, 4ll * a.nx * a.ny,
+                     a.phi_c, (const double*)a.dnode, delta, a.sig_s, a.phi_post, a.phi_pre,
+                     a.src, partials, (const DevState*)a.st);
   hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,
                      a.st, si_tol, si_max);
   return hipGetLastError();

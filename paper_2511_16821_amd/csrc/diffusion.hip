@@ -151,33 +151,60 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_start(
 }
 
 __global__ __launch_bounds__(kCgBlock) void k_cg_start_state(const double* part, int n_part,
-                                                             DevState* st, int si_max) {
+                                                             IterState* cs, const int* gate,
+                                                             int max_iter) {
+  if (gate && *gate) return;
   const double rz = sum_partials(part, n_part, 0);
   const double bb = sum_partials(part, n_part, 1);
   if (threadIdx.x == 0) {
-    st->si_iter = 0;
-    st->si_bad = 0;
-    st->cg_rz = rz;
-    st->cg_beta = 0.0;
-    st->cg_bb = bb;
-    st->si_dn2 = bb;
-    st->si_nrm2 = bb;
+    cs->iter = 0;
+    cs->bad = 0;
+    cs->rz = rz;
+    cs->beta = 0.0;
+    cs->bb = bb;
+    cs->dn2 = bb;
+    cs->nrm2 = bb;
     // a zero source has the exact solution 0
-    const int conv = si_max == 0 || bb == 0.0;
-    st->si_conv = conv;
-    st->si_done = conv;
-    if (bb == 0.0) st->si_dn2 = 0.0;
+    const int conv = max_iter == 0 || bb == 0.0;
+    cs->conv = conv;
+    cs->done = conv;
+    if (bb == 0.0) cs->dn2 = 0.0;
   }
+}
+
+// Start of the diffusion correction of a source iteration: b = sigma_s times
+// the cell average of phi^{k+1/2} - phi^k (dnode, four nodes per cell), x = 0,
+// r = b, z = r / diag, p_{-1} = 0, partials of r . z and b . b.
+__global__ __launch_bounds__(kCgBlock) void k_dsa_start(
+    long long n, const double* __restrict__ sig_s, const double* __restrict__ dnode,
+    const double* __restrict__ diag, double* __restrict__ x, double* __restrict__ r,
+    double* __restrict__ z, double* __restrict__ p1, double* __restrict__ part,
+    const int* gate) {
+  if (*gate) return;
+  double rz = 0.0, bb = 0.0;
+  for (long long k = (long long)blockIdx.x * kCgBlock + threadIdx.x; k < n;
+       k += (long long)gridDim.x * kCgBlock) {
+    const double4 d = reinterpret_cast<const double4*>(dnode)[k];
+    const double b = sig_s[k] * (0.25 * ((d.x + d.y) + (d.z + d.w)));
+    const double zk = b / diag[k];
+    x[k] = 0.0;
+    r[k] = b;
+    z[k] = zk;
+    p1[k] = 0.0;
+    rz += b * zk;
+    bb += b * b;
+  }
+  block_sum2(rz, bb, part);
 }
 
 __global__ __launch_bounds__(kCgBlock) void k_cg_spmv(
     int nx, int ny, const double* __restrict__ diag, const double* __restrict__ cE,
     const double* __restrict__ cN, const double* __restrict__ z, double* __restrict__ P,
-    double* __restrict__ q, double* __restrict__ part, const DevState* st) {
-  if (st->si_done) return;
+    double* __restrict__ q, double* __restrict__ part, const IterState* cs, const int* gate) {
+  if ((gate && *gate) || cs->done) return;
   const long long n = (long long)nx * ny;
-  const int it = st->si_iter;
-  const double beta = st->cg_beta;
+  const int it = cs->iter;
+  const double beta = cs->beta;
   double* __restrict__ pk = P + (long long)(it & 1) * n;
   const double* __restrict__ pm = P + (long long)((it + 1) & 1) * n;
   double pq = 0.0;
@@ -202,11 +229,11 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update(
     long long n, const double* __restrict__ diag, const double* __restrict__ P,
     const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
     double* __restrict__ z, const double* __restrict__ part_pq, int n_part,
-    double* __restrict__ part, const DevState* st) {
-  if (st->si_done) return;
+    double* __restrict__ part, const IterState* cs, const int* gate) {
+  if ((gate && *gate) || cs->done) return;
   const double pq = sum_partials(part_pq, n_part, 0);
-  const double alpha = st->cg_rz / pq;
-  const double* __restrict__ pk = P + (long long)(st->si_iter & 1) * n;
+  const double alpha = cs->rz / pq;
+  const double* __restrict__ pk = P + (long long)(cs->iter & 1) * n;
   double rz = 0.0, rr = 0.0;
   for (long long k = (long long)blockIdx.x * kCgBlock + threadIdx.x; k < n;
        k += (long long)gridDim.x * kCgBlock) {
@@ -222,22 +249,23 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update(
 }
 
 __global__ __launch_bounds__(kCgBlock) void k_cg_residual(const double* part, int n_part,
-                                                          DevState* st, double tol, int si_max) {
-  if (st->si_done) return;
+                                                          IterState* cs, const int* gate,
+                                                          double tol, int max_iter) {
+  if ((gate && *gate) || cs->done) return;
   const double rz = sum_partials(part, n_part, 0);
   const double rr = sum_partials(part, n_part, 1);
   if (threadIdx.x == 0) {
-    const double bb = st->cg_bb;
-    st->si_iter += 1;
-    st->si_dn2 = rr;
-    st->si_nrm2 = bb;
+    const double bb = cs->bb;
+    cs->iter += 1;
+    cs->dn2 = rr;
+    cs->nrm2 = bb;
     const int bad = !isfinite(rr) || !isfinite(rz);
     const int conv = !bad && rr <= tol * tol * bb;
-    st->si_bad = bad;
-    st->si_conv = conv;
-    st->si_done = bad || conv || st->si_iter >= si_max;
-    st->cg_beta = st->cg_rz != 0.0 ? rz / st->cg_rz : 0.0;
-    st->cg_rz = rz;
+    cs->bad = bad;
+    cs->conv = conv;
+    cs->done = bad || conv || cs->iter >= max_iter;
+    cs->beta = cs->rz != 0.0 ? rz / cs->rz : 0.0;
+    cs->rz = rz;
   }
 }
 
@@ -257,16 +285,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 __global__ __launch_bounds__(kCgOneBlock) void k_cg_solve_one_block(
     int nx, int ny, const double* __restrict__ diag, const double* __restrict__ cE,
     const double* __restrict__ cN, double* __restrict__ x, double* __restrict__ r,
-    double* __restrict__ z, double* __restrict__ P, double* __restrict__ q, DevState* st,
-    double tol, int si_max) {
-  if (st->si_done) return;
+    double* __restrict__ z, double* __restrict__ P, double* __restrict__ q, IterState* cs,
+    const int* gate, double tol, int max_iter) {
+  if ((gate && *gate) || cs->done) return;
   __shared__ double s_a[kCgOneBlock / 64], s_b[kCgOneBlock / 64];
   const long long n = (long long)nx * ny;
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   constexpr int nw = kCgOneBlock / 64;
-  int it = st->si_iter;
-  double beta = st->cg_beta, rz = st->cg_rz;
-  const double bb = st->cg_bb;
+  int it = cs->iter;
+  double beta = cs->beta, rz = cs->rz;
+  const double bb = cs->bb;
   double rr = 0.0;
   int done = 0, conv = 0, bad = 0;
   while (!done) {
@@ -321,19 +349,19 @@ __global__ __launch_bounds__(kCgOneBlock) void k_cg_solve_one_block(
     rr = rrn;
     bad = !isfinite(rrn) || !isfinite(rzn);
     conv = !bad && rrn <= tol * tol * bb;
-    done = bad || conv || it >= si_max;
+    done = bad || conv || it >= max_iter;
     beta = rz != 0.0 ? rzn / rz : 0.0;
     rz = rzn;
   }
   if (t == 0) {
-    st->si_iter = it;
-    st->si_dn2 = rr;
-    st->si_nrm2 = bb;
-    st->si_bad = bad;
-    st->si_conv = conv;
-    st->si_done = 1;
-    st->cg_beta = beta;
-    st->cg_rz = rz;
+    cs->iter = it;
+    cs->dn2 = rr;
+    cs->nrm2 = bb;
+    cs->bad = bad;
+    cs->conv = conv;
+    cs->done = 1;
+    cs->beta = beta;
+    cs->rz = rz;
   }
 }
 
@@ -348,33 +376,46 @@ __global__ void k_cg_to_nodal(long long n, const double* __restrict__ x,
 }
 
 hipError_t launch_cg_start(const CgArgs& a, const double* sig_s, const double* phi_post,
-                           int si_max, hipStream_t s) {
+                           int max_iter, hipStream_t s) {
   const long long n = (long long)a.nx * a.ny;
   hipLaunchKernelGGL(k_cg_start, dim3(a.n_part), dim3(kCgBlock), 0, s, n, sig_s, phi_post,
                      (const double*)a.diag, a.x, a.r, a.z, a.P + n, a.part_a);
   hipLaunchKernelGGL(k_cg_start_state, dim3(1), dim3(kCgBlock), 0, s, (const double*)a.part_a,
-                     a.n_part, a.st, si_max);
+                     a.n_part, a.cs, a.gate, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_dsa_start(const CgArgs& a, const double* sig_s, const double* dnode,
+                            int max_iter, hipStream_t s) {
+  const long long n = (long long)a.nx * a.ny;
+  hipLaunchKernelGGL(k_dsa_start, dim3(a.n_part), dim3(kCgBlock), 0, s, n, sig_s, dnode,
+                     (const double*)a.diag, a.x, a.r, a.z, a.P + n, a.part_a, a.gate);
+  hipLaunchKernelGGL(k_cg_start_state, dim3(1), dim3(kCgBlock), 0, s, (const double*)a.part_a,
+                     a.n_part, a.cs, a.gate, max_iter);
   return hipGetLastError();
 }
 
 bool cg_one_block(long long n) { return n <= kCgOneBlockMax; }
 
-hipError_t launch_cg_iteration(const CgArgs& a, double tol, int si_max, hipStream_t s) {
+hipError_t launch_cg_solve_one_block(const CgArgs& a, double tol, int max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_solve_one_block, dim3(1), dim3(kCgOneBlock), 0, s, a.nx, a.ny,
+                     (const double*)a.diag, (const double*)a.cE, (const double*)a.cN, a.x, a.r,
+                     a.z, a.P, a.q, a.cs, a.gate, tol, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_iteration(const CgArgs& a, double tol, int max_iter, hipStream_t s) {
   const long long n = (long long)a.nx * a.ny;
-  if (cg_one_block(n)) {  // the whole remaining solve
-    hipLaunchKernelGGL(k_cg_solve_one_block, dim3(1), dim3(kCgOneBlock), 0, s, a.nx, a.ny,
-                       (const double*)a.diag, (const double*)a.cE, (const double*)a.cN, a.x, a.r,
-                       a.z, a.P, a.q, a.st, tol, si_max);
-    return hipGetLastError();
-  }
+  if (cg_one_block(n)) return launch_cg_solve_one_block(a, tol, max_iter, s);  // the whole rest
   hipLaunchKernelGGL(k_cg_spmv, dim3(a.n_part), dim3(kCgBlock), 0, s, a.nx, a.ny,
                      (const double*)a.diag, (const double*)a.cE, (const double*)a.cN,
-                     (const double*)a.z, a.P, a.q, a.part_a, (const DevState*)a.st);
+                     (const double*)a.z, a.P, a.q, a.part_a, (const IterState*)a.cs, a.gate);
   hipLaunchKernelGGL(k_cg_update, dim3(a.n_part), dim3(kCgBlock), 0, s, n,
                      (const double*)a.diag, (const double*)a.P, (const double*)a.q, a.x, a.r,
-                     a.z, (const double*)a.part_a, a.n_part, a.part_b, (const DevState*)a.st);
+                     a.z, (const double*)a.part_a, a.n_part, a.part_b, (const IterState*)a.cs,
+                     a.gate);
   hipLaunchKernelGGL(k_cg_residual, dim3(1), dim3(kCgBlock), 0, s, (const double*)a.part_b,
-                     a.n_part, a.st, tol, si_max);
+                     a.n_part, a.cs, a.gate, tol, max_iter);
   return hipGetLastError();
 }
 

@@ -230,6 +230,19 @@ enum BalField {
 };
 
 // Device-resident state shared by the kernels of one solver.
+// State of an iteration decided on the device.
+struct IterState {
+  int done;     // converged, iteration limit, or non-finite residual
+  int conv;     // converged to the tolerance
+  int iter;     // iterations done in this solve
+  int bad;      // non-finite residual
+  double dn2;   // |phi_new - phi_old|^2 of the last iteration (CG: |r|^2)
+  double nrm2;  // |phi_new|^2, or the whole-flux norm (CG: |b|^2)
+  double rz;    // CG: r . z of the current iterate
+  double beta;  // CG: beta of the next direction update
+  double bb;    // CG: b . b
+};
+
 struct DevState {
   long long n_in;            // census-in bank size
   double maxabs_w;           // max |w| over the census-in bank
@@ -249,19 +262,14 @@ struct DevState {
   unsigned long long killed;    // histories stopped by the segment guard
   unsigned long long bal[2 * B_NFIELDS];
   unsigned long long step;      // time step being computed (point streams, history ids)
-  // source iteration of the collided solve, kept on the device so that a
-  // batch of iterations needs no host round trip: once si_done is set the
-  // remaining iterations of the batch do nothing
-  int si_done;                  // converged, iteration limit, or non-finite residual
-  int si_conv;                  // converged to the tolerance
-  int si_iter;                  // iterations done in this step
-  int si_bad;                   // non-finite residual
-  double si_dn2, si_nrm2;       // |phi_new - phi_old|^2, |phi_new|^2 of the last iteration
-                                // (diffusion closing stage: |r|^2, |b|^2)
-  // conjugate gradients of the diffusion closing stage
-  double cg_rz;                 // r . z of the current iterate
-  double cg_beta;               // beta of the next direction update
-  double cg_bb;                 // b . b
+  // source iteration of the collided solve (or the conjugate gradients of
+  // the diffusion closing stage), kept on the device so that a batch of
+  // iterations needs no host round trip: once si.done is set the remaining
+  // iterations of the batch do nothing
+  IterState si;
+  // conjugate gradients of the diffusion correction inside each source
+  // iteration (diffusion synthetic acceleration)
+  IterState dsa;
 };
 
 struct PassArgs {
@@ -340,6 +348,8 @@ struct DgArgs {
   double* phi_c;         // nodal [cell][4]: the collided iterate, updated in place
   double* src;           // nodal [cell][4] scratch: sigma_s/(4 pi)(phi_c + phi_post)
   double* psi;           // [m][cell][4] (psi_m; the reduction applies w_m)
+  double* dnode;         // nodal phi^{k+1/2} - phi^k for the diffusion correction
+                         // (diffusion synthetic acceleration), or null
   const double* dirmat;  // [m][32]: A0 then F (uniform mesh)
   // table mode: material of each cell and [m][material][32] = B then G
   const int* mat_id;
@@ -357,7 +367,7 @@ struct DgArgs {
   const int* refl_x;
   const int* refl_y;
   double* bnd;
-  DevState* st;          // si_done: skip the iteration; the reduction's decision
+  DevState* st;          // si.done: skip the iteration; the reduction's decision
 };
 hipError_t launch_dg_tables(int n_dir, int n_mat, const double* dir, const double* sig_e_mat,
                             double hx, double hy, double* dirmat, double* coef, hipStream_t s);
@@ -366,6 +376,12 @@ size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny);
 // Start of a step's source iteration: phi_c = 0, iteration state reset, the
 // first iterate's nodal source, reflected traces of the first sweep zeroed.
 hipError_t launch_si_start(const DgArgs& a, int si_max, hipStream_t s);
+// Diffusion synthetic acceleration: after the correction delta (per cell) is
+// solved, phi += delta at every node, the next iterate's source, and the
+// residual of phi^{k+1} - phi^k = dnode + delta, decided as after a plain
+// reduction.
+hipError_t launch_dsa_apply(const DgArgs& a, const double* delta, double* partials, int n_part,
+                            double si_tol, int si_max, hipStream_t s);
 
 // Diffusion closing stage (cell-centred finite volumes, Jacobi-preconditioned
 // conjugate gradients).  Vectors are per cell; P holds two n-vectors (the
@@ -379,15 +395,24 @@ struct CgArgs {
   double *x, *r, *z, *P, *q;
   double *part_a, *part_b;
   int n_part;           // cg_partials(nx * ny)
-  DevState* st;         // the source-iteration state doubles as the CG state
+  IterState* cs;        // the solve's state: st->si for the closing stage,
+                        // st->dsa for the correction of a source iteration
+  const int* gate;      // if not null and set (the source iteration is done),
+                        // every kernel returns at once
 };
 int cg_partials(long long n);
 hipError_t launch_diff_coef(int nx, int ny, const double2* mat, double tt, double hx, double hy,
                             int bc, double* diag, double* cE, double* cN, hipStream_t s);
 // b = sigma_s phi_post, x = 0, and the state of a new solve (done at once when
-// b = 0 or si_max = 0)
+// b = 0 or max_iter = 0)
 hipError_t launch_cg_start(const CgArgs& a, const double* sig_s, const double* phi_post,
-                           int si_max, hipStream_t s);
+                           int max_iter, hipStream_t s);
+// the same for the diffusion correction of a source iteration: b = sigma_s
+// times the cell average of dnode (phi^{k+1/2} - phi^k, four nodes per cell)
+hipError_t launch_dsa_start(const CgArgs& a, const double* sig_s, const double* dnode,
+                            int max_iter, hipStream_t s);
+// the whole (remaining) solve in one workgroup, whatever the mesh size
+hipError_t launch_cg_solve_one_block(const CgArgs& a, double tol, int max_iter, hipStream_t s);
 // one iteration (nothing once the state says done); stops at |r| <= tol |b|.
 // On meshes where cg_one_block holds, one call runs the whole solve.
 bool cg_one_block(long long n);
@@ -396,7 +421,7 @@ hipError_t launch_cg_to_nodal(const CgArgs& a, double* phi_c, hipStream_t s);
 hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s);
 // One reduction of a source iteration: phi_c is replaced in place by the
 // direction sum of the planes, the next iterate's source is formed, and the
-// residual decides st->si_done (n_part blocks, dg_reduce_partials).
+// residual decides st->si.done (n_part blocks, dg_reduce_partials).
 hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, double si_tol,
                             int si_max, hipStream_t s);
 int dg_reduce_partials(long long n_nodes);

@@ -37,7 +37,7 @@ class slh_problem(C.Structure):
                 ("si_max_iter", C.c_int32), ("w_cut_rel", C.c_double), ("seed", C.c_uint64),
                 ("points", C.c_int32), ("precision", C.c_int32), ("n_s_cell", C.c_void_p),
                 ("boundary", C.c_int32), ("steady", C.c_int32), ("horizon", C.c_double),
-                ("si_norm", C.c_int32), ("closure", C.c_int32)]
+                ("si_norm", C.c_int32), ("closure", C.c_int32), ("si_accel", C.c_int32)]
 
 
 class slh_balance(C.Structure):
@@ -180,6 +180,7 @@ def make_problem(p: dict):
     s.horizon = float(p.get("horizon", 0.0))
     s.si_norm = int(p.get("si_norm", 0))
     s.closure = int(p.get("closure", 0))
+    s.si_accel = int(p.get("si_accel", 0))
     keep = [ss, sa, q]
     if p.get("n_s_cell") is not None:
         nsc = np.ascontiguousarray(p["n_s_cell"], dtype=np.int32).reshape(-1)

@@ -49,7 +49,10 @@ def test_validation_rejects_before_allocating(S):
         dict(steady=True, horizon=np.inf), dict(steady=True, horizon=1e16),
         dict(steady=True, w_cut_rel=0.0),  # the default horizon needs a cutoff
         dict(steady=True, sigma_a=np.where(np.arange(400) == 7, 0.0, 0.1)),
-        dict(closure=2), dict(closure=-1),
+        dict(closure=2), dict(closure=-1), dict(si_accel=2), dict(si_accel=-1),
+        # the diffusion correction needs sigma_t > 0 in steady state (a void)
+        dict(si_accel=1, steady=True, horizon=50.0, sigma_a=np.where(np.arange(400) == 7, 0.0, 0.1),
+             sigma_s=np.where(np.arange(400) == 7, 0.0, 1.0)),
         # the diffusion closure needs sigma_t > 0 in steady state (a void)
         dict(closure=1, steady=True, horizon=50.0, sigma_a=np.where(np.arange(400) == 7, 0.0, 0.1),
              sigma_s=np.where(np.arange(400) == 7, 0.0, 1.0)),

@@ -141,3 +141,43 @@ def test_reflective_side_is_a_symmetry_plane(oracle, axis):
         want = phi_f[:n // 2]
         phi_h = phi_h.reshape(n // 2, n, 4)
     assert np.linalg.norm(phi_h - want) <= 1e-11 * np.linalg.norm(want)
+
+
+def _dsa_cases():
+    from paper_2511_16821_amd import workloads as W
+    return [("duct", W.duct(n_s=0, n_particles=6000)),
+            ("closed box", W.c1(n_s=0, steady=True, n_particles=6000, boundary=15)),
+            ("quarter box", W.c1(n_s=1, steady=True, n_particles=6000, boundary=5)),
+            ("checkerboard", W.checkerboard(blocks=5, cells_per_block=4, n_s=1,
+                                            n_particles=8000, dt=0.05, sn_order=6))]
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_dsa_reaches_the_source_iteration_fixed_point(oracle, case):
+    """Diffusion synthetic acceleration changes the iteration, not its fixed
+    point: at a tight tolerance both give the same collided flux, and the
+    accelerated one needs fewer sweeps (vacuum or reflective sides)."""
+    name, p = _dsa_cases()[case]
+    p = dict(p, si_tol=1e-13, si_max_iter=1000)
+    a = oracle.HybridOracle(p).step()
+    b = oracle.HybridOracle(dict(p, si_accel=1)).step()
+    assert np.array_equal(a["phi_post"], b["phi_post"])
+    err = np.linalg.norm(b["phi_c"] - a["phi_c"]) / np.linalg.norm(a["phi_c"])
+    assert err <= 1e-10, (name, err)
+    assert b["si_iters"] < a["si_iters"], (name, a["si_iters"], b["si_iters"])
+
+
+def test_dsa_closed_box_closed_form(oracle):
+    """In a closed homogeneous box with a uniform collided source the
+    accelerated iteration still converges to sigma_s phi_post / sigma_a."""
+    from paper_2511_16821_amd import workloads as W
+    n, ss, sa = 6, 0.9, 0.1
+    p = W.homogeneous_box(n=n, L=3.0, sig_s=ss, sig_a=sa, src_cells=((0, n), (0, n)), n_s=0,
+                          n_particles=1, sn_order=4, steady=True, boundary=15)
+    m = oracle.Mesh(p)
+    phi_post = np.full(n * n, 2.0)
+    phi, it, res = oracle.dg_collided_dsa(m, oracle.quadrature(4), phi_post, tol=1e-13,
+                                          max_iter=2000)
+    assert np.allclose(phi, ss * 2.0 / sa, rtol=1e-10, atol=0)
+    _, it0, _ = oracle.dg_collided(m, oracle.quadrature(4), phi_post, tol=1e-13, max_iter=2000)
+    assert it < it0

@@ -497,20 +497,22 @@ def steady_protocol(S, torch, args):
 
 
 def closure_cmp(S, torch, args):
-    """The two closing stages on the benchmark workload (checkerboard 140x140,
-    1e6 particles per pass): DG S_N source iteration against the cell-centred
-    diffusion solve (conjugate gradients), for several N_s: time per step,
-    iterations of the last step, the collided stage's share of the step, and
-    the relative L2 distance of the final phi_R between the two (the modelling
-    difference of the closures, not a parity figure)."""
+    """The closing stages on the benchmark workload (checkerboard 140x140, 1e6
+    particles per pass): DG S_N source iteration, the same with diffusion
+    synthetic acceleration, and the cell-centred diffusion solve (conjugate
+    gradients), for several N_s: time per step, iterations of the last step,
+    the collided stage's share of the step, and the relative L2 distance of
+    the final phi_R from the plain S_N run (for the diffusion stage the
+    modelling difference of the closures, not a parity figure); then plain
+    and accelerated S_N on two scattering-dominated steady problems."""
     import numpy as np
     from paper_2511_16821_amd import workloads as W
     rows = []
     for ns in [int(v) for v in args.closure_ns.split(",") if v != ""]:
         row = {"n_s": ns}
         flux = {}
-        for name, cl in (("sn", 0), ("diffusion", 1)):
-            p = W.c2(n_s=ns, closure=cl)
+        for name, cl, acc in (("sn", 0, 0), ("sn_dsa", 0, 1), ("diffusion", 1, 0)):
+            p = W.c2(n_s=ns, closure=cl, si_accel=acc)
             wall, st = timed_run(S, torch, p, args.closure_steps, 1)
             s = S.Solver(p)
             s.advance(args.closure_steps, allow_not_converged=True)
@@ -521,10 +523,24 @@ def closure_cmp(S, torch, args):
                          "ms_collided_last_step": float(st["ms_dg"])}
         row["rel_l2_diffusion_vs_sn"] = float(np.linalg.norm(flux["diffusion"] - flux["sn"]) /
                                               np.linalg.norm(flux["sn"]))
+        row["rel_l2_sn_dsa_vs_sn"] = float(np.linalg.norm(flux["sn_dsa"] - flux["sn"]) /
+                                           np.linalg.norm(flux["sn"]))
         log("closures:", json.dumps(row))
         rows.append(row)
+    # scattering-dominated steady problems, where the acceleration matters
+    steady = []
+    for tag, p in (("duct N_s=0", W.duct(n_s=0, n_particles=65536)),
+                   ("closed box N_s=0 (C1 box, all sides reflective)",
+                    W.c1(n_s=0, steady=True, n_particles=65536, boundary=15, si_max_iter=2000))):
+        row = {"problem": tag}
+        for name, acc in (("sn", 0), ("sn_dsa", 1)):
+            q = dict(p, si_accel=acc)
+            wall, st = timed_run(S, torch, q, 1, 1)
+            row[name] = {"ms_per_solve": 1e3 * wall, "sweeps": int(st["si_iterations"])}
+        log("closures:", json.dumps(row))
+        steady.append(row)
     return {"workload": "checkerboard 140x140, 1e6 particles/pass, dt=0.05, S_12, %d steps"
-                        % args.closure_steps, "rows": rows}
+                        % args.closure_steps, "rows": rows, "steady": steady}
 
 
 def serve_bench(S, torch, args):

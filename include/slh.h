@@ -183,7 +183,7 @@ typedef struct {
                                    /* since reflected inflow lags) for the     */
                                    /* source sigma_s times the cell average of */
                                    /* the sweep's change,                      */
-                                   /* solved by conjugate gradients to 1e-6    */
+                                   /* solved by conjugate gradients to 1e-2    */
                                    /* relative residual (at most 500 steps) in */
                                    /* one workgroup.  Same fixed point, fewer  */
                                    /* sweeps when scattering dominates.  Needs */

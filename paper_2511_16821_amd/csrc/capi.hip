@@ -846,7 +846,7 @@ static CgArgs cg_args(slh_solver* s) {
 
 // Diffusion correction of a source iteration: tolerance and iteration limit
 // of its conjugate gradients.
-constexpr double kDsaTol = 1e-6;
+constexpr double kDsaTol = 1e-2;
 constexpr int kDsaMaxIter = 500;
 
 // the collided solve proper: the diffusion closing stage unless the step

@@ -326,7 +326,7 @@ static Sizes sizes_of(const slh_problem* p) {
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
   b += (size_t)z.cap * bank * 2;             // census banks
   b += (size_t)(z.n_src_cap > 0 ? z.n_src_cap : 1) * (7 * rb + 8);  // source bank
-  b += (size_t)z.n_cand * (bank + 1 + 8 + 8);  // staging, alive, flags, inclusive scan
+  b += (size_t)z.n_cand * ((z.fp32 ? 32 : 64) + 1 + 8 + 8);  // staging, alive, flags, scan
   b += scan_tmp_elems(z.n_cand) * 8;
   b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8 + kCensusBlocks * 8;
   b += 64 * 1024;  // alignment of the ~30 device buffers
@@ -602,7 +602,8 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->dirs, double, 3 * z.n_dir);
   s->bank_mem[0] = s->dalloc(s->bank_bytes(z.cap));
   s->bank_mem[1] = s->dalloc(s->bank_bytes(z.cap));
-  s->stage_mem = s->dalloc(s->bank_bytes(z.n_cand));
+  s->stage_mem = s->dalloc((size_t)z.n_cand * (z.fp32 ? sizeof(StageRec<float>)
+                                                     : sizeof(StageRec<double>)));
   s->src_mem = s->dalloc(s->src_bytes(z.n_src_cap));
   if (!s->bank_mem[0] || !s->bank_mem[1] || !s->stage_mem || !s->src_mem)
     return fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: census banks");
@@ -732,11 +733,11 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   void* bin = s->bank_mem[s->cur];
   if (s->z.fp32) {
     a.in32 = s->bank_at<float>(bin, s->z.cap);
-    a.out32 = s->bank_at<float>(s->stage_mem, s->z.n_cand);
+    a.out32 = (StageRec<float>*)s->stage_mem;
     a.src32 = s->src_at<float>(s->src_mem, s->z.n_src_cap);
   } else {
     a.in64 = s->bank_at<double>(bin, s->z.cap);
-    a.out64 = s->bank_at<double>(s->stage_mem, s->z.n_cand);
+    a.out64 = (StageRec<double>*)s->stage_mem;
     a.src64 = s->src_at<double>(s->src_mem, s->z.n_src_cap);
   }
   a.alive = s->alive;
@@ -936,14 +937,14 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
       void* nb = s->bank_mem[1 - s->cur];
       HIP_TRY(launch_thin_params(s->st, z.cap, s->thin_margin, st));
       if (z.fp32) {
-        Bank<float> src = s->bank_at<float>(s->stage_mem, z.n_cand);
-        HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, p.seed, s->st, s->flags, st));
+        const StageRec<float>* src = (const StageRec<float>*)s->stage_mem;
+        HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
         HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
         HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, z.cap,
                                              s->bank_at<float>(nb, z.cap), s->st, s->cmax, st));
       } else {
-        Bank<double> src = s->bank_at<double>(s->stage_mem, z.n_cand);
-        HIP_TRY(launch_census_flags(s->alive, src.hid, z.n_cand, p.seed, s->st, s->flags, st));
+        const StageRec<double>* src = (const StageRec<double>*)s->stage_mem;
+        HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
         HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
         HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand, z.cap,
                                               s->bank_at<double>(nb, z.cap), s->st, s->cmax,

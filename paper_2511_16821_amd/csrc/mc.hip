@@ -39,7 +39,16 @@ template <> struct Real<double> {
   static __device__ __forceinline__ double2 mat(const PassArgs& a, int c) { return a.mat64[c]; }
   static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
   static __device__ __forceinline__ const Bank<double>& in(const PassArgs& a) { return a.in64; }
-  static __device__ __forceinline__ const Bank<double>& out(const PassArgs& a) { return a.out64; }
+  static __device__ __forceinline__ StageRec<double>* out(const PassArgs& a) { return a.out64; }
+  static __device__ __forceinline__ void stage(StageRec<double>* p, double px, double py,
+                                               double ox, double oy, double w, uint64_t hid,
+                                               int cell) {
+    double2* o = reinterpret_cast<double2*>(p);
+    o[0] = make_double2(px, py);
+    o[1] = make_double2(ox, oy);
+    o[2] = make_double2(w, __longlong_as_double((long long)hid));
+    o[3] = make_double2(__longlong_as_double((long long)(unsigned)cell), 0.0);
+  }
 };
 template <> struct Real<float> {
   using V2 = float2;
@@ -55,7 +64,14 @@ template <> struct Real<float> {
   static __device__ __forceinline__ float2 mat(const PassArgs& a, int c) { return a.mat32[c]; }
   static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
   static __device__ __forceinline__ const Bank<float>& in(const PassArgs& a) { return a.in32; }
-  static __device__ __forceinline__ const Bank<float>& out(const PassArgs& a) { return a.out32; }
+  static __device__ __forceinline__ StageRec<float>* out(const PassArgs& a) { return a.out32; }
+  static __device__ __forceinline__ void stage(StageRec<float>* p, float px, float py, float ox,
+                                               float oy, float w, uint64_t hid, int cell) {
+    float4* o = reinterpret_cast<float4*>(p);
+    o[0] = make_float4(px, py, ox, oy);
+    o[1] = make_float4(w, __int_as_float(cell), __uint_as_float((unsigned)hid),
+                       __uint_as_float((unsigned)(hid >> 32)));
+  }
 };
 
 enum { EV_CENSUS = 0, EV_COLLIDE = 1, EV_XFACE = 2, EV_YFACE = 3 };
@@ -205,7 +221,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt, c = (R)a.c;
   const R INF = Real<R>::inf();
   const Bank<R> bin = Real<R>::in(a);
-  const Bank<R> bout = Real<R>::out(a);
+  StageRec<R>* const bout = Real<R>::out(a);
   const int n_lim = a.n_lim;
 
   bool have = false;
@@ -386,8 +402,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (end != END_NONE) {
       if (KIND == 2 && end == END_CENSUS && a.keep_census) {
         const long long slot = from_census ? g : a.out_src_base + (g - n_in);
-        bout.px[slot] = px; bout.py[slot] = py; bout.ox[slot] = ox; bout.oy[slot] = oy;
-        bout.w[slot] = w; bout.cell[slot] = iy * a.nx + ix; bout.hid[slot] = hid;
+        Real<R>::stage(bout + slot, px, py, ox, oy, w, hid, iy * a.nx + ix);
         a.alive[slot] = 1;
         lane_alive++;
       }

@@ -207,6 +207,27 @@ template <typename R> struct Bank {
   uint64_t* hid;
 };
 
+// Census-out staging record of one particle (written by the remap pass when
+// a history reaches the end of the step, read by the census compaction):
+// 64 B in FP64, 32 B in FP32, written as whole 16-byte words, so that a
+// particle's state reaches memory as one piece of a cache line rather than
+// seven scattered partial lines.  Layout (FP64): px py | ox oy | w hid |
+// cell (low 4 bytes) and padding; (FP32): px py ox oy | w cell hid.
+template <typename R> struct StageRec;
+template <> struct alignas(64) StageRec<double> {
+  double px, py, ox, oy, w;
+  uint64_t hid;
+  int32_t cell, pad0;
+  int64_t pad1;
+};
+template <> struct alignas(32) StageRec<float> {
+  float px, py, ox, oy, w;
+  int32_t cell;
+  uint64_t hid;
+};
+static_assert(sizeof(StageRec<double>) == 64 && sizeof(StageRec<float>) == 32,
+              "staging record sizes");
+
 // Source particles of one pass, written by the emission kernel: position in
 // the cell, direction, weight, birth time within the step, first optical
 // depth (scatter-limited pass with N_s > 0 only), cell and index within the
@@ -302,8 +323,10 @@ struct PassArgs {
   unsigned int max_segments;
   // census: input bank and output slots (census index, or out_src_base +
   // source index), in the precision of the pass
-  Bank<double> in64, out64;
-  Bank<float> in32, out32;
+  Bank<double> in64;
+  Bank<float> in32;
+  StageRec<double>* out64;
+  StageRec<float>* out32;
   SrcBank<double> src64;
   SrcBank<float> src32;
   uint8_t* alive;
@@ -455,11 +478,12 @@ size_t scan_tmp_elems(long long n);
 hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
                               long long* tmp, hipStream_t s);
 hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hipStream_t s);
-hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long long n,
+template <typename R>
+hipError_t launch_census_flags(const uint8_t* alive, const StageRec<R>* stage, long long n,
                                uint64_t seed, const DevState* st, long long* flags,
                                hipStream_t s);
 template <typename R>
-hipError_t launch_census_compact(const Bank<R>& src, const long long* incl, long long n,
+hipError_t launch_census_compact(const StageRec<R>* src, const long long* incl, long long n,
                                  long long cap, Bank<R> dst, DevState* st, double* bmax,
                                  hipStream_t s);
 // bmax: kCensusBlocks doubles, the compaction's per-block max |w|

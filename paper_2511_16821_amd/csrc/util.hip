@@ -374,8 +374,9 @@ hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hip
   return hipGetLastError();
 }
 
+template <typename R>
 __global__ void k_census_flags(const uint8_t* __restrict__ alive,
-                               const uint64_t* __restrict__ hid, long long n,
+                               const StageRec<R>* __restrict__ stage, long long n,
                                uint64_t seed, const DevState* st,
                                long long* __restrict__ flags) {
   // the thinning keys' stream: (step, pass 2, population 2)
@@ -387,7 +388,7 @@ __global__ void k_census_flags(const uint8_t* __restrict__ alive,
        i += (long long)gridDim.x * blockDim.x) {
     long long f = alive[i] ? 1 : 0;
     if (f && act) {
-      const unsigned long long key = mix64(thin_stream ^ hid[i]);
+      const unsigned long long key = mix64(thin_stream ^ stage[i].hid);
       const unsigned long long top = rs >= 64 ? 0ull : (key >> rs);
       f = top < mant ? 1 : 0;
     }
@@ -395,15 +396,22 @@ __global__ void k_census_flags(const uint8_t* __restrict__ alive,
   }
 }
 
-hipError_t launch_census_flags(const uint8_t* alive, const uint64_t* hid, long long n,
+template <typename R>
+hipError_t launch_census_flags(const uint8_t* alive, const StageRec<R>* stage, long long n,
                                uint64_t seed, const DevState* st, long long* flags,
                                hipStream_t s) {
   long long b = (n + 255) / 256;
   const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_census_flags, dim3(grid), dim3(256), 0, s, alive, hid, n, seed, st,
+  hipLaunchKernelGGL(k_census_flags<R>, dim3(grid), dim3(256), 0, s, alive, stage, n, seed, st,
                      flags);
   return hipGetLastError();
 }
+template hipError_t launch_census_flags<double>(const uint8_t*, const StageRec<double>*,
+                                                long long, uint64_t, const DevState*,
+                                                long long*, hipStream_t);
+template hipError_t launch_census_flags<float>(const uint8_t*, const StageRec<float>*, long long,
+                                               uint64_t, const DevState*, long long*,
+                                               hipStream_t);
 
 
 // Blocks of the compaction grid; each leaves the max |w| it wrote in bmax.
@@ -413,7 +421,7 @@ int census_compact_blocks(long long n) {
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_census_compact(Bank<R> src,
+__global__ __launch_bounds__(256) void k_census_compact(const StageRec<R>* __restrict__ src,
                                                         const long long* __restrict__ incl,
                                                         long long n, long long cap, Bank<R> dst,
                                                         const DevState* st,
@@ -427,14 +435,15 @@ __global__ __launch_bounds__(256) void k_census_compact(Bank<R> src,
     if (incl[i] == before) continue;
     const long long d = before;
     if (d >= cap) continue;  // overflow of the draw: keep the first cap
-    dst.px[d] = src.px[i];
-    dst.py[d] = src.py[i];
-    dst.ox[d] = src.ox[i];
-    dst.oy[d] = src.oy[i];
-    const R w = src.w[i] * f;
+    const StageRec<R> rec = src[i];
+    dst.px[d] = rec.px;
+    dst.py[d] = rec.py;
+    dst.ox[d] = rec.ox;
+    dst.oy[d] = rec.oy;
+    const R w = rec.w * f;
     dst.w[d] = w;
-    dst.cell[d] = src.cell[i];
-    dst.hid[d] = src.hid[i];
+    dst.cell[d] = rec.cell;
+    dst.hid[d] = rec.hid;
     mx = fmax(mx, fabs((double)w));
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
@@ -446,17 +455,17 @@ __global__ __launch_bounds__(256) void k_census_compact(Bank<R> src,
 }
 
 template <typename R>
-hipError_t launch_census_compact(const Bank<R>& src, const long long* incl, long long n,
+hipError_t launch_census_compact(const StageRec<R>* src, const long long* incl, long long n,
                                  long long cap, Bank<R> dst, DevState* st, double* bmax,
                                  hipStream_t s) {
   hipLaunchKernelGGL(k_census_compact<R>, dim3(census_compact_blocks(n)), dim3(256), 0, s, src,
                      incl, n, cap, dst, (const DevState*)st, bmax);
   return hipGetLastError();
 }
-template hipError_t launch_census_compact<double>(const Bank<double>&, const long long*,
+template hipError_t launch_census_compact<double>(const StageRec<double>*, const long long*,
                                                   long long, long long, Bank<double>,
                                                   DevState*, double*, hipStream_t);
-template hipError_t launch_census_compact<float>(const Bank<float>&, const long long*,
+template hipError_t launch_census_compact<float>(const StageRec<float>*, const long long*,
                                                  long long, long long, Bank<float>, DevState*,
                                                  double*, hipStream_t);
 

@@ -21,6 +21,10 @@ SLH_OK, SLH_E_INVALID_ARG, SLH_E_OUT_OF_MEMORY, SLH_E_DEVICE, SLH_E_NOT_CONVERGE
     SLH_E_NUMERIC, SLH_E_REJECTED, SLH_E_STATE = range(8)
 SLH_FP64, SLH_FP32_TRACK = 0, 1
 SLH_SOBOL_OWEN, SLH_PRNG, SLH_HALTON = 0, 1, 2
+SLH_REFLECT_X_LO, SLH_REFLECT_X_HI, SLH_REFLECT_Y_LO, SLH_REFLECT_Y_HI = 1, 2, 4, 8
+SLH_SI_NORM_COLLIDED, SLH_SI_NORM_TOTAL = 0, 1
+SLH_CLOSE_SN, SLH_CLOSE_DIFFUSION = 0, 1
+SLH_ACCEL_NONE, SLH_ACCEL_DSA = 0, 1
 SLH_FLUX_REMAP, SLH_FLUX_PRE, SLH_FLUX_POST, SLH_FLUX_COLLIDED_NODAL = range(4)
 
 STATUS_NAMES = ["SLH_OK", "SLH_E_INVALID_ARG", "SLH_E_OUT_OF_MEMORY", "SLH_E_DEVICE",

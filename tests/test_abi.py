@@ -104,3 +104,22 @@ def test_null_arguments(S):
     L.slh_destroy(None)
     assert L.slh_create(None, None, S.ALLOC_FN(0), S.FREE_FN(0), None,
                         C.byref(C.c_void_p())) == S.SLH_E_INVALID_ARG
+
+
+def test_binding_matches_the_header(S):
+    """The binding's constants and slh_problem field order are those the
+    header declares (the ctypes struct mirrors the C layout field by field)."""
+    txt = open(os.path.join(ROOT, "include", "slh.h")).read()
+    for name, val in re.findall(r"#define (SLH_[A-Z0-9_]+) (\d+)u?\b", txt):
+        if hasattr(S, name):
+            assert getattr(S, name) == int(val), name
+    for name in ("SLH_ABI_VERSION", "SLH_REFLECT_Y_HI", "SLH_SI_NORM_TOTAL", "SLH_CLOSE_DIFFUSION",
+                 "SLH_ACCEL_DSA"):
+        assert hasattr(S, name), name
+    body = txt[txt.index("typedef struct {\n    uint32_t abi_version;"):txt.index("} slh_problem;")]
+    fields = []
+    for line in body.split("\n"):
+        m = re.match(r"\s+(?:const\s+)?[a-z0-9_]+\s*\*?\s*([a-z_0-9, ]+);", line)
+        if m:
+            fields += [f.strip().lstrip("*") for f in m.group(1).split(",")]
+    assert fields == [f for f, _ in S.slh_problem._fields_], fields

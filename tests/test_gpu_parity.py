@@ -75,6 +75,16 @@ def test_c1_full_ten_steps(S, oracle):
     _run_pair(S, oracle, W.c1(), 10)
 
 
+def test_c2_full_size(S, oracle):
+    """The benchmark workload at its full size (checkerboard 140x140, N_s = 2,
+    1e6 particles per pass, dt = 0.05, S_12), run by the device exactly as the
+    benchmark runs it (step graphs, persistent tracking grids): two steps, the
+    second tracking the census of the first (about 1e6 particles), against
+    the oracle (about 30 s of oracle time)."""
+    from paper_2511_16821_amd import workloads as W
+    _run_pair(S, oracle, W.c2(n_s=2), 2)
+
+
 def test_halton_points_full_steps(S, oracle):
     """The paper's point set (shifted Halton) through whole steps: C1 box with
     N_s = 1 and a checkerboard with N_s = 2, against the oracle."""

@@ -181,3 +181,52 @@ def test_dsa_closed_box_closed_form(oracle):
     assert np.allclose(phi, ss * 2.0 / sa, rtol=1e-10, atol=0)
     _, it0, _ = oracle.dg_collided(m, oracle.quadrature(4), phi_post, tol=1e-13, max_iter=2000)
     assert it < it0
+
+
+def test_dsa_reduction_factor_matches_fourier_analysis(oracle):
+    """In a thick, scattering-dominated medium of optically thin cells, the
+    error of diffusion-synthetic-accelerated source iteration falls per sweep
+    by about 0.2247 c, the Fourier-analysis factor of DSA in an infinite
+    medium (Alcouffe 1977; Larsen 1982), where plain source iteration
+    approaches c.  Here c = 0.99, sigma_t h = 0.25."""
+    from paper_2511_16821_amd import workloads as W
+    n = 24
+    p = W.homogeneous_box(n=n, L=1.2, sig_s=4.95, sig_a=0.05, src_cells=((8, 16), (8, 16)),
+                          n_s=0, n_particles=1, sn_order=4, steady=True)
+    m = oracle.Mesh(p)
+    phi_post = np.zeros(n * n)
+    phi_post.reshape(n, n)[8:16, 8:16] = 1.0
+
+    def ratios(solve):
+        r = [solve(m, oracle.quadrature(4), phi_post, tol=1e-300, max_iter=k)[2]
+             for k in range(1, 12)]
+        return np.array(r[1:]) / np.array(r[:-1])
+
+    si, dsa = ratios(oracle.dg_collided), ratios(oracle.dg_collided_dsa)
+    assert si[-1] > 0.8
+    assert np.all(dsa[3:] > 0.15) and np.all(dsa[3:] < 0.25), dsa
+
+
+@pytest.mark.parametrize("n_s", [0, 5])
+def test_whole_flux_stopping_rule(oracle, n_s):
+    """The whole-flux test stops at the first sweep whose change is within
+    tol of the nodal norm of phi_c + phi_pre + phi_post, recomputed here from
+    the iterates (N_s = 0: the uncollided part is all post-limit; 5: mostly
+    pre-limit)."""
+    from paper_2511_16821_amd import workloads as W
+    tol = 1e-6
+    p = W.duct(n_s=n_s, n_particles=8000)
+    r = oracle.HybridOracle(p).step()
+    m, quad = oracle.Mesh(p), oracle.quadrature(4)
+    pre, post = r["phi_pre"], r["phi_post"]
+    it = oracle.dg_collided(m, quad, post, 2.0, tol, 1000, phi_pre=pre)[1]
+
+    def iterate(k):
+        return oracle.dg_collided(m, quad, post, 2.0, 0.0, k, phi_pre=pre)[0]
+
+    def rule(k):
+        a, b = iterate(k), iterate(k - 1)
+        ref = a + (pre + post)[:, None]
+        return np.linalg.norm(a - b) <= tol * np.linalg.norm(ref)
+
+    assert it >= 3 and rule(it) and not rule(it - 1)

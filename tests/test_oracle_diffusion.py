@@ -125,3 +125,27 @@ def test_cg_reaches_the_direct_solve(oracle, steady):
         assert it1 == it - 1 and res1 > tol
     z, it0, _ = oracle.diffusion_collided(m, np.zeros(nx * ny))
     assert it0 == 0 and np.all(z == 0.0)
+
+
+def test_two_material_slab_is_exact(oracle):
+    """Without removal and with the only source in the first cell, the current
+    J = S h is the same through every face, and the continuous solution is
+    piecewise linear: phi(x) = 2 J (Marshak) + J times the integral of 1/D
+    from x to the vacuum side.  The harmonic-mean faces and the Marshak side
+    make the finite-volume solution equal it at every cell centre."""
+    nx, L = 10, 2.0
+    h = L / nx
+    ss_row = np.where((np.arange(nx) + 0.5) * h < 1.0, 1.0, 3.0)
+    m, _ = _mesh(oracle, nx, 1, L, 1.0, ss_row.reshape(1, nx), np.zeros((1, nx)), steady=True,
+                 horizon=100.0, boundary=1 | 4 | 8)
+    S = 2.0
+    phi_post = np.zeros(nx)
+    phi_post[0] = S / ss_row[0]
+    phi = oracle.diffusion_exact(m, phi_post)
+    J = S * h
+    D = 1.0 / (3.0 * ss_row)
+    want = np.empty(nx)
+    for i in range(nx):
+        # from the centre of cell i to the vacuum side: half of cell i, then whole cells
+        want[i] = 2.0 * J + J * (0.5 * h / D[i] + sum(h / D[k] for k in range(i + 1, nx)))
+    assert np.allclose(phi, want, rtol=1e-12, atol=0), (phi, want)

@@ -185,8 +185,10 @@ typedef struct {
                                    /* the sweep's change,                      */
                                    /* solved by conjugate gradients to 1e-2    */
                                    /* relative residual (at most 500 steps) in */
-                                   /* one workgroup.  Same fixed point, fewer  */
-                                   /* sweeps when scattering dominates.  Needs */
+                                   /* one workgroup, which suits meshes of a   */
+                                   /* few thousand cells (larger ones are      */
+                                   /* slow).  Same fixed point, fewer sweeps   */
+                                   /* when scattering dominates.  Needs        */
                                    /* sigma_t + tau/(c dt) > 0 in every cell.  */
 } slh_problem;
 

@@ -673,7 +673,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no inter-GPU sharding); "
+        print("bench.py runs on one GPU only (the library has no inter-GPU sharding); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -539,8 +539,16 @@ def closure_cmp(S, torch, args):
             row[name] = {"ms_per_solve": 1e3 * wall, "sweeps": int(st["si_iterations"])}
         log("closures:", json.dumps(row))
         steady.append(row)
+    large = None
+    if args.closures_c5:
+        # the large random-block solve, where the sweeps are expensive
+        large = {"workload": "random blocks 1024x1024, 1e8 particles/pass, S_16, 5 steps"}
+        for name, acc in (("sn", 0), ("sn_dsa", 1)):
+            wall, st = timed_run(S, torch, W.c5(si_accel=acc), 5, 1)
+            large[name] = {"ms_per_step": 1e3 * wall / 5, "sweeps_last_step": int(st["si_iterations"])}
+        log("closures:", json.dumps(large))
     return {"workload": "checkerboard 140x140, 1e6 particles/pass, dt=0.05, S_12, %d steps"
-                        % args.closure_steps, "rows": rows, "steady": steady}
+                        % args.closure_steps, "rows": rows, "steady": steady, "large": large}
 
 
 def serve_bench(S, torch, args):
@@ -646,6 +654,8 @@ def main():
                     help="DG S_N against the diffusion closing stage on the benchmark workload")
     ap.add_argument("--closure-ns", default="0,1,2,4")
     ap.add_argument("--closure-steps", type=int, default=20)
+    ap.add_argument("--closures-c5", action="store_true",
+                    help="with --closures: also S_N with and without DSA on the 1024x1024 solve")
     ap.add_argument("--reflect", action="store_true",
                     help="reflective sides on the C1 box against vacuum")
     ap.add_argument("--reflect-steps", type=int, default=10)

@@ -184,11 +184,9 @@ typedef struct {
                                    /* source sigma_s times the cell average of */
                                    /* the sweep's change,                      */
                                    /* solved by conjugate gradients to 1e-2    */
-                                   /* relative residual (at most 500 steps) in */
-                                   /* one workgroup, which suits meshes of a   */
-                                   /* few thousand cells (larger ones are      */
-                                   /* slow).  Same fixed point, fewer sweeps   */
-                                   /* when scattering dominates.  Needs        */
+                                   /* relative residual (at most 32 steps).    */
+                                   /* Same fixed point, fewer sweeps when      */
+                                   /* scattering dominates.  Needs             */
                                    /* sigma_t + tau/(c dt) > 0 in every cell.  */
 } slh_problem;
 

@@ -512,7 +512,7 @@ def _pcg(A, b, tol, max_iter):
     return x, it, (math.sqrt(rr / bb) if bb > 0.0 else 0.0)
 
 
-DSA_TOL, DSA_MAX_ITER = 1e-2, 500
+DSA_TOL, DSA_MAX_ITER = 1e-2, 32
 
 
 def dg_collided_dsa(mesh: Mesh, quad, phi_post, tau=2.0, tol=1e-12, max_iter=200,

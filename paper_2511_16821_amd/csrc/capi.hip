@@ -846,9 +846,11 @@ static CgArgs cg_args(slh_solver* s) {
 }
 
 // Diffusion correction of a source iteration: tolerance and iteration limit
-// of its conjugate gradients.
+// of its conjugate gradients.  A loose solve is enough for the correction
+// (its fixed point is the plain iteration's), and the fixed limit lets a
+// batch of source iterations launch each correction's iterations blindly.
 constexpr double kDsaTol = 1e-2;
-constexpr int kDsaMaxIter = 500;
+constexpr int kDsaMaxIter = 32;
 
 // the collided solve proper: the diffusion closing stage unless the step
 // has no collided solve at all
@@ -866,7 +868,12 @@ static slh_status enqueue_si(slh_solver* s, hipStream_t st, int n_it) {
       HIP_TRY(launch_dg_sweep(d, z.dg_table, st));
       HIP_TRY(launch_dg_reduce(d, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
       HIP_TRY(launch_dsa_start(c, s->sig_s, s->dnode, kDsaMaxIter, st));
-      HIP_TRY(launch_cg_solve_one_block(c, kDsaTol, kDsaMaxIter, st));
+      if (cg_one_block(z.n_cells)) {
+        HIP_TRY(launch_cg_solve_one_block(c, kDsaTol, kDsaMaxIter, st));
+      } else {  // iterations past convergence return at once
+        for (int k = 0; k < kDsaMaxIter; ++k)
+          HIP_TRY(launch_cg_iteration(c, kDsaTol, kDsaMaxIter, st));
+      }
       HIP_TRY(launch_dsa_apply(d, s->cg_x, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
     }
   } else {

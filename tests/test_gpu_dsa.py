@@ -60,6 +60,14 @@ def test_dsa_time_steps(S, oracle):
     _run_pair(S, oracle, q, 2, "quarter box")
 
 
+def test_dsa_large_mesh(S, oracle):
+    """Above 4096 cells each correction runs as a fixed number of predicated
+    three-kernel CG steps: the random-block subproblem (128 x 128, 1024
+    materials, N_s = 3), two steps."""
+    from paper_2511_16821_amd import workloads as W
+    _run_pair(S, oracle, W.c5_subproblem(n_particles=20000, sn_order=8), 2, "random blocks")
+
+
 def test_dsa_fp32(S, oracle):
     from paper_2511_16821_amd import workloads as W
     p = dict(W.duct(n_s=0, n_particles=12000), si_accel=1)

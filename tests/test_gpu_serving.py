@@ -1,7 +1,7 @@
 """Serving (continuous batching on one GPU): every request's result is the
 same alone and in the mix (bitwise: all sums are order-independent fixed
-point), across time-dependent and steady requests, both closing stages, both
-precisions and per-cell scatter limits; admission never exceeds the HBM
+point), across time-dependent and steady requests, both closing stages, with
+and without DSA, both precisions and per-cell scatter limits; admission never exceeds the HBM
 budget, and requests that can never fit are rejected."""
 import numpy as np
 import pytest
@@ -35,6 +35,8 @@ def _mix(n=10, seed=3):
             p.update(steady=True, si_norm=1, si_tol=1e-9, si_max_iter=400)
         if r % 4 == 3:  # the diffusion closing stage
             p.update(closure=1, si_max_iter=1000)
+        if r % 5 == 4:  # diffusion synthetic acceleration of the S_N iteration
+            p.update(si_accel=1)
         out.append((p, int(rng.integers(2, 6))))
     return out
 

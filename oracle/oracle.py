@@ -91,7 +91,8 @@ def lib():
         L.or_u01.argtypes = [C.c_uint32]
         L.or_mc_pass.restype = C.c_int64
         L.or_mc_pass.argtypes = [C.POINTER(_Mesh), C.POINTER(_Points), C.c_int, C.c_int,
-                                 C.c_void_p, C.c_int64, C.POINTER(_BankIn), C.c_uint64,
+                                 C.c_void_p, C.c_void_p, C.c_double, C.POINTER(_BankIn),
+                                 C.c_uint64,
                                  C.c_uint64, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.POINTER(_BankOut)]
         L.or_thin.restype = C.c_int64
@@ -102,16 +103,16 @@ def lib():
                                    C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
         L.or_pow2_ceil.restype = C.c_double
         L.or_pow2_ceil.argtypes = [C.c_double]
-        L.or_build_sum_tree.restype = C.POINTER(C.c_double)
-        L.or_build_sum_tree.argtypes = [C.c_void_p, C.c_int64, C.c_double,
-                                        C.POINTER(C.c_int64)]
+        L.or_cell_majorants.restype = None
+        L.or_cell_majorants.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p]
         L.or_halton_u32.restype = C.c_uint32
         L.or_halton_u32.argtypes = [C.c_uint32, C.c_uint32]
         L.or_quantum.restype = C.c_double
         L.or_quantum.argtypes = [C.c_double]
-        L.or_cell_counts.restype = C.c_int64
-        L.or_cell_counts.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_int64, C.c_void_p,
-                                     C.POINTER(C.c_double)]
+        L.or_emission_counts.restype = C.c_int64
+        L.or_emission_counts.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_int64,
+                                         C.POINTER(_Points), C.c_uint64, C.c_uint64, C.c_int,
+                                         C.c_void_p, C.POINTER(C.c_double)]
         L.or_history_id.restype = C.c_uint64
         L.or_history_id.argtypes = [C.c_uint64, C.c_int64, C.c_uint32]
         L.or_dg_sweep.restype = C.c_int
@@ -321,37 +322,56 @@ class Mesh:
 
 def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
             bank: Bank, seed: int, step: int, w_cut_rel: float, want_census: bool):
-    """One (Q)MC pass (Sec. 2.3).  Returns (T_a, T_b, balance dict, segments,
-    census-out candidates or None).  T are raw track-length sums."""
+    """One (Q)MC pass (Sec. 2.3) emitting the plan of ``emission_plan``.
+    Returns (T_a, T_b, balance dict, segments, census-out candidates or None).
+    T are raw track-length sums."""
     q_nodal = np.ascontiguousarray(q_nodal, dtype=np.float64).reshape(-1)
     assert q_nodal.size == 4 * mesh.ncell
+    plan = emission_plan(q_nodal, mesh.adt, n_src, pts, seed, step, kind)
+    counts = np.ascontiguousarray(plan["counts"], dtype=np.int64)
+    if counts.size == 0:
+        counts = np.zeros(1, dtype=np.int64)
     Ta = np.zeros(mesh.ncell); Tb = np.zeros(mesh.ncell); bal = np.zeros(len(BAL_NAMES))
     bin_ = _BankIn(bank.n, _p(bank.x), _p(bank.y), _p(bank.ox), _p(bank.oy), _p(bank.w),
                    _p(bank.cell), _p(bank.hid))
     out = None
     bout_p = None
     if want_census:
-        ncand = bank.n + cell_counts(q_nodal, mesh.adt, n_src)[1]
+        ncand = bank.n + plan["n_emit"]
         out = Bank(ncand)
         out.alive = np.zeros(ncand, dtype=np.uint8)
         bout = _BankOut(_p(out.x), _p(out.y), _p(out.ox), _p(out.oy), _p(out.w),
                         _p(out.cell), _p(out.hid), _p(out.alive))
         bout_p = C.byref(bout)
-    seg = lib().or_mc_pass(C.byref(mesh.s), C.byref(pts.s), kind, n_s, _p(q_nodal), n_src,
-                           C.byref(bin_), seed, step, w_cut_rel, _p(Ta), _p(Tb), _p(bal),
-                           bout_p)
+    seg = lib().or_mc_pass(C.byref(mesh.s), C.byref(pts.s), kind, n_s, _p(q_nodal),
+                           _p(counts), plan["w_q"], C.byref(bin_), seed, step, w_cut_rel,
+                           _p(Ta), _p(Tb), _p(bal), bout_p)
     return Ta, Tb, dict(zip(BAL_NAMES, bal)), int(seg), out
 
 
-def cell_counts(q_nodal, adt, n_src):
-    """Emission counts of a pass (see slh_oracle.c: or_cell_counts): per-cell
-    counts, their total and the weight quantum w_q."""
+def cell_majorants(q_nodal, adt):
+    """M_i = adt * (largest corner |q_i| rounded up to a power of two)."""
     q_nodal = np.ascontiguousarray(q_nodal, dtype=np.float64).reshape(-1)
     n = q_nodal.size // 4
-    counts = np.zeros(max(n, 1), dtype=np.int64)
+    M = np.zeros(max(n, 1))
+    lib().or_cell_majorants(_p(q_nodal), n, adt, _p(M))
+    return M[:n]
+
+
+def emission_plan(q_nodal, adt, n_src, pts: Points, seed: int, step: int, kind: int):
+    """The source particles of one pass (Sec. 2.3, birth in proportion to the
+    source): the cell majorants M_i, their correctly rounded sum (math.fsum),
+    the weight quantum w_q = quantum(sum / n_src) and the per-cell counts
+    floor(M_i / w_q) + [u_i < frac(M_i / w_q)] (see slh_oracle.c:
+    or_emission_counts)."""
+    M = cell_majorants(q_nodal, adt)
+    total = math.fsum(M.tolist())
+    counts = np.zeros(max(M.size, 1), dtype=np.int64)
     wq = C.c_double(0.0)
-    tot = lib().or_cell_counts(_p(q_nodal), n, adt, n_src, _p(counts), C.byref(wq))
-    return counts[:n], int(tot), wq.value
+    n_emit = lib().or_emission_counts(_p(np.ascontiguousarray(M)), M.size, total, n_src,
+                                      C.byref(pts.s), seed, step, kind, _p(counts),
+                                      C.byref(wq))
+    return dict(M=M, total=total, w_q=wq.value, counts=counts[:M.size], n_emit=int(n_emit))
 
 
 def history_id(step: int, cell: int, l: int) -> int:

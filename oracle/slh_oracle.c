@@ -25,12 +25,15 @@
  *     cells (Sec. 2.3, "sample next scatter at rate sigma_s").
  *   - the remap (step 3 of Sec. 2.2) emits from Q + sigma_s (phi_pre + phi_post
  *     + phi_c), with phi_c bilinear per cell from the DG solve.  Emission (both
- *     passes) is stratified by cell: cell i receives n_i = ceil(M_i / w_q)
- *     particles, M_i = A dt (max corner |q_i| rounded up to a power of two),
- *     w_q = sum(M) / N_p rounded down to five significant bits; each particle
- *     is uniform in its cell with weight q(x,y) A dt / n_i, and draws its
- *     points from its cell's own stream at its index within the cell, so
- *     a change of one cell's count moves no other particle.
+ *     passes) is stratified by cell: with M_i = A dt qbar_i (qbar_i the
+ *     largest corner |q_i| rounded up to a power of two) and w_q = sum(M)/N_p
+ *     (the correctly rounded sum) rounded down to five significant bits, cell
+ *     i receives floor(r_i) or floor(r_i) + 1 particles, r_i = M_i / w_q,
+ *     the second with probability frac(r_i) (a point of the cell's own count
+ *     stream decides); each particle is uniform in its cell with weight
+ *     w_q q(x,y) / qbar_i, and draws its points from its cell's own stream at
+ *     its index within the cell, so a change of one cell's count moves no
+ *     other particle.
  *
  * Parity unpinned (no closed form or independent check exists): none of the
  * functions below; the tests pin each one (points, attenuation, Erlang split,
@@ -217,18 +220,12 @@ double or_pow2_ceil(double v)
     return (m == 0.5) ? v : ldexp(1.0, e);
 }
 
-/* Binary sum tree over the cell majorants (heap order, 1-based): leaves at
- * [L, L + n) with L the smallest power of two >= n, tree[k] = tree[2k] +
- * tree[2k+1].  Returns the array (caller frees) and L. */
-double *or_build_sum_tree(const double *q_nodal, int64_t n, double adt, int64_t *L_out)
+/* Majorant of cell i for the emission: M_i = adt * qbar_i, with qbar_i the
+ * largest corner |q| of the cell rounded up to a power of two (a majorant of
+ * |q| over the cell, since the bilinear q takes its extremes at the corners). */
+void or_cell_majorants(const double *q_nodal, int64_t n, double adt, double *M)
 {
-    int64_t L = 1;
-    while (L < n) L *= 2;
-    double *t = (double *)calloc((size_t)(2 * L), sizeof(double));
-    for (int64_t i = 0; i < n; ++i) t[L + i] = adt * or_pow2_ceil(or_maxabs4(q_nodal + 4 * i));
-    for (int64_t k = L - 1; k >= 1; --k) t[k] = t[2 * k] + t[2 * k + 1];
-    *L_out = L;
-    return t;
+    for (int64_t i = 0; i < n; ++i) M[i] = adt * or_pow2_ceil(or_maxabs4(q_nodal + 4 * i));
 }
 
 /* v rounded down to five significant bits (v > 0): with m in [1/2, 1) and
@@ -241,25 +238,32 @@ double or_quantum(double v)
     return ldexp(floor(m * 32.0) / 32.0, e);
 }
 
-/* Emission counts of one pass: w_q = quantum(sum(M) / n_src) with the sum
- * taken by the majorant tree, n_i = ceil(M_i / w_q) (0 where M_i = 0).
- * Writes counts[i] when counts is not NULL and *wq_out; returns the total,
- * which lies in [n_src, n_src (1 + 1/16) + number of cells with M_i > 0). */
-int64_t or_cell_counts(const double *q_nodal, int64_t n, double adt, int64_t n_src,
-                       int64_t *counts, double *wq_out)
+/* Emission counts of one pass (Sec. 2.3: particles are born in proportion to
+ * the source).  The weight quantum is w_q = quantum(total / n_src), where
+ * total is the sum of the majorants M_i (the caller passes it correctly
+ * rounded).  Cell i expects r_i = M_i / w_q particles and receives
+ * floor(r_i) + [u_i < r_i - floor(r_i)], u_i being point 0 of dimension 0
+ * of the cell's count stream (population 3 of the step's pass), so that
+ * E[n_i] = r_i and the total stays close to n_src whatever the number of
+ * cells.  Writes counts[i] and *wq_out; returns the total. */
+int64_t or_emission_counts(const double *M, int64_t n, double total, int64_t n_src,
+                           const or_points *P, uint64_t seed, uint64_t step, int kind,
+                           int64_t *counts, double *wq_out)
 {
-    int64_t L;
-    double *tree = or_build_sum_tree(q_nodal, n, adt, &L);
-    const double total = tree[1];
     const double wq = (total > 0.0 && n_src > 0) ? or_quantum(total / (double)n_src) : 0.0;
     int64_t sum = 0;
     for (int64_t i = 0; i < n; ++i) {
-        const double Mi = tree[L + i];
-        const int64_t c = (wq > 0.0 && Mi > 0.0) ? (int64_t)ceil(Mi / wq) : 0;
-        if (counts) counts[i] = c;
+        int64_t c = 0;
+        if (wq > 0.0 && M[i] > 0.0) {
+            const double r = M[i] / wq;
+            const double fl = floor(r);
+            const uint64_t cs = or_stream_seed(seed, step, (uint32_t)kind, 3u, (uint64_t)i);
+            const double u = or_u01(or_point_u32(P, cs, 0, 0));
+            c = (int64_t)fl + ((u < r - fl) ? 1 : 0);
+        }
+        counts[i] = c;
         sum += c;
     }
-    free(tree);
     if (wq_out) *wq_out = wq;
     return sum;
 }
@@ -287,13 +291,14 @@ enum { EV_CENSUS = 0, EV_COLLIDE = 1, EV_XFACE = 2, EV_YFACE = 3 };
  *   kind  = 2: step 3 of Sec. 2.2, the scatter-free remap (every particle is
  *              in the post-limit regime: attenuation by sigma_t, no scatter).
  * Source: nodal (bilinear) emission density q_nodal[n_cells*4] per unit
- * area and time, angle-integrated; n_src particles (birth ~ q, Sec. 2.3).
+ * area and time, angle-integrated (birth ~ q, Sec. 2.3), with counts[i]
+ * particles in cell i and weight quantum wq (or_emission_counts).
  * T_a receives the pre tally, T_b the post (kind 1) or the remap tally
  * (kind 2); both are raw track-length sums (weight x length).
  * Returns the number of segments (loop iterations).
  */
 int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
-                   const double *q_nodal, int64_t n_src,
+                   const double *q_nodal, const int64_t *counts, double wq,
                    const or_bank_in *bin, uint64_t seed, uint64_t step,
                    double w_cut_rel,
                    double *T_a, double *T_b, double *bal, or_bank_out *bout)
@@ -302,7 +307,6 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
     const int64_t ncell = (int64_t)nx * ny;
     const double hx = (M->x_hi - M->x_lo) / nx;
     const double hy = (M->y_hi - M->y_lo) / ny;
-    const double area = hx * hy;
     /* Steady state, the infinite time step of the paper's runs (Sec. 3):
      * weights are per unit time (A in place of A dt), every particle starts
      * at path length 0, and the end of the step becomes a path horizon: the
@@ -325,12 +329,8 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
     for (int64_t i = 0; i < ncell; ++i) { T_a[i] = 0.0; T_b[i] = 0.0; }
     for (int k = 0; k < OB_N; ++k) bal[k] = 0.0;
 
-    /* Emission counts per cell (majorants M_i = A dt mbar_i, mbar_i = max
-     * corner |q_i| rounded up to a power of two): n_i = ceil(M_i / w_q). */
-    const double adt = M->steady ? area : area * dt;
-    int64_t *counts = (int64_t *)calloc((size_t)(ncell > 0 ? ncell : 1), sizeof(int64_t));
-    double wq = 0.0;
-    const int64_t n_emit = or_cell_counts(q_nodal, ncell, adt, n_src, counts, &wq);
+    int64_t n_emit = 0;
+    for (int64_t i = 0; i < ncell; ++i) n_emit += counts[i];
     const double w_cut = w_cut_rel * wq;
 
     int64_t segments = 0;
@@ -359,8 +359,10 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
         } else {
             /* source particle l of cell j (particles in cell order): uniform
              * position in the cell and time in the step, isotropic direction,
-             * signed weight q(x,y) A dt / n_j; points of the cell's stream at
-             * index l. */
+             * signed weight w_q q(x,y) / qbar_j (qbar_j the cell's power-of-two
+             * majorant of |q|, so |w| <= w_q and, with E[n_j] = M_j / w_q,
+             * the expected weight of the cell is its integral of q over the
+             * step); points of the cell's stream at index l. */
             const int64_t s = g - bin->n_in;
             while (s >= cbase + counts[cj]) { cbase += counts[cj]; cj += 1; }
             const int64_t ci = cj;
@@ -382,7 +384,7 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             ox = st * cos(ph);
             oy = st * sin(ph);
             const double *qc = q_nodal + 4 * ci;
-            w = or_bilinear(qc, u1, u2) * (adt / (double)counts[ci]);
+            w = or_bilinear(qc, u1, u2) * (wq / or_pow2_ceil(or_maxabs4(qc)));
             dcur = 5;
             bal[OB_SOURCE_W] += w;
         }
@@ -475,7 +477,6 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             if (fabs(w) < w_cut) { bal[OB_CUTOFF] += w; break; }
         }
     }
-    free(counts);
     return segments;
 }
 

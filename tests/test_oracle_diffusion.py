@@ -94,14 +94,17 @@ def test_balance_and_m_matrix(oracle):
 def test_hybrid_step_with_diffusion_closure(oracle):
     """In a closed homogeneous box with a uniform source the diffusion closing
     stage is exact (its solution is the infinite-medium value), so a steady
-    step keeps the remap total Q/sigma_a."""
+    step keeps the remap total Q/sigma_a: exactly in expectation, here within
+    the sampling error of the per-cell counts (randomised rounding) and
+    positions, and exactly the remap pass's absorbed weight."""
     from paper_2511_16821_amd import workloads as W
     ss, sa, Q, n = 0.6, 0.4, 2.0, 4
     p = W.homogeneous_box(n=n, L=4.0, sig_s=ss, sig_a=sa, src_cells=((0, n), (0, n)), n_s=1,
                           n_particles=20000, sn_order=4, steady=True, boundary=15, closure=1)
     p["q"] = np.full((n, n), Q)
     r = oracle.HybridOracle(p).step()
-    assert r["phi_R"].mean() == pytest.approx(Q / sa, rel=1e-6)
+    assert r["phi_R"].mean() == pytest.approx(Q / sa, rel=2e-3)
+    assert r["phi_R"].mean() * sa * 16.0 == pytest.approx(r["bal_remap"]["absorbed"], rel=1e-12)
     assert r["phi_c"].mean() == pytest.approx(ss * r["phi_post"].mean() / sa, rel=1e-9)
 
 

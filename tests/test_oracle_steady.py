@@ -46,13 +46,15 @@ def test_steady_infinite_medium(oracle, n_s):
     assert abs(r["phi_pre"].mean() - pre) <= 1e-3 * Q / sa
     assert abs(r["phi_post"].mean() - post) <= 1e-3 * Q / sa
     # the remap's total is fixed by the balances of the three stages (up to
-    # the cutoff); its cells carry the noise of the remapped source (pure MC:
-    # of the scattering histories, where the points help least)
-    assert r["phi_R"].mean() == pytest.approx(Q / sa, rel=1e-6)
+    # the cutoff) in expectation; a run adds the rounding noise of the
+    # per-cell counts (at most one particle of weight <= w_q per cell and
+    # pass, about 16 / 20000 here); its cells carry the noise of the remapped
+    # source (pure MC: of the scattering histories, where the points help least)
+    assert r["phi_R"].mean() == pytest.approx(Q / sa, rel=2e-3)
     assert np.max(np.abs(r["phi_R"] - Q / sa)) <= (5e-2 if n_s < 0 else 1.5e-2) * Q / sa
     A = o.mesh.area
     b1 = r["bal_mc"]
-    assert b1["emitted"] == pytest.approx(Q * 16.0, rel=1e-13)
+    assert b1["emitted"] == pytest.approx(Q * 16.0, rel=16 / 20000 * 1.1)
     # a history alive at the default horizon carries at most the cutoff
     # weight w_cut_rel w_q (here sum_i n_i w_q <= 1.07 x emitted)
     assert b1["leaked"] == 0.0 and 0.0 <= b1["census"] <= 1.07e-8 * b1["emitted"]
@@ -105,7 +107,8 @@ def test_steady_void_box_runs_to_the_horizon(oracle):
     r = oracle.HybridOracle(p).step()
     for key, T in (("bal_mc", r["T_post"]), ("bal_remap", r["T_R"])):
         b = r[key]
-        assert b["emitted"] == pytest.approx(Q * 1.5 * 1.5, rel=1e-13)
+        # 36 cells, at most one particle of weight <= w_q more or less each
+        assert b["emitted"] == pytest.approx(Q * 1.5 * 1.5, rel=36 / 3000)
         assert b["census"] == pytest.approx(b["emitted"], rel=1e-13)
         assert b["absorbed"] == 0.0 and b["leaked"] == 0.0 and b["cutoff"] == 0.0
         assert T.sum() == pytest.approx(b["emitted"] * H, rel=1e-12)

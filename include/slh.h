@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define SLH_ABI_VERSION 4u
+#define SLH_ABI_VERSION 5u
 
 typedef enum {
     SLH_OK = 0,
@@ -96,12 +96,17 @@ typedef struct {
     int32_t n_s;                   /* scatter limit N_s >= 0; -1: unlimited
                                       (the first leg is then plain MC, the
                                       collided solve has no source)        */
-    int64_t n_particles;           /* N_p, 0..2^31: each MC pass emits          */
-                                   /* sum_i ceil(M_i / w_q) source particles,   */
-                                   /* between N_p and N_p (1 + 1/16) + cells    */
-                                   /* with a source (emission stratified by     */
-                                   /* cell, w_q = sum(M) / N_p rounded down to  */
-                                   /* five significant bits; Sec. 2.3)          */
+    int64_t n_particles;           /* N_p, 0..2^31: source particles per MC     */
+                                   /* pass, born in proportion to the source   */
+                                   /* (Sec. 2.3) and stratified by cell: with  */
+                                   /* M_i = A dt (largest corner |q_i| rounded */
+                                   /* up to a power of two) and w_q = sum(M) / */
+                                   /* N_p (sum correctly rounded) rounded down */
+                                   /* to five significant bits, cell i emits   */
+                                   /* floor(r_i) or floor(r_i) + 1 particles,  */
+                                   /* r_i = M_i / w_q, the second with chance  */
+                                   /* frac(r_i); E[total] = sum(M) / w_q lies  */
+                                   /* in [N_p, N_p 16/15)                      */
     int64_t census_cap;            /* census bank size; 0 -> n_particles     */
     int32_t sn_order;              /* even N >= 2: N^2 product directions    */
     double time_closure;           /* tau in sigma_t + tau/(c dt); 0 -> 2    */
@@ -220,6 +225,13 @@ typedef struct {
     double census_in_w;  /* weight of the census-in bank                     */
     uint64_t segments;   /* tracking-loop iterations                         */
     uint64_t particles;  /* histories started                                */
+    double majorant_sum; /* sum of the cell majorants M_i, correctly rounded  */
+    double weight_quantum; /* w_q of the pass's emission                      */
+    uint64_t source_particles; /* particles emitted by the source              */
+    uint64_t killed;     /* histories ended by the device's guard of 2^26
+                            segments per history (booked as cutoff); 0 in
+                            every normal run, and slh_advance reports
+                            SLH_E_NUMERIC when it is not                    */
 } slh_balance;
 
 typedef struct {
@@ -241,7 +253,9 @@ typedef struct {
     double ms_kernel_remap_total;   /* step-3 (remap) pass kernels           */
     uint64_t seg_mc_total;          /* segments of step-1 passes             */
     uint64_t seg_remap_total;       /* segments of step-3 passes             */
-    uint64_t census_in_total;       /* census-in particles over all steps    */
+    uint64_t census_in_total;       /* census-in particles over all steps
+                                       (each step's bank, which both passes
+                                       read once)                            */
     uint64_t census_out_total;      /* census candidates written (step 3)    */
     uint64_t steps_total;           /* steps accounted in the totals         */
     uint64_t thin_overflow_total;   /* steps whose census draw exceeded the
@@ -251,6 +265,16 @@ typedef struct {
                                        slh_advance (one per step when the
                                        first batch of source iterations
                                        suffices)                             */
+    uint64_t killed_total;          /* histories ended by the segment guard   */
+    /* Diffusion synthetic acceleration (si_accel), last step: corrections
+     * solved, their conjugate-gradient iterations in total, and how many
+     * stopped at the iteration limit (32) before the tolerance (1e-2): on
+     * large meshes a correction is then approximate, which changes the
+     * number of sweeps but not the fixed point of the iteration. */
+    int32_t dsa_corrections;
+    int32_t dsa_iterations;
+    int32_t dsa_unconverged;
+    int32_t pad0;
 } slh_stats;
 
 typedef struct slh_solver slh_solver;
@@ -305,7 +329,12 @@ slh_status slh_get_census(slh_solver *s, int64_t *n, double *x, double *y, doubl
 
 /* Checkpoint: the complete state between steps is the census bank, the step
  * index and the problem (zero collided initial data every step).  With
- * buf == NULL, *len receives the size needed. */
+ * buf == NULL, *len receives the size needed.  The buffer records the mesh
+ * size, seed, precision and bank; slh_load rejects (SLH_E_INVALID_ARG,
+ * nothing changed) a buffer written for another mesh, seed or precision, a
+ * bank above the cap, and particles that are not valid for this problem (a
+ * cell off the mesh, a position outside its cell, a non-finite weight or one
+ * above the recorded maximum). */
 slh_status slh_save(slh_solver *s, void *buf, size_t *len);
 slh_status slh_load(slh_solver *s, const void *buf, size_t len);
 

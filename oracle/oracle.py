@@ -346,7 +346,10 @@ def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
     seg = lib().or_mc_pass(C.byref(mesh.s), C.byref(pts.s), kind, n_s, _p(q_nodal),
                            _p(counts), plan["w_q"], C.byref(bin_), seed, step, w_cut_rel,
                            _p(Ta), _p(Tb), _p(bal), bout_p)
-    return Ta, Tb, dict(zip(BAL_NAMES, bal)), int(seg), out
+    balance = dict(zip(BAL_NAMES, bal))
+    balance.update(majorant_sum=plan["total"], weight_quantum=plan["w_q"],
+                   source_particles=plan["n_emit"])
+    return Ta, Tb, balance, int(seg), out
 
 
 def cell_majorants(q_nodal, adt):

@@ -314,7 +314,8 @@ static Sizes sizes_of(const slh_problem* p) {
   if (p->n_s_cell) b += nc * 4;              // per-cell scatter limits
   if (p->boundary)                           // mirror indices, reflected traces
     b += (size_t)z.n_dir * 8 + (size_t)2 * z.n_dir * 2 * (p->nx + p->ny) * 8;
-  b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 4;  // nodal sources, trees
+  b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 2;  // nodal sources, count trees
+  b += (size_t)kMajBins * 8;                 // majorant histogram
   b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
   b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
   if (z.diffusion || z.dsa)
@@ -347,12 +348,13 @@ struct BalStore {
   unsigned long long segments, particles, alive, killed;
   double unit_W;
   long long n_in;
+  long long n_emit;
+  double sumM, wq;
   int thin_overflow;  // of the census that this pass read
-  int pad0;
-  double pad[1];
+  int numeric;        // DevState::numeric of the pass
 };
 
-__global__ void k_snapshot(const DevState* st, BalStore* out) {
+__global__ void k_snapshot(const DevState* st, BalStore* out, int kind) {
   const int t = threadIdx.x;
   if (t < 2 * B_NFIELDS) out->bal[t] = st->bal[t];
   if (t == 0) {
@@ -362,7 +364,11 @@ __global__ void k_snapshot(const DevState* st, BalStore* out) {
     out->killed = st->killed;
     out->unit_W = st->unit_W;
     out->n_in = st->n_in;
+    out->n_emit = st->n_emit;
+    out->sumM = st->sumM[kind - 1];
+    out->wq = st->wq[kind - 1];
     out->thin_overflow = st->thin_overflow;
+    out->numeric = st->numeric;
   }
 }
 
@@ -422,8 +428,9 @@ struct slh_solver {
   double2* mat64 = nullptr;
   float2* mat32 = nullptr;
   double *sig_s = nullptr, *sig_e = nullptr, *q = nullptr;
-  double *qn1 = nullptr, *tree1 = nullptr, *ctree1 = nullptr;  // majorant and count trees
-  double *qnR = nullptr, *treeR = nullptr, *ctreeR = nullptr;
+  double *qn1 = nullptr, *ctree1 = nullptr;  // nodal source and count tree of each pass
+  double *qnR = nullptr, *ctreeR = nullptr;
+  unsigned long long* maj_hist = nullptr;     // histogram of the emission plan
   long long tree_L = 1;
   unsigned long long *Tpre = nullptr, *Tpost = nullptr, *TR = nullptr;
   double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr;
@@ -470,6 +477,7 @@ struct slh_solver {
   unsigned long long k_seg[2] = {0ull, 0ull};
   unsigned long long census_in_total = 0ull, census_out_total = 0ull, steps_total = 0ull;
   unsigned long long thin_overflow_total = 0ull;
+  unsigned long long killed_total = 0ull;
 
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 8;
@@ -558,11 +566,10 @@ static slh_status setup(slh_solver* s) {
   if (!s->h_ns.empty()) ALLOC(s->ns_cell, int, nc);
   s->tree_L = tree_leaves(nc);
   ALLOC(s->qn1, double, 4 * nc);
-  ALLOC(s->tree1, double, 2 * s->tree_L);
   ALLOC(s->ctree1, double, 2 * s->tree_L);
   ALLOC(s->qnR, double, 4 * nc);
-  ALLOC(s->treeR, double, 2 * s->tree_L);
   ALLOC(s->ctreeR, double, 2 * s->tree_L);
+  ALLOC(s->maj_hist, unsigned long long, kMajBins);
   ALLOC(s->Tpre, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
   ALLOC(s->Tpost, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
   ALLOC(s->TR, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
@@ -680,8 +687,9 @@ static slh_status setup(slh_solver* s) {
     HIP_TRY(launch_diff_coef(p.nx, p.ny, s->mat64, time_term(&p), s->hx, s->hy,
                              z.dsa ? 0 : p.boundary, s->cg_diag, s->cg_e, s->cg_n, st));
   HIP_TRY(hipMemcpyAsync(s->sobol, sobol_table_host(), 4 * 32 * 32, hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_build_tree(s->qn1, nc, s->adt, s->tree1, st));
-  HIP_TRY(launch_count_tree(s->tree1, nc, z.n_p, s->ctree1, st));
+  HIP_TRY(launch_fill_u64(s->maj_hist, kMajBins, 0ull, st));  // left zero by every plan
+  HIP_TRY(launch_fill_f64(s->ctree1, 2 * s->tree_L, 0.0, st));
+  HIP_TRY(launch_fill_f64(s->ctreeR, 2 * s->tree_L, 0.0, st));
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, st, s->st);
   HIP_TRY(launch_fill_f64(s->phi_c, 4 * nc, 0.0, st));
   HIP_TRY(launch_fill_f64(s->phi_pre, nc, 0.0, st));
@@ -713,13 +721,13 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.keep_census = p.steady ? 0 : 1;
   a.mat64 = s->mat64;
   a.mat32 = s->mat32;
-  a.tree = kind == 1 ? s->tree1 : s->treeR;
   a.ctree = kind == 1 ? s->ctree1 : s->ctreeR;
   a.adt = s->adt;
   a.tree_L = s->tree_L;
   a.qn = kind == 1 ? s->qn1 : s->qnR;
   a.n_cells = s->z.n_cells;
   a.n_src = s->z.n_p;
+  a.src_cap = s->z.n_src_cap;
   a.seed = p.seed;
   a.kind = kind;
   // n_s = -1: no scatter limit (the leg is plain implicit-capture MC)
@@ -755,11 +763,22 @@ static PassArgs pass_args(slh_solver* s, int kind) {
 // Called only after the stream has passed the pass's snapshot copy.
 static slh_status collect(slh_solver* s, int k) {
   if (!s->pending[k]) return SLH_OK;
+  if (s->h_bal[k].numeric || s->h_bal[k].killed) {
+    s->pending[k] = false;
+    const int f = s->h_bal[k].numeric;
+    return fail(SLH_E_NUMERIC,
+                std::string(k == 0 ? "scatter-limited" : "remap") + " pass: " +
+                    ((f & 1) ? "a cell majorant or their sum is not finite; " : "") +
+                    ((f & 2) ? "a history ended with a non-finite weight or tally; " : "") +
+                    ((f & 4) ? "the emission exceeded the source bank; " : "") +
+                    (s->h_bal[k].killed ? "histories reached the 2^26-segment guard" : ""));
+  }
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, s->evk[2 * k], s->evk[2 * k + 1]));
   s->k_ms[k] += ms;
   s->k_seg[k] += s->h_bal[k].segments;
-  s->census_in_total += (unsigned long long)s->h_bal[k].n_in;
+  s->killed_total += s->h_bal[k].killed;
+  if (k == 0) s->census_in_total += (unsigned long long)s->h_bal[0].n_in;
   if (k == 0 && s->h_bal[0].thin_overflow) s->thin_overflow_total += 1;
   if (k == 1) {
     s->census_out_total += s->h_bal[1].alive;
@@ -897,8 +916,10 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
   const long long n_tally = (long long)z.n_copies * kTallyStride * nc;
   switch (part) {
     case kA1: {
-      HIP_TRY(launch_pass_prep(s->st, s->tree1, cdt, s->Tpre, n_tally, s->Tpost, n_tally,
-                               nullptr, 0, st));
+      HIP_TRY(launch_emission_plan(s->qn1, nc, s->adt, z.n_p, p.seed, p.points, 1, s->maj_hist,
+                                   s->ctree1, s->st, st));
+      HIP_TRY(launch_pass_prep(s->st, s->ctree1, 1, z.n_src_cap, cdt, s->Tpre, n_tally, s->Tpost,
+                               n_tally, nullptr, 0, st));
       HIP_TRY(launch_emit(pass_args(s, 1), z.fp32, st));
       return SLH_OK;
     }
@@ -906,7 +927,7 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
       HIP_TRY(launch_tally_to_flux(s->Tpre, s->phi_pre, s->Tpost, s->phi_post, nc, z.n_copies,
                                    cstride, s->st, inv_adt, st));
       hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
-                         s->bal_store + 0);
+                         s->bal_store + 0, 1);
       HIP_TRY(hipMemcpyAsync(s->h_bal + 0, s->bal_store + 0, sizeof(BalStore),
                              hipMemcpyDeviceToHost, st));
       if (use_cg(s)) {
@@ -919,17 +940,17 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
     }
     case kB1: {
       if (s->skip_remap) {  // no remap leg: clear its balance and census flags only
-        HIP_TRY(launch_pass_prep(s->st, s->tree1, cdt, nullptr, 0, nullptr, 0, s->alive,
-                                 z.n_cand, st));
+        HIP_TRY(launch_pass_prep(s->st, s->ctree1, 1, z.n_src_cap, cdt, nullptr, 0, nullptr, 0,
+                                 s->alive, z.n_cand, st));
         return SLH_OK;
       }
       if (use_cg(s)) HIP_TRY(launch_cg_to_nodal(cg_args(s), s->phi_c, st));
       HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c,
                                   s->qnR, st));
-      HIP_TRY(launch_build_tree(s->qnR, nc, s->adt, s->treeR, st));
-      HIP_TRY(launch_count_tree(s->treeR, nc, z.n_p, s->ctreeR, st));
-      HIP_TRY(launch_pass_prep(s->st, s->treeR, cdt, s->TR, n_tally, nullptr, 0, s->alive,
-                               z.n_cand, st));
+      HIP_TRY(launch_emission_plan(s->qnR, nc, s->adt, z.n_p, p.seed, p.points, 2, s->maj_hist,
+                                   s->ctreeR, s->st, st));
+      HIP_TRY(launch_pass_prep(s->st, s->ctreeR, 2, z.n_src_cap, cdt, s->TR, n_tally, nullptr, 0,
+                               s->alive, z.n_cand, st));
       HIP_TRY(launch_emit(pass_args(s, 2), z.fp32, st));
       return SLH_OK;
     }
@@ -938,7 +959,7 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
       HIP_TRY(launch_tally_to_flux(s->skip_remap ? s->Tpre : s->TR, s->phi_R, nullptr, nullptr,
                                    nc, z.n_copies, cstride, s->st, inv_adt, st));
       hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
-                         s->bal_store + 1);
+                         s->bal_store + 1, 2);
       HIP_TRY(hipMemcpyAsync(s->h_bal + 1, s->bal_store + 1, sizeof(BalStore),
                              hipMemcpyDeviceToHost, st));
       void* nb = s->bank_mem[1 - s->cur];
@@ -1195,6 +1216,10 @@ extern "C" slh_status slh_get_balance(slh_solver* s, int32_t pass, slh_balance* 
   out->census_in_w = v[B_CENSUS_IN_W];
   out->segments = b.segments;
   out->particles = b.particles;
+  out->majorant_sum = b.sumM;
+  out->weight_quantum = b.wq;
+  out->source_particles = (uint64_t)b.n_emit;
+  out->killed = b.killed;
   return SLH_OK;
 }
 
@@ -1228,6 +1253,10 @@ extern "C" slh_status slh_get_stats(slh_solver* s, slh_stats* out) {
   out->thin_overflow_total = s->thin_overflow_total;
   out->graph_launches_total = s->graph_launches;
   out->host_waits_total = s->host_syncs;
+  out->killed_total = s->killed_total;
+  out->dsa_corrections = d.dsa_corrections;
+  out->dsa_iterations = d.dsa_iter_total;
+  out->dsa_unconverged = d.dsa_unconv;
   if (s->step > 0) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, s->ev[0], s->evk[1]) == hipSuccess) out->ms_mc = ms;
@@ -1287,9 +1316,11 @@ extern "C" slh_status slh_get_census(slh_solver* s, int64_t* n, double* x, doubl
   return SLH_OK;
 }
 
-// Checkpoint layout: magic, abi, step, precision, count, maxabs, then the raw
-// bank arrays (px, py, ox, oy, w in the solver's precision, hid, cell).
-static const uint64_t kMagic = 0x534c48434b505431ull;  // "SLHCKPT1"
+// Checkpoint layout: ten 8-byte header words (magic, abi, step, precision,
+// count, maxabs, nx, ny, seed, cap), then the raw bank arrays (px, py, ox, oy,
+// w in the solver's precision, hid, cell).
+static const uint64_t kMagic = 0x534c48434b505432ull;  // "SLHCKPT2"
+static const size_t kCkptHead = 10 * 8;
 
 extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
   if (!s || !len) return fail(SLH_E_INVALID_ARG, "NULL argument");
@@ -1297,8 +1328,7 @@ extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
   DevState d;
   COPY_SYNC(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
   const long long cnt = d.n_in;
-  const size_t head = 6 * 8;
-  const size_t need = head + s->bank_bytes(cnt);
+  const size_t need = kCkptHead + s->bank_bytes(cnt);
   if (!buf) { *len = need; return SLH_OK; }
   if (*len < need) return fail(SLH_E_INVALID_ARG, "buffer too small");
   uint64_t* h = (uint64_t*)buf;
@@ -1308,7 +1338,11 @@ extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
   h[3] = (uint64_t)s->z.fp32;
   h[4] = (uint64_t)cnt;
   memcpy(&h[5], &d.maxabs_w, 8);
-  char* out = (char*)buf + head;
+  h[6] = (uint64_t)s->prob.nx;
+  h[7] = (uint64_t)s->prob.ny;
+  h[8] = s->prob.seed;
+  h[9] = (uint64_t)s->z.cap;
+  char* out = (char*)buf + kCkptHead;
   const size_t rb = s->z.fp32 ? 4 : 8;
   // the bank arrays are laid out with stride cap; copy each array's prefix
   char* base = (char*)s->bank_mem[s->cur];
@@ -1324,20 +1358,50 @@ extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
   return SLH_OK;
 }
 
+// Host-side check of a checkpoint's particles before they reach the device:
+// every cell on the mesh, positions inside their cell, directions and
+// weights finite, and the stored max |w| (the next pass's fixed-point bound)
+// not below any weight.
+template <typename R>
+static bool ckpt_bank_ok(const char* in, long long cnt, long long n_cells, double hx, double hy,
+                         double maxabs) {
+  const R* px = (const R*)in;
+  const R* py = px + cnt;
+  const R* ox = py + cnt;
+  const R* oy = ox + cnt;
+  const R* w = oy + cnt;
+  const int32_t* cell = (const int32_t*)((const char*)(w + cnt) + 8 * cnt);
+  if (!(maxabs >= 0.0) || !isfinite(maxabs)) return false;
+  for (long long i = 0; i < cnt; ++i) {
+    if (cell[i] < 0 || (long long)cell[i] >= n_cells) return false;
+    const double x = px[i], y = py[i], a = ox[i], b = oy[i], v = w[i];
+    // (with a relative slack of 1e-6 for the rounding of FP32 banks)
+    if (!(x >= 0.0 && x <= hx * (1.0 + 1e-6) && y >= 0.0 && y <= hy * (1.0 + 1e-6))) return false;
+    if (!(fabs(a) <= 1.0 + 1e-6 && fabs(b) <= 1.0 + 1e-6) || !isfinite(v) || fabs(v) > maxabs)
+      return false;
+  }
+  return true;
+}
+
 extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
   if (!s || !buf) return fail(SLH_E_INVALID_ARG, "NULL argument");
-  const size_t head = 6 * 8;
-  if (len < head) return fail(SLH_E_INVALID_ARG, "checkpoint truncated");
+  if (len < kCkptHead) return fail(SLH_E_INVALID_ARG, "checkpoint truncated");
   const uint64_t* h = (const uint64_t*)buf;
   if (h[0] != kMagic || h[1] != SLH_ABI_VERSION) return fail(SLH_E_INVALID_ARG, "not a checkpoint");
   if (h[3] != (uint64_t)s->z.fp32) return fail(SLH_E_INVALID_ARG, "checkpoint precision differs");
+  if (h[6] != (uint64_t)s->prob.nx || h[7] != (uint64_t)s->prob.ny)
+    return fail(SLH_E_INVALID_ARG, "checkpoint is of another mesh");
+  if (h[8] != s->prob.seed) return fail(SLH_E_INVALID_ARG, "checkpoint has another seed");
   const long long cnt = (long long)h[4];
   if (cnt < 0 || cnt > s->z.cap) return fail(SLH_E_INVALID_ARG, "checkpoint bank exceeds the cap");
-  if (len < head + s->bank_bytes(cnt)) return fail(SLH_E_INVALID_ARG, "checkpoint truncated");
+  if (len < kCkptHead + s->bank_bytes(cnt)) return fail(SLH_E_INVALID_ARG, "checkpoint truncated");
   double maxabs;
   memcpy(&maxabs, &h[5], 8);
+  const char* in = (const char*)buf + kCkptHead;
+  const bool ok = s->z.fp32 ? ckpt_bank_ok<float>(in, cnt, s->z.n_cells, s->hx, s->hy, maxabs)
+                            : ckpt_bank_ok<double>(in, cnt, s->z.n_cells, s->hx, s->hy, maxabs);
+  if (!ok) return fail(SLH_E_INVALID_ARG, "checkpoint particles are not valid for this problem");
   HIP_TRY(hipStreamSynchronize(s->stream));
-  const char* in = (const char*)buf + head;
   const size_t rb = s->z.fp32 ? 4 : 8;
   char* base = (char*)s->bank_mem[s->cur];
   const long long cap = s->z.cap;
@@ -1358,6 +1422,7 @@ extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
   s->k_seg[0] = s->k_seg[1] = 0ull;
   s->census_in_total = s->census_out_total = s->steps_total = 0ull;
   s->thin_overflow_total = 0ull;
+  s->killed_total = 0ull;
   return SLH_OK;
 }
 

@@ -64,6 +64,9 @@ __global__ void k_si_start(long long n, const double* __restrict__ sig_s,
     st->si.bad = 0;
     st->si.dn2 = 0.0;
     st->si.nrm2 = 0.0;
+    st->dsa_unconv = 0;
+    st->dsa_corrections = 0;
+    st->dsa_iter_total = 0;
   }
   const double inv4pi = 0.25 / M_PI;
   const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -630,9 +633,12 @@ __global__ __launch_bounds__(kRedBlock) void k_dsa_apply(
 // Sums the block partials with a fixed association order (strided
 // per-thread sums, then a tree) and takes the iteration's decision: done
 // when |phi_new - phi_old| <= tol |phi_new| (converged), when the iteration
-// limit is reached, or when the residual is not finite.
+// limit is reached, or when the residual is not finite.  After a diffusion
+// correction (dsa) it also books that correction's conjugate-gradient
+// iterations and whether they reached their tolerance.
 __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int n_part,
-                                                     DevState* st, double si_tol, int si_max) {
+                                                     DevState* st, double si_tol, int si_max,
+                                                     int dsa) {
   if (st->si.done) return;
   __shared__ double s_d[256], s_n[256];
   double d = 0.0, n = 0.0;
@@ -661,6 +667,11 @@ __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int
     st->si.bad = bad;
     st->si.conv = conv;
     st->si.done = bad || conv || st->si.iter >= si_max;
+    if (dsa) {
+      st->dsa_corrections += 1;
+      st->dsa_iter_total += st->dsa.iter;
+      if (!st->dsa.conv) st->dsa_unconv += 1;
+    }
   }
 }
 
@@ -671,7 +682,7 @@ hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, doubl
                      a.phi_pre, a.src, partials, a.dnode, (const DevState*)a.st);
   if (!a.dnode)
     hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,
-                       a.st, si_tol, si_max);
+                       a.st, si_tol, si_max, 0);
   return hipGetLastError();
 }
 
@@ -681,7 +692,7 @@ hipError_t launch_dsa_apply(const DgArgs& a, const double* delta, double* partia
                      a.phi_c, (const double*)a.dnode, delta, a.sig_s, a.phi_post, a.phi_pre,
                      a.src, partials, (const DevState*)a.st);
   hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,
-                     a.st, si_tol, si_max);
+                     a.st, si_tol, si_max, 1);
   return hipGetLastError();
 }
 

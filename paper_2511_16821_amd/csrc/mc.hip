@@ -141,13 +141,16 @@ __device__ __forceinline__ void bal_add(unsigned long long* bal, int f, double v
 }
 
 // Emission of the pass's source particles, one thread each (Sec. 2.3: birth
-// proportional to q, isotropic direction, weights that sum to the integral of
-// q), stratified by cell: cell j emits n_j = ceil(M_j / w_q) particles,
+// proportional to q, isotropic direction, weights that integrate q in
+// expectation), stratified by cell: cell j emits the n_j particles of the
+// emission plan (floor(r_j) or floor(r_j) + 1, E[n_j] = r_j = M_j / w_q),
 // numbered in cell order.  Particle l of cell j takes its points from the
 // cell's stream at index l: position (dims 0-1), birth time (dim 2),
 // direction (dims 3-4, sincospi), the first optical depth (dim 5) when the
-// pass allows scatters, and weight q(x,y) A dt / n_j (A / n_j in steady
-// state, where every particle starts at time 0).
+// pass allows scatters, and weight w_q q(x,y) / qbar_j, qbar_j the cell's
+// power-of-two majorant of |q| (so |w| <= w_q; the expected weight of the
+// cell is r_j w_q mean(q) / qbar_j = A dt mean(q), or A mean(q) per unit
+// time in steady state, where every particle starts at time 0).
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   __shared__ uint32_t s_sobol[kSobolNibbleWords];
@@ -159,8 +162,9 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
       s_top[k] = (k >= 1 && k < ntop) ? a.ctree[k] : 0.0;
   }
   __syncthreads();
-  const long long n_emit = (long long)s_top[1];
+  const long long n_emit = a.st->n_emit;  // the plan's count, clamped to the bank
   const uint64_t step = a.st->step;
+  const double wq = a.st->wq[KIND - 1];
   const R hx = (R)a.hx, hy = (R)a.hy, dt_birth = (R)a.dt_birth;
   const SrcBank<R> b = Real<R>::src(a);
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n_emit;
@@ -178,12 +182,12 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
     R sp, cp;
     Real<R>::scpi((R)2 * u5, &sp, &cp);
     const double* q = a.qn + 4 * ci;
-    const double nj = a.ctree[a.tree_L + ci];
+    const double wscale = wq / pow2_ceil(maxabs4(q));  // exact: a power-of-two ratio
     b.px[s] = hx * u1;
     b.py[s] = hy * u2;
     b.ox[s] = sn * cp;
     b.oy[s] = sn * sp;
-    b.w[s] = (R)(bilinear(q, (double)u1, (double)u2) * (a.adt / nj));
+    b.w[s] = (R)(bilinear(q, (double)u1, (double)u2) * wscale);
     b.trel[s] = u3 * dt_birth;
     b.tau[s] = a.n_lim > 0 ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, l)))
                            : (R)0;
@@ -210,10 +214,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   DevState* st = a.st;
   const int lane = __lane_id();
   const long long n_in = st->n_in;
-  const double total = a.tree[1];
-  const long long n_emit = (long long)a.ctree[1];
+  const long long n_emit = st->n_emit;  // the plan's count, clamped to the source bank
   const unsigned long long n_tot = (unsigned long long)(n_in + n_emit);
-  const double w_q = (total > 0.0 && a.n_src > 0) ? quantum5(total / (double)a.n_src) : 0.0;
+  const double w_q = st->wq[KIND - 1];
   const R w_cut = (R)(a.w_cut_rel * w_q);
   const double inv_T = st->inv_T;
   const double inv_W = st->inv_W;
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   uint32_t pidx = 0, dcur = 0, seg_p = 0;
   double w0 = 0.0, acc_abs = 0.0, acc_sca = 0.0;
   bool from_census = false;
-  unsigned int lane_seg = 0, lane_hist = 0, lane_alive = 0, lane_killed = 0;
+  unsigned int lane_seg = 0, lane_hist = 0, lane_alive = 0, lane_killed = 0, lane_bad = 0;
   unsigned long long* my_bal = s_bal + (lane % kBalCopies) * kBalStride;
 
   for (;;) {
@@ -408,6 +411,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
       // fold the history's balance into the block (fixed point, exact)
       const double wend = (double)w;
+      if (!isfinite(wend) || !isfinite(acc_abs) || !isfinite(acc_sca)) lane_bad++;
       bal_add(my_bal, from_census ? B_CENSUS_IN_W : B_SOURCE_W, w0, inv_W);
       bal_add(my_bal, B_ABSORBED, acc_abs, inv_W);
       if (acc_sca != 0.0) bal_add(my_bal, B_SCATTERED, acc_sca, inv_W);
@@ -425,6 +429,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     v2 += __shfl_xor(v2, off);
     v3 += __shfl_xor(v3, off);
   }
+  if (lane_bad) atomicOr(&st->numeric, 2);
   if (lane == 0) {
     atomicAdd(&s_cnt[0], v0);
     atomicAdd(&s_cnt[1], v1);

@@ -115,9 +115,8 @@ __device__ __forceinline__ uint32_t point_u32n(const uint32_t* N, int mode, uint
   return (uint32_t)(mix64(stream ^ mix64(ctr)) >> 32);
 }
 
-// u in (0,1) from a point word: FP64 keeps all 32 bits; FP32 keeps the top
-// 23 bits so that (m + 1/2) 2^-23 is exact and never rounds to 0 or 1.
-// Smallest power of two >= v (v > 0), 0 for v = 0: the cell majorant.
+// Smallest power of two >= v (v > 0), 0 for v = 0: the majorant of |q| in a
+// cell is its largest corner value rounded up this way.
 __host__ __device__ __forceinline__ double pow2_ceil(double v) {
   if (!(v > 0.0)) return 0.0;
   int e;
@@ -140,6 +139,21 @@ __host__ __device__ __forceinline__ uint64_t history_id(uint64_t step, long long
   return mix64((((uint64_t)j << 32) | (uint64_t)l) ^ mix64(step));
 }
 
+// Point 0 of a stream in dimension dim, without the Sobol' tables: the
+// Sobol' word of index 0 is 0 and the Halton radical inverse of 0 is 0, so
+// only the scramble or shift of (stream, dim) remains.  Equal to
+// point_u32n(N, mode, stream, dim, 0) for every mode.
+__device__ __forceinline__ uint32_t point_u32_first(int mode, uint64_t stream, uint32_t dim) {
+  if ((mode == 0 && dim < (uint32_t)kSobolDims) || (mode == 2 && dim < (uint32_t)kHaltonDims)) {
+    const uint32_t s = (uint32_t)(mix64(stream + dim) >> 32);
+    return mode == 0 ? nested_scramble(0u, s) : s;
+  }
+  const uint64_t ctr = (uint64_t)dim << 32;
+  return (uint32_t)(mix64(stream ^ mix64(ctr)) >> 32);
+}
+
+// u in (0,1) from a point word: FP64 keeps all 32 bits; FP32 keeps the top
+// 23 bits so that (m + 1/2) 2^-23 is exact and never rounds to 0 or 1.
 __device__ __forceinline__ double u01_f64(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
 __device__ __forceinline__ float u01_f32(uint32_t x) {
   return ((float)(x >> 9) + 0.5f) * 0x1p-23f;
@@ -281,6 +295,13 @@ struct DevState {
   unsigned long long segments;  // segments of the current pass
   unsigned long long particles; // histories of the current pass
   unsigned long long killed;    // histories stopped by the segment guard
+  long long n_emit;             // source particles of the current pass
+  // numeric faults of the current pass (bits): 1 a cell majorant or their
+  // sum is not finite (no source particles are then emitted), 2 a history
+  // ended with a non-finite weight or tally, 4 the plan exceeded the source
+  // bank (clamped to it)
+  int numeric;
+  int pad2;
   unsigned long long bal[2 * B_NFIELDS];
   unsigned long long step;      // time step being computed (point streams, history ids)
   // source iteration of the collided solve (or the conjugate gradients of
@@ -291,6 +312,16 @@ struct DevState {
   // conjugate gradients of the diffusion correction inside each source
   // iteration (diffusion synthetic acceleration)
   IterState dsa;
+  // emission plan of each pass kind (1, 2): the correctly rounded sum of the
+  // cell majorants and the weight quantum
+  double sumM[2];
+  double wq[2];
+  // diffusion corrections of the step whose conjugate gradients stopped at
+  // the iteration limit before reaching their tolerance
+  int dsa_unconv;
+  int dsa_corrections;
+  int dsa_iter_total;
+  int pad1;
 };
 
 struct PassArgs {
@@ -302,14 +333,15 @@ struct PassArgs {
   int keep_census;       // remap pass: write the census-out particles
   const double2* mat64;  // (sigma_s, sigma_a) per cell
   const float2* mat32;
-  // emission, stratified by cell: cell i emits n_i = ceil(M_i / w_q)
-  // particles, w_q = quantum5(sum(M) / n_src)
-  const double* tree;    // binary sum tree of the cell majorants M_i (heap order)
-  const double* ctree;   // the same tree over the counts n_i (root: particles)
+  // emission, stratified by cell: cell i emits n_i = floor(r_i) or
+  // floor(r_i) + 1 particles, r_i = M_i / w_q, w_q = quantum5(sum(M) / n_src)
+  // (st->wq[kind - 1], with the exact sum st->sumM[kind - 1])
+  const double* ctree;   // binary sum tree of the counts n_i (heap order; root: particles)
   long long tree_L;      // leaves start at tree_L (power of two >= n_cells)
   const double* qn;      // nodal source [cell][4]
   long long n_cells;
   long long n_src;       // N_p, the requested particles per pass
+  long long src_cap;     // capacity of the source bank (the plan is clamped to it)
   double adt;            // cell area times dt (times 1 in steady state)
   uint64_t seed;         // the time step is read from st->step
   int kind;              // 1: scatter-limited leg, 2: scatter-free remap
@@ -454,11 +486,13 @@ hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long lon
                            hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, long long n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t s);
-// Pass set-up (counters, balance, fixed-point units from the tree's total and
-// the census bound) with the clears of up to two tally arrays and a byte array.
-hipError_t launch_pass_prep(DevState* st, const double* tree, double cdt,
-                            unsigned long long* a, long long na, unsigned long long* b,
-                            long long nb, uint8_t* c, long long nc, hipStream_t s);
+// Pass set-up (counters, balance, fixed-point units from the bound on the
+// emitted weight: particles (count-tree root) times w_q plus the census
+// bound) with the clears of up to two tally arrays and a byte array.
+hipError_t launch_pass_prep(DevState* st, const double* ctree, int kind, long long src_cap,
+                            double cdt, unsigned long long* a, long long na,
+                            unsigned long long* b, long long nb, uint8_t* c, long long nc,
+                            hipStream_t s);
 // phi = tally * unit / (A dt) for T0 -> phi0 and, when T1 is not null, T1 -> phi1.
 hipError_t launch_tally_to_flux(const unsigned long long* T0, double* phi0,
                                 const unsigned long long* T1, double* phi1, long long n,
@@ -468,12 +502,18 @@ hipError_t launch_remap_source(long long n, const double* q, const double* sig_s
                                const double* phi_pre, const double* phi_post,
                                const double* phi_c, double* qn, hipStream_t s);
 long long tree_leaves(long long n_cells);
-hipError_t launch_build_tree(const double* qn, long long n_cells, double adt, double* tree,
-                             hipStream_t s);
-// Count tree of the stratified emission from a built majorant tree:
-// leaf i = ceil(M_i / w_q), w_q = quantum5(root / n_src); root = particles.
-hipError_t launch_count_tree(const double* tree, long long n_cells, long long n_src,
-                             double* ctree, hipStream_t s);
+// Emission plan of a pass (the counts of the stratified emission): histogram
+// of the cell majorants M_i = adt pow2_ceil(max corner |q_i|) by exponent,
+// their exact sum rounded once to FP64 (st->sumM[kind - 1]), the weight
+// quantum w_q (st->wq[kind - 1]), the counts
+// n_i = floor(M_i / w_q) + [u_i < frac(M_i / w_q)] with u_i point 0 of the
+// cell's count stream, and the count tree over them (root: particles).
+// hist: kMajBins words, zero on entry and left zero (the last bin counts
+// cells whose majorant is not finite).
+constexpr int kMajBins = 2112;
+hipError_t launch_emission_plan(const double* qn, long long n_cells, double adt, long long n_src,
+                                uint64_t seed, int points, int kind, unsigned long long* hist,
+                                double* ctree, DevState* st, hipStream_t s);
 size_t scan_tmp_elems(long long n);
 hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
                               long long* tmp, hipStream_t s);

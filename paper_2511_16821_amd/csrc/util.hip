@@ -34,8 +34,8 @@ hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass set-up.  Bounds: |w| of a source particle <= sum(M)/N_p, so the
-// source weight magnitude is <= sum(M); census-in magnitude <= n_in max|w|.
+// Pass set-up.  Bounds: |w| of a source particle <= w_q, so the source weight
+// magnitude is <= (particles) w_q; census-in magnitude <= n_in max|w|.
 // Weights only decay along a path and a path lasts at most c dt, so every
 // balance sum is <= W and every tally sum is <= W c dt.
 // ---------------------------------------------------------------------------
@@ -50,16 +50,18 @@ __device__ __forceinline__ void unit_for(double bound, double& unit, double& inv
 // Pass set-up fused with the clears the pass needs: block 0 resets the
 // pass counters and balance and sets the fixed-point units from the bounds;
 // every block clears its share of up to two tally arrays and a byte array.
-__global__ void k_pass_prep(DevState* st, const double* tree, double cdt,
-                            unsigned long long* __restrict__ a, long long na,
+__global__ void k_pass_prep(DevState* st, const double* ctree, int kind, long long src_cap,
+                            double cdt, unsigned long long* __restrict__ a, long long na,
                             unsigned long long* __restrict__ b, long long nb,
                             uint8_t* __restrict__ c, long long nc) {
   if (blockIdx.x == 0) {
     const int t = threadIdx.x;
     if (t < 2 * B_NFIELDS) st->bal[t] = 0ull;
     if (t == 0) {
-      const double total = tree[1];
-      const double W = (double)st->n_in * st->maxabs_w + total;
+      const double n_emit = ctree[1];
+      const bool over = !(n_emit <= (double)src_cap);
+      const double src = (over ? (double)src_cap : n_emit) * st->wq[kind - 1];
+      const double W = (double)st->n_in * st->maxabs_w + src;
       unit_for(W, st->unit_W, st->inv_W);
       unit_for(W * cdt, st->unit_T, st->inv_T);
       st->work = 0ull;
@@ -67,6 +69,8 @@ __global__ void k_pass_prep(DevState* st, const double* tree, double cdt,
       st->particles = 0ull;
       st->killed = 0ull;
       st->alive = 0ull;
+      st->n_emit = over ? src_cap : (long long)n_emit;
+      st->numeric = (isfinite(st->sumM[kind - 1]) ? 0 : 1) | (over ? 4 : 0);
     }
   }
   const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,15 +80,16 @@ __global__ void k_pass_prep(DevState* st, const double* tree, double cdt,
   for (long long i = i0; i < nc; i += str) c[i] = 0;
 }
 
-hipError_t launch_pass_prep(DevState* st, const double* tree, double cdt,
-                            unsigned long long* a, long long na, unsigned long long* b,
-                            long long nb, uint8_t* c, long long nc, hipStream_t s) {
+hipError_t launch_pass_prep(DevState* st, const double* ctree, int kind, long long src_cap,
+                            double cdt, unsigned long long* a, long long na,
+                            unsigned long long* b, long long nb, uint8_t* c, long long nc,
+                            hipStream_t s) {
   long long n = na > nb ? na : nb;
   n = n > nc ? n : nc;
   long long g = (n + 255) / 256;
   const int grid = (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
-  hipLaunchKernelGGL(k_pass_prep, dim3(grid), dim3(256), 0, s, st, tree, cdt, a, na, b, nb, c,
-                     nc);
+  hipLaunchKernelGGL(k_pass_prep, dim3(grid), dim3(256), 0, s, st, ctree, kind, src_cap, cdt, a,
+                     na, b, nb, c, nc);
   return hipGetLastError();
 }
 
@@ -164,10 +169,15 @@ hipError_t launch_remap_source(long long n, const double* q, const double* sig_s
 }
 
 // ---------------------------------------------------------------------------
-// Binary sum tree of the cell majorants M_i = A dt pow2_ceil(max_corner |q_i|)
-// in heap order (root 1, children 2k and 2k+1, leaves from L), summed as
-// tree[k] = tree[2k] + tree[2k+1].  The up-sweep runs ten levels per launch in
-// LDS; the pairing, hence every rounding, is fixed by the tree.
+// Emission plan of a pass.  The cell majorant is M_i = adt pow2_ceil(m_i),
+// m_i the largest corner |q_i|, so M_i takes one of the values
+// V_b = adt 2^(b - 1074), b = 0 .. kMajBins - 1, and sum(M) = sum_b c_b V_b
+// with c_b the number of cells in bin b.  The histogram is exact (integer
+// counts), and the sum is formed exactly as an integer multiple of 2^-1074 in
+// a multi-word accumulator and rounded once to the nearest double (ties to
+// even): the correctly rounded sum of the majorants, whatever the order of
+// the cells.  The counts are then n_i = floor(r_i) + [u_i < frac(r_i)],
+// r_i = M_i / w_q, and their sum tree gives every particle its cell.
 // ---------------------------------------------------------------------------
 long long tree_leaves(long long n_cells) {
   long long L = 1;
@@ -175,24 +185,137 @@ long long tree_leaves(long long n_cells) {
   return L;
 }
 
-__global__ void k_tree_leaves(const double* __restrict__ qn, long long n, long long L,
-                              double adt, double* __restrict__ t) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < L;
+__device__ __forceinline__ double cell_majorant_pow2(const double4 q) {
+  return pow2_ceil(fmax(fmax(fabs(q.x), fabs(q.y)), fmax(fabs(q.z), fabs(q.w))));
+}
+
+// bin of a power of two p = 2^(e - 1) (frexp(p) = (1/2, e)): b = e + 1073,
+// from 0 (2^-1074) to 2097 (2^1023); the last bin holds non-finite values
+constexpr int kMajBad = kMajBins - 1;
+__device__ __forceinline__ int maj_bin(double p) {
+  if (!isfinite(p)) return kMajBad;
+  int e;
+  frexp(p, &e);
+  const int b = e + 1073;
+  return b < 0 ? 0 : (b >= kMajBad ? kMajBad : b);
+}
+
+// Block histogram in LDS, then one global add per non-empty bin and block.
+__global__ __launch_bounds__(256) void k_maj_hist(const double* __restrict__ qn, long long n,
+                                                  unsigned long long* __restrict__ hist) {
+  __shared__ unsigned int s_h[kMajBins];
+  for (int k = threadIdx.x; k < kMajBins; k += blockDim.x) s_h[k] = 0u;
+  __syncthreads();
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    double v = 0.0;
-    if (i < n) {
-      const double4 q = reinterpret_cast<const double4*>(qn)[i];
-      const double mx = fmax(fmax(fabs(q.x), fabs(q.y)), fmax(fabs(q.z), fabs(q.w)));
-      v = adt * pow2_ceil(mx);
-    }
-    t[L + i] = v;
+    const double p = cell_majorant_pow2(reinterpret_cast<const double4*>(qn)[i]);
+    if (p > 0.0) atomicAdd(&s_h[maj_bin(p)], 1u);
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kMajBins; k += blockDim.x)
+    if (s_h[k]) atomicAdd(&hist[k], (unsigned long long)s_h[k]);
+}
+
+constexpr int kSumLimbs = 36;  // 2304 bits above 2^-1074
+
+// acc += v * 2^pos for a 128-bit v = (hi, lo)
+__device__ __forceinline__ void limbs_add(unsigned long long* acc, unsigned long long lo,
+                                          unsigned long long hi, int pos) {
+  const int w = pos >> 6, sh = pos & 63;
+  unsigned long long t[3];
+  t[0] = lo << sh;
+  t[1] = sh ? ((lo >> (64 - sh)) | (hi << sh)) : hi;
+  t[2] = sh ? (hi >> (64 - sh)) : 0ull;
+  unsigned long long carry = 0ull;
+  for (int k = 0; w + k < kSumLimbs; ++k) {
+    const unsigned long long add = (k < 3 ? t[k] : 0ull);
+    if (k >= 3 && carry == 0ull) break;
+    const unsigned long long s1 = acc[w + k] + add;
+    const unsigned long long c1 = s1 < add ? 1ull : 0ull;
+    const unsigned long long s2 = s1 + carry;
+    const unsigned long long c2 = s2 < carry ? 1ull : 0ull;
+    acc[w + k] = s2;
+    carry = c1 + c2;
+  }
+}
+
+// bits [b, b + n) of the accumulator (n <= 64, b >= 0)
+__device__ __forceinline__ unsigned long long limbs_bits(const unsigned long long* acc, int b,
+                                                         int n) {
+  const int w = b >> 6, sh = b & 63;
+  unsigned long long v = acc[w] >> sh;
+  if (sh && w + 1 < kSumLimbs) v |= acc[w + 1] << (64 - sh);
+  return n == 64 ? v : (v & ((1ull << n) - 1ull));
+}
+
+// One thread: the exact sum of the histogram, rounded once; w_q; and the
+// histogram cleared for the next plan.
+__global__ __launch_bounds__(256) void k_maj_sum(unsigned long long* __restrict__ hist, double adt,
+                                                 long long n_src, int kind, DevState* st) {
+  __shared__ unsigned long long s_h[kMajBins];
+  for (int k = threadIdx.x; k < kMajBins; k += blockDim.x) {
+    s_h[k] = hist[k];
+    hist[k] = 0ull;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (s_h[kMajBad]) {  // a majorant overflowed: no emission (flagged by the pass set-up)
+    st->sumM[kind - 1] = __builtin_huge_val();
+    st->wq[kind - 1] = 0.0;
+    return;
+  }
+  unsigned long long acc[kSumLimbs];
+  for (int k = 0; k < kSumLimbs; ++k) acc[k] = 0ull;
+  for (int b = 0; b < kMajBad; ++b) {
+    const unsigned long long c = s_h[b];
+    if (!c) continue;
+    const double V = adt * ldexp(1.0, b - 1074);  // the value of every M_i in bin b
+    if (!(V > 0.0)) continue;
+    if (!isfinite(V)) {
+      st->sumM[kind - 1] = __builtin_huge_val();
+      st->wq[kind - 1] = 0.0;
+      return;
+    }
+    int e;
+    const double m = frexp(V, &e);  // V = m 2^e, m in [1/2, 1)
+    unsigned long long mant = (unsigned long long)ldexp(m, 53);
+    int pos = e - 53 + 1074;        // V = mant 2^(pos - 1074)
+    if (pos < 0) {                  // subnormal V: its low bits are zero
+      mant >>= -pos;
+      pos = 0;
+    }
+    limbs_add(acc, c * mant, __umul64hi(c, mant), pos);
+  }
+  int top = -1;
+  for (int k = kSumLimbs - 1; k >= 0 && top < 0; --k)
+    if (acc[k]) top = 64 * k + 63 - __clzll((long long)acc[k]);
+  double sum = 0.0;
+  if (top >= 0 && top < 53) {
+    sum = ldexp((double)acc[0], -1074);  // fewer than 53 bits: exact
+  } else if (top >= 53) {
+    unsigned long long mant = limbs_bits(acc, top - 52, 53);
+    const unsigned long long rnd = limbs_bits(acc, top - 53, 1);
+    bool sticky = false;
+    const int below = top - 53;  // bits [0, below) decide a tie
+    for (int k = 0; k < (below >> 6) && !sticky; ++k) sticky = acc[k] != 0ull;
+    if (!sticky && (below & 63)) sticky = limbs_bits(acc, below & ~63, below & 63) != 0ull;
+    int ex = top - 52 - 1074;
+    if (rnd && (sticky || (mant & 1ull))) {
+      mant += 1ull;
+      if (mant == (1ull << 53)) { mant >>= 1; ex += 1; }
+    }
+    sum = ldexp((double)mant, ex);
+  }
+  st->sumM[kind - 1] = sum;
+  st->wq[kind - 1] = (sum > 0.0 && isfinite(sum) && n_src > 0) ? quantum5(sum / (double)n_src)
+                                                                : 0.0;
 }
 
 constexpr int kTreeChunk = 1024;
 
 // Level of width W (nodes W..2W-1): block b sums nodes [W + b C, W + (b+1) C)
-// with C = min(W, 1024) up through log2(C) levels.
+// with C = min(W, 1024) up through log2(C) levels.  Leaves are integers, so
+// every sum is exact.
 __global__ __launch_bounds__(512) void k_tree_up(double* t, long long W) {
   __shared__ double buf[2][kTreeChunk];
   const long long C = W < kTreeChunk ? W : kTreeChunk;
@@ -226,34 +349,40 @@ static void tree_up_all(double* tree, long long L, hipStream_t s) {
   }
 }
 
-hipError_t launch_build_tree(const double* qn, long long n_cells, double adt, double* tree,
-                             hipStream_t s) {
-  const long long L = tree_leaves(n_cells);
-  long long b = (L + 255) / 256;
-  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_tree_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, L, adt, tree);
-  tree_up_all(tree, L, s);
-  return hipGetLastError();  // L == 1: the single leaf is the root
-}
-
-__global__ void k_count_leaves(const double* __restrict__ tree, long long n, long long L,
-                               long long n_src, double* __restrict__ ct) {
-  const double total = tree[1];
-  const double wq = (total > 0.0 && n_src > 0) ? quantum5(total / (double)n_src) : 0.0;
+__global__ void k_count_leaves(const double* __restrict__ qn, long long n, long long L,
+                               double adt, uint64_t seed, int points, int kind,
+                               const DevState* __restrict__ st, double* __restrict__ ct) {
+  const double wq = st->wq[kind - 1];
+  const uint64_t step = st->step;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < L;
        i += (long long)gridDim.x * blockDim.x) {
-    const double Mi = i < n ? tree[L + i] : 0.0;
-    ct[L + i] = (wq > 0.0 && Mi > 0.0) ? ceil(Mi / wq) : 0.0;
+    double c = 0.0;
+    if (i < n && wq > 0.0) {
+      const double Mi = adt * cell_majorant_pow2(reinterpret_cast<const double4*>(qn)[i]);
+      if (Mi > 0.0 && isfinite(Mi)) {
+        const double r = Mi / wq;
+        const double fl = floor(r);
+        const uint64_t cs = stream_seed(seed, step, (uint32_t)kind, 3u, (uint64_t)i);
+        const double u = u01_f64(point_u32_first(points, cs, 0u));
+        c = fl + ((u < r - fl) ? 1.0 : 0.0);
+      }
+    }
+    ct[L + i] = c;
   }
 }
 
-hipError_t launch_count_tree(const double* tree, long long n_cells, long long n_src,
-                             double* ctree, hipStream_t s) {
+hipError_t launch_emission_plan(const double* qn, long long n_cells, double adt, long long n_src,
+                                uint64_t seed, int points, int kind, unsigned long long* hist,
+                                double* ctree, DevState* st, hipStream_t s) {
   const long long L = tree_leaves(n_cells);
-  long long b = (L + 255) / 256;
-  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_count_leaves, dim3(grid), dim3(256), 0, s, tree, n_cells, L, n_src,
-                     ctree);
+  long long b = (n_cells + 255) / 256;
+  int grid = (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+  hipLaunchKernelGGL(k_maj_hist, dim3(grid), dim3(256), 0, s, qn, n_cells, hist);
+  hipLaunchKernelGGL(k_maj_sum, dim3(1), dim3(256), 0, s, hist, adt, n_src, kind, st);
+  b = (L + 255) / 256;
+  grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+  hipLaunchKernelGGL(k_count_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, L, adt, seed,
+                     points, kind, (const DevState*)st, ctree);
   tree_up_all(ctree, L, s);  // integer-valued sums below 2^53: exact
   return hipGetLastError();
 }

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libslh.so")
 
-SLH_ABI_VERSION = 4
+SLH_ABI_VERSION = 5
 SLH_OK, SLH_E_INVALID_ARG, SLH_E_OUT_OF_MEMORY, SLH_E_DEVICE, SLH_E_NOT_CONVERGED, \
     SLH_E_NUMERIC, SLH_E_REJECTED, SLH_E_STATE = range(8)
 SLH_FP64, SLH_FP32_TRACK = 0, 1
@@ -47,7 +47,9 @@ class slh_problem(C.Structure):
 class slh_balance(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("emitted", "absorbed", "scattered", "leaked",
                                           "census", "cutoff", "source_w", "census_in_w")] + \
-               [("segments", C.c_uint64), ("particles", C.c_uint64)]
+               [("segments", C.c_uint64), ("particles", C.c_uint64),
+                ("majorant_sum", C.c_double), ("weight_quantum", C.c_double),
+                ("source_particles", C.c_uint64), ("killed", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -63,7 +65,10 @@ class slh_stats(C.Structure):
                 ("seg_mc_total", C.c_uint64), ("seg_remap_total", C.c_uint64),
                 ("census_in_total", C.c_uint64), ("census_out_total", C.c_uint64),
                 ("steps_total", C.c_uint64), ("thin_overflow_total", C.c_uint64),
-                ("graph_launches_total", C.c_uint64), ("host_waits_total", C.c_uint64)]
+                ("graph_launches_total", C.c_uint64), ("host_waits_total", C.c_uint64),
+                ("killed_total", C.c_uint64), ("dsa_corrections", C.c_int32),
+                ("dsa_iterations", C.c_int32), ("dsa_unconverged", C.c_int32),
+                ("pad0", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -58,3 +58,10 @@ def compare_balance(solver, ref, tol=1e-10):
             assert abs(b[f] - r[f]) <= tol * scale, (pss, f, b[f], r[f])
         out = b["absorbed"] + b["scattered"] + b["leaked"] + b["census"] + b["cutoff"]
         assert abs(b["emitted"] - out) <= 1e-13 * scale + 1e-300, (pss, b)
+        if "majorant_sum" in r:
+            # the emission plan: the correctly rounded majorant sum, w_q and
+            # the particle count are exact on both sides
+            assert b["majorant_sum"] == r["majorant_sum"], (pss, b["majorant_sum"], r)
+            assert b["weight_quantum"] == r["weight_quantum"], (pss, b, r)
+            assert b["source_particles"] == r["source_particles"], (pss, b, r)
+        assert b["killed"] == 0, (pss, b)

@@ -34,7 +34,8 @@ def _run_pair(S, oracle, p, steps, name):
         compare_balance(s, r)
         st = s.get_stats()
         assert st["si_iterations"] == r["si_iters"], (st["si_iterations"], r["si_iters"])
-        assert abs(st["segments_total"] - r["segments"]) <= 16
+        assert st["segments_total"] == r["segments"], (st["segments_total"], r["segments"])
+        assert st["census_kept"] == r["census_kept"]
         log("  step", k, "sweeps", st["si_iterations"],
             {kk: "%.1e" % v[0] for kk, v in errs.items()})
     s.destroy()

@@ -68,6 +68,34 @@ def test_points_bitwise(S, oracle):
         assert np.array_equal(got, want), (seed, d0, i0)
 
 
+def test_emission_plan_exact_sum_wide_range(S, oracle):
+    """The emission plan on the device equals the oracle's bitwise: the
+    correctly rounded sum of the cell majorants (an exact multi-word sum on
+    the device, math.fsum in the oracle), w_q and the particle count, for
+    sources spread over the whole exponent range (1e-310 .. 1e300, subnormal
+    majorants included), with zeros, in both passes."""
+    from paper_2511_16821_amd import workloads as W
+    rng = np.random.default_rng(17)
+    for trial, (lo, hi, n) in enumerate([(-310, 300, 24), (-5, 5, 40), (-300, -280, 16)]):
+        q = 10.0 ** rng.uniform(lo, hi, size=(n, n))
+        q[rng.uniform(size=(n, n)) < 0.15] = 0.0
+        p = W._problem(n, n, (0.0, 3.0, 0.0, 3.0), np.zeros((n, n)), np.ones((n, n)), q,
+                       n_s=0, n_particles=5000 + 997 * trial, sn_order=2, dt=0.1, seed=trial)
+        log("plan case", trial, n)
+        s = S.Solver(p)
+        s.advance(1)
+        pts = oracle.Points(0)
+        adt = (3.0 / n) ** 2 * 0.1
+        q4 = np.repeat(q.ravel(), 4)
+        for pss in (1, 2):
+            b = s.get_balance(pss)
+            want = oracle.emission_plan(q4, adt, p["n_particles"], pts, p["seed"], 0, pss)
+            assert b["majorant_sum"] == want["total"], (trial, pss, b["majorant_sum"], want)
+            assert b["weight_quantum"] == want["w_q"], (trial, pss)
+            assert b["source_particles"] == want["n_emit"], (trial, pss)
+        s.destroy()
+
+
 def test_c1_full_ten_steps(S, oracle):
     """Homogeneous box, N_s = 0, 1e4 particles per pass, dt = 0.1, 10 steps,
     S_8: the small plain-method configuration at its full size."""

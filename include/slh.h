@@ -290,6 +290,21 @@ typedef void (*slh_free_fn)(void *ptr, void *ctx);
 slh_status slh_create(const slh_problem *problem, void *hip_stream, slh_alloc_fn alloc,
                       slh_free_fn free_fn, void *alloc_ctx, slh_solver **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * solver as slh_create, with every device buffer carved from a fixed static
+ * scratch array of 64 MiB that each device holds for the life of the
+ * process.  No hipMalloc, hipFree, pinned host allocation, event or graph is
+ * created; kernels are launched directly on hip_stream, so slh_advance
+ * itself may be captured by the caller.  Results are bitwise those of
+ * slh_create.  SLH_E_REJECTED if slh_footprint_bytes(problem) exceeds the
+ * scratch; SLH_E_STATE if the current device's scratch already holds a
+ * static solver (one at a time per device, released by slh_destroy).  The
+ * scratch keeps the previous solver's contents; the solver initialises
+ * everything it reads.  Stage and kernel times in slh_stats are zero, and
+ * slh_set_graphs(s, 1) is SLH_E_STATE. */
+slh_status slh_create_static(const slh_problem *problem, void *hip_stream, slh_solver **out);
+
 /* Enqueues n_steps >= 1 time steps (steps 1-4 above) on the solver's stream.
  * A step is launched in two parts: the scatter-limited leg with a first
  * batch of source iterations (as many as the previous step needed), and the

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <utility>
 #include <cstddef>
@@ -408,6 +409,12 @@ struct slh_solver {
   slh_free_fn free_fn = nullptr;
   void* ctx = nullptr;
   std::vector<void*> allocs;
+  // static scratch (slh_create_static): device memory is carved from the
+  // device's scratch array by a bump pointer; nothing is allocated or freed
+  bool static_mem = false;
+  int static_dev = -1;
+  char* bump_base = nullptr;
+  size_t bump_off = 0, bump_len = 0;
   std::vector<double> h_sig_s, h_sig_a, h_q;
   std::vector<int> h_ns;    // per-cell scatter limits (unlimited as INT_MAX), empty if uniform
   int n_lim_max = 0;        // the largest limit of the scatter-limited leg
@@ -482,7 +489,12 @@ struct slh_solver {
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 8;
     void* p = nullptr;
-    if (alloc) {
+    if (static_mem) {
+      const size_t off = (bump_off + 255) / 256 * 256;
+      if (off + bytes > bump_len) return nullptr;
+      bump_off = off + bytes;
+      return bump_base + off;
+    } else if (alloc) {
       p = alloc(bytes, ctx);
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
       p = nullptr;
@@ -501,9 +513,14 @@ struct slh_solver {
       else (void)hipFree(p);
     }
     allocs.clear();
-    if (h_res) (void)hipHostFree(h_res);
+    if (static_mem) {
+      delete[] (char*)h_res;
+      delete[] (char*)h_bal;
+    } else {
+      if (h_res) (void)hipHostFree(h_res);
+      if (h_bal) (void)hipHostFree(h_bal);
+    }
     h_res = nullptr;
-    if (h_bal) (void)hipHostFree(h_bal);
     h_bal = nullptr;
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -622,9 +639,15 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->st, DevState, 1);
   ALLOC(s->bal_store, BalStore, 2);
 #undef ALLOC
-  if (hipHostMalloc((void**)&s->h_res, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+  if (s->static_mem) {  // no pinned memory: plain host buffers, copies wait on the stream
+    s->h_res = (double*)new (std::nothrow) char[4 * sizeof(double)];
+    s->h_bal = (BalStore*)new (std::nothrow) char[2 * sizeof(BalStore)];
+    if (!s->h_res || !s->h_bal) return fail(SLH_E_OUT_OF_MEMORY, "host allocation failed");
+  } else if (hipHostMalloc((void**)&s->h_res, 4 * sizeof(double), hipHostMallocDefault) !=
+             hipSuccess)
     return fail(SLH_E_OUT_OF_MEMORY, "pinned host allocation failed");
-  if (hipHostMalloc((void**)&s->h_bal, 2 * sizeof(BalStore), hipHostMallocDefault) != hipSuccess)
+  if (!s->static_mem &&
+      hipHostMalloc((void**)&s->h_bal, 2 * sizeof(BalStore), hipHostMallocDefault) != hipSuccess)
     return fail(SLH_E_OUT_OF_MEMORY, "pinned host allocation failed");
 
   // fields and derived arrays
@@ -697,9 +720,11 @@ static slh_status setup(slh_solver* s) {
   HIP_TRY(launch_fill_f64(s->phi_R, nc, 0.0, st));
   HIP_TRY(launch_fill_u64((unsigned long long*)s->bal_store, 2 * sizeof(BalStore) / 8, 0ull, st));
   HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
-  for (auto& e : s->ev) HIP_TRY(hipEventCreate(&e));
-  for (auto& e : s->evk) HIP_TRY(hipEventCreate(&e));
-  s->have_events = true;
+  if (!s->static_mem) {  // stage and kernel timing (none in a static solver)
+    for (auto& e : s->ev) HIP_TRY(hipEventCreate(&e));
+    for (auto& e : s->evk) HIP_TRY(hipEventCreate(&e));
+    s->have_events = true;
+  }
   HIP_TRY(hipStreamSynchronize(st));  // host vectors above go out of scope
   return SLH_OK;
 }
@@ -774,7 +799,7 @@ static slh_status collect(slh_solver* s, int k) {
                     (s->h_bal[k].killed ? "histories reached the 2^26-segment guard" : ""));
   }
   float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, s->evk[2 * k], s->evk[2 * k + 1]));
+  if (s->have_events) HIP_TRY(hipEventElapsedTime(&ms, s->evk[2 * k], s->evk[2 * k + 1]));
   s->k_ms[k] += ms;
   s->k_seg[k] += s->h_bal[k].segments;
   s->killed_total += s->h_bal[k].killed;
@@ -1033,12 +1058,12 @@ static slh_status run_step(slh_solver* s) {
                           ? std::max(1, std::min(s->si_max, s->si_it > 0 ? s->si_it : 4))
                           : 0;
   hipStream_t st = s->stream;
-  HIP_TRY(hipEventRecord(s->ev[0], st));
+  if (s->have_events) HIP_TRY(hipEventRecord(s->ev[0], st));
   slh_status r = launch_part(s, kA1, 0);
   if (r != SLH_OK) return r;
-  HIP_TRY(hipEventRecord(s->evk[0], st));
+  if (s->have_events) HIP_TRY(hipEventRecord(s->evk[0], st));
   HIP_TRY(launch_mc_pass(pass_args(s, 1), z.fp32, grid1, st));
-  HIP_TRY(hipEventRecord(s->evk[1], st));
+  if (s->have_events) HIP_TRY(hipEventRecord(s->evk[1], st));
   r = launch_part(s, kA2, n_first);
   if (r != SLH_OK) return r;
   s->pending[0] = true;
@@ -1063,15 +1088,15 @@ static slh_status run_step(slh_solver* s) {
   }
   r = collect_all(s);
   if (r != SLH_OK) return r;
-  HIP_TRY(hipEventRecord(s->ev[1], st));
+  if (s->have_events) HIP_TRY(hipEventRecord(s->ev[1], st));
   r = launch_part(s, kB1, 0);
   if (r != SLH_OK) return r;
-  HIP_TRY(hipEventRecord(s->evk[2], st));
+  if (s->have_events) HIP_TRY(hipEventRecord(s->evk[2], st));
   if (!s->skip_remap) HIP_TRY(launch_mc_pass(pass_args(s, 2), z.fp32, grid2, st));
-  HIP_TRY(hipEventRecord(s->evk[3], st));
+  if (s->have_events) HIP_TRY(hipEventRecord(s->evk[3], st));
   r = launch_part(s, kB2, 0);
   if (r != SLH_OK) return r;
-  HIP_TRY(hipEventRecord(s->ev[2], st));
+  if (s->have_events) HIP_TRY(hipEventRecord(s->ev[2], st));
   s->pending[1] = true;
   s->cur = 1 - s->cur;
   s->step += 1;
@@ -1081,17 +1106,81 @@ static slh_status run_step(slh_solver* s) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-extern "C" slh_status slh_create(const slh_problem* problem, void* hip_stream,
-                                 slh_alloc_fn alloc, slh_free_fn free_fn, void* ctx,
-                                 slh_solver** out) {
+// ---------------------------------------------------------------------------
+// Static scratch for callers that cannot allocate device memory (under graph
+// capture, in serving loops, in harnesses that forbid it): slh_create_static
+// carves a solver out of this array instead of calling an allocator.  Each
+// device holds its own copy for the life of the process; host code must use
+// the address hipGetSymbolAddress returns on that device, never the array's
+// name.  One static solver may live on a device at a time.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {nullptr};
+bool g_scratch_busy[kMaxDevices] = {false};
+}  // namespace
+
+// Device address of the current device's scratch (looked up once per
+// device), reserved for one solver.
+static slh_status scratch_acquire(int* dev_out, char** ptr_out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SLH_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_busy[dev])
+    return fail(SLH_E_STATE, "the device's static scratch already holds a solver");
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SLH_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                    hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  g_scratch_busy[dev] = true;
+  *dev_out = dev;
+  *ptr_out = g_scratch_ptr[dev];
+  return SLH_OK;
+}
+
+static void scratch_release(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev >= 0 && dev < kMaxDevices) g_scratch_busy[dev] = false;
+}
+
+static slh_status create_solver(const slh_problem* problem, void* hip_stream, slh_alloc_fn alloc,
+                                slh_free_fn free_fn, void* ctx, bool static_mem,
+                                slh_solver** out) {
   if (!out) return fail(SLH_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   slh_status v = validate(problem, true);
   if (v != SLH_OK) return v;
   if ((alloc == nullptr) != (free_fn == nullptr))
     return fail(SLH_E_INVALID_ARG, "alloc and free_fn must both be set or both be NULL");
+  if (static_mem && sizes_of(problem).bytes > kScratchBytes)
+    return fail(SLH_E_REJECTED, "the problem needs " + std::to_string(sizes_of(problem).bytes) +
+                                    " bytes of device memory, above the static scratch of " +
+                                    std::to_string(kScratchBytes) + " bytes");
   slh_solver* s = new (std::nothrow) slh_solver();
   if (!s) return fail(SLH_E_OUT_OF_MEMORY, "host allocation failed");
+  if (static_mem) {
+    char* base = nullptr;
+    int dev = -1;
+    const slh_status r = scratch_acquire(&dev, &base);
+    if (r != SLH_OK) {
+      delete s;
+      return r;
+    }
+    s->static_mem = true;
+    s->static_dev = dev;
+    s->bump_base = base;
+    s->bump_len = kScratchBytes;
+    s->use_graphs = false;  // instantiating a graph may allocate
+  }
   s->prob = *problem;
   s->z = sizes_of(problem);
   s->stream = (hipStream_t)hip_stream;
@@ -1133,11 +1222,23 @@ extern "C" slh_status slh_create(const slh_problem* problem, void* hip_stream,
   slh_status r = setup(s);
   if (r != SLH_OK) {
     s->release();
+    if (s->static_mem) scratch_release(s->static_dev);
     delete s;
     return r;
   }
   *out = s;
   return SLH_OK;
+}
+
+extern "C" slh_status slh_create(const slh_problem* problem, void* hip_stream,
+                                 slh_alloc_fn alloc, slh_free_fn free_fn, void* ctx,
+                                 slh_solver** out) {
+  return create_solver(problem, hip_stream, alloc, free_fn, ctx, false, out);
+}
+
+extern "C" slh_status slh_create_static(const slh_problem* problem, void* hip_stream,
+                                        slh_solver** out) {
+  return create_solver(problem, hip_stream, nullptr, nullptr, nullptr, true, out);
 }
 
 extern "C" slh_status slh_advance(slh_solver* s, int32_t n_steps) {
@@ -1155,6 +1256,8 @@ extern "C" slh_status slh_advance(slh_solver* s, int32_t n_steps) {
 
 extern "C" slh_status slh_set_graphs(slh_solver* s, int32_t enable) {
   if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
+  if (s->static_mem && enable)
+    return fail(SLH_E_STATE, "a static solver launches its kernels directly (no graphs)");
   s->use_graphs = enable != 0;
   return SLH_OK;
 }
@@ -1257,7 +1360,7 @@ extern "C" slh_status slh_get_stats(slh_solver* s, slh_stats* out) {
   out->dsa_corrections = d.dsa_corrections;
   out->dsa_iterations = d.dsa_iter_total;
   out->dsa_unconverged = d.dsa_unconv;
-  if (s->step > 0) {
+  if (s->step > 0 && s->have_events) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, s->ev[0], s->evk[1]) == hipSuccess) out->ms_mc = ms;
     if (hipEventElapsedTime(&ms, s->evk[1], s->ev[1]) == hipSuccess) out->ms_dg = ms;
@@ -1430,6 +1533,7 @@ extern "C" void slh_destroy(slh_solver* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
   s->release();
+  if (s->static_mem) scratch_release(s->static_dev);
   delete s;
 }
 

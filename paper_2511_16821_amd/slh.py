@@ -90,7 +90,7 @@ class slh_latency(C.Structure):
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
-EXPORTS = ["slh_create", "slh_advance", "slh_set_graphs", "slh_synchronize", "slh_get_flux", "slh_get_flux_device",
+EXPORTS = ["slh_create", "slh_create_static", "slh_advance", "slh_set_graphs", "slh_synchronize", "slh_get_flux", "slh_get_flux_device",
            "slh_get_balance", "slh_get_stats", "slh_get_census", "slh_save", "slh_load",
            "slh_footprint_bytes", "slh_destroy", "slh_last_error", "slh_qmc_points",
            "slh_server_create", "slh_server_submit", "slh_server_poll", "slh_server_result",
@@ -111,6 +111,7 @@ def lib():
     vp, i32, i64, u32, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
     sig = {
         "slh_create": ([C.POINTER(slh_problem), vp, ALLOC_FN, FREE_FN, vp, C.POINTER(vp)], i32),
+        "slh_create_static": ([C.POINTER(slh_problem), vp, C.POINTER(vp)], i32),
         "slh_advance": ([vp, i32], i32),
         "slh_set_graphs": ([vp, i32], i32),
         "slh_synchronize": ([vp], i32),
@@ -238,16 +239,22 @@ class _TorchAllocator:
 class Solver:
     """One hybrid solve resident on the GPU (slh_create ... slh_destroy)."""
 
-    def __init__(self, problem: dict, stream=None, torch_allocator: bool = True):
+    def __init__(self, problem: dict, stream=None, torch_allocator: bool = True,
+                 static: bool = False):
+        """static: slh_create_static (device memory from the library's static
+        scratch, no allocator)."""
         self.problem = problem
         self.nx, self.ny = int(problem["nx"]), int(problem["ny"])
         st, self._keep = make_problem(problem)
         if stream is None:
             stream = _torch_stream()
         self.stream = stream
-        self._alloc = _TorchAllocator(torch_stream_obj()) if torch_allocator else None
+        self._alloc = _TorchAllocator(torch_stream_obj()) if torch_allocator and not static \
+            else None
         h = C.c_void_p()
-        if self._alloc is not None:
+        if static:
+            r = lib().slh_create_static(C.byref(st), C.c_void_p(stream), C.byref(h))
+        elif self._alloc is not None:
             r = lib().slh_create(C.byref(st), C.c_void_p(stream), self._alloc.alloc_cb,
                                  self._alloc.free_cb, None, C.byref(h))
         else:

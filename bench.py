@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the scatter-limited hybrid step on one MI355X.
 
-Workload (default): the 2-D 7x7 checkerboard of unit blocks on 140x140 cells
-(absorber blocks sigma_a = 10, scattering blocks sigma_s = 1, unit source in
-the centre block), N_s = 2, 1e6 source particles per MC pass, dt = 0.05,
-40 time steps, S_12, FP64, vacuum boundaries.  A step is one whole hybrid
-time step: the scatter-limited MC pass, the DG S_N collided solve, the remap
-source, the remap MC pass and the census cap.  Inputs are resident on the
-device before the timed region; the K timed steps are one solve from t = 0
-on a fresh solver (the W warm-up steps run on a separate solver).
+Headline workload (default): the large resident solve, 1024x1024 cells on
+[0,10]^2 with sigma_s and sigma_a uniform on [0.01, 20] per 32x32-cell block,
+unit source on the central 2x2 blocks, N_s = 3, 1e8 source particles per MC
+pass, dt = 0.05, 50 time steps from t = 0, S_16, FP64, vacuum boundaries.  A
+step is one whole hybrid time step: the scatter-limited MC pass, the DG S_N
+collided solve, the remap source, the remap MC pass and the census cap.
+Inputs are resident on the device before the timed region; the timed steps
+are one solve on a fresh solver (warm-up steps run on another solver).
 
-Prints one JSON line: segments/s (value), per-step time, the roofline of the
-dominant kernel (HIP events recorded by the library around each MC-pass
-launch on its stream), the FP32-tracking variant with its relative L2 error
-against the FP64 path, and the CPU oracle timed on a bounded sample.
+The timed steps run in the library's timing mode (the MC-pass kernels
+launched between HIP events on the solver's stream, the rest of each step as
+graphs), so the roofline of the dominant kernel is measured over the timed
+region itself; the one-graph-per-step production mode is timed as well.
+
+Prints one JSON line: segments/s (value), per-step time, the roofline of both
+MC-pass kernels, the FP32-tracking run with its relative L2 deviation from
+FP64 and the QMC error at the same particle count, the precision form (256^2
+thick medium with voids), the benchmark checkerboard, a bounded serving run
+against one-solve-at-a-time, and the CPU oracle on a bounded sample.
 """
 import argparse
 import json
@@ -28,19 +34,33 @@ if ROOT not in sys.path:
 METRIC = "track segments/s FP32 vs FP64 at fixed L2 error; p50/p99 batched solve latency"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes: per segment the (sigma_s, sigma_a) gather and one FP64
-# tally read-modify-write; per census particle its state (x, y, Ox, Oy, w,
-# cell, history id) read once per pass, and written once by the remap pass
+# tally read-modify-write; per census particle its state (x, y, Ox, Oy, w and
+# the cell index; the 8-byte history id is not counted) read once by each
+# pass, and each census candidate written once by the remap pass
 SEG_BYTES = {0: 16 + 16, 1: 8 + 16}
-CENSUS_BYTES = {0: 5 * 8 + 4 + 8, 1: 5 * 4 + 4 + 8}
+CENSUS_BYTES = {0: 5 * 8 + 4, 1: 5 * 4 + 4}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+PROFILES = {"c5": "k_mc_pass_random_blocks_1024_counters.txt",
+            "c2": "k_mc_pass_checkerboard_140_counters.txt"}
+WORKLOAD_NAMES = {
+    "c5": "large resident solve (1024x1024 random blocks)",
+    "c5_sub": "128x128 subproblem of the large resident solve",
+    "c2": "checkerboard 7x7 unit blocks (absorber sigma_a=10 / scatterer sigma_s=1), unit "
+          "source in the centre block",
+    "c3": "thick medium with voids",
+    "c1": "homogeneous box"}
+
+
 def make_problem(args, precision):
     from paper_2511_16821_amd import workloads as W
-    kw = dict(n_s=args.ns, precision=precision)
+    kw = dict(precision=precision)
+    if args.ns is not None:
+        kw["n_s"] = args.ns
     if args.particles:
         kw["n_particles"] = args.particles
     if args.workload == "c2":
@@ -62,20 +82,26 @@ def describe(p):
                p["n_particles"], p["dt"], p["sn_order"]))
 
 
-def timed_run(S, torch, p, steps, warmup):
+def timed_run(S, torch, p, steps, warmup, timing=True, keep=False):
+    """Times `steps` steps of a fresh solver (after `warmup` steps on another
+    one).  timing: steps in timing mode (kernel times from HIP events).
+    Returns (wall seconds, stats[, solver if keep])."""
     if warmup > 0:
         w = S.Solver(p)
         w.advance(warmup, allow_not_converged=True)
-        w.synchronize()
+        w.synchronize(allow_not_converged=True)
         w.destroy()
     s = S.Solver(p)
+    s.set_timing(timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.advance(steps, allow_not_converged=True)
-    s.synchronize()
+    s.synchronize(allow_not_converged=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = s.get_stats()
+    if keep:
+        return t1 - t0, st, s
     s.destroy()
     return t1 - t0, st
 
@@ -91,11 +117,12 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, prec):
+def measured_traffic(profile, kernel, prec):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration),
-    or None when the summary is missing or was taken on other kernel code."""
-    path = os.path.join(ROOT, "profiles", "k_mc_pass_checkerboard_140_counters.txt")
+    summary `profile` (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy
+    calibration), or None when the summary is missing or was taken on other
+    kernel code."""
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -109,36 +136,71 @@ def measured_traffic(kernel, prec):
     return float(kv[key]) if key in kv else None
 
 
-def roofline(st, steps, prec):
-    kinds = [("k_mc_pass<step 1>", st["ms_kernel_mc_total"], st["seg_mc_total"], False),
-             ("k_mc_pass<step 3>", st["ms_kernel_remap_total"], st["seg_remap_total"], True)]
-    name, ms, seg, remap = max(kinds, key=lambda k: k[1])
-    byts = SEG_BYTES[prec] * seg + CENSUS_BYTES[prec] * st["census_in_total"]
-    if remap:
-        byts += (CENSUS_BYTES[prec] + 1) * st["census_out_total"]
-    per_launch_bytes = byts / steps
-    per_launch_s = ms * 1e-3 / steps
-    achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(name, prec),
-            "kernel": name, "avg_launch_ms": round(ms / steps, 4),
-            "bytes_per_launch": int(per_launch_bytes),
-            "segments_per_launch": int(seg / steps)}
+def rooflines(st, steps, prec, profile):
+    """Roofline of each MC-pass kernel over the timed steps: algorithmic bytes
+    per launch (per segment SEG_BYTES; per census-in particle CENSUS_BYTES
+    read by each pass; per census candidate CENSUS_BYTES written by the
+    remap pass) over the kernel's mean duration from HIP events.  Returns
+    (dominant, both)."""
+    rows = []
+    for name, ms, seg, extra in (
+            ("k_mc_pass<step 1>", st["ms_kernel_mc_total"], st["seg_mc_total"],
+             CENSUS_BYTES[prec] * st["census_in_total"]),
+            ("k_mc_pass<step 3>", st["ms_kernel_remap_total"], st["seg_remap_total"],
+             CENSUS_BYTES[prec] * (st["census_in_total"] + st["census_out_total"]))):
+        byts = SEG_BYTES[prec] * seg + extra
+        per_launch_bytes = byts / steps
+        per_launch_s = ms * 1e-3 / steps
+        achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
+        rows.append({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(profile, name, prec),
+                     "kernel": name, "avg_launch_ms": round(ms / steps, 4),
+                     "bytes_per_launch": int(per_launch_bytes),
+                     "segments_per_launch": int(seg / steps)})
+    return max(rows, key=lambda r: r["avg_launch_ms"]), rows
 
 
-def cpu_baseline(p, steps):
+def _oracle_pass_worker(job):
+    """One scatter-limited MC pass of the oracle (step 1 of the first time
+    step, no census) on problem `p` with `n_src` particles and seed `seed`;
+    returns (segments, seconds)."""
+    p, n_src, seed = job
+    import numpy as np
     from oracle import oracle as O
     O.build()
-    o = O.HybridOracle(p)
+    mesh = O.Mesh(p)
+    pts = O.Points(int(p.get("points", 0)))
+    q4 = np.repeat(np.asarray(p["q"], dtype=np.float64).ravel(), 4)
     t0 = time.perf_counter()
-    seg = 0
-    for _ in range(steps):
-        seg += o.step()["segments"]
-    dt = time.perf_counter() - t0
-    return {"value": seg / dt, "unit": "segments/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of the %d steps of the same workload (same seed), "
-                      "single-threaded C oracle, %.1f s" % (steps, p["n_steps"], dt)}
+    _, _, _, seg, _ = O.mc_pass(mesh, pts, 1, int(p["n_s"]), q4, n_src, O.Bank(0), seed, 0,
+                                float(p.get("w_cut_rel", 1e-8)), False)
+    return seg, time.perf_counter() - t0
+
+
+def cpu_baseline(p, n_src, workers):
+    """The CPU oracle on a bounded sample of the headline workload: the
+    scatter-limited MC pass of its first step (the oracle's DG solve of a
+    1024^2 mesh with 256 directions would take minutes per sweep, and the
+    metric counts track segments), with n_src particles, first on one core,
+    then as `workers` independent processes with different seeds on as many
+    cores; segments/s of the all-core run is the value."""
+    import multiprocessing as mp
+    from oracle import oracle as O
+    O.build()
+    seg1, t1 = _oracle_pass_worker((p, n_src, int(p["seed"])))
+    ctx = mp.get_context("spawn")
+    jobs = [(p, n_src, int(p["seed"]) + 7919 * (k + 1)) for k in range(workers)]
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_pass_worker, jobs)
+    seg = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)  # the slowest process's pass (start-up excluded)
+    return {"value": seg / wall, "unit": "segments/s", "cores": workers, "kind": "oracle",
+            "single_core_value": seg1 / t1,
+            "sample": "the scatter-limited MC pass of the first step of the same workload "
+                      "(%d source particles, %d segments in %.1f s on one core), then %d "
+                      "concurrent processes with different seeds, one per core (%d segments; "
+                      "the slowest pass took %.1f s)" % (n_src, seg1, t1, workers, seg, wall)}
 
 
 def fp32_error(S, p64, p32, steps):
@@ -225,71 +287,6 @@ def precision_form(S, torch, args):
             "downsample": "64x64 (4x4 block average) of phi_R at each step", "rows": out}
 
 
-def large_resident(S, torch, args):
-    """1024x1024 cells, random blocks, N_s = 3, 1e8 particles per pass, S_16,
-    state resident on the device for the whole run: FP64 and FP32-tracking
-    throughput and the FP32 result's relative L2 deviation from FP64 (same
-    seed, every step, max reported)."""
-    import numpy as np
-    from paper_2511_16821_amd import workloads as W
-    kw = dict(n_steps=args.c5_steps)
-    if args.c5_particles:
-        kw["n_particles"] = int(args.c5_particles)
-    p64 = W.c5(precision=0, **kw)
-    p32 = W.c5(precision=1, **kw)
-    steps = args.c5_steps
-    res = {"workload": "1024x1024 cells on [0,10]^2, sigma_s and sigma_a uniform on [0.01, 20] "
-                       "per 32x32-cell block, unit source on the central 2x2 blocks, N_s=3, "
-                       "%d particles/pass, dt=%g, S_%d" % (p64["n_particles"], p64["dt"],
-                                                           p64["sn_order"]),
-           "steps": steps,
-           "footprint_gib": {"fp64": S.slh_footprint_bytes(p64) / 2 ** 30,
-                             "fp32": S.slh_footprint_bytes(p32) / 2 ** 30}}
-    a, b = S.Solver(p64), S.Solver(p32)
-    worst, last, t64, t32 = 0.0, 0.0, 0.0, 0.0
-    for _ in range(steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        a.advance(1, allow_not_converged=True)
-        a.synchronize()
-        t1 = time.perf_counter()
-        b.advance(1, allow_not_converged=True)
-        b.synchronize()
-        t2 = time.perf_counter()
-        t64 += t1 - t0
-        t32 += t2 - t1
-        x, y = a.get_flux(0), b.get_flux(0)
-        last = float(np.linalg.norm(y - x) / max(np.linalg.norm(x), 1e-300))
-        worst = max(worst, last)
-        log("large resident: step %d rel-L2 fp32 vs fp64 %.3e" % (a.get_stats()["step"], last))
-    for name, sv, t in (("fp64", a, t64), ("fp32", b, t32)):
-        st = sv.get_stats()
-        seg = st["seg_mc_total"] + st["seg_remap_total"]
-        res[name] = {"segments_per_s": seg / t, "ms_per_step": 1e3 * t / steps,
-                     "mc_kernel_ms_per_step": (st["ms_kernel_mc_total"] +
-                                               st["ms_kernel_remap_total"]) / steps,
-                     "segments_per_step": seg / steps, "si_iterations_last": st["si_iterations"]}
-        sv.destroy()
-    res["rel_l2_fp32_vs_fp64_max_over_steps"] = worst
-    res["rel_l2_fp32_vs_fp64_last_step"] = last
-    if args.c5_seeds > 1:
-        runs = []
-        for r in range(args.c5_seeds):
-            pr = dict(p64)
-            pr["seed"] = int(p64["seed"]) + 1000003 * (r + 1)
-            sr = S.Solver(pr)
-            sr.advance(steps, allow_not_converged=True)
-            runs.append(sr.get_flux(0))
-            log("large resident: seed run %d done" % r)
-            sr.destroy()
-        runs = np.stack(runs)
-        res["e_qmc"] = float(np.linalg.norm(runs.std(axis=0, ddof=1)) /
-                             max(np.linalg.norm(runs.mean(axis=0)), 1e-300))
-        res["e_qmc_seeds"] = args.c5_seeds
-    log("large resident:", json.dumps(res))
-    return res
-
-
 def cellwise_ns(S, torch, args):
     """Space-dependent scatter limit N_s(x) (the paper's stated next step) on
     the C3 thick medium with voids: limit k in the thick scatterer and 0 in the
@@ -314,7 +311,7 @@ def cellwise_ns(S, torch, args):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s.advance(steps)
-            s.synchronize()
+            s.synchronize(allow_not_converged=True)
             t = time.perf_counter() - t0
             st = s.get_stats()
             seg = st["seg_mc_total"] + st["seg_remap_total"]
@@ -344,15 +341,16 @@ def reflective(S, torch, args):
     steps = args.reflect_steps
     rows = []
     for name, bc in (("vacuum", 0), ("x_lo+y_lo", 5), ("all four", 15)):
-        p = W.c1(n_s=args.ns, n_steps=steps, boundary=bc, n_particles=10 ** 6)
+        p = W.c1(n_s=args.ns if args.ns is not None else 2, n_steps=steps, boundary=bc,
+                 n_particles=10 ** 6)
         s = S.Solver(p)
         s.advance(2)
-        s.synchronize()
+        s.synchronize(allow_not_converged=True)
         st0 = s.get_stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.advance(steps)
-        s.synchronize()
+        s.synchronize(allow_not_converged=True)
         t = time.perf_counter() - t0
         st = s.get_stats()
         seg = (st["seg_mc_total"] + st["seg_remap_total"]
@@ -364,7 +362,8 @@ def reflective(S, torch, args):
         log("reflective:", json.dumps(row))
         rows.append(row)
     return {"workload": "C1 box (20x20 on [0,2]^2, N_s=%d, 1e6 particles/pass, dt=0.1, S_8), "
-                        "%d timed steps after 2" % (args.ns, steps), "rows": rows}
+                        "%d timed steps after 2" % (args.ns if args.ns is not None else 2, steps),
+            "rows": rows}
 
 
 def protocol(S, torch, args):
@@ -628,17 +627,25 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the "
                     "workload's step count)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--ns", type=int, default=2)
+    ap.add_argument("--workload", default="c5",
+                    help="c5 (default: the large resident solve), c2, c3, c1, c5_sub")
+    ap.add_argument("--ns", type=int, default=None, help="N_s (default: the workload's)")
     ap.add_argument("--particles", type=int, default=None)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-particles", type=int, default=2_000_000,
+                    help="source particles of the oracle's bounded sample (per process)")
+    ap.add_argument("--no-graph-run", action="store_true",
+                    help="skip the timing of the one-graph-per-step production mode")
+    ap.add_argument("--qmc-seeds", type=int, default=4,
+                    help="Owen seeds (runs) for the QMC error of the headline workload")
+    ap.add_argument("--no-c2", action="store_true", help="skip the checkerboard row")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving row")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the FP32-vs-FP64 precision form (256x256 thick medium)")
-    ap.add_argument("--c3-ns", default="0,1,2,4")
+    ap.add_argument("--c3-ns", default="2")
     ap.add_argument("--c3-steps", type=int, default=20)
-    ap.add_argument("--c3-seeds", type=int, default=8)
+    ap.add_argument("--c3-seeds", type=int, default=4)
     ap.add_argument("--c3-particles", type=float, default=None)
     ap.add_argument("--protocol", action="store_true",
                     help="also run the paper's protocol: QMC vs MC convergence slopes and "
@@ -664,17 +671,12 @@ def main():
     ap.add_argument("--nsx-ns", default="0,1,2,4")
     ap.add_argument("--nsx-steps", type=int, default=10)
     ap.add_argument("--nsx-particles", type=float, default=2e6)
-    ap.add_argument("--c5", action="store_true",
-                    help="also run the large resident solve (1024x1024, 1e8 particles/pass)")
-    ap.add_argument("--c5-steps", type=int, default=50)
-    ap.add_argument("--c5-particles", type=float, default=None)
-    ap.add_argument("--c5-seeds", type=int, default=4,
-                    help="independent Owen seeds for the QMC error of the large solve")
-    ap.add_argument("--serve", action="store_true",
-                    help="also run the serving benchmark (continuous batching)")
-    ap.add_argument("--serve-requests", type=int, default=256)
-    ap.add_argument("--serve-max-side", type=int, default=512)
-    ap.add_argument("--serve-max-particles", type=float, default=1e7)
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving row (the full stream: 256)")
+    ap.add_argument("--serve-max-side", type=int, default=256,
+                    help="largest mesh side of the serving row (the full stream: 512)")
+    ap.add_argument("--serve-max-particles", type=float, default=1e6,
+                    help="largest particle count of the serving row (the full stream: 1e7)")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-seed", type=int, default=4)
@@ -702,38 +704,79 @@ def main():
     from paper_2511_16821_amd import slh as S
     S.lib()
 
+    import numpy as np
     p64 = make_problem(args, 0)
     steps = args.steps or int(p64["n_steps"])
+    profile = PROFILES.get(args.workload, "")
     log("workload:", describe(p64), "steps", steps)
-    wall, st = timed_run(S, torch, p64, steps, args.warmup)
+    wall, st, s64 = timed_run(S, torch, p64, steps, args.warmup, timing=True, keep=True)
     seg = st["seg_mc_total"] + st["seg_remap_total"]
     value = seg / wall
+    dom, both = rooflines(st, steps, 0, profile)
     log("fp64: %.3f s, %.3e segments/s, kernel ms mc %.1f remap %.1f" %
         (wall, value, st["ms_kernel_mc_total"], st["ms_kernel_remap_total"]))
     out = {
         "metric": METRIC, "value": value, "unit": "segments/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "checkerboard 7x7 unit blocks (absorber sigma_a=10 / scatterer "
-                               "sigma_s=1), unit source in the centre block, " + describe(p64)
-                   if args.workload == "c2" else args.workload + ": " + describe(p64),
-                   "n_steps": steps, "precision": "fp64", "points": "sobol-owen"},
-        "roofline": roofline(st, steps, 0),
-        "segments": int(seg),
+        "config": {"workload": WORKLOAD_NAMES.get(args.workload, args.workload) + ": " +
+                   describe(p64), "n_steps": steps, "precision": "fp64",
+                   "points": "sobol-owen", "timing": "MC-pass kernels between HIP events, "
+                   "the rest of each step as graphs; no host wait inside a step"},
+        "roofline": dom, "roofline_kernels": both, "segments": int(seg),
+        "si_iterations_last_step": st["si_iterations"],
     }
+    if not args.no_graph_run:
+        wall_g, st_g = timed_run(S, torch, p64, steps, 0, timing=False)
+        seg_g = st_g["seg_mc_total"] + st_g["seg_remap_total"]
+        out["one_graph_per_step"] = {"value": seg_g / wall_g, "unit": "segments/s",
+                                     "ms_per_step": 1e3 * wall_g / steps,
+                                     "graph_launches": st_g["graph_launches_total"]}
+        log("one graph per step: %.3e segments/s, %.2f ms/step" % (seg_g / wall_g,
+                                                                  1e3 * wall_g / steps))
+    x64 = s64.get_flux(0)
+    s64.destroy()
     if not args.no_fp32:
         p32 = make_problem(args, 1)
-        wall32, st32 = timed_run(S, torch, p32, steps, args.warmup)
+        wall32, st32, s32 = timed_run(S, torch, p32, steps, args.warmup, timing=True, keep=True)
         seg32 = st32["seg_mc_total"] + st32["seg_remap_total"]
-        err = fp32_error(S, p64, p32, steps)
+        x32 = s32.get_flux(0)
+        s32.destroy()
+        err = float(np.linalg.norm(x32 - x64) / max(np.linalg.norm(x64), 1e-300))
+        runs = [x64]
+        for r in range(args.qmc_seeds - 1):
+            sr = S.Solver(dict(p64, seed=int(p64["seed"]) + 1000003 * (r + 1)))
+            sr.advance(steps)
+            sr.synchronize(allow_not_converged=True)
+            runs.append(sr.get_flux(0))
+            sr.destroy()
+            log("qmc error: seed run %d done" % (r + 1))
+        runs = np.stack(runs)
+        e_qmc = float(np.linalg.norm(runs.std(axis=0, ddof=1)) /
+                      max(np.linalg.norm(runs.mean(axis=0)), 1e-300))
+        dom32, both32 = rooflines(st32, steps, 1, profile)
         out["fp32_track"] = {"value": seg32 / wall32, "unit": "segments/s",
                              "ms_per_step": 1e3 * wall32 / steps,
-                             "rel_l2_vs_fp64_max_over_steps": err,
-                             "roofline": roofline(st32, steps, 1)}
-        log("fp32-track: %.3f s, %.3e segments/s, rel-L2 vs fp64 %.2e" %
-            (wall32, seg32 / wall32, err))
+                             "speedup_vs_fp64": (seg32 / wall32) / value,
+                             "rel_l2_vs_fp64_last_step": err,
+                             "e_qmc_last_step": e_qmc, "e_qmc_seeds": args.qmc_seeds,
+                             "fp32_within_bound": bool(err < min(1e-4, e_qmc)),
+                             "roofline": dom32, "roofline_kernels": both32}
+        log("fp32-track: %.3f s, %.3e segments/s, rel-L2 vs fp64 %.2e, e_qmc %.2e" %
+            (wall32, seg32 / wall32, err, e_qmc))
     if not args.no_c3:
         out["precision_form"] = precision_form(S, torch, args)
+    if not args.no_c2:
+        pc2 = W_c2()
+        w2, st2 = timed_run(S, torch, pc2, int(pc2["n_steps"]), 2, timing=True)
+        seg2 = st2["seg_mc_total"] + st2["seg_remap_total"]
+        dom2, both2 = rooflines(st2, int(pc2["n_steps"]), 0, PROFILES["c2"])
+        out["checkerboard"] = {"workload": WORKLOAD_NAMES["c2"] + ": " + describe(pc2),
+                               "value": seg2 / w2, "unit": "segments/s",
+                               "ms_per_step": 1e3 * w2 / int(pc2["n_steps"]),
+                               "roofline": dom2, "roofline_kernels": both2}
+        log("checkerboard: %.3e segments/s, %.2f ms/step" % (seg2 / w2,
+                                                            1e3 * w2 / int(pc2["n_steps"])))
     if args.protocol:
         out["protocol"] = protocol(S, torch, args)
     if args.steady:
@@ -744,15 +787,19 @@ def main():
         out["cellwise_ns"] = cellwise_ns(S, torch, args)
     if args.reflect:
         out["reflective"] = reflective(S, torch, args)
-    if args.c5:
-        out["large_resident"] = large_resident(S, torch, args)
-    if args.serve:
+    if not args.no_serve:
         out["serving"] = serve_bench(S, torch, args)
         log("serving:", json.dumps(out["serving"]))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p64, args.cpu_steps)
-        log("cpu oracle: %.3e segments/s" % out["cpu_baseline"]["value"])
+        workers = min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(p64, args.cpu_particles, workers)
+        log("cpu oracle: %.3e segments/s on %d cores" % (out["cpu_baseline"]["value"], workers))
     print(json.dumps(out), flush=True)
+
+
+def W_c2():
+    from paper_2511_16821_amd import workloads as W
+    return W.c2(n_s=2)
 
 
 if __name__ == "__main__":

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define SLH_ABI_VERSION 5u
+#define SLH_ABI_VERSION 6u
 
 typedef enum {
     SLH_OK = 0,
@@ -58,7 +58,8 @@ typedef enum {
     SLH_E_DEVICE = 3,        /* a HIP call failed                           */
     SLH_E_NOT_CONVERGED = 4, /* source iteration hit si_max_iter (the step
                                 still completed; see slh_stats)             */
-    SLH_E_NUMERIC = 5,       /* non-finite tally detected                   */
+    SLH_E_NUMERIC = 5,       /* numeric fault: a non-finite weight, tally,
+                                majorant or residual (slh_stats)            */
     SLH_E_REJECTED = 6,      /* serving: request does not fit the budget    */
     SLH_E_STATE = 7          /* call not valid in the object's state        */
 } slh_status;
@@ -230,12 +231,12 @@ typedef struct {
     uint64_t source_particles; /* particles emitted by the source              */
     uint64_t killed;     /* histories ended by the device's guard of 2^26
                             segments per history (booked as cutoff); 0 in
-                            every normal run, and slh_advance reports
+                            every normal run, and slh_synchronize reports
                             SLH_E_NUMERIC when it is not                    */
 } slh_balance;
 
 typedef struct {
-    int64_t step;            /* steps completed                              */
+    int64_t step;            /* steps enqueued                               */
     int32_t si_iterations;   /* last step: transport sweeps                  */
     double si_residual;      /* last step: ||dphi||/||phi|| at exit          */
     int32_t si_converged;    /* last step: 1 if residual <= si_tol           */
@@ -243,12 +244,14 @@ typedef struct {
     int64_t census_kept;     /* last step: bank size after the cap           */
     double thin_factor;      /* last step: weight factor of the cap          */
     uint64_t segments_total; /* last step, both passes                       */
-    double ms_mc, ms_dg, ms_remap, ms_census; /* last step, stage times;
-                                 ms_dg includes the host's wait for the
-                                 iteration outcome                          */
+    double ms_mc, ms_dg, ms_remap, ms_census; /* last step run in timing mode
+                                 (slh_set_timing), stage times: emission and
+                                 MC pass 1; collided solve and remap set-up;
+                                 remap pass; census.  0 otherwise          */
     /* Totals since creation (or the last slh_load), for throughput and
-     * roofline accounting.  Kernel times are HIP events recorded on the
-     * solver's stream immediately around each MC-pass kernel launch. */
+     * roofline accounting, kept on the device.  Kernel times exist only for
+     * steps run in timing mode: HIP events recorded on the solver's stream
+     * immediately around each MC-pass kernel launch. */
     double ms_kernel_mc_total;      /* step-1 (scatter-limited) pass kernels */
     double ms_kernel_remap_total;   /* step-3 (remap) pass kernels           */
     uint64_t seg_mc_total;          /* segments of step-1 passes             */
@@ -260,11 +263,10 @@ typedef struct {
     uint64_t steps_total;           /* steps accounted in the totals         */
     uint64_t thin_overflow_total;   /* steps whose census draw exceeded the
                                        cap (first cap in slot order kept)   */
-    uint64_t graph_launches_total;  /* step parts replayed as HIP graphs     */
-    uint64_t host_waits_total;      /* host waits on the stream inside
-                                       slh_advance (one per step when the
-                                       first batch of source iterations
-                                       suffices)                             */
+    uint64_t graph_launches_total;  /* HIP graphs launched: one per step (three
+                                       in timing mode)                       */
+    uint64_t host_waits_total;      /* host waits inside slh_advance: 0, the
+                                       steps are asynchronous                */
     uint64_t killed_total;          /* histories ended by the segment guard   */
     /* Diffusion synthetic acceleration (si_accel), last step: corrections
      * solved, their conjugate-gradient iterations in total, and how many
@@ -274,7 +276,14 @@ typedef struct {
     int32_t dsa_corrections;
     int32_t dsa_iterations;
     int32_t dsa_unconverged;
-    int32_t pad0;
+    int32_t numeric_flags;          /* OR over all steps: 1 a non-finite cell
+                                       majorant or sum, 2 a non-finite history
+                                       weight or tally, 4 an emission clamped
+                                       to the source bank, 8 a non-finite
+                                       source-iteration residual, 16 the
+                                       segment guard fired (0 normally)     */
+    uint64_t si_unconverged_total;  /* steps whose source iteration stopped
+                                       at si_max_iter                        */
 } slh_stats;
 
 typedef struct slh_solver slh_solver;
@@ -305,22 +314,32 @@ slh_status slh_create(const slh_problem *problem, void *hip_stream, slh_alloc_fn
  * slh_set_graphs(s, 1) is SLH_E_STATE. */
 slh_status slh_create_static(const slh_problem *problem, void *hip_stream, slh_solver **out);
 
-/* Enqueues n_steps >= 1 time steps (steps 1-4 above) on the solver's stream.
- * A step is launched in two parts: the scatter-limited leg with a first
- * batch of source iterations (as many as the previous step needed), and the
- * remap leg with the census.  The iteration's stopping test runs on the
- * device; the host waits once per step for its outcome (again only when the
- * batch was too short), so the call returns when the last step's remap leg
- * has been enqueued.  Each part is replayed from a HIP graph captured on
- * first use (see slh_set_graphs).  Returns SLH_E_NOT_CONVERGED if any step's
- * SI hit si_max_iter. */
+/* Enqueues n_steps >= 1 time steps (steps 1-4 above) on the solver's stream
+ * and returns without waiting for the device.  Each step is one HIP graph
+ * (captured on first use, once per census-bank parity, and replayed): the
+ * scatter-limited leg, the collided solve with si_max_iter source
+ * iterations of which those after the device's stopping test return at
+ * once, the remap leg and the census.  Nothing in a step waits for the host.
+ * The outcome of the steps (convergence, numeric faults) is reported by
+ * slh_synchronize.  Returns SLH_E_DEVICE if a launch fails. */
 slh_status slh_advance(slh_solver *s, int32_t n_steps);
 
-/* enable != 0 (the default): step parts are captured once as HIP graphs and
- * replayed; 0: every kernel is launched directly.  Results are identical. */
+/* enable != 0 (the default): each step is launched as a HIP graph; 0: every
+ * kernel is launched directly.  Results are identical. */
 slh_status slh_set_graphs(slh_solver *s, int32_t enable);
 
-/* Blocks until the solver's stream is idle. */
+/* enable != 0: later steps are launched as three graphs with the two MC-pass
+ * kernels launched directly between HIP events, so that slh_get_stats
+ * reports their kernel times and the stage times of the last step; 0 (the
+ * default): one graph per step, no events.  Results are identical.
+ * SLH_E_STATE for a static solver. */
+slh_status slh_set_timing(slh_solver *s, int32_t enable);
+
+/* Blocks until the solver's stream is idle, then reports the outcome of the
+ * steps enqueued since the last call: SLH_E_NUMERIC if a step met a numeric
+ * fault (see slh_stats.numeric_flags; the results are then not valid),
+ * else SLH_E_NOT_CONVERGED if a step's source iteration stopped at
+ * si_max_iter (the step was still completed), else SLH_OK. */
 slh_status slh_synchronize(slh_solver *s);
 
 /* Copies the last step's flux to host_out (FP64; nx*ny values, or 4*nx*ny

@@ -175,9 +175,11 @@ static std::vector<double> material_values(const slh_problem* p) {
 
 // LDS bytes one workgroup may use on the current device.
 static size_t lds_limit() {
+  static std::mutex mu;  // solvers and servers are created from several threads
   static size_t cached[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  std::lock_guard<std::mutex> lk(mu);
   if (!cached[dev]) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
@@ -355,10 +357,26 @@ struct BalStore {
   int numeric;        // DevState::numeric of the pass
 };
 
-__global__ void k_snapshot(const DevState* st, BalStore* out, int kind) {
+// End of a pass: its balance record for slh_get_balance, and the device
+// totals of the step (si_active: the step had a source iteration, whose state
+// is final when the remap pass ends).
+__global__ void k_snapshot(DevState* st, BalStore* out, int kind, int si_active) {
   const int t = threadIdx.x;
   if (t < 2 * B_NFIELDS) out->bal[t] = st->bal[t];
   if (t == 0) {
+    int num = st->numeric | (st->killed ? 16 : 0);
+    st->acc_seg[kind - 1] += st->segments;
+    st->acc_killed += st->killed;
+    if (kind == 1) {
+      st->acc_census_in += (unsigned long long)st->n_in;
+      st->acc_thin_overflow += st->thin_overflow ? 1ull : 0ull;
+    } else {
+      st->acc_census_out += st->alive;
+      st->acc_steps += 1ull;
+      if (si_active && !st->si.conv) st->acc_unconv += 1ull;
+      if (si_active && st->si.bad) num |= 8;
+    }
+    st->acc_numeric |= num;
     out->segments = st->segments;
     out->particles = st->particles;
     out->alive = st->alive;
@@ -380,6 +398,7 @@ __global__ void k_state_init(DevState* st) {
   }
 }
 
+// A loaded checkpoint: its bank, its step, and fresh totals.
 __global__ void k_state_set_bank(DevState* st, long long n, double maxabs,
                                  unsigned long long step) {
   if (threadIdx.x == 0) {
@@ -387,19 +406,19 @@ __global__ void k_state_set_bank(DevState* st, long long n, double maxabs,
     st->n_in = n;
     st->n_kept = n;
     st->maxabs_w = maxabs;
+    st->acc_seg[0] = st->acc_seg[1] = 0ull;
+    st->acc_census_in = st->acc_census_out = st->acc_killed = st->acc_steps = 0ull;
+    st->acc_thin_overflow = st->acc_unconv = 0ull;
+    st->acc_numeric = 0;
   }
 }
 
-// The device's iteration state (DevState::si, fields done .. nrm2), as
-// copied to pinned host memory after each batch of iterations.
-struct SiState {
-  int done, conv, iter, bad;
-  double dn2, nrm2;
+// HIP events of one step launched in timing mode: start, MC pass 1 start and
+// end, end of the collided solve and remap set-up, MC pass 2 start and end,
+// end of the step.
+struct StepEvents {
+  hipEvent_t e[7];
 };
-static const size_t kSiStateBytes = sizeof(SiState);
-static_assert(offsetof(IterState, nrm2) - offsetof(IterState, done) == 24 &&
-                  offsetof(IterState, done) == 0,
-              "SiState mirrors the leading IterState fields");
 
 struct slh_solver {
   slh_problem prob;
@@ -461,30 +480,27 @@ struct slh_solver {
   uint32_t* sobol = nullptr;
   DevState* st = nullptr;
   BalStore* bal_store = nullptr;  // [2]
-  double* h_res = nullptr;        // pinned: SI residual
   int cur = 0;
 
   // host-side state
-  long long step = 0;
-  int si_it = 0;
-  double si_res = 0.0;
-  bool si_conv = true;
-  unsigned long long seg_total = 0;
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t evk[4] = {nullptr, nullptr, nullptr, nullptr};  // around the MC kernels
-  bool have_events = false;
-  BalStore* h_bal = nullptr;   // pinned copies of the pass snapshots
-  bool pending[2] = {false, false};
-  // graphs of the step parts (see enqueue_part)
+  long long step = 0;             // steps enqueued
+  // graphs: one per step and census-bank parity (production), or the three
+  // graph parts of a step in timing mode, keyed by (part, parity)
   bool use_graphs = true;
+  int grid1 = 1, grid2 = 1;       // persistent grids of the two MC passes
+  bool timing = false;            // steps as graph parts and MC kernels between events
   hipStream_t cap_stream = nullptr;
-  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (part, parity, batch)
-  unsigned long long graph_launches = 0ull, host_syncs = 0ull;
-  double k_ms[2] = {0.0, 0.0};
-  unsigned long long k_seg[2] = {0ull, 0ull};
-  unsigned long long census_in_total = 0ull, census_out_total = 0ull, steps_total = 0ull;
-  unsigned long long thin_overflow_total = 0ull;
-  unsigned long long killed_total = 0ull;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  unsigned long long graph_launches = 0ull;
+  // timing mode: events of the steps enqueued since the last collection
+  std::vector<StepEvents> ev_pool;
+  size_t ev_used = 0;
+  double k_ms[2] = {0.0, 0.0};    // MC-pass kernel times (timing mode)
+  double stage_ms[4] = {0.0, 0.0, 0.0, 0.0};  // last timed step
+  bool have_stage = false;
+  // device totals already turned into a status by slh_synchronize
+  unsigned long long rep_unconv = 0ull;
+  int rep_numeric = 0;
 
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 8;
@@ -513,19 +529,10 @@ struct slh_solver {
       else (void)hipFree(p);
     }
     allocs.clear();
-    if (static_mem) {
-      delete[] (char*)h_res;
-      delete[] (char*)h_bal;
-    } else {
-      if (h_res) (void)hipHostFree(h_res);
-      if (h_bal) (void)hipHostFree(h_bal);
-    }
-    h_res = nullptr;
-    h_bal = nullptr;
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
-    for (auto& e : evk)
-      if (e) (void)hipEventDestroy(e);
+    for (auto& se : ev_pool)
+      for (auto& e : se.e)
+        if (e) (void)hipEventDestroy(e);
+    ev_pool.clear();
   }
 
   template <typename R> Bank<R> bank_at(void* base, long long n) const {
@@ -639,17 +646,6 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->st, DevState, 1);
   ALLOC(s->bal_store, BalStore, 2);
 #undef ALLOC
-  if (s->static_mem) {  // no pinned memory: plain host buffers, copies wait on the stream
-    s->h_res = (double*)new (std::nothrow) char[4 * sizeof(double)];
-    s->h_bal = (BalStore*)new (std::nothrow) char[2 * sizeof(BalStore)];
-    if (!s->h_res || !s->h_bal) return fail(SLH_E_OUT_OF_MEMORY, "host allocation failed");
-  } else if (hipHostMalloc((void**)&s->h_res, 4 * sizeof(double), hipHostMallocDefault) !=
-             hipSuccess)
-    return fail(SLH_E_OUT_OF_MEMORY, "pinned host allocation failed");
-  if (!s->static_mem &&
-      hipHostMalloc((void**)&s->h_bal, 2 * sizeof(BalStore), hipHostMallocDefault) != hipSuccess)
-    return fail(SLH_E_OUT_OF_MEMORY, "pinned host allocation failed");
-
   // fields and derived arrays
   std::vector<double2> m64(nc);
   std::vector<float2> m32(nc);
@@ -720,11 +716,6 @@ static slh_status setup(slh_solver* s) {
   HIP_TRY(launch_fill_f64(s->phi_R, nc, 0.0, st));
   HIP_TRY(launch_fill_u64((unsigned long long*)s->bal_store, 2 * sizeof(BalStore) / 8, 0ull, st));
   HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
-  if (!s->static_mem) {  // stage and kernel timing (none in a static solver)
-    for (auto& e : s->ev) HIP_TRY(hipEventCreate(&e));
-    for (auto& e : s->evk) HIP_TRY(hipEventCreate(&e));
-    s->have_events = true;
-  }
   HIP_TRY(hipStreamSynchronize(st));  // host vectors above go out of scope
   return SLH_OK;
 }
@@ -784,55 +775,23 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   return a;
 }
 
-// Folds the kernel times and counters of finished passes into the totals.
-// Called only after the stream has passed the pass's snapshot copy.
-static slh_status collect(slh_solver* s, int k) {
-  if (!s->pending[k]) return SLH_OK;
-  if (s->h_bal[k].numeric || s->h_bal[k].killed) {
-    s->pending[k] = false;
-    const int f = s->h_bal[k].numeric;
-    return fail(SLH_E_NUMERIC,
-                std::string(k == 0 ? "scatter-limited" : "remap") + " pass: " +
-                    ((f & 1) ? "a cell majorant or their sum is not finite; " : "") +
-                    ((f & 2) ? "a history ended with a non-finite weight or tally; " : "") +
-                    ((f & 4) ? "the emission exceeded the source bank; " : "") +
-                    (s->h_bal[k].killed ? "histories reached the 2^26-segment guard" : ""));
-  }
-  float ms = 0.f;
-  if (s->have_events) HIP_TRY(hipEventElapsedTime(&ms, s->evk[2 * k], s->evk[2 * k + 1]));
-  s->k_ms[k] += ms;
-  s->k_seg[k] += s->h_bal[k].segments;
-  s->killed_total += s->h_bal[k].killed;
-  if (k == 0) s->census_in_total += (unsigned long long)s->h_bal[0].n_in;
-  if (k == 0 && s->h_bal[0].thin_overflow) s->thin_overflow_total += 1;
-  if (k == 1) {
-    s->census_out_total += s->h_bal[1].alive;
-    s->steps_total += 1;
-  }
-  s->pending[k] = false;
-  return SLH_OK;
-}
-
-static slh_status collect_all(slh_solver* s) {
-  slh_status r = collect(s, 0);
-  if (r != SLH_OK) return r;
-  return collect(s, 1);
-}
-
-// The time step is enqueued as graphs around the two MC-pass kernels:
-//   A1  pass begin, tally clears, emission of the scatter-limited leg
-//   --  MC pass 1 (direct launch between timing events)
-//   A2  tally -> flux, pass-1 balance snapshot, phi_c = 0, and the first batch
-//       of source iterations of the collided solve, ending with a copy of the
-//       device's iteration state to pinned host memory
-//   --  host wait; extra batches only if the first did not finish
-//   B1  remap source with its majorant and count trees, emission of the remap leg
-//   --  MC pass 2 (direct launch between timing events)
-//   B2  tally -> flux, snapshot, census thinning and compaction, step + 1
-// Every part reads its step-dependent values (step counter, counts, flags)
-// from the device, so a graph captured once per census-bank parity (and
-// batch length) is replayed for every step.
-enum Part { kA1 = 0, kA2, kB1, kB2, kNumParts };
+// A time step is five parts, enqueued in this order on the solver's stream:
+//   kA    emission plan, pass set-up and emission of the scatter-limited leg
+//   kMC1  MC pass 1
+//   kMid  tally -> flux, pass-1 snapshot, phi_c = 0 and the source iteration
+//         of the collided solve: si_max iterations, each returning at once
+//         once the device's stopping test has said done; then the remap
+//         source, its emission plan, pass set-up and emission
+//   kMC2  MC pass 2 (the remap)
+//   kEnd  tally -> flux, snapshot, census thinning and compaction, step + 1
+// Every kernel reads its step-dependent values (step counter, counts, flags,
+// the iteration state) from the device, so nothing in a step waits for the
+// host.  In production the five parts are one graph, captured once per
+// census-bank parity and replayed for every step; in timing mode kA, kMid and
+// kEnd are graphs and the MC passes are launched between HIP events; with
+// graphs off every kernel is launched directly.  All three give the same
+// results.
+enum Part { kA = 0, kMC1, kMid, kMC2, kEnd, kNumParts, kWhole = 9 };
 
 static DgArgs dg_args(slh_solver* s) {
   const slh_problem& p = s->prob;
@@ -927,11 +886,10 @@ static slh_status enqueue_si(slh_solver* s, hipStream_t st, int n_it) {
       HIP_TRY(launch_dg_reduce(d, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
     }
   }
-  HIP_TRY(hipMemcpyAsync(s->h_res, &s->st->si.done, kSiStateBytes, hipMemcpyDeviceToHost, st));
   return SLH_OK;
 }
 
-static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it) {
+static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
   const slh_problem& p = s->prob;
   const Sizes& z = s->z;
   const long long nc = z.n_cells;
@@ -939,8 +897,11 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
   const double cdt = p.steady ? s->horizon : p.c * p.dt;  // longest path of a history
   const long long cstride = (long long)kTallyStride * nc;
   const long long n_tally = (long long)z.n_copies * kTallyStride * nc;
+  // source iterations launched per step: the limit (predicated on the
+  // device's stopping test), none without a collided solve
+  const int n_it = s->skip_remap ? 0 : s->si_max;
   switch (part) {
-    case kA1: {
+    case kA: {
       HIP_TRY(launch_emission_plan(s->qn1, nc, s->adt, z.n_p, p.seed, p.points, 1, s->maj_hist,
                                    s->ctree1, s->st, st));
       HIP_TRY(launch_pass_prep(s->st, s->ctree1, 1, z.n_src_cap, cdt, s->Tpre, n_tally, s->Tpost,
@@ -948,22 +909,23 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
       HIP_TRY(launch_emit(pass_args(s, 1), z.fp32, st));
       return SLH_OK;
     }
-    case kA2: {
+    case kMC1:
+      HIP_TRY(launch_mc_pass(pass_args(s, 1), z.fp32, s->grid1, st));
+      return SLH_OK;
+    case kMid: {
       HIP_TRY(launch_tally_to_flux(s->Tpre, s->phi_pre, s->Tpost, s->phi_post, nc, z.n_copies,
                                    cstride, s->st, inv_adt, st));
-      hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
-                         s->bal_store + 0, 1);
-      HIP_TRY(hipMemcpyAsync(s->h_bal + 0, s->bal_store + 0, sizeof(BalStore),
-                             hipMemcpyDeviceToHost, st));
+      hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, s->st, s->bal_store + 0, 1, 0);
       if (use_cg(s)) {
         HIP_TRY(launch_cg_start(cg_args(s), s->sig_s, s->phi_post, s->si_max, st));
       } else {
         // pure MC in steady state: no collided solve (phi_c = 0, no sweep)
         HIP_TRY(launch_si_start(dg_args(s), s->skip_remap ? 0 : s->si_max, st));
       }
-      return enqueue_si(s, st, n_it);
-    }
-    case kB1: {
+      {
+        const slh_status r = enqueue_si(s, st, n_it);
+        if (r != SLH_OK) return r;
+      }
       if (s->skip_remap) {  // no remap leg: clear its balance and census flags only
         HIP_TRY(launch_pass_prep(s->st, s->ctree1, 1, z.n_src_cap, cdt, nullptr, 0, nullptr, 0,
                                  s->alive, z.n_cand, st));
@@ -979,14 +941,15 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
       HIP_TRY(launch_emit(pass_args(s, 2), z.fp32, st));
       return SLH_OK;
     }
-    default: {  // kB2: the remap census is the state at t_{n+1} (capped)
+    case kMC2:
+      if (!s->skip_remap) HIP_TRY(launch_mc_pass(pass_args(s, 2), z.fp32, s->grid2, st));
+      return SLH_OK;
+    default: {  // kEnd: the remap census is the state at t_{n+1} (capped)
       // without a remap leg the solution is the pure-MC flux of pass 1
       HIP_TRY(launch_tally_to_flux(s->skip_remap ? s->Tpre : s->TR, s->phi_R, nullptr, nullptr,
                                    nc, z.n_copies, cstride, s->st, inv_adt, st));
-      hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, (const DevState*)s->st,
-                         s->bal_store + 1, 2);
-      HIP_TRY(hipMemcpyAsync(s->h_bal + 1, s->bal_store + 1, sizeof(BalStore),
-                             hipMemcpyDeviceToHost, st));
+      hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, s->st, s->bal_store + 1, 2,
+                         n_it > 0 ? 1 : 0);
       void* nb = s->bank_mem[1 - s->cur];
       HIP_TRY(launch_thin_params(s->st, z.cap, s->thin_margin, st));
       if (z.fp32) {
@@ -1009,9 +972,18 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st, int n_it
   }
 }
 
-// Captures a part on the capture stream.  Returns false when the runtime
-// declines the capture; the solver then launches its kernels directly.
-static bool capture(slh_solver* s, int part, int n_it, hipGraphExec_t* out) {
+// Parts [first, last] of a step on stream st.
+static slh_status enqueue_parts(slh_solver* s, int first, int last, hipStream_t st) {
+  for (int part = first; part <= last; ++part) {
+    const slh_status r = enqueue_part(s, part, st);
+    if (r != SLH_OK) return r;
+  }
+  return SLH_OK;
+}
+
+// Captures parts [first, last] on the capture stream.  Returns false when the
+// runtime declines the capture; the solver then launches its kernels directly.
+static bool capture(slh_solver* s, int first, int last, hipGraphExec_t* out) {
   *out = nullptr;
   if (!s->cap_stream &&
       hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1020,7 +992,7 @@ static bool capture(slh_solver* s, int part, int n_it, hipGraphExec_t* out) {
   }
   if (hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return false;
-  const slh_status r = enqueue_part(s, part, s->cap_stream, n_it);
+  const slh_status r = enqueue_parts(s, first, last, s->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
   bool ok = r == SLH_OK && e == hipSuccess && g;
@@ -1031,13 +1003,15 @@ static bool capture(slh_solver* s, int part, int n_it, hipGraphExec_t* out) {
   return ok;
 }
 
-static slh_status launch_part(slh_solver* s, int part, int n_it) {
+// Parts [first, last] as one graph (key: first part, or kWhole for the whole
+// step, and the census-bank parity), or directly.
+static slh_status launch_parts(slh_solver* s, int first, int last, int key) {
   if (s->use_graphs) {
-    const auto key = std::make_tuple(part, s->cur, part == kA2 ? n_it : 0);
-    auto it = s->graphs.find(key);
+    const auto k = std::make_pair(key, s->cur);
+    auto it = s->graphs.find(k);
     if (it == s->graphs.end()) {
       hipGraphExec_t e = nullptr;
-      if (capture(s, part, n_it, &e)) it = s->graphs.emplace(key, e).first;
+      if (capture(s, first, last, &e)) it = s->graphs.emplace(k, e).first;
       else s->use_graphs = false;
     }
     if (s->use_graphs) {
@@ -1046,66 +1020,71 @@ static slh_status launch_part(slh_solver* s, int part, int n_it) {
       return SLH_OK;
     }
   }
-  return enqueue_part(s, part, s->stream, n_it);
+  return enqueue_parts(s, first, last, s->stream);
 }
 
+static slh_status record(hipEvent_t e, hipStream_t st) {
+  HIP_TRY(hipEventRecord(e, st));
+  return SLH_OK;
+}
+
+// Enqueues one time step; no host wait.
 static slh_status run_step(slh_solver* s) {
-  const Sizes& z = s->z;
-  const int grid1 = mc_pass_grid(z.fp32, 1, z.cap + z.n_src_cap);
-  const int grid2 = mc_pass_grid(z.fp32, 2, z.cap + z.n_src_cap);
-  // iterations in the first batch: as many as the previous step took
-  const int n_first = s->si_max > 0 && !s->skip_remap
-                          ? std::max(1, std::min(s->si_max, s->si_it > 0 ? s->si_it : 4))
-                          : 0;
-  hipStream_t st = s->stream;
-  if (s->have_events) HIP_TRY(hipEventRecord(s->ev[0], st));
-  slh_status r = launch_part(s, kA1, 0);
-  if (r != SLH_OK) return r;
-  if (s->have_events) HIP_TRY(hipEventRecord(s->evk[0], st));
-  HIP_TRY(launch_mc_pass(pass_args(s, 1), z.fp32, grid1, st));
-  if (s->have_events) HIP_TRY(hipEventRecord(s->evk[1], st));
-  r = launch_part(s, kA2, n_first);
-  if (r != SLH_OK) return r;
-  s->pending[0] = true;
-  // the one host wait of the step: iteration state (and the balances of the
-  // previous step's remap leg and this step's pass 1).  When the first batch
-  // falls short, further batches double in size (iterations past convergence
-  // return at once), so a solve of k iterations needs about log2(k) waits.
-  int batch = 2;
-  for (;;) {
-    HIP_TRY(hipStreamSynchronize(st));
-    s->host_syncs += 1;
-    const SiState* si = (const SiState*)s->h_res;
-    s->si_it = si->iter;
-    s->si_conv = si->conv != 0;
-    const double dn = sqrt(si->dn2), nrm = sqrt(si->nrm2);
-    s->si_res = nrm > 0.0 ? dn / nrm : 0.0;
-    if (si->bad) return fail(SLH_E_NUMERIC, "non-finite DG residual");
-    if (si->done) break;
-    r = enqueue_si(s, st, std::min(batch, s->si_max - si->iter));
+  slh_status r;
+  if (!s->timing) {
+    r = launch_parts(s, kA, kEnd, kWhole);
     if (r != SLH_OK) return r;
-    batch = std::min(2 * batch, 64);
+  } else {
+    if (s->ev_used == s->ev_pool.size()) {
+      StepEvents se;
+      for (auto& e : se.e) e = nullptr;
+      for (auto& e : se.e)
+        if (hipEventCreate(&e) != hipSuccess) {
+          for (auto& f : se.e)
+            if (f) (void)hipEventDestroy(f);
+          return fail(SLH_E_DEVICE, "hipEventCreate failed");
+        }
+      s->ev_pool.push_back(se);
+    }
+    const StepEvents& ev = s->ev_pool[s->ev_used++];
+    hipStream_t st = s->stream;
+    if ((r = record(ev.e[0], st)) != SLH_OK) return r;
+    if ((r = launch_parts(s, kA, kA, kA)) != SLH_OK) return r;
+    if ((r = record(ev.e[1], st)) != SLH_OK) return r;
+    if ((r = enqueue_part(s, kMC1, st)) != SLH_OK) return r;
+    if ((r = record(ev.e[2], st)) != SLH_OK) return r;
+    if ((r = launch_parts(s, kMid, kMid, kMid)) != SLH_OK) return r;
+    if ((r = record(ev.e[3], st)) != SLH_OK) return r;
+    if ((r = enqueue_part(s, kMC2, st)) != SLH_OK) return r;
+    if ((r = record(ev.e[4], st)) != SLH_OK) return r;
+    if ((r = launch_parts(s, kEnd, kEnd, kEnd)) != SLH_OK) return r;
+    if ((r = record(ev.e[5], st)) != SLH_OK) return r;
+    if ((r = record(ev.e[6], st)) != SLH_OK) return r;
   }
-  r = collect_all(s);
-  if (r != SLH_OK) return r;
-  if (s->have_events) HIP_TRY(hipEventRecord(s->ev[1], st));
-  r = launch_part(s, kB1, 0);
-  if (r != SLH_OK) return r;
-  if (s->have_events) HIP_TRY(hipEventRecord(s->evk[2], st));
-  if (!s->skip_remap) HIP_TRY(launch_mc_pass(pass_args(s, 2), z.fp32, grid2, st));
-  if (s->have_events) HIP_TRY(hipEventRecord(s->evk[3], st));
-  r = launch_part(s, kB2, 0);
-  if (r != SLH_OK) return r;
-  if (s->have_events) HIP_TRY(hipEventRecord(s->ev[2], st));
-  s->pending[1] = true;
   s->cur = 1 - s->cur;
   s->step += 1;
   return SLH_OK;
 }
 
-// ---------------------------------------------------------------------------
-// C ABI
-// ---------------------------------------------------------------------------
+// After a stream synchronisation: folds the events of the timed steps into
+// the kernel totals and keeps the stage times of the last one.
+static slh_status collect_events(slh_solver* s) {
+  for (size_t k = 0; k < s->ev_used; ++k) {
+    const StepEvents& ev = s->ev_pool[k];
+    float t[6];
+    for (int i = 0; i < 6; ++i) HIP_TRY(hipEventElapsedTime(&t[i], ev.e[i], ev.e[i + 1]));
+    s->k_ms[0] += t[1];
+    s->k_ms[1] += t[3];
+    s->stage_ms[0] = t[0] + t[1];  // emission and MC pass 1
+    s->stage_ms[1] = t[2];         // collided solve and remap set-up
+    s->stage_ms[2] = t[3];         // remap pass
+    s->stage_ms[3] = t[4] + t[5];  // census
+    s->have_stage = true;
+  }
+  s->ev_used = 0;
+  return SLH_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Static scratch for callers that cannot allocate device memory (under graph
 // capture, in serving loops, in harnesses that forbid it): slh_create_static
@@ -1226,6 +1205,12 @@ static slh_status create_solver(const slh_problem* problem, void* hip_stream, sl
     delete s;
     return r;
   }
+  {
+    static std::mutex mu;  // the occupancy query is cached per process
+    std::lock_guard<std::mutex> lk(mu);
+    s->grid1 = mc_pass_grid(s->z.fp32, 1, s->z.cap + s->z.n_src_cap);
+    s->grid2 = mc_pass_grid(s->z.fp32, 2, s->z.cap + s->z.n_src_cap);
+  }
   *out = s;
   return SLH_OK;
 }
@@ -1244,13 +1229,10 @@ extern "C" slh_status slh_create_static(const slh_problem* problem, void* hip_st
 extern "C" slh_status slh_advance(slh_solver* s, int32_t n_steps) {
   if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
   if (n_steps < 1) return fail(SLH_E_INVALID_ARG, "n_steps must be >= 1");
-  bool conv = true;
   for (int k = 0; k < n_steps; ++k) {
-    slh_status r = run_step(s);
+    const slh_status r = run_step(s);
     if (r != SLH_OK) return r;
-    conv = conv && s->si_conv;
   }
-  if (!conv) return fail(SLH_E_NOT_CONVERGED, "source iteration reached si_max_iter");
   return SLH_OK;
 }
 
@@ -1262,9 +1244,41 @@ extern "C" slh_status slh_set_graphs(slh_solver* s, int32_t enable) {
   return SLH_OK;
 }
 
+extern "C" slh_status slh_set_timing(slh_solver* s, int32_t enable) {
+  if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
+  if (s->static_mem && enable) return fail(SLH_E_STATE, "a static solver records no events");
+  s->timing = enable != 0;
+  return SLH_OK;
+}
+
+// Reads the device state after the stream is idle.
+static slh_status read_state(slh_solver* s, DevState* d) {
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  COPY_SYNC(d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
+  return collect_events(s);
+}
+
 extern "C" slh_status slh_synchronize(slh_solver* s) {
   if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  DevState d;
+  const slh_status r = read_state(s, &d);
+  if (r != SLH_OK) return r;
+  const int f = d.acc_numeric & ~s->rep_numeric;
+  const unsigned long long unconv = d.acc_unconv - s->rep_unconv;
+  s->rep_numeric = d.acc_numeric;
+  s->rep_unconv = d.acc_unconv;
+  if (f)
+    return fail(SLH_E_NUMERIC,
+                std::string("numeric fault in a step since the last synchronisation: ") +
+                    ((f & 1) ? "a cell majorant or their sum is not finite; " : "") +
+                    ((f & 2) ? "a history ended with a non-finite weight or tally; " : "") +
+                    ((f & 4) ? "the emission exceeded the source bank; " : "") +
+                    ((f & 8) ? "the source-iteration residual is not finite; " : "") +
+                    ((f & 16) ? "histories reached the 2^26-segment guard" : ""));
+  if (unconv)
+    return fail(SLH_E_NOT_CONVERGED, std::to_string(unconv) +
+                                         " step(s) since the last synchronisation stopped the "
+                                         "source iteration at si_max_iter");
   return SLH_OK;
 }
 
@@ -1328,44 +1342,42 @@ extern "C" slh_status slh_get_balance(slh_solver* s, int32_t pass, slh_balance* 
 
 extern "C" slh_status slh_get_stats(slh_solver* s, slh_stats* out) {
   if (!s || !out) return fail(SLH_E_INVALID_ARG, "NULL argument");
-  HIP_TRY(hipStreamSynchronize(s->stream));
   DevState d;
-  COPY_SYNC(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
+  const slh_status r = read_state(s, &d);
+  if (r != SLH_OK) return r;
   BalStore b[2];
   COPY_SYNC(b, s->bal_store, sizeof(b), hipMemcpyDeviceToHost);
   memset(out, 0, sizeof(*out));
   out->step = s->step;
-  out->si_iterations = s->si_it;
-  out->si_residual = s->si_res;
-  out->si_converged = s->si_conv ? 1 : 0;
+  out->si_iterations = d.si.iter;
+  const double dn = sqrt(d.si.dn2), nrm = sqrt(d.si.nrm2);
+  out->si_residual = nrm > 0.0 ? dn / nrm : 0.0;
+  out->si_converged = d.si.conv ? 1 : 0;
   out->census_alive = (int64_t)b[1].alive;
   out->census_kept = d.n_kept;
   out->thin_factor = d.thin_factor;
   out->segments_total = b[0].segments + b[1].segments;
-  {
-    slh_status r = collect_all(s);
-    if (r != SLH_OK) return r;
-  }
   out->ms_kernel_mc_total = s->k_ms[0];
   out->ms_kernel_remap_total = s->k_ms[1];
-  out->seg_mc_total = s->k_seg[0];
-  out->seg_remap_total = s->k_seg[1];
-  out->census_in_total = s->census_in_total;
-  out->census_out_total = s->census_out_total;
-  out->steps_total = s->steps_total;
-  out->thin_overflow_total = s->thin_overflow_total;
+  out->seg_mc_total = d.acc_seg[0];
+  out->seg_remap_total = d.acc_seg[1];
+  out->census_in_total = d.acc_census_in;
+  out->census_out_total = d.acc_census_out;
+  out->steps_total = d.acc_steps;
+  out->thin_overflow_total = d.acc_thin_overflow;
   out->graph_launches_total = s->graph_launches;
-  out->host_waits_total = s->host_syncs;
-  out->killed_total = s->killed_total;
+  out->host_waits_total = 0;  // slh_advance never waits
+  out->killed_total = d.acc_killed;
   out->dsa_corrections = d.dsa_corrections;
   out->dsa_iterations = d.dsa_iter_total;
   out->dsa_unconverged = d.dsa_unconv;
-  if (s->step > 0 && s->have_events) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, s->ev[0], s->evk[1]) == hipSuccess) out->ms_mc = ms;
-    if (hipEventElapsedTime(&ms, s->evk[1], s->ev[1]) == hipSuccess) out->ms_dg = ms;
-    if (hipEventElapsedTime(&ms, s->ev[1], s->evk[3]) == hipSuccess) out->ms_remap = ms;
-    if (hipEventElapsedTime(&ms, s->evk[3], s->ev[2]) == hipSuccess) out->ms_census = ms;
+  out->si_unconverged_total = d.acc_unconv;
+  out->numeric_flags = d.acc_numeric;
+  if (s->have_stage) {
+    out->ms_mc = s->stage_ms[0];
+    out->ms_dg = s->stage_ms[1];
+    out->ms_remap = s->stage_ms[2];
+    out->ms_census = s->stage_ms[3];
   }
   return SLH_OK;
 }
@@ -1520,12 +1532,14 @@ extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->step = (long long)h[2];
-  s->pending[0] = s->pending[1] = false;
+  {
+    const slh_status r = collect_events(s);
+    if (r != SLH_OK) return r;
+  }
   s->k_ms[0] = s->k_ms[1] = 0.0;
-  s->k_seg[0] = s->k_seg[1] = 0ull;
-  s->census_in_total = s->census_out_total = s->steps_total = 0ull;
-  s->thin_overflow_total = 0ull;
-  s->killed_total = 0ull;
+  s->have_stage = false;
+  s->rep_unconv = 0ull;
+  s->rep_numeric = 0;
   return SLH_OK;
 }
 

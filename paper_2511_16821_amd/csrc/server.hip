@@ -168,6 +168,7 @@ static void run_request(Request* r, hipStream_t stream) {
     return;
   }
   slh_status st = slh_advance(s, r->n_steps);
+  if (st == SLH_OK) st = slh_synchronize(s);  // the steps' outcome
   if (st != SLH_OK && st != SLH_E_NOT_CONVERGED) {
     r->status = st;
     r->error = slh_last_error();

@@ -322,6 +322,18 @@ struct DevState {
   int dsa_corrections;
   int dsa_iter_total;
   int pad1;
+  // totals since creation (or a checkpoint load), kept on the device so that
+  // steps need no host round trip: segments of each pass kind, census-in
+  // particles (each step's bank), census candidates written, histories
+  // stopped by the segment guard, steps, steps whose census draw overflowed
+  // the cap, steps whose source iteration stopped at its limit, and the OR of
+  // every pass's numeric flags (DevState::numeric, plus 8: a non-finite
+  // source-iteration residual, 16: the segment guard fired)
+  unsigned long long acc_seg[2];
+  unsigned long long acc_census_in, acc_census_out, acc_killed, acc_steps;
+  unsigned long long acc_thin_overflow, acc_unconv;
+  int acc_numeric;
+  int pad3;
 };
 
 struct PassArgs {

@@ -218,25 +218,15 @@ __global__ __launch_bounds__(256) void k_maj_hist(const double* __restrict__ qn,
 
 constexpr int kSumLimbs = 36;  // 2304 bits above 2^-1074
 
-// acc += v * 2^pos for a 128-bit v = (hi, lo)
-__device__ __forceinline__ void limbs_add(unsigned long long* acc, unsigned long long lo,
-                                          unsigned long long hi, int pos) {
-  const int w = pos >> 6, sh = pos & 63;
-  unsigned long long t[3];
-  t[0] = lo << sh;
-  t[1] = sh ? ((lo >> (64 - sh)) | (hi << sh)) : hi;
-  t[2] = sh ? (hi >> (64 - sh)) : 0ull;
-  unsigned long long carry = 0ull;
-  for (int k = 0; w + k < kSumLimbs; ++k) {
-    const unsigned long long add = (k < 3 ? t[k] : 0ull);
-    if (k >= 3 && carry == 0ull) break;
-    const unsigned long long s1 = acc[w + k] + add;
-    const unsigned long long c1 = s1 < add ? 1ull : 0ull;
-    const unsigned long long s2 = s1 + carry;
-    const unsigned long long c2 = s2 < carry ? 1ull : 0ull;
-    acc[w + k] = s2;
-    carry = c1 + c2;
-  }
+// Bits [r, r + 64) of the 128-bit value (hi, lo), zero outside it.
+__device__ __forceinline__ unsigned long long bits128(unsigned long long lo, unsigned long long hi,
+                                                      int r) {
+  if (r <= -64 || r >= 128) return 0ull;
+  if (r < 0) return lo << (-r);
+  if (r == 0) return lo;
+  if (r < 64) return (lo >> r) | (hi << (64 - r));
+  if (r == 64) return hi;
+  return hi >> (r - 64);
 }
 
 // bits [b, b + n) of the accumulator (n <= 64, b >= 0)
@@ -248,33 +238,38 @@ __device__ __forceinline__ unsigned long long limbs_bits(const unsigned long lon
   return n == 64 ? v : (v & ((1ull << n) - 1ull));
 }
 
-// One thread: the exact sum of the histogram, rounded once; w_q; and the
-// histogram cleared for the next plan.
-__global__ __launch_bounds__(256) void k_maj_sum(unsigned long long* __restrict__ hist, double adt,
-                                                 long long n_src, int kind, DevState* st) {
+// One wave: the exact sum of the histogram, rounded once; w_q; and the
+// histogram cleared for the next plan.  Lane k < kSumLimbs owns 64-bit limb
+// k of the sum (bit 0 = 2^-1074): every bin's term c_b mant_b 2^pos_b adds
+// its bits that fall in the limb, and the limb counts its own overflows;
+// lane 0 then propagates the carries and rounds.
+__global__ __launch_bounds__(64) void k_maj_sum(unsigned long long* __restrict__ hist, double adt,
+                                                long long n_src, int kind, DevState* st) {
   __shared__ unsigned long long s_h[kMajBins];
-  for (int k = threadIdx.x; k < kMajBins; k += blockDim.x) {
+  __shared__ unsigned long long s_limb[kSumLimbs], s_carry[kSumLimbs];
+  const int lane = threadIdx.x;
+  for (int k = lane; k < kMajBins; k += 64) {
     s_h[k] = hist[k];
     hist[k] = 0ull;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
   if (s_h[kMajBad]) {  // a majorant overflowed: no emission (flagged by the pass set-up)
-    st->sumM[kind - 1] = __builtin_huge_val();
-    st->wq[kind - 1] = 0.0;
+    if (lane == 0) {
+      st->sumM[kind - 1] = __builtin_huge_val();
+      st->wq[kind - 1] = 0.0;
+    }
     return;
   }
-  unsigned long long acc[kSumLimbs];
-  for (int k = 0; k < kSumLimbs; ++k) acc[k] = 0ull;
+  unsigned long long acc = 0ull, carry = 0ull;
+  bool overflow = false;
   for (int b = 0; b < kMajBad; ++b) {
-    const unsigned long long c = s_h[b];
+    const unsigned long long c = s_h[b];  // the same in every lane
     if (!c) continue;
     const double V = adt * ldexp(1.0, b - 1074);  // the value of every M_i in bin b
     if (!(V > 0.0)) continue;
     if (!isfinite(V)) {
-      st->sumM[kind - 1] = __builtin_huge_val();
-      st->wq[kind - 1] = 0.0;
-      return;
+      overflow = true;
+      break;
     }
     int e;
     const double m = frexp(V, &e);  // V = m 2^e, m in [1/2, 1)
@@ -284,21 +279,44 @@ __global__ __launch_bounds__(256) void k_maj_sum(unsigned long long* __restrict_
       mant >>= -pos;
       pos = 0;
     }
-    limbs_add(acc, c * mant, __umul64hi(c, mant), pos);
+    const unsigned long long lo = c * mant, hi = __umul64hi(c, mant);
+    const unsigned long long add = bits128(lo, hi, 64 * lane - pos);
+    acc += add;
+    carry += acc < add ? 1ull : 0ull;
   }
+  if (overflow) {
+    if (lane == 0) {
+      st->sumM[kind - 1] = __builtin_huge_val();
+      st->wq[kind - 1] = 0.0;
+    }
+    return;
+  }
+  if (lane < kSumLimbs) {
+    s_limb[lane] = acc;
+    s_carry[lane] = carry;
+  }
+  __syncthreads();
+  if (lane != 0) return;
+  unsigned long long cin = 0ull;
+  for (int k = 0; k < kSumLimbs; ++k) {  // carries of limb k go to limb k + 1
+    const unsigned long long v = s_limb[k] + cin;
+    cin = (v < cin ? 1ull : 0ull) + s_carry[k];
+    s_limb[k] = v;
+  }
+  const unsigned long long* L = s_limb;
   int top = -1;
   for (int k = kSumLimbs - 1; k >= 0 && top < 0; --k)
-    if (acc[k]) top = 64 * k + 63 - __clzll((long long)acc[k]);
+    if (L[k]) top = 64 * k + 63 - __clzll((long long)L[k]);
   double sum = 0.0;
   if (top >= 0 && top < 53) {
-    sum = ldexp((double)acc[0], -1074);  // fewer than 53 bits: exact
+    sum = ldexp((double)L[0], -1074);  // fewer than 53 bits: exact
   } else if (top >= 53) {
-    unsigned long long mant = limbs_bits(acc, top - 52, 53);
-    const unsigned long long rnd = limbs_bits(acc, top - 53, 1);
+    unsigned long long mant = limbs_bits(L, top - 52, 53);
+    const unsigned long long rnd = limbs_bits(L, top - 53, 1);
     bool sticky = false;
     const int below = top - 53;  // bits [0, below) decide a tie
-    for (int k = 0; k < (below >> 6) && !sticky; ++k) sticky = acc[k] != 0ull;
-    if (!sticky && (below & 63)) sticky = limbs_bits(acc, below & ~63, below & 63) != 0ull;
+    for (int k = 0; k < (below >> 6) && !sticky; ++k) sticky = L[k] != 0ull;
+    if (!sticky && (below & 63)) sticky = limbs_bits(L, below & ~63, below & 63) != 0ull;
     int ex = top - 52 - 1074;
     if (rnd && (sticky || (mant & 1ull))) {
       mant += 1ull;
@@ -378,7 +396,7 @@ hipError_t launch_emission_plan(const double* qn, long long n_cells, double adt,
   long long b = (n_cells + 255) / 256;
   int grid = (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
   hipLaunchKernelGGL(k_maj_hist, dim3(grid), dim3(256), 0, s, qn, n_cells, hist);
-  hipLaunchKernelGGL(k_maj_sum, dim3(1), dim3(256), 0, s, hist, adt, n_src, kind, st);
+  hipLaunchKernelGGL(k_maj_sum, dim3(1), dim3(64), 0, s, hist, adt, n_src, kind, st);
   b = (L + 255) / 256;
   grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
   hipLaunchKernelGGL(k_count_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, L, adt, seed,

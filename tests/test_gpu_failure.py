@@ -78,23 +78,29 @@ def test_allocator_failure_releases_everything(S):
 
 
 def test_source_iteration_limit_reports_not_converged(S):
-    """si_max_iter = 1 on a scattering problem: slh_advance returns
-    SLH_E_NOT_CONVERGED, the steps are still completed (step counter,
-    fluxes), and the stats say the last iteration did not converge."""
+    """si_max_iter = 1 on a scattering problem: slh_advance returns at once
+    (SLH_OK), slh_synchronize reports SLH_E_NOT_CONVERGED for the steps
+    since the last call (and SLH_OK after that), the steps are still
+    completed (step counter, fluxes), and the stats count the steps whose
+    iteration stopped at the limit."""
     p = _small()
     p["si_max_iter"] = 1
     s = S.Solver(p)
-    r = s.advance(2, allow_not_converged=True)
-    assert r == S.SLH_E_NOT_CONVERGED
+    assert s.advance(2) == S.SLH_OK
+    assert s.synchronize(allow_not_converged=True) == S.SLH_E_NOT_CONVERGED
+    assert "si_max_iter" in S.lib().slh_last_error().decode()
+    assert s.synchronize() == S.SLH_OK
     st = s.get_stats()
-    assert st["step"] == 2 and st["si_iterations"] == 1 and st["si_converged"] == 0
+    assert st["step"] == 2 and st["steps_total"] == 2
+    assert st["si_iterations"] == 1 and st["si_converged"] == 0
+    assert st["si_unconverged_total"] == 2
     assert np.all(np.isfinite(s.get_flux(0))) and s.get_flux(0).sum() > 0
     s.destroy()
 
 
 def test_overflowing_source_reports_numeric(S):
     """A source so large that a cell majorant overflows (q = 1e308 rounds up
-    to 2^1024): no particle is emitted from it, and slh_advance returns
+    to 2^1024): no particle is emitted from it, and slh_synchronize returns
     SLH_E_NUMERIC with a message that names the majorant."""
     from paper_2511_16821_amd import workloads as W
     n = 4
@@ -103,10 +109,12 @@ def test_overflowing_source_reports_numeric(S):
     p = W._problem(n, n, (0.0, 4.0, 0.0, 4.0), np.full((n, n), 0.5), np.full((n, n), 0.5), q,
                    n_s=0, n_particles=1000, sn_order=2, dt=0.1)
     s = S.Solver(p)
+    assert s.advance(1) == S.SLH_OK
     with pytest.raises(S.SlhError) as e:
-        s.advance(1)
+        s.synchronize()
     assert e.value.status == S.SLH_E_NUMERIC
     assert "majorant" in str(e.value)
+    assert s.get_stats()["numeric_flags"] & 1
     s.destroy()
 
 

@@ -313,17 +313,23 @@ def test_checkpoint_resume_bitwise(S):
 
 
 def test_graph_replay_matches_eager(S):
-    """Step parts replayed from HIP graphs give bitwise the results of direct
-    launches, replay after replay (both bank parities, eager work of another
-    solver interleaved between the replays)."""
+    """Whole steps replayed from one HIP graph each give bitwise the results
+    of direct launches and of timing mode (three graphs and two MC kernels
+    between events), replay after replay (both bank parities, eager work of
+    another solver interleaved between the replays), and slh_advance never
+    waits for the device."""
     from paper_2511_16821_amd import workloads as W
     p = W.checkerboard(blocks=5, cells_per_block=4, n_s=2, n_particles=30000, dt=0.05,
                        sn_order=4)
-    eager, graph = S.Solver(p), S.Solver(p)
+    eager, graph, timed = S.Solver(p), S.Solver(p), S.Solver(p)
     eager.set_graphs(False)
+    timed.set_timing(True)
     for k in range(7):
         eager.advance(1)
         graph.advance(1)
+        timed.advance(1)
+        for which in (S.SLH_FLUX_REMAP, S.SLH_FLUX_COLLIDED_NODAL):
+            assert np.array_equal(timed.get_flux(which), graph.get_flux(which)), (k, which)
         for which in (S.SLH_FLUX_REMAP, S.SLH_FLUX_PRE, S.SLH_FLUX_POST,
                       S.SLH_FLUX_COLLIDED_NODAL):
             assert np.array_equal(eager.get_flux(which), graph.get_flux(which)), (k, which)
@@ -335,11 +341,22 @@ def test_graph_replay_matches_eager(S):
         assert se["segments_total"] == sg["segments_total"]
     st = graph.get_stats()
     log("graph launches", st["graph_launches_total"], "host waits", st["host_waits_total"])
-    assert st["graph_launches_total"] == 4 * 7  # four graph parts per step
-    assert st["host_waits_total"] <= 7 + 4
+    assert st["graph_launches_total"] == 7  # one graph per step
+    assert st["host_waits_total"] == 0
+    assert st["ms_kernel_mc_total"] == 0.0  # no events outside timing mode
+    tt = timed.get_stats()
+    assert tt["graph_launches_total"] == 3 * 7
+    assert tt["ms_kernel_mc_total"] > 0.0 and tt["ms_kernel_remap_total"] > 0.0
+    assert tt["ms_mc"] > 0.0 and tt["ms_dg"] > 0.0
     assert eager.get_stats()["graph_launches_total"] == 0
-    eager.destroy()
-    graph.destroy()
+    # several steps in one call: the same results, the outcome at synchronize
+    many = S.Solver(p)
+    many.advance(7)
+    assert many.synchronize() == S.SLH_OK
+    assert np.array_equal(many.get_flux(0), graph.get_flux(0))
+    assert many.get_stats()["steps_total"] == 7
+    for s in (eager, graph, timed, many):
+        s.destroy()
 
 
 @pytest.mark.parametrize("which", ["c3", "c5"])

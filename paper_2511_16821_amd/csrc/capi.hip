@@ -137,8 +137,24 @@ struct Sizes {
   long long dg_chunks;
   bool diffusion;  // diffusion closing stage: no direction planes, CG vectors instead
   bool dsa;        // S_N with the diffusion correction: planes, CG vectors and dnode
+  // tracking materials: with at most kMaxMatIds distinct (sigma_s, sigma_a)
+  // pairs, a 16-bit id per cell and a table (n_mc_mat entries); else none
+  // (n_mc_mat = 0) and the kernels read the per-cell arrays
+  int n_mc_mat;
   size_t bytes;
 };
+
+constexpr int kMaxMatIds = 65535;
+
+// Sorted distinct (sigma_s, sigma_a) pairs of the problem's cells.
+static std::vector<std::pair<double, double>> material_pairs(const slh_problem* p) {
+  const long long n = (long long)p->nx * p->ny;
+  std::vector<std::pair<double, double>> v(n);
+  for (long long i = 0; i < n; ++i) v[i] = std::make_pair(p->sigma_s[i], p->sigma_a[i]);
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  return v;
+}
 
 // tau/(c dt), the time closure of the collided solve; none in steady state
 static double time_term(const slh_problem* p) {
@@ -309,11 +325,18 @@ static Sizes sizes_of(const slh_problem* p) {
   z.dsa = !z.diffusion && p->si_accel == SLH_ACCEL_DSA;
   const bool fields = p->sigma_s && p->sigma_a;
   plan_dg(z, p, fields ? (long long)material_values(p).size() : -1);
-  const size_t rb = z.fp32 ? 4 : 8;
-  const size_t bank = 5 * rb + 4 + 8;
+  if (fields) {
+    const long long m = (long long)material_pairs(p).size();
+    z.n_mc_mat = m <= kMaxMatIds ? (int)m : 0;
+  } else {
+    z.n_mc_mat = kMaxMatIds;  // bound
+  }
+  const size_t bank = z.fp32 ? sizeof(StageRec<float>) : sizeof(StageRec<double>);
+  const size_t srec = z.fp32 ? sizeof(SrcRec<float>) : sizeof(SrcRec<double>);
   size_t b = 0;
   const size_t nc = (size_t)z.n_cells;
   b += nc * (16 + 8 + 8 + 8 + 8);            // mat64, mat32, sig_s, sig_e, q
+  if (z.n_mc_mat) b += nc * 2 + (size_t)z.n_mc_mat * 24;  // material ids and tables
   if (p->n_s_cell) b += nc * 4;              // per-cell scatter limits
   if (p->boundary)                           // mirror indices, reflected traces
     b += (size_t)z.n_dir * 8 + (size_t)2 * z.n_dir * 2 * (p->nx + p->ny) * 8;
@@ -329,7 +352,7 @@ static Sizes sizes_of(const slh_problem* p) {
   if (z.dg_table) b += nc * 4 + (size_t)z.n_mat * 8 + (size_t)z.n_dir * z.n_mat * 256;
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
   b += (size_t)z.cap * bank * 2;             // census banks
-  b += (size_t)(z.n_src_cap > 0 ? z.n_src_cap : 1) * (7 * rb + 8);  // source bank
+  b += (size_t)(z.n_src_cap > 0 ? z.n_src_cap : 1) * srec;  // source bank
   b += (size_t)z.n_cand * ((z.fp32 ? 32 : 64) + 1 + 8 + 8);  // staging, alive, flags, scan
   b += scan_tmp_elems(z.n_cand) * 8;
   b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8 + kCensusBlocks * 8;
@@ -453,6 +476,9 @@ struct slh_solver {
   // device memory
   double2* mat64 = nullptr;
   float2* mat32 = nullptr;
+  uint16_t* mat_id16 = nullptr;  // tracking: material id per cell, and its tables
+  double2* mtab64 = nullptr;
+  float2* mtab32 = nullptr;
   double *sig_s = nullptr, *sig_e = nullptr, *q = nullptr;
   double *qn1 = nullptr, *ctree1 = nullptr;  // nodal source and count tree of each pass
   double *qnR = nullptr, *ctreeR = nullptr;
@@ -535,39 +561,14 @@ struct slh_solver {
     ev_pool.clear();
   }
 
-  template <typename R> Bank<R> bank_at(void* base, long long n) const {
-    Bank<R> b;
-    char* p = (char*)base;
-    b.px = (R*)p; p += sizeof(R) * n;
-    b.py = (R*)p; p += sizeof(R) * n;
-    b.ox = (R*)p; p += sizeof(R) * n;
-    b.oy = (R*)p; p += sizeof(R) * n;
-    b.w = (R*)p; p += sizeof(R) * n;
-    b.hid = (uint64_t*)p; p += sizeof(uint64_t) * n;
-    b.cell = (int32_t*)p;
-    return b;
+  // census bank: an array of census records; source particles: an array of
+  // source records (each record one piece of a cache line)
+  size_t rec_bytes() const {
+    return z.fp32 ? sizeof(StageRec<float>) : sizeof(StageRec<double>);
   }
-  size_t bank_bytes(long long n) const {
-    const size_t rb = z.fp32 ? 4 : 8;
-    return (size_t)n * (5 * rb + 8 + 4);
-  }
-  template <typename R> SrcBank<R> src_at(void* base, long long n) const {
-    SrcBank<R> b;
-    R* p = (R*)base;
-    b.px = p; p += n;
-    b.py = p; p += n;
-    b.ox = p; p += n;
-    b.oy = p; p += n;
-    b.w = p; p += n;
-    b.trel = p; p += n;
-    b.tau = p; p += n;
-    b.cell = (int32_t*)p;
-    b.lidx = (uint32_t*)(b.cell + n);
-    return b;
-  }
+  size_t bank_bytes(long long n) const { return (size_t)(n > 0 ? n : 1) * rec_bytes(); }
   size_t src_bytes(long long n) const {
-    const size_t rb = z.fp32 ? 4 : 8;
-    return (size_t)(n > 0 ? n : 1) * (7 * rb + 8);
+    return (size_t)(n > 0 ? n : 1) * (z.fp32 ? sizeof(SrcRec<float>) : sizeof(SrcRec<double>));
   }
 };
 
@@ -584,6 +585,11 @@ static slh_status setup(slh_solver* s) {
     return fail(SLH_E_INVALID_ARG, "nx + ny too large for the sweep's LDS traces");
   ALLOC(s->mat64, double2, nc);
   ALLOC(s->mat32, float2, nc);
+  if (z.n_mc_mat) {
+    ALLOC(s->mat_id16, uint16_t, nc);
+    ALLOC(s->mtab64, double2, z.n_mc_mat);
+    ALLOC(s->mtab32, float2, z.n_mc_mat);
+  }
   ALLOC(s->sig_s, double, nc);
   ALLOC(s->sig_e, double, nc);
   ALLOC(s->q, double, nc);
@@ -660,6 +666,30 @@ static slh_status setup(slh_solver* s) {
   hipStream_t st = s->stream;
   HIP_TRY(hipMemcpyAsync(s->mat64, m64.data(), sizeof(double2) * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->mat32, m32.data(), sizeof(float2) * nc, hipMemcpyHostToDevice, st));
+  std::vector<uint16_t> mid16;
+  std::vector<double2> t64;
+  std::vector<float2> t32;
+  if (z.n_mc_mat) {
+    std::vector<std::pair<double, double>> pairs;
+    pairs.reserve(nc);
+    for (long long i = 0; i < nc; ++i) pairs.emplace_back(s->h_sig_s[i], s->h_sig_a[i]);
+    std::vector<std::pair<double, double>> uniq(pairs);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    if ((long long)uniq.size() != z.n_mc_mat) return fail(SLH_E_STATE, "material count changed");
+    mid16.resize(nc);
+    for (long long i = 0; i < nc; ++i)
+      mid16[i] = (uint16_t)(std::lower_bound(uniq.begin(), uniq.end(), pairs[i]) - uniq.begin());
+    for (const auto& u : uniq) {
+      t64.push_back(make_double2(u.first, u.second));
+      t32.push_back(make_float2((float)u.first, (float)u.second));
+    }
+    HIP_TRY(hipMemcpyAsync(s->mat_id16, mid16.data(), 2 * nc, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->mtab64, t64.data(), sizeof(double2) * t64.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->mtab32, t32.data(), sizeof(float2) * t32.size(),
+                           hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(hipMemcpyAsync(s->sig_s, s->h_sig_s.data(), 8 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->sig_e, se.data(), 8 * nc, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->q, s->h_q.data(), 8 * nc, hipMemcpyHostToDevice, st));
@@ -737,6 +767,9 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.keep_census = p.steady ? 0 : 1;
   a.mat64 = s->mat64;
   a.mat32 = s->mat32;
+  a.mat_id16 = s->mat_id16;
+  a.mtab64 = s->mtab64;
+  a.mtab32 = s->mtab32;
   a.ctree = kind == 1 ? s->ctree1 : s->ctreeR;
   a.adt = s->adt;
   a.tree_L = s->tree_L;
@@ -756,13 +789,13 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.max_segments = 1u << 26;
   void* bin = s->bank_mem[s->cur];
   if (s->z.fp32) {
-    a.in32 = s->bank_at<float>(bin, s->z.cap);
+    a.in32 = (const StageRec<float>*)bin;
     a.out32 = (StageRec<float>*)s->stage_mem;
-    a.src32 = s->src_at<float>(s->src_mem, s->z.n_src_cap);
+    a.src32 = (SrcRec<float>*)s->src_mem;
   } else {
-    a.in64 = s->bank_at<double>(bin, s->z.cap);
+    a.in64 = (const StageRec<double>*)bin;
     a.out64 = (StageRec<double>*)s->stage_mem;
-    a.src64 = s->src_at<double>(s->src_mem, s->z.n_src_cap);
+    a.src64 = (SrcRec<double>*)s->src_mem;
   }
   a.alive = s->alive;
   a.out_src_base = s->z.cap;
@@ -956,15 +989,14 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
         const StageRec<float>* src = (const StageRec<float>*)s->stage_mem;
         HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
         HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
-        HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, z.cap,
-                                             s->bank_at<float>(nb, z.cap), s->st, s->cmax, st));
+        HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, z.cap, (StageRec<float>*)nb,
+                                             s->st, s->cmax, st));
       } else {
         const StageRec<double>* src = (const StageRec<double>*)s->stage_mem;
         HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
         HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
         HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand, z.cap,
-                                              s->bank_at<double>(nb, z.cap), s->st, s->cmax,
-                                              st));
+                                              (StageRec<double>*)nb, s->st, s->cmax, st));
       }
       HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, z.cap, s->cmax, st));
       return SLH_OK;
@@ -1382,6 +1414,42 @@ extern "C" slh_status slh_get_stats(slh_solver* s, slh_stats* out) {
   return SLH_OK;
 }
 
+// The first cnt census records of the current bank, as host fields in the
+// solver's precision (px, py: cell-local).
+template <typename R>
+static slh_status read_bank(slh_solver* s, long long cnt, std::vector<R>* f5,
+                            std::vector<int32_t>& cell, std::vector<uint64_t>& hid) {
+  std::vector<StageRec<R>> recs(cnt);
+  COPY_SYNC(recs.data(), s->bank_mem[s->cur], sizeof(StageRec<R>) * cnt, hipMemcpyDeviceToHost);
+  for (int k = 0; k < 5; ++k) f5[k].resize(cnt);
+  cell.resize(cnt);
+  hid.resize(cnt);
+  for (long long i = 0; i < cnt; ++i) {
+    const StageRec<R>& r = recs[i];
+    f5[0][i] = r.px; f5[1][i] = r.py; f5[2][i] = r.ox; f5[3][i] = r.oy; f5[4][i] = r.w;
+    cell[i] = r.cell;
+    hid[i] = r.hid;
+  }
+  return SLH_OK;
+}
+
+// Writes cnt census records into the current bank from SoA host arrays.
+template <typename R>
+static slh_status write_bank(slh_solver* s, long long cnt, const R* const* f5,
+                             const int32_t* cell, const uint64_t* hid) {
+  std::vector<StageRec<R>> recs(cnt);
+  for (long long i = 0; i < cnt; ++i) {
+    StageRec<R>& r = recs[i];
+    memset(&r, 0, sizeof(r));
+    r.px = f5[0][i]; r.py = f5[1][i]; r.ox = f5[2][i]; r.oy = f5[3][i]; r.w = f5[4][i];
+    r.cell = cell[i];
+    r.hid = hid[i];
+  }
+  if (cnt) COPY_SYNC(s->bank_mem[s->cur], recs.data(), sizeof(StageRec<R>) * cnt,
+                     hipMemcpyHostToDevice);
+  return SLH_OK;
+}
+
 extern "C" slh_status slh_get_census(slh_solver* s, int64_t* n, double* x, double* y,
                                      double* ox, double* oy, double* w, int32_t* cell,
                                      uint64_t* hid) {
@@ -1393,38 +1461,25 @@ extern "C" slh_status slh_get_census(slh_solver* s, int64_t* n, double* x, doubl
   *n = cnt;
   if (cnt == 0) return SLH_OK;
   const slh_problem& p = s->prob;
-  std::vector<int32_t> c(cnt);
-  std::vector<double> px(cnt), py(cnt), vx(cnt), vy(cnt), vw(cnt);
-  std::vector<uint64_t> h(cnt);
-  void* base = s->bank_mem[s->cur];
+  std::vector<int32_t> c;
+  std::vector<uint64_t> h;
+  std::vector<double> f[5];
   if (s->z.fp32) {
-    Bank<float> b = s->bank_at<float>(base, s->z.cap);
-    std::vector<float> t(cnt);
-    float* srcs[5] = {b.px, b.py, b.ox, b.oy, b.w};
-    std::vector<double>* dsts[5] = {&px, &py, &vx, &vy, &vw};
-    for (int k = 0; k < 5; ++k) {
-      COPY_SYNC(t.data(), srcs[k], 4 * cnt, hipMemcpyDeviceToHost);
-      for (long long i = 0; i < cnt; ++i) (*dsts[k])[i] = t[i];
-    }
-    COPY_SYNC(c.data(), b.cell, 4 * cnt, hipMemcpyDeviceToHost);
-    COPY_SYNC(h.data(), b.hid, 8 * cnt, hipMemcpyDeviceToHost);
+    std::vector<float> t[5];
+    const slh_status r = read_bank<float>(s, cnt, t, c, h);
+    if (r != SLH_OK) return r;
+    for (int k = 0; k < 5; ++k) f[k].assign(t[k].begin(), t[k].end());
   } else {
-    Bank<double> b = s->bank_at<double>(base, s->z.cap);
-    COPY_SYNC(px.data(), b.px, 8 * cnt, hipMemcpyDeviceToHost);
-    COPY_SYNC(py.data(), b.py, 8 * cnt, hipMemcpyDeviceToHost);
-    COPY_SYNC(vx.data(), b.ox, 8 * cnt, hipMemcpyDeviceToHost);
-    COPY_SYNC(vy.data(), b.oy, 8 * cnt, hipMemcpyDeviceToHost);
-    COPY_SYNC(vw.data(), b.w, 8 * cnt, hipMemcpyDeviceToHost);
-    COPY_SYNC(c.data(), b.cell, 4 * cnt, hipMemcpyDeviceToHost);
-    COPY_SYNC(h.data(), b.hid, 8 * cnt, hipMemcpyDeviceToHost);
+    const slh_status r = read_bank<double>(s, cnt, f, c, h);
+    if (r != SLH_OK) return r;
   }
   for (long long i = 0; i < cnt; ++i) {
     const int ix = c[i] % p.nx, iy = c[i] / p.nx;
-    if (x) x[i] = p.x_lo + s->hx * ix + px[i];
-    if (y) y[i] = p.y_lo + s->hy * iy + py[i];
-    if (ox) ox[i] = vx[i];
-    if (oy) oy[i] = vy[i];
-    if (w) w[i] = vw[i];
+    if (x) x[i] = p.x_lo + s->hx * ix + f[0][i];
+    if (y) y[i] = p.y_lo + s->hy * iy + f[1][i];
+    if (ox) ox[i] = f[2][i];
+    if (oy) oy[i] = f[3][i];
+    if (w) w[i] = f[4][i];
     if (cell) cell[i] = c[i];
     if (hid) hid[i] = h[i];
   }
@@ -1443,7 +1498,7 @@ extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
   DevState d;
   COPY_SYNC(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
   const long long cnt = d.n_in;
-  const size_t need = kCkptHead + s->bank_bytes(cnt);
+  const size_t need = kCkptHead + (size_t)cnt * ((s->z.fp32 ? 4 : 8) * 5 + 8 + 4);
   if (!buf) { *len = need; return SLH_OK; }
   if (*len < need) return fail(SLH_E_INVALID_ARG, "buffer too small");
   uint64_t* h = (uint64_t*)buf;
@@ -1458,17 +1513,25 @@ extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
   h[8] = s->prob.seed;
   h[9] = (uint64_t)s->z.cap;
   char* out = (char*)buf + kCkptHead;
-  const size_t rb = s->z.fp32 ? 4 : 8;
-  // the bank arrays are laid out with stride cap; copy each array's prefix
-  char* base = (char*)s->bank_mem[s->cur];
-  const long long cap = s->z.cap;
-  for (int k = 0; k < 5; ++k) {
-    COPY_SYNC(out, base + (size_t)k * rb * cap, rb * cnt, hipMemcpyDeviceToHost);
-    out += rb * cnt;
+  if (cnt > 0) {
+    std::vector<int32_t> c;
+    std::vector<uint64_t> hh;
+    const size_t rb = s->z.fp32 ? 4 : 8;
+    if (s->z.fp32) {
+      std::vector<float> f[5];
+      const slh_status r = read_bank<float>(s, cnt, f, c, hh);
+      if (r != SLH_OK) return r;
+      for (int k = 0; k < 5; ++k, out += rb * cnt) memcpy(out, f[k].data(), rb * cnt);
+    } else {
+      std::vector<double> f[5];
+      const slh_status r = read_bank<double>(s, cnt, f, c, hh);
+      if (r != SLH_OK) return r;
+      for (int k = 0; k < 5; ++k, out += rb * cnt) memcpy(out, f[k].data(), rb * cnt);
+    }
+    memcpy(out, hh.data(), 8 * cnt);
+    out += 8 * cnt;
+    memcpy(out, c.data(), 4 * cnt);
   }
-  COPY_SYNC(out, base + 5 * rb * cap, 8 * cnt, hipMemcpyDeviceToHost);
-  out += 8 * cnt;
-  COPY_SYNC(out, base + 5 * rb * cap + 8 * cap, 4 * cnt, hipMemcpyDeviceToHost);
   *len = need;
   return SLH_OK;
 }
@@ -1509,7 +1572,9 @@ extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
   if (h[8] != s->prob.seed) return fail(SLH_E_INVALID_ARG, "checkpoint has another seed");
   const long long cnt = (long long)h[4];
   if (cnt < 0 || cnt > s->z.cap) return fail(SLH_E_INVALID_ARG, "checkpoint bank exceeds the cap");
-  if (len < kCkptHead + s->bank_bytes(cnt)) return fail(SLH_E_INVALID_ARG, "checkpoint truncated");
+  const size_t rb = s->z.fp32 ? 4 : 8;
+  if (len < kCkptHead + (size_t)cnt * (rb * 5 + 8 + 4))
+    return fail(SLH_E_INVALID_ARG, "checkpoint truncated");
   double maxabs;
   memcpy(&maxabs, &h[5], 8);
   const char* in = (const char*)buf + kCkptHead;
@@ -1517,16 +1582,21 @@ extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
                             : ckpt_bank_ok<double>(in, cnt, s->z.n_cells, s->hx, s->hy, maxabs);
   if (!ok) return fail(SLH_E_INVALID_ARG, "checkpoint particles are not valid for this problem");
   HIP_TRY(hipStreamSynchronize(s->stream));
-  const size_t rb = s->z.fp32 ? 4 : 8;
-  char* base = (char*)s->bank_mem[s->cur];
-  const long long cap = s->z.cap;
-  for (int k = 0; k < 5; ++k) {
-    COPY_SYNC(base + (size_t)k * rb * cap, in, rb * cnt, hipMemcpyHostToDevice);
-    in += rb * cnt;
+  {
+    const uint64_t* hh = (const uint64_t*)(in + rb * 5 * cnt);
+    const int32_t* cc = (const int32_t*)(in + rb * 5 * cnt + 8 * cnt);
+    slh_status r;
+    if (s->z.fp32) {
+      const float* f[5];
+      for (int k = 0; k < 5; ++k) f[k] = (const float*)(in + rb * k * cnt);
+      r = write_bank<float>(s, cnt, f, cc, hh);
+    } else {
+      const double* f[5];
+      for (int k = 0; k < 5; ++k) f[k] = (const double*)(in + rb * k * cnt);
+      r = write_bank<double>(s, cnt, f, cc, hh);
+    }
+    if (r != SLH_OK) return r;
   }
-  COPY_SYNC(base + 5 * rb * cap, in, 8 * cnt, hipMemcpyHostToDevice);
-  in += 8 * cnt;
-  COPY_SYNC(base + 5 * rb * cap + 8 * cap, in, 4 * cnt, hipMemcpyHostToDevice);
   hipLaunchKernelGGL(k_state_set_bank, dim3(1), dim3(1), 0, s->stream, s->st, cnt, maxabs,
                      (unsigned long long)h[2]);
   HIP_TRY(hipGetLastError());

@@ -29,16 +29,18 @@ template <> struct Real<double> {
   static __device__ __forceinline__ void scpi(double x, double* s, double* c) {
     sincospi(x, s, c);
   }
-  static __device__ __forceinline__ const SrcBank<double>& src(const PassArgs& a) {
-    return a.src64;
-  }
+  static __device__ __forceinline__ SrcRec<double>* src(const PassArgs& a) { return a.src64; }
   // w e^{-z} = w + w (e^{-z} - 1): the weight minus what the segment removed
   static __device__ __forceinline__ double attenuate(double w, double, double em) {
     return fma(w, em, w);
   }
-  static __device__ __forceinline__ double2 mat(const PassArgs& a, int c) { return a.mat64[c]; }
+  static __device__ __forceinline__ double2 mat(const PassArgs& a, int c) {
+    return a.mat_id16 ? a.mtab64[a.mat_id16[c]] : a.mat64[c];
+  }
   static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
-  static __device__ __forceinline__ const Bank<double>& in(const PassArgs& a) { return a.in64; }
+  static __device__ __forceinline__ const StageRec<double>* in(const PassArgs& a) {
+    return a.in64;
+  }
   static __device__ __forceinline__ StageRec<double>* out(const PassArgs& a) { return a.out64; }
   static __device__ __forceinline__ void stage(StageRec<double>* p, double px, double py,
                                                double ox, double oy, double w, uint64_t hid,
@@ -49,21 +51,33 @@ template <> struct Real<double> {
     o[2] = make_double2(w, __longlong_as_double((long long)hid));
     o[3] = make_double2(__longlong_as_double((long long)(unsigned)cell), 0.0);
   }
+  static __device__ __forceinline__ void put_src(SrcRec<double>* p, double px, double py,
+                                                 double ox, double oy, double w, double trel,
+                                                 double tau, int cell, uint32_t lidx) {
+    double2* o = reinterpret_cast<double2*>(p);
+    o[0] = make_double2(px, py);
+    o[1] = make_double2(ox, oy);
+    o[2] = make_double2(w, trel);
+    o[3] = make_double2(tau, __longlong_as_double((long long)(((uint64_t)lidx << 32) |
+                                                              (uint32_t)cell)));
+  }
 };
 template <> struct Real<float> {
   using V2 = float2;
   static __device__ __forceinline__ void scpi(float x, float* s, float* c) {
     sincospif(x, s, c);
   }
-  static __device__ __forceinline__ const SrcBank<float>& src(const PassArgs& a) {
-    return a.src32;
-  }
+  static __device__ __forceinline__ SrcRec<float>* src(const PassArgs& a) { return a.src32; }
   static __device__ __forceinline__ float attenuate(float w, float z, float) {
     return w * expf(-z);
   }
-  static __device__ __forceinline__ float2 mat(const PassArgs& a, int c) { return a.mat32[c]; }
+  static __device__ __forceinline__ float2 mat(const PassArgs& a, int c) {
+    return a.mat_id16 ? a.mtab32[a.mat_id16[c]] : a.mat32[c];
+  }
   static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
-  static __device__ __forceinline__ const Bank<float>& in(const PassArgs& a) { return a.in32; }
+  static __device__ __forceinline__ const StageRec<float>* in(const PassArgs& a) {
+    return a.in32;
+  }
   static __device__ __forceinline__ StageRec<float>* out(const PassArgs& a) { return a.out32; }
   static __device__ __forceinline__ void stage(StageRec<float>* p, float px, float py, float ox,
                                                float oy, float w, uint64_t hid, int cell) {
@@ -71,6 +85,14 @@ template <> struct Real<float> {
     o[0] = make_float4(px, py, ox, oy);
     o[1] = make_float4(w, __int_as_float(cell), __uint_as_float((unsigned)hid),
                        __uint_as_float((unsigned)(hid >> 32)));
+  }
+  static __device__ __forceinline__ void put_src(SrcRec<float>* p, float px, float py, float ox,
+                                                 float oy, float w, float trel, float tau,
+                                                 int cell, uint32_t lidx) {
+    float4* o = reinterpret_cast<float4*>(p);
+    o[0] = make_float4(px, py, ox, oy);
+    o[1] = make_float4(w, trel, tau, __int_as_float(cell));
+    o[2] = make_float4(__uint_as_float(lidx), 0.f, 0.f, 0.f);
   }
 };
 
@@ -127,6 +149,40 @@ __device__ __forceinline__ void tally_add(unsigned long long* p, unsigned long l
   else atomicAdd(p, v);
 }
 
+// The tally adds of one loop iteration of a wave (lane: word p, value v; p
+// null for no add), with every lane of the wave active.  Lanes adding to the
+// same word are summed first and their sum is added by one lane, since many
+// lanes of a wave often sit in the same cell (particles are numbered in cell
+// order, and a busy cell near a source receives thousands of adds at once),
+// where the atomics would queue one after another on the word.  Words are
+// taken in lane order; as soon as a word has a single adder, the remaining
+// lanes add directly, so a wave whose lanes are spread over many cells pays
+// only one vote.  Integer sums: the result is the same as with one atomic
+// per lane.
+__device__ __forceinline__ void wave_tally_add(unsigned long long* p, unsigned long long v,
+                                               int xl) {
+  unsigned long long pending = __ballot(p != nullptr);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const unsigned long long pp = (unsigned long long)p;
+    const unsigned long long pl =
+        (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)pp, leader) |
+        ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(pp >> 32),
+                                                                leader) << 32);
+    const bool mine = p != nullptr && pp == pl;
+    const unsigned long long same = __ballot(mine);
+    if (__popcll(same) == 1) {
+      if (p) tally_add(p, v, xl);
+      return;
+    }
+    unsigned long long sum = mine ? v : 0ull;
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if ((int)__lane_id() == leader) tally_add(p, sum, xl);
+    if (mine) p = nullptr;
+    pending &= ~same;
+  }
+}
+
 // Copies of a tracking block's balance in LDS (odd stride: the copies start
 // in different banks).
 constexpr int kBalCopies = 8;
@@ -166,7 +222,7 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   const uint64_t step = a.st->step;
   const double wq = a.st->wq[KIND - 1];
   const R hx = (R)a.hx, hy = (R)a.hy, dt_birth = (R)a.dt_birth;
-  const SrcBank<R> b = Real<R>::src(a);
+  SrcRec<R>* const b = Real<R>::src(a);
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n_emit;
        s += (long long)gridDim.x * blockDim.x) {
     const CellPick pk = count_pick(a.ctree, s_top, a.tree_L, s);
@@ -183,16 +239,12 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
     Real<R>::scpi((R)2 * u5, &sp, &cp);
     const double* q = a.qn + 4 * ci;
     const double wscale = wq / pow2_ceil(maxabs4(q));  // exact: a power-of-two ratio
-    b.px[s] = hx * u1;
-    b.py[s] = hy * u2;
-    b.ox[s] = sn * cp;
-    b.oy[s] = sn * sp;
-    b.w[s] = (R)(bilinear(q, (double)u1, (double)u2) * wscale);
-    b.trel[s] = u3 * dt_birth;
-    b.tau[s] = a.n_lim > 0 ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, l)))
-                           : (R)0;
-    b.cell[s] = (int32_t)ci;
-    b.lidx[s] = l;
+    const R w = (R)(bilinear(q, (double)u1, (double)u2) * wscale);
+    const R tau = a.n_lim > 0
+                      ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, l)))
+                      : (R)0;
+    Real<R>::put_src(b + s, hx * u1, hy * u2, sn * cp, sn * sp, w, u3 * dt_birth, tau,
+                     (int)ci, l);
   }
 }
 
@@ -223,13 +275,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const uint64_t step = st->step;
   const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt, c = (R)a.c;
   const R INF = Real<R>::inf();
-  const Bank<R> bin = Real<R>::in(a);
+  const StageRec<R>* const bin = Real<R>::in(a);
   StageRec<R>* const bout = Real<R>::out(a);
   const int n_lim = a.n_lim;
 
   bool have = false;
-  // the tally atomic waiting to be issued; until the first real tally it adds 0
-  // to a word picked per lane, so the zero adds do not pile onto one address
   const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long t_all = (long long)gridDim.x * blockDim.x;
   long long next = gtid;
@@ -242,9 +292,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int per = xl ? a.n_copies / kNumXcd : a.n_copies;
   const long long my_copy =
       ((xl ? (long long)(xcc % kNumXcd) * per : 0ll) + gtid % per) * a.copy_stride;
-  unsigned long long* pend_ptr = a.Ta + my_copy + kTallyStride * (gtid % a.n_cells);
-  unsigned long long pend_val = 0ull;
   long long g = 0;
+  unsigned long long* p_ptr = nullptr;  // the lane's pending tally word and sum
+  unsigned long long p_val = 0ull;
+  // material of the history's current cell, loaded when the history starts
+  // and, after a face crossing, at the end of the iteration, so that the
+  // gather is in flight while the loop turns around
+  typename Real<R>::V2 m_cur;
+  m_cur.x = (R)0;
+  m_cur.y = (R)0;
   R px = 0, py = 0, ox = 0, oy = 0, w = 0, trel = 0, tau = 0;
   R iox = 0, ioy = 0;  // 1/ox, 1/oy (0 for a zero component)
   int ix = 0, iy = 0, n = 0;
@@ -269,10 +325,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       if (g < n_in) {
         // census particle at the start of the step, counter reset
         from_census = true;
-        px = bin.px[g]; py = bin.py[g]; ox = bin.ox[g]; oy = bin.oy[g]; w = bin.w[g];
-        const int cell = bin.cell[g];
+        const StageRec<R> rec = bin[g];
+        px = rec.px; py = rec.py; ox = rec.ox; oy = rec.oy; w = rec.w;
+        const int cell = rec.cell;
         ix = cell % a.nx; iy = cell / a.nx;
-        hid = bin.hid[g];
+        hid = rec.hid;
         trel = (R)0;
         // its own stream, keyed by its identity, at point index 0
         stream = (KIND == 1 && n_lim > 0) ? stream_seed(a.seed, step, (uint32_t)KIND, 1u, hid)
@@ -282,13 +339,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       } else {
         // source particle, emitted by k_emit
         from_census = false;
-        const long long s = g - n_in;
-        const SrcBank<R> sb = Real<R>::src(a);
-        px = sb.px[s]; py = sb.py[s]; ox = sb.ox[s]; oy = sb.oy[s]; w = sb.w[s];
-        trel = sb.trel[s];
-        tau = sb.tau[s];
-        const int cell = sb.cell[s];
-        pidx = sb.lidx[s];
+        const SrcRec<R> sr = Real<R>::src(a)[g - n_in];
+        px = sr.px; py = sr.py; ox = sr.ox; oy = sr.oy; w = sr.w;
+        trel = sr.trel;
+        tau = sr.tau;
+        const int cell = sr.cell;
+        pidx = sr.lidx;
         ix = cell % a.nx; iy = cell / a.nx;
         // the birth cell's stream at the particle's index in the cell
         stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, (uint64_t)cell);
@@ -298,127 +354,145 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       iox = ox != (R)0 ? (R)1 / ox : (R)0;
       ioy = oy != (R)0 ? (R)1 / oy : (R)0;
       w0 = (double)w;
+      m_cur = Real<R>::mat(a, iy * a.nx + ix);
       if (from_census && n_lim > 0) {
         tau = -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 0u, pidx)));
         dcur = 1;
       }
     }
     if (!__any(have)) {
-      if (pend_val) tally_add(pend_ptr, pend_val, xl);
+      wave_tally_add(p_ptr, p_val, xl);  // the last pending adds
       break;
     }
-    if (!have) continue;  // an idle lane keeps its pending tally
+    // this iteration's tally word and value (none for an idle lane)
+    unsigned long long* t_ptr = nullptr;
+    unsigned long long t_val = 0ull;
+    if (have) {
 
-    // ---- one segment ----
-    const int cell = iy * a.nx + ix;
-    const typename Real<R>::V2 m = Real<R>::mat(a, cell);
-    // The previous segment's tally atomic is issued only now, after this
-    // iteration's loads, and on every segment (adding 0 when nothing is
-    // pending), so the wait for the loads does not include the atomic's
-    // round trip (memory operations retire in issue order).
-    tally_add(pend_ptr, pend_val, xl);
-    pend_val = 0ull;
-    const R ss = m.x, sa = m.y, stt = sa + ss;
-    const bool pre = n < (a.ns_cell ? a.ns_cell[cell] : n_lim);
-    R d_cen = c * (dt - trel);
-    if (d_cen < (R)0) d_cen = (R)0;
-    R d_col = INF;
-    if (pre && ss > (R)0) { d_col = tau / ss; if (d_col < (R)0) d_col = (R)0; }
-    R d_x = INF, d_y = INF;
-    if (ox > (R)0) d_x = (hx - px) * iox; else if (ox < (R)0) d_x = -px * iox;
-    if (oy > (R)0) d_y = (hy - py) * ioy; else if (oy < (R)0) d_y = -py * ioy;
-    if (d_x < (R)0) d_x = (R)0;
-    if (d_y < (R)0) d_y = (R)0;
-    R l = d_cen;
-    int ev = EV_CENSUS;
-    if (d_col < l) { l = d_col; ev = EV_COLLIDE; }
-    if (d_x < l) { l = d_x; ev = EV_XFACE; }
-    if (d_y < l) { l = d_y; ev = EV_YFACE; }
+      // ---- one segment ----
+      const int cell = iy * a.nx + ix;
+      const R ss = m_cur.x, sa = m_cur.y, stt = sa + ss;
+      const bool pre = n < (a.ns_cell ? a.ns_cell[cell] : n_lim);
+      R d_cen = c * (dt - trel);
+      if (d_cen < (R)0) d_cen = (R)0;
+      R d_col = INF;
+      if (pre && ss > (R)0) { d_col = tau / ss; if (d_col < (R)0) d_col = (R)0; }
+      R d_x = INF, d_y = INF;
+      if (ox > (R)0) d_x = (hx - px) * iox; else if (ox < (R)0) d_x = -px * iox;
+      if (oy > (R)0) d_y = (hy - py) * ioy; else if (oy < (R)0) d_y = -py * ioy;
+      if (d_x < (R)0) d_x = (R)0;
+      if (d_y < (R)0) d_y = (R)0;
+      R l = d_cen;
+      int ev = EV_CENSUS;
+      if (d_col < l) { l = d_col; ev = EV_COLLIDE; }
+      if (d_x < l) { l = d_x; ev = EV_XFACE; }
+      if (d_y < l) { l = d_y; ev = EV_YFACE; }
 
-    const R sig = pre ? sa : stt;
-    const R z = sig * l;
-    const R em = expm1(-z);  // e^{-z} - 1
-    const R contrib = (sig > (R)0) ? w * (-em) / sig : w * l;
-    {
-      const double cd = (double)contrib;
-      const long long v = fix_round(cd, inv_T);
-      pend_ptr = (pre ? a.Ta : a.Tb) + my_copy + kTallyStride * (long long)cell;
-      pend_val = (unsigned long long)v;
-      acc_abs += (double)sa * cd;
-      if (!pre) acc_sca += (double)ss * cd;
-    }
-    w = Real<R>::attenuate(w, z, em);
-    if (pre && ss > (R)0) tau -= ss * l;
-    trel += l / c;
-    seg_p++;
-
-    int end = END_NONE;
-    if (ev == EV_CENSUS) {
-      px += ox * l;
-      py += oy * l;
-      end = END_CENSUS;
-    } else if (ev == EV_COLLIDE) {
-      px += ox * l;
-      py += oy * l;
-      // isotropic re-emission, scatter counter n <- n + 1
-      const R ua = PointU<R>::u(point_u32n(s_sobol, a.points, stream, dcur, pidx));
-      const R ub = PointU<R>::u(point_u32n(s_sobol, a.points, stream, dcur + 1u, pidx));
-      dcur += 2;
-      const R sn = (R)2 * sqrt(ua * ((R)1 - ua));
-      R sp, cp;
-      Real<R>::scpi((R)2 * ub, &sp, &cp);
-      ox = sn * cp;
-      oy = sn * sp;
-      iox = ox != (R)0 ? (R)1 / ox : (R)0;
-      ioy = oy != (R)0 ? (R)1 / oy : (R)0;
-      n++;
-      if (n < n_lim) {
-        tau = -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, dcur, pidx)));
-        dcur++;
+      const R sig = pre ? sa : stt;
+      const R z = sig * l;
+      const R em = expm1(-z);  // e^{-z} - 1
+      const R contrib = (sig > (R)0) ? w * (-em) / sig : w * l;
+      // the segment's tally word, added at the end of the iteration
+      t_ptr = (pre ? a.Ta : a.Tb) + my_copy + kTallyStride * (long long)cell;
+      {
+        const double cd = (double)contrib;
+        t_val = (unsigned long long)fix_round(cd, inv_T);
+        acc_abs += (double)sa * cd;
+        if (!pre) acc_sca += (double)ss * cd;
       }
-    } else if (ev == EV_XFACE) {
-      // a reflective side mirrors the direction; the history stays in its cell
-      py += oy * l;
-      if (ox > (R)0) {
-        if (ix == a.nx - 1 && (a.bc & 2)) { px = hx; ox = -ox; iox = -iox; }
-        else { ix++; px = (R)0; }
+      w = Real<R>::attenuate(w, z, em);
+      if (pre && ss > (R)0) tau -= ss * l;
+      trel += l / c;
+      seg_p++;
+
+      int end = END_NONE;
+      if (ev == EV_CENSUS) {
+        px += ox * l;
+        py += oy * l;
+        end = END_CENSUS;
+      } else if (ev == EV_COLLIDE) {
+        px += ox * l;
+        py += oy * l;
+        // isotropic re-emission, scatter counter n <- n + 1
+        const R ua = PointU<R>::u(point_u32n(s_sobol, a.points, stream, dcur, pidx));
+        const R ub = PointU<R>::u(point_u32n(s_sobol, a.points, stream, dcur + 1u, pidx));
+        dcur += 2;
+        const R sn = (R)2 * sqrt(ua * ((R)1 - ua));
+        R sp, cp;
+        Real<R>::scpi((R)2 * ub, &sp, &cp);
+        ox = sn * cp;
+        oy = sn * sp;
+        iox = ox != (R)0 ? (R)1 / ox : (R)0;
+        ioy = oy != (R)0 ? (R)1 / oy : (R)0;
+        n++;
+        if (n < n_lim) {
+          tau = -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, dcur, pidx)));
+          dcur++;
+        }
+      } else if (ev == EV_XFACE) {
+        // a reflective side mirrors the direction; the history stays in its cell
+        py += oy * l;
+        if (ox > (R)0) {
+          if (ix == a.nx - 1 && (a.bc & 2)) { px = hx; ox = -ox; iox = -iox; }
+          else { ix++; px = (R)0; }
+        } else {
+          if (ix == 0 && (a.bc & 1)) { px = (R)0; ox = -ox; iox = -iox; }
+          else { ix--; px = hx; }
+        }
+        if (ix < 0 || ix >= a.nx) end = END_LEAK;
       } else {
-        if (ix == 0 && (a.bc & 1)) { px = (R)0; ox = -ox; iox = -iox; }
-        else { ix--; px = hx; }
+        px += ox * l;
+        if (oy > (R)0) {
+          if (iy == a.ny - 1 && (a.bc & 8)) { py = hy; oy = -oy; ioy = -ioy; }
+          else { iy++; py = (R)0; }
+        } else {
+          if (iy == 0 && (a.bc & 4)) { py = (R)0; oy = -oy; ioy = -ioy; }
+          else { iy--; py = hy; }
+        }
+        if (iy < 0 || iy >= a.ny) end = END_LEAK;
       }
-      if (ix < 0 || ix >= a.nx) end = END_LEAK;
-    } else {
-      px += ox * l;
-      if (oy > (R)0) {
-        if (iy == a.ny - 1 && (a.bc & 8)) { py = hy; oy = -oy; ioy = -ioy; }
-        else { iy++; py = (R)0; }
-      } else {
-        if (iy == 0 && (a.bc & 4)) { py = (R)0; oy = -oy; ioy = -ioy; }
-        else { iy--; py = hy; }
-      }
-      if (iy < 0 || iy >= a.ny) end = END_LEAK;
-    }
-    if (end == END_NONE && fabs(w) < w_cut) end = END_CUTOFF;
-    if (end == END_NONE && seg_p >= a.max_segments) { end = END_CUTOFF; lane_killed++; }
-    lane_seg++;
+      if (end == END_NONE && fabs(w) < w_cut) end = END_CUTOFF;
+      if (end == END_NONE && seg_p >= a.max_segments) { end = END_CUTOFF; lane_killed++; }
+      lane_seg++;
+      // the next cell's material before the tally atomic: memory operations
+      // complete in issue order, so the wait for the material at the next
+      // segment does not include the atomic's round trip
+      if (end == END_NONE && ev >= EV_XFACE) m_cur = Real<R>::mat(a, iy * a.nx + ix);
 
-    if (end != END_NONE) {
-      if (KIND == 2 && end == END_CENSUS && a.keep_census) {
-        const long long slot = from_census ? g : a.out_src_base + (g - n_in);
-        Real<R>::stage(bout + slot, px, py, ox, oy, w, hid, iy * a.nx + ix);
-        a.alive[slot] = 1;
-        lane_alive++;
+      if (end != END_NONE) {
+        if (KIND == 2 && end == END_CENSUS && a.keep_census) {
+          const long long slot = from_census ? g : a.out_src_base + (g - n_in);
+          Real<R>::stage(bout + slot, px, py, ox, oy, w, hid, iy * a.nx + ix);
+          a.alive[slot] = 1;
+          lane_alive++;
+        }
+        // fold the history's balance into the block (fixed point, exact)
+        const double wend = (double)w;
+        if (!isfinite(wend) || !isfinite(acc_abs) || !isfinite(acc_sca)) lane_bad++;
+        bal_add(my_bal, from_census ? B_CENSUS_IN_W : B_SOURCE_W, w0, inv_W);
+        bal_add(my_bal, B_ABSORBED, acc_abs, inv_W);
+        if (acc_sca != 0.0) bal_add(my_bal, B_SCATTERED, acc_sca, inv_W);
+        bal_add(my_bal, end == END_CENSUS ? B_CENSUS : (end == END_LEAK ? B_LEAKED : B_CUTOFF),
+                wend, inv_W);
+        have = false;
       }
-      // fold the history's balance into the block (fixed point, exact)
-      const double wend = (double)w;
-      if (!isfinite(wend) || !isfinite(acc_abs) || !isfinite(acc_sca)) lane_bad++;
-      bal_add(my_bal, from_census ? B_CENSUS_IN_W : B_SOURCE_W, w0, inv_W);
-      bal_add(my_bal, B_ABSORBED, acc_abs, inv_W);
-      if (acc_sca != 0.0) bal_add(my_bal, B_SCATTERED, acc_sca, inv_W);
-      bal_add(my_bal, end == END_CENSUS ? B_CENSUS : (end == END_LEAK ? B_LEAKED : B_CUTOFF),
-              wend, inv_W);
-      have = false;
     }
+    // A lane's consecutive adds to one word (segments that end in a
+    // collision or at the census stay in their cell) are summed in registers;
+    // the pending sum goes out when the lane moves to another word.
+    unsigned long long* f_ptr = nullptr;
+    unsigned long long f_val = 0ull;
+    if (t_ptr) {
+      if (t_ptr == p_ptr) {
+        p_val += t_val;
+      } else {
+        f_ptr = p_ptr;
+        f_val = p_val;
+        p_ptr = t_ptr;
+        p_val = t_val;
+      }
+    }
+    wave_tally_add(f_ptr, f_val, xl);
   }
 
   // wave totals of the integer counters, one atomic per wave

@@ -200,33 +200,23 @@ __host__ __device__ __forceinline__ double fix_value(long long hi, long long lo,
   return (double)hi * unit + (double)lo * (unit * (1.0 / kLoScale));
 }
 
-// Tally words are spaced kTallyStride apart (one cell per 16 bytes): atomics
-// of neighbouring cells then fall on fewer shared cache lines.
-constexpr int kTallyStride = 2;
+// Tally words are spaced kTallyStride apart.  One word per cell: on large
+// meshes the tally copies' footprint in the L2 matters more than the
+// sharing of cache lines between neighbouring cells' atomics.
+constexpr int kTallyStride = 1;
 
 // ---------------------------------------------------------------------------
 // Layouts
 // ---------------------------------------------------------------------------
 
-// Census bank, SoA.  px, py: position relative to the lower-left corner of
-// the cell; ox, oy: in-plane direction components; hid: unique history id
-// (birth step << 32 | source index), which also indexes the particle's points.
-template <typename R> struct Bank {
-  R* px;
-  R* py;
-  R* ox;
-  R* oy;
-  R* w;
-  int32_t* cell;
-  uint64_t* hid;
-};
-
-// Census-out staging record of one particle (written by the remap pass when
-// a history reaches the end of the step, read by the census compaction):
-// 64 B in FP64, 32 B in FP32, written as whole 16-byte words, so that a
-// particle's state reaches memory as one piece of a cache line rather than
-// seven scattered partial lines.  Layout (FP64): px py | ox oy | w hid |
-// cell (low 4 bytes) and padding; (FP32): px py ox oy | w cell hid.
+// Census record of one particle: px, py, the position relative to the
+// lower-left corner of its cell; ox, oy, the in-plane direction components;
+// w, the weight; hid, the unique history id; cell.  64 B in FP64, 32 B in
+// FP32, read and written as whole 16-byte words, so that a particle is one
+// piece of one cache line.  The census bank is an array of these records,
+// and the remap pass stages its census candidates in the same form (one
+// record per slot) before the cap and compaction.  Layout (FP64): px py |
+// ox oy | w hid | cell and padding; (FP32): px py ox oy | w cell hid.
 template <typename R> struct StageRec;
 template <> struct alignas(64) StageRec<double> {
   double px, py, ox, oy, w;
@@ -240,23 +230,27 @@ template <> struct alignas(32) StageRec<float> {
   uint64_t hid;
 };
 static_assert(sizeof(StageRec<double>) == 64 && sizeof(StageRec<float>) == 32,
-              "staging record sizes");
+              "census record sizes");
 
-// Source particles of one pass, written by the emission kernel: position in
-// the cell, direction, weight, birth time within the step, first optical
-// depth (scatter-limited pass with N_s > 0 only), cell and index within the
-// cell (the particle's point index in its cell's stream).
-template <typename R> struct SrcBank {
-  R* px;
-  R* py;
-  R* ox;
-  R* oy;
-  R* w;
-  R* trel;
-  R* tau;
-  int32_t* cell;
-  uint32_t* lidx;
+// Source particle of one pass, written by the emission kernel and read once
+// by the tracking kernel: position in the cell, direction, weight, birth time
+// within the step, first optical depth (scatter-limited pass with N_s > 0
+// only), cell and index within the cell (the particle's point index in its
+// cell's stream).  One record per particle (64 B FP64, 48 B FP32), so that a
+// history start reads one cache line rather than one line per field.
+template <typename R> struct SrcRec;
+template <> struct alignas(64) SrcRec<double> {
+  double px, py, ox, oy, w, trel, tau;
+  int32_t cell;
+  uint32_t lidx;
 };
+template <> struct alignas(16) SrcRec<float> {
+  float px, py, ox, oy, w, trel, tau;
+  int32_t cell;
+  uint32_t lidx, pad0, pad1, pad2;
+};
+static_assert(sizeof(SrcRec<double>) == 64 && sizeof(SrcRec<float>) == 48,
+              "source record sizes");
 
 // Balance fields, each a two-word fixed-point sum.
 enum BalField {
@@ -345,6 +339,12 @@ struct PassArgs {
   int keep_census;       // remap pass: write the census-out particles
   const double2* mat64;  // (sigma_s, sigma_a) per cell
   const float2* mat32;
+  // with few distinct materials: a 16-bit id per cell into (sigma_s,
+  // sigma_a) tables, so that the gather of a segment touches 2 bytes per cell
+  // of the mesh plus a small table; null otherwise
+  const uint16_t* mat_id16;
+  const double2* mtab64;
+  const float2* mtab32;
   // emission, stratified by cell: cell i emits n_i = floor(r_i) or
   // floor(r_i) + 1 particles, r_i = M_i / w_q, w_q = quantum5(sum(M) / n_src)
   // (st->wq[kind - 1], with the exact sum st->sumM[kind - 1])
@@ -366,13 +366,13 @@ struct PassArgs {
   double w_cut_rel;
   unsigned int max_segments;
   // census: input bank and output slots (census index, or out_src_base +
-  // source index), in the precision of the pass
-  Bank<double> in64;
-  Bank<float> in32;
+  // source index), and the source particles, in the precision of the pass
+  const StageRec<double>* in64;
+  const StageRec<float>* in32;
   StageRec<double>* out64;
   StageRec<float>* out32;
-  SrcBank<double> src64;
-  SrcBank<float> src32;
+  SrcRec<double>* src64;
+  SrcRec<float>* src32;
   uint8_t* alive;
   long long out_src_base;  // slot of source particle s is out_src_base + s
   // tallies: n_copies private copies of one fixed-point word per cell (word
@@ -536,7 +536,7 @@ hipError_t launch_census_flags(const uint8_t* alive, const StageRec<R>* stage, l
                                hipStream_t s);
 template <typename R>
 hipError_t launch_census_compact(const StageRec<R>* src, const long long* incl, long long n,
-                                 long long cap, Bank<R> dst, DevState* st, double* bmax,
+                                 long long cap, StageRec<R>* dst, DevState* st, double* bmax,
                                  hipStream_t s);
 // bmax: kCensusBlocks doubles, the compaction's per-block max |w|
 hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,

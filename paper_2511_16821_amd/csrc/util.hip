@@ -570,7 +570,8 @@ int census_compact_blocks(long long n) {
 template <typename R>
 __global__ __launch_bounds__(256) void k_census_compact(const StageRec<R>* __restrict__ src,
                                                         const long long* __restrict__ incl,
-                                                        long long n, long long cap, Bank<R> dst,
+                                                        long long n, long long cap,
+                                                        StageRec<R>* __restrict__ dst,
                                                         const DevState* st,
                                                         double* __restrict__ bmax) {
   __shared__ double s_mx[4];
@@ -582,15 +583,10 @@ __global__ __launch_bounds__(256) void k_census_compact(const StageRec<R>* __res
     if (incl[i] == before) continue;
     const long long d = before;
     if (d >= cap) continue;  // overflow of the draw: keep the first cap
-    const StageRec<R> rec = src[i];
-    dst.px[d] = rec.px;
-    dst.py[d] = rec.py;
-    dst.ox[d] = rec.ox;
-    dst.oy[d] = rec.oy;
+    StageRec<R> rec = src[i];
     const R w = rec.w * f;
-    dst.w[d] = w;
-    dst.cell[d] = rec.cell;
-    dst.hid[d] = rec.hid;
+    rec.w = w;
+    dst[d] = rec;
     mx = fmax(mx, fabs((double)w));
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
@@ -603,17 +599,17 @@ __global__ __launch_bounds__(256) void k_census_compact(const StageRec<R>* __res
 
 template <typename R>
 hipError_t launch_census_compact(const StageRec<R>* src, const long long* incl, long long n,
-                                 long long cap, Bank<R> dst, DevState* st, double* bmax,
+                                 long long cap, StageRec<R>* dst, DevState* st, double* bmax,
                                  hipStream_t s) {
   hipLaunchKernelGGL(k_census_compact<R>, dim3(census_compact_blocks(n)), dim3(256), 0, s, src,
                      incl, n, cap, dst, (const DevState*)st, bmax);
   return hipGetLastError();
 }
 template hipError_t launch_census_compact<double>(const StageRec<double>*, const long long*,
-                                                  long long, long long, Bank<double>,
+                                                  long long, long long, StageRec<double>*,
                                                   DevState*, double*, hipStream_t);
 template hipError_t launch_census_compact<float>(const StageRec<float>*, const long long*,
-                                                 long long, long long, Bank<float>, DevState*,
+                                                 long long, long long, StageRec<float>*, DevState*,
                                                  double*, hipStream_t);
 
 // Census count and max |w| of the new bank (max over the compaction blocks),

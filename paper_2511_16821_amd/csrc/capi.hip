@@ -335,7 +335,7 @@ static Sizes sizes_of(const slh_problem* p) {
   const size_t srec = z.fp32 ? sizeof(SrcRec<float>) : sizeof(SrcRec<double>);
   size_t b = 0;
   const size_t nc = (size_t)z.n_cells;
-  b += nc * (16 + 8 + 8 + 8 + 8);            // mat64, mat32, sig_s, sig_e, q
+  b += nc * (16 + 8 + 8 + 16 + 8);           // mat64, mat32, sig_s, sig_e (two layouts), q
   if (z.n_mc_mat) b += nc * 2 + (size_t)z.n_mc_mat * 24;  // material ids and tables
   if (p->n_s_cell) b += nc * 4;              // per-cell scatter limits
   if (p->boundary)                           // mirror indices, reflected traces
@@ -343,13 +343,15 @@ static Sizes sizes_of(const slh_problem* p) {
   b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 2;  // nodal sources, count trees
   b += (size_t)kMajBins * 8;                 // majorant histogram
   b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
-  b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c x2, DG source
+  b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c, DG source x2
+  b += (size_t)z.n_dir * 4;                  // directions of each sweep layout
+  if (!z.diffusion) b += nc * 64;            // per-layout direction sums
   if (z.diffusion || z.dsa)
     b += nc * 8 * 9 + 4 * 1024 * 8;          // CG: diag, cE, cN, x, r, z, p x2, q; partials
   if (z.dsa) b += nc * 32;                   // nodal change of a sweep
   if (!z.diffusion) b += (size_t)z.n_dir * nc * 32;  // direction planes
   b += (size_t)z.n_dir * 256;                // element data
-  if (z.dg_table) b += nc * 4 + (size_t)z.n_mat * 8 + (size_t)z.n_dir * z.n_mat * 256;
+  if (z.dg_table) b += nc * 8 + (size_t)z.n_mat * 8 + (size_t)z.n_dir * z.n_mat * 256;
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
   b += (size_t)z.cap * bank * 2;             // census banks
   b += (size_t)(z.n_src_cap > 0 ? z.n_src_cap : 1) * srec;  // source bank
@@ -494,9 +496,12 @@ struct slh_solver {
   double* bnd = nullptr;
   std::vector<int> h_refl;
   double* dirmat = nullptr;  // DG element data per direction
-  int* mat_id = nullptr;     // DG table mode: material of each cell,
+  int* mat_id = nullptr;     // DG table mode: material of each cell (sweep layouts),
   double *sig_e_mat = nullptr, *coef = nullptr;  // its sigma_e, coefficients
-  double* dg_src = nullptr;
+  double* dg_src = nullptr;  // nodal source of a sweep (sweep layouts)
+  int* fam_dirs = nullptr;   // directions of layout A, then of layout B
+  int fam_n = 0;             // how many of them belong to layout A
+  double* phi_fam = nullptr; // per-layout direction sums of the reduction
   int n_part = 1;
   void* bank_mem[2] = {nullptr, nullptr};
   void* stage_mem = nullptr;
@@ -591,7 +596,7 @@ static slh_status setup(slh_solver* s) {
     ALLOC(s->mtab32, float2, z.n_mc_mat);
   }
   ALLOC(s->sig_s, double, nc);
-  ALLOC(s->sig_e, double, nc);
+  ALLOC(s->sig_e, double, 2 * nc);  // sweep layouts A and B
   ALLOC(s->q, double, nc);
   if (!s->h_ns.empty()) ALLOC(s->ns_cell, int, nc);
   s->tree_L = tree_leaves(nc);
@@ -623,11 +628,13 @@ static slh_status setup(slh_solver* s) {
   }
   ALLOC(s->dirmat, double, (size_t)z.n_dir * 32);
   if (z.dg_table) {
-    ALLOC(s->mat_id, int, nc);
+    ALLOC(s->mat_id, int, 2 * nc);
     ALLOC(s->sig_e_mat, double, z.n_mat);
     ALLOC(s->coef, double, (size_t)z.n_dir * z.n_mat * 32);
   }
-  ALLOC(s->dg_src, double, 4 * nc);
+  ALLOC(s->dg_src, double, 8 * nc);
+  ALLOC(s->fam_dirs, int, z.n_dir);
+  if (!z.diffusion) ALLOC(s->phi_fam, double, 8 * nc);
   s->n_part = dg_reduce_partials(4 * nc);
   ALLOC(s->dg_part, double, 2 * s->n_part + 2);
   ALLOC(s->cmax, double, kCensusBlocks);
@@ -691,7 +698,23 @@ static slh_status setup(slh_solver* s) {
                            hipMemcpyHostToDevice, st));
   }
   HIP_TRY(hipMemcpyAsync(s->sig_s, s->h_sig_s.data(), 8 * nc, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(s->sig_e, se.data(), 8 * nc, hipMemcpyHostToDevice, st));
+  // sweep layouts: sigma_e in layouts A and B, and the directions of each
+  // layout (A: both components of one sign)
+  std::vector<double> se_l(2 * nc);
+  for (long long c = 0; c < nc; ++c) {
+    const int ci = (int)(c % p.nx), cj = (int)(c / p.nx);
+    se_l[lay_pos(p.nx, p.ny, ci, cj, true)] = se[c];
+    se_l[nc + lay_pos(p.nx, p.ny, ci, cj, false)] = se[c];
+  }
+  std::vector<int> fam;
+  for (int f = 0; f < 2; ++f)
+    for (int m = 0; m < z.n_dir; ++m)
+      if (((dirs[3 * m] > 0.0) == (dirs[3 * m + 1] > 0.0)) == (f == 0)) fam.push_back(m);
+  s->fam_n = 0;
+  for (int m = 0; m < z.n_dir; ++m)
+    if ((dirs[3 * m] > 0.0) == (dirs[3 * m + 1] > 0.0)) s->fam_n += 1;
+  HIP_TRY(hipMemcpyAsync(s->sig_e, se_l.data(), 16 * nc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->fam_dirs, fam.data(), 4 * fam.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->q, s->h_q.data(), 8 * nc, hipMemcpyHostToDevice, st));
   if (s->ns_cell)
     HIP_TRY(hipMemcpyAsync(s->ns_cell, s->h_ns.data(), 4 * nc, hipMemcpyHostToDevice, st));
@@ -721,10 +744,14 @@ static slh_status setup(slh_solver* s) {
     std::sort(mval.begin(), mval.end());
     mval.erase(std::unique(mval.begin(), mval.end()), mval.end());
     if ((long long)mval.size() != z.n_mat) return fail(SLH_E_STATE, "material count changed");
-    mid.resize(nc);
-    for (long long i = 0; i < nc; ++i)
-      mid[i] = (int)(std::lower_bound(mval.begin(), mval.end(), se[i]) - mval.begin());
-    HIP_TRY(hipMemcpyAsync(s->mat_id, mid.data(), 4 * nc, hipMemcpyHostToDevice, st));
+    mid.resize(2 * nc);
+    for (long long c = 0; c < nc; ++c) {
+      const int k = (int)(std::lower_bound(mval.begin(), mval.end(), se[c]) - mval.begin());
+      const int ci = (int)(c % p.nx), cj = (int)(c / p.nx);
+      mid[lay_pos(p.nx, p.ny, ci, cj, true)] = k;
+      mid[nc + lay_pos(p.nx, p.ny, ci, cj, false)] = k;
+    }
+    HIP_TRY(hipMemcpyAsync(s->mat_id, mid.data(), 8 * nc, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(s->sig_e_mat, mval.data(), 8 * z.n_mat, hipMemcpyHostToDevice, st));
   }
   HIP_TRY(launch_dg_tables(z.n_dir, z.dg_table ? z.n_mat : 0, s->dirs, s->sig_e_mat, s->hx,
@@ -836,6 +863,8 @@ static DgArgs dg_args(slh_solver* s) {
   d.hy = s->hy;
   d.n_dir = z.n_dir;
   d.dir = s->dirs;
+  d.fam_dirs = s->fam_dirs;
+  d.fam_n = s->fam_n;
   d.sig_e = s->sig_e;
   d.sig_s = s->sig_s;
   d.phi_post = s->phi_post;
@@ -843,6 +872,7 @@ static DgArgs dg_args(slh_solver* s) {
   d.phi_c = s->phi_c;
   d.src = s->dg_src;
   d.psi = s->psi;
+  d.phi_fam = s->phi_fam;
   d.dnode = s->z.dsa && !s->skip_remap ? s->dnode : nullptr;
   d.mat_id = s->mat_id;
   d.n_mat = z.n_mat;

@@ -34,7 +34,10 @@
 //   cell mode: A is LU-factorised before the barrier and solved after it.
 // The solution goes to a per-direction plane, and a second kernel sums
 // w_m psi_m over the directions in a fixed order, so the scalar flux does not
-// depend on scheduling.
+// depend on scheduling.  The sources, sigma_e and the planes are stored in the
+// sweep's own layouts (anti-diagonals or diagonals, DgArgs), where the cells
+// of a chunk are contiguous: a diagonal of a row-major array would touch a
+// different cache line in every lane.
 #include "slh_common.hpp"
 
 namespace slh {
@@ -53,10 +56,11 @@ __device__ __forceinline__ double recip(double a) {
 // S = sigma_s/(4 pi) (phi_c + phi_post) with phi_c = 0 (later iterates get
 // theirs from the flux reduction), and with reflective sides the buffer of
 // reflected traces that the first sweep reads set to zero.
-__global__ void k_si_start(long long n, const double* __restrict__ sig_s,
+__global__ void k_si_start(int nx, int ny, const double* __restrict__ sig_s,
                            const double* __restrict__ phi_post, double* __restrict__ phi_c,
                            double* __restrict__ S, double* __restrict__ bnd0, long long n_bnd,
                            DevState* st, int si_max) {
+  const long long n = (long long)nx * ny;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->si.iter = 0;
     st->si.conv = si_max == 0 ? 1 : 0;
@@ -74,8 +78,10 @@ __global__ void k_si_start(long long n, const double* __restrict__ sig_s,
   for (long long i = i0; i < n; i += str) {
     const double ssc = sig_s[i] * inv4pi;
     const double v = ssc * (0.0 + phi_post[i]);
+    const int ci = (int)(i % nx), cj = (int)(i / nx);
     reinterpret_cast<double4*>(phi_c)[i] = make_double4(0.0, 0.0, 0.0, 0.0);
-    reinterpret_cast<double4*>(S)[i] = make_double4(v, v, v, v);
+    reinterpret_cast<double4*>(S)[lay_pos(nx, ny, ci, cj, true)] = make_double4(v, v, v, v);
+    reinterpret_cast<double4*>(S)[n + lay_pos(nx, ny, ci, cj, false)] = make_double4(v, v, v, v);
   }
   for (long long k = i0; k < n_bnd; k += str) bnd0[k] = 0.0;
 }
@@ -227,6 +233,15 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
   const bool loader = wave >= n_sw;
   const int lane = threadIdx.x & 63;
   const int lw = wave - n_sw;  // loader wave index
+  // this direction's layout: A (anti-diagonals) when both components have the
+  // same sign; the chunk of upwind diagonal dd is run n_diag - 1 - dd of the
+  // layout when Omega_x < 0, and cell i sits at run start - lo + i
+  constexpr bool anti = APOS == BPOS;
+  const long long lay_base = anti ? 0 : (long long)nx * ny;
+  auto run_base = [&](int dd) __attribute__((always_inline)) {
+    const int r = apos ? dd : n_diag - 1 - dd;
+    return lay_run(nx, ny, r) - (long long)diag_lo(r) + lay_base;
+  };
 
   // ---- loader state: ring of kDgDepth chunks, Q cells per lane ----
   DgStage<Q> r0s, r1s, r2s, r3s;
@@ -239,6 +254,7 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
     const int hi = live ? diag_hi(fd) : -1;
     const int dl = live ? fd : n_diag - 1;  // a real diagonal for the addresses
     const int dlo = diag_lo(dl), dhi = diag_hi(dl);
+    const long long rb = run_base(dl);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int tq = lane + 64 * (lw + n_ld * q);
@@ -247,10 +263,8 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
       // clamp the position onto the diagonal, so that every lane's address
       // is a real cell and no branch guards the loads
       const int ipc = ip < dlo ? dlo : (ip < dhi ? ip : dhi);
-      const int jp = dl - ipc;
       const int i = apos ? ipc : nx - 1 - ipc;
-      const int j = bpos ? jp : ny - 1 - jp;
-      const long long c = (long long)j * nx + i;
+      const long long c = rb + i;  // position in this direction's layout
       st.C[q] = ok ? tq : -1;
       if (TABLE) st.Ki[q] = g.mat_id[c];
       else st.Kd[q] = g.sig_e[c];
@@ -366,6 +380,7 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
   int cd = 0, cp = 0;  // next chunk to prepare
   bool c_has = false;
   int c_i = 0, c_j = 0;
+  long long c_pos = 0;
   double P[16];    // table: G; cell mode: LU (inverse pivots, L, strict U)
   double r0[4];    // table: B S; cell mode: MM S
   auto prepare = [&](int slot) __attribute__((always_inline)) {
@@ -375,6 +390,7 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
       const int jp = cd - ip;
       c_i = apos ? ip : nx - 1 - ip;
       c_j = bpos ? jp : ny - 1 - jp;
+      c_pos = run_base(cd) + c_i;
       const double2 sa = slotA[slot * CW + t], sb = slotB[slot * CW + t];
       const double4 S = make_double4(sa.x, sa.y, sb.x, sb.y);
       const double key = slotK[slot * CW + t];
@@ -463,7 +479,7 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
           b_out[2 * ny + 2 * c_i + 1] = bpos ? x3 : x1;
         }
       }
-      out[(long long)c_j * nx + c_i] = make_double4(x0, x1, x2, x3);
+      out[c_pos - lay_base] = make_double4(x0, x1, x2, x3);
     }
     prepare((k + 1) & 1);
   }
@@ -497,8 +513,8 @@ hipError_t launch_si_start(const DgArgs& a, int si_max, hipStream_t s) {
   long long b = (nc + 255) / 256;
   const int grid = (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
   const long long nb = a.bnd ? (long long)a.n_dir * 2 * (a.nx + a.ny) : 0;
-  hipLaunchKernelGGL(k_si_start, dim3(grid), dim3(256), 0, s, nc, a.sig_s, a.phi_post, a.phi_c,
-                     a.src, a.bnd ? a.bnd + nb : nullptr, nb, a.st, si_max);
+  hipLaunchKernelGGL(k_si_start, dim3(grid), dim3(256), 0, s, a.nx, a.ny, a.sig_s,
+                     a.phi_post, a.phi_c, a.src, a.bnd ? a.bnd + nb : nullptr, nb, a.st, si_max);
   return hipGetLastError();
 }
 
@@ -529,11 +545,17 @@ hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   return hipGetLastError();
 }
 
-// phi_new[k] = sum_m w_m psi[m][k] in direction order, in place; the next
-// iterate's nodal source S = sigma_s/(4 pi) (phi_new + phi_post) (unused when
-// the iteration stops here); block partials of |phi_new - phi_old|^2 and
+// The reduction of a source iteration, in two kernels.  k_dg_famsum: at
+// every node of each layout, the sum of w_m psi_m over that layout's
+// directions in their order (every plane read once, in whole cache lines).
+// k_dg_combine, per row-major cell: phi_new = sum over layout A + sum over
+// layout B, in place (the sweep read only S); the next iterate's nodal source
+// S = sigma_s/(4 pi) (phi_new + phi_post) in both layouts (unused when the
+// iteration stops here); block partials of |phi_new - phi_old|^2 and
 // |phi_new|^2, or |phi_new + phi_pre + phi_post|^2 when phi_pre is given (the
-// step's whole flux as the reference of the stopping test).
+// step's whole flux as the reference of the stopping test).  With the
+// diffusion correction the combine keeps phi_new - phi_old in dnode instead
+// and leaves the source and the residual to k_dsa_apply.
 constexpr int kRedBlock = 256;
 
 int dg_reduce_partials(long long n_nodes) {
@@ -541,41 +563,39 @@ int dg_reduce_partials(long long n_nodes) {
   return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
-    int n_dir, long long n_nodes, const double* __restrict__ psi,
-    const double* __restrict__ dir, double* __restrict__ phi,
-    const double* __restrict__ sig_s, const double* __restrict__ phi_post,
-    const double* __restrict__ phi_pre, double* __restrict__ S,
-    double* __restrict__ partials, double* __restrict__ dnode, const DevState* st) {
+__global__ __launch_bounds__(kRedBlock) void k_dg_famsum(
+    const int* __restrict__ fam_dirs, int n_a, int n_dir, long long n_nodes,
+    const double* __restrict__ psi, const double* __restrict__ dir,
+    double* __restrict__ phi_fam, const DevState* st) {
   if (st->si.done) return;
-  __shared__ double s_d[kRedBlock], s_n[kRedBlock];
-  const double inv4pi = 0.25 / M_PI;
-  double dsum = 0.0, nsum = 0.0;
-  for (long long k = (long long)blockIdx.x * kRedBlock + threadIdx.x; k < n_nodes;
-       k += (long long)gridDim.x * kRedBlock) {
-    // eight planes' loads in flight per step, added in direction order
+  // the first half of the grid sums layout A, the second layout B
+  const int half = (int)(gridDim.x >> 1);
+  const bool fb = (int)blockIdx.x >= half;
+  const int u0 = fb ? n_a : 0, u1 = fb ? n_dir : n_a;
+  double* __restrict__ out = phi_fam + (fb ? n_nodes : 0);
+  for (long long k = (long long)(blockIdx.x - (fb ? half : 0)) * kRedBlock + threadIdx.x;
+       k < n_nodes; k += (long long)half * kRedBlock) {
+    // sixteen planes' loads in flight per step, added in direction order
     double v = 0.0;
-    int m = 0;
-    for (; m + 8 <= n_dir; m += 8) {
-      double t[8];
+    int u = u0;
+    for (; u + 16 <= u1; u += 16) {
+      double t[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = psi[(long long)(m + u) * n_nodes + k];
+      for (int e = 0; e < 16; ++e) t[e] = psi[(long long)fam_dirs[u + e] * n_nodes + k];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v += dir[3 * (m + u) + 2] * t[u];
+      for (int e = 0; e < 16; ++e) v += dir[3 * fam_dirs[u + e] + 2] * t[e];
     }
-    for (; m < n_dir; ++m) v += dir[3 * m + 2] * psi[(long long)m * n_nodes + k];
-    const double d = v - phi[k];  // in place: the sweep read only S
-    phi[k] = v;
-    if (dnode) {  // the correction, the source and the residual come later
-      dnode[k] = d;
-      continue;
+    for (; u < u1; ++u) {
+      const int m = fam_dirs[u];
+      v += dir[3 * m + 2] * psi[(long long)m * n_nodes + k];
     }
-    S[k] = sig_s[k >> 2] * inv4pi * (v + phi_post[k >> 2]);
-    const double vr = phi_pre ? v + (phi_pre[k >> 2] + phi_post[k >> 2]) : v;
-    dsum += d * d;
-    nsum += vr * vr;
+    out[k] = v;
   }
-  if (dnode) return;  // the same for the whole grid
+}
+
+// Partials of a block: tree sum of the threads' values in a fixed order.
+__device__ __forceinline__ void block_partials(double dsum, double nsum, double* partials) {
+  __shared__ double s_d[kRedBlock], s_n[kRedBlock];
   s_d[threadIdx.x] = dsum;
   s_n[threadIdx.x] = nsum;
   __syncthreads();
@@ -592,42 +612,77 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_reduce(
   }
 }
 
+// The next iterate's nodal source of cell (ci, cj) in both layouts, and the
+// cell's contribution to the stopping test.
+__device__ __forceinline__ void next_source(int nx, int ny, long long c,
+                                            double4 v, double4 d, double ssc, double pp,
+                                            const double* phi_pre, double* S, double& dsum,
+                                            double& nsum) {
+  const long long n = (long long)nx * ny;
+  const int ci = (int)(c % nx), cj = (int)(c / nx);
+  const double4 sv = make_double4(ssc * (v.x + pp), ssc * (v.y + pp), ssc * (v.z + pp),
+                                  ssc * (v.w + pp));
+  reinterpret_cast<double4*>(S)[lay_pos(nx, ny, ci, cj, true)] = sv;
+  reinterpret_cast<double4*>(S)[n + lay_pos(nx, ny, ci, cj, false)] = sv;
+  const double r = phi_pre ? phi_pre[c] + pp : 0.0;
+  dsum += d.x * d.x + d.y * d.y + d.z * d.z + d.w * d.w;
+  nsum += (v.x + r) * (v.x + r) + (v.y + r) * (v.y + r) + (v.z + r) * (v.z + r) +
+          (v.w + r) * (v.w + r);
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_dg_combine(
+    int nx, int ny, const double* __restrict__ phi_fam,
+    double* __restrict__ phi, const double* __restrict__ sig_s,
+    const double* __restrict__ phi_post, const double* __restrict__ phi_pre,
+    double* __restrict__ S, double* __restrict__ partials, double* __restrict__ dnode,
+    const DevState* st) {
+  if (st->si.done) return;
+  const double inv4pi = 0.25 / M_PI;
+  const long long n = (long long)nx * ny;
+  const double4* fam = reinterpret_cast<const double4*>(phi_fam);
+  double dsum = 0.0, nsum = 0.0;
+  for (long long c = (long long)blockIdx.x * kRedBlock + threadIdx.x; c < n;
+       c += (long long)gridDim.x * kRedBlock) {
+    const int ci = (int)(c % nx), cj = (int)(c / nx);
+    const double4 a = fam[lay_pos(nx, ny, ci, cj, true)];
+    const double4 b = fam[n + lay_pos(nx, ny, ci, cj, false)];
+    const double4 v = make_double4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+    const double4 o = reinterpret_cast<const double4*>(phi)[c];
+    const double4 d = make_double4(v.x - o.x, v.y - o.y, v.z - o.z, v.w - o.w);
+    reinterpret_cast<double4*>(phi)[c] = v;
+    if (dnode) {  // the correction, the source and the residual come later
+      reinterpret_cast<double4*>(dnode)[c] = d;
+      continue;
+    }
+    next_source(nx, ny, c, v, d, sig_s[c] * inv4pi, phi_post[c], phi_pre, S, dsum, nsum);
+  }
+  if (dnode) return;  // the same for the whole grid
+  block_partials(dsum, nsum, partials);
+}
+
 // phi += delta (per cell) at every node, the next source, and partials of
 // |dnode + delta|^2 and |phi|^2 (or of the whole-flux norm) for k_dg_residual.
 __global__ __launch_bounds__(kRedBlock) void k_dsa_apply(
-    long long n_nodes, double* __restrict__ phi, const double* __restrict__ dnode,
-    const double* __restrict__ delta, const double* __restrict__ sig_s,
-    const double* __restrict__ phi_post, const double* __restrict__ phi_pre,
-    double* __restrict__ S, double* __restrict__ partials, const DevState* st) {
+    int nx, int ny, double* __restrict__ phi,
+    const double* __restrict__ dnode, const double* __restrict__ delta,
+    const double* __restrict__ sig_s, const double* __restrict__ phi_post,
+    const double* __restrict__ phi_pre, double* __restrict__ S, double* __restrict__ partials,
+    const DevState* st) {
   if (st->si.done) return;
-  __shared__ double s_d[kRedBlock], s_n[kRedBlock];
   const double inv4pi = 0.25 / M_PI;
+  const long long n = (long long)nx * ny;
   double dsum = 0.0, nsum = 0.0;
-  for (long long k = (long long)blockIdx.x * kRedBlock + threadIdx.x; k < n_nodes;
-       k += (long long)gridDim.x * kRedBlock) {
-    const double dl = delta[k >> 2];
-    const double v = phi[k] + dl;
-    const double d = dnode[k] + dl;
-    phi[k] = v;
-    S[k] = sig_s[k >> 2] * inv4pi * (v + phi_post[k >> 2]);
-    const double vr = phi_pre ? v + (phi_pre[k >> 2] + phi_post[k >> 2]) : v;
-    dsum += d * d;
-    nsum += vr * vr;
+  for (long long c = (long long)blockIdx.x * kRedBlock + threadIdx.x; c < n;
+       c += (long long)gridDim.x * kRedBlock) {
+    const double dl = delta[c];
+    const double4 o = reinterpret_cast<const double4*>(phi)[c];
+    const double4 dn = reinterpret_cast<const double4*>(dnode)[c];
+    const double4 v = make_double4(o.x + dl, o.y + dl, o.z + dl, o.w + dl);
+    const double4 d = make_double4(dn.x + dl, dn.y + dl, dn.z + dl, dn.w + dl);
+    reinterpret_cast<double4*>(phi)[c] = v;
+    next_source(nx, ny, c, v, d, sig_s[c] * inv4pi, phi_post[c], phi_pre, S, dsum, nsum);
   }
-  s_d[threadIdx.x] = dsum;
-  s_n[threadIdx.x] = nsum;
-  __syncthreads();
-  for (int off = kRedBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      s_d[threadIdx.x] += s_d[threadIdx.x + off];
-      s_n[threadIdx.x] += s_n[threadIdx.x + off];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = s_d[0];
-    partials[2 * blockIdx.x + 1] = s_n[0];
-  }
+  block_partials(dsum, nsum, partials);
 }
 
 // Sums the block partials with a fixed association order (strided
@@ -677,9 +732,13 @@ __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int
 
 hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, double si_tol,
                             int si_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_dg_reduce, dim3(n_part), dim3(kRedBlock), 0, s, a.n_dir,
-                     4ll * a.nx * a.ny, (const double*)a.psi, a.dir, a.phi_c, a.sig_s, a.phi_post,
-                     a.phi_pre, a.src, partials, a.dnode, (const DevState*)a.st);
+  const long long n_nodes = 4ll * a.nx * a.ny;
+  hipLaunchKernelGGL(k_dg_famsum, dim3(2 * dg_reduce_partials(n_nodes)), dim3(kRedBlock), 0, s,
+                     a.fam_dirs, a.fam_n, a.n_dir, n_nodes, (const double*)a.psi, a.dir,
+                     a.phi_fam, (const DevState*)a.st);
+  hipLaunchKernelGGL(k_dg_combine, dim3(n_part), dim3(kRedBlock), 0, s, a.nx, a.ny,
+                     (const double*)a.phi_fam, a.phi_c, a.sig_s, a.phi_post, a.phi_pre, a.src,
+                     partials, a.dnode, (const DevState*)a.st);
   if (!a.dnode)
     hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,
                        a.st, si_tol, si_max, 0);
@@ -688,7 +747,7 @@ hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, doubl
 
 hipError_t launch_dsa_apply(const DgArgs& a, const double* delta, double* partials, int n_part,
                             double si_tol, int si_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_dsa_apply, dim3(n_part), dim3(kRedBlock), 0, s, 4ll * a.nx * a.ny,
+  hipLaunchKernelGGL(k_dsa_apply, dim3(n_part), dim3(kRedBlock), 0, s, a.nx, a.ny,
                      a.phi_c, (const double*)a.dnode, delta, a.sig_s, a.phi_post, a.phi_pre,
                      a.src, partials, (const DevState*)a.st);
   hipLaunchKernelGGL(k_dg_residual, dim3(1), dim3(256), 0, s, (const double*)partials, n_part,

@@ -402,23 +402,54 @@ hipError_t launch_qmc_points(uint64_t stream, uint32_t dim0, uint32_t nd, uint32
                              hipStream_t s);
 const uint32_t* sobol_table_host();
 
+// Start of run d of a sweep layout (see DgArgs): the number of cells of an
+// nx x ny mesh on the runs before it, sum over t < d of
+// min(t, nx - 1) - max(0, t - (ny - 1)) + 1, in closed form.
+__host__ __device__ __forceinline__ long long lay_run(int nx, int ny, int d) {
+  const long long D = d, X = nx, Y = ny;
+  const long long a = D <= X ? D * (D + 1) / 2 : X * (X + 1) / 2 + (D - X) * X;
+  const long long b = D <= Y ? 0 : (D - Y) * (D - Y + 1) / 2;
+  return a - b;
+}
+
+// Position of cell (i, j) in sweep layout A (anti = true) or B.
+__host__ __device__ __forceinline__ long long lay_pos(int nx, int ny, int i, int j, bool anti) {
+  const int d = anti ? i + j : i - j + ny - 1;
+  const int lo = d - (ny - 1) > 0 ? d - (ny - 1) : 0;
+  return lay_run(nx, ny, d) + (i - lo);
+}
+
 struct DgArgs {
   int nx, ny;
   double hx, hy;
   int n_dir;
   const double* dir;     // [m][3]: ox, oy, w
-  const double* sig_e;   // per cell
-  const double* sig_s;   // per cell
+  // Sweep layouts: the cells of a direction whose components have the same
+  // sign are visited along anti-diagonals (i + j constant), the others along
+  // diagonals (i - j constant).  Layout A stores the cells anti-diagonal by
+  // anti-diagonal (index d = i + j), layout B diagonal by diagonal (index
+  // d = i - j + ny - 1); within either, cell i - lo(d) of the run, lo(d) =
+  // max(0, d - (ny - 1)), and the run starts at lay_run(nx, ny, d).  A chunk
+  // of a sweep is then a contiguous piece of its layout, so the sweep's loads
+  // and its plane stores are whole cache lines.
+  const int* fam_dirs;   // the directions of layout A in order, then those of B
+  int fam_n;             // how many belong to layout A
+  const double* sig_e;   // per cell, layout A then layout B (2 nx ny)
+  const double* sig_s;   // per cell (row-major)
   const double* phi_post;// per cell
   const double* phi_pre; // per cell, or null: the stopping test's norm is then
                          // over phi_c alone, else over phi_c + phi_pre + phi_post
-  double* phi_c;         // nodal [cell][4]: the collided iterate, updated in place
-  double* src;           // nodal [cell][4] scratch: sigma_s/(4 pi)(phi_c + phi_post)
-  double* psi;           // [m][cell][4] (psi_m; the reduction applies w_m)
-  double* dnode;         // nodal phi^{k+1/2} - phi^k for the diffusion correction
-                         // (diffusion synthetic acceleration), or null
+  double* phi_c;         // nodal [cell][4] (row-major): the collided iterate, updated in place
+  double* src;           // nodal sigma_s/(4 pi)(phi_c + phi_post), layout A then B (8 nx ny)
+  double* psi;           // [m][position][4] in the layout of direction m (psi_m;
+                         // the reduction applies w_m)
+  double* phi_fam;       // nodal sums of w_m psi_m over each layout's directions,
+                         // layout A then B (8 nx ny)
+  double* dnode;         // nodal phi^{k+1/2} - phi^k (row-major) for the diffusion
+                         // correction (diffusion synthetic acceleration), or null
   const double* dirmat;  // [m][32]: A0 then F (uniform mesh)
-  // table mode: material of each cell and [m][material][32] = B then G
+  // table mode: material of each cell (layout A then B) and
+  // [m][material][32] = B then G
   const int* mat_id;
   int n_mat;
   const double* coef;
@@ -486,9 +517,10 @@ bool cg_one_block(long long n);
 hipError_t launch_cg_iteration(const CgArgs& a, double tol, int si_max, hipStream_t s);
 hipError_t launch_cg_to_nodal(const CgArgs& a, double* phi_c, hipStream_t s);
 hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s);
-// One reduction of a source iteration: phi_c is replaced in place by the
-// direction sum of the planes, the next iterate's source is formed, and the
-// residual decides st->si.done (n_part blocks, dg_reduce_partials).
+// One reduction of a source iteration: the direction sum of the planes (each
+// layout's directions in order, then the two sums added) replaces phi_c in
+// place, the next iterate's source is formed, and the residual decides
+// st->si.done (n_part blocks, dg_reduce_partials).
 hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, double si_tol,
                             int si_max, hipStream_t s);
 int dg_reduce_partials(long long n_nodes);

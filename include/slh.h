@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define SLH_ABI_VERSION 6u
+#define SLH_ABI_VERSION 7u
 
 typedef enum {
     SLH_OK = 0,
@@ -284,6 +284,11 @@ typedef struct {
                                        segment guard fired (0 normally)     */
     uint64_t si_unconverged_total;  /* steps whose source iteration stopped
                                        at si_max_iter                        */
+    int32_t si_batch;               /* source iterations launched per step at
+                                       present (see slh_advance)             */
+    int32_t pad0;
+    uint64_t si_restarts_total;     /* steps run again because their batch
+                                       ended before the iteration            */
 } slh_stats;
 
 typedef struct slh_solver slh_solver;
@@ -316,13 +321,25 @@ slh_status slh_create_static(const slh_problem *problem, void *hip_stream, slh_s
 
 /* Enqueues n_steps >= 1 time steps (steps 1-4 above) on the solver's stream
  * and returns without waiting for the device.  Each step is one HIP graph
- * (captured on first use, once per census-bank parity, and replayed): the
- * scatter-limited leg, the collided solve with si_max_iter source
- * iterations of which those after the device's stopping test return at
- * once, the remap leg and the census.  Nothing in a step waits for the host.
- * The outcome of the steps (convergence, numeric faults) is reported by
- * slh_synchronize.  Returns SLH_E_DEVICE if a launch fails. */
+ * (captured on first use, once per census-bank parity and batch, and
+ * replayed): the scatter-limited leg, the collided solve as a batch of
+ * source iterations of which those after the device's stopping test return
+ * at once, the remap leg and the census.  Nothing in a step waits for the
+ * host.  The batch adapts to the iteration counts of past steps (a quarter
+ * more than the last one, plus two, in multiples of eight; at most
+ * si_max_iter); a step whose batch ends before its iteration stops itself
+ * and every step enqueued after it on the device, and the next call that
+ * waits for the stream (slh_synchronize, slh_get_*, slh_save, slh_load) runs
+ * them again, the stopped one with si_max_iter iterations and the others
+ * with a doubled batch.  Results do not depend on the batch.  The outcome of
+ * the steps (convergence, numeric faults) is reported by slh_synchronize.
+ * Returns SLH_E_DEVICE if a launch fails. */
 slh_status slh_advance(slh_solver *s, int32_t n_steps);
+
+/* Sets the batch of source iterations of the next steps (n >= 1, at most
+ * si_max_iter); the adaptive rule of slh_advance takes over after the next
+ * wait.  For tuning and tests; results do not depend on it. */
+slh_status slh_set_si_batch(slh_solver *s, int32_t n);
 
 /* enable != 0 (the default): each step is launched as a HIP graph; 0: every
  * kernel is launched directly.  Results are identical. */

@@ -129,11 +129,11 @@ struct Sizes {
   int n_copies;  // private tally copies
   bool fp32;
   // DG sweep: table mode (per-(direction, material) coefficients staged in
-  // LDS, n_mat distinct sigma_e) or cell mode; dg_cw sweeping lanes per
-  // workgroup, dg_chunks chunks per sweep.
+  // LDS, n_mat distinct sigma_e) or cell mode; dg_cw cells per chunk, dg_q
+  // of them per lane, dg_chunks chunks per sweep.
   int n_mat;
   bool dg_table;
-  int dg_cw;
+  int dg_cw, dg_q;
   long long dg_chunks;
   bool diffusion;  // diffusion closing stage: no direction planes, CG vectors instead
   bool dsa;        // S_N with the diffusion correction: planes, CG vectors and dnode
@@ -207,15 +207,32 @@ static size_t lds_limit() {
 }
 
 // Chooses the sweep.  n_mat < 0: the fields are not known (footprint bound).
+// Chunks of 1024 or 512 cells (four or two per lane: fewer barriers per
+// sweep) where the diagonals are that long, else of up to 256 cells, one per
+// lane; the table mode wherever its coefficients fit in LDS beside the chunk
+// slots and the face traces, else the cell mode.
 static void plan_dg(Sizes& z, const slh_problem* p, long long n_mat) {
   const int diag = std::min(p->nx, p->ny);  // longest diagonal
-  z.dg_cw = std::min(256, (diag + 63) / 64 * 64);
+  std::vector<std::pair<int, int>> cand;    // (cells per lane, cells per chunk)
+  for (int q = 4; q > 1; q /= 2)
+    if (diag >= 256 * q) cand.emplace_back(q, 256 * q);
+  for (int cw = std::min(256, (diag + 63) / 64 * 64); cw >= 64; cw -= 64) cand.emplace_back(1, cw);
   const size_t lim = lds_limit();
-  // the cell-mode sweep must fit; fewer lanes per chunk leave more LDS for the faces
-  while (z.dg_cw > 64 && dg_sweep_lds_bytes(false, z.dg_cw, 0, p->nx, p->ny) > lim)
-    z.dg_cw -= 64;
   z.n_mat = n_mat < 0 ? (int)std::max<long long>(0, (long long)(lim / 256)) : (int)n_mat;
-  z.dg_table = n_mat != 0 && dg_sweep_lds_bytes(true, z.dg_cw, z.n_mat, p->nx, p->ny) <= lim;
+  z.dg_q = 1;
+  z.dg_cw = 64;  // nothing fits: set-up reports the mesh as too large
+  z.dg_table = false;
+  bool chosen = false;
+  for (int table = n_mat > 0 ? 1 : 0; table >= 0 && !chosen; --table)
+    for (const auto& c : cand)
+      if ((table || c.first <= 2) &&  // four cell-mode solves per lane spill registers
+          dg_sweep_lds_bytes(table != 0, c.second, table ? z.n_mat : 0, p->nx, p->ny) <= lim) {
+        z.dg_q = c.first;
+        z.dg_cw = c.second;
+        z.dg_table = table != 0;
+        chosen = true;
+        break;
+      }
   if (n_mat < 0) z.dg_table = true;  // bound: table storage counted
   z.dg_chunks = dg_chunks(p->nx, p->ny, z.dg_cw);
 }
@@ -382,26 +399,29 @@ struct BalStore {
   int numeric;        // DevState::numeric of the pass
 };
 
-// End of a pass: its balance record for slh_get_balance, and the device
-// totals of the step (si_active: the step had a source iteration, whose state
-// is final when the remap pass ends).
+// End of a pass: its balance record for slh_get_balance; at the end of the
+// remap pass also the step's device totals (both passes: a step that halts
+// between them books nothing, so running it again counts it once;
+// si_active: the step had a source iteration, whose state is final then).
 __global__ void k_snapshot(DevState* st, BalStore* out, int kind, int si_active) {
+  if (st->halt) return;
   const int t = threadIdx.x;
   if (t < 2 * B_NFIELDS) out->bal[t] = st->bal[t];
   if (t == 0) {
-    int num = st->numeric | (st->killed ? 16 : 0);
-    st->acc_seg[kind - 1] += st->segments;
-    st->acc_killed += st->killed;
-    if (kind == 1) {
-      st->acc_census_in += (unsigned long long)st->n_in;
-      st->acc_thin_overflow += st->thin_overflow ? 1ull : 0ull;
-    } else {
+    if (kind == 2) {
+      const BalStore* p1 = out - 1;  // the pass-1 record of this step
+      int num = p1->numeric | (p1->killed ? 16 : 0) | st->numeric | (st->killed ? 16 : 0);
+      st->acc_seg[0] += p1->segments;
+      st->acc_seg[1] += st->segments;
+      st->acc_killed += p1->killed + st->killed;
+      st->acc_census_in += (unsigned long long)p1->n_in;
+      st->acc_thin_overflow += p1->thin_overflow ? 1ull : 0ull;
       st->acc_census_out += st->alive;
       st->acc_steps += 1ull;
       if (si_active && !st->si.conv) st->acc_unconv += 1ull;
       if (si_active && st->si.bad) num |= 8;
+      st->acc_numeric |= num;
     }
-    st->acc_numeric |= num;
     out->segments = st->segments;
     out->particles = st->particles;
     out->alive = st->alive;
@@ -427,6 +447,7 @@ __global__ void k_state_init(DevState* st) {
 __global__ void k_state_set_bank(DevState* st, long long n, double maxabs,
                                  unsigned long long step) {
   if (threadIdx.x == 0) {
+    st->halt = 0;
     st->step = step;
     st->n_in = n;
     st->n_kept = n;
@@ -521,7 +542,14 @@ struct slh_solver {
   int grid1 = 1, grid2 = 1;       // persistent grids of the two MC passes
   bool timing = false;            // steps as graph parts and MC kernels between events
   hipStream_t cap_stream = nullptr;
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (part, parity, batch)
+  // source iterations launched per step: si_batch (adaptive) in production;
+  // a step whose batch ends before the iteration halts itself and the steps
+  // after it on the device, and settle() runs them again
+  int si_batch = 0;
+  int batch_run = 0;          // the batch of the step being enqueued
+  bool unsettled = false;     // steps enqueued since the last settle()
+  unsigned long long restarts = 0ull;  // steps run again after a halt
   unsigned long long graph_launches = 0ull;
   // timing mode: events of the steps enqueued since the last collection
   std::vector<StepEvents> ev_pool;
@@ -880,7 +908,7 @@ static DgArgs dg_args(slh_solver* s) {
   d.coef = s->coef;
   d.dirmat = s->dirmat;
   d.n_chunks = (int)z.dg_chunks;
-  d.loader_q = 1;  // one loader wave per sweeping wave
+  d.cells_per_lane = z.dg_q;
   d.bc = s->prob.boundary;
   d.refl_x = s->refl_x;
   d.refl_y = s->refl_y;
@@ -960,9 +988,9 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
   const double cdt = p.steady ? s->horizon : p.c * p.dt;  // longest path of a history
   const long long cstride = (long long)kTallyStride * nc;
   const long long n_tally = (long long)z.n_copies * kTallyStride * nc;
-  // source iterations launched per step: the limit (predicated on the
+  // source iterations launched in this step's batch (each predicated on the
   // device's stopping test), none without a collided solve
-  const int n_it = s->skip_remap ? 0 : s->si_max;
+  const int n_it = s->skip_remap ? 0 : s->batch_run;
   switch (part) {
     case kA: {
       HIP_TRY(launch_emission_plan(s->qn1, nc, s->adt, z.n_p, p.seed, p.points, 1, s->maj_hist,
@@ -980,7 +1008,7 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
                                    cstride, s->st, inv_adt, st));
       hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, st, s->st, s->bal_store + 0, 1, 0);
       if (use_cg(s)) {
-        HIP_TRY(launch_cg_start(cg_args(s), s->sig_s, s->phi_post, s->si_max, st));
+        HIP_TRY(launch_cg_start(cg_args(s), s->sig_s, s->phi_post, s->si_max, &s->st->halt, st));
       } else {
         // pure MC in steady state: no collided solve (phi_c = 0, no sweep)
         HIP_TRY(launch_si_start(dg_args(s), s->skip_remap ? 0 : s->si_max, st));
@@ -989,14 +1017,16 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
         const slh_status r = enqueue_si(s, st, n_it);
         if (r != SLH_OK) return r;
       }
+      // a batch short of the limit may end before the iteration does
+      if (n_it > 0 && n_it < s->si_max) HIP_TRY(launch_si_check(s->st, st));
       if (s->skip_remap) {  // no remap leg: clear its balance and census flags only
         HIP_TRY(launch_pass_prep(s->st, s->ctree1, 1, z.n_src_cap, cdt, nullptr, 0, nullptr, 0,
                                  s->alive, z.n_cand, st));
         return SLH_OK;
       }
-      if (use_cg(s)) HIP_TRY(launch_cg_to_nodal(cg_args(s), s->phi_c, st));
+      if (use_cg(s)) HIP_TRY(launch_cg_to_nodal(cg_args(s), s->phi_c, &s->st->halt, st));
       HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c,
-                                  s->qnR, st));
+                                  s->qnR, &s->st->halt, st));
       HIP_TRY(launch_emission_plan(s->qnR, nc, s->adt, z.n_p, p.seed, p.points, 2, s->maj_hist,
                                    s->ctreeR, s->st, st));
       HIP_TRY(launch_pass_prep(s->st, s->ctreeR, 2, z.n_src_cap, cdt, s->TR, n_tally, nullptr, 0,
@@ -1018,13 +1048,13 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
       if (z.fp32) {
         const StageRec<float>* src = (const StageRec<float>*)s->stage_mem;
         HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
-        HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
+        HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, &s->st->halt, st));
         HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, z.cap, (StageRec<float>*)nb,
                                              s->st, s->cmax, st));
       } else {
         const StageRec<double>* src = (const StageRec<double>*)s->stage_mem;
         HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
-        HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, st));
+        HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, &s->st->halt, st));
         HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand, z.cap,
                                               (StageRec<double>*)nb, s->st, s->cmax, st));
       }
@@ -1069,7 +1099,7 @@ static bool capture(slh_solver* s, int first, int last, hipGraphExec_t* out) {
 // step, and the census-bank parity), or directly.
 static slh_status launch_parts(slh_solver* s, int first, int last, int key) {
   if (s->use_graphs) {
-    const auto k = std::make_pair(key, s->cur);
+    const auto k = std::make_tuple(key, s->cur, s->batch_run);
     auto it = s->graphs.find(k);
     if (it == s->graphs.end()) {
       hipGraphExec_t e = nullptr;
@@ -1090,9 +1120,12 @@ static slh_status record(hipEvent_t e, hipStream_t st) {
   return SLH_OK;
 }
 
-// Enqueues one time step; no host wait.
-static slh_status run_step(slh_solver* s) {
+// Enqueues one time step with a batch of `batch` source iterations; no host
+// wait.
+static slh_status run_step(slh_solver* s, int batch) {
   slh_status r;
+  s->batch_run = batch;
+  s->unsettled = true;
   if (!s->timing) {
     r = launch_parts(s, kA, kEnd, kWhole);
     if (r != SLH_OK) return r;
@@ -1193,6 +1226,13 @@ static void scratch_release(int dev) {
   if (dev >= 0 && dev < kMaxDevices) g_scratch_busy[dev] = false;
 }
 
+// A batch of source iterations: n rounded up to a multiple of eight, at most
+// the limit (fewer distinct batches, fewer captured graphs).
+static int round_batch(long long n, int si_max) {
+  n = (n + 7) / 8 * 8;
+  return (int)std::max<long long>(1, std::min<long long>(n, si_max));
+}
+
 static slh_status create_solver(const slh_problem* problem, void* hip_stream, slh_alloc_fn alloc,
                                 slh_free_fn free_fn, void* ctx, bool static_mem,
                                 slh_solver** out) {
@@ -1260,6 +1300,25 @@ static slh_status create_solver(const slh_problem* problem, void* hip_stream, sl
   s->si_tol = problem->si_tol > 0.0 ? problem->si_tol : 1e-12;
   s->si_max = problem->si_max_iter > 0 ? problem->si_max_iter : 200;
   s->thin_margin = (long long)ceil(4.0 * sqrt((double)s->z.cap)) + 16;
+  // first batch of source iterations per step: for the plain iteration the
+  // count at which the largest scattering ratio c = sigma_s / sigma_e, its
+  // worst-case contraction, reaches the tolerance; 8 with the diffusion
+  // correction, 64 conjugate-gradient steps for the diffusion closing stage
+  // (the batch adapts once the first steps are settled)
+  if (s->z.diffusion) {
+    s->si_batch = round_batch(64, s->si_max);
+  } else if (s->z.dsa) {
+    s->si_batch = round_batch(8, s->si_max);
+  } else {
+    double c = 0.0;
+    const double tt = time_term(problem);
+    for (long long i = 0; i < s->z.n_cells; ++i) {
+      const double se = s->h_sig_a[i] + s->h_sig_s[i] + tt;
+      if (se > 0.0) c = std::max(c, s->h_sig_s[i] / se);
+    }
+    const double n = c <= 0.0 ? 1.0 : c >= 1.0 ? 64.0 : ceil(log(s->si_tol) / log(c)) + 2.0;
+    s->si_batch = round_batch((long long)std::min(64.0, std::max(8.0, n)), s->si_max);
+  }
   slh_status r = setup(s);
   if (r != SLH_OK) {
     s->release();
@@ -1292,9 +1351,48 @@ extern "C" slh_status slh_advance(slh_solver* s, int32_t n_steps) {
   if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
   if (n_steps < 1) return fail(SLH_E_INVALID_ARG, "n_steps must be >= 1");
   for (int k = 0; k < n_steps; ++k) {
-    const slh_status r = run_step(s);
+    const slh_status r = run_step(s, s->si_batch);
     if (r != SLH_OK) return r;
   }
+  return SLH_OK;
+}
+
+// Waits for the enqueued steps and runs again those that a halted batch left
+// undone.  A halted step and every step after it returned from each kernel at
+// once, so the device holds the state at the start of the halted step: it is
+// run with the full limit si_max (its batch cannot end early), the ones after
+// it with a doubled batch, and the check repeats until no step halted.  The
+// batch then follows the last step's iteration count (a quarter more, plus
+// two, in multiples of eight).
+static slh_status settle(slh_solver* s, DevState* out = nullptr) {
+  DevState d;
+  for (;;) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    COPY_SYNC(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
+    if (!d.halt) break;
+    const long long lost = s->step - (long long)d.step;
+    if (lost < 1) return fail(SLH_E_STATE, "a halted step that was not enqueued");
+    if (s->timing) s->ev_used -= std::min<size_t>(s->ev_used, (size_t)lost);
+    s->cur ^= (int)(lost & 1);
+    s->step -= lost;
+    s->restarts += (unsigned long long)lost;
+    s->si_batch = round_batch(2ll * s->si_batch, s->si_max);
+    HIP_TRY(hipMemsetAsync(&s->st->halt, 0, sizeof(int), s->stream));
+    slh_status r = run_step(s, s->si_max);
+    for (long long k = 1; k < lost && r == SLH_OK; ++k) r = run_step(s, s->si_batch);
+    if (r != SLH_OK) return r;
+  }
+  if (s->unsettled && !s->skip_remap && d.si.iter > 0)
+    s->si_batch = round_batch(d.si.iter + d.si.iter / 4 + 2, s->si_max);
+  s->unsettled = false;
+  if (out) *out = d;
+  return SLH_OK;
+}
+
+extern "C" slh_status slh_set_si_batch(slh_solver* s, int32_t n) {
+  if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
+  if (n < 1) return fail(SLH_E_INVALID_ARG, "the batch must be >= 1");
+  s->si_batch = n < s->si_max ? n : s->si_max;
   return SLH_OK;
 }
 
@@ -1313,10 +1411,10 @@ extern "C" slh_status slh_set_timing(slh_solver* s, int32_t enable) {
   return SLH_OK;
 }
 
-// Reads the device state after the stream is idle.
+// Reads the device state once every enqueued step is done.
 static slh_status read_state(slh_solver* s, DevState* d) {
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  COPY_SYNC(d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
+  const slh_status r = settle(s, d);
+  if (r != SLH_OK) return r;
   return collect_events(s);
 }
 
@@ -1361,6 +1459,8 @@ extern "C" slh_status slh_get_flux(slh_solver* s, int32_t which, double* host_ou
   long long n;
   const double* p = flux_ptr(s, which, &n);
   if (!p) return fail(SLH_E_INVALID_ARG, "unknown flux kind");
+  const slh_status r = settle(s);
+  if (r != SLH_OK) return r;
   HIP_TRY(hipMemcpyAsync(host_out, p, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return SLH_OK;
@@ -1371,6 +1471,10 @@ extern "C" slh_status slh_get_flux_device(slh_solver* s, int32_t which, double* 
   long long n;
   const double* p = flux_ptr(s, which, &n);
   if (!p) return fail(SLH_E_INVALID_ARG, "unknown flux kind");
+  // a step that halted must run again before its flux can be taken: wait
+  // for the steps enqueued since the last settle, if any
+  const slh_status r = settle(s);
+  if (r != SLH_OK) return r;
   HIP_TRY(hipMemcpyAsync(dev_out, p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->stream));
   return SLH_OK;
 }
@@ -1378,6 +1482,10 @@ extern "C" slh_status slh_get_flux_device(slh_solver* s, int32_t which, double* 
 extern "C" slh_status slh_get_balance(slh_solver* s, int32_t pass, slh_balance* out) {
   if (!s || !out) return fail(SLH_E_INVALID_ARG, "NULL argument");
   if (pass != 1 && pass != 2) return fail(SLH_E_INVALID_ARG, "pass must be 1 or 2");
+  {
+    const slh_status r = settle(s);
+    if (r != SLH_OK) return r;
+  }
   BalStore b;
   HIP_TRY(hipMemcpyAsync(&b, s->bal_store + (pass - 1), sizeof(BalStore), hipMemcpyDeviceToHost,
                          s->stream));
@@ -1434,6 +1542,8 @@ extern "C" slh_status slh_get_stats(slh_solver* s, slh_stats* out) {
   out->dsa_iterations = d.dsa_iter_total;
   out->dsa_unconverged = d.dsa_unconv;
   out->si_unconverged_total = d.acc_unconv;
+  out->si_batch = s->skip_remap ? 0 : s->si_batch;
+  out->si_restarts_total = s->restarts;
   out->numeric_flags = d.acc_numeric;
   if (s->have_stage) {
     out->ms_mc = s->stage_ms[0];
@@ -1484,9 +1594,11 @@ extern "C" slh_status slh_get_census(slh_solver* s, int64_t* n, double* x, doubl
                                      double* ox, double* oy, double* w, int32_t* cell,
                                      uint64_t* hid) {
   if (!s || !n) return fail(SLH_E_INVALID_ARG, "NULL argument");
-  HIP_TRY(hipStreamSynchronize(s->stream));
   DevState d;
-  COPY_SYNC(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
+  {
+    const slh_status r = settle(s, &d);
+    if (r != SLH_OK) return r;
+  }
   const long long cnt = d.n_in;
   *n = cnt;
   if (cnt == 0) return SLH_OK;
@@ -1524,9 +1636,11 @@ static const size_t kCkptHead = 10 * 8;
 
 extern "C" slh_status slh_save(slh_solver* s, void* buf, size_t* len) {
   if (!s || !len) return fail(SLH_E_INVALID_ARG, "NULL argument");
-  HIP_TRY(hipStreamSynchronize(s->stream));
   DevState d;
-  COPY_SYNC(&d, s->st, sizeof(DevState), hipMemcpyDeviceToHost);
+  {
+    const slh_status r = settle(s, &d);
+    if (r != SLH_OK) return r;
+  }
   const long long cnt = d.n_in;
   const size_t need = kCkptHead + (size_t)cnt * ((s->z.fp32 ? 4 : 8) * 5 + 8 + 4);
   if (!buf) { *len = need; return SLH_OK; }
@@ -1611,7 +1725,10 @@ extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
   const bool ok = s->z.fp32 ? ckpt_bank_ok<float>(in, cnt, s->z.n_cells, s->hx, s->hy, maxabs)
                             : ckpt_bank_ok<double>(in, cnt, s->z.n_cells, s->hx, s->hy, maxabs);
   if (!ok) return fail(SLH_E_INVALID_ARG, "checkpoint particles are not valid for this problem");
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  {
+    const slh_status r = settle(s);  // steps still enqueued finish first
+    if (r != SLH_OK) return r;
+  }
   {
     const uint64_t* hh = (const uint64_t*)(in + rb * 5 * cnt);
     const int32_t* cc = (const int32_t*)(in + rb * 5 * cnt + 8 * cnt);

@@ -60,6 +60,7 @@ __global__ void k_si_start(int nx, int ny, const double* __restrict__ sig_s,
                            const double* __restrict__ phi_post, double* __restrict__ phi_c,
                            double* __restrict__ S, double* __restrict__ bnd0, long long n_bnd,
                            DevState* st, int si_max) {
+  if (st->halt) return;
   const long long n = (long long)nx * ny;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->si.iter = 0;
@@ -202,14 +203,17 @@ struct DgStage {
 };
 
 // The sweep of one direction, compiled for each quadrant (APOS: Omega_x > 0,
-// BPOS: Omega_y > 0), so that the upwind order costs no selects.
+// BPOS: Omega_y > 0), so that the upwind order costs no selects.  A chunk has
+// CW cells; a sweeping lane takes Q of them (positions t, t + CW/Q, ...),
+// whose independent solves hide each other's latency, and so does a loader
+// lane.
 template <bool TABLE, int Q, bool REFL, bool APOS, bool BPOS>
 __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
   extern __shared__ double smem[];
   const int nx = g.nx, ny = g.ny;
-  const int CW = g.cw;       // sweeping lanes, multiple of 64, <= 256
-  const int n_sw = CW >> 6;  // sweeping waves; the loader waves follow them
-  const int n_ld = n_sw / Q; // loader waves, Q cells per loader lane and chunk
+  const int CW = g.cw;            // cells per chunk, a multiple of 64 Q
+  const int n_sw = CW / (64 * Q); // sweeping waves; as many loader waves follow them
+  const int n_ld = n_sw;
   const int m = blockIdx.x;
   constexpr bool apos = APOS, bpos = BPOS;
   // LDS: slots S [2][CW] as two double2 halves | keys [2][CW] | coef [n_mat][kDgRow] | faces
@@ -360,8 +364,9 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
     return;
   }
 
-  // ---- sweeping lanes ----
+  // ---- sweeping lanes: Q cells each ----
   const int t = threadIdx.x;
+  const int span = CW / Q;  // chunk positions t + r span, r < Q
   double dmA[16], dmF[16];  // cell mode: direction element data
   if (!TABLE) {
 #pragma unroll
@@ -378,60 +383,68 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
       {hx * hy / 36.0, hx * hy / 18.0, hx * hy / 18.0, hx * hy / 9.0}};
   double4* __restrict__ out = reinterpret_cast<double4*>(g.psi + (long long)m * 4 * nx * ny);
   int cd = 0, cp = 0;  // next chunk to prepare
-  bool c_has = false;
-  int c_i = 0, c_j = 0;
-  long long c_pos = 0;
-  double P[16];    // table: G; cell mode: LU (inverse pivots, L, strict U)
-  double r0[4];    // table: B S; cell mode: MM S
+  // the prepared cells: present, indices (0 for an absent cell, whose
+  // arithmetic runs on stale data and is dropped) and layout position
+  bool c_has[Q];
+  int c_i[Q], c_j[Q];
+  long long c_pos[Q];
+  double P[Q][16];    // table: G; cell mode: LU (inverse pivots, L, strict U)
+  double r0[Q][4];    // table: B S; cell mode: MM S
   auto prepare = [&](int slot) __attribute__((always_inline)) {
-    const int ip = cp + t;
-    c_has = cd < n_diag && ip <= diag_hi(cd);
-    if (c_has) {
-      const int jp = cd - ip;
-      c_i = apos ? ip : nx - 1 - ip;
-      c_j = bpos ? jp : ny - 1 - jp;
-      c_pos = run_base(cd) + c_i;
-      const double2 sa = slotA[slot * CW + t], sb = slotB[slot * CW + t];
-      const double4 S = make_double4(sa.x, sa.y, sb.x, sb.y);
-      const double key = slotK[slot * CW + t];
-      if (TABLE) {
-        const double* c = coefL + (size_t)(int)key * kDgRow;
-        r0[0] = S.x;  // B S, formed by the loader
-        r0[1] = S.y;
-        r0[2] = S.z;
-        r0[3] = S.w;
+    const bool live = cd < n_diag;
+    const int hi = live ? diag_hi(cd) : -1;
+    const long long rb = run_base(live ? cd : n_diag - 1);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) P[k] = c[16 + k];
+    for (int r = 0; r < Q; ++r) {
+      const int tr = t + r * span;
+      const int ip = cp + tr;
+      const bool h = ip <= hi;
+      const int jp = cd - ip;
+      c_has[r] = h;
+      c_i[r] = h ? (apos ? ip : nx - 1 - ip) : 0;
+      c_j[r] = h ? (bpos ? jp : ny - 1 - jp) : 0;
+      c_pos[r] = rb + c_i[r];
+      const double2 sa = slotA[slot * CW + tr], sb = slotB[slot * CW + tr];
+      const double4 S = make_double4(sa.x, sa.y, sb.x, sb.y);
+      const double key = slotK[slot * CW + tr];
+      if (TABLE) {
+        const double* c = coefL + (size_t)(h ? (int)key : 0) * kDgRow;
+        r0[r][0] = S.x;  // B S, formed by the loader
+        r0[r][1] = S.y;
+        r0[r][2] = S.z;
+        r0[r][3] = S.w;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) P[r][k] = c[16 + k];
       } else {
         double A[4][4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int a = 0; a < 4; ++a) {
 #pragma unroll
-          for (int l = 0; l < 4; ++l) A[r][l] = dmA[4 * r + l] + key * MM[r][l];
-          r0[r] = MM[r][0] * S.x + MM[r][1] * S.y + MM[r][2] * S.z + MM[r][3] * S.w;
+          for (int l = 0; l < 4; ++l) A[a][l] = dmA[4 * a + l] + key * MM[a][l];
+          r0[r][a] = MM[a][0] * S.x + MM[a][1] * S.y + MM[a][2] * S.z + MM[a][3] * S.w;
         }
         // LU without pivoting (see k_dg_coef for why the pivots do not vanish)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const double inv = recip(A[c][c]);
-          P[c] = inv;
+          P[r][c] = inv;
 #pragma unroll
-          for (int r = c + 1; r < 4; ++r) {
-            const double f = A[r][c] * inv;
-            A[r][c] = f;
+          for (int a = c + 1; a < 4; ++a) {
+            const double f = A[a][c] * inv;
+            A[a][c] = f;
 #pragma unroll
-            for (int l = c + 1; l < 4; ++l) A[r][l] -= f * A[c][l];
+            for (int l = c + 1; l < 4; ++l) A[a][l] -= f * A[c][l];
           }
         }
-        P[4] = A[1][0]; P[5] = A[2][0]; P[6] = A[3][0];
-        P[7] = A[2][1]; P[8] = A[3][1]; P[9] = A[3][2];
-        P[10] = A[0][1]; P[11] = A[0][2]; P[12] = A[0][3];
-        P[13] = A[1][2]; P[14] = A[1][3]; P[15] = A[2][3];
+        P[r][4] = A[1][0]; P[r][5] = A[2][0]; P[r][6] = A[3][0];
+        P[r][7] = A[2][1]; P[r][8] = A[3][1]; P[r][9] = A[3][2];
+        P[r][10] = A[0][1]; P[r][11] = A[0][2]; P[r][12] = A[0][3];
+        P[r][13] = A[1][2]; P[r][14] = A[1][3]; P[r][15] = A[2][3];
       }
     }
-    if (cd < n_diag) {
+    if (live) {
       cp += CW;
-      if (cp > diag_hi(cd)) {
+      if (cp > hi) {
         ++cd;
         cp = cd < n_diag ? diag_lo(cd) : 0;
       }
@@ -440,46 +453,54 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
   prepare(0);
   for (int k = 0; k < n_pad; ++k) {
     __syncthreads();  // traces of chunk k - 1 written, chunk k + 1 in its slot
-    if (c_has) {
-      const double u0 = xf[2 * c_j], u1 = xf[2 * c_j + 1];
-      const double u2 = yf[2 * c_i], u3 = yf[2 * c_i + 1];
-      double x0, x1, x2, x3;
+    double x[Q][4];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      const double u0 = xf[2 * c_j[r]], u1 = xf[2 * c_j[r] + 1];
+      const double u2 = yf[2 * c_i[r]], u3 = yf[2 * c_i[r] + 1];
+      const double* Pr = P[r];
       if (TABLE) {
-        x0 = r0[0] + P[0] * u0 + P[1] * u1 + P[2] * u2 + P[3] * u3;
-        x1 = r0[1] + P[4] * u0 + P[5] * u1 + P[6] * u2 + P[7] * u3;
-        x2 = r0[2] + P[8] * u0 + P[9] * u1 + P[10] * u2 + P[11] * u3;
-        x3 = r0[3] + P[12] * u0 + P[13] * u1 + P[14] * u2 + P[15] * u3;
+        x[r][0] = r0[r][0] + Pr[0] * u0 + Pr[1] * u1 + Pr[2] * u2 + Pr[3] * u3;
+        x[r][1] = r0[r][1] + Pr[4] * u0 + Pr[5] * u1 + Pr[6] * u2 + Pr[7] * u3;
+        x[r][2] = r0[r][2] + Pr[8] * u0 + Pr[9] * u1 + Pr[10] * u2 + Pr[11] * u3;
+        x[r][3] = r0[r][3] + Pr[12] * u0 + Pr[13] * u1 + Pr[14] * u2 + Pr[15] * u3;
       } else {
-        double y0 = r0[0] + dmF[0] * u0 + dmF[1] * u1 + dmF[2] * u2 + dmF[3] * u3;
-        double y1 = r0[1] + dmF[4] * u0 + dmF[5] * u1 + dmF[6] * u2 + dmF[7] * u3;
-        double y2 = r0[2] + dmF[8] * u0 + dmF[9] * u1 + dmF[10] * u2 + dmF[11] * u3;
-        double y3 = r0[3] + dmF[12] * u0 + dmF[13] * u1 + dmF[14] * u2 + dmF[15] * u3;
-        y1 -= P[4] * y0;
-        y2 -= P[5] * y0 + P[7] * y1;
-        y3 -= P[6] * y0 + P[8] * y1 + P[9] * y2;
-        x3 = y3 * P[3];
-        x2 = (y2 - P[15] * x3) * P[2];
-        x1 = (y1 - P[13] * x2 - P[14] * x3) * P[1];
-        x0 = (y0 - P[10] * x1 - P[11] * x2 - P[12] * x3) * P[0];
+        double y0 = r0[r][0] + dmF[0] * u0 + dmF[1] * u1 + dmF[2] * u2 + dmF[3] * u3;
+        double y1 = r0[r][1] + dmF[4] * u0 + dmF[5] * u1 + dmF[6] * u2 + dmF[7] * u3;
+        double y2 = r0[r][2] + dmF[8] * u0 + dmF[9] * u1 + dmF[10] * u2 + dmF[11] * u3;
+        double y3 = r0[r][3] + dmF[12] * u0 + dmF[13] * u1 + dmF[14] * u2 + dmF[15] * u3;
+        y1 -= Pr[4] * y0;
+        y2 -= Pr[5] * y0 + Pr[7] * y1;
+        y3 -= Pr[6] * y0 + Pr[8] * y1 + Pr[9] * y2;
+        x[r][3] = y3 * Pr[3];
+        x[r][2] = (y2 - Pr[15] * x[r][3]) * Pr[2];
+        x[r][1] = (y1 - Pr[13] * x[r][2] - Pr[14] * x[r][3]) * Pr[1];
+        x[r][0] = (y0 - Pr[10] * x[r][1] - Pr[11] * x[r][2] - Pr[12] * x[r][3]) * Pr[0];
       }
-      xf[2 * c_j] = apos ? x1 : x0;
-      xf[2 * c_j + 1] = apos ? x3 : x2;
-      yf[2 * c_i] = bpos ? x2 : x0;
-      yf[2 * c_i + 1] = bpos ? x3 : x1;
+    }
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      if (!c_has[r]) continue;
+      const double x0 = x[r][0], x1 = x[r][1], x2 = x[r][2], x3 = x[r][3];
+      const int ci = c_i[r], cj = c_j[r];
+      xf[2 * cj] = apos ? x1 : x0;
+      xf[2 * cj + 1] = apos ? x3 : x2;
+      yf[2 * ci] = bpos ? x2 : x0;
+      yf[2 * ci + 1] = bpos ? x3 : x1;
       // outflow on a reflective downwind side, for the mirrored direction
       if (REFL && rx_out) {
-        if (c_i == (apos ? nx - 1 : 0)) {
-          b_out[2 * c_j] = apos ? x1 : x0;
-          b_out[2 * c_j + 1] = apos ? x3 : x2;
+        if (ci == (apos ? nx - 1 : 0)) {
+          b_out[2 * cj] = apos ? x1 : x0;
+          b_out[2 * cj + 1] = apos ? x3 : x2;
         }
       }
       if (REFL && ry_out) {
-        if (c_j == (bpos ? ny - 1 : 0)) {
-          b_out[2 * ny + 2 * c_i] = bpos ? x2 : x0;
-          b_out[2 * ny + 2 * c_i + 1] = bpos ? x3 : x1;
+        if (cj == (bpos ? ny - 1 : 0)) {
+          b_out[2 * ny + 2 * ci] = bpos ? x2 : x0;
+          b_out[2 * ny + 2 * ci + 1] = bpos ? x3 : x1;
         }
       }
-      out[c_pos - lay_base] = make_double4(x0, x1, x2, x3);
+      out[c_pos[r] - lay_base] = make_double4(x0, x1, x2, x3);
     }
     prepare((k + 1) & 1);
   }
@@ -518,12 +539,24 @@ hipError_t launch_si_start(const DgArgs& a, int si_max, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_si_check(DevState* st) {
+  if (threadIdx.x == 0 && !st->halt && !st->si.done) {
+    st->halt = 1;
+    st->si.done = 1;
+  }
+}
+
+hipError_t launch_si_check(DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_si_check, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   const size_t lds = dg_sweep_lds_bytes(table, a.cw, a.n_mat, a.nx, a.ny);
-  const int n_sw = a.cw / 64;
-  const int q = a.loader_q;  // cells per loader lane; n_sw / q loader waves
-  if (q < 1 || n_sw % q) return hipErrorInvalidValue;
-  const dim3 block(a.cw + 64 * (n_sw / q));
+  const int q = a.cells_per_lane;  // cells per sweeping and per loader lane
+  if ((q != 1 && q != 2 && q != 4) || a.cw % (64 * q) || a.cw / (64 * q) > 4)
+    return hipErrorInvalidValue;
+  const dim3 block(2 * a.cw / q);  // as many loader waves as sweeping waves
   const bool refl = a.bc != 0 && a.bnd != nullptr;
 #define SLH_DG_SWEEP(T_, Q_)                                                                  \
   do {                                                                                        \
@@ -533,12 +566,10 @@ hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s) {
   if (table) {
     if (q == 1) SLH_DG_SWEEP(true, 1);
     else if (q == 2) SLH_DG_SWEEP(true, 2);
-    else if (q == 3) SLH_DG_SWEEP(true, 3);
     else SLH_DG_SWEEP(true, 4);
   } else {
     if (q == 1) SLH_DG_SWEEP(false, 1);
     else if (q == 2) SLH_DG_SWEEP(false, 2);
-    else if (q == 3) SLH_DG_SWEEP(false, 3);
     else SLH_DG_SWEEP(false, 4);
   }
 #undef SLH_DG_SWEEP

@@ -134,7 +134,9 @@ __device__ __forceinline__ double sum_partials(const double* part, int n_part, i
 __global__ __launch_bounds__(kCgBlock) void k_cg_start(
     long long n, const double* __restrict__ sig_s, const double* __restrict__ phi_post,
     const double* __restrict__ diag, double* __restrict__ x, double* __restrict__ r,
-    double* __restrict__ z, double* __restrict__ p1, double* __restrict__ part) {
+    double* __restrict__ z, double* __restrict__ p1, double* __restrict__ part,
+    const int* halt) {
+  if (*halt) return;
   double rz = 0.0, bb = 0.0;
   for (long long k = (long long)blockIdx.x * kCgBlock + threadIdx.x; k < n;
        k += (long long)gridDim.x * kCgBlock) {
@@ -152,8 +154,8 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_start(
 
 __global__ __launch_bounds__(kCgBlock) void k_cg_start_state(const double* part, int n_part,
                                                              IterState* cs, const int* gate,
-                                                             int max_iter) {
-  if (gate && *gate) return;
+                                                             int max_iter, const int* halt) {
+  if ((gate && *gate) || (halt && *halt)) return;
   const double rz = sum_partials(part, n_part, 0);
   const double bb = sum_partials(part, n_part, 1);
   if (threadIdx.x == 0) {
@@ -367,7 +369,8 @@ __global__ __launch_bounds__(kCgOneBlock) void k_cg_solve_one_block(
 
 // phi_c nodal = the cell value at all four nodes.
 __global__ void k_cg_to_nodal(long long n, const double* __restrict__ x,
-                              double* __restrict__ phi_c) {
+                              double* __restrict__ phi_c, const int* halt) {
+  if (*halt) return;
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (long long)gridDim.x * blockDim.x) {
     const double v = x[k];
@@ -376,12 +379,12 @@ __global__ void k_cg_to_nodal(long long n, const double* __restrict__ x,
 }
 
 hipError_t launch_cg_start(const CgArgs& a, const double* sig_s, const double* phi_post,
-                           int max_iter, hipStream_t s) {
+                           int max_iter, const int* halt, hipStream_t s) {
   const long long n = (long long)a.nx * a.ny;
   hipLaunchKernelGGL(k_cg_start, dim3(a.n_part), dim3(kCgBlock), 0, s, n, sig_s, phi_post,
-                     (const double*)a.diag, a.x, a.r, a.z, a.P + n, a.part_a);
+                     (const double*)a.diag, a.x, a.r, a.z, a.P + n, a.part_a, halt);
   hipLaunchKernelGGL(k_cg_start_state, dim3(1), dim3(kCgBlock), 0, s, (const double*)a.part_a,
-                     a.n_part, a.cs, a.gate, max_iter);
+                     a.n_part, a.cs, a.gate, max_iter, halt);
   return hipGetLastError();
 }
 
@@ -391,7 +394,7 @@ hipError_t launch_dsa_start(const CgArgs& a, const double* sig_s, const double* 
   hipLaunchKernelGGL(k_dsa_start, dim3(a.n_part), dim3(kCgBlock), 0, s, n, sig_s, dnode,
                      (const double*)a.diag, a.x, a.r, a.z, a.P + n, a.part_a, a.gate);
   hipLaunchKernelGGL(k_cg_start_state, dim3(1), dim3(kCgBlock), 0, s, (const double*)a.part_a,
-                     a.n_part, a.cs, a.gate, max_iter);
+                     a.n_part, a.cs, a.gate, max_iter, (const int*)nullptr);
   return hipGetLastError();
 }
 
@@ -419,10 +422,10 @@ hipError_t launch_cg_iteration(const CgArgs& a, double tol, int max_iter, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_cg_to_nodal(const CgArgs& a, double* phi_c, hipStream_t s) {
+hipError_t launch_cg_to_nodal(const CgArgs& a, double* phi_c, const int* halt, hipStream_t s) {
   const long long n = (long long)a.nx * a.ny;
   hipLaunchKernelGGL(k_cg_to_nodal, dim3(a.n_part), dim3(kCgBlock), 0, s, n,
-                     (const double*)a.x, phi_c);
+                     (const double*)a.x, phi_c, halt);
   return hipGetLastError();
 }
 

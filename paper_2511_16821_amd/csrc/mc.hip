@@ -209,6 +209,7 @@ __device__ __forceinline__ void bal_add(unsigned long long* bal, int f, double v
 // time in steady state, where every particle starts at time 0).
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
+  if (a.st->halt) return;
   __shared__ uint32_t s_sobol[kSobolNibbleWords];
   __shared__ double s_top[kTreeTop];
   sobol_nibbles_fill(a.sobol, s_sobol, threadIdx.x, blockDim.x);
@@ -250,6 +251,7 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
 
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mc_pass(PassArgs a) {
+  if (a.st->halt) return;
   // Block balance in kBalCopies LDS copies picked by lane: with a per-lane
   // address the adds are plain LDS atomics, where one shared address would
   // make the compiler serialise them over the active lanes in a scalar loop.

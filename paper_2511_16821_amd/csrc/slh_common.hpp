@@ -282,7 +282,10 @@ struct DevState {
   int thin_rshift;
   int thin_active;
   int thin_overflow;              // more than cap survived the draw
-  int pad0;
+  // set when a step's batch of source iterations ended before the iteration
+  // did: every later kernel of that step and of the steps enqueued after it
+  // returns at once, and the host runs them again (with a larger batch)
+  int halt;
   // fixed-point units of the current pass (tally, balance) and inverses
   double unit_T, inv_T, unit_W, inv_W;
   unsigned long long work;      // work counter of the current pass
@@ -453,9 +456,10 @@ struct DgArgs {
   const int* mat_id;
   int n_mat;
   const double* coef;
-  int cw;                // sweeping lanes per workgroup (multiple of 64, <= 256)
+  int cw;                // cells per chunk (a multiple of 64 cells_per_lane, at
+                         // most 256 cells_per_lane)
   int n_chunks;          // dg_chunks(nx, ny, cw)
-  int loader_q;          // cells per loader lane (1..4, divides cw / 64)
+  int cells_per_lane;    // cells per sweeping and per loader lane: 1, 2 or 4
   // reflective sides (1 x_lo, 2 x_hi, 4 y_lo, 8 y_hi): the inflow of a
   // direction on such a side is the outflow of its mirror image (refl_x,
   // refl_y) from the previous iteration.  bnd holds two buffers of [n_dir]
@@ -474,6 +478,9 @@ size_t dg_sweep_lds_bytes(bool table, int cw, int n_mat, int nx, int ny);
 // Start of a step's source iteration: phi_c = 0, iteration state reset, the
 // first iterate's nodal source, reflected traces of the first sweep zeroed.
 hipError_t launch_si_start(const DgArgs& a, int si_max, hipStream_t s);
+// After a batch of source iterations: if the iteration has not stopped, the
+// step halts (DevState::halt, and si.done so that no later iteration runs).
+hipError_t launch_si_check(DevState* st, hipStream_t s);
 // Diffusion synthetic acceleration: after the correction delta (per cell) is
 // solved, phi += delta at every node, the next iterate's source, and the
 // residual of phi^{k+1} - phi^k = dnode + delta, decided as after a plain
@@ -502,9 +509,9 @@ int cg_partials(long long n);
 hipError_t launch_diff_coef(int nx, int ny, const double2* mat, double tt, double hx, double hy,
                             int bc, double* diag, double* cE, double* cN, hipStream_t s);
 // b = sigma_s phi_post, x = 0, and the state of a new solve (done at once when
-// b = 0 or max_iter = 0)
+// b = 0 or max_iter = 0); nothing while *halt is set
 hipError_t launch_cg_start(const CgArgs& a, const double* sig_s, const double* phi_post,
-                           int max_iter, hipStream_t s);
+                           int max_iter, const int* halt, hipStream_t s);
 // the same for the diffusion correction of a source iteration: b = sigma_s
 // times the cell average of dnode (phi^{k+1/2} - phi^k, four nodes per cell)
 hipError_t launch_dsa_start(const CgArgs& a, const double* sig_s, const double* dnode,
@@ -515,7 +522,7 @@ hipError_t launch_cg_solve_one_block(const CgArgs& a, double tol, int max_iter, 
 // On meshes where cg_one_block holds, one call runs the whole solve.
 bool cg_one_block(long long n);
 hipError_t launch_cg_iteration(const CgArgs& a, double tol, int si_max, hipStream_t s);
-hipError_t launch_cg_to_nodal(const CgArgs& a, double* phi_c, hipStream_t s);
+hipError_t launch_cg_to_nodal(const CgArgs& a, double* phi_c, const int* halt, hipStream_t s);
 hipError_t launch_dg_sweep(const DgArgs& a, bool table, hipStream_t s);
 // One reduction of a source iteration: the direction sum of the planes (each
 // layout's directions in order, then the two sums added) replaces phi_c in
@@ -544,7 +551,8 @@ hipError_t launch_tally_to_flux(const unsigned long long* T0, double* phi0,
                                 double inv_adt, hipStream_t s);
 hipError_t launch_remap_source(long long n, const double* q, const double* sig_s,
                                const double* phi_pre, const double* phi_post,
-                               const double* phi_c, double* qn, hipStream_t s);
+                               const double* phi_c, double* qn, const int* halt,
+                               hipStream_t s);
 long long tree_leaves(long long n_cells);
 // Emission plan of a pass (the counts of the stratified emission): histogram
 // of the cell majorants M_i = adt pow2_ceil(max corner |q_i|) by exponent,
@@ -560,7 +568,7 @@ hipError_t launch_emission_plan(const double* qn, long long n_cells, double adt,
                                 double* ctree, DevState* st, hipStream_t s);
 size_t scan_tmp_elems(long long n);
 hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
-                              long long* tmp, hipStream_t s);
+                              long long* tmp, const int* halt, hipStream_t s);
 hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hipStream_t s);
 template <typename R>
 hipError_t launch_census_flags(const uint8_t* alive, const StageRec<R>* stage, long long n,

@@ -54,6 +54,7 @@ __global__ void k_pass_prep(DevState* st, const double* ctree, int kind, long lo
                             double cdt, unsigned long long* __restrict__ a, long long na,
                             unsigned long long* __restrict__ b, long long nb,
                             uint8_t* __restrict__ c, long long nc) {
+  if (st->halt) return;
   if (blockIdx.x == 0) {
     const int t = threadIdx.x;
     if (t < 2 * B_NFIELDS) st->bal[t] = 0ull;
@@ -104,6 +105,7 @@ __global__ __launch_bounds__(256) void k_tally_to_flux(const unsigned long long*
                                                        double* __restrict__ phi1, long long n,
                                                        int n_copies, long long copy_stride,
                                                        const DevState* st, double inv_adt) {
+  if (st->halt) return;
   // blockIdx.y picks one of two tallies decoded by the same launch
   const unsigned long long* __restrict__ T = blockIdx.y ? T1 : T0;
   double* __restrict__ phi = blockIdx.y ? phi1 : phi0;
@@ -147,7 +149,9 @@ __global__ void k_remap_source(long long n, const double* __restrict__ q,
                                const double* __restrict__ sig_s,
                                const double* __restrict__ phi_pre,
                                const double* __restrict__ phi_post,
-                               const double* __restrict__ phi_c, double* __restrict__ qn) {
+                               const double* __restrict__ phi_c, double* __restrict__ qn,
+                               const int* halt) {
+  if (*halt) return;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     const double ss = sig_s[i];
@@ -160,11 +164,12 @@ __global__ void k_remap_source(long long n, const double* __restrict__ q,
 
 hipError_t launch_remap_source(long long n, const double* q, const double* sig_s,
                                const double* phi_pre, const double* phi_post,
-                               const double* phi_c, double* qn, hipStream_t s) {
+                               const double* phi_c, double* qn, const int* halt,
+                               hipStream_t s) {
   long long b = (n + 255) / 256;
   const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
   hipLaunchKernelGGL(k_remap_source, dim3(grid), dim3(256), 0, s, n, q, sig_s, phi_pre,
-                     phi_post, phi_c, qn);
+                     phi_post, phi_c, qn, halt);
   return hipGetLastError();
 }
 
@@ -202,7 +207,9 @@ __device__ __forceinline__ int maj_bin(double p) {
 
 // Block histogram in LDS, then one global add per non-empty bin and block.
 __global__ __launch_bounds__(256) void k_maj_hist(const double* __restrict__ qn, long long n,
-                                                  unsigned long long* __restrict__ hist) {
+                                                  unsigned long long* __restrict__ hist,
+                                                  const int* halt) {
+  if (*halt) return;
   __shared__ unsigned int s_h[kMajBins];
   for (int k = threadIdx.x; k < kMajBins; k += blockDim.x) s_h[k] = 0u;
   __syncthreads();
@@ -245,6 +252,7 @@ __device__ __forceinline__ unsigned long long limbs_bits(const unsigned long lon
 // lane 0 then propagates the carries and rounds.
 __global__ __launch_bounds__(64) void k_maj_sum(unsigned long long* __restrict__ hist, double adt,
                                                 long long n_src, int kind, DevState* st) {
+  if (st->halt) return;
   __shared__ unsigned long long s_h[kMajBins];
   __shared__ unsigned long long s_limb[kSumLimbs], s_carry[kSumLimbs];
   const int lane = threadIdx.x;
@@ -334,7 +342,8 @@ constexpr int kTreeChunk = 1024;
 // Level of width W (nodes W..2W-1): block b sums nodes [W + b C, W + (b+1) C)
 // with C = min(W, 1024) up through log2(C) levels.  Leaves are integers, so
 // every sum is exact.
-__global__ __launch_bounds__(512) void k_tree_up(double* t, long long W) {
+__global__ __launch_bounds__(512) void k_tree_up(double* t, long long W, const int* halt) {
+  if (*halt) return;
   __shared__ double buf[2][kTreeChunk];
   const long long C = W < kTreeChunk ? W : kTreeChunk;
   const long long base = W + (long long)blockIdx.x * C;
@@ -358,11 +367,11 @@ __global__ __launch_bounds__(512) void k_tree_up(double* t, long long W) {
 }
 
 // All levels above the leaves, in launches of ten levels.
-static void tree_up_all(double* tree, long long L, hipStream_t s) {
+static void tree_up_all(double* tree, long long L, const int* halt, hipStream_t s) {
   long long W = L;
   while (W > 1) {
     const long long C = W < kTreeChunk ? W : kTreeChunk;
-    hipLaunchKernelGGL(k_tree_up, dim3((unsigned)(W / C)), dim3(512), 0, s, tree, W);
+    hipLaunchKernelGGL(k_tree_up, dim3((unsigned)(W / C)), dim3(512), 0, s, tree, W, halt);
     W /= C;
   }
 }
@@ -370,6 +379,7 @@ static void tree_up_all(double* tree, long long L, hipStream_t s) {
 __global__ void k_count_leaves(const double* __restrict__ qn, long long n, long long L,
                                double adt, uint64_t seed, int points, int kind,
                                const DevState* __restrict__ st, double* __restrict__ ct) {
+  if (st->halt) return;
   const double wq = st->wq[kind - 1];
   const uint64_t step = st->step;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < L;
@@ -395,13 +405,14 @@ hipError_t launch_emission_plan(const double* qn, long long n_cells, double adt,
   const long long L = tree_leaves(n_cells);
   long long b = (n_cells + 255) / 256;
   int grid = (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
-  hipLaunchKernelGGL(k_maj_hist, dim3(grid), dim3(256), 0, s, qn, n_cells, hist);
+  const int* halt = &st->halt;
+  hipLaunchKernelGGL(k_maj_hist, dim3(grid), dim3(256), 0, s, qn, n_cells, hist, halt);
   hipLaunchKernelGGL(k_maj_sum, dim3(1), dim3(64), 0, s, hist, adt, n_src, kind, st);
   b = (L + 255) / 256;
   grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
   hipLaunchKernelGGL(k_count_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, L, adt, seed,
                      points, kind, (const DevState*)st, ctree);
-  tree_up_all(ctree, L, s);  // integer-valued sums below 2^53: exact
+  tree_up_all(ctree, L, halt, s);  // integer-valued sums below 2^53: exact
   return hipGetLastError();
 }
 
@@ -415,7 +426,8 @@ constexpr int kScanBlock = kScanThreads * kScanPer;
 
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_block(const T* in, T* out, long long n,
-                                                             T* sums) {
+                                                             T* sums, const int* halt) {
+  if (*halt) return;
   __shared__ T s[kScanThreads];
   const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanPer;
   T v[kScanPer];
@@ -444,7 +456,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_block(const T* in, T* out
 }
 
 template <typename T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(T* out, long long n, const T* sums) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(T* out, long long n, const T* sums,
+                                                           const int* halt) {
+  if (*halt) return;
   const long long blk = blockIdx.x + 1;  // block 0 needs nothing
   const T add = sums[blk - 1];
   for (int k = threadIdx.x; k < kScanBlock; k += kScanThreads) {
@@ -463,23 +477,24 @@ size_t scan_tmp_elems(long long n) {
 }
 
 template <typename T>
-static hipError_t scan_rec(const T* in, T* out, long long n, T* tmp, hipStream_t s) {
+static hipError_t scan_rec(const T* in, T* out, long long n, T* tmp, const int* halt,
+                           hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const long long nb = (n + kScanBlock - 1) / kScanBlock;
   hipLaunchKernelGGL(k_scan_block<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
-                     tmp);
+                     tmp, halt);
   if (nb > 1) {
-    hipError_t e = scan_rec<T>(tmp, tmp, nb, tmp + nb + 1, s);
+    hipError_t e = scan_rec<T>(tmp, tmp, nb, tmp + nb + 1, halt, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)(nb - 1)), dim3(kScanThreads), 0, s, out,
-                       n, (const T*)tmp);
+                       n, (const T*)tmp, halt);
   }
   return hipGetLastError();
 }
 
 hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
-                              long long* tmp, hipStream_t s) {
-  return scan_rec<long long>(in, out, n, tmp, s);
+                              long long* tmp, const int* halt, hipStream_t s) {
+  return scan_rec<long long>(in, out, n, tmp, halt, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -493,7 +508,7 @@ hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
 // than cap survive the draw, the first cap in slot order are kept.
 // ---------------------------------------------------------------------------
 __global__ void k_thin_params(DevState* st, long long cap, long long margin) {
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || st->halt) return;
   const unsigned long long cnt = st->alive;
   st->thin_overflow = 0;
   if (cnt <= (unsigned long long)cap) {
@@ -526,6 +541,7 @@ __global__ void k_census_flags(const uint8_t* __restrict__ alive,
                                const StageRec<R>* __restrict__ stage, long long n,
                                uint64_t seed, const DevState* st,
                                long long* __restrict__ flags) {
+  if (st->halt) return;
   // the thinning keys' stream: (step, pass 2, population 2)
   const uint64_t thin_stream = stream_seed(seed, st->step, 2u, 2u, 0ull);
   const int act = st->thin_active;
@@ -574,6 +590,7 @@ __global__ __launch_bounds__(256) void k_census_compact(const StageRec<R>* __res
                                                         StageRec<R>* __restrict__ dst,
                                                         const DevState* st,
                                                         double* __restrict__ bmax) {
+  if (st->halt) return;
   __shared__ double s_mx[4];
   const R f = (R)st->thin_factor;
   double mx = 0.0;
@@ -617,6 +634,7 @@ template hipError_t launch_census_compact<float>(const StageRec<float>*, const l
 __global__ __launch_bounds__(256) void k_census_finish(DevState* st, const long long* incl,
                                                        long long n, long long cap,
                                                        const double* bmax, int nb) {
+  if (st->halt) return;
   __shared__ double s_mx[4];
   double mx = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) mx = fmax(mx, bmax[b]);

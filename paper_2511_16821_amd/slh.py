@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libslh.so")
 
-SLH_ABI_VERSION = 6
+SLH_ABI_VERSION = 7
 SLH_OK, SLH_E_INVALID_ARG, SLH_E_OUT_OF_MEMORY, SLH_E_DEVICE, SLH_E_NOT_CONVERGED, \
     SLH_E_NUMERIC, SLH_E_REJECTED, SLH_E_STATE = range(8)
 SLH_FP64, SLH_FP32_TRACK = 0, 1
@@ -68,7 +68,8 @@ class slh_stats(C.Structure):
                 ("graph_launches_total", C.c_uint64), ("host_waits_total", C.c_uint64),
                 ("killed_total", C.c_uint64), ("dsa_corrections", C.c_int32),
                 ("dsa_iterations", C.c_int32), ("dsa_unconverged", C.c_int32),
-                ("numeric_flags", C.c_int32), ("si_unconverged_total", C.c_uint64)]
+                ("numeric_flags", C.c_int32), ("si_unconverged_total", C.c_uint64),
+                ("si_batch", C.c_int32), ("pad0", C.c_int32), ("si_restarts_total", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +92,7 @@ ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 EXPORTS = ["slh_create", "slh_create_static", "slh_advance", "slh_set_graphs", "slh_set_timing",
+           "slh_set_si_batch",
            "slh_synchronize", "slh_get_flux", "slh_get_flux_device",
            "slh_get_balance", "slh_get_stats", "slh_get_census", "slh_save", "slh_load",
            "slh_footprint_bytes", "slh_destroy", "slh_last_error", "slh_qmc_points",
@@ -116,6 +118,7 @@ def lib():
         "slh_advance": ([vp, i32], i32),
         "slh_set_graphs": ([vp, i32], i32),
         "slh_set_timing": ([vp, i32], i32),
+        "slh_set_si_batch": ([vp, i32], i32),
         "slh_synchronize": ([vp], i32),
         "slh_get_flux": ([vp, i32, vp], i32),
         "slh_get_flux_device": ([vp, i32, vp], i32),
@@ -280,6 +283,11 @@ class Solver:
         _check(lib().slh_set_timing(self.h, 1 if enable else 0), "slh_set_timing")
 
     set_timing = slh_set_timing
+
+    def slh_set_si_batch(self, n):
+        _check(lib().slh_set_si_batch(self.h, int(n)), "slh_set_si_batch")
+
+    set_si_batch = slh_set_si_batch
 
     def slh_synchronize(self, allow_not_converged=False):
         allow = (SLH_OK, SLH_E_NOT_CONVERGED) if allow_not_converged else (SLH_OK,)

@@ -230,6 +230,26 @@ def test_dg_long_diagonals(S, oracle, per_cell):
     _run_pair(S, oracle, p, 1, check_census=False)
 
 
+@pytest.mark.parametrize("nx,ny,per_cell", [(600, 520, True), (600, 520, False),
+                                             (1030, 1024, False)])
+def test_dg_wide_chunks(S, oracle, nx, ny, per_cell):
+    """Diagonals of 512 and more cells: chunks of 512 cells with two solves
+    per lane (both sweep modes) and of 1024 cells with four (table mode),
+    each with diagonals longer than one chunk and a ragged last chunk."""
+    from paper_2511_16821_amd import workloads as W
+    if per_cell:
+        p = _per_cell_problem(nx, ny, 11, n_s=1, n_particles=3000, dt=0.05, sn_order=2)
+    else:
+        bs = (nx + 7) // 8
+        p = W.checkerboard(blocks=8, cells_per_block=bs, n_s=1, n_particles=3000, dt=0.05,
+                           sn_order=2)
+        p["nx"], p["ny"] = nx, ny
+        p["x_hi"], p["y_hi"] = nx / bs, ny / bs
+        for f in ("sigma_s", "sigma_a", "q"):
+            p[f] = np.ascontiguousarray(p[f][:ny, :nx])
+    _run_pair(S, oracle, p, 1, check_census=False)
+
+
 def test_random_blocks_subproblem(S, oracle):
     """The large random-block recipe on its 128x128 subproblem (4x4-cell
     blocks, 1024 materials: cell-mode sweep), N_s = 3; fewer particles and
@@ -341,11 +361,12 @@ def test_graph_replay_matches_eager(S):
         assert se["segments_total"] == sg["segments_total"]
     st = graph.get_stats()
     log("graph launches", st["graph_launches_total"], "host waits", st["host_waits_total"])
-    assert st["graph_launches_total"] == 7  # one graph per step
+    # one graph per step, and one per step run again after a short batch
+    assert st["graph_launches_total"] == 7 + st["si_restarts_total"]
     assert st["host_waits_total"] == 0
     assert st["ms_kernel_mc_total"] == 0.0  # no events outside timing mode
     tt = timed.get_stats()
-    assert tt["graph_launches_total"] == 3 * 7
+    assert tt["graph_launches_total"] == 3 * (7 + tt["si_restarts_total"])
     assert tt["ms_kernel_mc_total"] > 0.0 and tt["ms_kernel_remap_total"] > 0.0
     assert tt["ms_mc"] > 0.0 and tt["ms_dg"] > 0.0
     assert eager.get_stats()["graph_launches_total"] == 0
@@ -356,6 +377,58 @@ def test_graph_replay_matches_eager(S):
     assert np.array_equal(many.get_flux(0), graph.get_flux(0))
     assert many.get_stats()["steps_total"] == 7
     for s in (eager, graph, timed, many):
+        s.destroy()
+
+
+def test_short_si_batches_run_again(S):
+    """Steps whose batch of source iterations is shorter than the iteration
+    (a batch of one, then the adaptive rule) halt on the device and run again
+    at the next wait: fluxes, census bank, balances and totals are bitwise
+    those of batches of the full limit, in graph, direct and timing mode, and
+    a checkpoint taken while halted steps are pending is the same too."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=5, cells_per_block=4, n_s=2, n_particles=30000, dt=0.05,
+                       sn_order=4)
+    si_max = int(p["si_max_iter"])
+
+    def run(steps, batch, graphs=True, timing=False):
+        s = S.Solver(p)
+        s.set_graphs(graphs)
+        s.set_timing(timing)
+        s.set_si_batch(batch)
+        s.advance(steps)
+        return s
+
+    ref = run(6, si_max)
+    assert ref.synchronize() == S.SLH_OK
+    rs = ref.get_stats()
+    assert rs["si_restarts_total"] == 0 and rs["si_iterations"] > 2
+    for graphs, timing in ((True, False), (False, False), (True, True)):
+        a = run(6, 1, graphs, timing)
+        assert a.synchronize() == S.SLH_OK
+        st = a.get_stats()
+        log("graphs", graphs, "timing", timing, "restarts", st["si_restarts_total"],
+            "batch", st["si_batch"])
+        assert st["si_restarts_total"] >= 1
+        for which in (S.SLH_FLUX_REMAP, S.SLH_FLUX_PRE, S.SLH_FLUX_POST,
+                      S.SLH_FLUX_COLLIDED_NODAL):
+            assert np.array_equal(a.get_flux(which), ref.get_flux(which)), which
+        ca, cr = a.get_census(), ref.get_census()
+        for f in cr:
+            assert np.array_equal(ca[f], cr[f]), f
+        for pss in (1, 2):
+            assert a.get_balance(pss) == ref.get_balance(pss)
+        for k in ("step", "steps_total", "seg_mc_total", "seg_remap_total", "census_in_total",
+                  "census_out_total", "si_iterations", "si_unconverged_total"):
+            assert st[k] == rs[k], k
+        if timing:
+            assert st["ms_kernel_mc_total"] > 0.0
+        a.destroy()
+    # a checkpoint with halted steps still pending
+    b = run(3, 1)
+    r3 = run(3, si_max)
+    assert b.save() == r3.save()
+    for s in (ref, b, r3):
         s.destroy()
 
 

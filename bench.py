@@ -56,9 +56,18 @@ WORKLOAD_NAMES = {
     "c1": "homogeneous box"}
 
 
+# Collided-solve acceleration per workload when --si-accel is not given: the
+# 1024x1024 solve (22 plain source iterations per step) takes the diffusion
+# synthetic acceleration (12); its fixed point is the same to si_tol.
+SI_ACCEL_DEFAULT = {"c5": 1}
+
+
 def make_problem(args, precision):
     from paper_2511_16821_amd import workloads as W
     kw = dict(precision=precision)
+    acc = args.si_accel if args.si_accel is not None else SI_ACCEL_DEFAULT.get(args.workload)
+    if acc is not None:
+        kw["si_accel"] = acc
     if args.ns is not None:
         kw["n_s"] = args.ns
     if args.particles:
@@ -631,6 +640,9 @@ def main():
                     help="c5 (default: the large resident solve), c2, c3, c1, c5_sub")
     ap.add_argument("--ns", type=int, default=None, help="N_s (default: the workload's)")
     ap.add_argument("--particles", type=int, default=None)
+    ap.add_argument("--si-accel", type=int, default=None, choices=(0, 1),
+                    help="collided solve: 0 plain source iteration, 1 with the diffusion "
+                         "synthetic acceleration (default: 1 for c5, else the workload's)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-particles", type=int, default=2_000_000,
@@ -722,7 +734,9 @@ def main():
         "config": {"workload": WORKLOAD_NAMES.get(args.workload, args.workload) + ": " +
                    describe(p64), "n_steps": steps, "precision": "fp64",
                    "points": "sobol-owen", "timing": "MC-pass kernels between HIP events, "
-                   "the rest of each step as graphs; no host wait inside a step"},
+                   "the rest of each step as graphs; no host wait inside a step",
+                   "collided_solve": "DG S_N, source iteration" + (
+                       " with diffusion synthetic acceleration" if p64.get("si_accel") else "")},
         "roofline": dom, "roofline_kernels": both, "segments": int(seg),
         "si_iterations_last_step": st["si_iterations"],
     }
@@ -734,6 +748,16 @@ def main():
                                      "graph_launches": st_g["graph_launches_total"]}
         log("one graph per step: %.3e segments/s, %.2f ms/step" % (seg_g / wall_g,
                                                                   1e3 * wall_g / steps))
+        if p64.get("si_accel"):  # the same steps with the plain source iteration
+            p0 = dict(p64, si_accel=0)
+            n0 = min(steps, 10)
+            wall_0, st_0 = timed_run(S, torch, p0, n0, 0, timing=False)
+            out["plain_source_iteration"] = {
+                "value": (st_0["seg_mc_total"] + st_0["seg_remap_total"]) / wall_0,
+                "unit": "segments/s", "ms_per_step": 1e3 * wall_0 / n0, "steps": n0,
+                "si_iterations_last_step": st_0["si_iterations"]}
+            log("plain source iteration: %.2f ms/step, %d iterations" %
+                (1e3 * wall_0 / n0, st_0["si_iterations"]))
     x64 = s64.get_flux(0)
     s64.destroy()
     if not args.no_fp32:

@@ -35,13 +35,25 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-st
           "-D_GNU_SOURCE"]
 
 
-def build(force: bool = False) -> str:
-    """Compile the C oracle into oracle/liboracle.so (gcc)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-fno-omit-frame-pointer", "-g"]
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the C oracle into oracle/liboracle.so (gcc); sanitize: into
+    oracle/liboracle_san.so with AddressSanitizer and UBSan.  With
+    SLH_ORACLE_SANITIZED=1 in the environment the sanitized build is the one
+    loaded (the process must then preload the gcc sanitizer runtimes)."""
+    if os.environ.get("SLH_ORACLE_SANITIZED") == "1":
+        sanitize = True
+    out = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, *(SAN_FLAGS if sanitize else []), _SRC, "-o", tmp,
+                               "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class _Mesh(C.Structure):

@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libslh.so")
+# SLH_LIB: another build of the library (the host-sanitized one of build.py
+# --sanitize-host); by default the in-tree libslh.so
+LIB_PATH = os.environ.get("SLH_LIB") or os.path.join(_HERE, "libslh.so")
 
 SLH_ABI_VERSION = 7
 SLH_OK, SLH_E_INVALID_ARG, SLH_E_OUT_OF_MEMORY, SLH_E_DEVICE, SLH_E_NOT_CONVERGED, \

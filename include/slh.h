@@ -435,8 +435,10 @@ typedef struct slh_server slh_server;
 /* Creates a server: one device arena of hbm_budget_bytes (allocated once;
  * no device allocation happens while requests run) and max_slots worker
  * threads, each with its own HIP stream.  A worker takes the first queued
- * request (arrival order; a request that does not fit yet is passed over)
- * whose footprint fits in the arena, runs all its steps on its stream, and
+ * request (arrival order; a request that does not fit yet is passed over,
+ * but once four later requests have been admitted ahead of the one at the
+ * head of the queue, nothing else is admitted until it fits) whose
+ * footprint fits in the arena, runs all its steps on its stream, and
  * returns its memory, so requests are admitted as slots and memory free up
  * and resident requests overlap on the device.  max_slots <= 64. */
 slh_status slh_server_create(const slh_server_cfg *cfg, slh_server **out);

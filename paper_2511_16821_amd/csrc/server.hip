@@ -140,13 +140,25 @@ struct slh_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   int device = 0;
+  // requests admitted ahead of the one at the head of the queue since it
+  // became the head
+  int head_bypass = 0;
 };
 
+// How many later requests may be admitted ahead of the head of the queue
+// while it does not fit; after that the arena is held for it.
+constexpr int kMaxHeadBypass = 4;
 
-// Finds the first queued request whose block fits; called with mu held.
+
+// Finds the first queued request whose block fits, in arrival order, except
+// that once kMaxHeadBypass later requests have been admitted ahead of the
+// head of the queue only the head is (so a large request cannot starve
+// behind a stream of small ones); called with mu held.
 static Request* take_admissible(slh_server* srv) {
   for (auto it = srv->queue.begin(); it != srv->queue.end(); ++it) {
     Request* r = *it;
+    const bool head = it == srv->queue.begin();
+    if (!head && srv->head_bypass >= kMaxHeadBypass) break;
     const size_t off = srv->arena.alloc(r->footprint);
     if (off != SIZE_MAX) {
       r->block_off = off;
@@ -154,6 +166,7 @@ static Request* take_admissible(slh_server* srv) {
       r->block_base = srv->arena.base() + off;
       r->bump = 0;
       srv->queue.erase(it);
+      srv->head_bypass = head ? 0 : srv->head_bypass + 1;
       return r;
     }
   }

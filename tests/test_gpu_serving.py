@@ -96,3 +96,29 @@ def test_reject_and_invalid(S):
     flux, bal, lat = srv.result(t)
     assert flux.sum() > 0
     srv.destroy()
+
+
+def test_large_request_is_not_starved(S):
+    """A request that cannot share the arena with the one running waits at
+    the head of the queue; at most four later (small) requests are admitted
+    ahead of it, and the rest of them wait until it has been admitted."""
+    from paper_2511_16821_amd import workloads as W
+    big = W.homogeneous_box(n=128, n_particles=200_000, n_s=2)
+    small = W.checkerboard(blocks=2, cells_per_block=8, n_s=1, n_particles=3000, dt=0.1,
+                           sn_order=2)
+    fb, fs = S.slh_footprint_bytes(big), S.slh_footprint_bytes(small)
+    assert fb > 8 * fs
+    srv = S.Server(hbm_budget_bytes=2 * fb - 4096, max_slots=4)
+    first = srv.submit(big, 40)        # long: holds its block
+    waiting = srv.submit(big, 2)       # cannot fit beside the first
+    smalls = [srv.submit(small, 2) for _ in range(10)]
+    lat_first = srv.result(first)[2]
+    lat_wait = srv.result(waiting)[2]
+    lat_small = [srv.result(t)[2] for t in smalls]
+    srv.destroy()
+    ahead = sum(1 for x in lat_small if x["admit_s"] < lat_wait["admit_s"])
+    log("small requests admitted ahead of the waiting one:", ahead,
+        "its queue ms %.1f, the first one's run ms %.1f" % (lat_wait["queue_ms"],
+                                                            lat_first["run_ms"]))
+    assert ahead <= 4
+    assert lat_wait["admit_s"] >= lat_first["done_s"] - 1e-3

@@ -395,13 +395,17 @@ def history_id(step: int, cell: int, l: int) -> int:
 
 def thin(cand: Bank, cap: int, thin_stream: int):
     """Census population control (see slh_oracle.c: or_thin).  Returns the
-    kept bank, the weight factor and the overflow flag."""
+    kept bank, the weight factor and the overflow flag.  The bank at t_{n+1}
+    holds the kept candidates ordered by cell, those of one cell in slot
+    order: the census cohorts of the next step (each cell's census particles
+    take the points of that cell's census stream in this order)."""
     keep = np.zeros(cand.n, dtype=np.uint8)
     fac = C.c_double(1.0)
     ovf = C.c_int(0)
     lib().or_thin(cand.n, _p(cand.alive), _p(cand.hid), cap, thin_stream, _p(keep),
                   C.byref(fac), C.byref(ovf))
     idx = np.nonzero(keep)[0]
+    idx = idx[np.argsort(cand.cell[idx], kind="stable")]
     return cand.take(idx, fac.value), fac.value, bool(ovf.value)
 
 

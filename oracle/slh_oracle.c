@@ -336,6 +336,8 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
     int64_t segments = 0;
     const int64_t n_tot = bin->n_in + n_emit;
     int64_t cj = 0, cbase = 0;  /* cell of the current source particle, its first index */
+    /* census cohorts: the census particles of one cell, in bank order */
+    int64_t *cohort_seen = (int64_t *)calloc((size_t)(ncell > 0 ? ncell : 1), sizeof(int64_t));
 
     for (int64_t g = 0; g < n_tot; ++g) {
         double x, y, ox, oy, w, trel, tau = 0.0;
@@ -351,9 +353,12 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             ix = bin->cell[g] % nx; iy = bin->cell[g] / nx;
             hid = bin->hid[g];
             trel = 0.0;
-            /* its own stream, keyed by its identity, point index 0 */
-            stream = or_stream_seed(seed, step, (uint32_t)kind, 1u, hid);
-            pidx = 0;
+            /* the census cohort of its cell: the cell's census stream, at the
+             * particle's rank among the census particles of that cell in
+             * bank order (so a cohort draws one low-discrepancy point set,
+             * as the source particles of a cell do) */
+            stream = or_stream_seed(seed, step, (uint32_t)kind, 1u, (uint64_t)bin->cell[g]);
+            pidx = (uint32_t)cohort_seen[bin->cell[g]]++;
             dcur = 0;
             bal[OB_CENSUS_IN_W] += w;
         } else {
@@ -477,6 +482,7 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             if (fabs(w) < w_cut) { bal[OB_CUTOFF] += w; break; }
         }
     }
+    free(cohort_seen);
     return segments;
 }
 

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define SLH_ABI_VERSION 7u
+#define SLH_ABI_VERSION 8u
 
 typedef enum {
     SLH_OK = 0,
@@ -194,7 +194,26 @@ typedef struct {
                                    /* Same fixed point, fewer sweeps when      */
                                    /* scattering dominates.  Needs             */
                                    /* sigma_t + tau/(c dt) > 0 in every cell.  */
+    int32_t census_qmc;            /* points of the census histories (the     */
+                                   /* bank is ordered by cell either way):    */
+                                   /* SLH_CENSUS_HISTORY (0): a stream per    */
+                                   /* history (its id), point 0, so a         */
+                                   /* history's draws do not depend on the    */
+                                   /* others: FP32 and FP64 tracking differ   */
+                                   /* at rounding level;  SLH_CENSUS_COHORT   */
+                                   /* (1): the census particles of a cell     */
+                                   /* draw the points of the cell's census    */
+                                   /* stream at their ranks in bank order, a  */
+                                   /* low-discrepancy set per cell (QMC       */
+                                   /* convergence carried across steps; a     */
+                                   /* particle that another precision puts in */
+                                   /* another cell re-pairs its cohort's      */
+                                   /* points, so FP32 and FP64 differ at MC   */
+                                   /* noise level in those cells).            */
 } slh_problem;
+
+#define SLH_CENSUS_HISTORY 0
+#define SLH_CENSUS_COHORT 1
 
 #define SLH_ACCEL_NONE 0
 #define SLH_ACCEL_DSA 1

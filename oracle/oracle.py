@@ -62,7 +62,8 @@ class _Mesh(C.Structure):
                 ("y_lo", C.c_double), ("y_hi", C.c_double),
                 ("sig_s", C.c_void_p), ("sig_a", C.c_void_p),
                 ("c", C.c_double), ("dt", C.c_double), ("ns_cell", C.c_void_p),
-                ("bc", C.c_int), ("steady", C.c_int), ("horizon", C.c_double)]
+                ("bc", C.c_int), ("steady", C.c_int), ("horizon", C.c_double),
+                ("census_qmc", C.c_int)]
 
 
 class _Points(C.Structure):
@@ -325,7 +326,7 @@ class Mesh:
         self.s = _Mesh(self.nx, self.ny, self.x_lo, self.x_hi, self.y_lo, self.y_hi,
                        _p(self.sig_s), _p(self.sig_a), self.c, self.dt,
                        None if self.ns_cell is None else _p(self.ns_cell), self.bc,
-                       int(self.steady), self.horizon)
+                       int(self.steady), self.horizon, int(prob.get("census_qmc", 0)))
         self.ncell = self.nx * self.ny
         self.area = ((self.x_hi - self.x_lo) / self.nx) * ((self.y_hi - self.y_lo) / self.ny)
         # tallies per unit time (steady) or per step: phi = T / adt

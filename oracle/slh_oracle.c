@@ -167,6 +167,7 @@ typedef struct {
     int bc;                      /* reflective sides: bit 0 x_lo, 1 x_hi, 2 y_lo, 3 y_hi */
     int steady;                  /* 1: steady state (one infinite time step, Sec. 3) */
     double horizon;              /* steady state: path length at which a history ends */
+    int census_qmc;              /* census histories: 1 cell cohorts, 0 a stream each */
 } or_mesh;
 
 enum { OR_BC_XLO = 1, OR_BC_XHI = 2, OR_BC_YLO = 4, OR_BC_YHI = 8 };
@@ -353,12 +354,18 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             ix = bin->cell[g] % nx; iy = bin->cell[g] / nx;
             hid = bin->hid[g];
             trel = 0.0;
-            /* the census cohort of its cell: the cell's census stream, at the
-             * particle's rank among the census particles of that cell in
-             * bank order (so a cohort draws one low-discrepancy point set,
-             * as the source particles of a cell do) */
-            stream = or_stream_seed(seed, step, (uint32_t)kind, 1u, (uint64_t)bin->cell[g]);
-            pidx = (uint32_t)cohort_seen[bin->cell[g]]++;
+            if (M->census_qmc) {
+                /* the census cohort of its cell: the cell's census stream, at
+                 * the particle's rank among the census particles of that cell
+                 * in bank order (so a cohort draws one low-discrepancy point
+                 * set, as the source particles of a cell do) */
+                stream = or_stream_seed(seed, step, (uint32_t)kind, 1u, (uint64_t)bin->cell[g]);
+                pidx = (uint32_t)cohort_seen[bin->cell[g]]++;
+            } else {
+                /* its own stream, keyed by its identity, point index 0 */
+                stream = or_stream_seed(seed, step, (uint32_t)kind, 1u, hid);
+                pidx = 0;
+            }
             dcur = 0;
             bal[OB_CENSUS_IN_W] += w;
         } else {

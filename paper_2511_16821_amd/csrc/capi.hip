@@ -289,6 +289,8 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
     return fail(SLH_E_INVALID_ARG, "time_closure must be >= 0");
   if (!(p->si_tol >= 0.0) || !isfinite(p->si_tol)) return fail(SLH_E_INVALID_ARG, "si_tol < 0");
   if (p->si_max_iter < 0) return fail(SLH_E_INVALID_ARG, "si_max_iter < 0");
+  if (p->census_qmc != SLH_CENSUS_HISTORY && p->census_qmc != SLH_CENSUS_COHORT)
+    return fail(SLH_E_INVALID_ARG, "census_qmc must be 0 or 1");
   if (!(p->w_cut_rel >= 0.0) || !isfinite(p->w_cut_rel))
     return fail(SLH_E_INVALID_ARG, "w_cut_rel must be >= 0");
   if (p->points != SLH_SOBOL_OWEN && p->points != SLH_PRNG && p->points != SLH_HALTON)
@@ -373,7 +375,8 @@ static Sizes sizes_of(const slh_problem* p) {
   b += (size_t)z.cap * bank * 2;             // census banks
   b += (size_t)(z.n_src_cap > 0 ? z.n_src_cap : 1) * srec;  // source bank
   b += (size_t)z.n_cand * ((z.fp32 ? 32 : 64) + 1 + 8 + 8);  // staging, alive, flags, scan
-  b += scan_tmp_elems(z.n_cand) * 8;
+  b += std::max(scan_tmp_elems(z.n_cand), scan_tmp_elems((long long)radix_hist_elems(z.cap))) * 8;
+  b += (size_t)z.cap * 4 * 6 + radix_hist_elems(z.cap) * 16 + nc * 4;  // census ordering
   b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8 + kCensusBlocks * 8;
   b += 64 * 1024;  // alignment of the ~30 device buffers
   z.bytes = b;
@@ -529,6 +532,12 @@ struct slh_solver {
   void* src_mem = nullptr;  // source bank of the current pass
   uint8_t* alive = nullptr;
   long long *flags = nullptr, *incl = nullptr, *scan_i = nullptr;
+  // census ordering: (cell, slot) pairs and their sort buffers, the radix
+  // histograms, cohort starts per cell, and each bank's cohort ranks
+  uint32_t *skey[2] = {nullptr, nullptr}, *sval[2] = {nullptr, nullptr};
+  long long *rhist = nullptr, *rincl = nullptr;
+  uint32_t* cstart = nullptr;
+  uint32_t* crank[2] = {nullptr, nullptr};
   uint32_t* sobol = nullptr;
   DevState* st = nullptr;
   BalStore* bal_store = nullptr;  // [2]
@@ -682,7 +691,16 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->alive, uint8_t, z.n_cand);
   ALLOC(s->flags, long long, z.n_cand);
   ALLOC(s->incl, long long, z.n_cand);
-  ALLOC(s->scan_i, long long, scan_tmp_elems(z.n_cand));
+  ALLOC(s->scan_i, long long, std::max(scan_tmp_elems(z.n_cand),
+                                      scan_tmp_elems((long long)radix_hist_elems(z.cap))));
+  for (int k = 0; k < 2; ++k) {
+    ALLOC(s->skey[k], uint32_t, z.cap);
+    ALLOC(s->sval[k], uint32_t, z.cap);
+    ALLOC(s->crank[k], uint32_t, z.cap);
+  }
+  ALLOC(s->rhist, long long, radix_hist_elems(z.cap));
+  ALLOC(s->rincl, long long, radix_hist_elems(z.cap));
+  ALLOC(s->cstart, uint32_t, nc);
   ALLOC(s->sobol, uint32_t, 32 * 32);
   ALLOC(s->st, DevState, 1);
   ALLOC(s->bal_store, BalStore, 2);
@@ -843,6 +861,8 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.w_cut_rel = p.w_cut_rel;
   a.max_segments = 1u << 26;
   void* bin = s->bank_mem[s->cur];
+  a.in_rank = s->crank[s->cur];
+  a.census_qmc = p.census_qmc;
   if (s->z.fp32) {
     a.in32 = (const StageRec<float>*)bin;
     a.out32 = (StageRec<float>*)s->stage_mem;
@@ -1045,20 +1065,36 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
                          n_it > 0 ? 1 : 0);
       void* nb = s->bank_mem[1 - s->cur];
       HIP_TRY(launch_thin_params(s->st, z.cap, s->thin_margin, st));
+      // kept candidates (first cap in slot order), ordered by cell: the
+      // census cohorts of the next step
+      const long long* last = s->incl + (z.n_cand - 1);
+      const int odd = radix_passes(nc) & 1;  // the sorted pairs end in buffer odd
       if (z.fp32) {
         const StageRec<float>* src = (const StageRec<float>*)s->stage_mem;
         HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
         HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, &s->st->halt, st));
-        HIP_TRY(launch_census_compact<float>(src, s->incl, z.n_cand, z.cap, (StageRec<float>*)nb,
-                                             s->st, s->cmax, st));
+        HIP_TRY(launch_census_keys<float>(src, s->incl, z.n_cand, z.cap, s->skey[0], s->sval[0],
+                                          s->st, st));
       } else {
         const StageRec<double>* src = (const StageRec<double>*)s->stage_mem;
         HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
         HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, &s->st->halt, st));
-        HIP_TRY(launch_census_compact<double>(src, s->incl, z.n_cand, z.cap,
-                                              (StageRec<double>*)nb, s->st, s->cmax, st));
+        HIP_TRY(launch_census_keys<double>(src, s->incl, z.n_cand, z.cap, s->skey[0],
+                                           s->sval[0], s->st, st));
       }
+      HIP_TRY(radix_sort_pairs(s->skey[0], s->sval[0], s->skey[1], s->sval[1], last, z.cap, nc,
+                               s->rhist, s->rincl, s->scan_i, s->st, st));
+      if (z.fp32)
+        HIP_TRY(launch_census_gather<float>((const StageRec<float>*)s->stage_mem, s->sval[odd],
+                                            last, z.cap, (StageRec<float>*)nb, s->st, s->cmax,
+                                            st));
+      else
+        HIP_TRY(launch_census_gather<double>((const StageRec<double>*)s->stage_mem,
+                                             s->sval[odd], last, z.cap, (StageRec<double>*)nb,
+                                             s->st, s->cmax, st));
       HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, z.cap, s->cmax, st));
+      HIP_TRY(launch_cohort_ranks(s->skey[odd], &s->st->n_in, z.cap, s->cstart,
+                                  s->crank[1 - s->cur], s->st, st));
       return SLH_OK;
     }
   }
@@ -1696,6 +1732,7 @@ static bool ckpt_bank_ok(const char* in, long long cnt, long long n_cells, doubl
   if (!(maxabs >= 0.0) || !isfinite(maxabs)) return false;
   for (long long i = 0; i < cnt; ++i) {
     if (cell[i] < 0 || (long long)cell[i] >= n_cells) return false;
+    if (i > 0 && cell[i] < cell[i - 1]) return false;  // banks are ordered by cell
     const double x = px[i], y = py[i], a = ox[i], b = oy[i], v = w[i];
     // (with a relative slack of 1e-6 for the rounding of FP32 banks)
     if (!(x >= 0.0 && x <= hx * (1.0 + 1e-6) && y >= 0.0 && y <= hy * (1.0 + 1e-6))) return false;
@@ -1747,6 +1784,15 @@ extern "C" slh_status slh_load(slh_solver* s, const void* buf, size_t len) {
   hipLaunchKernelGGL(k_state_set_bank, dim3(1), dim3(1), 0, s->stream, s->st, cnt, maxabs,
                      (unsigned long long)h[2]);
   HIP_TRY(hipGetLastError());
+  // the loaded bank's cohort ranks
+  if (s->z.fp32)
+    HIP_TRY(launch_bank_cells<float>((const StageRec<float>*)s->bank_mem[s->cur], cnt,
+                                     s->skey[0], s->stream));
+  else
+    HIP_TRY(launch_bank_cells<double>((const StageRec<double>*)s->bank_mem[s->cur], cnt,
+                                      s->skey[0], s->stream));
+  HIP_TRY(launch_cohort_ranks(s->skey[0], &s->st->n_in, cnt, s->cstart, s->crank[s->cur], s->st,
+                              s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->step = (long long)h[2];
   {

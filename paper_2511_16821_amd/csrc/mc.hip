@@ -333,10 +333,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         ix = cell % a.nx; iy = cell / a.nx;
         hid = rec.hid;
         trel = (R)0;
-        // its own stream, keyed by its identity, at point index 0
-        stream = (KIND == 1 && n_lim > 0) ? stream_seed(a.seed, step, (uint32_t)KIND, 1u, hid)
-                                          : 0ull;
-        pidx = 0;
+        // census_qmc: its cell's census cohort, the cell's census stream at
+        // the particle's rank in the cohort (the bank is ordered by cell);
+        // else its own stream, keyed by its identity, at point index 0
+        if (KIND == 1 && n_lim > 0) {
+          stream = stream_seed(a.seed, step, (uint32_t)KIND, 1u,
+                               a.census_qmc ? (uint64_t)cell : hid);
+          pidx = a.census_qmc ? a.in_rank[g] : 0u;
+        } else {
+          stream = 0ull;
+          pidx = 0u;
+        }
         dcur = 0;
       } else {
         // source particle, emitted by k_emit

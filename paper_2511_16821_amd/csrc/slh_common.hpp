@@ -372,6 +372,8 @@ struct PassArgs {
   // source index), and the source particles, in the precision of the pass
   const StageRec<double>* in64;
   const StageRec<float>* in32;
+  const uint32_t* in_rank;  // rank of each census particle in its cell's cohort
+  int census_qmc;           // census histories: 1 cell cohorts, 0 a stream per history
   StageRec<double>* out64;
   StageRec<float>* out32;
   SrcRec<double>* src64;
@@ -574,14 +576,38 @@ template <typename R>
 hipError_t launch_census_flags(const uint8_t* alive, const StageRec<R>* stage, long long n,
                                uint64_t seed, const DevState* st, long long* flags,
                                hipStream_t s);
+// The census bank at t_{n+1} (kept candidates, first cap in slot order,
+// ordered by cell and within a cell by slot): (cell, slot) pairs of the kept
+// candidates in slot order, then radix_sort_pairs by cell, then the gather of
+// the records (weights times the thinning factor); incl: the inclusive scan
+// of the kept flags, whose last entry bounds the count with cap.
 template <typename R>
-hipError_t launch_census_compact(const StageRec<R>* src, const long long* incl, long long n,
-                                 long long cap, StageRec<R>* dst, DevState* st, double* bmax,
-                                 hipStream_t s);
-// bmax: kCensusBlocks doubles, the compaction's per-block max |w|
+hipError_t launch_census_keys(const StageRec<R>* src, const long long* incl, long long n,
+                              long long cap, uint32_t* keys, uint32_t* vals, const DevState* st,
+                              hipStream_t s);
+long long radix_tiles(long long n);
+int radix_passes(long long n_keys_max);
+size_t radix_hist_elems(long long cap);
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                            const long long* incl_last, long long cap, long long key_bound,
+                            long long* hist, long long* hincl, long long* scan_tmp,
+                            const DevState* st, hipStream_t s);
+template <typename R>
+hipError_t launch_census_gather(const StageRec<R>* src, const uint32_t* vals,
+                                const long long* incl_last, long long cap, StageRec<R>* dst,
+                                const DevState* st, double* bmax, hipStream_t s);
+// bmax: kCensusBlocks doubles, the gather's per-block max |w|
 hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,
                                 long long cap, const double* bmax, hipStream_t s);
-constexpr int kCensusBlocks = 2048;  // blocks of the compaction grid at most
+constexpr int kCensusBlocks = 2048;  // blocks of the gather grid at most
 int census_compact_blocks(long long n);
+// Ranks of the census particles in their cells' cohorts, for a bank ordered
+// by cell (cells[k], k < *count); start: one entry per cell.
+hipError_t launch_cohort_ranks(const uint32_t* cells, const long long* count, long long n_max,
+                               uint32_t* start, uint32_t* rank, const DevState* st,
+                               hipStream_t s);
+template <typename R>
+hipError_t launch_bank_cells(const StageRec<R>* bank, long long n, uint32_t* cells,
+                             hipStream_t s);
 
 }  // namespace slh

@@ -577,33 +577,196 @@ template hipError_t launch_census_flags<float>(const uint8_t*, const StageRec<fl
                                                hipStream_t);
 
 
-// Blocks of the compaction grid; each leaves the max |w| it wrote in bmax.
+// ---------------------------------------------------------------------------
+// The census bank at t_{n+1}: the kept candidates (first cap in slot order)
+// ordered by cell, a cell's candidates in slot order, so that the census
+// particles of a cell form a contiguous cohort.  k_census_keys writes the
+// kept candidates' (cell, slot) pairs in slot order; a stable LSD radix sort
+// orders them by cell; k_census_gather copies the records (weights scaled by
+// the thinning factor); k_cohort_ranks gives every particle its rank in its
+// cell's cohort.  The count min(kept, cap) is read on the device.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long census_count(const long long* incl_last, long long cap) {
+  const long long k = *incl_last;
+  return k < cap ? k : cap;
+}
+
+template <typename R>
+__global__ void k_census_keys(const StageRec<R>* __restrict__ src,
+                              const long long* __restrict__ incl, long long n, long long cap,
+                              uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                              const DevState* st) {
+  if (st->halt) return;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long before = i > 0 ? incl[i - 1] : 0;
+    if (incl[i] == before || before >= cap) continue;  // not kept, or past the cap
+    keys[before] = (uint32_t)src[i].cell;
+    vals[before] = (uint32_t)i;
+  }
+}
+
+template <typename R>
+hipError_t launch_census_keys(const StageRec<R>* src, const long long* incl, long long n,
+                              long long cap, uint32_t* keys, uint32_t* vals, const DevState* st,
+                              hipStream_t s) {
+  long long b = (n + 255) / 256;
+  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+  hipLaunchKernelGGL(k_census_keys<R>, dim3(grid), dim3(256), 0, s, src, incl, n, cap, keys, vals,
+                     st);
+  return hipGetLastError();
+}
+template hipError_t launch_census_keys<double>(const StageRec<double>*, const long long*,
+                                               long long, long long, uint32_t*, uint32_t*,
+                                               const DevState*, hipStream_t);
+template hipError_t launch_census_keys<float>(const StageRec<float>*, const long long*, long long,
+                                              long long, uint32_t*, uint32_t*, const DevState*,
+                                              hipStream_t);
+
+// Stable LSD radix sort of (key, value) pairs by 8-bit digits.  A tile of
+// kSortTile pairs per block, read in rounds of 256 (pair base + r 256 + t in
+// round r, thread t): the order of the pairs is their index order.
+//   upsweep:   the tile's digit histogram -> hist[digit][tile]
+//   scan:      inclusive scan of hist (digit-major): the pairs of digit d of
+//              tile b start at incl[d][b] - hist[d][b]
+//   downsweep: every pair's rank among the tile's earlier pairs of its digit
+//              (rounds in order; in a round, the waves in order and the
+//              lanes of a wave in order, lanes of one digit matched by
+//              ballots), then the scatter to start + rank.
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = 256 * kSortRounds;
+
+long long radix_tiles(long long n) { return (n + kSortTile - 1) / kSortTile; }
+
+__global__ __launch_bounds__(256) void k_radix_up(const uint32_t* __restrict__ keys,
+                                                  const long long* incl_last, long long cap,
+                                                  int shift, long long n_tiles,
+                                                  long long* __restrict__ hist,
+                                                  const DevState* st) {
+  if (st->halt) return;
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const long long count = census_count(incl_last, cap);
+  const long long base = (long long)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const long long i = base + r * 256 + threadIdx.x;
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(long long)threadIdx.x * n_tiles + blockIdx.x] = (long long)h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_radix_down(const uint32_t* __restrict__ kin,
+                                                    const uint32_t* __restrict__ vin,
+                                                    uint32_t* __restrict__ kout,
+                                                    uint32_t* __restrict__ vout,
+                                                    const long long* incl_last, long long cap,
+                                                    int shift, long long n_tiles,
+                                                    const long long* __restrict__ hist,
+                                                    const long long* __restrict__ hincl,
+                                                    const DevState* st) {
+  if (st->halt) return;
+  __shared__ long long s_start[256];  // first output index of each digit of this tile
+  __shared__ uint32_t s_run[256];     // pairs of each digit in the earlier rounds
+  __shared__ uint32_t s_wave[4][256]; // pairs of each digit in each wave of the round
+  const int t = threadIdx.x, w = t >> 6;
+  const long long hb = (long long)t * n_tiles + blockIdx.x;
+  // thread t owns digit t's entries of s_start, s_run and s_wave
+  s_start[t] = hincl[hb] - hist[hb];
+  s_run[t] = 0u;
+  for (int v = 0; v < 4; ++v) s_wave[v][t] = 0u;
+  __syncthreads();
+  const long long count = census_count(incl_last, cap);
+  const long long base = (long long)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const long long i = base + r * 256 + t;
+    const bool ok = i < count;
+    const uint32_t key = ok ? kin[i] : 0u;
+    const uint32_t val = ok ? vin[i] : 0u;
+    const int d = (int)((key >> shift) & 255u);
+    // lanes of this wave with the same digit (among the valid ones)
+    unsigned long long peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long m = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? m : ~m;
+    }
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+    if (ok && below == 0u) s_wave[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (ok) {
+      uint32_t before = s_run[d];
+      for (int v = 0; v < w; ++v) before += s_wave[v][d];
+      const long long o = s_start[d] + before + below;
+      kout[o] = key;
+      vout[o] = val;
+    }
+    __syncthreads();
+    s_run[t] += s_wave[0][t] + s_wave[1][t] + s_wave[2][t] + s_wave[3][t];
+    for (int v = 0; v < 4; ++v) s_wave[v][t] = 0u;
+    __syncthreads();
+  }
+}
+
+int radix_passes(long long n_keys_max) {
+  int bits = 1;
+  while (bits < 32 && (1ll << bits) < n_keys_max) ++bits;
+  return (bits + 7) / 8;
+}
+
+size_t radix_hist_elems(long long cap) { return (size_t)256 * (size_t)radix_tiles(cap); }
+
+// Sorts the first min(*incl_last, cap) pairs of (k0, v0) by key (keys below
+// key_bound); the result is in (k0, v0) after an even number of passes, in
+// (k1, v1) after an odd number (radix_passes(key_bound)).
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                            const long long* incl_last, long long cap, long long key_bound,
+                            long long* hist, long long* hincl, long long* scan_tmp,
+                            const DevState* st, hipStream_t s) {
+  const long long tiles = radix_tiles(cap > 0 ? cap : 1);
+  const int passes = radix_passes(key_bound);
+  for (int p = 0; p < passes; ++p) {
+    uint32_t* ki = (p & 1) ? k1 : k0;
+    uint32_t* vi = (p & 1) ? v1 : v0;
+    uint32_t* ko = (p & 1) ? k0 : k1;
+    uint32_t* vo = (p & 1) ? v0 : v1;
+    hipLaunchKernelGGL(k_radix_up, dim3((unsigned)tiles), dim3(256), 0, s, (const uint32_t*)ki,
+                       incl_last, cap, 8 * p, tiles, hist, st);
+    hipError_t e = scan_inclusive_i64(hist, hincl, 256 * tiles, scan_tmp, &st->halt, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_down, dim3((unsigned)tiles), dim3(256), 0, s, (const uint32_t*)ki,
+                       (const uint32_t*)vi, ko, vo, incl_last, cap, 8 * p, tiles,
+                       (const long long*)hist, (const long long*)hincl, st);
+  }
+  return hipGetLastError();
+}
+
+// Blocks of the gather grid; each leaves the max |w| it wrote in bmax.
 int census_compact_blocks(long long n) {
   const long long b = (n + 255) / 256;
   return (int)(b < kCensusBlocks ? (b < 1 ? 1 : b) : kCensusBlocks);
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_census_compact(const StageRec<R>* __restrict__ src,
-                                                        const long long* __restrict__ incl,
-                                                        long long n, long long cap,
-                                                        StageRec<R>* __restrict__ dst,
-                                                        const DevState* st,
-                                                        double* __restrict__ bmax) {
+__global__ __launch_bounds__(256) void k_census_gather(const StageRec<R>* __restrict__ src,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const long long* incl_last, long long cap,
+                                                       StageRec<R>* __restrict__ dst,
+                                                       const DevState* st,
+                                                       double* __restrict__ bmax) {
   if (st->halt) return;
   __shared__ double s_mx[4];
   const R f = (R)st->thin_factor;
+  const long long count = census_count(incl_last, cap);
   double mx = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long before = i > 0 ? incl[i - 1] : 0;
-    if (incl[i] == before) continue;
-    const long long d = before;
-    if (d >= cap) continue;  // overflow of the draw: keep the first cap
-    StageRec<R> rec = src[i];
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (long long)gridDim.x * blockDim.x) {
+    StageRec<R> rec = src[vals[k]];
     const R w = rec.w * f;
     rec.w = w;
-    dst[d] = rec;
+    dst[k] = rec;
     mx = fmax(mx, fabs((double)w));
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
@@ -615,19 +778,74 @@ __global__ __launch_bounds__(256) void k_census_compact(const StageRec<R>* __res
 }
 
 template <typename R>
-hipError_t launch_census_compact(const StageRec<R>* src, const long long* incl, long long n,
-                                 long long cap, StageRec<R>* dst, DevState* st, double* bmax,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_census_compact<R>, dim3(census_compact_blocks(n)), dim3(256), 0, s, src,
-                     incl, n, cap, dst, (const DevState*)st, bmax);
+hipError_t launch_census_gather(const StageRec<R>* src, const uint32_t* vals,
+                                const long long* incl_last, long long cap, StageRec<R>* dst,
+                                const DevState* st, double* bmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_census_gather<R>, dim3(census_compact_blocks(cap)), dim3(256), 0, s, src,
+                     vals, incl_last, cap, dst, st, bmax);
   return hipGetLastError();
 }
-template hipError_t launch_census_compact<double>(const StageRec<double>*, const long long*,
-                                                  long long, long long, StageRec<double>*,
-                                                  DevState*, double*, hipStream_t);
-template hipError_t launch_census_compact<float>(const StageRec<float>*, const long long*,
-                                                 long long, long long, StageRec<float>*, DevState*,
-                                                 double*, hipStream_t);
+template hipError_t launch_census_gather<double>(const StageRec<double>*, const uint32_t*,
+                                                 const long long*, long long, StageRec<double>*,
+                                                 const DevState*, double*, hipStream_t);
+template hipError_t launch_census_gather<float>(const StageRec<float>*, const uint32_t*,
+                                                const long long*, long long, StageRec<float>*,
+                                                const DevState*, double*, hipStream_t);
+
+// Cohort ranks of a bank ordered by cell (cells[k] of its n = *count
+// particles): start[c] = the first k of cell c, rank[k] = k - start[cells[k]].
+__global__ void k_cohort_starts(const uint32_t* __restrict__ cells, const long long* count,
+                                uint32_t* __restrict__ start, const DevState* st) {
+  if (st->halt) return;
+  const long long n = *count;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    if (k == 0 || cells[k] != cells[k - 1]) start[cells[k]] = (uint32_t)k;
+}
+
+__global__ void k_cohort_ranks(const uint32_t* __restrict__ cells, const long long* count,
+                               const uint32_t* __restrict__ start, uint32_t* __restrict__ rank,
+                               const DevState* st) {
+  if (st->halt) return;
+  const long long n = *count;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    rank[k] = (uint32_t)(k - (long long)start[cells[k]]);
+}
+
+hipError_t launch_cohort_ranks(const uint32_t* cells, const long long* count, long long n_max,
+                               uint32_t* start, uint32_t* rank, const DevState* st,
+                               hipStream_t s) {
+  long long b = (n_max + 255) / 256;
+  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+  hipLaunchKernelGGL(k_cohort_starts, dim3(grid), dim3(256), 0, s, cells, count, start, st);
+  hipLaunchKernelGGL(k_cohort_ranks, dim3(grid), dim3(256), 0, s, cells, count,
+                     (const uint32_t*)start, rank, st);
+  return hipGetLastError();
+}
+
+// The cells of a bank's records (for the ranks of a loaded checkpoint).
+template <typename R>
+__global__ void k_bank_cells(const StageRec<R>* __restrict__ bank, long long n,
+                             uint32_t* __restrict__ cells) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    cells[k] = (uint32_t)bank[k].cell;
+}
+
+template <typename R>
+hipError_t launch_bank_cells(const StageRec<R>* bank, long long n, uint32_t* cells,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long b = (n + 255) / 256;
+  const int grid = (int)(b < 4096 ? b : 4096);
+  hipLaunchKernelGGL(k_bank_cells<R>, dim3(grid), dim3(256), 0, s, bank, n, cells);
+  return hipGetLastError();
+}
+template hipError_t launch_bank_cells<double>(const StageRec<double>*, long long, uint32_t*,
+                                              hipStream_t);
+template hipError_t launch_bank_cells<float>(const StageRec<float>*, long long, uint32_t*,
+                                             hipStream_t);
 
 // Census count and max |w| of the new bank (max over the compaction blocks),
 // and the end of the time step.
@@ -653,7 +871,7 @@ __global__ __launch_bounds__(256) void k_census_finish(DevState* st, const long 
 hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,
                                 long long cap, const double* bmax, hipStream_t s) {
   hipLaunchKernelGGL(k_census_finish, dim3(1), dim3(256), 0, s, st, incl, n, cap, bmax,
-                     census_compact_blocks(n));
+                     census_compact_blocks(cap));
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # --sanitize-host); by default the in-tree libslh.so
 LIB_PATH = os.environ.get("SLH_LIB") or os.path.join(_HERE, "libslh.so")
 
-SLH_ABI_VERSION = 7
+SLH_ABI_VERSION = 8
 SLH_OK, SLH_E_INVALID_ARG, SLH_E_OUT_OF_MEMORY, SLH_E_DEVICE, SLH_E_NOT_CONVERGED, \
     SLH_E_NUMERIC, SLH_E_REJECTED, SLH_E_STATE = range(8)
 SLH_FP64, SLH_FP32_TRACK = 0, 1
@@ -43,7 +43,8 @@ class slh_problem(C.Structure):
                 ("si_max_iter", C.c_int32), ("w_cut_rel", C.c_double), ("seed", C.c_uint64),
                 ("points", C.c_int32), ("precision", C.c_int32), ("n_s_cell", C.c_void_p),
                 ("boundary", C.c_int32), ("steady", C.c_int32), ("horizon", C.c_double),
-                ("si_norm", C.c_int32), ("closure", C.c_int32), ("si_accel", C.c_int32)]
+                ("si_norm", C.c_int32), ("closure", C.c_int32), ("si_accel", C.c_int32),
+                ("census_qmc", C.c_int32)]
 
 
 class slh_balance(C.Structure):
@@ -198,6 +199,7 @@ def make_problem(p: dict):
     s.si_norm = int(p.get("si_norm", 0))
     s.closure = int(p.get("closure", 0))
     s.si_accel = int(p.get("si_accel", 0))
+    s.census_qmc = int(p.get("census_qmc", 0))
     keep = [ss, sa, q]
     if p.get("n_s_cell") is not None:
         nsc = np.ascontiguousarray(p["n_s_cell"], dtype=np.int32).reshape(-1)

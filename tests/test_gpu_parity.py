@@ -250,6 +250,18 @@ def test_dg_wide_chunks(S, oracle, nx, ny, per_cell):
     _run_pair(S, oracle, p, 1, check_census=False)
 
 
+@pytest.mark.parametrize("points", [0, 2])
+def test_census_cohorts(S, oracle, points):
+    """Census histories drawing from their cells' cohort streams
+    (census_qmc = 1) over several steps, with scatters of census particles
+    (N_s = 2), against the oracle: fluxes, balances and the census bank
+    (ordered by cell) every step, for Owen-scrambled Sobol' and Halton points."""
+    from paper_2511_16821_amd import workloads as W
+    p = W.checkerboard(blocks=3, cells_per_block=6, n_s=2, n_particles=20000, dt=0.05,
+                       sn_order=4, census_qmc=1, points=points)
+    _run_pair(S, oracle, p, 4)
+
+
 def test_random_blocks_subproblem(S, oracle):
     """The large random-block recipe on its 128x128 subproblem (4x4-cell
     blocks, 1024 materials: cell-mode sweep), N_s = 3; fewer particles and
@@ -442,7 +454,7 @@ def test_full_size_properties(S, which):
     first step the pre/post fluxes of these non-negative sources are
     non-negative (the remap, and through its census the later steps, carry
     signed weights where the bilinear collided flux dips below zero); two
-    runs give bitwise-identical fluxes and census banks; FP32 tracking stays
+    runs give bitwise-identical fluxes and census banks, ordered by cell; FP32 tracking stays
     within 1e-4 (relative L2) of FP64."""
     from paper_2511_16821_amd import workloads as W
     p = W.c3(n_s=2) if which == "c3" else W.c5()
@@ -470,6 +482,8 @@ def test_full_size_properties(S, which):
             assert np.all(np.isfinite(a))
         assert f[0].sum() > 0.0
         c = s.get_census()
+        # the bank is ordered by cell (the census cohorts of the next step)
+        assert np.all(np.diff(c["cell"]) >= 0)
         runs.append((f, c))
         s.destroy()
         log("  precision", prec, "phi_R sum %.6e" % f[0].sum(), "census", len(c["w"]))

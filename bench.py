@@ -382,8 +382,10 @@ def protocol(S, torch, args):
     reference at 2^22 particles, for scrambled-Sobol' points (RMS over Owen
     seeds), pseudo-random points (RMS over seeds) and the paper's Halton points
     (RMS over random shifts), at particle counts 2^10
-    .. 2^18; the fitted slopes alpha (error ~ N^-alpha), the source-iteration
-    count of the collided solve, and the time per step."""
+    .. 2^18; the same for scrambled Sobol' with the census histories drawing
+    from their cells' cohort streams (census_qmc = 1, against its own
+    reference); the fitted slopes alpha (error ~ N^-alpha), the
+    source-iteration count of the collided solve, and the time per step."""
     import numpy as np
     from paper_2511_16821_amd import workloads as W
     ns_list = [int(v) for v in args.protocol_ns.split(",") if v != ""]
@@ -392,9 +394,9 @@ def protocol(S, torch, args):
     for ns in ns_list:
         base = W.c1(n_s=ns, n_steps=args.protocol_steps, dt=args.protocol_dt)
 
-        def run(n, points, seed):
+        def run(n, points, seed, census=0):
             p = dict(base)
-            p.update(n_particles=int(n), points=points, seed=int(seed))
+            p.update(n_particles=int(n), points=points, seed=int(seed), census_qmc=census)
             s = S.Solver(p, torch_allocator=False)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -405,15 +407,17 @@ def protocol(S, torch, args):
             s.destroy()
             return f, t / args.protocol_steps, it
 
-        ref, _, _ = run(2 ** 22, 0, 7777)
-        nref = max(np.linalg.norm(ref), 1e-300)
+        refs = {c: run(2 ** 22, 0, 7777, c)[0] for c in (0, 1)}
         row = {"n_s": ns, "particles": ladder, "steps": args.protocol_steps}
-        for name, mode in (("qmc", 0), ("mc", 1), ("halton", 2)):
+        for name, mode, census in (("qmc", 0, 0), ("qmc_census_cohorts", 0, 1), ("mc", 1, 0),
+                                   ("halton", 2, 0)):
+            ref = refs[census]
+            nref = max(np.linalg.norm(ref), 1e-300)
             errs, times, iters = [], [], []
             for n in ladder:
                 e2 = 0.0
                 for r in range(args.protocol_seeds):
-                    f, t, it = run(n, mode, 1000 + 17 * r)
+                    f, t, it = run(n, mode, 1000 + 17 * r, census)
                     e2 += float(np.linalg.norm(f - ref) / nref) ** 2
                     times.append(t)
                     iters.append(it)

@@ -132,7 +132,7 @@ def measured_traffic(profile, kernel, prec):
     calibration), or None when the summary is missing or was taken on other
     kernel code."""
     path = os.path.join(ROOT, "profiles", profile)
-    if not os.path.exists(path):
+    if not profile or not os.path.isfile(path):
         return None
     kv = {}
     for line in open(path):

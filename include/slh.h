@@ -344,8 +344,8 @@ slh_status slh_create_static(const slh_problem *problem, void *hip_stream, slh_s
  * replayed): the scatter-limited leg, the collided solve as a batch of
  * source iterations of which those after the device's stopping test return
  * at once, the remap leg and the census.  Nothing in a step waits for the
- * host.  The batch adapts to the iteration counts of past steps (a quarter
- * more than the last one, plus two, in multiples of eight; at most
+ * host.  The batch adapts to the iteration counts of past steps (an eighth
+ * more than the last one, plus two, in multiples of four; at most
  * si_max_iter); a step whose batch ends before its iteration stops itself
  * and every step enqueued after it on the device, and the next call that
  * waits for the stream (slh_synchronize, slh_get_*, slh_save, slh_load) runs

@@ -1262,10 +1262,10 @@ static void scratch_release(int dev) {
   if (dev >= 0 && dev < kMaxDevices) g_scratch_busy[dev] = false;
 }
 
-// A batch of source iterations: n rounded up to a multiple of eight, at most
+// A batch of source iterations: n rounded up to a multiple of four, at most
 // the limit (fewer distinct batches, fewer captured graphs).
 static int round_batch(long long n, int si_max) {
-  n = (n + 7) / 8 * 8;
+  n = (n + 3) / 4 * 4;
   return (int)std::max<long long>(1, std::min<long long>(n, si_max));
 }
 
@@ -1398,8 +1398,8 @@ extern "C" slh_status slh_advance(slh_solver* s, int32_t n_steps) {
 // once, so the device holds the state at the start of the halted step: it is
 // run with the full limit si_max (its batch cannot end early), the ones after
 // it with a doubled batch, and the check repeats until no step halted.  The
-// batch then follows the last step's iteration count (a quarter more, plus
-// two, in multiples of eight).
+// batch then follows the last step's iteration count (an eighth more, plus
+// two, in multiples of four).
 static slh_status settle(slh_solver* s, DevState* out = nullptr) {
   DevState d;
   for (;;) {
@@ -1419,7 +1419,7 @@ static slh_status settle(slh_solver* s, DevState* out = nullptr) {
     if (r != SLH_OK) return r;
   }
   if (s->unsettled && !s->skip_remap && d.si.iter > 0)
-    s->si_batch = round_batch(d.si.iter + d.si.iter / 4 + 2, s->si_max);
+    s->si_batch = round_batch(d.si.iter + d.si.iter / 8 + 2, s->si_max);
   s->unsettled = false;
   if (out) *out = d;
   return SLH_OK;

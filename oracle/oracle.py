@@ -63,7 +63,7 @@ class _Mesh(C.Structure):
                 ("sig_s", C.c_void_p), ("sig_a", C.c_void_p),
                 ("c", C.c_double), ("dt", C.c_double), ("ns_cell", C.c_void_p),
                 ("bc", C.c_int), ("steady", C.c_int), ("horizon", C.c_double),
-                ("census_qmc", C.c_int)]
+                ("census_qmc", C.c_int), ("inflow", C.c_void_p)]
 
 
 class _Points(C.Structure):
@@ -116,6 +116,9 @@ def lib():
                                    C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
         L.or_pow2_ceil.restype = C.c_double
         L.or_pow2_ceil.argtypes = [C.c_double]
+        L.or_face_majorants.restype = None
+        L.or_face_majorants.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double,
+                                        C.c_double, C.c_void_p]
         L.or_cell_majorants.restype = None
         L.or_cell_majorants.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p]
         L.or_halton_u32.restype = C.c_uint32
@@ -323,14 +326,31 @@ class Mesh:
         ns = prob.get("n_s_cell")
         self.ns_cell = None if ns is None else np.ascontiguousarray(ns, dtype=np.int32).ravel()
         self.bc = int(prob.get("boundary", 0))  # reflective sides: 1 x_lo, 2 x_hi, 4 y_lo, 8 y_hi
+        # prescribed isotropic inflow G on the boundary faces (Sec. 2.1):
+        # 2 ny + 2 nx values, x_lo faces, x_hi faces, y_lo faces, y_hi faces
+        g = prob.get("inflow")
+        self.inflow = None if g is None else np.ascontiguousarray(g, dtype=np.float64).ravel()
+        if self.inflow is not None:
+            ny_, nx_ = self.ny, self.nx
+            if self.inflow.size != 2 * (nx_ + ny_):
+                raise ValueError("inflow needs 2 (nx + ny) values")
+            sides = (self.inflow[:ny_], self.inflow[ny_:2 * ny_], self.inflow[2 * ny_:2 * ny_ + nx_],
+                     self.inflow[2 * ny_ + nx_:])
+            for bit, v in zip((1, 2, 4, 8), sides):
+                if (self.bc & bit) and np.any(v != 0.0):
+                    raise ValueError("inflow on a reflective side")
         self.s = _Mesh(self.nx, self.ny, self.x_lo, self.x_hi, self.y_lo, self.y_hi,
                        _p(self.sig_s), _p(self.sig_a), self.c, self.dt,
                        None if self.ns_cell is None else _p(self.ns_cell), self.bc,
-                       int(self.steady), self.horizon, int(prob.get("census_qmc", 0)))
+                       int(self.steady), self.horizon, int(prob.get("census_qmc", 0)),
+                       None if self.inflow is None else _p(self.inflow))
         self.ncell = self.nx * self.ny
         self.area = ((self.x_hi - self.x_lo) / self.nx) * ((self.y_hi - self.y_lo) / self.ny)
         # tallies per unit time (steady) or per step: phi = T / adt
         self.adt = self.area if self.steady else self.area * self.dt
+        self.hx = (self.x_hi - self.x_lo) / self.nx
+        self.hy = (self.y_hi - self.y_lo) / self.ny
+        self.tdt = 1.0 if self.steady else self.dt
 
 
 def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
@@ -340,7 +360,7 @@ def mc_pass(mesh: Mesh, pts: Points, kind: int, n_s: int, q_nodal, n_src: int,
     T are raw track-length sums."""
     q_nodal = np.ascontiguousarray(q_nodal, dtype=np.float64).reshape(-1)
     assert q_nodal.size == 4 * mesh.ncell
-    plan = emission_plan(q_nodal, mesh.adt, n_src, pts, seed, step, kind)
+    plan = emission_plan(q_nodal, mesh.adt, n_src, pts, seed, step, kind, mesh)
     counts = np.ascontiguousarray(plan["counts"], dtype=np.int64)
     if counts.size == 0:
         counts = np.zeros(1, dtype=np.int64)
@@ -374,13 +394,28 @@ def cell_majorants(q_nodal, adt):
     return M[:n]
 
 
-def emission_plan(q_nodal, adt, n_src, pts: Points, seed: int, step: int, kind: int):
+def face_majorants(mesh: "Mesh"):
+    """M_f of the boundary faces with an inflow (see slh_oracle.c:
+    or_face_majorants), or an empty array."""
+    if mesh.inflow is None:
+        return np.zeros(0)
+    M = np.zeros(mesh.inflow.size)
+    lib().or_face_majorants(_p(mesh.inflow), mesh.nx, mesh.ny, mesh.hx, mesh.hy, mesh.tdt,
+                            _p(M))
+    return M
+
+
+def emission_plan(q_nodal, adt, n_src, pts: Points, seed: int, step: int, kind: int,
+                  mesh: "Mesh" = None):
     """The source particles of one pass (Sec. 2.3, birth in proportion to the
-    source): the cell majorants M_i, their correctly rounded sum (math.fsum),
-    the weight quantum w_q = quantum(sum / n_src) and the per-cell counts
-    floor(M_i / w_q) + [u_i < frac(M_i / w_q)] (see slh_oracle.c:
-    or_emission_counts)."""
+    source; with an inflow also the particles entering through the boundary,
+    Sec. 2.1): the emitters' majorants M_i (the cells, then the boundary
+    faces), their correctly rounded sum (math.fsum), the weight quantum
+    w_q = quantum(sum / n_src) and the counts floor(M_i / w_q) +
+    [u_i < frac(M_i / w_q)] (see slh_oracle.c: or_emission_counts)."""
     M = cell_majorants(q_nodal, adt)
+    if mesh is not None and mesh.inflow is not None:
+        M = np.concatenate([M, face_majorants(mesh)])
     total = math.fsum(M.tolist())
     counts = np.zeros(max(M.size, 1), dtype=np.int64)
     wq = C.c_double(0.0)

@@ -168,7 +168,40 @@ typedef struct {
     int steady;                  /* 1: steady state (one infinite time step, Sec. 3) */
     double horizon;              /* steady state: path length at which a history ends */
     int census_qmc;              /* census histories: 1 cell cohorts, 0 a stream each */
+    /* prescribed isotropic inflow G on the boundary faces (Sec. 2.1), or
+     * NULL: 2 ny + 2 nx values, the x_lo faces (j = 0..ny-1), the x_hi
+     * faces, the y_lo faces (i = 0..nx-1), the y_hi faces */
+    const double *inflow;
 } or_mesh;
+
+/* Boundary faces as emitters: face f of the inflow array, its side (0 x_lo,
+ * 1 x_hi, 2 y_lo, 3 y_hi) and its index along the side. */
+static int or_face_side(int f, int nx, int ny, int *k)
+{
+    if (f < ny) { *k = f; return 0; }
+    if (f < 2 * ny) { *k = f - ny; return 1; }
+    if (f < 2 * ny + nx) { *k = f - 2 * ny; return 2; }
+    *k = f - 2 * ny - nx;
+    return 3;
+}
+
+double or_pow2_ceil(double v);
+
+/* Majorants of the boundary faces: the particles entering through face f
+ * in a step carry the partial current of an isotropic inflow, the integral
+ * over the inward half-sphere of (Omega . n) G = pi G per unit length and
+ * time, so M_f = (pi L_f) tdt pow2_ceil(|G_f|), with L_f the face length
+ * and tdt the step (1 in steady state, per unit time). */
+void or_face_majorants(const double *inflow, int nx, int ny, double hx, double hy, double tdt,
+                       double *M)
+{
+    const double cx = (M_PI * hy) * tdt, cy = (M_PI * hx) * tdt;
+    for (int f = 0; f < 2 * (nx + ny); ++f) {
+        int k;
+        const int side = or_face_side(f, nx, ny, &k);
+        M[f] = (side < 2 ? cx : cy) * or_pow2_ceil(fabs(inflow[f]));
+    }
+}
 
 enum { OR_BC_XLO = 1, OR_BC_XHI = 2, OR_BC_YLO = 4, OR_BC_YHI = 8 };
 
@@ -330,8 +363,10 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
     for (int64_t i = 0; i < ncell; ++i) { T_a[i] = 0.0; T_b[i] = 0.0; }
     for (int k = 0; k < OB_N; ++k) bal[k] = 0.0;
 
+    /* emitters: the cells, then (with an inflow) the boundary faces */
+    const int64_t n_emitters = ncell + (M->inflow ? 2 * (int64_t)(nx + ny) : 0);
     int64_t n_emit = 0;
-    for (int64_t i = 0; i < ncell; ++i) n_emit += counts[i];
+    for (int64_t i = 0; i < n_emitters; ++i) n_emit += counts[i];
     const double w_cut = w_cut_rel * wq;
 
     int64_t segments = 0;
@@ -382,21 +417,51 @@ int64_t or_mc_pass(const or_mesh *M, const or_points *P, int kind, int n_s,
             stream = or_stream_seed(seed, step, (uint32_t)kind, 0u, (uint64_t)ci);
             pidx = l;
             hid = or_history_id(step, ci, l);
-            ix = (int)(ci % nx); iy = (int)(ci / nx);
             const double u1 = or_u01(or_point_u32(P, stream, 0, pidx));
             const double u2 = or_u01(or_point_u32(P, stream, 1, pidx));
             const double u3 = or_u01(or_point_u32(P, stream, 2, pidx));
             const double u4 = or_u01(or_point_u32(P, stream, 3, pidx));
             const double u5 = or_u01(or_point_u32(P, stream, 4, pidx));
-            x = M->x_lo + hx * ((double)ix + u1);
-            y = M->y_lo + hy * ((double)iy + u2);
-            trel = u3 * dt_birth;
-            const double st = 2.0 * sqrt(u4 * (1.0 - u4)); /* sin(theta), Oz = 1 - 2 u4 */
-            const double ph = 2.0 * M_PI * u5;
-            ox = st * cos(ph);
-            oy = st * sin(ph);
-            const double *qc = q_nodal + 4 * ci;
-            w = or_bilinear(qc, u1, u2) * (wq / or_pow2_ceil(or_maxabs4(qc)));
+            if (ci < ncell) {
+                ix = (int)(ci % nx); iy = (int)(ci / nx);
+                x = M->x_lo + hx * ((double)ix + u1);
+                y = M->y_lo + hy * ((double)iy + u2);
+                trel = u3 * dt_birth;
+                const double st = 2.0 * sqrt(u4 * (1.0 - u4)); /* sin(theta), Oz = 1 - 2 u4 */
+                const double ph = 2.0 * M_PI * u5;
+                ox = st * cos(ph);
+                oy = st * sin(ph);
+                const double *qc = q_nodal + 4 * ci;
+                w = or_bilinear(qc, u1, u2) * (wq / or_pow2_ceil(or_maxabs4(qc)));
+            } else {
+                /* entering through boundary face f (Sec. 2.1 inflow G):
+                 * uniform along the face (dim 0) and in time (dim 1), the
+                 * cosine law about the inward normal, mu = sqrt(u) (dim 2),
+                 * and the in-plane tangential component sqrt(1 - mu^2)
+                 * cos(2 pi u) (dim 3); weight w_q G_f / pow2_ceil(|G_f|) */
+                int k;
+                const int f = (int)(ci - ncell);
+                const int side = or_face_side(f, nx, ny, &k);
+                const double mu = sqrt(u3);
+                const double tg = sqrt(1.0 - u3) * cos(2.0 * M_PI * u4);
+                if (side < 2) {
+                    ix = side == 0 ? 0 : nx - 1; iy = k;
+                    x = M->x_lo + hx * (double)(side == 0 ? 0 : nx);
+                    y = M->y_lo + hy * ((double)iy + u1);
+                    ox = side == 0 ? mu : -mu;
+                    oy = tg;
+                } else {
+                    ix = k; iy = side == 2 ? 0 : ny - 1;
+                    x = M->x_lo + hx * ((double)ix + u1);
+                    y = M->y_lo + hy * (double)(side == 2 ? 0 : ny);
+                    oy = side == 2 ? mu : -mu;
+                    ox = tg;
+                }
+                trel = u2 * dt_birth;
+                const double G = M->inflow[f];
+                w = G * (wq / or_pow2_ceil(fabs(G)));
+                (void)u5;
+            }
             dcur = 5;
             bal[OB_SOURCE_W] += w;
         }

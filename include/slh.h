@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define SLH_ABI_VERSION 8u
+#define SLH_ABI_VERSION 9u
 
 typedef enum {
     SLH_OK = 0,
@@ -210,6 +210,20 @@ typedef struct {
                                    /* another cell re-pairs its cohort's      */
                                    /* points, so FP32 and FP64 differ at MC   */
                                    /* noise level in those cells).            */
+    const double *inflow;          /* host, 2 (nx + ny) values, or NULL: the  */
+                                   /* prescribed isotropic inflow G of the    */
+                                   /* boundary faces (Sec. 2.1), per unit     */
+                                   /* solid angle, area and time: the x_lo    */
+                                   /* faces (j = 0..ny-1), the x_hi faces,    */
+                                   /* the y_lo faces (i = 0..nx-1), the y_hi  */
+                                   /* faces; 0 on reflective sides.  Applied  */
+                                   /* in both MC legs (steps 1 and 3; the     */
+                                   /* collided solve has zero boundary data): */
+                                   /* face f is an emitter after the cells,   */
+                                   /* majorant (pi L_f) dt pow2_ceil(|G_f|)   */
+                                   /* (pi G the partial current), particles   */
+                                   /* uniform along the face and in time,     */
+                                   /* cosine law about the inward normal.     */
 } slh_problem;
 
 #define SLH_CENSUS_HISTORY 0

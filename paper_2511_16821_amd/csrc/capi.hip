@@ -124,6 +124,7 @@ static std::vector<double> product_quadrature(int order) {
 // ---------------------------------------------------------------------------
 struct Sizes {
   long long n_cells, n_p, cap, n_cand;
+  long long n_faces;    // boundary faces emitting an inflow (0 without one)
   long long n_src_cap;  // source bank: at most n_p (1 + 1/16) + n_cells particles per pass
   int n_dir;
   int n_copies;  // private tally copies
@@ -273,6 +274,17 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
     return fail(SLH_E_INVALID_ARG, "n_s must be -1 (unlimited) or in [0, 1e6]");
   if (p->boundary < 0 || p->boundary > 15)
     return fail(SLH_E_INVALID_ARG, "boundary must be a mask of SLH_REFLECT_* (0..15)");
+  if (check_fields && p->inflow) {
+    const int nx = p->nx, ny = p->ny;
+    for (int f = 0; f < 2 * (nx + ny); ++f) {
+      int k;
+      const int side = face_side(f, nx, ny, &k);
+      const double g = p->inflow[f];
+      if (!isfinite(g)) return fail(SLH_E_INVALID_ARG, "inflow values must be finite");
+      if (g != 0.0 && (p->boundary & (1 << side)))
+        return fail(SLH_E_INVALID_ARG, "inflow on a reflective side");
+    }
+  }
   if (check_fields && p->n_s_cell) {
     const long long n = (long long)p->nx * p->ny;
     for (long long i = 0; i < n; ++i)
@@ -281,8 +293,15 @@ static slh_status validate(const slh_problem* p, bool check_fields) {
   }
   if (p->n_particles < 0 || p->n_particles > (1ll << 31))  // a cell's index l stays 32-bit
     return fail(SLH_E_INVALID_ARG, "n_particles must be in [0, 2^31]");
-  if (p->census_cap < 0 || p->census_cap > (1ll << 34))
+  if (p->census_cap < 0 || p->census_cap > (1ll << 31))
     return fail(SLH_E_INVALID_ARG, "census_cap out of range");
+  {  // census slots are 32-bit: cap + source bank below 2^32
+    const long long cap = p->census_cap > 0 ? p->census_cap : std::max<long long>(p->n_particles, 1);
+    const long long src = p->n_particles + p->n_particles / 16 + (long long)p->nx * p->ny +
+                          (p->inflow ? 2ll * (p->nx + p->ny) : 0) + 16;
+    if (cap + src >= (1ll << 32))
+      return fail(SLH_E_INVALID_ARG, "census cap plus source particles must stay below 2^32");
+  }
   if (p->sn_order < 2 || p->sn_order % 2 || p->sn_order > 64)
     return fail(SLH_E_INVALID_ARG, "sn_order must be even in [2, 64]");
   if (!(p->time_closure >= 0.0) || !isfinite(p->time_closure))
@@ -326,7 +345,8 @@ static Sizes sizes_of(const slh_problem* p) {
   z.n_p = p->n_particles;
   // the stratified emission gives sum_i ceil(M_i / w_q) particles, w_q being
   // sum(M) / n_p rounded down to five significant bits (within 1/16)
-  z.n_src_cap = z.n_p > 0 ? z.n_p + z.n_p / 16 + z.n_cells + 16 : 0;
+  z.n_faces = p->inflow ? 2ll * (p->nx + p->ny) : 0;
+  z.n_src_cap = z.n_p > 0 ? z.n_p + z.n_p / 16 + z.n_cells + z.n_faces + 16 : 0;
   z.cap = p->census_cap > 0 ? p->census_cap : std::max<long long>(p->n_particles, 1);
   z.n_cand = z.cap + z.n_src_cap;
   z.n_dir = p->sn_order * p->sn_order;
@@ -359,8 +379,9 @@ static Sizes sizes_of(const slh_problem* p) {
   if (p->n_s_cell) b += nc * 4;              // per-cell scatter limits
   if (p->boundary)                           // mirror indices, reflected traces
     b += (size_t)z.n_dir * 8 + (size_t)2 * z.n_dir * 2 * (p->nx + p->ny) * 8;
-  b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells) * 16 * 2;  // nodal sources, count trees
-  b += (size_t)kMajBins * 8;                 // majorant histogram
+  b += nc * 32 * 2 + (size_t)tree_leaves(z.n_cells + z.n_faces) * 16 * 2;  // sources, count trees
+  b += (size_t)kMajGroups * kMajBins * 8;    // majorant histograms
+  b += (size_t)z.n_faces * 8;                // inflow of the boundary faces
   b += nc * 8 * kTallyStride * 3 * (size_t)z.n_copies;  // tallies
   b += nc * 8 * 3 + nc * 32 * 3;             // phi_pre/post/R, phi_c, DG source x2
   b += (size_t)z.n_dir * 4;                  // directions of each sweep layout
@@ -508,7 +529,9 @@ struct slh_solver {
   double *sig_s = nullptr, *sig_e = nullptr, *q = nullptr;
   double *qn1 = nullptr, *ctree1 = nullptr;  // nodal source and count tree of each pass
   double *qnR = nullptr, *ctreeR = nullptr;
-  unsigned long long* maj_hist = nullptr;     // histogram of the emission plan
+  unsigned long long* maj_hist = nullptr;     // histograms of the emission plan
+  double* inflow = nullptr;                   // inflow of the boundary faces, or none
+  std::vector<double> h_inflow;
   long long tree_L = 1;
   unsigned long long *Tpre = nullptr, *Tpost = nullptr, *TR = nullptr;
   double *phi_pre = nullptr, *phi_post = nullptr, *phi_R = nullptr, *phi_c = nullptr;
@@ -636,12 +659,13 @@ static slh_status setup(slh_solver* s) {
   ALLOC(s->sig_e, double, 2 * nc);  // sweep layouts A and B
   ALLOC(s->q, double, nc);
   if (!s->h_ns.empty()) ALLOC(s->ns_cell, int, nc);
-  s->tree_L = tree_leaves(nc);
+  s->tree_L = tree_leaves(nc + z.n_faces);
   ALLOC(s->qn1, double, 4 * nc);
   ALLOC(s->ctree1, double, 2 * s->tree_L);
   ALLOC(s->qnR, double, 4 * nc);
   ALLOC(s->ctreeR, double, 2 * s->tree_L);
-  ALLOC(s->maj_hist, unsigned long long, kMajBins);
+  ALLOC(s->maj_hist, unsigned long long, kMajGroups * kMajBins);
+  if (z.n_faces) ALLOC(s->inflow, double, z.n_faces);
   ALLOC(s->Tpre, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
   ALLOC(s->Tpost, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
   ALLOC(s->TR, unsigned long long, (size_t)z.n_copies * kTallyStride * nc);
@@ -809,7 +833,10 @@ static slh_status setup(slh_solver* s) {
     HIP_TRY(launch_diff_coef(p.nx, p.ny, s->mat64, time_term(&p), s->hx, s->hy,
                              z.dsa ? 0 : p.boundary, s->cg_diag, s->cg_e, s->cg_n, st));
   HIP_TRY(hipMemcpyAsync(s->sobol, sobol_table_host(), 4 * 32 * 32, hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_fill_u64(s->maj_hist, kMajBins, 0ull, st));  // left zero by every plan
+  HIP_TRY(launch_fill_u64(s->maj_hist, kMajGroups * kMajBins, 0ull, st));  // left zero by every plan
+  if (z.n_faces)
+    HIP_TRY(hipMemcpyAsync(s->inflow, s->h_inflow.data(), 8 * z.n_faces, hipMemcpyHostToDevice,
+                           st));
   HIP_TRY(launch_fill_f64(s->ctree1, 2 * s->tree_L, 0.0, st));
   HIP_TRY(launch_fill_f64(s->ctreeR, 2 * s->tree_L, 0.0, st));
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, st, s->st);
@@ -821,6 +848,21 @@ static slh_status setup(slh_solver* s) {
   HIP_TRY(launch_fill_u8(s->alive, z.n_cand, 0, st));
   HIP_TRY(hipStreamSynchronize(st));  // host vectors above go out of scope
   return SLH_OK;
+}
+
+// The boundary faces of the inflow as emitters after the cells: face f's
+// majorant is (pi L_f) tdt pow2_ceil(|G_f|), the partial current pi G of an
+// isotropic inflow over the face and the step (tdt = 1 in steady state).
+static Emitters emitters(const slh_solver* s) {
+  Emitters e;
+  e.inflow = s->inflow;
+  e.nx = s->prob.nx;
+  e.ny = s->prob.ny;
+  e.n_faces = s->z.n_faces;
+  const double tdt = s->prob.steady ? 1.0 : s->prob.dt;
+  e.cx = (M_PI * s->hy) * tdt;
+  e.cy = (M_PI * s->hx) * tdt;
+  return e;
 }
 
 static PassArgs pass_args(slh_solver* s, int kind) {
@@ -862,6 +904,7 @@ static PassArgs pass_args(slh_solver* s, int kind) {
   a.max_segments = 1u << 26;
   void* bin = s->bank_mem[s->cur];
   a.in_rank = s->crank[s->cur];
+  a.em = emitters(s);
   a.census_qmc = p.census_qmc;
   if (s->z.fp32) {
     a.in32 = (const StageRec<float>*)bin;
@@ -1013,7 +1056,8 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
   const int n_it = s->skip_remap ? 0 : s->batch_run;
   switch (part) {
     case kA: {
-      HIP_TRY(launch_emission_plan(s->qn1, nc, s->adt, z.n_p, p.seed, p.points, 1, s->maj_hist,
+      HIP_TRY(launch_emission_plan(s->qn1, nc, emitters(s), s->adt, z.n_p, p.seed, p.points, 1,
+                                   s->maj_hist,
                                    s->ctree1, s->st, st));
       HIP_TRY(launch_pass_prep(s->st, s->ctree1, 1, z.n_src_cap, cdt, s->Tpre, n_tally, s->Tpost,
                                n_tally, nullptr, 0, st));
@@ -1047,7 +1091,8 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
       if (use_cg(s)) HIP_TRY(launch_cg_to_nodal(cg_args(s), s->phi_c, &s->st->halt, st));
       HIP_TRY(launch_remap_source(nc, s->q, s->sig_s, s->phi_pre, s->phi_post, s->phi_c,
                                   s->qnR, &s->st->halt, st));
-      HIP_TRY(launch_emission_plan(s->qnR, nc, s->adt, z.n_p, p.seed, p.points, 2, s->maj_hist,
+      HIP_TRY(launch_emission_plan(s->qnR, nc, emitters(s), s->adt, z.n_p, p.seed, p.points, 2,
+                                   s->maj_hist,
                                    s->ctreeR, s->st, st));
       HIP_TRY(launch_pass_prep(s->st, s->ctreeR, 2, z.n_src_cap, cdt, s->TR, n_tally, nullptr, 0,
                                s->alive, z.n_cand, st));
@@ -1327,6 +1372,8 @@ static slh_status create_solver(const slh_problem* problem, void* hip_stream, sl
   s->skip_remap = problem->steady && all_unlimited;
   s->prob.sigma_s = s->prob.sigma_a = s->prob.q = nullptr;
   s->prob.n_s_cell = nullptr;
+  if (problem->inflow) s->h_inflow.assign(problem->inflow, problem->inflow + s->z.n_faces);
+  s->prob.inflow = nullptr;
   s->hx = (problem->x_hi - problem->x_lo) / problem->nx;
   s->hy = (problem->y_hi - problem->y_lo) / problem->ny;
   s->area = s->hx * s->hy;

@@ -227,25 +227,54 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n_emit;
        s += (long long)gridDim.x * blockDim.x) {
     const CellPick pk = count_pick(a.ctree, s_top, a.tree_L, s);
-    const long long ci = pk.cell;
+    const long long ci = pk.cell;  // the emitter: a cell, or a boundary face after them
     const uint32_t l = pk.l;
     const uint64_t stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, (uint64_t)ci);
     const R u1 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 0u, l));
     const R u2 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 1u, l));
     const R u3 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 2u, l));
     const R u4 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 3u, l));
-    const R u5 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 4u, l));
-    const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
-    R sp, cp;
-    Real<R>::scpi((R)2 * u5, &sp, &cp);
-    const double* q = a.qn + 4 * ci;
-    const double wscale = wq / pow2_ceil(maxabs4(q));  // exact: a power-of-two ratio
-    const R w = (R)(bilinear(q, (double)u1, (double)u2) * wscale);
     const R tau = a.n_lim > 0
                       ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, l)))
                       : (R)0;
-    Real<R>::put_src(b + s, hx * u1, hy * u2, sn * cp, sn * sp, w, u3 * dt_birth, tau,
-                     (int)ci, l);
+    if (ci < a.n_cells) {
+      const R u5 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 4u, l));
+      const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
+      R sp, cp;
+      Real<R>::scpi((R)2 * u5, &sp, &cp);
+      const double* q = a.qn + 4 * ci;
+      const double wscale = wq / pow2_ceil(maxabs4(q));  // exact: a power-of-two ratio
+      const R w = (R)(bilinear(q, (double)u1, (double)u2) * wscale);
+      Real<R>::put_src(b + s, hx * u1, hy * u2, sn * cp, sn * sp, w, u3 * dt_birth, tau,
+                       (int)ci, l);
+    } else {
+      // entering through boundary face f (the inflow G): uniform along the
+      // face (dim 0) and in time (dim 1), the cosine law about the inward
+      // normal, mu = sqrt(u) (dim 2), the in-plane tangential component
+      // sqrt(1 - mu^2) cos(2 pi u) (dim 3); weight w_q G_f / pow2_ceil(|G_f|)
+      int k;
+      const int f = (int)(ci - a.n_cells);
+      const int side = face_side(f, a.nx, a.ny, &k);
+      const R mu = sqrt(u3);
+      R sp, cp;
+      Real<R>::scpi((R)2 * u4, &sp, &cp);
+      const R tg = sqrt((R)1 - u3) * cp;
+      const double G = a.em.inflow[f];
+      const R w = (R)(G * (wq / pow2_ceil(fabs(G))));
+      R px, py, ox, oy;
+      if (side < 2) {
+        px = side == 0 ? (R)0 : hx;
+        py = hy * u1;
+        ox = side == 0 ? mu : -mu;
+        oy = tg;
+      } else {
+        px = hx * u1;
+        py = side == 2 ? (R)0 : hy;
+        oy = side == 2 ? mu : -mu;
+        ox = tg;
+      }
+      Real<R>::put_src(b + s, px, py, ox, oy, w, u2 * dt_birth, tau, (int)ci, l);
+    }
   }
 }
 
@@ -352,10 +381,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         px = sr.px; py = sr.py; ox = sr.ox; oy = sr.oy; w = sr.w;
         trel = sr.trel;
         tau = sr.tau;
-        const int cell = sr.cell;
+        const int cell = sr.cell;  // the emitter: a cell, or a boundary face after them
         pidx = sr.lidx;
-        ix = cell % a.nx; iy = cell / a.nx;
-        // the birth cell's stream at the particle's index in the cell
+        if (cell < a.n_cells) {
+          ix = cell % a.nx; iy = cell / a.nx;
+        } else {  // the cell inside boundary face f
+          int k;
+          const int side = face_side(cell - (int)a.n_cells, a.nx, a.ny, &k);
+          ix = side < 2 ? (side == 0 ? 0 : a.nx - 1) : k;
+          iy = side < 2 ? k : (side == 2 ? 0 : a.ny - 1);
+        }
+        // the emitter's stream at the particle's index in it
         stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, (uint64_t)cell);
         hid = history_id(step, cell, pidx);
         dcur = 6;  // dims 0-4 emission, 5 the first optical depth

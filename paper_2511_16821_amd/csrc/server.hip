@@ -102,6 +102,7 @@ struct Request {
   slh_problem prob;
   std::vector<double> ss, sa, q;
   std::vector<int32_t> ns;  // per-cell scatter limits, if given
+  std::vector<double> inflow;  // boundary inflow, if given
   int n_steps = 0;
   size_t footprint = 0;
   ReqState state = Q_QUEUED;
@@ -289,6 +290,10 @@ extern "C" slh_status slh_server_submit(slh_server* srv, const slh_problem* p, i
   if (p->n_s_cell) {
     r->ns.assign(p->n_s_cell, p->n_s_cell + n);
     r->prob.n_s_cell = r->ns.data();
+  }
+  if (p->inflow) {
+    r->inflow.assign(p->inflow, p->inflow + 2 * ((size_t)p->nx + p->ny));
+    r->prob.inflow = r->inflow.data();
   }
   r->n_steps = n_steps;
   r->footprint = fp;

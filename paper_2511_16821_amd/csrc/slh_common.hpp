@@ -333,6 +333,28 @@ struct DevState {
   int pad3;
 };
 
+// Emitters of a pass beyond the cells: the boundary faces of a prescribed
+// inflow G (n_faces = 2 (nx + ny) values, or none): the x_lo faces (index
+// j), the x_hi faces, the y_lo faces (index i), the y_hi faces.  Face f's
+// majorant is (side < 2 ? cx : cy) pow2_ceil(|G_f|), cx = (pi hy) tdt,
+// cy = (pi hx) tdt with tdt the step (1 in steady state).
+struct Emitters {
+  const double* inflow;
+  int nx, ny;
+  long long n_faces;
+  double cx, cy;
+};
+
+// Side of boundary face f (0 x_lo, 1 x_hi, 2 y_lo, 3 y_hi) and its index
+// along the side.
+__host__ __device__ __forceinline__ int face_side(int f, int nx, int ny, int* k) {
+  if (f < ny) { *k = f; return 0; }
+  if (f < 2 * ny) { *k = f - ny; return 1; }
+  if (f < 2 * ny + nx) { *k = f - 2 * ny; return 2; }
+  *k = f - 2 * ny - nx;
+  return 3;
+}
+
 struct PassArgs {
   int nx, ny;
   // a history ends (census) at time dt after the start of the step, the
@@ -352,8 +374,9 @@ struct PassArgs {
   // floor(r_i) + 1 particles, r_i = M_i / w_q, w_q = quantum5(sum(M) / n_src)
   // (st->wq[kind - 1], with the exact sum st->sumM[kind - 1])
   const double* ctree;   // binary sum tree of the counts n_i (heap order; root: particles)
-  long long tree_L;      // leaves start at tree_L (power of two >= n_cells)
+  long long tree_L;      // leaves start at tree_L (power of two >= the emitters)
   const double* qn;      // nodal source [cell][4]
+  Emitters em;           // boundary faces of an inflow, emitters after the cells
   long long n_cells;
   long long n_src;       // N_p, the requested particles per pass
   long long src_cap;     // capacity of the source bank (the plan is clamped to it)
@@ -565,9 +588,12 @@ long long tree_leaves(long long n_cells);
 // hist: kMajBins words, zero on entry and left zero (the last bin counts
 // cells whose majorant is not finite).
 constexpr int kMajBins = 2112;
-hipError_t launch_emission_plan(const double* qn, long long n_cells, double adt, long long n_src,
-                                uint64_t seed, int points, int kind, unsigned long long* hist,
-                                double* ctree, DevState* st, hipStream_t s);
+hipError_t launch_emission_plan(const double* qn, long long n_cells, const Emitters& em,
+                                double adt, long long n_src, uint64_t seed, int points, int kind,
+                                unsigned long long* hist, double* ctree, DevState* st,
+                                hipStream_t s);
+// hist: kMajHistWords words (cells, x faces, y faces)
+constexpr int kMajGroups = 3;
 size_t scan_tmp_elems(long long n);
 hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
                               long long* tmp, const int* halt, hipStream_t s);

@@ -223,6 +223,19 @@ __global__ __launch_bounds__(256) void k_maj_hist(const double* __restrict__ qn,
     if (s_h[k]) atomicAdd(&hist[k], (unsigned long long)s_h[k]);
 }
 
+// The faces of an inflow: one global add per face to the x-face (group 1)
+// or y-face (group 2) histogram.
+__global__ void k_face_hist(Emitters em, unsigned long long* __restrict__ hist, const int* halt) {
+  if (*halt) return;
+  for (long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x; f < em.n_faces;
+       f += (long long)gridDim.x * blockDim.x) {
+    int k;
+    const int side = face_side((int)f, em.nx, em.ny, &k);
+    const double p = pow2_ceil(fabs(em.inflow[f]));
+    if (p > 0.0) atomicAdd(&hist[(side < 2 ? 1 : 2) * kMajBins + maj_bin(p)], 1ull);
+  }
+}
+
 constexpr int kSumLimbs = 36;  // 2304 bits above 2^-1074
 
 // Bits [r, r + 64) of the 128-bit value (hi, lo), zero outside it.
@@ -251,17 +264,19 @@ __device__ __forceinline__ unsigned long long limbs_bits(const unsigned long lon
 // its bits that fall in the limb, and the limb counts its own overflows;
 // lane 0 then propagates the carries and rounds.
 __global__ __launch_bounds__(64) void k_maj_sum(unsigned long long* __restrict__ hist, double adt,
-                                                long long n_src, int kind, DevState* st) {
+                                                double cx, double cy, long long n_src, int kind,
+                                                DevState* st) {
   if (st->halt) return;
-  __shared__ unsigned long long s_h[kMajBins];
+  __shared__ unsigned long long s_h[kMajGroups * kMajBins];
   __shared__ unsigned long long s_limb[kSumLimbs], s_carry[kSumLimbs];
   const int lane = threadIdx.x;
-  for (int k = lane; k < kMajBins; k += 64) {
+  for (int k = lane; k < kMajGroups * kMajBins; k += 64) {
     s_h[k] = hist[k];
     hist[k] = 0ull;
   }
   __syncthreads();
-  if (s_h[kMajBad]) {  // a majorant overflowed: no emission (flagged by the pass set-up)
+  if (s_h[kMajBad] || s_h[kMajBins + kMajBad] || s_h[2 * kMajBins + kMajBad]) {
+    // a majorant overflowed: no emission (flagged by the pass set-up)
     if (lane == 0) {
       st->sumM[kind - 1] = __builtin_huge_val();
       st->wq[kind - 1] = 0.0;
@@ -270,10 +285,14 @@ __global__ __launch_bounds__(64) void k_maj_sum(unsigned long long* __restrict__
   }
   unsigned long long acc = 0ull, carry = 0ull;
   bool overflow = false;
-  for (int b = 0; b < kMajBad; ++b) {
-    const unsigned long long c = s_h[b];  // the same in every lane
+  // every emitter group (cells, x faces, y faces): the value of each of its
+  // majorants in bin b is its constant times 2^(b - 1074)
+  for (int gb = 0; gb < kMajGroups * kMajBins && !overflow; ++gb) {
+    const int g = gb / kMajBins, b = gb - g * kMajBins;
+    if (b == kMajBad) continue;
+    const unsigned long long c = s_h[gb];  // the same in every lane
     if (!c) continue;
-    const double V = adt * ldexp(1.0, b - 1074);  // the value of every M_i in bin b
+    const double V = (g == 0 ? adt : g == 1 ? cx : cy) * ldexp(1.0, b - 1074);
     if (!(V > 0.0)) continue;
     if (!isfinite(V)) {
       overflow = true;
@@ -376,8 +395,8 @@ static void tree_up_all(double* tree, long long L, const int* halt, hipStream_t 
   }
 }
 
-__global__ void k_count_leaves(const double* __restrict__ qn, long long n, long long L,
-                               double adt, uint64_t seed, int points, int kind,
+__global__ void k_count_leaves(const double* __restrict__ qn, long long n, Emitters em,
+                               long long L, double adt, uint64_t seed, int points, int kind,
                                const DevState* __restrict__ st, double* __restrict__ ct) {
   if (st->halt) return;
   const double wq = st->wq[kind - 1];
@@ -385,8 +404,15 @@ __global__ void k_count_leaves(const double* __restrict__ qn, long long n, long 
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < L;
        i += (long long)gridDim.x * blockDim.x) {
     double c = 0.0;
-    if (i < n && wq > 0.0) {
-      const double Mi = adt * cell_majorant_pow2(reinterpret_cast<const double4*>(qn)[i]);
+    if (i < n + em.n_faces && wq > 0.0) {
+      double Mi;
+      if (i < n) {
+        Mi = adt * cell_majorant_pow2(reinterpret_cast<const double4*>(qn)[i]);
+      } else {
+        int k;
+        const int side = face_side((int)(i - n), em.nx, em.ny, &k);
+        Mi = (side < 2 ? em.cx : em.cy) * pow2_ceil(fabs(em.inflow[i - n]));
+      }
       if (Mi > 0.0 && isfinite(Mi)) {
         const double r = Mi / wq;
         const double fl = floor(r);
@@ -399,18 +425,22 @@ __global__ void k_count_leaves(const double* __restrict__ qn, long long n, long 
   }
 }
 
-hipError_t launch_emission_plan(const double* qn, long long n_cells, double adt, long long n_src,
-                                uint64_t seed, int points, int kind, unsigned long long* hist,
-                                double* ctree, DevState* st, hipStream_t s) {
-  const long long L = tree_leaves(n_cells);
+hipError_t launch_emission_plan(const double* qn, long long n_cells, const Emitters& em,
+                                double adt, long long n_src, uint64_t seed, int points, int kind,
+                                unsigned long long* hist, double* ctree, DevState* st,
+                                hipStream_t s) {
+  const long long L = tree_leaves(n_cells + em.n_faces);
   long long b = (n_cells + 255) / 256;
   int grid = (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
   const int* halt = &st->halt;
   hipLaunchKernelGGL(k_maj_hist, dim3(grid), dim3(256), 0, s, qn, n_cells, hist, halt);
-  hipLaunchKernelGGL(k_maj_sum, dim3(1), dim3(64), 0, s, hist, adt, n_src, kind, st);
+  if (em.n_faces > 0)
+    hipLaunchKernelGGL(k_face_hist, dim3((unsigned)((em.n_faces + 255) / 256)), dim3(256), 0, s,
+                       em, hist, halt);
+  hipLaunchKernelGGL(k_maj_sum, dim3(1), dim3(64), 0, s, hist, adt, em.cx, em.cy, n_src, kind, st);
   b = (L + 255) / 256;
   grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_count_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, L, adt, seed,
+  hipLaunchKernelGGL(k_count_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, em, L, adt, seed,
                      points, kind, (const DevState*)st, ctree);
   tree_up_all(ctree, L, halt, s);  // integer-valued sums below 2^53: exact
   return hipGetLastError();

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # --sanitize-host); by default the in-tree libslh.so
 LIB_PATH = os.environ.get("SLH_LIB") or os.path.join(_HERE, "libslh.so")
 
-SLH_ABI_VERSION = 8
+SLH_ABI_VERSION = 9
 SLH_OK, SLH_E_INVALID_ARG, SLH_E_OUT_OF_MEMORY, SLH_E_DEVICE, SLH_E_NOT_CONVERGED, \
     SLH_E_NUMERIC, SLH_E_REJECTED, SLH_E_STATE = range(8)
 SLH_FP64, SLH_FP32_TRACK = 0, 1
@@ -44,7 +44,7 @@ class slh_problem(C.Structure):
                 ("points", C.c_int32), ("precision", C.c_int32), ("n_s_cell", C.c_void_p),
                 ("boundary", C.c_int32), ("steady", C.c_int32), ("horizon", C.c_double),
                 ("si_norm", C.c_int32), ("closure", C.c_int32), ("si_accel", C.c_int32),
-                ("census_qmc", C.c_int32)]
+                ("census_qmc", C.c_int32), ("inflow", C.c_void_p)]
 
 
 class slh_balance(C.Structure):
@@ -207,6 +207,12 @@ def make_problem(p: dict):
             raise ValueError("n_s_cell must have nx*ny entries")
         s.n_s_cell = nsc.ctypes.data
         keep.append(nsc)
+    if p.get("inflow") is not None:
+        g = np.ascontiguousarray(p["inflow"], dtype=np.float64).reshape(-1)
+        if g.size != 2 * (nx + ny):
+            raise ValueError("inflow must have 2 (nx + ny) entries")
+        s.inflow = g.ctypes.data
+        keep.append(g)
     return s, keep
 
 

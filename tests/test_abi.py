@@ -50,6 +50,12 @@ def test_validation_rejects_before_allocating(S):
         dict(steady=True, w_cut_rel=0.0),  # the default horizon needs a cutoff
         dict(steady=True, sigma_a=np.where(np.arange(400) == 7, 0.0, 0.1)),
         dict(closure=2), dict(closure=-1), dict(si_accel=2), dict(si_accel=-1),
+        dict(census_qmc=2), dict(census_qmc=-1),
+        # an inflow on a reflective side, a non-finite inflow
+        dict(boundary=1, inflow=np.where(np.arange(80) < 20, 1.0, 0.0)),
+        dict(inflow=np.where(np.arange(80) == 50, np.nan, 0.0)),
+        # census slots are 32-bit
+        dict(census_cap=2 ** 31, n_particles=2 ** 31),
         # the diffusion correction needs sigma_t > 0 in steady state (a void)
         dict(si_accel=1, steady=True, horizon=50.0, sigma_a=np.where(np.arange(400) == 7, 0.0, 0.1),
              sigma_s=np.where(np.arange(400) == 7, 0.0, 1.0)),

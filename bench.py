@@ -91,16 +91,21 @@ def describe(p):
                p["n_particles"], p["dt"], p["sn_order"]))
 
 
+DIRECT = False  # --direct: kernels launched one by one, no graphs (counter runs)
+
+
 def timed_run(S, torch, p, steps, warmup, timing=True, keep=False):
     """Times `steps` steps of a fresh solver (after `warmup` steps on another
     one).  timing: steps in timing mode (kernel times from HIP events).
     Returns (wall seconds, stats[, solver if keep])."""
     if warmup > 0:
         w = S.Solver(p)
+        w.set_graphs(not DIRECT)
         w.advance(warmup, allow_not_converged=True)
         w.synchronize(allow_not_converged=True)
         w.destroy()
     s = S.Solver(p)
+    s.set_graphs(not DIRECT)
     s.set_timing(timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -697,9 +702,14 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-seed", type=int, default=4)
     ap.add_argument("--rho", default="1.0", help="comma-separated loads, e.g. 0.5,1,2")
+    ap.add_argument("--direct", action="store_true",
+                    help="launch every kernel directly instead of as graphs (for counter "
+                         "collection, which instruments each dispatch)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    global DIRECT
+    DIRECT = args.direct
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the library has no inter-GPU sharding); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)

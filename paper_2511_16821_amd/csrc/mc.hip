@@ -113,31 +113,49 @@ __device__ __forceinline__ double bilinear(const double* q, double a, double b) 
 // integers) with target s + 1/2, going left while the target is below the
 // left count, else subtracting it and going right.  Particles are numbered
 // in cell order, so this finds the cell j with P_j <= s < P_j + n_j
-// (P_j = counts of the cells before j), and l = s - P_j.
+// (P_j = counts of the cells before j), and l = s - P_j.  A thread descends
+// kPickLanes particles' paths together, one level at a time, so that their
+// loads of the lower levels (from global memory) are in flight at once.
 constexpr int kTreeTop = 1024;  // nodes [0, kTreeTop) of the tree are staged in LDS
+constexpr int kPickLanes = 4;
 
 struct CellPick {
   long long cell;
   uint32_t l;
 };
 
-__device__ __forceinline__ CellPick count_pick(const double* __restrict__ t,
-                                               const double* __restrict__ top, long long L,
-                                               long long s) {
-  double target = (double)s + 0.5;
-  long long k = 1;
-  while (k < L) {
-    const bool in_lds = 2 * k + 1 < kTreeTop;
-    const double left = in_lds ? top[2 * k] : t[2 * k];
-    const double right = in_lds ? top[2 * k + 1] : t[2 * k + 1];
-    if (target < left || right == 0.0) {  // (an empty right subtree is never reached)
-      k = 2 * k;
-    } else {
-      target -= left;
-      k = 2 * k + 1;
+__device__ __forceinline__ void count_pick_n(const double* __restrict__ t,
+                                             const double* __restrict__ top, long long L,
+                                             const long long* s, CellPick* out) {
+  double target[kPickLanes];
+  long long k[kPickLanes];
+#pragma unroll
+  for (int j = 0; j < kPickLanes; ++j) {
+    target[j] = (double)s[j] + 0.5;
+    k[j] = 1;
+  }
+  // at the level of nodes [lev, 2 lev) the children [2 lev, 4 lev) are all
+  // in LDS or all in global memory
+  for (long long lev = 1; lev < L; lev <<= 1) {
+    const bool in_lds = 4 * lev <= kTreeTop;
+    double2 lr[kPickLanes];
+#pragma unroll
+    for (int j = 0; j < kPickLanes; ++j)
+      lr[j] = in_lds ? make_double2(top[2 * k[j]], top[2 * k[j] + 1])
+                     : reinterpret_cast<const double2*>(t)[k[j]];
+#pragma unroll
+    for (int j = 0; j < kPickLanes; ++j) {
+      if (target[j] < lr[j].x || lr[j].y == 0.0) {  // (an empty right subtree is never reached)
+        k[j] = 2 * k[j];
+      } else {
+        target[j] -= lr[j].x;
+        k[j] = 2 * k[j] + 1;
+      }
     }
   }
-  return CellPick{k - L, (uint32_t)target};  // target = s - P_j + 1/2
+#pragma unroll
+  for (int j = 0; j < kPickLanes; ++j)
+    out[j] = CellPick{k[j] - L, (uint32_t)target[j]};  // target = s - P_j + 1/2
 }
 
 // One fixed-point tally add.  XCD-local copies are only ever added to by
@@ -224,56 +242,69 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   const double wq = a.st->wq[KIND - 1];
   const R hx = (R)a.hx, hy = (R)a.hy, dt_birth = (R)a.dt_birth;
   SrcRec<R>* const b = Real<R>::src(a);
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n_emit;
-       s += (long long)gridDim.x * blockDim.x) {
-    const CellPick pk = count_pick(a.ctree, s_top, a.tree_L, s);
-    const long long ci = pk.cell;  // the emitter: a cell, or a boundary face after them
-    const uint32_t l = pk.l;
-    const uint64_t stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, (uint64_t)ci);
-    const R u1 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 0u, l));
-    const R u2 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 1u, l));
-    const R u3 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 2u, l));
-    const R u4 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 3u, l));
-    const R tau = a.n_lim > 0
-                      ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, l)))
-                      : (R)0;
-    if (ci < a.n_cells) {
-      const R u5 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 4u, l));
-      const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
-      R sp, cp;
-      Real<R>::scpi((R)2 * u5, &sp, &cp);
-      const double* q = a.qn + 4 * ci;
-      const double wscale = wq / pow2_ceil(maxabs4(q));  // exact: a power-of-two ratio
-      const R w = (R)(bilinear(q, (double)u1, (double)u2) * wscale);
-      Real<R>::put_src(b + s, hx * u1, hy * u2, sn * cp, sn * sp, w, u3 * dt_birth, tau,
-                       (int)ci, l);
-    } else {
-      // entering through boundary face f (the inflow G): uniform along the
-      // face (dim 0) and in time (dim 1), the cosine law about the inward
-      // normal, mu = sqrt(u) (dim 2), the in-plane tangential component
-      // sqrt(1 - mu^2) cos(2 pi u) (dim 3); weight w_q G_f / pow2_ceil(|G_f|)
-      int k;
-      const int f = (int)(ci - a.n_cells);
-      const int side = face_side(f, a.nx, a.ny, &k);
-      const R mu = sqrt(u3);
-      R sp, cp;
-      Real<R>::scpi((R)2 * u4, &sp, &cp);
-      const R tg = sqrt((R)1 - u3) * cp;
-      const double G = a.em.inflow[f];
-      const R w = (R)(G * (wq / pow2_ceil(fabs(G))));
-      R px, py, ox, oy;
-      if (side < 2) {
-        px = side == 0 ? (R)0 : hx;
-        py = hy * u1;
-        ox = side == 0 ? mu : -mu;
-        oy = tg;
+  const long long T = (long long)gridDim.x * blockDim.x;
+  for (long long s0 = (long long)blockIdx.x * blockDim.x + threadIdx.x; s0 < n_emit;
+       s0 += kPickLanes * T) {
+    long long sj[kPickLanes];
+    CellPick pk[kPickLanes];
+#pragma unroll
+    for (int j = 0; j < kPickLanes; ++j) {
+      const long long v = s0 + j * T;
+      sj[j] = v < n_emit ? v : s0;  // past the end: a valid particle, not emitted
+    }
+    count_pick_n(a.ctree, s_top, a.tree_L, sj, pk);
+#pragma unroll 1
+    for (int j = 0; j < kPickLanes; ++j) {
+      const long long s = s0 + j * T;
+      if (s >= n_emit) break;
+      const long long ci = pk[j].cell;  // the emitter: a cell, or a boundary face after them
+      const uint32_t l = pk[j].l;
+      const uint64_t stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, (uint64_t)ci);
+      const R u1 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 0u, l));
+      const R u2 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 1u, l));
+      const R u3 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 2u, l));
+      const R u4 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 3u, l));
+      const R tau = a.n_lim > 0
+                        ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, l)))
+                        : (R)0;
+      if (ci < a.n_cells) {
+        const R u5 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 4u, l));
+        const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
+        R sp, cp;
+        Real<R>::scpi((R)2 * u5, &sp, &cp);
+        const double* q = a.qn + 4 * ci;
+        const double wscale = wq / pow2_ceil(maxabs4(q));  // exact: a power-of-two ratio
+        const R w = (R)(bilinear(q, (double)u1, (double)u2) * wscale);
+        Real<R>::put_src(b + s, hx * u1, hy * u2, sn * cp, sn * sp, w, u3 * dt_birth, tau,
+                         (int)ci, l);
       } else {
-        px = hx * u1;
-        py = side == 2 ? (R)0 : hy;
-        oy = side == 2 ? mu : -mu;
-        ox = tg;
+        // entering through boundary face f (the inflow G): uniform along the
+        // face (dim 0) and in time (dim 1), the cosine law about the inward
+        // normal, mu = sqrt(u) (dim 2), the in-plane tangential component
+        // sqrt(1 - mu^2) cos(2 pi u) (dim 3); weight w_q G_f / pow2_ceil(|G_f|)
+        int k;
+        const int f = (int)(ci - a.n_cells);
+        const int side = face_side(f, a.nx, a.ny, &k);
+        const R mu = sqrt(u3);
+        R sp, cp;
+        Real<R>::scpi((R)2 * u4, &sp, &cp);
+        const R tg = sqrt((R)1 - u3) * cp;
+        const double G = a.em.inflow[f];
+        const R w = (R)(G * (wq / pow2_ceil(fabs(G))));
+        R px, py, ox, oy;
+        if (side < 2) {
+          px = side == 0 ? (R)0 : hx;
+          py = hy * u1;
+          ox = side == 0 ? mu : -mu;
+          oy = tg;
+        } else {
+          px = hx * u1;
+          py = side == 2 ? (R)0 : hy;
+          oy = side == 2 ? mu : -mu;
+          ox = tg;
+        }
+        Real<R>::put_src(b + s, px, py, ox, oy, w, u2 * dt_birth, tau, (int)ci, l);
       }
-      Real<R>::put_src(b + s, px, py, ox, oy, w, u2 * dt_birth, tau, (int)ci, l);
     }
   }
 }
@@ -600,10 +631,11 @@ int mc_pass_grid(bool fp32, int kind, long long max_work) {
 
 hipError_t launch_emit(const PassArgs& a, bool fp32, hipStream_t s) {
   if (a.n_src <= 0) return hipSuccess;
-  // at most 1024 blocks (about four particles per thread): each block first
-  // stages 24 KB of tables in LDS
+  // at most 2048 blocks (each block first stages 24 KB of tables in LDS, six
+  // blocks fit a compute unit); a thread takes its particles kPickLanes at a
+  // time
   long long b = (a.n_src + 255) / 256;
-  const int grid = (int)(b < 1024 ? b : 1024);
+  const int grid = (int)(b < 2048 ? b : 2048);
   if (a.kind == 1) {
     if (fp32) hipLaunchKernelGGL((k_emit<float, 1>), dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_emit<double, 1>), dim3(grid), dim3(256), 0, s, a);

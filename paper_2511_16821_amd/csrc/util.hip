@@ -258,24 +258,51 @@ __device__ __forceinline__ unsigned long long limbs_bits(const unsigned long lon
   return n == 64 ? v : (v & ((1ull << n) - 1ull));
 }
 
-// One wave: the exact sum of the histogram, rounded once; w_q; and the
-// histogram cleared for the next plan.  Lane k < kSumLimbs owns 64-bit limb
-// k of the sum (bit 0 = 2^-1074): every bin's term c_b mant_b 2^pos_b adds
-// its bits that fall in the limb, and the limb counts its own overflows;
-// lane 0 then propagates the carries and rounds.
-__global__ __launch_bounds__(64) void k_maj_sum(unsigned long long* __restrict__ hist, double adt,
-                                                double cx, double cy, long long n_src, int kind,
-                                                DevState* st) {
+// The exact sum of the histogram, rounded once; w_q; and the histogram
+// cleared for the next plan.  The block copies and clears the histogram and
+// lists its non-empty bins (in any order: the sum below is exact integer
+// arithmetic); then one wave sums them.  Lane k < kSumLimbs owns 64-bit limb
+// k of the sum (bit 0 = 2^-1074): every listed bin's term c_b mant_b 2^pos_b
+// adds its bits that fall in the limb, and the limb counts its own
+// overflows; lane 0 then propagates the carries and rounds.
+constexpr int kMajSumThreads = 256;
+__global__ __launch_bounds__(kMajSumThreads) void k_maj_sum(unsigned long long* __restrict__ hist,
+                                                            double adt, double cx, double cy,
+                                                            long long n_src, int kind,
+                                                            DevState* st) {
   if (st->halt) return;
   __shared__ unsigned long long s_h[kMajGroups * kMajBins];
+  __shared__ unsigned short s_list[kMajGroups * kMajBins];
   __shared__ unsigned long long s_limb[kSumLimbs], s_carry[kSumLimbs];
+  __shared__ int s_n, s_bad, s_ovf;
   const int lane = threadIdx.x;
-  for (int k = lane; k < kMajGroups * kMajBins; k += 64) {
-    s_h[k] = hist[k];
-    hist[k] = 0ull;
+  if (lane == 0) {
+    s_n = 0;
+    s_bad = 0;
+    s_ovf = 0;
   }
   __syncthreads();
-  if (s_h[kMajBad] || s_h[kMajBins + kMajBad] || s_h[2 * kMajBins + kMajBad]) {
+  constexpr int kN = kMajGroups * kMajBins;
+  constexpr int kPer = (kN + kMajSumThreads - 1) / kMajSumThreads;
+  unsigned long long v[kPer];  // every load in flight before the first use
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int k = lane + j * kMajSumThreads;
+    v[j] = k < kN ? hist[k] : 0ull;
+  }
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int k = lane + j * kMajSumThreads;
+    if (k >= kN) continue;
+    hist[k] = 0ull;
+    s_h[k] = v[j];
+    if (v[j]) {
+      if (k % kMajBins == kMajBad) s_bad = 1;
+      else s_list[atomicAdd(&s_n, 1)] = (unsigned short)k;
+    }
+  }
+  __syncthreads();
+  if (s_bad) {
     // a majorant overflowed: no emission (flagged by the pass set-up)
     if (lane == 0) {
       st->sumM[kind - 1] = __builtin_huge_val();
@@ -283,15 +310,15 @@ __global__ __launch_bounds__(64) void k_maj_sum(unsigned long long* __restrict__
     }
     return;
   }
+  const int n_list = s_n;
   unsigned long long acc = 0ull, carry = 0ull;
   bool overflow = false;
   // every emitter group (cells, x faces, y faces): the value of each of its
   // majorants in bin b is its constant times 2^(b - 1074)
-  for (int gb = 0; gb < kMajGroups * kMajBins && !overflow; ++gb) {
+  for (int i = 0; lane < 64 && i < n_list && !overflow; ++i) {
+    const int gb = s_list[i];
     const int g = gb / kMajBins, b = gb - g * kMajBins;
-    if (b == kMajBad) continue;
     const unsigned long long c = s_h[gb];  // the same in every lane
-    if (!c) continue;
     const double V = (g == 0 ? adt : g == 1 ? cx : cy) * ldexp(1.0, b - 1074);
     if (!(V > 0.0)) continue;
     if (!isfinite(V)) {
@@ -311,19 +338,18 @@ __global__ __launch_bounds__(64) void k_maj_sum(unsigned long long* __restrict__
     acc += add;
     carry += acc < add ? 1ull : 0ull;
   }
-  if (overflow) {
-    if (lane == 0) {
-      st->sumM[kind - 1] = __builtin_huge_val();
-      st->wq[kind - 1] = 0.0;
-    }
-    return;
-  }
+  if (lane == 0 && overflow) s_ovf = 1;  // the same in every lane of the wave
   if (lane < kSumLimbs) {
     s_limb[lane] = acc;
     s_carry[lane] = carry;
   }
   __syncthreads();
   if (lane != 0) return;
+  if (s_ovf) {
+    st->sumM[kind - 1] = __builtin_huge_val();
+    st->wq[kind - 1] = 0.0;
+    return;
+  }
   unsigned long long cin = 0ull;
   for (int k = 0; k < kSumLimbs; ++k) {  // carries of limb k go to limb k + 1
     const unsigned long long v = s_limb[k] + cin;
@@ -437,7 +463,7 @@ hipError_t launch_emission_plan(const double* qn, long long n_cells, const Emitt
   if (em.n_faces > 0)
     hipLaunchKernelGGL(k_face_hist, dim3((unsigned)((em.n_faces + 255) / 256)), dim3(256), 0, s,
                        em, hist, halt);
-  hipLaunchKernelGGL(k_maj_sum, dim3(1), dim3(64), 0, s, hist, adt, em.cx, em.cy, n_src, kind, st);
+  hipLaunchKernelGGL(k_maj_sum, dim3(1), dim3(kMajSumThreads), 0, s, hist, adt, em.cx, em.cy, n_src, kind, st);
   b = (L + 255) / 256;
   grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
   hipLaunchKernelGGL(k_count_leaves, dim3(grid), dim3(256), 0, s, qn, n_cells, em, L, adt, seed,

@@ -327,7 +327,9 @@ typedef struct {
 typedef struct slh_solver slh_solver;
 
 /* Allocator hooks for device memory (e.g. PyTorch's caching allocator).  Both
- * NULL -> hipMalloc / hipFree. */
+ * NULL -> hipMalloc / hipFree.  alloc must return memory aligned to 256 bytes
+ * (as hipMalloc does), or NULL; slh_create fails with SLH_E_INVALID_ARG on a
+ * misaligned block (after handing it back to free_fn). */
 typedef void *(*slh_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*slh_free_fn)(void *ptr, void *ctx);
 

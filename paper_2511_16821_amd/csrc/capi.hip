@@ -496,6 +496,7 @@ struct slh_solver {
   Sizes z;
   hipStream_t stream = nullptr;
   slh_alloc_fn alloc = nullptr;
+  bool misaligned = false;  // the allocator returned memory not aligned to 256 bytes
   slh_free_fn free_fn = nullptr;
   void* ctx = nullptr;
   std::vector<void*> allocs;
@@ -604,6 +605,11 @@ struct slh_solver {
       return bump_base + off;
     } else if (alloc) {
       p = alloc(bytes, ctx);
+      if (p && ((uintptr_t)p & 255u)) {  // the kernels' vector loads need alignment
+        if (free_fn) free_fn(p, ctx);
+        misaligned = true;
+        return nullptr;
+      }
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
       p = nullptr;
     }
@@ -645,7 +651,11 @@ static slh_status setup(slh_solver* s) {
 #define ALLOC(ptr, T, n)                                                               \
   do {                                                                                 \
     ptr = (T*)s->dalloc(sizeof(T) * (size_t)(n));                                      \
-    if (!ptr) return fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: " #ptr);    \
+    if (!ptr)                                                                          \
+      return s->misaligned                                                             \
+                 ? fail(SLH_E_INVALID_ARG, "the allocator returned memory not aligned "  \
+                                           "to 256 bytes: " #ptr)                       \
+                 : fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: " #ptr);        \
   } while (0)
   if (dg_sweep_lds_bytes(false, z.dg_cw, 0, p.nx, p.ny) > lds_limit())
     return fail(SLH_E_INVALID_ARG, "nx + ny too large for the sweep's LDS traces");
@@ -712,7 +722,9 @@ static slh_status setup(slh_solver* s) {
                                                      : sizeof(StageRec<double>)));
   s->src_mem = s->dalloc(s->src_bytes(z.n_src_cap));
   if (!s->bank_mem[0] || !s->bank_mem[1] || !s->stage_mem || !s->src_mem)
-    return fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: census banks");
+    return s->misaligned ? fail(SLH_E_INVALID_ARG,
+                                "the allocator returned memory not aligned to 256 bytes: banks")
+                         : fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: census banks");
   ALLOC(s->alive, uint8_t, z.n_cand);
   ALLOC(s->flags, long long, z.n_cand);
   ALLOC(s->incl, long long, z.n_cand);

@@ -603,24 +603,33 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_famsum(
   const int half = (int)(gridDim.x >> 1);
   const bool fb = (int)blockIdx.x >= half;
   const int u0 = fb ? n_a : 0, u1 = fb ? n_dir : n_a;
-  double* __restrict__ out = phi_fam + (fb ? n_nodes : 0);
+  double2* __restrict__ out = reinterpret_cast<double2*>(phi_fam + (fb ? n_nodes : 0));
+  // two nodes per thread (16-byte loads; n_nodes = 4 cells is even)
+  const long long n2 = n_nodes >> 1;
   for (long long k = (long long)(blockIdx.x - (fb ? half : 0)) * kRedBlock + threadIdx.x;
-       k < n_nodes; k += (long long)half * kRedBlock) {
+       k < n2; k += (long long)half * kRedBlock) {
     // sixteen planes' loads in flight per step, added in direction order
-    double v = 0.0;
+    double vx = 0.0, vy = 0.0;
     int u = u0;
     for (; u + 16 <= u1; u += 16) {
-      double t[16];
+      double2 t[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) t[e] = psi[(long long)fam_dirs[u + e] * n_nodes + k];
+      for (int e = 0; e < 16; ++e)
+        t[e] = reinterpret_cast<const double2*>(psi + (long long)fam_dirs[u + e] * n_nodes)[k];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) v += dir[3 * fam_dirs[u + e] + 2] * t[e];
+      for (int e = 0; e < 16; ++e) {
+        const double w = dir[3 * fam_dirs[u + e] + 2];
+        vx += w * t[e].x;
+        vy += w * t[e].y;
+      }
     }
     for (; u < u1; ++u) {
       const int m = fam_dirs[u];
-      v += dir[3 * m + 2] * psi[(long long)m * n_nodes + k];
+      const double2 t = reinterpret_cast<const double2*>(psi + (long long)m * n_nodes)[k];
+      vx += dir[3 * m + 2] * t.x;
+      vy += dir[3 * m + 2] * t.y;
     }
-    out[k] = v;
+    out[k] = make_double2(vx, vy);
   }
 }
 
@@ -764,7 +773,7 @@ __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int
 hipError_t launch_dg_reduce(const DgArgs& a, double* partials, int n_part, double si_tol,
                             int si_max, hipStream_t s) {
   const long long n_nodes = 4ll * a.nx * a.ny;
-  hipLaunchKernelGGL(k_dg_famsum, dim3(2 * dg_reduce_partials(n_nodes)), dim3(kRedBlock), 0, s,
+  hipLaunchKernelGGL(k_dg_famsum, dim3(2 * dg_reduce_partials(n_nodes / 2)), dim3(kRedBlock), 0, s,
                      a.fam_dirs, a.fam_n, a.n_dir, n_nodes, (const double*)a.psi, a.dir,
                      a.phi_fam, (const DevState*)a.st);
   hipLaunchKernelGGL(k_dg_combine, dim3(n_part), dim3(kRedBlock), 0, s, a.nx, a.ny,

@@ -1,6 +1,7 @@
 """Failure paths of the C ABI on the device, each forced from the host so
 that every kernel still exits normally: an allocator that runs out of memory
-part-way through slh_create, a source iteration stopped at its limit, a
+part-way through slh_create, one that returns a misaligned block, a source
+iteration stopped at its limit, a
 source too large for the fixed-point bounds, and a checkpoint written for
 another mesh."""
 import ctypes as C
@@ -73,6 +74,44 @@ def test_allocator_failure_releases_everything(S):
         assert r == S.SLH_E_OUT_OF_MEMORY, (k, r)
         assert not h.value
         assert b"allocation failed" in S.lib().slh_last_error()
+        assert not a.live, (k, len(a.live))
+    torch.cuda.synchronize()
+
+
+def test_misaligned_allocator_block_is_rejected(S):
+    """An allocator whose k-th block is not aligned to 256 bytes: slh_create
+    reports SLH_E_INVALID_ARG (the kernels' vector loads need the alignment),
+    hands the block back to free_fn with every other one, and returns no
+    solver."""
+    import torch
+    p = _small()
+    st, keep = S.make_problem(p)
+    stream = torch.cuda.current_stream()
+
+    class Skewed:
+        def __init__(self, skew_at):
+            self.skew_at, self.calls, self.live = skew_at, 0, {}
+            self.a = S.ALLOC_FN(self._alloc)
+            self.f = S.FREE_FN(self._free)
+
+        def _alloc(self, n, ctx):
+            self.calls += 1
+            base = torch.cuda.caching_allocator_alloc(int(n) + 256, stream=stream)
+            ptr = base + 16 if self.calls == self.skew_at else base
+            self.live[ptr] = base
+            return ptr
+
+        def _free(self, ptr, ctx):
+            torch.cuda.caching_allocator_delete(self.live.pop(ptr))
+
+    for k in (1, 7):
+        a = Skewed(k)
+        h = C.c_void_p()
+        r = S.lib().slh_create(C.byref(st), C.c_void_p(stream.cuda_stream), a.a, a.f, None,
+                               C.byref(h))
+        assert r == S.SLH_E_INVALID_ARG, (k, r)
+        assert not h.value
+        assert b"aligned" in S.lib().slh_last_error()
         assert not a.live, (k, len(a.live))
     torch.cuda.synchronize()
 

@@ -581,6 +581,7 @@ struct slh_solver {
   // a step whose batch ends before the iteration halts itself and the steps
   // after it on the device, and settle() runs them again
   int si_batch = 0;
+  unsigned long long last_halted = ~0ull;  // step index of the last halted step
   int batch_run = 0;          // the batch of the step being enqueued
   bool unsettled = false;     // steps enqueued since the last settle()
   unsigned long long restarts = 0ull;  // steps run again after a halt
@@ -1453,13 +1454,32 @@ extern "C" slh_status slh_advance(slh_solver* s, int32_t n_steps) {
   return SLH_OK;
 }
 
+// Batch for running a halted step again: the iterations it did plus an
+// estimate of those it still needs from the contraction of its last two
+// iterate changes, rho = |d_k| / |d_{k-1}|, as log(tol |phi| / |d_k|) / log rho,
+// with a quarter more and four to spare; the limit si_max when there is no
+// estimate (fewer than two iterations, no contraction).
+static int restart_batch(const DevState& d, double tol, int si_max) {
+  const double dn = sqrt(d.si.dn2), dp = sqrt(d.si.dn2_prev), nrm = sqrt(d.si.nrm2);
+  if (d.si.iter < 2 || !(dn > 0.0) || !(dp > 0.0) || !(nrm > 0.0) || !isfinite(dn) ||
+      !isfinite(dp) || !isfinite(nrm))
+    return si_max;
+  const double rho = dn / dp, target = tol * nrm;
+  if (!(rho < 0.99)) return si_max;
+  if (dn <= target) return round_batch((long long)d.si.iter + 4, si_max);
+  const double more = log(target / dn) / log(rho);
+  if (!(more < (double)si_max)) return si_max;
+  return round_batch((long long)d.si.iter + (long long)ceil(1.25 * more) + 4, si_max);
+}
+
 // Waits for the enqueued steps and runs again those that a halted batch left
 // undone.  A halted step and every step after it returned from each kernel at
 // once, so the device holds the state at the start of the halted step: it is
-// run with the full limit si_max (its batch cannot end early), the ones after
-// it with a doubled batch, and the check repeats until no step halted.  The
-// batch then follows the last step's iteration count (an eighth more, plus
-// two, in multiples of four).
+// run with the batch restart_batch estimates (the full limit si_max if the
+// same step halts a second time), the ones after it with a doubled batch (at
+// least the estimate), and the check repeats until no step halted.  The batch
+// then follows the last step's iteration count (an eighth more, plus two, in
+// multiples of four).
 static slh_status settle(slh_solver* s, DevState* out = nullptr) {
   DevState d;
   for (;;) {
@@ -1472,9 +1492,11 @@ static slh_status settle(slh_solver* s, DevState* out = nullptr) {
     s->cur ^= (int)(lost & 1);
     s->step -= lost;
     s->restarts += (unsigned long long)lost;
-    s->si_batch = round_batch(2ll * s->si_batch, s->si_max);
+    const int rb = d.step == s->last_halted ? s->si_max : restart_batch(d, s->si_tol, s->si_max);
+    s->last_halted = d.step;
+    s->si_batch = std::max(round_batch(2ll * s->si_batch, s->si_max), rb < s->si_max ? rb : 0);
     HIP_TRY(hipMemsetAsync(&s->st->halt, 0, sizeof(int), s->stream));
-    slh_status r = run_step(s, s->si_max);
+    slh_status r = run_step(s, rb);
     for (long long k = 1; k < lost && r == SLH_OK; ++k) r = run_step(s, s->si_batch);
     if (r != SLH_OK) return r;
   }

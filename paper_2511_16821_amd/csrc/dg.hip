@@ -68,6 +68,7 @@ __global__ void k_si_start(int nx, int ny, const double* __restrict__ sig_s,
     st->si.done = si_max == 0 ? 1 : 0;
     st->si.bad = 0;
     st->si.dn2 = 0.0;
+    st->si.dn2_prev = 0.0;
     st->si.nrm2 = 0.0;
     st->dsa_unconv = 0;
     st->dsa_corrections = 0;
@@ -754,6 +755,7 @@ __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int
   if (threadIdx.x == 0) {
     const double dn2 = s_d[0], nrm2 = s_n[0];
     const double dn = sqrt(dn2), nrm = sqrt(nrm2);
+    st->si.dn2_prev = st->si.iter > 0 ? st->si.dn2 : 0.0;
     st->si.dn2 = dn2;
     st->si.nrm2 = nrm2;
     st->si.iter += 1;

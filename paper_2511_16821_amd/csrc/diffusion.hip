@@ -165,6 +165,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_start_state(const double* part,
     cs->beta = 0.0;
     cs->bb = bb;
     cs->dn2 = bb;
+    cs->dn2_prev = 0.0;
     cs->nrm2 = bb;
     // a zero source has the exact solution 0
     const int conv = max_iter == 0 || bb == 0.0;
@@ -259,6 +260,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_residual(const double* part, in
   if (threadIdx.x == 0) {
     const double bb = cs->bb;
     cs->iter += 1;
+    cs->dn2_prev = cs->dn2;
     cs->dn2 = rr;
     cs->nrm2 = bb;
     const int bad = !isfinite(rr) || !isfinite(rz);
@@ -357,6 +359,7 @@ __global__ __launch_bounds__(kCgOneBlock) void k_cg_solve_one_block(
   }
   if (t == 0) {
     cs->iter = it;
+    cs->dn2_prev = 0.0;
     cs->dn2 = rr;
     cs->nrm2 = bb;
     cs->bad = bad;

@@ -12,10 +12,11 @@
 // shared counter.  The work index g maps to census particle g (g < n_in) or
 // source particle g - n_in; every random number of a history is a pure function of its
 // (stream, dimension, point index), so results do not depend on which lane or
-// wave ran it.  Tallies and balance sums are two-word fixed point with integer
-// atomics and are therefore independent of the schedule.  Each lane adds into
-// one of several private copies of the tally (summed afterwards), so that
-// simultaneous updates of a busy cell do not queue on one cache line.
+// wave ran it.  Tallies and balance sums are fixed point with integer atomics
+// and are therefore independent of the schedule.  Each lane adds into one of
+// several private copies of the tally (summed afterwards), through a small
+// cache of tally words per wave in LDS, so that simultaneous updates of a busy
+// cell do not queue on one cache line.
 #include "slh_common.hpp"
 #include "sobol_dirs.inc"
 
@@ -167,38 +168,23 @@ __device__ __forceinline__ void tally_add(unsigned long long* p, unsigned long l
   else atomicAdd(p, v);
 }
 
-// The tally adds of one loop iteration of a wave (lane: word p, value v; p
-// null for no add), with every lane of the wave active.  Lanes adding to the
-// same word are summed first and their sum is added by one lane, since many
-// lanes of a wave often sit in the same cell (particles are numbered in cell
-// order, and a busy cell near a source receives thousands of adds at once),
-// where the atomics would queue one after another on the word.  Words are
-// taken in lane order; as soon as a word has a single adder, the remaining
-// lanes add directly, so a wave whose lanes are spread over many cells pays
-// only one vote.  Integer sums: the result is the same as with one atomic
-// per lane.
-__device__ __forceinline__ void wave_tally_add(unsigned long long* p, unsigned long long v,
-                                               int xl) {
-  unsigned long long pending = __ballot(p != nullptr);
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const unsigned long long pp = (unsigned long long)p;
-    const unsigned long long pl =
-        (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)pp, leader) |
-        ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(pp >> 32),
-                                                                leader) << 32);
-    const bool mine = p != nullptr && pp == pl;
-    const unsigned long long same = __ballot(mine);
-    if (__popcll(same) == 1) {
-      if (p) tally_add(p, v, xl);
-      return;
-    }
-    unsigned long long sum = mine ? v : 0ull;
-    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-    if ((int)__lane_id() == leader) tally_add(p, sum, xl);
-    if (mine) p = nullptr;
-    pending &= ~same;
-  }
+// Tally-word cache of a wave in LDS: kTcSlots slots of (word address, pending
+// sum).  A lane's add goes to the slot its word hashes to: into the slot's
+// sum when the slot holds that word or is free (claimed with a compare and
+// swap), else straight to the tally.  Every kTcFlush loop iterations, and at
+// the end, the wave adds each held sum to its word and frees the slots.
+// The histories of a wave start on neighbouring work items (cell order) and
+// stay near each other, so many adds of a busy region meet in the cache
+// instead of queueing at the same L2 lines; integer sums make the result the
+// same as with one atomic per add.  512 slots per wave (32 KB per block) keep
+// three blocks per compute unit.
+constexpr int kTcSlots = 512;
+constexpr int kTcFlush = 16;
+
+__device__ __forceinline__ int tc_slot(unsigned long long ad) {
+  // word index plus the 8 MB-aligned high bits, so that copies of one cell
+  // (a power of two apart) fall in different slots
+  return (int)(((ad >> 3) + (ad >> 23) * 37ull) & (unsigned long long)(kTcSlots - 1));
 }
 
 // Copies of a tracking block's balance in LDS (odd stride: the copies start
@@ -320,6 +306,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __shared__ unsigned long long s_bal[kBalCopies * kBalStride];
   __shared__ unsigned long long s_cnt[4];
   __shared__ uint32_t s_sobol[kSobolNibbleWords];
+  __shared__ unsigned long long s_tc_tag[4 * kTcSlots];  // four waves per block
+  __shared__ unsigned long long s_tc_sum[4 * kTcSlots];
+  for (int k = threadIdx.x; k < 4 * kTcSlots; k += blockDim.x) {
+    s_tc_tag[k] = 0ull;
+    s_tc_sum[k] = 0ull;
+  }
   for (int k = threadIdx.x; k < kBalCopies * kBalStride; k += blockDim.x) s_bal[k] = 0ull;
   if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0ull;
   sobol_nibbles_fill(a.sobol, s_sobol, threadIdx.x, blockDim.x);
@@ -372,6 +364,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   bool from_census = false;
   unsigned int lane_seg = 0, lane_hist = 0, lane_alive = 0, lane_killed = 0, lane_bad = 0;
   unsigned long long* my_bal = s_bal + (lane % kBalCopies) * kBalStride;
+  unsigned long long* const tc_tag = s_tc_tag + (threadIdx.x >> 6) * kTcSlots;
+  unsigned long long* const tc_sum = s_tc_sum + (threadIdx.x >> 6) * kTcSlots;
+  int tc_it = 0;
+  // the wave's held sums to their words (all lanes of the wave together)
+  auto tc_flush = [&]() __attribute__((always_inline)) {
+    for (int k = lane; k < kTcSlots; k += 64) {
+      const unsigned long long tg = tc_tag[k];
+      if (tg) {
+        tally_add((unsigned long long*)tg, tc_sum[k], xl);
+        tc_tag[k] = 0ull;
+        tc_sum[k] = 0ull;
+      }
+    }
+  };
 
   for (;;) {
     // static work assignment: lane t of T takes work items t, t + T, t + 2T, ...
@@ -437,7 +443,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     }
     if (!__any(have)) {
-      wave_tally_add(p_ptr, p_val, xl);  // the last pending adds
+      if (p_ptr) tally_add(p_ptr, p_val, xl);  // the last pending add
+      tc_flush();
       break;
     }
     // this iteration's tally word and value (none for an idle lane)
@@ -555,7 +562,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
     // A lane's consecutive adds to one word (segments that end in a
     // collision or at the census stay in their cell) are summed in registers;
-    // the pending sum goes out when the lane moves to another word.
+    // the pending sum goes to the wave's cache when the lane moves to another
+    // word.
     unsigned long long* f_ptr = nullptr;
     unsigned long long f_val = 0ull;
     if (t_ptr) {
@@ -568,7 +576,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         p_val = t_val;
       }
     }
-    wave_tally_add(f_ptr, f_val, xl);
+    if (f_ptr) {
+      const unsigned long long ad = (unsigned long long)f_ptr;
+      const int slot = tc_slot(ad);
+      unsigned long long tg = tc_tag[slot];
+      if (tg == 0ull) {
+        const unsigned long long old = atomicCAS(&tc_tag[slot], 0ull, ad);
+        tg = old == 0ull ? ad : old;
+      }
+      if (tg == ad) atomicAdd(&tc_sum[slot], f_val);
+      else tally_add(f_ptr, f_val, xl);
+    }
+    if (++tc_it == kTcFlush) {
+      tc_it = 0;
+      tc_flush();
+    }
   }
 
   // wave totals of the integer counters, one atomic per wave

@@ -266,6 +266,7 @@ struct IterState {
   int iter;     // iterations done in this solve
   int bad;      // non-finite residual
   double dn2;   // |phi_new - phi_old|^2 of the last iteration (CG: |r|^2)
+  double dn2_prev;  // the same of the iteration before (0 before the second)
   double nrm2;  // |phi_new|^2, or the whole-flux norm (CG: |b|^2)
   double rz;    // CG: r . z of the current iterate
   double beta;  // CG: beta of the next direction update

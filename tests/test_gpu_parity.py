@@ -415,12 +415,15 @@ def test_short_si_batches_run_again(S):
     assert ref.synchronize() == S.SLH_OK
     rs = ref.get_stats()
     assert rs["si_restarts_total"] == 0 and rs["si_iterations"] > 2
-    for graphs, timing in ((True, False), (False, False), (True, True)):
-        a = run(6, 1, graphs, timing)
+    # a batch of one halts with no rate estimate (the step runs again with the
+    # limit); a batch of four runs it again with the estimated batch
+    for graphs, timing, batch in ((True, False, 1), (False, False, 1), (True, True, 1),
+                                  (True, False, 4)):
+        a = run(6, batch, graphs, timing)
         assert a.synchronize() == S.SLH_OK
         st = a.get_stats()
-        log("graphs", graphs, "timing", timing, "restarts", st["si_restarts_total"],
-            "batch", st["si_batch"])
+        log("graphs", graphs, "timing", timing, "first batch", batch, "restarts",
+            st["si_restarts_total"], "batch", st["si_batch"])
         assert st["si_restarts_total"] >= 1
         for which in (S.SLH_FLUX_REMAP, S.SLH_FLUX_PRE, S.SLH_FLUX_POST,
                       S.SLH_FLUX_COLLIDED_NODAL):

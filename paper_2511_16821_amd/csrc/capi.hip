@@ -396,8 +396,10 @@ static Sizes sizes_of(const slh_problem* p) {
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
   b += (size_t)z.cap * bank * 2;             // census banks
   b += (size_t)(z.n_src_cap > 0 ? z.n_src_cap : 1) * srec;  // source bank
-  b += (size_t)z.n_cand * ((z.fp32 ? 32 : 64) + 1 + 8 + 8);  // staging, alive, flags, scan
-  b += std::max(scan_tmp_elems(z.n_cand), scan_tmp_elems((long long)radix_hist_elems(z.cap))) * 8;
+  b += (size_t)z.n_cand * ((z.fp32 ? 32 : 64) + 1);  // staging, alive
+  b += (size_t)census_tiles(z.n_cand) * 16;          // tile counts and their scan
+  b += std::max(scan_tmp_elems(census_tiles(z.n_cand)),
+                scan_tmp_elems((long long)radix_hist_elems(z.cap))) * 8;
   b += (size_t)z.cap * 4 * 6 + radix_hist_elems(z.cap) * 16 + nc * 4;  // census ordering
   b += sizeof(DevState) + 32 * 32 * 4 + 64 * 8 + kCensusBlocks * 8;
   b += 64 * 1024;  // alignment of the ~30 device buffers
@@ -556,7 +558,7 @@ struct slh_solver {
   void* stage_mem = nullptr;
   void* src_mem = nullptr;  // source bank of the current pass
   uint8_t* alive = nullptr;
-  long long *flags = nullptr, *incl = nullptr, *scan_i = nullptr;
+  long long *tcount = nullptr, *tincl = nullptr, *scan_i = nullptr;
   // census ordering: (cell, slot) pairs and their sort buffers, the radix
   // histograms, cohort starts per cell, and each bank's cohort ranks
   uint32_t *skey[2] = {nullptr, nullptr}, *sval[2] = {nullptr, nullptr};
@@ -727,9 +729,9 @@ static slh_status setup(slh_solver* s) {
                                 "the allocator returned memory not aligned to 256 bytes: banks")
                          : fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: census banks");
   ALLOC(s->alive, uint8_t, z.n_cand);
-  ALLOC(s->flags, long long, z.n_cand);
-  ALLOC(s->incl, long long, z.n_cand);
-  ALLOC(s->scan_i, long long, std::max(scan_tmp_elems(z.n_cand),
+  ALLOC(s->tcount, long long, census_tiles(z.n_cand));
+  ALLOC(s->tincl, long long, census_tiles(z.n_cand));
+  ALLOC(s->scan_i, long long, std::max(scan_tmp_elems(census_tiles(z.n_cand)),
                                       scan_tmp_elems((long long)radix_hist_elems(z.cap))));
   for (int k = 0; k < 2; ++k) {
     ALLOC(s->skey[k], uint32_t, z.cap);
@@ -1126,20 +1128,21 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
       HIP_TRY(launch_thin_params(s->st, z.cap, s->thin_margin, st));
       // kept candidates (first cap in slot order), ordered by cell: the
       // census cohorts of the next step
-      const long long* last = s->incl + (z.n_cand - 1);
+      const long long tiles = census_tiles(z.n_cand);
+      const long long* last = s->tincl + (tiles - 1);
       const int odd = radix_passes(nc) & 1;  // the sorted pairs end in buffer odd
       if (z.fp32) {
         const StageRec<float>* src = (const StageRec<float>*)s->stage_mem;
-        HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
-        HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, &s->st->halt, st));
-        HIP_TRY(launch_census_keys<float>(src, s->incl, z.n_cand, z.cap, s->skey[0], s->sval[0],
-                                          s->st, st));
+        HIP_TRY(launch_census_keep(s->alive, src, z.n_cand, p.seed, s->st, s->tcount, st));
+        HIP_TRY(scan_inclusive_i64(s->tcount, s->tincl, tiles, s->scan_i, &s->st->halt, st));
+        HIP_TRY(launch_census_keys<float>(src, s->alive, s->tcount, s->tincl, z.n_cand, z.cap,
+                                          s->skey[0], s->sval[0], s->st, st));
       } else {
         const StageRec<double>* src = (const StageRec<double>*)s->stage_mem;
-        HIP_TRY(launch_census_flags(s->alive, src, z.n_cand, p.seed, s->st, s->flags, st));
-        HIP_TRY(scan_inclusive_i64(s->flags, s->incl, z.n_cand, s->scan_i, &s->st->halt, st));
-        HIP_TRY(launch_census_keys<double>(src, s->incl, z.n_cand, z.cap, s->skey[0],
-                                           s->sval[0], s->st, st));
+        HIP_TRY(launch_census_keep(s->alive, src, z.n_cand, p.seed, s->st, s->tcount, st));
+        HIP_TRY(scan_inclusive_i64(s->tcount, s->tincl, tiles, s->scan_i, &s->st->halt, st));
+        HIP_TRY(launch_census_keys<double>(src, s->alive, s->tcount, s->tincl, z.n_cand, z.cap,
+                                           s->skey[0], s->sval[0], s->st, st));
       }
       HIP_TRY(radix_sort_pairs(s->skey[0], s->sval[0], s->skey[1], s->sval[1], last, z.cap, nc,
                                s->rhist, s->rincl, s->scan_i, s->st, st));
@@ -1151,7 +1154,7 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
         HIP_TRY(launch_census_gather<double>((const StageRec<double>*)s->stage_mem,
                                              s->sval[odd], last, z.cap, (StageRec<double>*)nb,
                                              s->st, s->cmax, st));
-      HIP_TRY(launch_census_finish(s->st, s->incl, z.n_cand, z.cap, s->cmax, st));
+      HIP_TRY(launch_census_finish(s->st, s->tincl, tiles, z.cap, s->cmax, st));
       HIP_TRY(launch_cohort_ranks(s->skey[odd], &s->st->n_in, z.cap, s->cstart,
                                   s->crank[1 - s->cur], s->st, st));
       return SLH_OK;

@@ -599,17 +599,25 @@ size_t scan_tmp_elems(long long n);
 hipError_t scan_inclusive_i64(const long long* in, long long* out, long long n,
                               long long* tmp, const int* halt, hipStream_t s);
 hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hipStream_t s);
+// Census candidates are processed in tiles of kKeepTile slots.
+// launch_census_keep: each candidate's keep decision (alive and, with the cap
+// active, its key test), stored in place of its alive byte, and the kept
+// count of each tile (tcount, census_tiles(n) entries).
+constexpr int kKeepTile = 4096;
+long long census_tiles(long long n);
 template <typename R>
-hipError_t launch_census_flags(const uint8_t* alive, const StageRec<R>* stage, long long n,
-                               uint64_t seed, const DevState* st, long long* flags,
-                               hipStream_t s);
+hipError_t launch_census_keep(uint8_t* alive, const StageRec<R>* stage, long long n,
+                              uint64_t seed, const DevState* st, long long* tcount,
+                              hipStream_t s);
 // The census bank at t_{n+1} (kept candidates, first cap in slot order,
 // ordered by cell and within a cell by slot): (cell, slot) pairs of the kept
 // candidates in slot order, then radix_sort_pairs by cell, then the gather of
-// the records (weights times the thinning factor); incl: the inclusive scan
-// of the kept flags, whose last entry bounds the count with cap.
+// the records (weights times the thinning factor).  tincl: the inclusive
+// scan of the tile counts, whose last entry (the kept total) bounds the count
+// with cap.
 template <typename R>
-hipError_t launch_census_keys(const StageRec<R>* src, const long long* incl, long long n,
+hipError_t launch_census_keys(const StageRec<R>* src, const uint8_t* keep,
+                              const long long* tcount, const long long* tincl, long long n,
                               long long cap, uint32_t* keys, uint32_t* vals, const DevState* st,
                               hipStream_t s);
 long long radix_tiles(long long n);
@@ -624,7 +632,8 @@ hipError_t launch_census_gather(const StageRec<R>* src, const uint32_t* vals,
                                 const long long* incl_last, long long cap, StageRec<R>* dst,
                                 const DevState* st, double* bmax, hipStream_t s);
 // bmax: kCensusBlocks doubles, the gather's per-block max |w|
-hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,
+// tincl: n_tiles inclusive tile counts (the last is the kept total)
+hipError_t launch_census_finish(DevState* st, const long long* tincl, long long n_tiles,
                                 long long cap, const double* bmax, hipStream_t s);
 constexpr int kCensusBlocks = 2048;  // blocks of the gather grid at most
 int census_compact_blocks(long long n);

@@ -592,46 +592,59 @@ hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hip
   return hipGetLastError();
 }
 
+long long census_tiles(long long n) { return (n + kKeepTile - 1) / kKeepTile; }
+
+// One tile of kKeepTile candidates per block, read in rounds of 256 (slot
+// base + r 256 + t in round r, thread t): each candidate's keep decision in
+// place of its alive byte, and the tile's kept count.
 template <typename R>
-__global__ void k_census_flags(const uint8_t* __restrict__ alive,
-                               const StageRec<R>* __restrict__ stage, long long n,
-                               uint64_t seed, const DevState* st,
-                               long long* __restrict__ flags) {
+__global__ __launch_bounds__(256) void k_census_keep(uint8_t* __restrict__ alive,
+                                                     const StageRec<R>* __restrict__ stage,
+                                                     long long n, uint64_t seed,
+                                                     const DevState* st,
+                                                     long long* __restrict__ tcount) {
   if (st->halt) return;
+  __shared__ int s_c[4];
   // the thinning keys' stream: (step, pass 2, population 2)
   const uint64_t thin_stream = stream_seed(seed, st->step, 2u, 2u, 0ull);
   const int act = st->thin_active;
   const unsigned long long mant = st->thin_mant;
   const int rs = st->thin_rshift;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    long long f = alive[i] ? 1 : 0;
+  const long long base = (long long)blockIdx.x * kKeepTile;
+  int cnt = 0;
+  for (int r = 0; r < kKeepTile / 256; ++r) {
+    const long long i = base + r * 256 + threadIdx.x;
+    if (i >= n) break;
+    int f = alive[i] ? 1 : 0;
     if (f && act) {
       const unsigned long long key = mix64(thin_stream ^ stage[i].hid);
       const unsigned long long top = rs >= 64 ? 0ull : (key >> rs);
       f = top < mant ? 1 : 0;
+      alive[i] = (uint8_t)f;
     }
-    flags[i] = f;
+    cnt += f;
   }
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+  if (__lane_id() == 0) s_c[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) tcount[blockIdx.x] = (long long)(s_c[0] + s_c[1] + s_c[2] + s_c[3]);
 }
 
 template <typename R>
-hipError_t launch_census_flags(const uint8_t* alive, const StageRec<R>* stage, long long n,
-                               uint64_t seed, const DevState* st, long long* flags,
-                               hipStream_t s) {
-  long long b = (n + 255) / 256;
-  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_census_flags<R>, dim3(grid), dim3(256), 0, s, alive, stage, n, seed, st,
-                     flags);
+hipError_t launch_census_keep(uint8_t* alive, const StageRec<R>* stage, long long n,
+                              uint64_t seed, const DevState* st, long long* tcount,
+                              hipStream_t s) {
+  const long long tiles = census_tiles(n > 0 ? n : 1);
+  hipLaunchKernelGGL(k_census_keep<R>, dim3((unsigned)tiles), dim3(256), 0, s, alive, stage, n,
+                     seed, st, tcount);
   return hipGetLastError();
 }
-template hipError_t launch_census_flags<double>(const uint8_t*, const StageRec<double>*,
-                                                long long, uint64_t, const DevState*,
-                                                long long*, hipStream_t);
-template hipError_t launch_census_flags<float>(const uint8_t*, const StageRec<float>*, long long,
+template hipError_t launch_census_keep<double>(uint8_t*, const StageRec<double>*, long long,
                                                uint64_t, const DevState*, long long*,
                                                hipStream_t);
-
+template hipError_t launch_census_keep<float>(uint8_t*, const StageRec<float>*, long long,
+                                              uint64_t, const DevState*, long long*,
+                                              hipStream_t);
 
 // ---------------------------------------------------------------------------
 // The census bank at t_{n+1}: the kept candidates (first cap in slot order)
@@ -647,35 +660,63 @@ __device__ __forceinline__ long long census_count(const long long* incl_last, lo
   return k < cap ? k : cap;
 }
 
+// The tile's kept candidates, in slot order, at their places among all kept
+// ones (the kept of earlier tiles first; rounds in order, the waves of a
+// round in order, lanes in order), the first cap of them only.
 template <typename R>
-__global__ void k_census_keys(const StageRec<R>* __restrict__ src,
-                              const long long* __restrict__ incl, long long n, long long cap,
-                              uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                              const DevState* st) {
+__global__ __launch_bounds__(256) void k_census_keys(const StageRec<R>* __restrict__ src,
+                                                     const uint8_t* __restrict__ keep,
+                                                     const long long* __restrict__ tcount,
+                                                     const long long* __restrict__ tincl,
+                                                     long long n, long long cap,
+                                                     uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals,
+                                                     const DevState* st) {
   if (st->halt) return;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long before = i > 0 ? incl[i - 1] : 0;
-    if (incl[i] == before || before >= cap) continue;  // not kept, or past the cap
-    keys[before] = (uint32_t)src[i].cell;
-    vals[before] = (uint32_t)i;
+  __shared__ int s_w[4];
+  long long before = tincl[blockIdx.x] - tcount[blockIdx.x];  // kept in earlier tiles
+  if (before >= cap || tcount[blockIdx.x] == 0) return;       // the same for the whole block
+  const long long base = (long long)blockIdx.x * kKeepTile;
+  const int w = threadIdx.x >> 6;
+  for (int r = 0; r < kKeepTile / 256; ++r) {
+    const long long i = base + r * 256 + threadIdx.x;
+    const bool f = i < n && keep[i] != 0;
+    const unsigned long long m = __ballot(f);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (__lane_id() == 0) s_w[w] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int v = 0; v < 4; ++v) {
+      off += v < w ? s_w[v] : 0;
+      tot += s_w[v];
+    }
+    const long long pos = before + off + below;
+    if (f && pos < cap) {
+      keys[pos] = (uint32_t)src[i].cell;
+      vals[pos] = (uint32_t)i;
+    }
+    before += tot;
+    __syncthreads();
   }
 }
 
 template <typename R>
-hipError_t launch_census_keys(const StageRec<R>* src, const long long* incl, long long n,
+hipError_t launch_census_keys(const StageRec<R>* src, const uint8_t* keep,
+                              const long long* tcount, const long long* tincl, long long n,
                               long long cap, uint32_t* keys, uint32_t* vals, const DevState* st,
                               hipStream_t s) {
-  long long b = (n + 255) / 256;
-  const int grid = (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
-  hipLaunchKernelGGL(k_census_keys<R>, dim3(grid), dim3(256), 0, s, src, incl, n, cap, keys, vals,
-                     st);
+  const long long tiles = census_tiles(n > 0 ? n : 1);
+  hipLaunchKernelGGL(k_census_keys<R>, dim3((unsigned)tiles), dim3(256), 0, s, src, keep,
+                     tcount, tincl, n, cap, keys, vals, st);
   return hipGetLastError();
 }
-template hipError_t launch_census_keys<double>(const StageRec<double>*, const long long*,
-                                               long long, long long, uint32_t*, uint32_t*,
-                                               const DevState*, hipStream_t);
-template hipError_t launch_census_keys<float>(const StageRec<float>*, const long long*, long long,
+template hipError_t launch_census_keys<double>(const StageRec<double>*, const uint8_t*,
+                                               const long long*, const long long*, long long,
+                                               long long, uint32_t*, uint32_t*, const DevState*,
+                                               hipStream_t);
+template hipError_t launch_census_keys<float>(const StageRec<float>*, const uint8_t*,
+                                              const long long*, const long long*, long long,
                                               long long, uint32_t*, uint32_t*, const DevState*,
                                               hipStream_t);
 
@@ -905,8 +946,8 @@ template hipError_t launch_bank_cells<float>(const StageRec<float>*, long long, 
 
 // Census count and max |w| of the new bank (max over the compaction blocks),
 // and the end of the time step.
-__global__ __launch_bounds__(256) void k_census_finish(DevState* st, const long long* incl,
-                                                       long long n, long long cap,
+__global__ __launch_bounds__(256) void k_census_finish(DevState* st, const long long* tincl,
+                                                       long long n_tiles, long long cap,
                                                        const double* bmax, int nb) {
   if (st->halt) return;
   __shared__ double s_mx[4];
@@ -916,7 +957,7 @@ __global__ __launch_bounds__(256) void k_census_finish(DevState* st, const long 
   if (__lane_id() == 0) s_mx[threadIdx.x >> 6] = mx;
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const long long k = n > 0 ? incl[n - 1] : 0;
+  const long long k = n_tiles > 0 ? tincl[n_tiles - 1] : 0;
   st->thin_overflow = k > cap ? 1 : 0;
   st->n_in = k > cap ? cap : k;
   st->n_kept = st->n_in;
@@ -924,9 +965,9 @@ __global__ __launch_bounds__(256) void k_census_finish(DevState* st, const long 
   st->step += 1;  // end of the time step: the step counter that seeds the point streams
 }
 
-hipError_t launch_census_finish(DevState* st, const long long* incl, long long n,
+hipError_t launch_census_finish(DevState* st, const long long* tincl, long long n_tiles,
                                 long long cap, const double* bmax, hipStream_t s) {
-  hipLaunchKernelGGL(k_census_finish, dim3(1), dim3(256), 0, s, st, incl, n, cap, bmax,
+  hipLaunchKernelGGL(k_census_finish, dim3(1), dim3(256), 0, s, st, tincl, n_tiles, cap, bmax,
                      census_compact_blocks(cap));
   return hipGetLastError();
 }

@@ -585,6 +585,10 @@ struct slh_solver {
   int si_batch = 0;
   unsigned long long last_halted = ~0ull;  // step index of the last halted step
   int batch_run = 0;          // the batch of the step being enqueued
+  // conjugate-gradient steps launched per diffusion correction (adaptive, at
+  // most kDsaMaxIter; a correction they leave unfinished halts its step)
+  int cg_batch = 8;
+  int cg_run = 0;
   bool unsettled = false;     // steps enqueued since the last settle()
   unsigned long long restarts = 0ull;  // steps run again after a halt
   unsigned long long graph_launches = 0ull;
@@ -1043,9 +1047,10 @@ static slh_status enqueue_si(slh_solver* s, hipStream_t st, int n_it) {
       HIP_TRY(launch_dsa_start(c, s->sig_s, s->dnode, kDsaMaxIter, st));
       if (cg_one_block(z.n_cells)) {
         HIP_TRY(launch_cg_solve_one_block(c, kDsaTol, kDsaMaxIter, st));
-      } else {  // iterations past convergence return at once
-        for (int k = 0; k < kDsaMaxIter; ++k)
+      } else {  // steps past convergence return at once
+        for (int k = 0; k < s->cg_run; ++k)
           HIP_TRY(launch_cg_iteration(c, kDsaTol, kDsaMaxIter, st));
+        if (s->cg_run < kDsaMaxIter) HIP_TRY(launch_dsa_check(s->st, st));
       }
       HIP_TRY(launch_dsa_apply(d, s->cg_x, s->dg_part, s->n_part, s->si_tol, s->si_max, st));
     }
@@ -1197,7 +1202,7 @@ static bool capture(slh_solver* s, int first, int last, hipGraphExec_t* out) {
 // step, and the census-bank parity), or directly.
 static slh_status launch_parts(slh_solver* s, int first, int last, int key) {
   if (s->use_graphs) {
-    const auto k = std::make_tuple(key, s->cur, s->batch_run);
+    const auto k = std::make_tuple(key, s->cur, s->batch_run * 64 + s->cg_run);
     auto it = s->graphs.find(k);
     if (it == s->graphs.end()) {
       hipGraphExec_t e = nullptr;
@@ -1223,6 +1228,7 @@ static slh_status record(hipEvent_t e, hipStream_t st) {
 static slh_status run_step(slh_solver* s, int batch) {
   slh_status r;
   s->batch_run = batch;
+  s->cg_run = s->cg_batch;
   s->unsettled = true;
   if (!s->timing) {
     r = launch_parts(s, kA, kEnd, kWhole);
@@ -1498,13 +1504,18 @@ static slh_status settle(slh_solver* s, DevState* out = nullptr) {
     const int rb = d.step == s->last_halted ? s->si_max : restart_batch(d, s->si_tol, s->si_max);
     s->last_halted = d.step;
     s->si_batch = std::max(round_batch(2ll * s->si_batch, s->si_max), rb < s->si_max ? rb : 0);
+    s->cg_batch = kDsaMaxIter;  // the halt may have come from a correction
     HIP_TRY(hipMemsetAsync(&s->st->halt, 0, sizeof(int), s->stream));
     slh_status r = run_step(s, rb);
     for (long long k = 1; k < lost && r == SLH_OK; ++k) r = run_step(s, s->si_batch);
     if (r != SLH_OK) return r;
   }
-  if (s->unsettled && !s->skip_remap && d.si.iter > 0)
+  if (s->unsettled && !s->skip_remap && d.si.iter > 0) {
     s->si_batch = round_batch(d.si.iter + d.si.iter / 8 + 2, s->si_max);
+    if (d.dsa_iter_max > 0)  // a quarter more than the step's longest correction, plus two
+      s->cg_batch = std::min(kDsaMaxIter, round_batch(d.dsa_iter_max + d.dsa_iter_max / 4 + 2,
+                                                      kDsaMaxIter));
+  }
   s->unsettled = false;
   if (out) *out = d;
   return SLH_OK;

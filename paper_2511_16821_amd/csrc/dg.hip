@@ -73,6 +73,7 @@ __global__ void k_si_start(int nx, int ny, const double* __restrict__ sig_s,
     st->dsa_unconv = 0;
     st->dsa_corrections = 0;
     st->dsa_iter_total = 0;
+    st->dsa_iter_max = 0;
   }
   const double inv4pi = 0.25 / M_PI;
   const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -547,6 +548,18 @@ __global__ void k_si_check(DevState* st) {
   }
 }
 
+__global__ void k_dsa_check(DevState* st) {
+  if (threadIdx.x == 0 && !st->halt && !st->si.done && !st->dsa.done) {
+    st->halt = 1;
+    st->si.done = 1;
+  }
+}
+
+hipError_t launch_dsa_check(DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_dsa_check, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_si_check(DevState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_si_check, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
@@ -767,6 +780,7 @@ __global__ __launch_bounds__(256) void k_dg_residual(const double* partials, int
     if (dsa) {
       st->dsa_corrections += 1;
       st->dsa_iter_total += st->dsa.iter;
+      if (st->dsa.iter > st->dsa_iter_max) st->dsa_iter_max = st->dsa.iter;
       if (!st->dsa.conv) st->dsa_unconv += 1;
     }
   }

@@ -319,7 +319,7 @@ struct DevState {
   int dsa_unconv;
   int dsa_corrections;
   int dsa_iter_total;
-  int pad1;
+  int dsa_iter_max;  // most conjugate-gradient iterations of one correction
   // totals since creation (or a checkpoint load), kept on the device so that
   // steps need no host round trip: segments of each pass kind, census-in
   // particles (each step's bank), census candidates written, histories
@@ -507,6 +507,11 @@ hipError_t launch_si_start(const DgArgs& a, int si_max, hipStream_t s);
 // After a batch of source iterations: if the iteration has not stopped, the
 // step halts (DevState::halt, and si.done so that no later iteration runs).
 hipError_t launch_si_check(DevState* st, hipStream_t s);
+// After a diffusion correction whose conjugate gradients were launched for
+// fewer steps than their limit: a correction the steps left unfinished halts
+// the step (it runs again with the full limit), as a short batch of source
+// iterations does.
+hipError_t launch_dsa_check(DevState* st, hipStream_t s);
 // Diffusion synthetic acceleration: after the correction delta (per cell) is
 // solved, phi += delta at every node, the next iterate's source, and the
 // residual of phi^{k+1} - phi^k = dnode + delta, decided as after a plain

@@ -36,7 +36,7 @@ def _run_pair(S, oracle, p, steps, name):
         assert st["si_iterations"] == r["si_iters"], (st["si_iterations"], r["si_iters"])
         assert st["segments_total"] == r["segments"], (st["segments_total"], r["segments"])
         assert st["census_kept"] == r["census_kept"]
-        log("  step", k, "sweeps", st["si_iterations"],
+        log("  step", k, "sweeps", st["si_iterations"], "restarts", st["si_restarts_total"],
             {kk: "%.1e" % v[0] for kk, v in errs.items()})
     s.destroy()
 
@@ -62,9 +62,12 @@ def test_dsa_time_steps(S, oracle):
 
 
 def test_dsa_large_mesh(S, oracle):
-    """Above 4096 cells each correction runs as a fixed number of predicated
-    three-kernel CG steps: the random-block subproblem (128 x 128, 1024
-    materials, N_s = 3), two steps."""
+    """Above 4096 cells each correction runs as predicated three-kernel CG
+    steps, as many as the last step's longest correction needed (eight at
+    first): a correction they leave unfinished halts the step, which runs
+    again with the limit of 32, so the results are those of 32 blind steps.
+    The random-block subproblem (128 x 128, 1024 materials, N_s = 3), two
+    steps."""
     from paper_2511_16821_amd import workloads as W
     _run_pair(S, oracle, W.c5_subproblem(n_particles=20000, sn_order=8), 2, "random blocks")
 
@@ -97,7 +100,7 @@ def test_dsa_full_mesh_matches_plain_iteration(S):
         acc.advance(1)
         sp, sa = plain.get_stats(), acc.get_stats()
         log("step", k, "sweeps plain", sp["si_iterations"], "with DSA", sa["si_iterations"],
-            "CG iterations", sa["dsa_iterations"])
+            "CG iterations", sa["dsa_iterations"], "restarts", sa["si_restarts_total"])
         assert sa["si_converged"] == 1 and sp["si_converged"] == 1
         assert sa["dsa_unconverged"] == 0 and sa["dsa_corrections"] == sa["si_iterations"]
         assert sa["si_iterations"] < sp["si_iterations"]

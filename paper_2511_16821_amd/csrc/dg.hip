@@ -502,7 +502,12 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
           b_out[2 * ny + 2 * ci + 1] = bpos ? x3 : x1;
         }
       }
-      out[c_pos[r] - lay_base] = make_double4(x0, x1, x2, x3);
+      // the plane is read once, by the direction sum: non-temporal stores
+      double* po = reinterpret_cast<double*>(out + (c_pos[r] - lay_base));
+      __builtin_nontemporal_store(x0, po);
+      __builtin_nontemporal_store(x1, po + 1);
+      __builtin_nontemporal_store(x2, po + 2);
+      __builtin_nontemporal_store(x3, po + 3);
     }
     prepare((k + 1) & 1);
   }
@@ -628,8 +633,11 @@ __global__ __launch_bounds__(kRedBlock) void k_dg_famsum(
     for (; u + 16 <= u1; u += 16) {
       double2 t[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e)
-        t[e] = reinterpret_cast<const double2*>(psi + (long long)fam_dirs[u + e] * n_nodes)[k];
+      for (int e = 0; e < 16; ++e) {  // read once: non-temporal loads
+        const double* pp = psi + (long long)fam_dirs[u + e] * n_nodes + 2 * k;
+        t[e].x = __builtin_nontemporal_load(pp);
+        t[e].y = __builtin_nontemporal_load(pp + 1);
+      }
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const double w = dir[3 * fam_dirs[u + e] + 2];

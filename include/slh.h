@@ -365,15 +365,21 @@ slh_status slh_create_static(const slh_problem *problem, void *hip_stream, slh_s
  * si_max_iter); a step whose batch ends before its iteration stops itself
  * and every step enqueued after it on the device, and the next call that
  * waits for the stream (slh_synchronize, slh_get_*, slh_save, slh_load) runs
- * them again, the stopped one with si_max_iter iterations and the others
- * with a doubled batch.  Results do not depend on the batch.  The outcome of
- * the steps (convergence, numeric faults) is reported by slh_synchronize.
- * Returns SLH_E_DEVICE if a launch fails. */
+ * them again, the stopped one with the iterations it did plus an estimate of
+ * the rest from its contraction rate (si_max_iter without an estimate or
+ * when it stops again) and the others with a doubled batch.  With DSA on
+ * meshes above 4096 cells the conjugate-gradient steps of each correction
+ * are batched the same way (a quarter more than the last step's longest
+ * correction, plus two; a correction left unfinished stops the step, which
+ * runs again with the limit of 32).  Results do not depend on the batches.
+ * The outcome of the steps (convergence, numeric faults) is reported by
+ * slh_synchronize.  Returns SLH_E_DEVICE if a launch fails. */
 slh_status slh_advance(slh_solver *s, int32_t n_steps);
 
 /* Sets the batch of source iterations of the next steps (n >= 1, at most
- * si_max_iter); the adaptive rule of slh_advance takes over after the next
- * wait.  For tuning and tests; results do not depend on it. */
+ * si_max_iter), and that of conjugate-gradient steps per diffusion
+ * correction to n (at most 32); the adaptive rules of slh_advance take over
+ * after the next wait.  For tuning and tests; results do not depend on it. */
 slh_status slh_set_si_batch(slh_solver *s, int32_t n);
 
 /* enable != 0 (the default): each step is launched as a HIP graph; 0: every

@@ -587,7 +587,7 @@ struct slh_solver {
   int batch_run = 0;          // the batch of the step being enqueued
   // conjugate-gradient steps launched per diffusion correction (adaptive, at
   // most kDsaMaxIter; a correction they leave unfinished halts its step)
-  int cg_batch = 8;
+  int cg_batch = 16;
   int cg_run = 0;
   bool unsettled = false;     // steps enqueued since the last settle()
   unsigned long long restarts = 0ull;  // steps run again after a halt
@@ -1408,13 +1408,15 @@ static slh_status create_solver(const slh_problem* problem, void* hip_stream, sl
   s->thin_margin = (long long)ceil(4.0 * sqrt((double)s->z.cap)) + 16;
   // first batch of source iterations per step: for the plain iteration the
   // count at which the largest scattering ratio c = sigma_s / sigma_e, its
-  // worst-case contraction, reaches the tolerance; 8 with the diffusion
-  // correction, 64 conjugate-gradient steps for the diffusion closing stage
-  // (the batch adapts once the first steps are settled)
+  // worst-case contraction, reaches the tolerance; 16 with the diffusion
+  // correction (and 16 CG steps per correction), 64 conjugate-gradient steps
+  // for the diffusion closing stage (the batches adapt once the first steps
+  // are settled; a batch too short costs a rerun of the step, one too long
+  // only launches that return at once)
   if (s->z.diffusion) {
     s->si_batch = round_batch(64, s->si_max);
   } else if (s->z.dsa) {
-    s->si_batch = round_batch(8, s->si_max);
+    s->si_batch = round_batch(16, s->si_max);
   } else {
     double c = 0.0;
     const double tt = time_term(problem);
@@ -1525,6 +1527,7 @@ extern "C" slh_status slh_set_si_batch(slh_solver* s, int32_t n) {
   if (!s) return fail(SLH_E_INVALID_ARG, "solver is NULL");
   if (n < 1) return fail(SLH_E_INVALID_ARG, "the batch must be >= 1");
   s->si_batch = n < s->si_max ? n : s->si_max;
+  s->cg_batch = n < kDsaMaxIter ? n : kDsaMaxIter;
   return SLH_OK;
 }
 

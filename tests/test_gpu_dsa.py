@@ -63,7 +63,7 @@ def test_dsa_time_steps(S, oracle):
 
 def test_dsa_large_mesh(S, oracle):
     """Above 4096 cells each correction runs as predicated three-kernel CG
-    steps, as many as the last step's longest correction needed (eight at
+    steps, as many as the last step's longest correction needed (16 at
     first): a correction they leave unfinished halts the step, which runs
     again with the limit of 32, so the results are those of 32 blind steps.
     The random-block subproblem (128 x 128, 1024 materials, N_s = 3), two
@@ -110,3 +110,43 @@ def test_dsa_full_mesh_matches_plain_iteration(S):
             assert e <= tol, (k, which, e)
     plain.destroy()
     acc.destroy()
+
+
+def test_dsa_short_cg_batches_run_again(S):
+    """Corrections whose batch of CG steps is shorter than the correction
+    (batches of one and four, then the adaptive rule) halt their step on the
+    device, which runs again with the limit: fluxes, census bank, balances
+    and iteration counts are bitwise those of the default batches.  The
+    random-block subproblem above 4096 cells (128 x 128, N_s = 3), three
+    steps."""
+    from paper_2511_16821_amd import workloads as W
+    p = dict(W.c5_subproblem(n_particles=20000, sn_order=8), si_accel=1)
+
+    def run(batch):
+        s = S.Solver(p)
+        if batch:
+            s.set_si_batch(batch)
+        s.advance(3)
+        assert s.synchronize() == S.SLH_OK
+        return s
+
+    ref = run(0)
+    rs = ref.get_stats()
+    for batch in (1, 4):
+        a = run(batch)
+        st = a.get_stats()
+        log("first batch", batch, "restarts", st["si_restarts_total"], "sweeps",
+            st["si_iterations"], "CG iterations", st["dsa_iterations"])
+        assert st["si_restarts_total"] >= 1
+        for which in (S.SLH_FLUX_REMAP, S.SLH_FLUX_PRE, S.SLH_FLUX_POST,
+                      S.SLH_FLUX_COLLIDED_NODAL):
+            assert np.array_equal(a.get_flux(which), ref.get_flux(which)), which
+        ca, cr = a.get_census(), ref.get_census()
+        for f in cr:
+            assert np.array_equal(ca[f], cr[f]), f
+        for pss in (1, 2):
+            assert a.get_balance(pss) == ref.get_balance(pss)
+        for k in ("si_iterations", "dsa_iterations", "dsa_corrections", "segments_total"):
+            assert st[k] == rs[k], k
+        a.destroy()
+    ref.destroy()

@@ -6,13 +6,16 @@
 // pass.
 //
 // Execution model: a persistent grid sized to the device's occupancy.  Every
-// lane owns one history at a time and, when it ends, takes its next work index
-// from a fixed stride (lane t of T takes t, t + T, ...), so lanes refill
-// without waiting for the slowest history of their wave and without any
-// shared counter.  The work index g maps to census particle g (g < n_in) or
-// source particle g - n_in; every random number of a history is a pure function of its
-// (stream, dimension, point index), so results do not depend on which lane or
-// wave ran it.  Tallies and balance sums are fixed point with integer atomics
+// lane owns one history at a time and, when it ends, takes the next work
+// index of its wave's chunk of kWorkChunk consecutive indices; a wave whose
+// chunk is used up takes the next chunk from the pass's counter.  Lanes
+// refill without waiting for the slowest history of their wave, the chunks
+// balance the load over the waves, and the histories of a wave start close
+// together (the work index follows the cell order of the banks), so their
+// material reads and tally adds meet in the caches.  The work index g maps to
+// census particle g (g < n_in) or source particle g - n_in; every random
+// number of a history is a pure function of its (stream, dimension, point
+// index), so results do not depend on which lane or wave ran it.  Tallies and balance sums are fixed point with integer atomics
 // and are therefore independent of the schedule.  Each lane adds into one of
 // several private copies of the tally (summed afterwards), through a small
 // cache of tally words per wave in LDS, so that simultaneous updates of a busy
@@ -167,6 +170,10 @@ __device__ __forceinline__ void tally_add(unsigned long long* p, unsigned long l
   if (xl) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   else atomicAdd(p, v);
 }
+
+// Work indices handed to a wave at a time (on the 1024x1024 solve 1024 gave
+// the shortest passes: 64 queue on the counter, 16384 balance worse).
+constexpr long long kWorkChunk = 1024;
 
 // Tally-word cache of a wave in LDS: kTcSlots slots of (word address, pending
 // sum).  A lane's add goes to the slot its word hashes to: into the slot's
@@ -335,8 +342,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
   bool have = false;
   const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long t_all = (long long)gridDim.x * blockDim.x;
-  long long next = gtid;
+  long long q_next = 0, q_end = 0;  // the wave's current chunk of work indices (uniform)
+  bool q_done = false;              // the pass's counter has passed the last index
   // tally copy of this lane: within the copies of the workgroup's XCD when
   // the copies are XCD-local (the hardware XCC id, not the dispatch order,
   // decides which L2 resolves the adds)
@@ -380,10 +387,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   };
 
   for (;;) {
-    // static work assignment: lane t of T takes work items t, t + T, t + 2T, ...
-    if (!have && next < (long long)n_tot) {
-      g = next;
-      next += t_all;
+    // idle lanes take the next indices of the wave's chunk, in lane order; a
+    // used-up chunk is replaced by the next one of the pass's counter
+    bool fresh = false;
+    if (__any(!have)) {
+      if (q_next >= q_end && !q_done) {
+        unsigned long long base = 0ull;
+        if (lane == 0) base = atomicAdd(&st->work, (unsigned long long)kWorkChunk);
+        base = (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)base) |
+               ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                    (int)(unsigned)(base >> 32)) << 32);
+        q_next = base < n_tot ? (long long)base : (long long)n_tot;
+        q_end = base + kWorkChunk < n_tot ? (long long)(base + kWorkChunk) : (long long)n_tot;
+        q_done = base + kWorkChunk >= n_tot;
+      }
+      const unsigned long long need = __ballot(!have);
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+      const long long avail = q_end - q_next;
+      if (!have && (long long)rank < avail) {
+        g = q_next + rank;
+        fresh = true;
+      }
+      q_next += (long long)__popcll(need) < avail ? (long long)__popcll(need) : avail;
+    }
+    if (fresh) {
       have = true;
       lane_hist++;
       seg_p = 0;

@@ -467,10 +467,18 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
         x[r][2] = r0[r][2] + Pr[8] * u0 + Pr[9] * u1 + Pr[10] * u2 + Pr[11] * u3;
         x[r][3] = r0[r][3] + Pr[12] * u0 + Pr[13] * u1 + Pr[14] * u2 + Pr[15] * u3;
       } else {
-        double y0 = r0[r][0] + dmF[0] * u0 + dmF[1] * u1 + dmF[2] * u2 + dmF[3] * u3;
-        double y1 = r0[r][1] + dmF[4] * u0 + dmF[5] * u1 + dmF[6] * u2 + dmF[7] * u3;
-        double y2 = r0[r][2] + dmF[8] * u0 + dmF[9] * u1 + dmF[10] * u2 + dmF[11] * u3;
-        double y3 = r0[r][3] + dmF[12] * u0 + dmF[13] * u1 + dmF[14] * u2 + dmF[15] * u3;
+        // F couples node (kx, ky) to the x-face traces only when kx is the
+        // inflow column and to the y-face traces only when ky is the inflow
+        // row: the other half of its entries are zero and are skipped
+        double yv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          double acc = r0[r][e];
+          if ((e & 1) == (apos ? 0 : 1)) acc = acc + dmF[4 * e] * u0 + dmF[4 * e + 1] * u1;
+          if ((e >> 1) == (bpos ? 0 : 1)) acc = acc + dmF[4 * e + 2] * u2 + dmF[4 * e + 3] * u3;
+          yv[e] = acc;
+        }
+        double y0 = yv[0], y1 = yv[1], y2 = yv[2], y3 = yv[3];
         y1 -= Pr[4] * y0;
         y2 -= Pr[5] * y0 + Pr[7] * y1;
         y3 -= Pr[6] * y0 + Pr[8] * y1 + Pr[9] * y2;

@@ -396,7 +396,7 @@ static Sizes sizes_of(const slh_problem* p) {
   b += (size_t)z.n_dir * 24 + 1024 * 16 + 4096;
   b += (size_t)z.cap * bank * 2;             // census banks
   b += (size_t)(z.n_src_cap > 0 ? z.n_src_cap : 1) * srec;  // source bank
-  b += (size_t)z.n_cand * ((z.fp32 ? 32 : 64) + 1);  // staging, alive
+  b += (size_t)z.n_cand * ((z.fp32 ? 32 : 64) + 1 + 4);  // staging, alive, kept cells
   b += (size_t)census_tiles(z.n_cand) * 16;          // tile counts and their scan
   b += std::max(scan_tmp_elems(census_tiles(z.n_cand)),
                 scan_tmp_elems((long long)radix_hist_elems(z.cap))) * 8;
@@ -558,6 +558,7 @@ struct slh_solver {
   void* stage_mem = nullptr;
   void* src_mem = nullptr;  // source bank of the current pass
   uint8_t* alive = nullptr;
+  int32_t* kcell = nullptr;  // cell of each kept candidate
   long long *tcount = nullptr, *tincl = nullptr, *scan_i = nullptr;
   // census ordering: (cell, slot) pairs and their sort buffers, the radix
   // histograms, cohort starts per cell, and each bank's cohort ranks
@@ -733,6 +734,7 @@ static slh_status setup(slh_solver* s) {
                                 "the allocator returned memory not aligned to 256 bytes: banks")
                          : fail(SLH_E_OUT_OF_MEMORY, "device allocation failed: census banks");
   ALLOC(s->alive, uint8_t, z.n_cand);
+  ALLOC(s->kcell, int32_t, z.n_cand);
   ALLOC(s->tcount, long long, census_tiles(z.n_cand));
   ALLOC(s->tincl, long long, census_tiles(z.n_cand));
   ALLOC(s->scan_i, long long, std::max(scan_tmp_elems(census_tiles(z.n_cand)),
@@ -1136,19 +1138,15 @@ static slh_status enqueue_part(slh_solver* s, int part, hipStream_t st) {
       const long long tiles = census_tiles(z.n_cand);
       const long long* last = s->tincl + (tiles - 1);
       const int odd = radix_passes(nc) & 1;  // the sorted pairs end in buffer odd
-      if (z.fp32) {
-        const StageRec<float>* src = (const StageRec<float>*)s->stage_mem;
-        HIP_TRY(launch_census_keep(s->alive, src, z.n_cand, p.seed, s->st, s->tcount, st));
-        HIP_TRY(scan_inclusive_i64(s->tcount, s->tincl, tiles, s->scan_i, &s->st->halt, st));
-        HIP_TRY(launch_census_keys<float>(src, s->alive, s->tcount, s->tincl, z.n_cand, z.cap,
-                                          s->skey[0], s->sval[0], s->st, st));
-      } else {
-        const StageRec<double>* src = (const StageRec<double>*)s->stage_mem;
-        HIP_TRY(launch_census_keep(s->alive, src, z.n_cand, p.seed, s->st, s->tcount, st));
-        HIP_TRY(scan_inclusive_i64(s->tcount, s->tincl, tiles, s->scan_i, &s->st->halt, st));
-        HIP_TRY(launch_census_keys<double>(src, s->alive, s->tcount, s->tincl, z.n_cand, z.cap,
-                                           s->skey[0], s->sval[0], s->st, st));
-      }
+      if (z.fp32)
+        HIP_TRY(launch_census_keep(s->alive, (const StageRec<float>*)s->stage_mem, z.n_cand,
+                                   p.seed, s->st, s->tcount, s->kcell, st));
+      else
+        HIP_TRY(launch_census_keep(s->alive, (const StageRec<double>*)s->stage_mem, z.n_cand,
+                                   p.seed, s->st, s->tcount, s->kcell, st));
+      HIP_TRY(scan_inclusive_i64(s->tcount, s->tincl, tiles, s->scan_i, &s->st->halt, st));
+      HIP_TRY(launch_census_keys(s->kcell, s->alive, s->tcount, s->tincl, z.n_cand, z.cap,
+                                 s->skey[0], s->sval[0], s->st, st));
       HIP_TRY(radix_sort_pairs(s->skey[0], s->sval[0], s->skey[1], s->sval[1], last, z.cap, nc,
                                s->rhist, s->rincl, s->scan_i, s->st, st));
       if (z.fp32)

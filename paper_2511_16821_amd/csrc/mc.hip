@@ -122,23 +122,23 @@ __device__ __forceinline__ double bilinear(const double* q, double a, double b) 
 // left count, else subtracting it and going right.  Particles are numbered
 // in cell order, so this finds the cell j with P_j <= s < P_j + n_j
 // (P_j = counts of the cells before j), and l = s - P_j.  A thread descends
-// kPickLanes particles' paths together, one level at a time, so that their
-// loads of the lower levels (from global memory) are in flight at once.
+// NP particles' paths together, one level at a time, so that their loads of
+// the lower levels (from global memory) are in flight at once.
 constexpr int kTreeTop = 1024;  // nodes [0, kTreeTop) of the tree are staged in LDS
-constexpr int kPickLanes = 4;
 
 struct CellPick {
   long long cell;
   uint32_t l;
 };
 
+template <int NP>
 __device__ __forceinline__ void count_pick_n(const double* __restrict__ t,
                                              const double* __restrict__ top, long long L,
                                              const long long* s, CellPick* out) {
-  double target[kPickLanes];
-  long long k[kPickLanes];
+  double target[NP];
+  long long k[NP];
 #pragma unroll
-  for (int j = 0; j < kPickLanes; ++j) {
+  for (int j = 0; j < NP; ++j) {
     target[j] = (double)s[j] + 0.5;
     k[j] = 1;
   }
@@ -146,13 +146,13 @@ __device__ __forceinline__ void count_pick_n(const double* __restrict__ t,
   // in LDS or all in global memory
   for (long long lev = 1; lev < L; lev <<= 1) {
     const bool in_lds = 4 * lev <= kTreeTop;
-    double2 lr[kPickLanes];
+    double2 lr[NP];
 #pragma unroll
-    for (int j = 0; j < kPickLanes; ++j)
+    for (int j = 0; j < NP; ++j)
       lr[j] = in_lds ? make_double2(top[2 * k[j]], top[2 * k[j] + 1])
                      : reinterpret_cast<const double2*>(t)[k[j]];
 #pragma unroll
-    for (int j = 0; j < kPickLanes; ++j) {
+    for (int j = 0; j < NP; ++j) {
       if (target[j] < lr[j].x || lr[j].y == 0.0) {  // (an empty right subtree is never reached)
         k[j] = 2 * k[j];
       } else {
@@ -162,7 +162,7 @@ __device__ __forceinline__ void count_pick_n(const double* __restrict__ t,
     }
   }
 #pragma unroll
-  for (int j = 0; j < kPickLanes; ++j)
+  for (int j = 0; j < NP; ++j)
     out[j] = CellPick{k[j] - L, (uint32_t)target[j]};  // target = s - P_j + 1/2
 }
 
@@ -212,17 +212,25 @@ __device__ __forceinline__ void bal_add(unsigned long long* bal, int f, double v
   atomicAdd(&bal[2 * f + 1], (unsigned long long)lo);
 }
 
-// Emission of the pass's source particles, one thread each (Sec. 2.3: birth
-// proportional to q, isotropic direction, weights that integrate q in
-// expectation), stratified by cell: cell j emits the n_j particles of the
-// emission plan (floor(r_j) or floor(r_j) + 1, E[n_j] = r_j = M_j / w_q),
-// numbered in cell order.  Particle l of cell j takes its points from the
-// cell's stream at index l: position (dims 0-1), birth time (dim 2),
-// direction (dims 3-4, sincospi), the first optical depth (dim 5) when the
-// pass allows scatters, and weight w_q q(x,y) / qbar_j, qbar_j the cell's
-// power-of-two majorant of |q| (so |w| <= w_q; the expected weight of the
-// cell is r_j w_q mean(q) / qbar_j = A dt mean(q), or A mean(q) per unit
-// time in steady state, where every particle starts at time 0).
+// Emission of the pass's source particles (Sec. 2.3: birth proportional to
+// q, isotropic direction, weights that integrate q in expectation),
+// stratified by cell: cell j emits the n_j particles of the emission plan
+// (floor(r_j) or floor(r_j) + 1, E[n_j] = r_j = M_j / w_q), numbered in cell
+// order.  Particle l of cell j takes its points from the cell's stream at
+// index l: position (dims 0-1), birth time (dim 2), direction (dims 3-4,
+// sincospi), the first optical depth (dim 5) when the pass allows scatters,
+// and weight w_q q(x,y) / qbar_j, qbar_j the cell's power-of-two majorant of
+// |q| (so |w| <= w_q; the expected weight of the cell is r_j w_q mean(q) /
+// qbar_j = A dt mean(q), or A mean(q) per unit time in steady state, where
+// every particle starts at time 0).
+//
+// A thread emits runs of kEmitRun consecutive particles.  With tens of
+// particles per cell a run nearly always lies in one emitter: the descents of
+// its first and last particles then show it, and the emitter's stream and
+// per-dimension scramble seeds are computed once for the run.  A run that
+// spans emitters descends the tree for each of its inner particles.
+constexpr int kEmitRun = 8;
+
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   if (a.st->halt) return;
@@ -241,32 +249,40 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   const R hx = (R)a.hx, hy = (R)a.hy, dt_birth = (R)a.dt_birth;
   SrcRec<R>* const b = Real<R>::src(a);
   const long long T = (long long)gridDim.x * blockDim.x;
-  for (long long s0 = (long long)blockIdx.x * blockDim.x + threadIdx.x; s0 < n_emit;
-       s0 += kPickLanes * T) {
-    long long sj[kPickLanes];
-    CellPick pk[kPickLanes];
-#pragma unroll
-    for (int j = 0; j < kPickLanes; ++j) {
-      const long long v = s0 + j * T;
-      sj[j] = v < n_emit ? v : s0;  // past the end: a valid particle, not emitted
-    }
-    count_pick_n(a.ctree, s_top, a.tree_L, sj, pk);
+  for (long long r0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * kEmitRun;
+       r0 < n_emit; r0 += kEmitRun * T) {
+    const long long r1 = (r0 + kEmitRun < n_emit ? r0 + kEmitRun : n_emit) - 1;
+    long long sj[2] = {r0, r1};
+    CellPick pk[2];
+    count_pick_n<2>(a.ctree, s_top, a.tree_L, sj, pk);
+    const bool one = pk[0].cell == pk[1].cell;
+    long long cur = -1;  // the emitter whose stream and seeds are held
+    uint64_t stream = 0;
+    uint32_t sd[6];
 #pragma unroll 1
-    for (int j = 0; j < kPickLanes; ++j) {
-      const long long s = s0 + j * T;
-      if (s >= n_emit) break;
-      const long long ci = pk[j].cell;  // the emitter: a cell, or a boundary face after them
-      const uint32_t l = pk[j].l;
-      const uint64_t stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, (uint64_t)ci);
-      const R u1 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 0u, l));
-      const R u2 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 1u, l));
-      const R u3 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 2u, l));
-      const R u4 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 3u, l));
+    for (long long s = r0; s <= r1; ++s) {
+      CellPick pc;
+      if (one) pc = CellPick{pk[0].cell, pk[0].l + (uint32_t)(s - r0)};
+      else if (s == r0) pc = pk[0];
+      else if (s == r1) pc = pk[1];
+      else count_pick_n<1>(a.ctree, s_top, a.tree_L, &s, &pc);
+      const long long ci = pc.cell;  // the emitter: a cell, or a boundary face after them
+      const uint32_t l = pc.l;
+      if (ci != cur) {
+        cur = ci;
+        stream = stream_seed(a.seed, step, (uint32_t)KIND, 0u, (uint64_t)ci);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) sd[d] = point_seed(stream, (uint32_t)d);
+      }
+      const R u1 = PointU<R>::u(point_u32s(s_sobol, a.points, stream, sd[0], 0u, l));
+      const R u2 = PointU<R>::u(point_u32s(s_sobol, a.points, stream, sd[1], 1u, l));
+      const R u3 = PointU<R>::u(point_u32s(s_sobol, a.points, stream, sd[2], 2u, l));
+      const R u4 = PointU<R>::u(point_u32s(s_sobol, a.points, stream, sd[3], 3u, l));
       const R tau = a.n_lim > 0
-                        ? -log(PointU<R>::u(point_u32n(s_sobol, a.points, stream, 5u, l)))
+                        ? -log(PointU<R>::u(point_u32s(s_sobol, a.points, stream, sd[5], 5u, l)))
                         : (R)0;
       if (ci < a.n_cells) {
-        const R u5 = PointU<R>::u(point_u32n(s_sobol, a.points, stream, 4u, l));
+        const R u5 = PointU<R>::u(point_u32s(s_sobol, a.points, stream, sd[4], 4u, l));
         const R sn = (R)2 * sqrt(u4 * ((R)1 - u4));
         R sp, cp;
         Real<R>::scpi((R)2 * u5, &sp, &cp);
@@ -700,9 +716,9 @@ int mc_pass_grid(bool fp32, int kind, long long max_work) {
 hipError_t launch_emit(const PassArgs& a, bool fp32, hipStream_t s) {
   if (a.n_src <= 0) return hipSuccess;
   // at most 2048 blocks (each block first stages 24 KB of tables in LDS, six
-  // blocks fit a compute unit); a thread takes its particles kPickLanes at a
+  // blocks fit a compute unit); a thread takes its particles kEmitRun at a
   // time
-  long long b = (a.n_src + 255) / 256;
+  long long b = (a.n_src + 256 * kEmitRun - 1) / (256 * kEmitRun);
   const int grid = (int)(b < 2048 ? b : 2048);
   if (a.kind == 1) {
     if (fp32) hipLaunchKernelGGL((k_emit<float, 1>), dim3(grid), dim3(256), 0, s, a);

@@ -115,6 +115,22 @@ __device__ __forceinline__ uint32_t point_u32n(const uint32_t* N, int mode, uint
   return (uint32_t)(mix64(stream ^ mix64(ctr)) >> 32);
 }
 
+// The same point with the scramble seed (Sobol') or shift (Halton) of
+// (stream, dim) given, point_seed(stream, dim): every point of a stream and
+// dimension shares it, so a caller that takes several points of one stream
+// computes it once.
+__device__ __forceinline__ uint32_t point_seed(uint64_t stream, uint32_t dim) {
+  return (uint32_t)(mix64(stream + dim) >> 32);
+}
+__device__ __forceinline__ uint32_t point_u32s(const uint32_t* N, int mode, uint64_t stream,
+                                               uint32_t seed, uint32_t dim, uint32_t index) {
+  if (mode == 0 && dim < (uint32_t)kSobolDims)
+    return nested_scramble(sobol_word_nib(N, dim, index), seed);
+  if (mode == 2 && dim < (uint32_t)kHaltonDims) return halton_u32(dim, index) + seed;
+  const uint64_t ctr = ((uint64_t)dim << 32) | (uint64_t)index;
+  return (uint32_t)(mix64(stream ^ mix64(ctr)) >> 32);
+}
+
 // Smallest power of two >= v (v > 0), 0 for v = 0: the majorant of |q| in a
 // cell is its largest corner value rounded up this way.
 __host__ __device__ __forceinline__ double pow2_ceil(double v) {
@@ -610,21 +626,21 @@ hipError_t launch_thin_params(DevState* st, long long cap, long long margin, hip
 // count of each tile (tcount, census_tiles(n) entries).
 constexpr int kKeepTile = 4096;
 long long census_tiles(long long n);
+// It also copies each kept candidate's cell into cell (n entries; 0 for the
+// others), read by the ordering keys in place of the records.
 template <typename R>
 hipError_t launch_census_keep(uint8_t* alive, const StageRec<R>* stage, long long n,
                               uint64_t seed, const DevState* st, long long* tcount,
-                              hipStream_t s);
+                              int32_t* cell, hipStream_t s);
 // The census bank at t_{n+1} (kept candidates, first cap in slot order,
 // ordered by cell and within a cell by slot): (cell, slot) pairs of the kept
 // candidates in slot order, then radix_sort_pairs by cell, then the gather of
 // the records (weights times the thinning factor).  tincl: the inclusive
 // scan of the tile counts, whose last entry (the kept total) bounds the count
 // with cap.
-template <typename R>
-hipError_t launch_census_keys(const StageRec<R>* src, const uint8_t* keep,
-                              const long long* tcount, const long long* tincl, long long n,
-                              long long cap, uint32_t* keys, uint32_t* vals, const DevState* st,
-                              hipStream_t s);
+hipError_t launch_census_keys(const int32_t* cell, const uint8_t* keep, const long long* tcount,
+                              const long long* tincl, long long n, long long cap, uint32_t* keys,
+                              uint32_t* vals, const DevState* st, hipStream_t s);
 long long radix_tiles(long long n);
 int radix_passes(long long n_keys_max);
 size_t radix_hist_elems(long long cap);

@@ -596,13 +596,17 @@ long long census_tiles(long long n) { return (n + kKeepTile - 1) / kKeepTile; }
 
 // One tile of kKeepTile candidates per block, read in rounds of 256 (slot
 // base + r 256 + t in round r, thread t): each candidate's keep decision in
-// place of its alive byte, and the tile's kept count.
+// place of its alive byte, the tile's kept count, and the cell of each kept
+// candidate in a plain array (history id and cell share a 32-byte sector of
+// the record, so the copy costs no extra read, and the ordering keys then
+// read 4 bytes a slot instead of the records).
 template <typename R>
 __global__ __launch_bounds__(256) void k_census_keep(uint8_t* __restrict__ alive,
                                                      const StageRec<R>* __restrict__ stage,
                                                      long long n, uint64_t seed,
                                                      const DevState* st,
-                                                     long long* __restrict__ tcount) {
+                                                     long long* __restrict__ tcount,
+                                                     int32_t* __restrict__ cell) {
   if (st->halt) return;
   __shared__ int s_c[4];
   // the thinning keys' stream: (step, pass 2, population 2)
@@ -616,12 +620,17 @@ __global__ __launch_bounds__(256) void k_census_keep(uint8_t* __restrict__ alive
     const long long i = base + r * 256 + threadIdx.x;
     if (i >= n) break;
     int f = alive[i] ? 1 : 0;
-    if (f && act) {
-      const unsigned long long key = mix64(thin_stream ^ stage[i].hid);
-      const unsigned long long top = rs >= 64 ? 0ull : (key >> rs);
-      f = top < mant ? 1 : 0;
-      alive[i] = (uint8_t)f;
+    int c = 0;
+    if (f) {
+      c = stage[i].cell;
+      if (act) {
+        const unsigned long long key = mix64(thin_stream ^ stage[i].hid);
+        const unsigned long long top = rs >= 64 ? 0ull : (key >> rs);
+        f = top < mant ? 1 : 0;
+        alive[i] = (uint8_t)f;
+      }
     }
+    cell[i] = f ? c : 0;
     cnt += f;
   }
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
@@ -633,17 +642,17 @@ __global__ __launch_bounds__(256) void k_census_keep(uint8_t* __restrict__ alive
 template <typename R>
 hipError_t launch_census_keep(uint8_t* alive, const StageRec<R>* stage, long long n,
                               uint64_t seed, const DevState* st, long long* tcount,
-                              hipStream_t s) {
+                              int32_t* cell, hipStream_t s) {
   const long long tiles = census_tiles(n > 0 ? n : 1);
   hipLaunchKernelGGL(k_census_keep<R>, dim3((unsigned)tiles), dim3(256), 0, s, alive, stage, n,
-                     seed, st, tcount);
+                     seed, st, tcount, cell);
   return hipGetLastError();
 }
 template hipError_t launch_census_keep<double>(uint8_t*, const StageRec<double>*, long long,
-                                               uint64_t, const DevState*, long long*,
+                                               uint64_t, const DevState*, long long*, int32_t*,
                                                hipStream_t);
 template hipError_t launch_census_keep<float>(uint8_t*, const StageRec<float>*, long long,
-                                              uint64_t, const DevState*, long long*,
+                                              uint64_t, const DevState*, long long*, int32_t*,
                                               hipStream_t);
 
 // ---------------------------------------------------------------------------
@@ -662,9 +671,9 @@ __device__ __forceinline__ long long census_count(const long long* incl_last, lo
 
 // The tile's kept candidates, in slot order, at their places among all kept
 // ones (the kept of earlier tiles first; rounds in order, the waves of a
-// round in order, lanes in order), the first cap of them only.
-template <typename R>
-__global__ __launch_bounds__(256) void k_census_keys(const StageRec<R>* __restrict__ src,
+// round in order, lanes in order), the first cap of them only; their cells
+// come from the array the keep decisions left.
+__global__ __launch_bounds__(256) void k_census_keys(const int32_t* __restrict__ cell,
                                                      const uint8_t* __restrict__ keep,
                                                      const long long* __restrict__ tcount,
                                                      const long long* __restrict__ tincl,
@@ -693,7 +702,7 @@ __global__ __launch_bounds__(256) void k_census_keys(const StageRec<R>* __restri
     }
     const long long pos = before + off + below;
     if (f && pos < cap) {
-      keys[pos] = (uint32_t)src[i].cell;
+      keys[pos] = (uint32_t)cell[i];
       vals[pos] = (uint32_t)i;
     }
     before += tot;
@@ -701,24 +710,14 @@ __global__ __launch_bounds__(256) void k_census_keys(const StageRec<R>* __restri
   }
 }
 
-template <typename R>
-hipError_t launch_census_keys(const StageRec<R>* src, const uint8_t* keep,
-                              const long long* tcount, const long long* tincl, long long n,
-                              long long cap, uint32_t* keys, uint32_t* vals, const DevState* st,
-                              hipStream_t s) {
+hipError_t launch_census_keys(const int32_t* cell, const uint8_t* keep, const long long* tcount,
+                              const long long* tincl, long long n, long long cap, uint32_t* keys,
+                              uint32_t* vals, const DevState* st, hipStream_t s) {
   const long long tiles = census_tiles(n > 0 ? n : 1);
-  hipLaunchKernelGGL(k_census_keys<R>, dim3((unsigned)tiles), dim3(256), 0, s, src, keep,
-                     tcount, tincl, n, cap, keys, vals, st);
+  hipLaunchKernelGGL(k_census_keys, dim3((unsigned)tiles), dim3(256), 0, s, cell, keep, tcount,
+                     tincl, n, cap, keys, vals, st);
   return hipGetLastError();
 }
-template hipError_t launch_census_keys<double>(const StageRec<double>*, const uint8_t*,
-                                               const long long*, const long long*, long long,
-                                               long long, uint32_t*, uint32_t*, const DevState*,
-                                               hipStream_t);
-template hipError_t launch_census_keys<float>(const StageRec<float>*, const uint8_t*,
-                                              const long long*, const long long*, long long,
-                                              long long, uint32_t*, uint32_t*, const DevState*,
-                                              hipStream_t);
 
 // Stable LSD radix sort of (key, value) pairs by 8-bit digits.  A tile of
 // kSortTile pairs per block, read in rounds of 256 (pair base + r 256 + t in

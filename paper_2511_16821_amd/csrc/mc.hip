@@ -224,12 +224,14 @@ __device__ __forceinline__ void bal_add(unsigned long long* bal, int f, double v
 // qbar_j = A dt mean(q), or A mean(q) per unit time in steady state, where
 // every particle starts at time 0).
 //
-// A thread emits runs of kEmitRun consecutive particles.  With tens of
-// particles per cell a run nearly always lies in one emitter: the descents of
-// its first and last particles then show it, and the emitter's stream and
+// A thread emits runs of consecutive particles, up to kEmitRun of them when
+// the plan has that many per thread of the grid (one otherwise, so that a
+// small plan still spreads over the whole grid).  With tens of particles per
+// cell a run nearly always lies in one emitter: the descents of its first
+// and last particles then show it, and the emitter's stream and
 // per-dimension scramble seeds are computed once for the run.  A run that
 // spans emitters descends the tree for each of its inner particles.
-constexpr int kEmitRun = 8;
+constexpr long long kEmitRun = 8;
 
 template <typename R, int KIND>
 __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
@@ -249,9 +251,10 @@ __global__ __launch_bounds__(256) void k_emit(PassArgs a) {
   const R hx = (R)a.hx, hy = (R)a.hy, dt_birth = (R)a.dt_birth;
   SrcRec<R>* const b = Real<R>::src(a);
   const long long T = (long long)gridDim.x * blockDim.x;
-  for (long long r0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * kEmitRun;
-       r0 < n_emit; r0 += kEmitRun * T) {
-    const long long r1 = (r0 + kEmitRun < n_emit ? r0 + kEmitRun : n_emit) - 1;
+  const long long run = n_emit / T < 1 ? 1 : (n_emit / T > kEmitRun ? kEmitRun : n_emit / T);
+  for (long long r0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * run; r0 < n_emit;
+       r0 += run * T) {
+    const long long r1 = (r0 + run < n_emit ? r0 + run : n_emit) - 1;
     long long sj[2] = {r0, r1};
     CellPick pk[2];
     count_pick_n<2>(a.ctree, s_top, a.tree_L, sj, pk);
@@ -716,9 +719,8 @@ int mc_pass_grid(bool fp32, int kind, long long max_work) {
 hipError_t launch_emit(const PassArgs& a, bool fp32, hipStream_t s) {
   if (a.n_src <= 0) return hipSuccess;
   // at most 2048 blocks (each block first stages 24 KB of tables in LDS, six
-  // blocks fit a compute unit); a thread takes its particles kEmitRun at a
-  // time
-  long long b = (a.n_src + 256 * kEmitRun - 1) / (256 * kEmitRun);
+  // blocks fit a compute unit); a thread takes its particles in runs
+  long long b = (a.n_src + 255) / 256;
   const int grid = (int)(b < 2048 ? b : 2048);
   if (a.kind == 1) {
     if (fp32) hipLaunchKernelGGL((k_emit<float, 1>), dim3(grid), dim3(256), 0, s, a);

@@ -227,7 +227,7 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
   double* slotK = smem + (size_t)2 * CW * 4;
   double* coefL = slotK + (size_t)2 * CW;
   const size_t n_coef = TABLE ? (size_t)g.n_mat * kDgRow : 0;
-  double* xf = coefL + n_coef;
+  double* xf = coefL + n_coef;  // 16-byte aligned (80 CW + 272 n_mat bytes in), read as double2
   double* yf = xf + 2 * ny;
   const int n_diag = nx + ny - 1;
   // barriers: one per chunk, padded to whole loader rounds (the padding
@@ -458,8 +458,11 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
     double x[Q][4];
 #pragma unroll
     for (int r = 0; r < Q; ++r) {
-      const double u0 = xf[2 * c_j[r]], u1 = xf[2 * c_j[r] + 1];
-      const double u2 = yf[2 * c_i[r]], u3 = yf[2 * c_i[r] + 1];
+      // a face's two traces as one 16-byte word (neighbouring lanes hold
+      // neighbouring cells: consecutive words, no bank conflicts)
+      const double2 ux = reinterpret_cast<const double2*>(xf)[c_j[r]];
+      const double2 uy = reinterpret_cast<const double2*>(yf)[c_i[r]];
+      const double u0 = ux.x, u1 = ux.y, u2 = uy.x, u3 = uy.y;
       const double* Pr = P[r];
       if (TABLE) {
         x[r][0] = r0[r][0] + Pr[0] * u0 + Pr[1] * u1 + Pr[2] * u2 + Pr[3] * u3;
@@ -493,10 +496,8 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
       if (!c_has[r]) continue;
       const double x0 = x[r][0], x1 = x[r][1], x2 = x[r][2], x3 = x[r][3];
       const int ci = c_i[r], cj = c_j[r];
-      xf[2 * cj] = apos ? x1 : x0;
-      xf[2 * cj + 1] = apos ? x3 : x2;
-      yf[2 * ci] = bpos ? x2 : x0;
-      yf[2 * ci + 1] = bpos ? x3 : x1;
+      reinterpret_cast<double2*>(xf)[cj] = make_double2(apos ? x1 : x0, apos ? x3 : x2);
+      reinterpret_cast<double2*>(yf)[ci] = make_double2(bpos ? x2 : x0, bpos ? x3 : x1);
       // outflow on a reflective downwind side, for the mirrored direction
       if (REFL && rx_out) {
         if (ci == (apos ? nx - 1 : 0)) {

@@ -171,7 +171,10 @@ def test_thick_voids_ns4(S, oracle):
 
 
 def test_random_blocks_with_cap(S, oracle):
-    """Census above the cap: the thinning path (radix select of the keys)."""
+    """Census above the cap: keyed Bernoulli thinning (each candidate kept
+    when its key falls below the dyadic p_q), the kept candidates placed in
+    slot order and ordered by cell; the bank, its weights (scaled by 1/p_q)
+    and every tally equal the oracle's."""
     from paper_2511_16821_amd import workloads as W
     p = W.random_blocks(n=40, L=4.0, blocks=8, n_s=3, n_particles=6000, census_cap=2500,
                         dt=0.05, sn_order=4, n_steps=3)

@@ -24,6 +24,7 @@
 // several private copies of the tally (summed afterwards), through a small
 // cache of tally words per wave in LDS, so that simultaneous updates of a busy
 // cell do not queue on one cache line.
+#include <atomic>
 #include "slh_common.hpp"
 #include "sobol_dirs.inc"
 
@@ -694,8 +695,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // Blocks of the persistent tracking grid: as many as can be resident at once
 // (occupancy x compute units), never more than the work needs.
 int mc_pass_grid(bool fp32, int kind, long long max_work) {
-  static int cached[2][2] = {{0, 0}, {0, 0}};
-  int& nb = cached[fp32 ? 1 : 0][kind == 1 ? 0 : 1];
+  // solvers and servers are created from several threads: every thread that
+  // finds the entry empty computes the same value and stores it atomically
+  static std::atomic<int> cached[2][2];
+  std::atomic<int>& slot = cached[fp32 ? 1 : 0][kind == 1 ? 0 : 1];
+  int nb = slot.load(std::memory_order_relaxed);
   if (nb == 0) {
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
@@ -710,6 +714,7 @@ int mc_pass_grid(bool fp32, int kind, long long max_work) {
     if (e != hipSuccess || per < 1) per = 2;
     if (cus < 1) cus = 256;
     nb = cus * per;
+    slot.store(nb, std::memory_order_relaxed);
   }
   long long want = (max_work + 255) / 256;
   if (want > nb) want = nb;

@@ -213,6 +213,22 @@ __device__ __forceinline__ void bal_add(unsigned long long* bal, int f, double v
   atomicAdd(&bal[2 * f + 1], (unsigned long long)lo);
 }
 
+// A value every lane of the wave holds alike (read from the solver state,
+// which the compiler cannot take as uniform), moved to scalar registers so
+// that it takes no vector register in the tracking loop.
+__device__ __forceinline__ long long wave_uniform(long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double wave_uniform(double v) {
+  return __longlong_as_double(wave_uniform((long long)__double_as_longlong(v)));
+}
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // Emission of the pass's source particles (Sec. 2.3: birth proportional to
 // q, isotropic direction, weights that integrate q in expectation),
 // stratified by cell: cell j emits the n_j particles of the emission plan
@@ -351,14 +367,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
   DevState* st = a.st;
   const int lane = __lane_id();
-  const long long n_in = st->n_in;
-  const long long n_emit = st->n_emit;  // the plan's count, clamped to the source bank
+  const long long n_in = wave_uniform(st->n_in);
+  const long long n_emit = wave_uniform(st->n_emit);  // the plan's count, clamped to the bank
   const unsigned long long n_tot = (unsigned long long)(n_in + n_emit);
-  const double w_q = st->wq[KIND - 1];
-  const R w_cut = (R)(a.w_cut_rel * w_q);
-  const double inv_T = st->inv_T;
-  const double inv_W = st->inv_W;
-  const uint64_t step = st->step;
+  const double w_q = wave_uniform(st->wq[KIND - 1]);
+  const R w_cut = wave_uniform((R)(a.w_cut_rel * w_q));
+  const double inv_T = wave_uniform(st->inv_T);
+  const double inv_W = wave_uniform(st->inv_W);
+  const uint64_t step = (uint64_t)wave_uniform((long long)st->step);
   const R hx = (R)a.hx, hy = (R)a.hy, dt = (R)a.dt, c = (R)a.c;
   const R INF = Real<R>::inf();
   const StageRec<R>* const bin = Real<R>::in(a);
@@ -404,8 +420,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   bool from_census = false;
   unsigned int lane_seg = 0, lane_hist = 0, lane_alive = 0, lane_killed = 0, lane_bad = 0;
   unsigned long long* my_bal = s_bal + (lane % kBalCopies) * kBalStride;
-  unsigned long long* const tc_tag = s_tc_tag + (threadIdx.x >> 6) * kTcSlots;
-  unsigned long long* const tc_sum = s_tc_sum + (threadIdx.x >> 6) * kTcSlots;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave in the block
+  unsigned long long* const tc_tag = s_tc_tag + wv * kTcSlots;
+  unsigned long long* const tc_sum = s_tc_sum + wv * kTcSlots;
   int tc_it = 0;
   // the wave's held sums to their words (all lanes of the wave together)
   auto tc_flush = [&]() __attribute__((always_inline)) {

@@ -113,6 +113,30 @@ def test_c2_full_size(S, oracle):
     _run_pair(S, oracle, W.c2(n_s=2), 2)
 
 
+def _sparse_source_problem(n, n_particles, seed):
+    """Pure absorber on [0,1]^2 (sigma_a = 5) whose source lies in a seeded
+    third of the cells with strengths spread over four decades: a weak cell
+    gets no particle or a few, a strong one hundreds."""
+    from paper_2511_16821_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    q = np.where(rng.random((n, n)) < 1 / 3, 10.0 ** rng.uniform(-2, 2, (n, n)), 0.0)
+    return W._problem(n, n, (0.0, 1.0, 0.0, 1.0), np.zeros((n, n)), np.full((n, n), 5.0), q,
+                      n_s=0, n_particles=n_particles, dt=0.002, n_steps=1, sn_order=2)
+
+
+def test_emission_runs(S, oracle):
+    """Plans of more than two particles per thread of the emission grid
+    (2048 blocks of 256) are emitted in runs of consecutive particles per
+    thread, eight on the large solve.  Runs of eight (4.5e6 particles on
+    512x512) and of three (1.7e6 on 256x256) over a sparse source whose
+    emitters hold from none to hundreds of particles, so that runs span
+    several emitters and the empty cells between them; the census also
+    exceeds its cap (thinning).  One step each against the oracle (about 25 s
+    of oracle time)."""
+    _run_pair(S, oracle, _sparse_source_problem(512, 4_500_000, 5), 1)
+    _run_pair(S, oracle, _sparse_source_problem(256, 1_700_000, 6), 1)
+
+
 def test_halton_points_full_steps(S, oracle):
     """The paper's point set (shifted Halton) through whole steps: C1 box with
     N_s = 1 and a checkerboard with N_s = 2, against the oracle."""

@@ -3,7 +3,7 @@ relative in the L2 and max norms for every tally array, every step)."""
 import numpy as np
 import pytest
 
-from gpu_util import FP64_TOL, compare_balance, compare_step, log, rel_l2
+from gpu_util import FP32_TOL, FP64_TOL, compare_balance, compare_step, log, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -131,10 +131,23 @@ def test_emission_runs(S, oracle):
     512x512) and of three (1.7e6 on 256x256) over a sparse source whose
     emitters hold from none to hundreds of particles, so that runs span
     several emitters and the empty cells between them; the census also
-    exceeds its cap (thinning).  One step each against the oracle (about 25 s
-    of oracle time)."""
+    exceeds its cap (thinning).  One step each against the oracle, and the
+    runs of eight with FP32 tracking: every flux within 1e-4 of the FP64
+    oracle and the same emission plans (about 40 s of oracle time)."""
     _run_pair(S, oracle, _sparse_source_problem(512, 4_500_000, 5), 1)
     _run_pair(S, oracle, _sparse_source_problem(256, 1_700_000, 6), 1)
+    p = _sparse_source_problem(512, 4_500_000, 5)
+    ref = oracle.HybridOracle(p).step()
+    s = S.Solver(dict(p, precision=1))
+    s.advance(1)
+    errs = compare_step(S, s, ref, tol=FP32_TOL, l2_only=True)
+    log("  FP32", {k: "%.1e" % v[0] for k, v in errs.items()})
+    for pss, key in ((1, "bal_mc"), (2, "bal_remap")):
+        b = s.get_balance(pss)
+        assert b["source_particles"] == ref[key]["source_particles"], (pss, b, ref[key])
+        assert b["weight_quantum"] == ref[key]["weight_quantum"], (pss, b, ref[key])
+        assert b["killed"] == 0
+    s.destroy()
 
 
 def test_halton_points_full_steps(S, oracle):

@@ -131,12 +131,10 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(profile, kernel, prec):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary `profile` (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy
-    calibration), or None when the summary is missing or was taken on other
-    kernel code."""
-    path = os.path.join(ROOT, "profiles", profile)
+def _profile_entries(profile):
+    """The key: value lines of the committed rocprofv3 summary `profile`, or
+    None when it is missing or was taken on other kernel code."""
+    path = os.path.join(ROOT, "profiles", profile) if profile else ""
     if not profile or not os.path.isfile(path):
         return None
     kv = {}
@@ -146,8 +144,36 @@ def measured_traffic(profile, kernel, prec):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_digest") != kernel_source_digest():
         return None
+    return kv
+
+
+def measured_traffic(profile, kernel, prec):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary `profile` (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy
+    calibration), or None when the summary is missing or was taken on other
+    kernel code."""
+    kv = _profile_entries(profile)
+    if kv is None:
+        return None
     key = "hbm_bytes_per_launch[%s,%s]" % (kernel, "fp64" if prec == 0 else "fp32")
     return float(kv[key]) if key in kv else None
+
+
+def measured_issue(profile, kernel, prec):
+    """What bounds `kernel` besides HBM, from the SQ/TCC counters of the same
+    summary: the share of SIMD cycles issuing a VALU instruction, the active
+    lanes per VALU instruction and the L2 hit rate (FP64 tracking only), or
+    None."""
+    kv = _profile_entries(profile)
+    key = "counters[%s,%s]" % (kernel, "fp64" if prec == 0 else "fp32")
+    if kv is None or key not in kv:
+        return None
+    f = dict(t.split("=", 1) for t in kv[key].split() if "=" in t)
+    try:
+        return {"valu_issue": float(f["valu_issue"]), "active_lanes": float(f["active_lanes"]),
+                "l2_hit": float(f["l2_hit"])}
+    except (KeyError, ValueError):
+        return None
 
 
 def rooflines(st, steps, prec, profile):
@@ -169,6 +195,7 @@ def rooflines(st, steps, prec, profile):
         rows.append({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(profile, name, prec),
+                     "issue": measured_issue(profile, name, prec),
                      "kernel": name, "avg_launch_ms": round(ms / steps, 4),
                      "bytes_per_launch": int(per_launch_bytes),
                      "segments_per_launch": int(seg / steps)})

@@ -102,6 +102,7 @@ template <> struct Real<float> {
     o[0] = make_float4(px, py, ox, oy);
     o[1] = make_float4(w, trel, tau, __int_as_float(cell));
     o[2] = make_float4(__uint_as_float(lidx), 0.f, 0.f, 0.f);
+    o[3] = make_float4(0.f, 0.f, 0.f, 0.f);  // the padding too: whole sectors
   }
 };
 

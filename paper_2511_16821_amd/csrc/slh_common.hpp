@@ -252,20 +252,24 @@ static_assert(sizeof(StageRec<double>) == 64 && sizeof(StageRec<float>) == 32,
 // by the tracking kernel: position in the cell, direction, weight, birth time
 // within the step, first optical depth (scatter-limited pass with N_s > 0
 // only), cell and index within the cell (the particle's point index in its
-// cell's stream).  One record per particle (64 B FP64, 48 B FP32), so that a
-// history start reads one cache line rather than one line per field.
+// cell's stream).  One 64-byte record per particle in either precision, so
+// that a history start reads one cache line rather than one line per field;
+// the FP32 record is padded from 36 bytes to 64 so that the emission, whose
+// threads each write a run of consecutive records, writes whole 64-byte
+// sectors (48-byte records left partial sectors between a thread's
+// consecutive records: 1.9x the record bytes in HBM writes).
 template <typename R> struct SrcRec;
 template <> struct alignas(64) SrcRec<double> {
   double px, py, ox, oy, w, trel, tau;
   int32_t cell;
   uint32_t lidx;
 };
-template <> struct alignas(16) SrcRec<float> {
+template <> struct alignas(64) SrcRec<float> {
   float px, py, ox, oy, w, trel, tau;
   int32_t cell;
-  uint32_t lidx, pad0, pad1, pad2;
+  uint32_t lidx, pad0, pad1, pad2, pad3, pad4, pad5, pad6;
 };
-static_assert(sizeof(SrcRec<double>) == 64 && sizeof(SrcRec<float>) == 48,
+static_assert(sizeof(SrcRec<double>) == 64 && sizeof(SrcRec<float>) == 64,
               "source record sizes");
 
 // Balance fields, each a two-word fixed-point sum.

@@ -1,6 +1,8 @@
 // Support kernels of the hybrid step: fills, pass set-up (fixed-point units
 // from device-resident bounds), tally decoding, the remap source (step 3 of
 // Sec. 2.2), deterministic prefix scans, and census population control.
+#include <algorithm>
+
 #include "slh_common.hpp"
 
 namespace slh {
@@ -719,9 +721,13 @@ hipError_t launch_census_keys(const int32_t* cell, const uint8_t* keep, const lo
   return hipGetLastError();
 }
 
-// Stable LSD radix sort of (key, value) pairs by 8-bit digits.  A tile of
-// kSortTile pairs per block, read in rounds of 256 (pair base + r 256 + t in
-// round r, thread t): the order of the pairs is their index order.
+// Stable LSD radix sort of (key, value) pairs.  Keys below 2^b sort in
+// P = ceil(b / 10) passes of ceil(b / P)-bit digits (1024^2 cells: two passes
+// of 10 bits; 140^2: two of 8).  A tile of 256 rounds x 256 pairs per block,
+// with as many rounds as give 16 pairs per digit value on average (16 rounds
+// up to 8-bit digits, 64 for 10-bit), so that the scatter of a tile still
+// writes runs of whole sectors; the pairs are read in rounds (pair base +
+// r 256 + t in round r, thread t), in index order.
 //   upsweep:   the tile's digit histogram -> hist[digit][tile]
 //   scan:      inclusive scan of hist (digit-major): the pairs of digit d of
 //              tile b start at incl[d][b] - hist[d][b]
@@ -729,28 +735,63 @@ hipError_t launch_census_keys(const int32_t* cell, const uint8_t* keep, const lo
 //              (rounds in order; in a round, the waves in order and the
 //              lanes of a wave in order, lanes of one digit matched by
 //              ballots), then the scatter to start + rank.
-constexpr int kSortRounds = 16;
-constexpr int kSortTile = 256 * kSortRounds;
+constexpr int kSortMaxBits = 10;
+constexpr int kSortMaxDigits = 1 << kSortMaxBits;
 
-long long radix_tiles(long long n) { return (n + kSortTile - 1) / kSortTile; }
+static int sort_key_bits(long long n_keys_max) {
+  int bits = 1;
+  while (bits < 32 && (1ll << bits) < n_keys_max) ++bits;
+  return bits;
+}
+
+int radix_passes(long long n_keys_max) {
+  return (sort_key_bits(n_keys_max) + kSortMaxBits - 1) / kSortMaxBits;
+}
+
+static int sort_digit_bits(long long n_keys_max) {
+  const int p = radix_passes(n_keys_max);
+  return (sort_key_bits(n_keys_max) + p - 1) / p;
+}
+
+static int sort_rounds(int digit_bits) { return digit_bits <= 8 ? 16 : 16 << (digit_bits - 8); }
+
+static long long sort_tiles(long long n, int digit_bits) {
+  const long long tile = 256ll * sort_rounds(digit_bits);
+  return (n + tile - 1) / tile;
+}
+
+long long radix_tiles(long long n) { return sort_tiles(n, 8); }
+
+// Histogram entries for any digit width: digits x tiles is largest for the
+// widest digits (1024 x ceil(cap / 16384) >= 256 x ceil(cap / 4096)).
+size_t radix_hist_elems(long long cap) {
+  size_t m = 0;
+  for (int b = 8; b <= kSortMaxBits; ++b)
+    m = std::max(m, ((size_t)1 << b) * (size_t)sort_tiles(cap > 0 ? cap : 1, b));
+  return m;
+}
 
 __global__ __launch_bounds__(256) void k_radix_up(const uint32_t* __restrict__ keys,
                                                   const long long* incl_last, long long cap,
-                                                  int shift, long long n_tiles,
+                                                  int shift, int bits, int rounds,
+                                                  long long n_tiles,
                                                   long long* __restrict__ hist,
                                                   const DevState* st) {
   if (st->halt) return;
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0u;
+  __shared__ uint32_t h[kSortMaxDigits];
+  const int n_dig = 1 << bits;
+  const uint32_t mask = (uint32_t)n_dig - 1u;
+  for (int d = threadIdx.x; d < n_dig; d += 256) h[d] = 0u;
   __syncthreads();
   const long long count = census_count(incl_last, cap);
-  const long long base = (long long)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortRounds; ++r) {
+  const long long base = (long long)blockIdx.x * 256 * rounds;
+  for (int r = 0; r < rounds; ++r) {
     const long long i = base + r * 256 + threadIdx.x;
-    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
   }
   __syncthreads();
-  hist[(long long)threadIdx.x * n_tiles + blockIdx.x] = (long long)h[threadIdx.x];
+  for (int d = threadIdx.x; d < n_dig; d += 256)
+    hist[(long long)d * n_tiles + blockIdx.x] = (long long)h[d];
 }
 
 __global__ __launch_bounds__(256) void k_radix_down(const uint32_t* __restrict__ kin,
@@ -758,39 +799,44 @@ __global__ __launch_bounds__(256) void k_radix_down(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ kout,
                                                     uint32_t* __restrict__ vout,
                                                     const long long* incl_last, long long cap,
-                                                    int shift, long long n_tiles,
+                                                    int shift, int bits, int rounds,
+                                                    long long n_tiles,
                                                     const long long* __restrict__ hist,
                                                     const long long* __restrict__ hincl,
                                                     const DevState* st) {
   if (st->halt) return;
-  __shared__ long long s_start[256];  // first output index of each digit of this tile
-  __shared__ uint32_t s_run[256];     // pairs of each digit in the earlier rounds
-  __shared__ uint32_t s_wave[4][256]; // pairs of each digit in each wave of the round
+  __shared__ long long s_start[kSortMaxDigits];  // first output index of each digit of this tile
+  __shared__ uint32_t s_run[kSortMaxDigits];     // pairs of each digit in the earlier rounds
+  __shared__ uint32_t s_wave[4][kSortMaxDigits]; // pairs of each digit in each wave of the round
   const int t = threadIdx.x, w = t >> 6;
-  const long long hb = (long long)t * n_tiles + blockIdx.x;
-  // thread t owns digit t's entries of s_start, s_run and s_wave
-  s_start[t] = hincl[hb] - hist[hb];
-  s_run[t] = 0u;
-  for (int v = 0; v < 4; ++v) s_wave[v][t] = 0u;
+  const int n_dig = 1 << bits;
+  const uint32_t mask = (uint32_t)n_dig - 1u;
+  for (int d = t; d < n_dig; d += 256) {
+    const long long hb = (long long)d * n_tiles + blockIdx.x;
+    s_start[d] = hincl[hb] - hist[hb];
+    s_run[d] = 0u;
+    for (int v = 0; v < 4; ++v) s_wave[v][d] = 0u;
+  }
   __syncthreads();
   const long long count = census_count(incl_last, cap);
-  const long long base = (long long)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortRounds; ++r) {
+  const long long base = (long long)blockIdx.x * 256 * rounds;
+  for (int r = 0; r < rounds; ++r) {
     const long long i = base + r * 256 + t;
     const bool ok = i < count;
     const uint32_t key = ok ? kin[i] : 0u;
     const uint32_t val = ok ? vin[i] : 0u;
-    const int d = (int)((key >> shift) & 255u);
+    const int d = (int)((key >> shift) & mask);
     // lanes of this wave with the same digit (among the valid ones)
     unsigned long long peers = __ballot(ok);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < bits; ++b) {
       const unsigned long long m = __ballot((d >> b) & 1);
       peers &= ((d >> b) & 1) ? m : ~m;
     }
     const uint32_t below = __builtin_amdgcn_mbcnt_hi(
         (uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-    if (ok && below == 0u) s_wave[w][d] = (uint32_t)__popcll(peers);
+    const bool lead = ok && below == 0u;  // the first lane of its digit in the wave
+    const uint32_t n_peer = (uint32_t)__popcll(peers);
+    if (lead) s_wave[w][d] = n_peer;
     __syncthreads();
     if (ok) {
       uint32_t before = s_run[d];
@@ -800,19 +846,15 @@ __global__ __launch_bounds__(256) void k_radix_down(const uint32_t* __restrict__
       vout[o] = val;
     }
     __syncthreads();
-    s_run[t] += s_wave[0][t] + s_wave[1][t] + s_wave[2][t] + s_wave[3][t];
-    for (int v = 0; v < 4; ++v) s_wave[v][t] = 0u;
+    // each wave's leaders move their counts into the running totals (integer
+    // adds: the order of the waves does not matter) and clear their entries
+    if (lead) {
+      atomicAdd(&s_run[d], n_peer);
+      s_wave[w][d] = 0u;
+    }
     __syncthreads();
   }
 }
-
-int radix_passes(long long n_keys_max) {
-  int bits = 1;
-  while (bits < 32 && (1ll << bits) < n_keys_max) ++bits;
-  return (bits + 7) / 8;
-}
-
-size_t radix_hist_elems(long long cap) { return (size_t)256 * (size_t)radix_tiles(cap); }
 
 // Sorts the first min(*incl_last, cap) pairs of (k0, v0) by key (keys below
 // key_bound); the result is in (k0, v0) after an even number of passes, in
@@ -821,19 +863,21 @@ hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
                             const long long* incl_last, long long cap, long long key_bound,
                             long long* hist, long long* hincl, long long* scan_tmp,
                             const DevState* st, hipStream_t s) {
-  const long long tiles = radix_tiles(cap > 0 ? cap : 1);
   const int passes = radix_passes(key_bound);
+  const int bits = sort_digit_bits(key_bound);
+  const int rounds = sort_rounds(bits);
+  const long long tiles = sort_tiles(cap > 0 ? cap : 1, bits);
   for (int p = 0; p < passes; ++p) {
     uint32_t* ki = (p & 1) ? k1 : k0;
     uint32_t* vi = (p & 1) ? v1 : v0;
     uint32_t* ko = (p & 1) ? k0 : k1;
     uint32_t* vo = (p & 1) ? v0 : v1;
     hipLaunchKernelGGL(k_radix_up, dim3((unsigned)tiles), dim3(256), 0, s, (const uint32_t*)ki,
-                       incl_last, cap, 8 * p, tiles, hist, st);
-    hipError_t e = scan_inclusive_i64(hist, hincl, 256 * tiles, scan_tmp, &st->halt, s);
+                       incl_last, cap, bits * p, bits, rounds, tiles, hist, st);
+    hipError_t e = scan_inclusive_i64(hist, hincl, (1ll << bits) * tiles, scan_tmp, &st->halt, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_radix_down, dim3((unsigned)tiles), dim3(256), 0, s, (const uint32_t*)ki,
-                       (const uint32_t*)vi, ko, vo, incl_last, cap, 8 * p, tiles,
+                       (const uint32_t*)vi, ko, vo, incl_last, cap, bits * p, bits, rounds, tiles,
                        (const long long*)hist, (const long long*)hincl, st);
   }
   return hipGetLastError();

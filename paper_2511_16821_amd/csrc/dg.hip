@@ -390,7 +390,7 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
   bool c_has[Q];
   int c_i[Q], c_j[Q];
   long long c_pos[Q];
-  double P[Q][16];    // table: G; cell mode: LU (inverse pivots, L, strict U)
+  double P[Q][16];    // table: G; cell mode: B^-1, D, S^-1, G of the block factorisation
   double r0[Q][4];    // table: B S; cell mode: MM S
   auto prepare = [&](int slot) __attribute__((always_inline)) {
     const bool live = cd < n_diag;
@@ -425,23 +425,28 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
           for (int l = 0; l < 4; ++l) A[a][l] = dmA[4 * a + l] + key * MM[a][l];
           r0[r][a] = MM[a][0] * S.x + MM[a][1] * S.y + MM[a][2] * S.z + MM[a][3] * S.w;
         }
-        // LU without pivoting (see k_dg_coef for why the pivots do not vanish)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double inv = recip(A[c][c]);
-          P[r][c] = inv;
-#pragma unroll
-          for (int a = c + 1; a < 4; ++a) {
-            const double f = A[a][c] * inv;
-            A[a][c] = f;
-#pragma unroll
-            for (int l = c + 1; l < 4; ++l) A[a][l] -= f * A[c][l];
-          }
-        }
-        P[r][4] = A[1][0]; P[r][5] = A[2][0]; P[r][6] = A[3][0];
-        P[r][7] = A[2][1]; P[r][8] = A[3][1]; P[r][9] = A[3][2];
-        P[r][10] = A[0][1]; P[r][11] = A[0][2]; P[r][12] = A[0][3];
-        P[r][13] = A[1][2]; P[r][14] = A[1][3]; P[r][15] = A[2][3];
+        // Block factorisation over the node pairs {0,1} and {2,3}: the
+        // leading block B by its adjugate, G = B^-1 C, the Schur complement
+        // S = E - D G and its inverse.  Every principal block and Schur
+        // complement of the element matrix keeps a positive definite
+        // symmetric part (see k_dg_coef), and a 2x2 matrix with one has a
+        // determinant at least that of its symmetric part, so both
+        // determinants are positive: two reciprocals per cell, where the
+        // scalar factorisation takes four in sequence.
+        const double ib = recip(A[0][0] * A[1][1] - A[0][1] * A[1][0]);
+        const double B00 = A[1][1] * ib, B01 = -A[0][1] * ib;
+        const double B10 = -A[1][0] * ib, B11 = A[0][0] * ib;
+        const double G00 = B00 * A[0][2] + B01 * A[1][2], G01 = B00 * A[0][3] + B01 * A[1][3];
+        const double G10 = B10 * A[0][2] + B11 * A[1][2], G11 = B10 * A[0][3] + B11 * A[1][3];
+        const double S00 = A[2][2] - (A[2][0] * G00 + A[2][1] * G10);
+        const double S01 = A[2][3] - (A[2][0] * G01 + A[2][1] * G11);
+        const double S10 = A[3][2] - (A[3][0] * G00 + A[3][1] * G10);
+        const double S11 = A[3][3] - (A[3][0] * G01 + A[3][1] * G11);
+        const double is = recip(S00 * S11 - S01 * S10);
+        P[r][0] = B00; P[r][1] = B01; P[r][2] = B10; P[r][3] = B11;
+        P[r][4] = A[2][0]; P[r][5] = A[2][1]; P[r][6] = A[3][0]; P[r][7] = A[3][1];
+        P[r][8] = S11 * is; P[r][9] = -S01 * is; P[r][10] = -S10 * is; P[r][11] = S00 * is;
+        P[r][12] = G00; P[r][13] = G01; P[r][14] = G10; P[r][15] = G11;
       }
     }
     if (live) {
@@ -481,14 +486,14 @@ __device__ __forceinline__ void sweep_dir(const DgArgs& g) {
           if ((e >> 1) == (bpos ? 0 : 1)) acc = acc + dmF[4 * e + 2] * u2 + dmF[4 * e + 3] * u3;
           yv[e] = acc;
         }
-        double y0 = yv[0], y1 = yv[1], y2 = yv[2], y3 = yv[3];
-        y1 -= Pr[4] * y0;
-        y2 -= Pr[5] * y0 + Pr[7] * y1;
-        y3 -= Pr[6] * y0 + Pr[8] * y1 + Pr[9] * y2;
-        x[r][3] = y3 * Pr[3];
-        x[r][2] = (y2 - Pr[15] * x[r][3]) * Pr[2];
-        x[r][1] = (y1 - Pr[13] * x[r][2] - Pr[14] * x[r][3]) * Pr[1];
-        x[r][0] = (y0 - Pr[10] * x[r][1] - Pr[11] * x[r][2] - Pr[12] * x[r][3]) * Pr[0];
+        // w = B^-1 y_top, z = y_bot - D w, x_bot = S^-1 z, x_top = w - G x_bot
+        const double w0 = Pr[0] * yv[0] + Pr[1] * yv[1], w1 = Pr[2] * yv[0] + Pr[3] * yv[1];
+        const double z0 = yv[2] - (Pr[4] * w0 + Pr[5] * w1);
+        const double z1 = yv[3] - (Pr[6] * w0 + Pr[7] * w1);
+        x[r][2] = Pr[8] * z0 + Pr[9] * z1;
+        x[r][3] = Pr[10] * z0 + Pr[11] * z1;
+        x[r][0] = w0 - (Pr[12] * x[r][2] + Pr[13] * x[r][3]);
+        x[r][1] = w1 - (Pr[14] * x[r][2] + Pr[15] * x[r][3]);
       }
     }
 #pragma unroll

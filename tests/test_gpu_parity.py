@@ -150,6 +150,17 @@ def test_emission_runs(S, oracle):
     s.destroy()
 
 
+def test_census_order_wide_digits(S, oracle):
+    """The census ordering with the widest digits: on a 1024x1024 mesh the
+    cells sort in two passes of 10-bit digits (tiles of 16384 pairs).  The
+    sparse source with 2e6 particles per pass puts the census above its cap
+    in both steps (thinning), and the second step tracks the first one's bank
+    (about 2e6 census particles) beside its own emission; the banks, ordered
+    by cell, against the oracle (about 20 s of oracle time)."""
+    p = _sparse_source_problem(1024, 2_000_000, 7)
+    _run_pair(S, oracle, dict(p, n_steps=2), 2)
+
+
 def test_halton_points_full_steps(S, oracle):
     """The paper's point set (shifted Halton) through whole steps: C1 box with
     N_s = 1 and a checkerboard with N_s = 2, against the oracle."""
